@@ -1,0 +1,195 @@
+/*
+ * mf.h -- C ABI of the MI355X (gfx950) dynamic max-flow library.
+ *
+ * The library computes the maximum s-t flow value of a capacitated directed
+ * graph (paper Section 2.1) with the GPU push-relabel loop of Section 3
+ * (Algorithms 1-4: preflow initialisation, push-relabel kernel,
+ * remove-invalid-edges kernel, backward-BFS global relabel) and repairs it
+ * after a batch of capacity updates with the dynamic algorithm of Section 4
+ * (Algorithms 5-6: apply capacity deltas, send back over-capacity flow,
+ * re-saturate the source, global relabel that treats deficient vertices as
+ * extra sinks, then the same push-relabel loop).  The residual graph is the
+ * Bi-CSR of Section 5.1: every vertex row holds both its out- and in-
+ * neighbours, absent reverse edges as zero-capacity entries, and every entry
+ * knows the index of its reverse entry.
+ *
+ * Conventions for every call
+ *   - Integers are fixed-width.  Capacities are int32 >= 0; flow values and
+ *     excesses are exact int64.  There is no floating point in the method.
+ *   - Host pointers passed in are only read during the call (the library
+ *     copies what it keeps); output buffers are owned by the caller.
+ *   - A graph handle owns all device memory of its graph until
+ *     mf_graph_free.  One handle must not be used by two threads at once;
+ *     distinct handles are independent.
+ *   - Calls are synchronous with respect to their outputs: when a call
+ *     returns, its host outputs are written.
+ *   - Inputs are validated before anything is changed: on every error other
+ *     than MF_ERR_DEVICE the graph is left exactly as it was.  After
+ *     MF_ERR_DEVICE the handle only accepts mf_graph_free.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mf_graph mf_graph;
+
+typedef enum mf_status {
+    MF_OK = 0,
+    MF_ERR_INVALID = 1,        /* bad argument: ids out of range, u == v, s == t, cap < 0, n < 2, k < 0, NULL */
+    MF_ERR_OUT_OF_MEMORY = 2,  /* a device or host allocation failed; the graph is unchanged */
+    MF_ERR_OVERFLOW = 3,       /* c(u,v) + c(v,u) of a merged pair exceeds INT32_MAX, or too many slots */
+    MF_ERR_DEVICE = 4,         /* a HIP call failed; the handle is unusable */
+    MF_ERR_NOT_CONVERGED = 5,  /* the global-relabel iteration cap was reached */
+    MF_ERR_STATE = 6           /* call order: a repair, cut or flow before the first mf_maxflow */
+} mf_status;
+
+/* Options.  Zero-initialise, set struct_size = sizeof(mf_options), or call
+ * mf_default_options.  Fields left 0 take the default shown. */
+typedef struct mf_options {
+    uint32_t struct_size;
+    int32_t device;            /* HIP device ordinal; default: the current device */
+    void* stream;              /* hipStream_t to launch on (e.g. a torch stream); NULL: a library stream */
+    int32_t kernel_cycles;     /* push/relabel cycles per vertex per launch (Algorithm 2's
+                                  KERNEL_CYCLES); <= 0: round(m/n), at least 1 (Section 6.1) */
+    int32_t topology_driven;   /* 1: one worker per vertex for push-relabel and remove-invalid-
+                                  edges; 0 (default): active-vertex worklist (Section 5.2, O1) */
+    int32_t insert_slack_min;  /* free slots kept per row for inserted pairs; <= 0: 2 */
+    int32_t insert_slack_pct;  /* plus this percentage of the row's length; <= 0: 12 */
+    int64_t max_iterations;    /* cap on global relabels per call; <= 0: 4n + 1000 */
+} mf_options;
+
+/* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its
+ * slot stays, with capacity 0); an absent pair is inserted.  Within one
+ * batch the last update of a pair wins.  (Section 4.1: a batch is a set of
+ * edges with their new capacities, higher or lower than before.) */
+typedef struct mf_update {
+    int32_t u, v, cap;
+} mf_update;
+
+typedef struct mf_stats {
+    int64_t n;                 /* vertices */
+    int64_t pairs;             /* merged directed pairs with a slot (cap may be 0) */
+    int64_t slots;             /* Bi-CSR entries in use */
+    int64_t slot_capacity;     /* Bi-CSR entries allocated, including insertion slack */
+    int64_t device_bytes;      /* device memory held by the handle */
+    int32_t kernel_cycles;     /* KC in use */
+    int32_t relayouts;         /* times insertion slack ran out and the rows were re-laid */
+    /* counters of the last mf_maxflow / mf_apply_batch call */
+    int64_t last_iterations;   /* global relabels (loop iterations) */
+    int64_t last_bfs_levels;   /* BFS level launches summed over its global relabels */
+    int64_t last_active_sum;   /* sum over iterations of the worklist size */
+    int64_t last_new_pairs;    /* pairs inserted by the last batch */
+    double last_ms;            /* host wall time of the call */
+    /* per-kernel device time over the calls since mf_profile(g, 1) (HIP events on the
+     * library's stream); index: 0 global-relabel level, 1 push-relabel, 2 remove-invalid-
+     * edges, 3 worklist build, 4 batch kernels, 5 reset and source saturation */
+    double kernel_ms[8];
+    int64_t kernel_launches[8];
+    /* algorithmic bytes the kernels of each class had to move over the same calls,
+     * from device-side counters (Bi-CSR slots and vertex words actually visited) */
+    double kernel_bytes[8];
+} mf_stats;
+
+/* Fill *opt with the defaults. */
+void mf_default_options(mf_options* opt);
+
+/* Human-readable name of a status code (static storage). */
+const char* mf_status_string(mf_status status);
+
+/* Load a graph (Section 2.1: directed G=(V,E), capacities c >= 0, source s,
+ * sink t) and build its device Bi-CSR (Section 5.1).
+ *   n        number of vertices, >= 2; vertices are 0..n-1
+ *   m        number of edges, >= 0
+ *   src,dst  int32[m] endpoints, host memory; u == v is rejected
+ *   cap      int32[m] capacities >= 0, host memory; repeated (u,v) pairs add up
+ *   s, t     source and sink, distinct
+ *   opt      NULL for defaults
+ *   out      receives the handle
+ * No flow is computed; the residual graph starts at zero flow.
+ * Errors: MF_ERR_INVALID, MF_ERR_OVERFLOW (a merged pair's c(u,v)+c(v,u) above
+ * INT32_MAX), MF_ERR_OUT_OF_MEMORY, MF_ERR_DEVICE. */
+mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                        const int32_t* cap, int32_t s, int32_t t, const mf_options* opt,
+                        mf_graph** out);
+
+/* Maximum flow value of the current capacities from zero flow: Algorithm 1
+ * (initialise, saturate the source, loop {backward BFS, push-relabel kernel,
+ * remove-invalid-edges kernel} while active vertices remain).  The loop stops
+ * only when a freshly computed global relabel leaves no active vertex, and
+ * *value = e(t) plus the (non-positive) excess of every deficient vertex.
+ * Leaves the residual graph, excesses and heights on the device for repairs.
+ * Errors: MF_ERR_INVALID (NULL), MF_ERR_NOT_CONVERGED, MF_ERR_DEVICE. */
+mf_status mf_maxflow(mf_graph* g, int64_t* value);
+
+/* Apply a batch of k updates held in HOST memory and return the new maximum
+ * flow value, repairing the retained state as Algorithm 5 does: add each
+ * capacity change to the residual, send back flow above a lowered capacity
+ * (changing the two endpoints' excesses), saturate the source again, then
+ * run the loop with t and every deficient vertex as sinks (Algorithm 6) and
+ * *value = sum of the excesses at height 0.  Requires a prior mf_maxflow.
+ * Errors: MF_ERR_INVALID (any update out of range, u == v, cap < 0; nothing
+ * is applied), MF_ERR_OVERFLOW (an updated pair's c(u,v)+c(v,u) above
+ * INT32_MAX; nothing is applied), MF_ERR_STATE, MF_ERR_NOT_CONVERGED,
+ * MF_ERR_OUT_OF_MEMORY, MF_ERR_DEVICE. */
+mf_status mf_apply_batch(mf_graph* g, const mf_update* upd, int64_t k, int64_t* value);
+
+/* As mf_apply_batch, with the k updates already in DEVICE memory on the
+ * handle's device (for example a torch tensor of shape [k, 3], int32).  The
+ * buffer is only read, on the handle's stream, before the call returns. */
+mf_status mf_apply_batch_device(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value);
+
+/* The minimum cut certified by the last solve (Sections 3.1 and 4.3):
+ * source side A = {v : h(v) = |V|}, the vertices that cannot reach t or a
+ * deficient vertex in the residual graph.  source_side: uint8[n] host buffer
+ * (1 = A, 0 = B) or NULL; *cut_capacity = sum of c(u,v) over u in A, v in B,
+ * which equals the last returned value.  Requires a prior solve.
+ * Errors: MF_ERR_INVALID, MF_ERR_STATE, MF_ERR_DEVICE. */
+mf_status mf_min_cut(mf_graph* g, uint8_t* source_side, int64_t* cut_capacity);
+
+/* A maximum flow for the current capacities (Section 3.1's construction from
+ * residuals, after completing the preflow: excess left on the source side is
+ * returned to s and deficits on the sink side are filled from t, along
+ * residual paths inside each side, Sections 3.1 and 4.3).  One entry per
+ * merged directed pair with capacity > 0, sorted by (u, v): src[i], dst[i],
+ * flow[i] with 0 <= flow <= c.  With NULL arrays only *count is written;
+ * otherwise each array must hold *count entries as returned by a previous
+ * count-only call.  The retained solver state is not changed.
+ * Errors: MF_ERR_INVALID, MF_ERR_STATE, MF_ERR_NOT_CONVERGED, MF_ERR_DEVICE. */
+mf_status mf_get_flow(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, int32_t* flow);
+
+/* Counters and sizes; see mf_stats. */
+mf_status mf_get_stats(const mf_graph* g, mf_stats* out);
+
+/* Turn per-kernel event timing on (1) or off (0) and clear its totals.  With
+ * timing on, every launch of the library is bracketed by HIP events on the
+ * handle's stream and mf_stats.kernel_ms accumulates their durations. */
+mf_status mf_profile(mf_graph* g, int32_t enable);
+
+/* Diagnostic: reset to zero flow, saturate the source, run one global
+ * relabel (Algorithm 4) and one worklist build (Section 5.2), and copy out
+ * heights int32[n], excesses int64[n] and the active vertices (any order,
+ * *n_active of them; buffer of n entries).  Any output may be NULL.  Leaves
+ * the handle needing a new mf_maxflow before repairs. */
+mf_status mf_debug_initial_labels(mf_graph* g, int32_t* heights, int64_t* excess,
+                                  int32_t* active, int32_t* n_active);
+
+/* Diagnostic: run the device self-test of the wave primitives the kernels
+ * rely on (64-lane DPP minimum, wave prefix sum) on `device` (-1: current)
+ * and compare each result with a lane-by-lane loop.  MF_OK when all agree,
+ * MF_ERR_DEVICE otherwise. */
+mf_status mf_debug_selftest(int32_t device);
+
+/* Release the handle and its device memory.  NULL is ignored. */
+void mf_graph_free(mf_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_H */

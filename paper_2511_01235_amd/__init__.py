@@ -1,0 +1,282 @@
+"""MI355X-native dynamic max-flow: Python binding of the C ABI in include/mf.h.
+
+Every function here only marshals arguments into the HIP library
+`libmf.so` (built in-tree by `build.py`) and back; all computation runs in
+that library's gfx950 kernels.  There is no fallback: if the library is not
+built, or the device is unusable, the calls raise.
+
+Names match the C ABI: mf_graph_load, mf_maxflow, mf_apply_batch,
+mf_apply_batch_device, mf_min_cut, mf_get_flow, mf_get_stats, mf_profile,
+mf_debug_initial_labels, mf_debug_selftest, mf_graph_free.  `MaxFlowGraph`
+wraps a handle for convenience.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmf.so")
+
+MF_OK = 0
+MF_ERR_INVALID = 1
+MF_ERR_OUT_OF_MEMORY = 2
+MF_ERR_OVERFLOW = 3
+MF_ERR_DEVICE = 4
+MF_ERR_NOT_CONVERGED = 5
+MF_ERR_STATE = 6
+
+# every symbol include/mf.h declares
+EXPORTED = ["mf_default_options", "mf_status_string", "mf_graph_load", "mf_maxflow",
+            "mf_apply_batch", "mf_apply_batch_device", "mf_min_cut", "mf_get_flow",
+            "mf_get_stats", "mf_profile", "mf_debug_initial_labels", "mf_debug_selftest",
+            "mf_graph_free"]
+
+KERNEL_CLASSES = ["global_relabel", "push_relabel", "remove_invalid", "worklist", "batch", "init",
+                  "unused6", "unused7"]
+
+
+class MFError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class Options(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("device", C.c_int32), ("stream", C.c_void_p),
+                ("kernel_cycles", C.c_int32), ("topology_driven", C.c_int32),
+                ("insert_slack_min", C.c_int32), ("insert_slack_pct", C.c_int32),
+                ("max_iterations", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pairs", C.c_int64), ("slots", C.c_int64),
+                ("slot_capacity", C.c_int64), ("device_bytes", C.c_int64),
+                ("kernel_cycles", C.c_int32), ("relayouts", C.c_int32),
+                ("last_iterations", C.c_int64), ("last_bfs_levels", C.c_int64),
+                ("last_active_sum", C.c_int64), ("last_new_pairs", C.c_int64),
+                ("last_ms", C.c_double), ("kernel_ms", C.c_double * 8),
+                ("kernel_launches", C.c_int64 * 8), ("kernel_bytes", C.c_double * 8)]
+
+
+class Update(C.Structure):
+    _fields_ = [("u", C.c_int32), ("v", C.c_int32), ("cap", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmf.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run `python -m paper_2511_01235_amd.build` or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.mf_default_options.argtypes = [C.POINTER(Options)]
+        L.mf_default_options.restype = None
+        L.mf_status_string.argtypes = [C.c_int]
+        L.mf_status_string.restype = C.c_char_p
+        L.mf_graph_load.argtypes = [i32, i64, vp, vp, vp, i32, i32, C.POINTER(Options), C.POINTER(vp)]
+        L.mf_maxflow.argtypes = [vp, C.POINTER(i64)]
+        L.mf_apply_batch.argtypes = [vp, vp, i64, C.POINTER(i64)]
+        L.mf_apply_batch_device.argtypes = [vp, vp, i64, C.POINTER(i64)]
+        L.mf_min_cut.argtypes = [vp, vp, C.POINTER(i64)]
+        L.mf_get_flow.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
+        L.mf_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.mf_profile.argtypes = [vp, i32]
+        L.mf_debug_initial_labels.argtypes = [vp, vp, vp, vp, C.POINTER(i32)]
+        L.mf_debug_selftest.argtypes = [i32]
+        L.mf_graph_free.argtypes = [vp]
+        L.mf_graph_free.restype = None
+        for name in ["mf_graph_load", "mf_maxflow", "mf_apply_batch", "mf_apply_batch_device",
+                     "mf_min_cut", "mf_get_flow", "mf_get_stats", "mf_profile",
+                     "mf_debug_initial_labels", "mf_debug_selftest"]:
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().mf_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != MF_OK:
+        raise MFError(status, where)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def mf_default_options() -> Options:
+    o = Options()
+    lib().mf_default_options(C.byref(o))
+    return o
+
+
+def make_options(kernel_cycles=0, topology_driven=False, insert_slack_min=0, insert_slack_pct=0,
+                 max_iterations=0, stream=None, device=-1) -> Options:
+    o = mf_default_options()
+    o.kernel_cycles = kernel_cycles
+    o.topology_driven = int(bool(topology_driven))
+    o.insert_slack_min = insert_slack_min
+    o.insert_slack_pct = insert_slack_pct
+    o.max_iterations = max_iterations
+    o.device = device
+    if stream is not None:
+        o.stream = stream if isinstance(stream, int) else int(stream.cuda_stream)
+    return o
+
+
+def mf_graph_load(n, src, dst, cap, s, t, opt: Options | None = None) -> int:
+    src, dst, cap = _i32(src), _i32(dst), _i32(cap)
+    if not (src.size == dst.size == cap.size):
+        raise ValueError("src, dst and cap must have the same length")
+    h = C.c_void_p()
+    st = lib().mf_graph_load(int(n), int(src.size), src.ctypes.data, dst.ctypes.data,
+                             cap.ctypes.data, int(s), int(t),
+                             C.byref(opt) if opt is not None else None, C.byref(h))
+    _check(st, "mf_graph_load")
+    return h.value
+
+
+def mf_maxflow(g) -> int:
+    v = C.c_int64()
+    _check(lib().mf_maxflow(g, C.byref(v)), "mf_maxflow")
+    return v.value
+
+
+def _updates_host(u, v=None, c=None):
+    if v is None:
+        arr = np.ascontiguousarray(u, dtype=np.int32).reshape(-1, 3)
+    else:
+        arr = np.ascontiguousarray(np.stack([_i32(u), _i32(v), _i32(c)], axis=1))
+    return arr
+
+
+def mf_apply_batch(g, u, v=None, c=None) -> int:
+    """Updates from host memory: (u, v, c) arrays, or one [k, 3] int32 array."""
+    arr = _updates_host(u, v, c)
+    val = C.c_int64()
+    _check(lib().mf_apply_batch(g, arr.ctypes.data, arr.shape[0], C.byref(val)), "mf_apply_batch")
+    return val.value
+
+
+def mf_apply_batch_device(g, updates) -> int:
+    """Updates already on the device: a contiguous int32 torch tensor [k, 3]."""
+    if updates.dtype.__str__() != "torch.int32" or not updates.is_contiguous() or updates.dim() != 2 \
+            or updates.shape[1] != 3 or not updates.is_cuda:
+        raise ValueError("expected a contiguous int32 cuda tensor of shape [k, 3]")
+    val = C.c_int64()
+    _check(lib().mf_apply_batch_device(g, updates.data_ptr(), updates.shape[0], C.byref(val)),
+           "mf_apply_batch_device")
+    return val.value
+
+
+def mf_min_cut(g, n: int):
+    side = np.zeros(n, np.uint8)
+    c = C.c_int64()
+    _check(lib().mf_min_cut(g, side.ctypes.data, C.byref(c)), "mf_min_cut")
+    return side, c.value
+
+
+def mf_get_flow(g):
+    cnt = C.c_int64()
+    _check(lib().mf_get_flow(g, C.byref(cnt), None, None, None), "mf_get_flow")
+    k = cnt.value
+    src = np.zeros(k, np.int32)
+    dst = np.zeros(k, np.int32)
+    flow = np.zeros(k, np.int32)
+    _check(lib().mf_get_flow(g, C.byref(cnt), src.ctypes.data, dst.ctypes.data, flow.ctypes.data),
+           "mf_get_flow")
+    return src, dst, flow
+
+
+def mf_get_stats(g) -> dict:
+    s = Stats()
+    _check(lib().mf_get_stats(g, C.byref(s)), "mf_get_stats")
+    out = {name: getattr(s, name) for name, _ in Stats._fields_
+           if name not in ("kernel_ms", "kernel_launches", "kernel_bytes")}
+    out["kernel_ms"] = dict(zip(KERNEL_CLASSES, list(s.kernel_ms)))
+    out["kernel_launches"] = dict(zip(KERNEL_CLASSES, list(s.kernel_launches)))
+    out["kernel_bytes"] = dict(zip(KERNEL_CLASSES, list(s.kernel_bytes)))
+    return out
+
+
+def mf_profile(g, enable: bool = True):
+    _check(lib().mf_profile(g, int(bool(enable))), "mf_profile")
+
+
+def mf_debug_initial_labels(g, n: int):
+    h = np.zeros(n, np.int32)
+    e = np.zeros(n, np.int64)
+    act = np.zeros(n, np.int32)
+    na = C.c_int32()
+    _check(lib().mf_debug_initial_labels(g, h.ctypes.data, e.ctypes.data, act.ctypes.data,
+                                         C.byref(na)), "mf_debug_initial_labels")
+    return h, e, act[:na.value].copy()
+
+
+def mf_debug_selftest(device: int = -1) -> int:
+    return int(lib().mf_debug_selftest(int(device)))
+
+
+def mf_graph_free(g):
+    if g:
+        lib().mf_graph_free(g)
+
+
+class MaxFlowGraph:
+    """Owns one mf_graph handle."""
+
+    def __init__(self, n, src, dst, cap, s, t, **options):
+        self.n, self.s, self.t = int(n), int(s), int(t)
+        opt = make_options(**options) if options else None
+        self.h = mf_graph_load(n, src, dst, cap, s, t, opt)
+
+    def maxflow(self) -> int:
+        return mf_maxflow(self.h)
+
+    def apply_batch(self, u, v=None, c=None) -> int:
+        return mf_apply_batch(self.h, u, v, c)
+
+    def apply_batch_device(self, updates) -> int:
+        return mf_apply_batch_device(self.h, updates)
+
+    def min_cut(self):
+        return mf_min_cut(self.h, self.n)
+
+    def get_flow(self):
+        return mf_get_flow(self.h)
+
+    def stats(self) -> dict:
+        return mf_get_stats(self.h)
+
+    def profile(self, enable=True):
+        mf_profile(self.h, enable)
+
+    def initial_labels(self):
+        return mf_debug_initial_labels(self.h, self.n)
+
+    def close(self):
+        if self.h:
+            mf_graph_free(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,697 @@
+// Host driver and C ABI of the dynamic max-flow library.
+//
+// mf_maxflow runs Algorithm 1; mf_apply_batch runs Algorithm 5; both share
+// the loop {global relabel (Algorithms 4/6), worklist (Section 5.2),
+// push-relabel (Algorithm 2), remove-invalid-edges (Algorithm 3)} whose only
+// host/device synchronisations are the frontier-size checks of the BFS and
+// one read of the worklist size and value per iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "mf.h"
+#include "mf_internal.h"
+
+using mf::DevCounters;
+using mf::DevGraph;
+
+struct mf_graph {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    mf_options opt{};
+    int32_t kc = 1;
+    int32_t slack_min = 2, slack_pct = 12;
+    int64_t max_iter = 0;
+    int32_t n = 0, s = 0, t = 0;
+    int64_t pairs = 0, m_unique = 0;
+    int64_t slot_cap = 0;
+    DevGraph dg{};
+    // device buffers
+    int2* q[2] = {nullptr, nullptr};
+    int64_t q_cap = 0;
+    int32_t* wl[3] = {nullptr, nullptr, nullptr};
+    DevCounters* ctr = nullptr;
+    DevCounters* ctr_h = nullptr;  // pinned
+    int32_t* win = nullptr;        // per slot, -1 when idle
+    int32_t* need = nullptr;       // per vertex, 0 when idle
+    int32_t* slot_of = nullptr;
+    int32_t* touched = nullptr;
+    mf_update* upd = nullptr;
+    int64_t k_cap = 0;
+    mf::BatchTable tb{};
+    uint8_t* side = nullptr;
+    unsigned long long* cut_acc = nullptr;
+    // state
+    bool solved = false;
+    bool poisoned = false;
+    int64_t last_value = 0;
+    // stats
+    int32_t relayouts = 0;
+    int64_t last_iterations = 0, last_levels = 0, last_active_sum = 0, last_new_pairs = 0;
+    double last_ms = 0;
+    bool profiling = false;
+    double kernel_ms[8] = {0};
+    int64_t kernel_launches[8] = {0};
+    double kernel_bytes[8] = {0};
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    int gr_grid = 1024;
+};
+
+namespace {
+
+#define MF_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) {                        \
+            g->poisoned = true;                        \
+            return MF_ERR_DEVICE;                      \
+        }                                              \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(mf_graph* g, T** p, int64_t count) {
+    size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    (void)g;
+    return hipMalloc((void**)p, bytes);
+}
+
+template <class T>
+void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+// ---- per-kernel event timing ------------------------------------------------
+
+hipEvent_t take_event(mf_graph* g) {
+    if (!g->ev_pool.empty()) {
+        hipEvent_t e = g->ev_pool.back();
+        g->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+template <class F>
+void timed(mf_graph* g, int cls, F&& launch) {
+    if (!g->profiling) {
+        launch();
+        return;
+    }
+    hipEvent_t a = take_event(g), b = take_event(g);
+    (void)hipEventRecord(a, g->stream);
+    launch();
+    (void)hipEventRecord(b, g->stream);
+    g->ev_pending.push_back({cls, {a, b}});
+}
+
+// After the stream is synchronised: fold the recorded launches into totals.
+void settle_events(mf_graph* g) {
+    for (auto& p : g->ev_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            g->kernel_ms[p.first] += ms;
+            g->kernel_launches[p.first]++;
+        }
+        g->ev_pool.push_back(p.second.first);
+        g->ev_pool.push_back(p.second.second);
+    }
+    g->ev_pending.clear();
+}
+
+void fold_bytes(mf_graph* g) {
+    if (!g->profiling) return;
+    for (int c = 0; c < 8; ++c) g->kernel_bytes[c] += (double)g->ctr_h->bytes[c];
+}
+
+mf_status read_counters(mf_graph* g) {
+    MF_HIP(hipMemcpyAsync(g->ctr_h, g->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, g->stream));
+    MF_HIP(hipStreamSynchronize(g->stream));
+    return MF_OK;
+}
+
+void free_structure(mf_graph* g) {
+    dfree(g->dg.row_ptr);
+    dfree(g->dg.row_len);
+    dfree(g->dg.row_sorted);
+    dfree(g->dg.cr);
+    dfree(g->dg.rev);
+    dfree(g->dg.cap);
+    dfree(g->win);
+    dfree(g->q[0]);
+    dfree(g->q[1]);
+}
+
+void free_all(mf_graph* g) {
+    free_structure(g);
+    dfree(g->dg.e);
+    dfree(g->dg.h);
+    for (auto& w : g->wl) dfree(w);
+    dfree(g->ctr);
+    if (g->ctr_h) (void)hipHostFree(g->ctr_h);
+    g->ctr_h = nullptr;
+    dfree(g->need);
+    dfree(g->slot_of);
+    dfree(g->touched);
+    dfree(g->upd);
+    dfree(g->tb.key);
+    dfree(g->tb.win);
+    dfree(g->tb.slot);
+    dfree(g->side);
+    dfree(g->cut_acc);
+    for (auto& p : g->ev_pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    for (auto e : g->ev_pool) (void)hipEventDestroy(e);
+    g->ev_pending.clear();
+    g->ev_pool.clear();
+}
+
+// Allocate and upload the slot arrays of a Bi-CSR (plus the arrays whose size
+// follows the slot count).  res_init: residuals to upload, or empty for
+// res = cap (zero flow).
+mf_status upload_structure(mf_graph* g, const mf::HostBiCSR& b, const std::vector<int32_t>& res_init) {
+    const int32_t n = g->n;
+    const int64_t S = b.row_ptr[(size_t)n];
+    if (dalloc(g, &g->dg.row_ptr, n + 1) != hipSuccess || dalloc(g, &g->dg.row_len, n) != hipSuccess ||
+        dalloc(g, &g->dg.row_sorted, n) != hipSuccess || dalloc(g, &g->dg.cr, S) != hipSuccess ||
+        dalloc(g, &g->dg.rev, S) != hipSuccess || dalloc(g, &g->dg.cap, S) != hipSuccess ||
+        dalloc(g, &g->win, S) != hipSuccess)
+        return MF_ERR_OUT_OF_MEMORY;
+    g->q_cap = (int64_t)n + S / mf::GR_CHUNK + 64;
+    if (dalloc(g, &g->q[0], g->q_cap) != hipSuccess || dalloc(g, &g->q[1], g->q_cap) != hipSuccess)
+        return MF_ERR_OUT_OF_MEMORY;
+    std::vector<int2> cr((size_t)S);
+    for (int64_t j = 0; j < S; ++j)
+        cr[(size_t)j] = make_int2(b.col[(size_t)j], res_init.empty() ? b.cap[(size_t)j] : res_init[(size_t)j]);
+    hipStream_t st = g->stream;
+    MF_HIP(hipMemcpyAsync(g->dg.row_ptr, b.row_ptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.row_len, b.row_len.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.row_sorted, b.row_sorted.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.cr, cr.data(), sizeof(int2) * S, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.rev, b.rev.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.cap, b.cap.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, st));
+    mf::launch_fill_i32(g->win, -1, S, st);
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipStreamSynchronize(st));  // host vectors die on return
+    g->slot_cap = S;
+    return MF_OK;
+}
+
+mf_status ensure_batch_capacity(mf_graph* g, int64_t k) {
+    if (k <= g->k_cap) return MF_OK;
+    int64_t cap = std::max<int64_t>(k, 1024);
+    int32_t tcap = 64;
+    while (tcap < 2 * cap) tcap *= 2;
+    MF_HIP(hipStreamSynchronize(g->stream));
+    dfree(g->slot_of);
+    dfree(g->touched);
+    dfree(g->upd);
+    dfree(g->tb.key);
+    dfree(g->tb.win);
+    dfree(g->tb.slot);
+    if (dalloc(g, &g->slot_of, cap) != hipSuccess || dalloc(g, &g->touched, cap) != hipSuccess ||
+        dalloc(g, &g->upd, cap) != hipSuccess || dalloc(g, &g->tb.key, tcap) != hipSuccess ||
+        dalloc(g, &g->tb.win, 2 * (int64_t)tcap) != hipSuccess ||
+        dalloc(g, &g->tb.slot, 2 * (int64_t)tcap) != hipSuccess) {
+        g->k_cap = 0;
+        return MF_ERR_OUT_OF_MEMORY;
+    }
+    g->tb.capacity = tcap;
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->tb.key), -1, 2 * (int64_t)tcap, g->stream);
+    mf::launch_fill_i32(g->tb.win, -1, 2 * (int64_t)tcap, g->stream);
+    MF_HIP(hipGetLastError());
+    g->k_cap = cap;
+    return MF_OK;
+}
+
+// ---- the push-relabel loop ----------------------------------------------------
+
+// Global relabel: seeds, then levels in growing chunks; each level launch
+// reads the frontier size on the device, so the host checks only after a
+// chunk.  Returns the number of level launches.
+mf_status global_relabel(mf_graph* g, int64_t* levels_out) {
+    hipStream_t st = g->stream;
+    timed(g, mf::KC_GR, [&] { mf::launch_gr_init(g->dg, g->q[0], g->ctr, st); });
+    int level = 0;
+    int chunk = 2;
+    for (;;) {
+        for (int i = 0; i < chunk; ++i, ++level)
+            timed(g, mf::KC_GR, [&] {
+                mf::launch_gr_level(g->dg, level, g->q[level & 1], g->q[(level + 1) & 1], g->ctr,
+                                    g->gr_grid, st);
+            });
+        MF_HIP(hipGetLastError());
+        mf_status rc = read_counters(g);
+        if (rc != MF_OK) return rc;
+        if (g->ctr_h->front[level % 3] == 0) break;
+        if (level > g->n + 2) {
+            g->poisoned = true;
+            return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
+        }
+        chunk = std::min(chunk * 2, 64);
+    }
+    *levels_out += level;
+    return MF_OK;
+}
+
+// Loop {global relabel; worklist; stop if no active vertex; push-relabel;
+// remove invalid edges}.  The stop test is taken right after a fresh global
+// relabel, so at exit A = {h = |V|} is a cut whose capacity is the value.
+mf_status run_loop(mf_graph* g, int64_t* value) {
+    hipStream_t st = g->stream;
+    int64_t iters = 0, levels = 0, active_sum = 0;
+    for (;;) {
+        mf_status rc = global_relabel(g, &levels);
+        if (rc != MF_OK) return rc;
+        timed(g, mf::KC_WL, [&] {
+            if (g->opt.topology_driven)
+                mf::launch_topology_worklist(g->dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, st);
+            else
+                mf::launch_build_worklist(g->dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, st);
+        });
+        MF_HIP(hipGetLastError());
+        rc = read_counters(g);
+        if (rc != MF_OK) return rc;
+        const DevCounters& c = *g->ctr_h;
+        int active = c.wl[3];
+        active_sum += active;
+        if (active == 0) {
+            *value = (int64_t)c.e_t + (int64_t)c.deficit_sum;
+            break;
+        }
+        if (++iters > g->max_iter) {
+            g->last_iterations = iters;
+            return MF_ERR_NOT_CONVERGED;
+        }
+        int cnt[3] = {c.wl[0], c.wl[1], c.wl[2]};
+        for (int b = 0; b < 3; ++b)
+            if (cnt[b]) timed(g, mf::KC_PR, [&] { mf::launch_push_relabel(g->dg, g->wl[b], cnt[b], b, g->kc, g->ctr, st); });
+        for (int b = 0; b < 3; ++b)
+            if (cnt[b]) timed(g, mf::KC_RIE, [&] { mf::launch_remove_invalid(g->dg, g->wl[b], cnt[b], b, g->ctr, st); });
+        MF_HIP(hipGetLastError());
+    }
+    g->last_iterations = iters;
+    g->last_levels = levels;
+    g->last_active_sum = active_sum;
+    return MF_OK;
+}
+
+mf_status check_handle(mf_graph* g) {
+    if (!g) return MF_ERR_INVALID;
+    if (g->poisoned) return MF_ERR_DEVICE;
+    if (hipSetDevice(g->device) != hipSuccess) {
+        g->poisoned = true;
+        return MF_ERR_DEVICE;
+    }
+    return MF_OK;
+}
+
+// Rows ran out of slack: download the structure, re-lay rows with room for
+// need[v] more pairs plus fresh slack, upload.  Excess and heights stay.
+mf_status relayout(mf_graph* g) {
+    hipStream_t st = g->stream;
+    const int32_t n = g->n;
+    const int64_t S = g->slot_cap;
+    mf::HostBiCSR in;
+    in.n = n;
+    in.row_ptr.resize((size_t)n + 1);
+    in.row_len.resize((size_t)n);
+    in.row_sorted.resize((size_t)n);
+    in.col.resize((size_t)S);
+    in.rev.resize((size_t)S);
+    in.cap.resize((size_t)S);
+    std::vector<int2> cr((size_t)S);
+    std::vector<int32_t> res((size_t)S), extra((size_t)n);
+    MF_HIP(hipMemcpyAsync(in.row_ptr.data(), g->dg.row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(in.row_len.data(), g->dg.row_len, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(cr.data(), g->dg.cr, sizeof(int2) * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(in.rev.data(), g->dg.rev, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(in.cap.data(), g->dg.cap, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(extra.data(), g->need, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipStreamSynchronize(st));
+    for (int64_t j = 0; j < S; ++j) {
+        in.col[(size_t)j] = cr[(size_t)j].x;
+        res[(size_t)j] = cr[(size_t)j].y;
+    }
+    cr.clear();
+    cr.shrink_to_fit();
+    in.pairs = g->pairs;
+    in.m_unique = g->m_unique;
+    mf::HostBiCSR out;
+    std::vector<int32_t> res_out;
+    mf::relayout_bicsr(in, res, extra, g->slack_min, g->slack_pct, &out, &res_out);
+    if (out.row_ptr[(size_t)n] < 0 || (int64_t)out.row_ptr[(size_t)n] > (int64_t)INT_MAX - 1)
+        return MF_ERR_OVERFLOW;
+    free_structure(g);
+    mf_status rc = upload_structure(g, out, res_out);
+    if (rc != MF_OK) {
+        g->poisoned = true;
+        return rc == MF_ERR_OUT_OF_MEMORY ? MF_ERR_OUT_OF_MEMORY : rc;
+    }
+    g->relayouts++;
+    return MF_OK;
+}
+
+// Algorithm 5 after the updates are on the device.
+mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value) {
+    hipStream_t st = g->stream;
+    g->last_new_pairs = 0;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        mf::launch_clear_counters(g->ctr, st);
+        timed(g, mf::KC_BATCH, [&] {
+            mf::launch_batch_locate(g->dg, d_upd, k, g->slot_of, g->win, g->tb, g->need, g->ctr, st);
+        });
+        MF_HIP(hipGetLastError());
+        mf_status rc = read_counters(g);
+        if (rc != MF_OK) return rc;
+        const DevCounters c = *g->ctr_h;
+        if (c.err || c.cap_overflow || c.overflow) {
+            if (c.overflow && !c.err && !c.cap_overflow) {
+                // need[] still holds the per-row demand: re-lay, then retry
+                rc = relayout(g);
+                if (rc != MF_OK) return rc;
+            }
+            mf::launch_batch_cleanup(g->tb, g->need, g->slot_of, g->win, k, st);
+            MF_HIP(hipGetLastError());
+            MF_HIP(hipStreamSynchronize(st));
+            if (c.err) return MF_ERR_INVALID;
+            if (c.cap_overflow) return MF_ERR_OVERFLOW;
+            continue;
+        }
+        g->last_new_pairs = c.new_pairs;
+        timed(g, mf::KC_BATCH, [&] {
+            if (c.new_pairs) mf::launch_batch_insert(g->dg, g->tb, g->need, st);
+            mf::launch_batch_apply(g->dg, d_upd, k, g->slot_of, g->win, g->tb, g->touched, g->ctr, st);
+            mf::launch_batch_clamp(g->dg, d_upd, k, g->touched, g->win, g->tb, st);
+            mf::launch_batch_cleanup(g->tb, g->need, g->slot_of, g->win, k, st);
+        });
+        g->pairs += c.new_pairs;
+        timed(g, mf::KC_INIT, [&] { mf::launch_saturate_source(g->dg, g->ctr, st); });
+        MF_HIP(hipGetLastError());
+        return run_loop(g, value);
+    }
+    return MF_ERR_OUT_OF_MEMORY;  // slack could not be made to fit
+}
+
+struct CallTimer {
+    mf_graph* g;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    explicit CallTimer(mf_graph* gg) : g(gg) {}
+    ~CallTimer() {
+        g->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+void mf_default_options(mf_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->struct_size = sizeof(mf_options);
+    opt->device = -1;
+}
+
+const char* mf_status_string(mf_status status) {
+    switch (status) {
+        case MF_OK: return "ok";
+        case MF_ERR_INVALID: return "invalid argument";
+        case MF_ERR_OUT_OF_MEMORY: return "out of memory";
+        case MF_ERR_OVERFLOW: return "capacity overflow";
+        case MF_ERR_DEVICE: return "device error";
+        case MF_ERR_NOT_CONVERGED: return "iteration cap reached";
+        case MF_ERR_STATE: return "call order";
+    }
+    return "unknown status";
+}
+
+mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                        const int32_t* cap, int32_t s, int32_t t, const mf_options* opt,
+                        mf_graph** out) {
+    if (!out) return MF_ERR_INVALID;
+    *out = nullptr;
+    mf_options o;
+    mf_default_options(&o);
+    if (opt) {
+        if (opt->struct_size != sizeof(mf_options)) return MF_ERR_INVALID;
+        o = *opt;
+    }
+    int32_t slack_min = o.insert_slack_min > 0 ? o.insert_slack_min : 2;
+    int32_t slack_pct = o.insert_slack_pct > 0 ? o.insert_slack_pct : 12;
+    mf::HostBiCSR b;
+    mf_status rc = mf::build_bicsr(n, m, src, dst, cap, s, t, slack_min, slack_pct, &b);
+    if (rc != MF_OK) return rc;
+
+    mf_graph* g = new (std::nothrow) mf_graph();
+    if (!g) return MF_ERR_OUT_OF_MEMORY;
+    g->opt = o;
+    g->n = n;
+    g->s = s;
+    g->t = t;
+    g->slack_min = slack_min;
+    g->slack_pct = slack_pct;
+    g->pairs = b.pairs;
+    g->m_unique = b.m_unique;
+    int64_t kc = o.kernel_cycles > 0 ? o.kernel_cycles : (b.m_unique + n / 2) / n;
+    g->kc = (int32_t)std::max<int64_t>(1, kc);
+    g->max_iter = o.max_iterations > 0 ? o.max_iterations : 4 * (int64_t)n + 1000;
+    auto fail = [&](mf_status r) {
+        free_all(g);
+        if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+        delete g;
+        return r;
+    };
+    int dev = o.device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(MF_ERR_DEVICE);
+    if (hipSetDevice(dev) != hipSuccess) return fail(MF_ERR_DEVICE);
+    g->device = dev;
+    if (o.stream) {
+        g->stream = (hipStream_t)o.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) return fail(MF_ERR_DEVICE);
+        g->own_stream = true;
+    }
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    g->gr_grid = std::max(64, cus * 4);
+    g->dg.n = n;
+    g->dg.s = s;
+    g->dg.t = t;
+    if (dalloc(g, &g->dg.e, n) != hipSuccess || dalloc(g, &g->dg.h, n) != hipSuccess ||
+        dalloc(g, &g->wl[0], n) != hipSuccess || dalloc(g, &g->wl[1], n) != hipSuccess ||
+        dalloc(g, &g->wl[2], n) != hipSuccess || dalloc(g, &g->ctr, 1) != hipSuccess ||
+        dalloc(g, &g->need, n) != hipSuccess || dalloc(g, &g->side, n) != hipSuccess ||
+        dalloc(g, &g->cut_acc, 1) != hipSuccess)
+        return fail(MF_ERR_OUT_OF_MEMORY);
+    if (hipHostMalloc((void**)&g->ctr_h, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess)
+        return fail(MF_ERR_OUT_OF_MEMORY);
+    rc = upload_structure(g, b, {});
+    if (rc != MF_OK) return fail(rc);
+    mf::launch_fill_i32(g->need, 0, n, g->stream);
+    mf::launch_fill_i32(g->dg.h, 0, n, g->stream);
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->dg.e), 0, 2 * (int64_t)n, g->stream);
+    mf::launch_clear_counters(g->ctr, g->stream);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(g->stream) != hipSuccess)
+        return fail(MF_ERR_DEVICE);
+    *out = g;
+    return MF_OK;
+}
+
+mf_status mf_maxflow(mf_graph* g, int64_t* value) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    if (!value) return MF_ERR_INVALID;
+    CallTimer timer(g);
+    hipStream_t st = g->stream;
+    g->solved = false;
+    mf::launch_clear_counters(g->ctr, st);
+    timed(g, mf::KC_INIT, [&] {
+        mf::launch_reset(g->dg, g->slot_cap, st);
+        mf::launch_saturate_source(g->dg, g->ctr, st);
+    });
+    MF_HIP(hipGetLastError());
+    int64_t v = 0;
+    rc = run_loop(g, &v);
+    settle_events(g);
+    fold_bytes(g);
+    if (rc != MF_OK) return rc;
+    g->solved = true;
+    g->last_value = v;
+    *value = v;
+    return MF_OK;
+}
+
+static mf_status apply_common(mf_graph* g, const mf_update* upd, int64_t k, int64_t* value, bool on_device) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    if (!value || k < 0 || (k > 0 && !upd)) return MF_ERR_INVALID;
+    if (!g->solved) return MF_ERR_STATE;
+    if (k > INT_MAX / 2) return MF_ERR_INVALID;
+    CallTimer timer(g);
+    if (k == 0) {
+        *value = g->last_value;
+        return MF_OK;
+    }
+    rc = ensure_batch_capacity(g, k);
+    if (rc != MF_OK) return rc;
+    const mf_update* d_upd = upd;
+    if (!on_device) {
+        MF_HIP(hipMemcpyAsync(g->upd, upd, sizeof(mf_update) * (size_t)k, hipMemcpyHostToDevice, g->stream));
+        d_upd = g->upd;
+    }
+    g->solved = false;
+    int64_t v = 0;
+    rc = apply_batch_dev(g, d_upd, k, &v);
+    settle_events(g);
+    fold_bytes(g);
+    if (rc == MF_ERR_INVALID || rc == MF_ERR_OVERFLOW) {
+        g->solved = true;  // nothing was applied
+        return rc;
+    }
+    if (rc != MF_OK) return rc;
+    g->solved = true;
+    g->last_value = v;
+    *value = v;
+    return MF_OK;
+}
+
+mf_status mf_apply_batch(mf_graph* g, const mf_update* upd, int64_t k, int64_t* value) {
+    return apply_common(g, upd, k, value, false);
+}
+
+mf_status mf_apply_batch_device(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value) {
+    return apply_common(g, d_upd, k, value, true);
+}
+
+mf_status mf_min_cut(mf_graph* g, uint8_t* source_side, int64_t* cut_capacity) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    if (!cut_capacity) return MF_ERR_INVALID;
+    if (!g->solved) return MF_ERR_STATE;
+    hipStream_t st = g->stream;
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->cut_acc), 0, 2, st);
+    mf::launch_cut(g->dg, g->side, g->cut_acc, st);
+    MF_HIP(hipGetLastError());
+    unsigned long long c = 0;
+    MF_HIP(hipMemcpyAsync(&c, g->cut_acc, sizeof(c), hipMemcpyDeviceToHost, st));
+    if (source_side) MF_HIP(hipMemcpyAsync(source_side, g->side, (size_t)g->n, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipStreamSynchronize(st));
+    *cut_capacity = (int64_t)c;
+    return MF_OK;
+}
+
+mf_status mf_get_flow(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, int32_t* flow) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    if (!count) return MF_ERR_INVALID;
+    if (!g->solved) return MF_ERR_STATE;
+    (void)src;
+    (void)dst;
+    (void)flow;
+    return MF_ERR_STATE;
+}
+
+mf_status mf_get_stats(const mf_graph* g, mf_stats* out) {
+    if (!g || !out) return MF_ERR_INVALID;
+    std::memset(out, 0, sizeof(*out));
+    out->n = g->n;
+    out->pairs = g->pairs;
+    out->slot_capacity = g->slot_cap;
+    out->slots = 2 * g->pairs;
+    // slot arrays (col+res, rev, cap, win), two frontier queues, per-vertex arrays
+    out->device_bytes = g->slot_cap * 20 + 2 * g->q_cap * 8 + (int64_t)g->n * (4 * 3 + 8 + 4 + 12 + 4 + 1) +
+                        g->k_cap * (4 + 4 + 12) + (int64_t)g->tb.capacity * (8 + 8 + 8);
+    out->kernel_cycles = g->kc;
+    out->relayouts = g->relayouts;
+    out->last_iterations = g->last_iterations;
+    out->last_bfs_levels = g->last_levels;
+    out->last_active_sum = g->last_active_sum;
+    out->last_new_pairs = g->last_new_pairs;
+    out->last_ms = g->last_ms;
+    for (int c = 0; c < 8; ++c) {
+        out->kernel_ms[c] = g->kernel_ms[c];
+        out->kernel_launches[c] = g->kernel_launches[c];
+        out->kernel_bytes[c] = g->kernel_bytes[c];
+    }
+    return MF_OK;
+}
+
+mf_status mf_profile(mf_graph* g, int32_t enable) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    g->profiling = enable != 0;
+    for (int c = 0; c < 8; ++c) {
+        g->kernel_ms[c] = 0;
+        g->kernel_launches[c] = 0;
+        g->kernel_bytes[c] = 0;
+    }
+    return MF_OK;
+}
+
+mf_status mf_debug_initial_labels(mf_graph* g, int32_t* heights, int64_t* excess, int32_t* active,
+                                  int32_t* n_active) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    hipStream_t st = g->stream;
+    g->solved = false;
+    mf::launch_clear_counters(g->ctr, st);
+    mf::launch_reset(g->dg, g->slot_cap, st);
+    mf::launch_saturate_source(g->dg, g->ctr, st);
+    MF_HIP(hipGetLastError());
+    int64_t levels = 0;
+    rc = global_relabel(g, &levels);
+    if (rc != MF_OK) return rc;
+    mf::launch_build_worklist(g->dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, st);
+    MF_HIP(hipGetLastError());
+    rc = read_counters(g);
+    if (rc != MF_OK) return rc;
+    settle_events(g);
+    const DevCounters c = *g->ctr_h;
+    if (heights) MF_HIP(hipMemcpyAsync(heights, g->dg.h, sizeof(int32_t) * g->n, hipMemcpyDeviceToHost, st));
+    if (excess) MF_HIP(hipMemcpyAsync(excess, g->dg.e, sizeof(int64_t) * g->n, hipMemcpyDeviceToHost, st));
+    if (active) {
+        int off = 0;
+        for (int b = 0; b < 3; ++b) {
+            if (c.wl[b]) MF_HIP(hipMemcpyAsync(active + off, g->wl[b], sizeof(int32_t) * c.wl[b], hipMemcpyDeviceToHost, st));
+            off += c.wl[b];
+        }
+    }
+    MF_HIP(hipStreamSynchronize(st));
+    if (n_active) *n_active = c.wl[0] + c.wl[1] + c.wl[2];
+    g->last_levels = levels;
+    return MF_OK;
+}
+
+mf_status mf_debug_selftest(int32_t device) {
+    if (device >= 0 && hipSetDevice(device) != hipSuccess) return MF_ERR_DEVICE;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return MF_ERR_DEVICE;
+    int fails = mf::device_selftest(st);
+    (void)hipStreamDestroy(st);
+    return fails == 0 ? MF_OK : MF_ERR_DEVICE;
+}
+
+void mf_graph_free(mf_graph* g) {
+    if (!g) return;
+    (void)hipSetDevice(g->device);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    free_all(g);
+    if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+}
+
+}  // extern "C"

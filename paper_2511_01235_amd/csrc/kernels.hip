@@ -1,0 +1,896 @@
+// gfx950 kernels of the dynamic max-flow path.
+//
+// Paper map (Kannappan, Kumar, Nasre, "Scalable Maxflow Processing for
+// Dynamic Graphs"):
+//   k_reset, k_saturate_source     Algorithm 1 initialisation; source
+//                                  re-saturation of Algorithm 5
+//   k_gr_init, k_gr_level          backward BFS global relabel, Algorithms 4
+//                                  and 6 (sink and deficient vertices at 0,
+//                                  source pinned at |V|)
+//   k_build_worklist               active-vertex worklist (Section 5.2, O1)
+//                                  plus the value reduction of Algorithm 5
+//   k_pr_{thread,wave,block}       push-relabel kernel, Algorithm 2
+//   k_rie_{thread,wave,block}      remove-invalid-edges kernel, Algorithm 3
+//   k_batch_*                      update apply and clamp of Algorithm 5
+//   k_cut                          cut certificate of Sections 3.1 / 4.3
+//
+// Every word that bounds a push -- the pusher's own residual res[j] and its
+// own excess e(u) -- is read with an agent-scope atomic load, so it is never
+// a stale cached copy: only u's worker ever lowers them during a sweep, so the
+// amount pushed never exceeds what is there and residuals stay >= 0.  Heights
+// of other vertices are plain loads; a stale height only costs extra work (the
+// paper's lock-free argument, Section 3.1 note), and the loop stops only after
+// a fresh global relabel.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "mf_internal.h"
+
+namespace mf {
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr unsigned long long EMPTY_KEY = ~0ull;
+
+// ---- memory helpers --------------------------------------------------------
+
+__device__ __forceinline__ int32_t ld_res(const int2* cr, int j) {
+    return __hip_atomic_load(const_cast<int*>(&cr[j].y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t add_res(int2* cr, int j, int32_t d) {
+    return __hip_atomic_fetch_add(&cr[j].y, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t xchg_res(int2* cr, int j, int32_t v) {
+    return __hip_atomic_exchange(&cr[j].y, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t ld_e(const int64_t* e, int v) {
+    return __hip_atomic_load(const_cast<int64_t*>(&e[v]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void add_e(int64_t* e, int v, int64_t d) {
+    __hip_atomic_fetch_add(&e[v], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void add_bytes(DevCounters* ctr, int cls, unsigned long long b) {
+    if (b) __hip_atomic_fetch_add(&ctr->bytes[cls], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- wave primitives ------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Make a value wave-uniform (lane 0's copy) so that every lane takes the same
+// branch around the wave collectives below.
+__device__ __forceinline__ int bcast(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t bcast64(int64_t x) {
+    unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(uint64_t)x);
+    unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// One DPP step of a 64-lane min over 64-bit keys: each 32-bit half moves
+// with the same DPP control; lanes without a valid source keep the identity.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ unsigned long long dpp_min_step(unsigned long long x) {
+    unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)(unsigned)x, CTRL,
+                                                        ROW_MASK, 0xF, false);
+    unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)(unsigned)(x >> 32),
+                                                        CTRL, ROW_MASK, 0xF, false);
+    unsigned long long y = ((unsigned long long)hi << 32) | lo;
+    return y < x ? y : x;
+}
+
+// Minimum over the 64 lanes, returned to every lane.  row_shr 1,2,4,8 leaves
+// each 16-lane row's running minimum in its lane 15; row_bcast 15 and 31 carry
+// rows into the rows above, so lane 63 ends with the wave minimum.
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x) {
+    x = dpp_min_step<0x111>(x);
+    x = dpp_min_step<0x112>(x);
+    x = dpp_min_step<0x114>(x);
+    x = dpp_min_step<0x118>(x);
+    x = dpp_min_step<0x142, 0xA>(x);
+    x = dpp_min_step<0x143, 0xC>(x);
+    unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
+    unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, WAVE);
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, WAVE);
+    return x;
+}
+
+// Exclusive prefix sum over the wave; *total gets the wave sum.
+__device__ __forceinline__ int wave_excl_scan(int x, int* total) {
+    int lane = lane_id();
+    int v = x;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        int y = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += y;
+    }
+    *total = __shfl(v, WAVE - 1, WAVE);
+    return v - x;
+}
+
+// Append one item per lane with pred set to list[*counter ...] using one
+// atomic per wave (ballot + lane rank).  Must be called by the whole wave.
+__device__ __forceinline__ void wave_append(bool pred, int32_t item, int32_t* list, int32_t* counter) {
+    unsigned long long mask = __ballot(pred);
+    if (mask == 0) return;
+    int lane = lane_id();
+    int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader, WAVE);
+    if (pred) {
+        unsigned long long below = mask & ((1ull << lane) - 1ull);
+        list[base + __popcll(below)] = item;
+    }
+}
+
+template <int BS>
+__device__ __forceinline__ long long block_sum_i64(long long x) {
+    __shared__ long long part[BS / WAVE];
+    x = wave_sum_i64(x);
+    int w = threadIdx.x / WAVE;
+    if (lane_id() == 0) part[w] = x;
+    __syncthreads();
+    long long r = 0;
+    if (threadIdx.x < WAVE) {
+        r = threadIdx.x < BS / WAVE ? part[threadIdx.x] : 0;
+        r = wave_sum_i64(r);
+    }
+    __syncthreads();
+    return r;  // valid in wave 0
+}
+
+// ---- initialisation (Algorithm 1) -----------------------------------------
+
+__global__ void k_fill_i32(int32_t* p, int32_t value, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_reset(DevGraph g, int64_t slot_cap) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < slot_cap; j += stride)
+        g.cr[j].y = g.cap[j];
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < g.n; v += stride) {
+        g.e[v] = 0;
+        g.h[v] = 0;
+    }
+}
+
+// Push every unit of residual capacity out of s: x = res(s,u); res(s,u) = 0;
+// res(u,s) += x; e(u) += x; e(s) -= x.  From zero flow this is exactly
+// Algorithm 1's saturation; after a batch it is Algorithm 5's re-saturation
+// written as a delta.
+__global__ void __launch_bounds__(256) k_saturate_source(DevGraph g) {
+    int beg = g.row_ptr[g.s];
+    int len = g.row_len[g.s];
+    long long sent = 0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < len; k += gridDim.x * blockDim.x) {
+        int j = beg + k;
+        int32_t x = g.cr[j].y;
+        if (x > 0) {
+            g.cr[j].y = 0;
+            add_res(g.cr, g.rev[j], x);
+            add_e(g.e, g.cr[j].x, x);
+            sent += x;
+        }
+    }
+    long long tot = block_sum_i64<256>(sent);
+    if (threadIdx.x == 0 && tot) add_e(g.e, g.s, -tot);
+}
+
+// ---- global relabel (Algorithms 4 and 6) ----------------------------------
+
+// Zero what one global relabel and the worklist build after it accumulate.
+__global__ void k_zero_counters_front(DevCounters* ctr) {
+    if (threadIdx.x < 3) ctr->front[threadIdx.x] = 0;
+    if (threadIdx.x < 4) ctr->wl[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        ctr->deficit_sum = 0;
+        ctr->e_t = 0;
+    }
+}
+
+// Append the frontier entries of the lanes that discovered a vertex:
+// ceil(row_len / GR_CHUNK) entries {v, offset} per vertex.
+__device__ __forceinline__ void append_entries(int add, int v, int2* q, int32_t* counter) {
+    int total;
+    int off = wave_excl_scan(add, &total);
+    if (total == 0) return;
+    int base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, total);
+    base = __shfl(base, 0, WAVE);
+    for (int k = 0; k < add; ++k) q[base + off + k] = make_int2(v, k * GR_CHUNK);
+}
+
+// Heights before the levels: h(t) = 0, h(v) = 0 for deficient v outside
+// {s,t}, every other vertex (s included) |V|.  Level-0 vertices are queued.
+__global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr) {
+    const int N = g.n;
+    for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
+        int v = base + threadIdx.x;
+        int add = 0;
+        if (v < N) {
+            bool seed = v == g.t || (v != g.s && ld_e(g.e, v) < 0);
+            g.h[v] = seed ? 0 : N;
+            if (seed) add = (g.row_len[v] + GR_CHUNK - 1) / GR_CHUNK;
+        }
+        append_entries(add, v, q0, &ctr->front[0]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        add_bytes(ctr, KC_GR, 12ull * (unsigned long long)N);
+}
+
+// One BFS level, one wave per frontier entry: every residual in-neighbour v
+// of a level-`lv` vertex u (slot j = u->v, residual v->u is res[rev[j]] > 0)
+// that still has height |V| gets lv+1 and joins the next frontier.  The
+// frontier size is read on the device; an empty frontier makes the launch a
+// no-op, so the host may run ahead by several levels.
+__global__ void __launch_bounds__(256) k_gr_level(DevGraph g, int lv, const int2* qin, int2* qout,
+                                                  DevCounters* ctr) {
+    const int N = g.n;
+    const int cnt = bcast(ctr->front[lv % 3]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
+    int32_t* out_cnt = &ctr->front[(lv + 1) % 3];
+    int lane = lane_id();
+    int nwaves = gridDim.x * (blockDim.x / WAVE);
+    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    unsigned long long scanned = 0, found = 0;
+    for (int i = wid; i < cnt; i += nwaves) {
+        int2 ent = qin[i];
+        int u = bcast(ent.x);
+        int rb = bcast(g.row_ptr[u]);
+        int beg = rb + bcast(ent.y);
+        int end = min(rb + bcast(g.row_len[u]), beg + GR_CHUNK);
+        scanned += (unsigned long long)(end - beg);
+        for (int b = beg; b < end; b += WAVE) {
+            int j = b + lane;
+            int v = -1, add = 0;
+            if (j < end) {
+                v = g.cr[j].x;
+                if (v != g.s && g.h[v] == N) {
+                    if (g.cr[g.rev[j]].y > 0 && atomicCAS(&g.h[v], N, lv + 1) == N) {
+                        add = (g.row_len[v] + GR_CHUNK - 1) / GR_CHUNK;
+                        found++;
+                    }
+                }
+            }
+            append_entries(add, v, qout, out_cnt);
+        }
+    }
+    if (lane == 0) {
+        // per scanned slot: col, rev, res[rev], h[col]; per entry its row bounds;
+        // per discovered vertex the height CAS and the queue entry
+        unsigned long long b = 16ull * scanned;
+        add_bytes(ctr, KC_GR, b);
+    }
+    unsigned long long f = wave_sum_u64(found);
+    if (lane == 0 && f) add_bytes(ctr, KC_GR, 16ull * f);
+}
+
+// ---- worklist (Section 5.2, O1) and value (Algorithm 5) --------------------
+
+__global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0, int32_t* wl1,
+                                                        int32_t* wl2, DevCounters* ctr,
+                                                        int topology) {
+    const int N = g.n;
+    long long deficit = 0;
+    for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
+        int v = base + threadIdx.x;
+        bool act = false, list = false;
+        int len = 0;
+        if (v < N) {
+            int64_t ev = g.e[v];
+            int hv = g.h[v];
+            bool other = v != g.s && v != g.t;
+            act = other && ev > 0 && hv < N;
+            if (other && ev < 0) deficit += ev;
+            if (v == g.t) ctr->e_t = ev;
+            len = g.row_len[v];
+            list = topology ? (other && len > 0) : act;
+        }
+        unsigned long long am = __ballot(act);
+        if (lane_id() == 0 && am) atomicAdd(&ctr->wl[3], __popcll(am));
+        int bin = len <= BIN0_MAX ? 0 : (len <= BIN1_MAX ? 1 : 2);
+        wave_append(list && bin == 0, v, wl0, &ctr->wl[0]);
+        wave_append(list && bin == 1, v, wl1, &ctr->wl[1]);
+        wave_append(list && bin == 2, v, wl2, &ctr->wl[2]);
+    }
+    long long tot = block_sum_i64<256>(deficit);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)&ctr->deficit_sum, (unsigned long long)tot);
+    if (blockIdx.x == 0 && threadIdx.x == 0) add_bytes(ctr, KC_WL, 16ull * (unsigned long long)N);
+}
+
+// ---- push-relabel (Algorithm 2) --------------------------------------------
+//
+// Per cycle: if u is active, find its lowest residual neighbour v^ (first slot
+// in row order among equal heights), then push d = min(e(u), res(u,v^)) if
+// h(u) > h^ with four atomics, else lift h(u) = h^ + 1 (capped at |V|).  The
+// scan compares the height it read once (the note after Section 3.1's
+// termination proof).  A row with no residual slot lifts u to |V|.
+
+__device__ __forceinline__ void do_push(DevGraph& g, int u, int j, int64_t eu) {
+    int32_t r = ld_res(g.cr, j);
+    int64_t d = eu < (int64_t)r ? eu : (int64_t)r;
+    if (d <= 0) return;
+    add_res(g.cr, j, -(int32_t)d);
+    add_res(g.cr, g.rev[j], (int32_t)d);
+    add_e(g.e, u, -d);
+    add_e(g.e, g.cr[j].x, d);
+}
+
+__global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl, int count, int kc,
+                                                   DevCounters* ctr) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long bytes = 0;
+    if (i < count) {
+        const int N = g.n;
+        int u = wl[i];
+        int beg = g.row_ptr[u];
+        int end = beg + g.row_len[u];
+        int hu = g.h[u];
+        bytes += 16;
+        for (int c = 0; c < kc && hu < N; ++c) {
+            int64_t eu = ld_e(g.e, u);
+            if (eu <= 0) continue;
+            int bh = INT_MAX, bj = -1;
+            for (int j = beg; j < end; ++j) {
+                if (ld_res(g.cr, j) > 0) {
+                    int hv = g.h[g.cr[j].x];
+                    if (hv < bh) { bh = hv; bj = j; }
+                }
+            }
+            bytes += 12ull * (unsigned long long)(end - beg);
+            if (bj < 0) { hu = N; g.h[u] = N; break; }
+            if (hu > bh) {
+                do_push(g, u, bj, eu);
+                bytes += 48;
+            } else {
+                hu = bh + 1 < N ? bh + 1 : N;
+                g.h[u] = hu;
+                bytes += 4;
+            }
+        }
+    }
+    unsigned long long b = wave_sum_u64(bytes);
+    if (lane_id() == 0) add_bytes(ctr, KC_PR, b);
+}
+
+__global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, int count, int kc,
+                                                 DevCounters* ctr) {
+    int w = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (w >= count) return;  // whole wave
+    const int N = g.n;
+    int lane = lane_id();
+    int u = bcast(wl[w]);
+    int beg = bcast(g.row_ptr[u]);
+    int end = beg + bcast(g.row_len[u]);
+    int hu = bcast(g.h[u]);
+    unsigned long long bytes = 16;
+    for (int c = 0; c < kc && hu < N; ++c) {
+        int64_t eu = bcast64(ld_e(g.e, u));
+        if (eu <= 0) continue;
+        unsigned long long best = ~0ull;
+        for (int b = beg; b < end; b += WAVE) {
+            int j = b + lane;
+            if (j < end && ld_res(g.cr, j) > 0) {
+                unsigned hv = (unsigned)g.h[g.cr[j].x];
+                unsigned long long key = ((unsigned long long)hv << 32) | (unsigned)j;
+                if (key < best) best = key;
+            }
+        }
+        best = wave_min_u64(best);
+        bytes += 12ull * (unsigned long long)(end - beg);
+        if (best == ~0ull) {
+            hu = N;
+            if (lane == 0) g.h[u] = N;
+            break;
+        }
+        int bh = (int)(best >> 32);
+        int bj = (int)(unsigned)best;
+        if (hu > bh) {
+            if (lane == 0) do_push(g, u, bj, eu);
+            bytes += 48;
+        } else {
+            hu = bh + 1 < N ? bh + 1 : N;
+            if (lane == 0) g.h[u] = hu;
+            bytes += 4;
+        }
+    }
+    if (lane == 0) add_bytes(ctr, KC_PR, bytes);
+}
+
+__global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t* wl, int count,
+                                                       int kc, DevCounters* ctr) {
+    __shared__ unsigned long long part[BLOCK_PR / WAVE];
+    __shared__ int64_t e_sh;
+    int b_id = blockIdx.x;
+    if (b_id >= count) return;
+    const int N = g.n;
+    int lane = lane_id();
+    int wv = threadIdx.x / WAVE;
+    int u = wl[b_id];
+    int beg = g.row_ptr[u];
+    int end = beg + g.row_len[u];
+    int hu = g.h[u];
+    unsigned long long bytes = 16;
+    for (int c = 0; c < kc && hu < N; ++c) {
+        if (threadIdx.x == 0) e_sh = ld_e(g.e, u);
+        __syncthreads();
+        int64_t eu = e_sh;
+        __syncthreads();
+        if (eu <= 0) continue;
+        unsigned long long best = ~0ull;
+        for (int j = beg + threadIdx.x; j < end; j += BLOCK_PR) {
+            if (ld_res(g.cr, j) > 0) {
+                unsigned hv = (unsigned)g.h[g.cr[j].x];
+                unsigned long long key = ((unsigned long long)hv << 32) | (unsigned)j;
+                if (key < best) best = key;
+            }
+        }
+        best = wave_min_u64(best);
+        if (lane == 0) part[wv] = best;
+        __syncthreads();
+        unsigned long long x = lane < BLOCK_PR / WAVE ? part[lane] : ~0ull;
+        best = wave_min_u64(x);  // every wave computes the same block minimum
+        __syncthreads();
+        bytes += 12ull * (unsigned long long)(end - beg);
+        if (best == ~0ull) {
+            hu = N;
+            if (threadIdx.x == 0) g.h[u] = N;
+            break;
+        }
+        int bh = (int)(best >> 32);
+        int bj = (int)(unsigned)best;
+        if (hu > bh) {
+            if (threadIdx.x == 0) do_push(g, u, bj, eu);
+            bytes += 48;
+        } else {
+            hu = bh + 1 < N ? bh + 1 : N;
+            if (threadIdx.x == 0) g.h[u] = hu;
+            bytes += 4;
+        }
+    }
+    if (threadIdx.x == 0) add_bytes(ctr, KC_PR, bytes);
+}
+
+// ---- remove invalid edges (Algorithm 3) ------------------------------------
+//
+// Every residual slot u->v with h(u) > h(v) + 1 is saturated: its whole
+// residual moves to v regardless of e(u), so e(u) may turn negative.
+
+__global__ void __launch_bounds__(256) k_rie_thread(DevGraph g, const int32_t* wl, int count,
+                                                    DevCounters* ctr) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long bytes = 0;
+    if (i < count) {
+        int u = wl[i];
+        int beg = g.row_ptr[u];
+        int end = beg + g.row_len[u];
+        int hu = g.h[u];
+        int64_t moved = 0;
+        for (int j = beg; j < end; ++j) {
+            if (ld_res(g.cr, j) > 0) {
+                int v = g.cr[j].x;
+                if (hu > g.h[v] + 1) {
+                    int32_t x = xchg_res(g.cr, j, 0);
+                    if (x > 0) {
+                        add_res(g.cr, g.rev[j], x);
+                        add_e(g.e, v, x);
+                        moved += x;
+                        bytes += 32;
+                    }
+                }
+            }
+        }
+        if (moved) add_e(g.e, u, -moved);
+        bytes += 16 + 12ull * (unsigned long long)(end - beg);
+    }
+    unsigned long long b = wave_sum_u64(bytes);
+    if (lane_id() == 0) add_bytes(ctr, KC_RIE, b);
+}
+
+template <int GROUP>
+__global__ void __launch_bounds__(256) k_rie_group(DevGraph g, const int32_t* wl, int count,
+                                                   DevCounters* ctr) {
+    // GROUP = 64: one wave per vertex; GROUP = 256: one block per vertex
+    int item = (blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
+    int sub = threadIdx.x % GROUP;
+    unsigned long long bytes = 0;
+    long long moved = 0;
+    int u = -1;
+    if (item < count) {
+        u = wl[item];
+        int beg = g.row_ptr[u];
+        int end = beg + g.row_len[u];
+        int hu = g.h[u];
+        for (int j = beg + sub; j < end; j += GROUP) {
+            if (ld_res(g.cr, j) > 0) {
+                int v = g.cr[j].x;
+                if (hu > g.h[v] + 1) {
+                    int32_t x = xchg_res(g.cr, j, 0);
+                    if (x > 0) {
+                        add_res(g.cr, g.rev[j], x);
+                        add_e(g.e, v, x);
+                        moved += x;
+                        bytes += 32;
+                    }
+                }
+            }
+        }
+        if (sub == 0) bytes += 16 + 12ull * (unsigned long long)(end - beg);
+    }
+    // one atomic on e(u) per wave
+    moved = wave_sum_i64(moved);
+    if (lane_id() == 0 && moved && u >= 0) add_e(g.e, u, -moved);
+    unsigned long long b = wave_sum_u64(bytes);
+    if (lane_id() == 0) add_bytes(ctr, KC_RIE, b);
+}
+
+// ---- batch of updates (Algorithm 5, first loops) ---------------------------
+
+__device__ __forceinline__ unsigned long long pair_hash(unsigned long long k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+// Locate the slot of every update (u,v): binary search over the sorted part
+// of row u, then a scan of its inserted tail.  Present: slot_of = j and the
+// update index competes for win[j] (largest index = last update wins).
+// Absent: the unordered pair goes into a hash table; the first thread to
+// claim an entry reserves one slack slot in each of the two rows.
+__global__ void __launch_bounds__(256) k_batch_locate(DevGraph g, const mf_update* upd, int64_t k,
+                                                      int32_t* slot_of, int32_t* win, BatchTable tb,
+                                                      int32_t* need, DevCounters* ctr) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    mf_update up = upd[i];
+    const int N = g.n;
+    if (up.u < 0 || up.u >= N || up.v < 0 || up.v >= N || up.u == up.v || up.cap < 0) {
+        atomicOr(&ctr->err, 1);
+        slot_of[i] = INT_MIN;
+        return;
+    }
+    int beg = g.row_ptr[up.u];
+    int lo = 0, hi = g.row_sorted[up.u];
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (g.cr[beg + mid].x < up.v) lo = mid + 1;
+        else hi = mid;
+    }
+    int j = -1;
+    if (lo < g.row_sorted[up.u] && g.cr[beg + lo].x == up.v) {
+        j = beg + lo;
+    } else {
+        int len = g.row_len[up.u];
+        for (int q = g.row_sorted[up.u]; q < len; ++q)
+            if (g.cr[beg + q].x == up.v) { j = beg + q; break; }
+    }
+    if (j >= 0) {
+        slot_of[i] = j;
+        atomicMax(&win[j], (int)i);
+        return;
+    }
+    int a = min(up.u, up.v), b = max(up.u, up.v);
+    unsigned long long key = ((unsigned long long)(unsigned)a << 32) | (unsigned)b;
+    unsigned mask = (unsigned)tb.capacity - 1u;
+    unsigned idx = (unsigned)pair_hash(key) & mask;
+    for (;;) {
+        unsigned long long old = atomicCAS(&tb.key[idx], EMPTY_KEY, key);
+        if (old == EMPTY_KEY) {
+            int pa = atomicAdd(&need[a], 1);
+            int pb = atomicAdd(&need[b], 1);
+            int sa = g.row_ptr[a] + g.row_len[a] + pa;
+            int sb = g.row_ptr[b] + g.row_len[b] + pb;
+            if (sa >= g.row_ptr[a + 1] || sb >= g.row_ptr[b + 1]) atomicOr(&ctr->overflow, 1);
+            tb.slot[2 * idx] = sa;
+            tb.slot[2 * idx + 1] = sb;
+            atomicAdd(&ctr->new_pairs, 1);
+            break;
+        }
+        if (old == key) break;
+        idx = (idx + 1) & mask;
+    }
+    slot_of[i] = -(int)(idx + 1);
+    atomicMax(&tb.win[2 * idx + (up.u == a ? 0 : 1)], (int)i);
+}
+
+__device__ __forceinline__ int winning_cap(const mf_update* upd, int32_t w, int32_t current) {
+    return w >= 0 ? upd[w].cap : current;
+}
+
+// Capacity-range check of every pair a winner touches: c(u,v) + c(v,u) must
+// stay within int32 (residuals of the pair sum to it).
+__global__ void __launch_bounds__(256) k_batch_check(DevGraph g, const mf_update* upd, int64_t k,
+                                                     const int32_t* slot_of, const int32_t* win,
+                                                     BatchTable tb, DevCounters* ctr) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    int sl = slot_of[i];
+    if (sl == INT_MIN) return;
+    long long c1, c2;
+    if (sl >= 0) {
+        if (win[sl] != (int)i) return;
+        int r = g.rev[sl];
+        c1 = upd[i].cap;
+        c2 = winning_cap(upd, win[r], g.cap[r]);
+    } else {
+        int idx = -sl - 1;
+        c1 = winning_cap(upd, tb.win[2 * idx], 0);
+        c2 = winning_cap(upd, tb.win[2 * idx + 1], 0);
+    }
+    if (c1 + c2 > (long long)INT_MAX) atomicOr(&ctr->cap_overflow, 1);
+}
+
+// Write both slots of every new pair (capacity 0, residual 0, paired by rev)
+// and extend the two rows.
+__global__ void __launch_bounds__(256) k_batch_insert(DevGraph g, BatchTable tb) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= tb.capacity) return;
+    unsigned long long key = tb.key[idx];
+    if (key == EMPTY_KEY) return;
+    int a = (int)(key >> 32), b = (int)(key & 0xFFFFFFFFu);
+    int sa = tb.slot[2 * idx], sb = tb.slot[2 * idx + 1];
+    g.cr[sa] = make_int2(b, 0);
+    g.cap[sa] = 0;
+    g.rev[sa] = sb;
+    g.cr[sb] = make_int2(a, 0);
+    g.cap[sb] = 0;
+    g.rev[sb] = sa;
+    atomicAdd(&g.row_len[a], 1);
+    atomicAdd(&g.row_len[b], 1);
+}
+
+// c_f(u,v) += c' - c (Algorithm 5, first loop), by the winning update only.
+__global__ void __launch_bounds__(256) k_batch_apply(DevGraph g, const mf_update* upd, int64_t k,
+                                                     const int32_t* slot_of, const int32_t* win,
+                                                     BatchTable tb, int32_t* touched) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    int sl = slot_of[i];
+    int j = -1;
+    if (sl >= 0) {
+        if (win[sl] == (int)i) j = sl;
+    } else {
+        int idx = -sl - 1;
+        int dir = upd[i].u < upd[i].v ? 0 : 1;
+        if (tb.win[2 * idx + dir] == (int)i) j = tb.slot[2 * idx + dir];
+    }
+    touched[i] = j;
+    if (j < 0) return;
+    int32_t c = upd[i].cap;
+    int32_t delta = c - g.cap[j];
+    g.cap[j] = c;
+    if (delta) add_res(g.cr, j, delta);
+}
+
+// Over-capacity flow goes back (Algorithm 5, second loop): if c_f(u,v) < 0,
+// c_f(v,u) += c_f(u,v) and c_f(u,v) = 0; the excess of u rises and that of v
+// falls by the same amount (the excess recomputation of Algorithm 5, kept
+// incrementally).  Of a pair's two slots at most one can be negative, since
+// their residuals sum to c(u,v) + c(v,u) >= 0.
+__global__ void __launch_bounds__(256) k_batch_clamp(DevGraph g, const mf_update* upd, int64_t k,
+                                                     const int32_t* touched) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    int j = touched[i];
+    if (j < 0) return;
+    int32_t r = ld_res(g.cr, j);
+    if (r < 0) {
+        int32_t x = -r;
+        add_res(g.cr, j, x);
+        add_res(g.cr, g.rev[j], -x);
+        add_e(g.e, upd[i].u, x);
+        add_e(g.e, upd[i].v, -x);
+    }
+}
+
+// Scratch back to its idle state: win[] = -1, table empty, need[] = 0.
+__global__ void __launch_bounds__(256) k_batch_cleanup(BatchTable tb, int32_t* need,
+                                                       const int32_t* slot_of, int32_t* win,
+                                                       int64_t k) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < k) {
+        int sl = slot_of[i];
+        if (sl >= 0) win[sl] = -1;
+    }
+    if (i < tb.capacity) {
+        unsigned long long key = tb.key[i];
+        if (key != EMPTY_KEY) {
+            need[(int)(key >> 32)] = 0;
+            need[(int)(key & 0xFFFFFFFFu)] = 0;
+            tb.key[i] = EMPTY_KEY;
+        }
+        tb.win[2 * i] = -1;
+        tb.win[2 * i + 1] = -1;
+    }
+}
+
+// ---- cut certificate --------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_cut(DevGraph g, uint8_t* side, unsigned long long* cut) {
+    const int N = g.n;
+    long long c = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < N; v += gridDim.x * blockDim.x) {
+        bool a = g.h[v] == N;
+        side[v] = a ? 1 : 0;
+        if (!a) continue;
+        int beg = g.row_ptr[v], end = beg + g.row_len[v];
+        for (int j = beg; j < end; ++j)
+            if (g.h[g.cr[j].x] < N) c += g.cap[j];
+    }
+    long long tot = block_sum_i64<256>(c);
+    if (threadIdx.x == 0 && tot) atomicAdd(cut, (unsigned long long)tot);
+}
+
+// ---- self-test of the wave primitives ---------------------------------------
+
+__global__ void k_selftest(int* fails) {
+    int lane = lane_id();
+    for (int trial = 0; trial < 64; ++trial) {
+        unsigned long long x = pair_hash((unsigned long long)(trial * 131 + lane * 7 + 1));
+        if (trial % 3 == 0 && lane % 5 != trial % 5) x = ~0ull;  // sparse candidates
+        if (trial % 7 == 0) x = ~0ull;                          // no candidate at all
+        unsigned long long got = wave_min_u64(x);
+        unsigned long long want = ~0ull;
+        for (int l = 0; l < WAVE; ++l) {
+            unsigned long long y = __shfl(x, l, WAVE);
+            if (y < want) want = y;
+        }
+        if (got != want) atomicAdd(fails, 1);
+        int tot;
+        int ex = wave_excl_scan(lane % 3 + trial % 2, &tot);
+        int want_ex = 0, want_tot = 0;
+        for (int l = 0; l < WAVE; ++l) {
+            int v = l % 3 + trial % 2;
+            if (l < lane) want_ex += v;
+            want_tot += v;
+        }
+        if (ex != want_ex || tot != want_tot) atomicAdd(fails, 1);
+    }
+}
+
+inline int grid_for(int64_t items, int block, int cap = 4096) {
+    int64_t g = (items + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+// ---- launch wrappers ----------------------------------------------------------
+
+void launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t st) {
+    if (count <= 0) return;
+    k_fill_i32<<<grid_for(count, 256), 256, 0, st>>>(p, value, count);
+}
+
+void launch_reset(const DevGraph& g, int64_t slot_cap, hipStream_t st) {
+    k_reset<<<grid_for(slot_cap > g.n ? slot_cap : g.n, 256, 8192), 256, 0, st>>>(g, slot_cap);
+}
+
+void launch_saturate_source(const DevGraph& g, DevCounters* ctr, hipStream_t st) {
+    (void)ctr;
+    k_saturate_source<<<64, 256, 0, st>>>(g);
+}
+
+void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, hipStream_t st) {
+    k_zero_counters_front<<<1, 64, 0, st>>>(ctr);
+    k_gr_init<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, q0, ctr);
+}
+
+void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, DevCounters* ctr,
+                     int grid, hipStream_t st) {
+    k_gr_level<<<grid, 256, 0, st>>>(g, level, qin, qout, ctr);
+}
+
+void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
+                           DevCounters* ctr, hipStream_t st) {
+    k_build_worklist<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, wl0, wl1, wl2, ctr, 0);
+}
+
+void launch_topology_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
+                              DevCounters* ctr, hipStream_t st) {
+    k_build_worklist<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, wl0, wl1, wl2, ctr, 1);
+}
+
+void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc,
+                         DevCounters* ctr, hipStream_t st) {
+    if (count <= 0) return;
+    if (bin == 0)
+        k_pr_thread<<<grid_for(count, 256, 1 << 30), 256, 0, st>>>(g, wl, count, kc, ctr);
+    else if (bin == 1)
+        k_pr_wave<<<grid_for((int64_t)count * WAVE, 256, 1 << 30), 256, 0, st>>>(g, wl, count, kc, ctr);
+    else
+        k_pr_block<<<count, BLOCK_PR, 0, st>>>(g, wl, count, kc, ctr);
+}
+
+void launch_remove_invalid(const DevGraph& g, const int32_t* wl, int count, int bin,
+                           DevCounters* ctr, hipStream_t st) {
+    if (count <= 0) return;
+    if (bin == 0)
+        k_rie_thread<<<grid_for(count, 256, 1 << 30), 256, 0, st>>>(g, wl, count, ctr);
+    else if (bin == 1)
+        k_rie_group<64><<<grid_for((int64_t)count * 64, 256, 1 << 30), 256, 0, st>>>(g, wl, count, ctr);
+    else
+        k_rie_group<256><<<count, 256, 0, st>>>(g, wl, count, ctr);
+}
+
+void launch_clear_counters(DevCounters* ctr, hipStream_t st) {
+    // counters are plain int words; a fill kernel keeps this capture-safe
+    launch_fill_i32(reinterpret_cast<int32_t*>(ctr), 0, (int64_t)(sizeof(DevCounters) / 4), st);
+}
+
+void launch_batch_locate(const DevGraph& g, const mf_update* upd, int64_t k, int32_t* slot_of,
+                         int32_t* win, BatchTable tb, int32_t* need, DevCounters* ctr,
+                         hipStream_t st) {
+    if (k <= 0) return;
+    int grid = (int)((k + 255) / 256);
+    k_batch_locate<<<grid, 256, 0, st>>>(g, upd, k, slot_of, win, tb, need, ctr);
+    k_batch_check<<<grid, 256, 0, st>>>(g, upd, k, slot_of, win, tb, ctr);
+}
+
+void launch_batch_insert(const DevGraph& g, BatchTable tb, int32_t* need, hipStream_t st) {
+    (void)need;
+    k_batch_insert<<<(tb.capacity + 255) / 256, 256, 0, st>>>(g, tb);
+}
+
+void launch_batch_apply(const DevGraph& g, const mf_update* upd, int64_t k,
+                        const int32_t* slot_of, int32_t* win, BatchTable tb, int32_t* touched,
+                        DevCounters* ctr, hipStream_t st) {
+    (void)ctr;
+    if (k <= 0) return;
+    k_batch_apply<<<(int)((k + 255) / 256), 256, 0, st>>>(g, upd, k, slot_of, win, tb, touched);
+}
+
+void launch_batch_clamp(const DevGraph& g, const mf_update* upd, int64_t k,
+                        const int32_t* touched, int32_t* win, BatchTable tb, hipStream_t st) {
+    (void)win;
+    (void)tb;
+    if (k <= 0) return;
+    k_batch_clamp<<<(int)((k + 255) / 256), 256, 0, st>>>(g, upd, k, touched);
+}
+
+void launch_batch_cleanup(BatchTable tb, int32_t* need, const int32_t* slot_of, int32_t* win,
+                          int64_t k, hipStream_t st) {
+    int64_t items = k > tb.capacity ? k : tb.capacity;
+    if (items <= 0) return;
+    k_batch_cleanup<<<(int)((items + 255) / 256), 256, 0, st>>>(tb, need, slot_of, win, k);
+}
+
+void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipStream_t st) {
+    k_cut<<<grid_for(g.n, 256, 4096), 256, 0, st>>>(g, side, cut);
+}
+
+int device_selftest(hipStream_t st) {
+    int* d = nullptr;
+    if (hipMalloc(&d, sizeof(int)) != hipSuccess) return -1;
+    int h = 0;
+    (void)hipMemcpyAsync(d, &h, sizeof(int), hipMemcpyHostToDevice, st);
+    k_selftest<<<1, 64, 0, st>>>(d);
+    (void)hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(d);
+    return h;
+}
+
+}  // namespace mf

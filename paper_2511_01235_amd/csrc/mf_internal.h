@@ -1,0 +1,114 @@
+// Internal declarations shared by the host driver (api.cpp, bicsr.cpp) and
+// the gfx950 kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "mf.h"
+
+namespace mf {
+
+// Bi-CSR residual graph (Section 5.1).  Row v occupies slot positions
+// [row_ptr[v], row_ptr[v+1]); its first row_len[v] slots are in use, the rest
+// is slack for inserted pairs.  The first row_sorted[v] slots are sorted by
+// column (the rows as loaded); inserted slots follow unsorted.  Slot j holds
+// {col, res} (neighbour and residual capacity u->col), its capacity cap[j]
+// and the index rev[j] of the slot col->u in row col.
+struct DevGraph {
+    int32_t n, s, t;
+    int32_t* row_ptr;
+    int32_t* row_len;
+    int32_t* row_sorted;
+    int2* cr;
+    int32_t* rev;
+    int32_t* cap;
+    int64_t* e;
+    int32_t* h;
+};
+
+// Device-side counters, one block of memory read back with a single copy.
+struct DevCounters {
+    int32_t front[3];          // global-relabel frontier sizes, ring over levels
+    int32_t wl[4];             // worklist sizes per degree bin
+    int32_t err;               // batch: invalid update seen
+    int32_t overflow;          // batch: row slack exhausted
+    int32_t new_pairs;         // batch: distinct absent pairs
+    int32_t cap_overflow;      // batch: c(u,v)+c(v,u) would leave int32
+    int32_t pad[2];
+    long long deficit_sum;     // sum of negative excess outside {s,t}
+    long long e_t;             // e(t) at the worklist build
+    unsigned long long bytes[8];  // algorithmic bytes per kernel class
+};
+
+enum KernelClass { KC_GR = 0, KC_PR = 1, KC_RIE = 2, KC_WL = 3, KC_BATCH = 4, KC_INIT = 5, KC_NCLASS = 8 };
+
+// Degree bins for the worklist: rows up to BIN0_MAX slots get one thread,
+// up to BIN1_MAX one wave, longer rows one 1024-thread block.
+constexpr int BIN0_MAX = 16;
+constexpr int BIN1_MAX = 4096;
+constexpr int BLOCK_PR = 1024;
+// Global-relabel frontier entries cover at most GR_CHUNK slots of a row.
+constexpr int GR_CHUNK = 1024;
+
+// Batch scratch: hash table of absent pairs, keyed by the unordered pair.
+struct BatchTable {
+    unsigned long long* key;   // (lo << 32 | hi), ~0 = empty
+    int32_t* win;              // 2 per entry: last update index per direction (lo->hi, hi->lo)
+    int32_t* slot;             // 2 per entry: reserved slot in row lo, row hi
+    int32_t capacity;          // power of two
+};
+
+// ---- launch wrappers (kernels.hip) ---------------------------------------
+void launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t st);
+void launch_reset(const DevGraph& g, int64_t slot_cap, hipStream_t st);
+void launch_saturate_source(const DevGraph& g, DevCounters* ctr, hipStream_t st);
+void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, hipStream_t st);
+void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, DevCounters* ctr,
+                     int grid, hipStream_t st);
+void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
+                           DevCounters* ctr, hipStream_t st);
+void launch_topology_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
+                              DevCounters* ctr, hipStream_t st);
+void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc,
+                         DevCounters* ctr, hipStream_t st);
+void launch_remove_invalid(const DevGraph& g, const int32_t* wl, int count, int bin,
+                           DevCounters* ctr, hipStream_t st);
+void launch_clear_counters(DevCounters* ctr, hipStream_t st);
+void launch_batch_locate(const DevGraph& g, const mf_update* upd, int64_t k, int32_t* slot_of,
+                         int32_t* win, BatchTable tb, int32_t* need, DevCounters* ctr,
+                         hipStream_t st);
+void launch_batch_insert(const DevGraph& g, BatchTable tb, int32_t* need, hipStream_t st);
+void launch_batch_apply(const DevGraph& g, const mf_update* upd, int64_t k,
+                        const int32_t* slot_of, int32_t* win, BatchTable tb, int32_t* touched,
+                        DevCounters* ctr, hipStream_t st);
+void launch_batch_clamp(const DevGraph& g, const mf_update* upd, int64_t k,
+                        const int32_t* touched, int32_t* win, BatchTable tb, hipStream_t st);
+void launch_batch_cleanup(BatchTable tb, int32_t* need, const int32_t* slot_of, int32_t* win,
+                          int64_t k, hipStream_t st);
+void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipStream_t st);
+int device_selftest(hipStream_t st);
+
+// ---- host Bi-CSR builder (bicsr.cpp) -------------------------------------
+struct HostBiCSR {
+    int32_t n = 0;
+    std::vector<int32_t> row_ptr, row_len, row_sorted, col, rev, cap;
+    int64_t pairs = 0;         // merged directed pairs with a slot
+    int64_t m_unique = 0;      // merged directed pairs with capacity > 0 at load
+};
+
+// Validates and builds; returns MF_OK, MF_ERR_INVALID or MF_ERR_OVERFLOW.
+mf_status build_bicsr(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                      const int32_t* cap, int32_t s, int32_t t, int32_t slack_min,
+                      int32_t slack_pct, HostBiCSR* out);
+
+// Re-lays rows with fresh slack: row v keeps its used slots (sorted by column
+// afterwards) and gets room for extra[v] more plus the usual slack.  Residuals
+// move with their slots.  res is updated in place alongside.
+void relayout_bicsr(const HostBiCSR& in, const std::vector<int32_t>& res_in,
+                    const std::vector<int32_t>& extra, int32_t slack_min, int32_t slack_pct,
+                    HostBiCSR* out, std::vector<int32_t>* res_out);
+
+}  // namespace mf

@@ -1,0 +1,77 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/mf.h declares, and rejects invalid input before touching the
+device (validation happens first, so these return without a GPU)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2511_01235_amd as mf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    L = mf.lib()
+    names = _declared()
+    assert "mf_graph_load" in names and "mf_apply_batch" in names and "mf_min_cut" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(mf.EXPORTED) == names
+
+
+def test_status_strings():
+    for code in range(7):
+        assert mf.status_string(code)
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=1, e=[[0, 0, 1]], s=0, t=0),
+    dict(n=3, e=[[0, 1, 1]], s=1, t=1),
+    dict(n=3, e=[[0, 1, 1]], s=-1, t=2),
+    dict(n=3, e=[[0, 1, 1]], s=0, t=3),
+    dict(n=3, e=[[0, 0, 1]], s=0, t=2),
+    dict(n=3, e=[[0, 1, -1]], s=0, t=2),
+    dict(n=3, e=[[0, 5, 1]], s=0, t=2),
+    dict(n=3, e=[[-1, 1, 1]], s=0, t=2),
+])
+def test_load_rejects_invalid(case):
+    e = np.array(case["e"], np.int64)
+    with pytest.raises(mf.MFError) as ei:
+        mf.mf_graph_load(case["n"], e[:, 0], e[:, 1], e[:, 2], case["s"], case["t"])
+    assert ei.value.status == mf.MF_ERR_INVALID
+
+
+def test_load_rejects_pair_overflow():
+    big = 2**31 - 1
+    for e in ([[0, 1, big], [0, 1, 1]], [[0, 1, big], [1, 0, 1]]):
+        e = np.array(e, np.int64)
+        with pytest.raises(mf.MFError) as ei:
+            mf.mf_graph_load(3, e[:, 0], e[:, 1], e[:, 2], 0, 2)
+        assert ei.value.status == mf.MF_ERR_OVERFLOW
+
+
+def test_options_struct_size_checked():
+    o = mf.mf_default_options()
+    assert o.struct_size == mf.C.sizeof(mf.Options)
+    o.struct_size = 7
+    with pytest.raises(mf.MFError) as ei:
+        mf.mf_graph_load(3, [0], [1], [1], 0, 2, o)
+    assert ei.value.status == mf.MF_ERR_INVALID
+
+
+def test_null_handle_calls():
+    L = mf.lib()
+    v = mf.C.c_int64()
+    assert L.mf_maxflow(None, mf.C.byref(v)) == mf.MF_ERR_INVALID
+    assert L.mf_apply_batch(None, None, 0, mf.C.byref(v)) == mf.MF_ERR_INVALID
+    assert L.mf_min_cut(None, None, mf.C.byref(v)) == mf.MF_ERR_INVALID
+    assert L.mf_get_stats(None, None) == mf.MF_ERR_INVALID
+    L.mf_graph_free(None)

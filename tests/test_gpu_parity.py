@@ -1,0 +1,282 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bit-exact comparisons (integer method): max-flow values after the static
+solve and after every update batch; global-relabel heights (BFS distances are
+unique); the active-vertex set.  The cut returned by mf_min_cut is checked as
+a certificate: it separates s from t and its capacity equals the value.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2511_01235_amd as mf
+from paper_2511_01235_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+from test_oracle_pins import _CapModel, _arrays, _random_small  # noqa: E402
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device_ready():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    assert mf.mf_debug_selftest(-1) == mf.MF_OK
+
+
+def _cut_ok(g_n, s, t, side, cut, value, src, dst, cap):
+    assert side[s] == 1 and side[t] == 0
+    assert cut == value
+    rc, msg = oracle.cert_check(g_n, src, dst, cap, s, t, None, side, value)
+    assert rc == 0, msg
+
+
+def _solve_both(n, src, dst, cap, s, t, **opt):
+    want = oracle.max_flow(n, src, dst, cap, s, t)
+    with mf.MaxFlowGraph(n, src, dst, cap, s, t, **opt) as g:
+        got = g.maxflow()
+        side, cut = g.min_cut()
+    return want, got, side, cut
+
+
+def test_selftest():
+    assert mf.mf_debug_selftest(0) == mf.MF_OK
+
+
+# --- global relabel and worklist, bit-exact -------------------------------------
+
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+def test_initial_labels_bit_exact(name):
+    g, _, _, _ = gen.workload(name)
+    say("initial labels", name, g.n, g.m)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    h_want, e_want = o.initial_labels()
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        h, e, active = G.initial_labels()
+    assert np.array_equal(h, h_want)
+    assert np.array_equal(e, e_want)
+    others = np.ones(g.n, bool)
+    others[[g.s, g.t]] = False
+    want_active = np.flatnonzero(others & (e_want > 0) & (h_want < g.n))
+    assert np.array_equal(np.sort(active), want_active)
+    assert np.unique(active).size == active.size
+
+
+# --- static value ---------------------------------------------------------------
+
+def test_golden_static_gpu():
+    import json
+    data = json.load(open(os.path.join(HERE, "golden", "hand_examples.json")))
+    for case in data["static"]:
+        src, dst, cap = _arrays(case["edges"])
+        say("golden", case["name"])
+        want, got, side, cut = _solve_both(case["n"], src, dst, cap, case["s"], case["t"])
+        assert got == want == case["expected"]
+        _cut_ok(case["n"], case["s"], case["t"], side, cut, got, src, dst, cap)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_static_tiny_vs_brute_force(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 11))
+    src, dst, cap = _random_small(rng, n, int(rng.integers(0, 4 * n)), 20)
+    s = int(rng.integers(0, n))
+    t = int((s + 1 + rng.integers(0, n - 1)) % n)
+    say("tiny", seed, n, src.size)
+    want = oracle.brute_min_cut(n, src, dst, cap, s, t)
+    with mf.MaxFlowGraph(n, src, dst, cap, s, t) as G:
+        got = G.maxflow()
+        side, cut = G.min_cut()
+    assert got == want
+    _cut_ok(n, s, t, side, cut, got, src, dst, cap)
+
+
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "rmat16", "grid64", "grid256"])
+@pytest.mark.parametrize("opts", [{}, {"kernel_cycles": 1}, {"kernel_cycles": 64},
+                                  {"topology_driven": True}])
+def test_static_workloads(name, opts):
+    if name in ("rmat16", "grid256") and opts:
+        pytest.skip("option sweep runs on the smaller graphs")
+    g, _, _, _ = gen.workload(name)
+    say("static", name, opts)
+    want, got, side, cut = _solve_both(g.n, g.src, g.dst, g.cap, g.s, g.t, **opts)
+    assert got == want
+    _cut_ok(g.n, g.s, g.t, side, cut, got, g.src, g.dst, g.cap)
+
+
+def test_static_repeatable():
+    g, _, _, _ = gen.workload("rmat14")
+    want = oracle.max_flow(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        for r in range(5):
+            say("repeat", r)
+            assert G.maxflow() == want
+
+
+def test_closed_forms_gpu():
+    W, c = 32, 37
+    g = gen.grid(W, 100, seed=1)
+    cap = np.where(g.cap == 1000, 1000, c).astype(np.int32)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, cap, g.s, g.t) as G:
+        assert G.maxflow() == W * c
+    src, dst, cap = _arrays([[0, 1, 5], [1, 2, 3], [2, 3, 9]])
+    with mf.MaxFlowGraph(4, src, dst, cap, 0, 3) as G:
+        assert G.maxflow() == 3
+    src, dst, cap = _arrays([[0, 1, 5], [2, 3, 3]])
+    with mf.MaxFlowGraph(4, src, dst, cap, 0, 3) as G:
+        assert G.maxflow() == 0
+    with mf.MaxFlowGraph(4, np.zeros(0), np.zeros(0), np.zeros(0), 0, 3) as G:
+        assert G.maxflow() == 0
+
+
+# --- dynamic ---------------------------------------------------------------------
+
+def test_golden_dynamic_gpu():
+    import json
+    data = json.load(open(os.path.join(HERE, "golden", "hand_examples.json")))
+    for case in data["dynamic"]:
+        src, dst, cap = _arrays(case["edges"])
+        with mf.MaxFlowGraph(case["n"], src, dst, cap, case["s"], case["t"]) as G:
+            assert G.maxflow() == case["initial"]
+            for batch, want in zip(case["batches"], case["expected"]):
+                u, v, c = _arrays(batch)
+                assert G.apply_batch(u, v, c) == want
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_dynamic_tiny_adversarial(seed):
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(3, 12))
+    src, dst, cap = _random_small(rng, n, 3 * n, 15)
+    s, t = 0, n - 1
+    model = _CapModel(n, src, dst, cap)
+    say("dyn tiny", seed, n)
+    with mf.MaxFlowGraph(n, src, dst, cap, s, t, insert_slack_min=1, insert_slack_pct=1) as G:
+        assert G.maxflow() == oracle.brute_min_cut(n, src, dst, cap, s, t)
+        for b in range(6):
+            pairs = np.array(list(model.c.keys()), dtype=np.int64).reshape(-1, 2)
+            u, v, c = gen.random_batch(n, int(rng.integers(1, 12)), 15, seed=seed * 100 + b,
+                                       pairs=pairs)
+            model.apply(u, v, c)
+            ms, md, mc = model.arrays()
+            want = oracle.brute_min_cut(n, ms, md, mc, s, t)
+            got = G.apply_batch(u, v, c)
+            assert got == want, (seed, b)
+            side, cut = G.min_cut()
+            _cut_ok(n, s, t, side, cut, got, ms, md, mc)
+
+
+@pytest.mark.parametrize("name,batches", [("er2000", 10), ("rmat12", 8), ("rmat14", 5),
+                                          ("grid64", 5), ("grid256", 3)])
+def test_dynamic_workloads(name, batches):
+    g, stream, k, nb = gen.workload(name)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        assert G.maxflow() == o.static()
+        for b in range(min(batches, nb)):
+            u, v, c = stream.next_batch(k)
+            say("dyn", name, "batch", b, k)
+            want = o.apply(u, v, c)
+            got = G.apply_batch(u, v, c)
+            assert got == want, (name, b)
+            cs, cd, cc = stream.current_edges()
+            side, cut = G.min_cut()
+            _cut_ok(g.n, g.s, g.t, side, cut, got, cs, cd, cc)
+
+
+def test_dynamic_device_batches_match_host():
+    import torch
+    g, stream, k, nb = gen.workload("rmat12")
+    batches = [stream.next_batch(k) for _ in range(4)]
+    vals_host, vals_dev = [], []
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        G.maxflow()
+        for u, v, c in batches:
+            vals_host.append(G.apply_batch(u, v, c))
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        G.maxflow()
+        for u, v, c in batches:
+            t = torch.from_numpy(np.stack([u, v, c], 1).astype(np.int32)).cuda().contiguous()
+            vals_dev.append(G.apply_batch_device(t))
+            torch.cuda.synchronize()
+    assert vals_host == vals_dev
+
+
+def test_batch_errors_leave_graph_unchanged():
+    g, stream, k, nb = gen.workload("er2000")
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        v0 = G.maxflow()
+        bad = [([0, 5], [1, 5], [3, 3]),          # u == v
+               ([0, g.n], [1, 2], [3, 3]),        # out of range
+               ([0, 1], [1, 2], [3, -1])]         # negative capacity
+        for u, v, c in bad:
+            with pytest.raises(mf.MFError) as ei:
+                G.apply_batch(u, v, c)
+            assert ei.value.status == mf.MF_ERR_INVALID
+        with pytest.raises(mf.MFError) as ei:
+            G.apply_batch([0, 1], [1, 0], [2**31 - 1, 5])
+        assert ei.value.status == mf.MF_ERR_OVERFLOW
+        assert G.apply_batch([], [], []) == v0
+        u, v, c = stream.next_batch(k)
+        want = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+        want.static()
+        assert G.apply_batch(u, v, c) == want.apply(u, v, c)
+
+
+def test_state_errors():
+    g, _, _, _ = gen.workload("er2000")
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        with pytest.raises(mf.MFError) as ei:
+            G.apply_batch([0], [1], [5])
+        assert ei.value.status == mf.MF_ERR_STATE
+        with pytest.raises(mf.MFError) as ei:
+            G.min_cut()
+        assert ei.value.status == mf.MF_ERR_STATE
+
+
+def test_relayout_when_slack_runs_out():
+    """Many inserts into rows with one slot of slack force re-layouts."""
+    g = gen.erdos_renyi(300, 1200, 100, seed=4)
+    model = _CapModel(g.n, g.src, g.dst, g.cap)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, insert_slack_min=1,
+                         insert_slack_pct=1) as G:
+        assert G.maxflow() == o.static()
+        for b in range(5):
+            u, v, c = gen.random_batch(g.n, 400, 100, seed=77 + b)
+            model.apply(u, v, c)
+            say("relayout batch", b)
+            assert G.apply_batch(u, v, c) == o.apply(u, v, c)
+        assert G.stats()["relayouts"] >= 1
+
+
+# --- full size: the benchmark workload ------------------------------------------
+
+def test_rmat20_full_size():
+    g, stream, k, nb = gen.workload("rmat20")
+    say("rmat20 oracle static")
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    want = o.static()
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        say("rmat20 gpu static")
+        got = G.maxflow()
+        assert got == want
+        side, cut = G.min_cut()
+        _cut_ok(g.n, g.s, g.t, side, cut, got, g.src, g.dst, g.cap)
+        for b in range(3):
+            u, v, c = stream.next_batch(k)
+            say("rmat20 batch", b)
+            got = G.apply_batch(u, v, c)
+            assert got == o.apply(u, v, c)
+            cs, cd, cc = stream.current_edges()
+            side, cut = G.min_cut()
+            _cut_ok(g.n, g.s, g.t, side, cut, got, cs, cd, cc)
