@@ -86,7 +86,7 @@ typedef struct mf_stats {
     int64_t last_active_sum;   /* sum over iterations of the worklist size */
     int64_t last_new_pairs;    /* pairs inserted by the last batch */
     double last_ms;            /* host wall time of the call */
-    /* per-kernel device time over the calls since mf_profile(g, 1) (HIP events on the
+    /* per-kernel device time over the calls since mf_profile (HIP events on the
      * library's stream); index: 0 global-relabel level, 1 push-relabel, 2 remove-invalid-
      * edges, 3 worklist build, 4 batch kernels, 5 reset and source saturation */
     double kernel_ms[8];
@@ -157,19 +157,23 @@ mf_status mf_min_cut(mf_graph* g, uint8_t* source_side, int64_t* cut_capacity);
  * returned to s and deficits on the sink side are filled from t, along
  * residual paths inside each side, Sections 3.1 and 4.3).  One entry per
  * merged directed pair with capacity > 0, sorted by (u, v): src[i], dst[i],
- * flow[i] with 0 <= flow <= c.  With NULL arrays only *count is written;
- * otherwise each array must hold *count entries as returned by a previous
- * count-only call.  The retained solver state is not changed.
+ * flow[i] with 0 <= flow <= c.  With all three arrays NULL only *count is
+ * written (the number of entries).  Otherwise *count must hold the arrays'
+ * length on input (MF_ERR_INVALID if it is too short) and receives the
+ * number written.  The completion runs on a copy: the retained solver state
+ * is not changed.
  * Errors: MF_ERR_INVALID, MF_ERR_STATE, MF_ERR_NOT_CONVERGED, MF_ERR_DEVICE. */
 mf_status mf_get_flow(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, int32_t* flow);
 
 /* Counters and sizes; see mf_stats. */
 mf_status mf_get_stats(const mf_graph* g, mf_stats* out);
 
-/* Turn per-kernel event timing on (1) or off (0) and clear its totals.  With
- * timing on, every launch of the library is bracketed by HIP events on the
- * handle's stream and mf_stats.kernel_ms accumulates their durations. */
-mf_status mf_profile(mf_graph* g, int32_t enable);
+/* Per-kernel event timing.  class_mask selects kernel classes by bit (bit c =
+ * index c of mf_stats.kernel_ms; 0 turns timing off, 0xFF times every class)
+ * and clears the totals.  Each launch of a selected class is bracketed by HIP
+ * events on the handle's stream; mf_stats accumulates their durations, the
+ * launch counts and the algorithmic bytes of the selected classes. */
+mf_status mf_profile(mf_graph* g, int32_t class_mask);
 
 /* Diagnostic: reset to zero flow, saturate the source, run one global
  * relabel (Algorithm 4) and one worklist build (Section 5.2), and copy out

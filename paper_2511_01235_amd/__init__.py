@@ -190,12 +190,14 @@ def mf_get_flow(g):
     cnt = C.c_int64()
     _check(lib().mf_get_flow(g, C.byref(cnt), None, None, None), "mf_get_flow")
     k = cnt.value
+    cnt = C.c_int64(k)
     src = np.zeros(k, np.int32)
     dst = np.zeros(k, np.int32)
     flow = np.zeros(k, np.int32)
     _check(lib().mf_get_flow(g, C.byref(cnt), src.ctypes.data, dst.ctypes.data, flow.ctypes.data),
            "mf_get_flow")
-    return src, dst, flow
+    k = cnt.value
+    return src[:k], dst[:k], flow[:k]
 
 
 def mf_get_stats(g) -> dict:
@@ -209,8 +211,9 @@ def mf_get_stats(g) -> dict:
     return out
 
 
-def mf_profile(g, enable: bool = True):
-    _check(lib().mf_profile(g, int(bool(enable))), "mf_profile")
+def mf_profile(g, class_mask: int = 0xFF):
+    """class_mask: bit c times kernel class KERNEL_CLASSES[c]; 0 turns timing off."""
+    _check(lib().mf_profile(g, int(class_mask)), "mf_profile")
 
 
 def mf_debug_initial_labels(g, n: int):
@@ -258,8 +261,8 @@ class MaxFlowGraph:
     def stats(self) -> dict:
         return mf_get_stats(self.h)
 
-    def profile(self, enable=True):
-        mf_profile(self.h, enable)
+    def profile(self, class_mask=0xFF):
+        mf_profile(self.h, class_mask)
 
     def initial_labels(self):
         return mf_debug_initial_labels(self.h, self.n)

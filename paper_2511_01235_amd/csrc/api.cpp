@@ -57,7 +57,7 @@ struct mf_graph {
     int32_t relayouts = 0;
     int64_t last_iterations = 0, last_levels = 0, last_active_sum = 0, last_new_pairs = 0;
     double last_ms = 0;
-    bool profiling = false;
+    uint32_t prof_mask = 0;
     double kernel_ms[8] = {0};
     int64_t kernel_launches[8] = {0};
     double kernel_bytes[8] = {0};
@@ -105,7 +105,7 @@ hipEvent_t take_event(mf_graph* g) {
 
 template <class F>
 void timed(mf_graph* g, int cls, F&& launch) {
-    if (!g->profiling) {
+    if (!(g->prof_mask >> cls & 1u)) {
         launch();
         return;
     }
@@ -131,8 +131,8 @@ void settle_events(mf_graph* g) {
 }
 
 void fold_bytes(mf_graph* g) {
-    if (!g->profiling) return;
-    for (int c = 0; c < 8; ++c) g->kernel_bytes[c] += (double)g->ctr_h->bytes[c];
+    for (int c = 0; c < 8; ++c)
+        if (g->prof_mask >> c & 1u) g->kernel_bytes[c] += (double)g->ctr_h->bytes[c];
 }
 
 mf_status read_counters(mf_graph* g) {
@@ -239,19 +239,41 @@ mf_status ensure_batch_capacity(mf_graph* g, int64_t k) {
 
 // ---- the push-relabel loop ----------------------------------------------------
 
+// What one loop runs on.  The solve: backward BFS from t with deficits as
+// extra sinks, positive-excess worklist, push-relabel and remove-invalid-
+// edges.  Completing a preflow into a flow reuses the loop twice on a copy of
+// the state: pushes toward s (root s, t pinned), then pulls from t (forward
+// BFS, negative-excess worklist, s pinned).
+struct LoopMode {
+    DevGraph dg;
+    int seed_deficits = 1;
+    bool forward = false;
+    int sign = 1;
+    bool pull = false;
+    bool rie = true;
+    bool topology = false;
+};
+
+LoopMode solve_mode(mf_graph* g) {
+    LoopMode m;
+    m.dg = g->dg;
+    m.topology = g->opt.topology_driven != 0;
+    return m;
+}
+
 // Global relabel: seeds, then levels in growing chunks; each level launch
 // reads the frontier size on the device, so the host checks only after a
 // chunk.  Returns the number of level launches.
-mf_status global_relabel(mf_graph* g, int64_t* levels_out) {
+mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
     hipStream_t st = g->stream;
-    timed(g, mf::KC_GR, [&] { mf::launch_gr_init(g->dg, g->q[0], g->ctr, st); });
+    timed(g, mf::KC_GR, [&] { mf::launch_gr_init(m.dg, g->q[0], g->ctr, m.seed_deficits, st); });
     int level = 0;
     int chunk = 2;
     for (;;) {
         for (int i = 0; i < chunk; ++i, ++level)
             timed(g, mf::KC_GR, [&] {
-                mf::launch_gr_level(g->dg, level, g->q[level & 1], g->q[(level + 1) & 1], g->ctr,
-                                    g->gr_grid, st);
+                mf::launch_gr_level(m.dg, level, g->q[level & 1], g->q[(level + 1) & 1], g->ctr,
+                                    g->gr_grid, m.forward, st);
             });
         MF_HIP(hipGetLastError());
         mf_status rc = read_counters(g);
@@ -270,17 +292,14 @@ mf_status global_relabel(mf_graph* g, int64_t* levels_out) {
 // Loop {global relabel; worklist; stop if no active vertex; push-relabel;
 // remove invalid edges}.  The stop test is taken right after a fresh global
 // relabel, so at exit A = {h = |V|} is a cut whose capacity is the value.
-mf_status run_loop(mf_graph* g, int64_t* value) {
+mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     hipStream_t st = g->stream;
     int64_t iters = 0, levels = 0, active_sum = 0;
     for (;;) {
-        mf_status rc = global_relabel(g, &levels);
+        mf_status rc = global_relabel(g, m, &levels);
         if (rc != MF_OK) return rc;
         timed(g, mf::KC_WL, [&] {
-            if (g->opt.topology_driven)
-                mf::launch_topology_worklist(g->dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, st);
-            else
-                mf::launch_build_worklist(g->dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, st);
+            mf::launch_build_worklist(m.dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, m.topology, m.sign, st);
         });
         MF_HIP(hipGetLastError());
         rc = read_counters(g);
@@ -298,9 +317,14 @@ mf_status run_loop(mf_graph* g, int64_t* value) {
         }
         int cnt[3] = {c.wl[0], c.wl[1], c.wl[2]};
         for (int b = 0; b < 3; ++b)
-            if (cnt[b]) timed(g, mf::KC_PR, [&] { mf::launch_push_relabel(g->dg, g->wl[b], cnt[b], b, g->kc, g->ctr, st); });
-        for (int b = 0; b < 3; ++b)
-            if (cnt[b]) timed(g, mf::KC_RIE, [&] { mf::launch_remove_invalid(g->dg, g->wl[b], cnt[b], b, g->ctr, st); });
+            if (cnt[b])
+                timed(g, mf::KC_PR, [&] {
+                    mf::launch_push_relabel(m.dg, g->wl[b], cnt[b], b, g->kc, m.pull, g->ctr, st);
+                });
+        if (m.rie)
+            for (int b = 0; b < 3; ++b)
+                if (cnt[b])
+                    timed(g, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, g->wl[b], cnt[b], b, g->ctr, st); });
         MF_HIP(hipGetLastError());
     }
     g->last_iterations = iters;
@@ -401,7 +425,7 @@ mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_
         g->pairs += c.new_pairs;
         timed(g, mf::KC_INIT, [&] { mf::launch_saturate_source(g->dg, g->ctr, st); });
         MF_HIP(hipGetLastError());
-        return run_loop(g, value);
+        return run_loop(g, solve_mode(g), value);
     }
     return MF_ERR_OUT_OF_MEMORY;  // slack could not be made to fit
 }
@@ -491,6 +515,8 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     g->dg.n = n;
     g->dg.s = s;
     g->dg.t = t;
+    g->dg.root = t;
+    g->dg.pinned = s;
     if (dalloc(g, &g->dg.e, n) != hipSuccess || dalloc(g, &g->dg.h, n) != hipSuccess ||
         dalloc(g, &g->wl[0], n) != hipSuccess || dalloc(g, &g->wl[1], n) != hipSuccess ||
         dalloc(g, &g->wl[2], n) != hipSuccess || dalloc(g, &g->ctr, 1) != hipSuccess ||
@@ -525,7 +551,7 @@ mf_status mf_maxflow(mf_graph* g, int64_t* value) {
     });
     MF_HIP(hipGetLastError());
     int64_t v = 0;
-    rc = run_loop(g, &v);
+    rc = run_loop(g, solve_mode(g), &v);
     settle_events(g);
     fold_bytes(g);
     if (rc != MF_OK) return rc;
@@ -598,11 +624,98 @@ mf_status mf_get_flow(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, i
     mf_status rc = check_handle(g);
     if (rc != MF_OK) return rc;
     if (!count) return MF_ERR_INVALID;
+    bool want = src && dst && flow;
+    if ((src || dst || flow) && !want) return MF_ERR_INVALID;
     if (!g->solved) return MF_ERR_STATE;
-    (void)src;
-    (void)dst;
-    (void)flow;
-    return MF_ERR_STATE;
+    hipStream_t st = g->stream;
+    unsigned long long cnt = 0;
+    if (!want) {
+        mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->cut_acc), 0, 2, st);
+        mf::launch_flow_slots(g->dg, nullptr, g->cut_acc, st);
+        MF_HIP(hipGetLastError());
+        MF_HIP(hipMemcpyAsync(&cnt, g->cut_acc, sizeof(cnt), hipMemcpyDeviceToHost, st));
+        MF_HIP(hipStreamSynchronize(st));
+        *count = (int64_t)cnt;
+        return MF_OK;
+    }
+    const int32_t n = g->n;
+    const int64_t S = g->slot_cap;
+    int2* cr2 = nullptr;
+    int64_t* e2 = nullptr;
+    int32_t* h2 = nullptr;
+    int32_t* fslot = nullptr;
+    auto release = [&] {
+        dfree(cr2);
+        dfree(e2);
+        dfree(h2);
+        dfree(fslot);
+    };
+    if (dalloc(g, &cr2, S) != hipSuccess || dalloc(g, &e2, n) != hipSuccess ||
+        dalloc(g, &h2, n) != hipSuccess || dalloc(g, &fslot, S) != hipSuccess) {
+        release();
+        return MF_ERR_OUT_OF_MEMORY;
+    }
+    // work on a copy: the retained preflow stays as it is
+    MF_HIP(hipMemcpyAsync(cr2, g->dg.cr, sizeof(int2) * S, hipMemcpyDeviceToDevice, st));
+    MF_HIP(hipMemcpyAsync(e2, g->dg.e, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
+    LoopMode to_source;
+    to_source.dg = g->dg;
+    to_source.dg.cr = cr2;
+    to_source.dg.e = e2;
+    to_source.dg.h = h2;
+    to_source.dg.root = g->s;
+    to_source.dg.pinned = g->t;
+    to_source.seed_deficits = 0;
+    to_source.rie = false;
+    LoopMode from_sink = to_source;
+    from_sink.dg.root = g->t;
+    from_sink.dg.pinned = g->s;
+    from_sink.forward = true;
+    from_sink.sign = -1;
+    from_sink.pull = true;
+    int64_t dummy = 0;
+    int64_t it_keep = g->last_iterations, lv_keep = g->last_levels, act_keep = g->last_active_sum;
+    rc = run_loop(g, to_source, &dummy);
+    if (rc == MF_OK) rc = run_loop(g, from_sink, &dummy);
+    g->last_iterations = it_keep;
+    g->last_levels = lv_keep;
+    g->last_active_sum = act_keep;
+    if (rc != MF_OK) {
+        release();
+        return rc;
+    }
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->cut_acc), 0, 2, st);
+    mf::launch_flow_slots(to_source.dg, fslot, g->cut_acc, st);
+    MF_HIP(hipGetLastError());
+    std::vector<int32_t> fs((size_t)S), rp((size_t)n + 1), rl((size_t)n);
+    std::vector<int2> cr((size_t)S);
+    MF_HIP(hipMemcpyAsync(&cnt, g->cut_acc, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(fs.data(), fslot, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(cr.data(), g->dg.cr, sizeof(int2) * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(rp.data(), g->dg.row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(rl.data(), g->dg.row_len, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipStreamSynchronize(st));
+    release();
+    if ((int64_t)cnt > *count) return MF_ERR_INVALID;  // caller's arrays are too short
+    // emit rows in order, each row's entries by column
+    int64_t k = 0;
+    std::vector<std::pair<int32_t, int32_t>> row;
+    for (int32_t u = 0; u < n; ++u) {
+        row.clear();
+        for (int32_t q = 0; q < rl[(size_t)u]; ++q) {
+            int32_t j = rp[(size_t)u] + q;
+            if (fs[(size_t)j] >= 0) row.push_back({cr[(size_t)j].x, fs[(size_t)j]});
+        }
+        std::sort(row.begin(), row.end());
+        for (auto& p : row) {
+            src[k] = u;
+            dst[k] = p.first;
+            flow[k] = p.second;
+            ++k;
+        }
+    }
+    *count = k;
+    return MF_OK;
 }
 
 mf_status mf_get_stats(const mf_graph* g, mf_stats* out) {
@@ -630,10 +743,10 @@ mf_status mf_get_stats(const mf_graph* g, mf_stats* out) {
     return MF_OK;
 }
 
-mf_status mf_profile(mf_graph* g, int32_t enable) {
+mf_status mf_profile(mf_graph* g, int32_t class_mask) {
     mf_status rc = check_handle(g);
     if (rc != MF_OK) return rc;
-    g->profiling = enable != 0;
+    g->prof_mask = (uint32_t)class_mask & 0xFFu;
     for (int c = 0; c < 8; ++c) {
         g->kernel_ms[c] = 0;
         g->kernel_launches[c] = 0;
@@ -653,9 +766,10 @@ mf_status mf_debug_initial_labels(mf_graph* g, int32_t* heights, int64_t* excess
     mf::launch_saturate_source(g->dg, g->ctr, st);
     MF_HIP(hipGetLastError());
     int64_t levels = 0;
-    rc = global_relabel(g, &levels);
+    LoopMode m = solve_mode(g);
+    rc = global_relabel(g, m, &levels);
     if (rc != MF_OK) return rc;
-    mf::launch_build_worklist(g->dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, st);
+    mf::launch_build_worklist(g->dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, false, 1, st);
     MF_HIP(hipGetLastError());
     rc = read_counters(g);
     if (rc != MF_OK) return rc;

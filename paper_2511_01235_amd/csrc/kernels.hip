@@ -217,15 +217,19 @@ __device__ __forceinline__ void append_entries(int add, int v, int2* q, int32_t*
     for (int k = 0; k < add; ++k) q[base + off + k] = make_int2(v, k * GR_CHUNK);
 }
 
-// Heights before the levels: h(t) = 0, h(v) = 0 for deficient v outside
-// {s,t}, every other vertex (s included) |V|.  Level-0 vertices are queued.
-__global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr) {
+// Heights before the levels (Algorithms 4 and 6): h(root) = 0 and, with
+// seed_deficits, h(v) = 0 for every deficient v outside {root, pinned};
+// every other vertex, the pinned one included, gets |V|.  Level-0 vertices
+// are queued.  The solve uses root = t, pinned = s, deficits seeded.
+__global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr,
+                                                 int seed_deficits) {
     const int N = g.n;
     for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
         int v = base + threadIdx.x;
         int add = 0;
         if (v < N) {
-            bool seed = v == g.t || (v != g.s && ld_e(g.e, v) < 0);
+            bool seed = v == g.root ||
+                        (seed_deficits && v != g.pinned && v != g.s && v != g.t && ld_e(g.e, v) < 0);
             g.h[v] = seed ? 0 : N;
             if (seed) add = (g.row_len[v] + GR_CHUNK - 1) / GR_CHUNK;
         }
@@ -240,6 +244,10 @@ __global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounte
 // that still has height |V| gets lv+1 and joins the next frontier.  The
 // frontier size is read on the device; an empty frontier makes the launch a
 // no-op, so the host may run ahead by several levels.
+// FWD = false: backward BFS toward the root over residual in-edges (the
+// solve).  FWD = true: forward BFS from the root over residual out-edges (v
+// joins when res(u,v) > 0), used to fill deficits from t.
+template <bool FWD>
 __global__ void __launch_bounds__(256) k_gr_level(DevGraph g, int lv, const int2* qin, int2* qout,
                                                   DevCounters* ctr) {
     const int N = g.n;
@@ -262,8 +270,9 @@ __global__ void __launch_bounds__(256) k_gr_level(DevGraph g, int lv, const int2
             int v = -1, add = 0;
             if (j < end) {
                 v = g.cr[j].x;
-                if (v != g.s && g.h[v] == N) {
-                    if (g.cr[g.rev[j]].y > 0 && atomicCAS(&g.h[v], N, lv + 1) == N) {
+                if (v != g.pinned && g.h[v] == N) {
+                    int32_t r = FWD ? g.cr[j].y : g.cr[g.rev[j]].y;
+                    if (r > 0 && atomicCAS(&g.h[v], N, lv + 1) == N) {
                         add = (g.row_len[v] + GR_CHUNK - 1) / GR_CHUNK;
                         found++;
                     }
@@ -284,9 +293,11 @@ __global__ void __launch_bounds__(256) k_gr_level(DevGraph g, int lv, const int2
 
 // ---- worklist (Section 5.2, O1) and value (Algorithm 5) --------------------
 
+// sign = +1: active = positive excess below |V| (the solve); sign = -1:
+// active = negative excess below |V| (deficits to fill from t).
 __global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0, int32_t* wl1,
                                                         int32_t* wl2, DevCounters* ctr,
-                                                        int topology) {
+                                                        int topology, int sign) {
     const int N = g.n;
     long long deficit = 0;
     for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
@@ -297,7 +308,7 @@ __global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0
             int64_t ev = g.e[v];
             int hv = g.h[v];
             bool other = v != g.s && v != g.t;
-            act = other && ev > 0 && hv < N;
+            act = other && (sign > 0 ? ev > 0 : ev < 0) && hv < N;
             if (other && ev < 0) deficit += ev;
             if (v == g.t) ctr->e_t = ev;
             len = g.row_len[v];
@@ -323,16 +334,36 @@ __global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0
 // scan compares the height it read once (the note after Section 3.1's
 // termination proof).  A row with no residual slot lifts u to |V|.
 
-__device__ __forceinline__ void do_push(DevGraph& g, int u, int j, int64_t eu) {
-    int32_t r = ld_res(g.cr, j);
-    int64_t d = eu < (int64_t)r ? eu : (int64_t)r;
-    if (d <= 0) return;
-    add_res(g.cr, j, -(int32_t)d);
-    add_res(g.cr, g.rev[j], (int32_t)d);
-    add_e(g.e, u, -d);
-    add_e(g.e, g.cr[j].x, d);
+// PULL = false: u pushes along its residual out-slot j (res[j]) and
+// "amount" is its excess.  PULL = true (filling a deficit from t, the
+// mirror image used to complete a preflow): u pulls along the residual of
+// the in-edge col->u (res[rev[j]]) and "amount" is minus its excess.
+template <bool PULL>
+__device__ __forceinline__ int32_t scan_res(const DevGraph& g, int j) {
+    return PULL ? ld_res(g.cr, g.rev[j]) : ld_res(g.cr, j);
 }
 
+template <bool PULL>
+__device__ __forceinline__ int64_t amount(const DevGraph& g, int u) {
+    int64_t e = ld_e(g.e, u);
+    return PULL ? -e : e;
+}
+
+template <bool PULL>
+__device__ __forceinline__ void do_push(DevGraph& g, int u, int j, int64_t eu) {
+    int jo = PULL ? g.rev[j] : j;  // residual that shrinks
+    int ji = PULL ? j : g.rev[j];  // residual that grows
+    int32_t r = ld_res(g.cr, jo);
+    int64_t d = eu < (int64_t)r ? eu : (int64_t)r;
+    if (d <= 0) return;
+    add_res(g.cr, jo, -(int32_t)d);
+    add_res(g.cr, ji, (int32_t)d);
+    int w = g.cr[j].x;
+    add_e(g.e, PULL ? w : u, -d);
+    add_e(g.e, PULL ? u : w, d);
+}
+
+template <bool PULL>
 __global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl, int count, int kc,
                                                    DevCounters* ctr) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -345,11 +376,11 @@ __global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl
         int hu = g.h[u];
         bytes += 16;
         for (int c = 0; c < kc && hu < N; ++c) {
-            int64_t eu = ld_e(g.e, u);
+            int64_t eu = amount<PULL>(g, u);
             if (eu <= 0) continue;
             int bh = INT_MAX, bj = -1;
             for (int j = beg; j < end; ++j) {
-                if (ld_res(g.cr, j) > 0) {
+                if (scan_res<PULL>(g, j) > 0) {
                     int hv = g.h[g.cr[j].x];
                     if (hv < bh) { bh = hv; bj = j; }
                 }
@@ -357,7 +388,7 @@ __global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl
             bytes += 12ull * (unsigned long long)(end - beg);
             if (bj < 0) { hu = N; g.h[u] = N; break; }
             if (hu > bh) {
-                do_push(g, u, bj, eu);
+                do_push<PULL>(g, u, bj, eu);
                 bytes += 48;
             } else {
                 hu = bh + 1 < N ? bh + 1 : N;
@@ -370,6 +401,7 @@ __global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl
     if (lane_id() == 0) add_bytes(ctr, KC_PR, b);
 }
 
+template <bool PULL>
 __global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, int count, int kc,
                                                  DevCounters* ctr) {
     int w = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -382,12 +414,12 @@ __global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, 
     int hu = bcast(g.h[u]);
     unsigned long long bytes = 16;
     for (int c = 0; c < kc && hu < N; ++c) {
-        int64_t eu = bcast64(ld_e(g.e, u));
+        int64_t eu = bcast64(amount<PULL>(g, u));
         if (eu <= 0) continue;
         unsigned long long best = ~0ull;
         for (int b = beg; b < end; b += WAVE) {
             int j = b + lane;
-            if (j < end && ld_res(g.cr, j) > 0) {
+            if (j < end && scan_res<PULL>(g, j) > 0) {
                 unsigned hv = (unsigned)g.h[g.cr[j].x];
                 unsigned long long key = ((unsigned long long)hv << 32) | (unsigned)j;
                 if (key < best) best = key;
@@ -403,7 +435,7 @@ __global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, 
         int bh = (int)(best >> 32);
         int bj = (int)(unsigned)best;
         if (hu > bh) {
-            if (lane == 0) do_push(g, u, bj, eu);
+            if (lane == 0) do_push<PULL>(g, u, bj, eu);
             bytes += 48;
         } else {
             hu = bh + 1 < N ? bh + 1 : N;
@@ -414,6 +446,7 @@ __global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, 
     if (lane == 0) add_bytes(ctr, KC_PR, bytes);
 }
 
+template <bool PULL>
 __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t* wl, int count,
                                                        int kc, DevCounters* ctr) {
     __shared__ unsigned long long part[BLOCK_PR / WAVE];
@@ -429,14 +462,14 @@ __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t
     int hu = g.h[u];
     unsigned long long bytes = 16;
     for (int c = 0; c < kc && hu < N; ++c) {
-        if (threadIdx.x == 0) e_sh = ld_e(g.e, u);
+        if (threadIdx.x == 0) e_sh = amount<PULL>(g, u);
         __syncthreads();
         int64_t eu = e_sh;
         __syncthreads();
         if (eu <= 0) continue;
         unsigned long long best = ~0ull;
         for (int j = beg + threadIdx.x; j < end; j += BLOCK_PR) {
-            if (ld_res(g.cr, j) > 0) {
+            if (scan_res<PULL>(g, j) > 0) {
                 unsigned hv = (unsigned)g.h[g.cr[j].x];
                 unsigned long long key = ((unsigned long long)hv << 32) | (unsigned)j;
                 if (key < best) best = key;
@@ -457,7 +490,7 @@ __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t
         int bh = (int)(best >> 32);
         int bj = (int)(unsigned)best;
         if (hu > bh) {
-            if (threadIdx.x == 0) do_push(g, u, bj, eu);
+            if (threadIdx.x == 0) do_push<PULL>(g, u, bj, eu);
             bytes += 48;
         } else {
             hu = bh + 1 < N ? bh + 1 : N;
@@ -741,6 +774,31 @@ __global__ void __launch_bounds__(256) k_cut(DevGraph g, uint8_t* side, unsigned
     if (threadIdx.x == 0 && tot) atomicAdd(cut, (unsigned long long)tot);
 }
 
+// ---- flow from residuals (Section 3.1, the three cases per pair) --------------
+
+// For a completed flow: f(u,v) = c(u,v) - c_f(u,v) when positive, else 0.
+// flow_slot[j] gets that value for every used slot with c > 0 and -1 for the
+// rest; *count gets the number of such slots.
+__global__ void __launch_bounds__(256) k_flow_slots(DevGraph g, int32_t* flow_slot,
+                                                    unsigned long long* count) {
+    const int N = g.n;
+    long long c = 0;
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < N; u += gridDim.x * blockDim.x) {
+        int beg = g.row_ptr[u], len = g.row_len[u], cap_end = g.row_ptr[u + 1];
+        for (int j = beg; j < cap_end; ++j) {
+            int f = -1;
+            if (j < beg + len && g.cap[j] > 0) {
+                int d = g.cap[j] - g.cr[j].y;
+                f = d > 0 ? d : 0;
+                ++c;
+            }
+            if (flow_slot) flow_slot[j] = f;
+        }
+    }
+    long long tot = block_sum_i64<256>(c);
+    if (threadIdx.x == 0 && tot) atomicAdd(count, (unsigned long long)tot);
+}
+
 // ---- self-test of the wave primitives ---------------------------------------
 
 __global__ void k_selftest(int* fails) {
@@ -793,35 +851,43 @@ void launch_saturate_source(const DevGraph& g, DevCounters* ctr, hipStream_t st)
     k_saturate_source<<<64, 256, 0, st>>>(g);
 }
 
-void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, hipStream_t st) {
+void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, int seed_deficits, hipStream_t st) {
     k_zero_counters_front<<<1, 64, 0, st>>>(ctr);
-    k_gr_init<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, q0, ctr);
+    k_gr_init<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, q0, ctr, seed_deficits);
 }
 
 void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, DevCounters* ctr,
-                     int grid, hipStream_t st) {
-    k_gr_level<<<grid, 256, 0, st>>>(g, level, qin, qout, ctr);
+                     int grid, bool forward, hipStream_t st) {
+    if (forward)
+        k_gr_level<true><<<grid, 256, 0, st>>>(g, level, qin, qout, ctr);
+    else
+        k_gr_level<false><<<grid, 256, 0, st>>>(g, level, qin, qout, ctr);
 }
 
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
+                           DevCounters* ctr, bool topology, int sign, hipStream_t st) {
+    k_build_worklist<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, wl0, wl1, wl2, ctr, topology ? 1 : 0,
+                                                              sign);
+}
+
+template <bool PULL>
+static void launch_pr_bins(const DevGraph& g, const int32_t* wl, int count, int bin, int kc,
                            DevCounters* ctr, hipStream_t st) {
-    k_build_worklist<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, wl0, wl1, wl2, ctr, 0);
+    if (bin == 0)
+        k_pr_thread<PULL><<<grid_for(count, 256, 1 << 30), 256, 0, st>>>(g, wl, count, kc, ctr);
+    else if (bin == 1)
+        k_pr_wave<PULL><<<grid_for((int64_t)count * WAVE, 256, 1 << 30), 256, 0, st>>>(g, wl, count, kc, ctr);
+    else
+        k_pr_block<PULL><<<count, BLOCK_PR, 0, st>>>(g, wl, count, kc, ctr);
 }
 
-void launch_topology_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
-                              DevCounters* ctr, hipStream_t st) {
-    k_build_worklist<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, wl0, wl1, wl2, ctr, 1);
-}
-
-void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc,
+void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc, bool pull,
                          DevCounters* ctr, hipStream_t st) {
     if (count <= 0) return;
-    if (bin == 0)
-        k_pr_thread<<<grid_for(count, 256, 1 << 30), 256, 0, st>>>(g, wl, count, kc, ctr);
-    else if (bin == 1)
-        k_pr_wave<<<grid_for((int64_t)count * WAVE, 256, 1 << 30), 256, 0, st>>>(g, wl, count, kc, ctr);
+    if (pull)
+        launch_pr_bins<true>(g, wl, count, bin, kc, ctr, st);
     else
-        k_pr_block<<<count, BLOCK_PR, 0, st>>>(g, wl, count, kc, ctr);
+        launch_pr_bins<false>(g, wl, count, bin, kc, ctr, st);
 }
 
 void launch_remove_invalid(const DevGraph& g, const int32_t* wl, int count, int bin,
@@ -875,6 +941,11 @@ void launch_batch_cleanup(BatchTable tb, int32_t* need, const int32_t* slot_of, 
     int64_t items = k > tb.capacity ? k : tb.capacity;
     if (items <= 0) return;
     k_batch_cleanup<<<(int)((items + 255) / 256), 256, 0, st>>>(tb, need, slot_of, win, k);
+}
+
+void launch_flow_slots(const DevGraph& g, int32_t* flow_slot, unsigned long long* count,
+                       hipStream_t st) {
+    k_flow_slots<<<grid_for(g.n, 256, 4096), 256, 0, st>>>(g, flow_slot, count);
 }
 
 void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipStream_t st) {

@@ -19,6 +19,8 @@ namespace mf {
 // and the index rev[j] of the slot col->u in row col.
 struct DevGraph {
     int32_t n, s, t;
+    int32_t root;    // BFS root: t for the solve, s or t while completing a flow
+    int32_t pinned;  // never labelled by the BFS: s for the solve
     int32_t* row_ptr;
     int32_t* row_len;
     int32_t* row_sorted;
@@ -65,14 +67,12 @@ struct BatchTable {
 void launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t st);
 void launch_reset(const DevGraph& g, int64_t slot_cap, hipStream_t st);
 void launch_saturate_source(const DevGraph& g, DevCounters* ctr, hipStream_t st);
-void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, hipStream_t st);
+void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, int seed_deficits, hipStream_t st);
 void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, DevCounters* ctr,
-                     int grid, hipStream_t st);
+                     int grid, bool forward, hipStream_t st);
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
-                           DevCounters* ctr, hipStream_t st);
-void launch_topology_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
-                              DevCounters* ctr, hipStream_t st);
-void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc,
+                           DevCounters* ctr, bool topology, int sign, hipStream_t st);
+void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc, bool pull,
                          DevCounters* ctr, hipStream_t st);
 void launch_remove_invalid(const DevGraph& g, const int32_t* wl, int count, int bin,
                            DevCounters* ctr, hipStream_t st);
@@ -89,6 +89,8 @@ void launch_batch_clamp(const DevGraph& g, const mf_update* upd, int64_t k,
 void launch_batch_cleanup(BatchTable tb, int32_t* need, const int32_t* slot_of, int32_t* win,
                           int64_t k, hipStream_t st);
 void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipStream_t st);
+void launch_flow_slots(const DevGraph& g, int32_t* flow_slot, unsigned long long* count,
+                       hipStream_t st);
 int device_selftest(hipStream_t st);
 
 // ---- host Bi-CSR builder (bicsr.cpp) -------------------------------------

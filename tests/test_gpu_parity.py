@@ -259,6 +259,57 @@ def test_relayout_when_slack_runs_out():
         assert G.stats()["relayouts"] >= 1
 
 
+# --- flow output (certificate) --------------------------------------------------
+
+def _flow_cert(G, n, s, t, value, model):
+    fs, fd, ff = G.get_flow()
+    ms, md, mc = model.arrays()
+    live = mc > 0
+    assert np.array_equal(fs, ms[live]) and np.array_equal(fd, md[live])
+    side, cut = G.min_cut()
+    rc, msg = oracle.cert_check(n, fs, fd, mc[live], s, t, ff.astype(np.int64), side, value)
+    assert rc == 0, msg
+
+
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+def test_get_flow_is_a_max_flow(name):
+    g, stream, k, nb = gen.workload(name)
+    model = _CapModel(g.n, g.src, g.dst, g.cap)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        v = G.maxflow()
+        say("flow static", name)
+        _flow_cert(G, g.n, g.s, g.t, v, model)
+        for b in range(3):
+            u, vv, c = stream.next_batch(k)
+            model.apply(u, vv, c)
+            v = G.apply_batch(u, vv, c)
+            say("flow batch", name, b)
+            _flow_cert(G, g.n, g.s, g.t, v, model)
+            # the completion ran on a copy: the next repair still matches
+        u, vv, c = stream.next_batch(k)
+        model.apply(u, vv, c)
+        ms, md, mc = model.arrays()
+        assert G.apply_batch(u, vv, c) == oracle.max_flow(g.n, ms, md, mc, g.s, g.t)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_get_flow_tiny(seed):
+    rng = np.random.default_rng(9000 + seed)
+    n = int(rng.integers(3, 11))
+    src, dst, cap = _random_small(rng, n, 4 * n, 12)
+    model = _CapModel(n, src, dst, cap)
+    with mf.MaxFlowGraph(n, src, dst, cap, 0, n - 1) as G:
+        v = G.maxflow()
+        assert v == oracle.brute_min_cut(n, src, dst, cap, 0, n - 1)
+        _flow_cert(G, n, 0, n - 1, v, model)
+        for b in range(4):
+            pairs = np.array(list(model.c.keys()), dtype=np.int64).reshape(-1, 2)
+            u, vv, c = gen.random_batch(n, 6, 12, seed=seed * 10 + b, pairs=pairs)
+            model.apply(u, vv, c)
+            v = G.apply_batch(u, vv, c)
+            _flow_cert(G, n, 0, n - 1, v, model)
+
+
 # --- full size: the benchmark workload ------------------------------------------
 
 def test_rmat20_full_size():
