@@ -11,6 +11,7 @@
 #include <chrono>
 #include <climits>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <utility>
@@ -64,6 +65,7 @@ struct mf_graph {
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
     int gr_grid = 1024;
+    int bu_div = mf::GR_BOTTOM_UP_DIV;
 };
 
 namespace {
@@ -148,6 +150,7 @@ void free_structure(mf_graph* g) {
     dfree(g->dg.cr);
     dfree(g->dg.rev);
     dfree(g->dg.cap);
+    dfree(g->dg.capsum);
     dfree(g->win);
     dfree(g->q[0]);
     dfree(g->q[1]);
@@ -188,14 +191,18 @@ mf_status upload_structure(mf_graph* g, const mf::HostBiCSR& b, const std::vecto
     if (dalloc(g, &g->dg.row_ptr, n + 1) != hipSuccess || dalloc(g, &g->dg.row_len, n) != hipSuccess ||
         dalloc(g, &g->dg.row_sorted, n) != hipSuccess || dalloc(g, &g->dg.cr, S) != hipSuccess ||
         dalloc(g, &g->dg.rev, S) != hipSuccess || dalloc(g, &g->dg.cap, S) != hipSuccess ||
+        dalloc(g, &g->dg.capsum, S) != hipSuccess ||
         dalloc(g, &g->win, S) != hipSuccess)
         return MF_ERR_OUT_OF_MEMORY;
     g->q_cap = (int64_t)n + S / mf::GR_CHUNK + 64;
     if (dalloc(g, &g->q[0], g->q_cap) != hipSuccess || dalloc(g, &g->q[1], g->q_cap) != hipSuccess)
         return MF_ERR_OUT_OF_MEMORY;
     std::vector<int2> cr((size_t)S);
-    for (int64_t j = 0; j < S; ++j)
+    std::vector<int32_t> capsum((size_t)S, 0);
+    for (int64_t j = 0; j < S; ++j) {
         cr[(size_t)j] = make_int2(b.col[(size_t)j], res_init.empty() ? b.cap[(size_t)j] : res_init[(size_t)j]);
+        if (b.rev[(size_t)j] >= 0) capsum[(size_t)j] = b.cap[(size_t)j] + b.cap[(size_t)b.rev[(size_t)j]];
+    }
     hipStream_t st = g->stream;
     MF_HIP(hipMemcpyAsync(g->dg.row_ptr, b.row_ptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
     MF_HIP(hipMemcpyAsync(g->dg.row_len, b.row_len.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
@@ -203,6 +210,7 @@ mf_status upload_structure(mf_graph* g, const mf::HostBiCSR& b, const std::vecto
     MF_HIP(hipMemcpyAsync(g->dg.cr, cr.data(), sizeof(int2) * S, hipMemcpyHostToDevice, st));
     MF_HIP(hipMemcpyAsync(g->dg.rev, b.rev.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, st));
     MF_HIP(hipMemcpyAsync(g->dg.cap, b.cap.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.capsum, capsum.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, st));
     mf::launch_fill_i32(g->win, -1, S, st);
     MF_HIP(hipGetLastError());
     MF_HIP(hipStreamSynchronize(st));  // host vectors die on return
@@ -273,7 +281,7 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
         for (int i = 0; i < chunk; ++i, ++level)
             timed(g, mf::KC_GR, [&] {
                 mf::launch_gr_level(m.dg, level, g->q[level & 1], g->q[(level + 1) & 1], g->ctr,
-                                    g->gr_grid, m.forward, st);
+                                    g->gr_grid, m.forward, g->bu_div, st);
             });
         MF_HIP(hipGetLastError());
         mf_status rc = read_counters(g);
@@ -512,6 +520,8 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     g->gr_grid = std::max(64, cus * 4);
+    if (const char* env = std::getenv("MF_GR_BOTTOM_UP_DIV")) g->bu_div = std::atoi(env);
+    if (const char* env = std::getenv("MF_GR_GRID")) g->gr_grid = std::max(1, std::atoi(env));
     g->dg.n = n;
     g->dg.s = s;
     g->dg.t = t;
@@ -725,8 +735,8 @@ mf_status mf_get_stats(const mf_graph* g, mf_stats* out) {
     out->pairs = g->pairs;
     out->slot_capacity = g->slot_cap;
     out->slots = 2 * g->pairs;
-    // slot arrays (col+res, rev, cap, win), two frontier queues, per-vertex arrays
-    out->device_bytes = g->slot_cap * 20 + 2 * g->q_cap * 8 + (int64_t)g->n * (4 * 3 + 8 + 4 + 12 + 4 + 1) +
+    // slot arrays (col+res, rev, cap, capsum, win), two frontier queues, per-vertex arrays
+    out->device_bytes = g->slot_cap * 24 + 2 * g->q_cap * 8 + (int64_t)g->n * (4 * 3 + 8 + 4 + 12 + 4 + 1) +
                         g->k_cap * (4 + 4 + 12) + (int64_t)g->tb.capacity * (8 + 8 + 8);
     out->kernel_cycles = g->kc;
     out->relayouts = g->relayouts;

@@ -239,56 +239,117 @@ __global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounte
         add_bytes(ctr, KC_GR, 12ull * (unsigned long long)N);
 }
 
-// One BFS level, one wave per frontier entry: every residual in-neighbour v
-// of a level-`lv` vertex u (slot j = u->v, residual v->u is res[rev[j]] > 0)
-// that still has height |V| gets lv+1 and joins the next frontier.  The
-// frontier size is read on the device; an empty frontier makes the launch a
-// no-op, so the host may run ahead by several levels.
-// FWD = false: backward BFS toward the root over residual in-edges (the
-// solve).  FWD = true: forward BFS from the root over residual out-edges (v
-// joins when res(u,v) > 0), used to fill deficits from t.
+// One BFS level.  Top-down (small frontier): each block takes 256 frontier
+// entries, prefix-sums their slot counts in LDS and lets consecutive threads
+// take consecutive slots of the concatenated rows (coalesced, balanced
+// across short and long rows); every neighbour v of a level-`lv` vertex u
+// that can still be labelled and has the residual needed (backward: v->u,
+// i.e. capsum[j] - res[j] > 0 for slot j = u->v; forward: u->v, res[j] > 0)
+// gets lv+1 and joins the next frontier.  Bottom-up (frontier above
+// n / bu_div entries, bu_div > 0): every unlabelled vertex v scans its own row
+// for a neighbour at height lv with the residual needed (backward: res(v->u)
+// = res[j] > 0; forward: res(u->v) = capsum[j] - res[j] > 0) and stops at the
+// first.  Both produce exactly the BFS levels.  The frontier size is read on
+// the device; an empty frontier makes the launch a no-op, so the host may run
+// ahead by several levels.
+constexpr int GR_BLOCK = 256;
+
 template <bool FWD>
-__global__ void __launch_bounds__(256) k_gr_level(DevGraph g, int lv, const int2* qin, int2* qout,
-                                                  DevCounters* ctr) {
+__global__ void __launch_bounds__(GR_BLOCK) k_gr_level(DevGraph g, int lv, const int2* qin, int2* qout,
+                                                       DevCounters* ctr, int bu_div) {
+    __shared__ int s_u[GR_BLOCK];
+    __shared__ int s_beg[GR_BLOCK];
+    __shared__ int s_pre[GR_BLOCK + 1];
+    __shared__ int s_wsum[GR_BLOCK / WAVE];
     const int N = g.n;
     const int cnt = bcast(ctr->front[lv % 3]);
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
+    if (cnt == 0) return;
     int32_t* out_cnt = &ctr->front[(lv + 1) % 3];
-    int lane = lane_id();
-    int nwaves = gridDim.x * (blockDim.x / WAVE);
-    int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    unsigned long long scanned = 0, found = 0;
-    for (int i = wid; i < cnt; i += nwaves) {
-        int2 ent = qin[i];
-        int u = bcast(ent.x);
-        int rb = bcast(g.row_ptr[u]);
-        int beg = rb + bcast(ent.y);
-        int end = min(rb + bcast(g.row_len[u]), beg + GR_CHUNK);
-        scanned += (unsigned long long)(end - beg);
-        for (int b = beg; b < end; b += WAVE) {
-            int j = b + lane;
-            int v = -1, add = 0;
-            if (j < end) {
-                v = g.cr[j].x;
-                if (v != g.pinned && g.h[v] == N) {
-                    int32_t r = FWD ? g.cr[j].y : g.cr[g.rev[j]].y;
-                    if (r > 0 && atomicCAS(&g.h[v], N, lv + 1) == N) {
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    unsigned long long scanned = 0, found = 0, exam = 0;
+    if (bu_div > 0 && cnt > N / bu_div) {
+        for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
+            int v = base + tid;
+            int add = 0;
+            if (v < N) ++exam;
+            if (v < N && v != g.pinned && g.h[v] == N) {
+                int beg = g.row_ptr[v], end = beg + g.row_len[v];
+                exam += 2;  // the row bounds
+                for (int j = beg; j < end; ++j) {
+                    int2 cr = g.cr[j];
+                    ++scanned;
+                    int32_t r = FWD ? g.capsum[j] - cr.y : cr.y;
+                    if (r > 0 && g.h[cr.x] == lv) {
+                        g.h[v] = lv + 1;
                         add = (g.row_len[v] + GR_CHUNK - 1) / GR_CHUNK;
                         found++;
+                        break;
                     }
                 }
             }
             append_entries(add, v, qout, out_cnt);
         }
+    } else {
+        // entries per block: spread small frontiers over many blocks, up to
+        // GR_BLOCK entries per block for large ones
+        const int per = min(GR_BLOCK, max(1, (cnt + (int)gridDim.x - 1) / (int)gridDim.x));
+        for (int eb = blockIdx.x * per; eb < cnt; eb += gridDim.x * per) {
+            // stage this block's entries and prefix-sum their slot counts
+            int idx = eb + tid;
+            int len = 0;
+            if (tid < per && idx < cnt) {
+                int2 ent = qin[idx];
+                int rl = g.row_len[ent.x];
+                s_u[tid] = ent.x;
+                s_beg[tid] = g.row_ptr[ent.x] + ent.y;
+                len = min(rl - ent.y, GR_CHUNK);
+                exam += 3;
+            }
+            int wtot;
+            int wex = wave_excl_scan(len, &wtot);
+            if (lane == 0) s_wsum[tid / WAVE] = wtot;
+            __syncthreads();
+            int woff = 0, total = 0;
+            for (int w = 0; w < GR_BLOCK / WAVE; ++w) {
+                if (w < tid / WAVE) woff += s_wsum[w];
+                total += s_wsum[w];
+            }
+            s_pre[tid] = woff + wex;
+            if (tid == GR_BLOCK - 1) s_pre[GR_BLOCK] = total;
+            __syncthreads();
+            scanned += (unsigned long long)total;  // counted once per block (thread 0 below)
+            for (int base = 0; base < total; base += GR_BLOCK) {
+                int i = base + tid;
+                int v = -1, add = 0;
+                if (i < total) {
+                    // last entry k with s_pre[k] <= i
+                    int lo = 0, hi = GR_BLOCK;
+                    while (hi - lo > 1) {
+                        int mid = (lo + hi) >> 1;
+                        if (s_pre[mid] <= i) lo = mid;
+                        else hi = mid;
+                    }
+                    int j = s_beg[lo] + (i - s_pre[lo]);
+                    int2 cr = g.cr[j];
+                    v = cr.x;
+                    int32_t r = FWD ? cr.y : g.capsum[j] - cr.y;
+                    if (r > 0 && v != g.pinned && g.h[v] == N && atomicCAS(&g.h[v], N, lv + 1) == N) {
+                        add = (g.row_len[v] + GR_CHUNK - 1) / GR_CHUNK;
+                        found++;
+                    }
+                }
+                append_entries(add, v, qout, out_cnt);
+            }
+            __syncthreads();  // LDS is restaged next round
+        }
+        if (tid != 0) scanned = 0;
     }
-    if (lane == 0) {
-        // per scanned slot: col, rev, res[rev], h[col]; per entry its row bounds;
-        // per discovered vertex the height CAS and the queue entry
-        unsigned long long b = 16ull * scanned;
-        add_bytes(ctr, KC_GR, b);
-    }
-    unsigned long long f = wave_sum_u64(found);
-    if (lane == 0 && f) add_bytes(ctr, KC_GR, 16ull * f);
+    // per scanned slot: col, res, capsum, h[col]; per staged entry or examined
+    // vertex its words; per discovered vertex the CAS and queue entry
+    unsigned long long b = wave_sum_u64(16ull * scanned + 4ull * exam + 16ull * found);
+    if (lane == 0 && b) add_bytes(ctr, KC_GR, b);
 }
 
 // ---- worklist (Section 5.2, O1) and value (Algorithm 5) --------------------
@@ -363,6 +424,46 @@ __device__ __forceinline__ void do_push(DevGraph& g, int u, int j, int64_t eu) {
     add_e(g.e, PULL ? u : w, d);
 }
 
+// Key of slot j for the lowest-neighbour search: (h(col) << 32 | j) when the
+// residual the move would use is positive, else ~0.  The slot's col and res
+// come from one coherent 64-bit load.
+__device__ __forceinline__ unsigned long long ld_slot(const int2* cr, int j) {
+    return __hip_atomic_load(reinterpret_cast<unsigned long long*>(const_cast<int2*>(&cr[j])),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Scan slots [b + 0, b + STEP, ... b + (U-1)*STEP] (those below end) and fold
+// their keys into best.  All loads of the group are issued before any height
+// gather, so U slots are in flight per lane.
+template <bool PULL, int U, int STEP>
+__device__ __forceinline__ void scan_group(const DevGraph& g, int b, int end, unsigned long long& best) {
+    unsigned long long sv[U];
+    int32_t r[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        int j = b + q * STEP;
+        sv[q] = j < end ? ld_slot(g.cr, j) : 0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        int j = b + q * STEP;
+        r[q] = j < end ? (PULL ? ld_res(g.cr, g.rev[j]) : (int32_t)(sv[q] >> 32)) : 0;
+    }
+    unsigned hv[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) hv[q] = r[q] > 0 ? (unsigned)g.h[(int)(unsigned)sv[q]] : 0u;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        int j = b + q * STEP;
+        if (r[q] > 0) {
+            unsigned long long key = ((unsigned long long)hv[q] << 32) | (unsigned)j;
+            if (key < best) best = key;
+        }
+    }
+}
+
+constexpr int PR_UNROLL = 4;
+
 template <bool PULL>
 __global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl, int count, int kc,
                                                    DevCounters* ctr) {
@@ -378,15 +479,12 @@ __global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl
         for (int c = 0; c < kc && hu < N; ++c) {
             int64_t eu = amount<PULL>(g, u);
             if (eu <= 0) continue;
-            int bh = INT_MAX, bj = -1;
-            for (int j = beg; j < end; ++j) {
-                if (scan_res<PULL>(g, j) > 0) {
-                    int hv = g.h[g.cr[j].x];
-                    if (hv < bh) { bh = hv; bj = j; }
-                }
-            }
+            unsigned long long best = ~0ull;
+            for (int b = beg; b < end; b += PR_UNROLL) scan_group<PULL, PR_UNROLL, 1>(g, b, end, best);
             bytes += 12ull * (unsigned long long)(end - beg);
-            if (bj < 0) { hu = N; g.h[u] = N; break; }
+            if (best == ~0ull) { hu = N; g.h[u] = N; break; }
+            int bh = (int)(best >> 32);
+            int bj = (int)(unsigned)best;
             if (hu > bh) {
                 do_push<PULL>(g, u, bj, eu);
                 bytes += 48;
@@ -417,14 +515,8 @@ __global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, 
         int64_t eu = bcast64(amount<PULL>(g, u));
         if (eu <= 0) continue;
         unsigned long long best = ~0ull;
-        for (int b = beg; b < end; b += WAVE) {
-            int j = b + lane;
-            if (j < end && scan_res<PULL>(g, j) > 0) {
-                unsigned hv = (unsigned)g.h[g.cr[j].x];
-                unsigned long long key = ((unsigned long long)hv << 32) | (unsigned)j;
-                if (key < best) best = key;
-            }
-        }
+        for (int b = beg; b < end; b += PR_UNROLL * WAVE)
+            scan_group<PULL, PR_UNROLL, WAVE>(g, b + lane, end, best);
         best = wave_min_u64(best);
         bytes += 12ull * (unsigned long long)(end - beg);
         if (best == ~0ull) {
@@ -468,13 +560,8 @@ __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t
         __syncthreads();
         if (eu <= 0) continue;
         unsigned long long best = ~0ull;
-        for (int j = beg + threadIdx.x; j < end; j += BLOCK_PR) {
-            if (scan_res<PULL>(g, j) > 0) {
-                unsigned hv = (unsigned)g.h[g.cr[j].x];
-                unsigned long long key = ((unsigned long long)hv << 32) | (unsigned)j;
-                if (key < best) best = key;
-            }
-        }
+        for (int b = beg; b < end; b += PR_UNROLL * BLOCK_PR)
+            scan_group<PULL, PR_UNROLL, BLOCK_PR>(g, b + threadIdx.x, end, best);
         best = wave_min_u64(best);
         if (lane == 0) part[wv] = best;
         __syncthreads();
@@ -684,9 +771,11 @@ __global__ void __launch_bounds__(256) k_batch_insert(DevGraph g, BatchTable tb)
     int sa = tb.slot[2 * idx], sb = tb.slot[2 * idx + 1];
     g.cr[sa] = make_int2(b, 0);
     g.cap[sa] = 0;
+    g.capsum[sa] = 0;
     g.rev[sa] = sb;
     g.cr[sb] = make_int2(a, 0);
     g.cap[sb] = 0;
+    g.capsum[sb] = 0;
     g.rev[sb] = sa;
     atomicAdd(&g.row_len[a], 1);
     atomicAdd(&g.row_len[b], 1);
@@ -712,7 +801,11 @@ __global__ void __launch_bounds__(256) k_batch_apply(DevGraph g, const mf_update
     int32_t c = upd[i].cap;
     int32_t delta = c - g.cap[j];
     g.cap[j] = c;
-    if (delta) add_res(g.cr, j, delta);
+    if (delta) {
+        add_res(g.cr, j, delta);
+        atomicAdd(&g.capsum[j], delta);
+        atomicAdd(&g.capsum[g.rev[j]], delta);
+    }
 }
 
 // Over-capacity flow goes back (Algorithm 5, second loop): if c_f(u,v) < 0,
@@ -857,11 +950,11 @@ void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, int seed_defi
 }
 
 void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, DevCounters* ctr,
-                     int grid, bool forward, hipStream_t st) {
+                     int grid, bool forward, int bu_div, hipStream_t st) {
     if (forward)
-        k_gr_level<true><<<grid, 256, 0, st>>>(g, level, qin, qout, ctr);
+        k_gr_level<true><<<grid, GR_BLOCK, 0, st>>>(g, level, qin, qout, ctr, bu_div);
     else
-        k_gr_level<false><<<grid, 256, 0, st>>>(g, level, qin, qout, ctr);
+        k_gr_level<false><<<grid, GR_BLOCK, 0, st>>>(g, level, qin, qout, ctr, bu_div);
 }
 
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,

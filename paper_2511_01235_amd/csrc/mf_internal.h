@@ -16,7 +16,9 @@ namespace mf {
 // is slack for inserted pairs.  The first row_sorted[v] slots are sorted by
 // column (the rows as loaded); inserted slots follow unsorted.  Slot j holds
 // {col, res} (neighbour and residual capacity u->col), its capacity cap[j]
-// and the index rev[j] of the slot col->u in row col.
+// and the index rev[j] of the slot col->u in row col.  The two residuals of
+// a pair always sum to its two capacities (Section 3.1), so capsum[j] lets a
+// row scan see the reverse residual without touching the reverse slot.
 struct DevGraph {
     int32_t n, s, t;
     int32_t root;    // BFS root: t for the solve, s or t while completing a flow
@@ -27,6 +29,7 @@ struct DevGraph {
     int2* cr;
     int32_t* rev;
     int32_t* cap;
+    int32_t* capsum;  // cap[j] + cap[rev[j]]: res[rev[j]] = capsum[j] - res[j] between sweeps
     int64_t* e;
     int32_t* h;
 };
@@ -50,10 +53,14 @@ enum KernelClass { KC_GR = 0, KC_PR = 1, KC_RIE = 2, KC_WL = 3, KC_BATCH = 4, KC
 // Degree bins for the worklist: rows up to BIN0_MAX slots get one thread,
 // up to BIN1_MAX one wave, longer rows one 1024-thread block.
 constexpr int BIN0_MAX = 16;
-constexpr int BIN1_MAX = 4096;
+constexpr int BIN1_MAX = 512;
 constexpr int BLOCK_PR = 1024;
 // Global-relabel frontier entries cover at most GR_CHUNK slots of a row.
-constexpr int GR_CHUNK = 1024;
+constexpr int GR_CHUNK = 256;
+// A level scans bottom-up (unvisited vertices look for a parent in their own
+// row) when its frontier holds more than n / bu_div entries; bu_div = 0 keeps
+// every level top-down.  Default below; MF_GR_BOTTOM_UP_DIV overrides it.
+constexpr int GR_BOTTOM_UP_DIV = 0;
 
 // Batch scratch: hash table of absent pairs, keyed by the unordered pair.
 struct BatchTable {
@@ -69,7 +76,7 @@ void launch_reset(const DevGraph& g, int64_t slot_cap, hipStream_t st);
 void launch_saturate_source(const DevGraph& g, DevCounters* ctr, hipStream_t st);
 void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, int seed_deficits, hipStream_t st);
 void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, DevCounters* ctr,
-                     int grid, bool forward, hipStream_t st);
+                     int grid, bool forward, int bu_div, hipStream_t st);
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
                            DevCounters* ctr, bool topology, int sign, hipStream_t st);
 void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc, bool pull,
