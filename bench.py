@@ -53,6 +53,11 @@ def main():
     ap.add_argument("--scratch-runs", type=int, default=3)
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kc", type=int, default=0, help="push/relabel cycles per launch (0: m/n)")
+    ap.add_argument("--relabel-mode", type=int, default=0,
+                    help="0: one launch per BFS level; 1: one cooperative launch per relabel")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="repairs start with one sweep on the previous heights")
     ap.add_argument("--profile-all", action="store_true",
                     help="event-time every kernel class (adds event overhead to the steps)")
     args = ap.parse_args()
@@ -78,7 +83,9 @@ def main():
     batches_np = [bstream.next_batch(k) for _ in range(total)]
     log(f"generated {g.name}: n={g.n} m={g.m} batches={total}x{k} in {time.time() - t0:.1f}s")
 
-    G = mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0)
+    G = mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0,
+                        kernel_cycles=args.kc, warm_start=args.warm_start,
+                        relabel_mode=args.relabel_mode)
     st = G.stats()
     m_unique = None
     # static solve: median of a few from-zero runs on the loaded graph
@@ -95,6 +102,14 @@ def main():
     m_unique = int(key.size)
     static_med = float(np.median(static_ms))
     log(f"static value {static_val}: {static_ms} ms; iterations {G.stats()['last_iterations']}")
+
+    # a plain copy of known size (64 Mi int32 = 256 MiB read + 256 MiB written): under
+    # `rocprofv3 --pmc FETCH_SIZE` / `WRITE_SIZE` it calibrates the counters' units
+    cal_src = torch.ones(64 << 20, dtype=torch.int32, device=dev)
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    torch.cuda.synchronize()
+    del cal_src, cal_dst
 
     dev_batches = [torch.from_numpy(np.ascontiguousarray(np.stack(b, 1).astype(np.int32))).to(dev)
                    for b in batches_np]
@@ -141,6 +156,8 @@ def main():
     launches = prof["kernel_launches"][cls]
     kms = prof["kernel_ms"][cls]
     kbytes = prof["kernel_bytes"][cls]
+    if cls == "global_relabel" and prof["kernel_launches"]["worklist"] == 0:
+        kbytes += prof["kernel_bytes"]["worklist"]  # worklist build fused into the relabel launch
     achieved = (kbytes / (kms * 1e-3)) / 1e9 if kms > 0 else 0.0
     roofline = {"bound": "hbm", "kernel_class": cls, "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
@@ -169,7 +186,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "n": g.n,
                    "m_edges_generated": g.m, "m_pairs": m_unique, "s": g.s, "t": g.t,
-                   "batch_size": k, "kernel_cycles": st["kernel_cycles"]},
+                   "batch_size": k, "kernel_cycles": st["kernel_cycles"],
+                   "warm_start": bool(args.warm_start), "relabel_mode": args.relabel_mode},
         "incremental_ms_p50": round(float(np.percentile(arr, 50)), 4),
         "incremental_ms_p90": round(float(np.percentile(arr, 90)), 4),
         "incremental_ms_p99": round(float(np.percentile(arr, 99)), 4),

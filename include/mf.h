@@ -62,6 +62,12 @@ typedef struct mf_options {
     int32_t insert_slack_min;  /* free slots kept per row for inserted pairs; <= 0: 2 */
     int32_t insert_slack_pct;  /* plus this percentage of the row's length; <= 0: 12 */
     int64_t max_iterations;    /* cap on global relabels per call; <= 0: 4n + 1000 */
+    int32_t warm_start;        /* 1: a repair first runs one push-relabel and remove-invalid-edges
+                                  sweep on the heights left by the previous solve, then the loop;
+                                  0 (default): the loop right away (Algorithm 5) */
+    int32_t relabel_mode;      /* 0 (default): one launch per BFS level; 1: the whole global
+                                  relabel and worklist build in one cooperative launch with a grid
+                                  barrier per level (falls back to 0 where unsupported) */
 } mf_options;
 
 /* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its

@@ -66,6 +66,7 @@ struct mf_graph {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
     int gr_grid = 1024;
     int bu_div = mf::GR_BOTTOM_UP_DIV;
+    int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
 };
 
 namespace {
@@ -297,6 +298,38 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
     return MF_OK;
 }
 
+// Global relabel followed by the worklist build (and value), leaving the
+// counters in ctr_h.  With cooperative launch support this is one persistent
+// kernel (every BFS level behind a grid barrier); otherwise one launch per
+// level plus one for the worklist.
+mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) {
+    hipStream_t st = g->stream;
+    if (g->persistent_grid > 0) {
+        hipError_t err = hipSuccess;
+        timed(g, mf::KC_GR, [&] {
+            err = mf::launch_gr_persistent(m.dg, g->q[0], g->q[1], g->ctr, g->bu_div, m.seed_deficits,
+                                           m.forward, g->wl[0], g->wl[1], g->wl[2], m.topology, m.sign,
+                                           g->persistent_grid, st);
+        });
+        MF_HIP(err);
+        mf_status rc = read_counters(g);
+        if (rc != MF_OK) return rc;
+        if (g->ctr_h->bar_err) {
+            g->poisoned = true;
+            return MF_ERR_DEVICE;
+        }
+        *levels += g->ctr_h->levels;
+        return MF_OK;
+    }
+    mf_status rc = global_relabel(g, m, levels);
+    if (rc != MF_OK) return rc;
+    timed(g, mf::KC_WL, [&] {
+        mf::launch_build_worklist(m.dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, m.topology, m.sign, st);
+    });
+    MF_HIP(hipGetLastError());
+    return read_counters(g);
+}
+
 // Loop {global relabel; worklist; stop if no active vertex; push-relabel;
 // remove invalid edges}.  The stop test is taken right after a fresh global
 // relabel, so at exit A = {h = |V|} is a cut whose capacity is the value.
@@ -304,13 +337,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     hipStream_t st = g->stream;
     int64_t iters = 0, levels = 0, active_sum = 0;
     for (;;) {
-        mf_status rc = global_relabel(g, m, &levels);
-        if (rc != MF_OK) return rc;
-        timed(g, mf::KC_WL, [&] {
-            mf::launch_build_worklist(m.dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, m.topology, m.sign, st);
-        });
-        MF_HIP(hipGetLastError());
-        rc = read_counters(g);
+        mf_status rc = relabel_and_worklist(g, m, &levels);
         if (rc != MF_OK) return rc;
         const DevCounters& c = *g->ctr_h;
         int active = c.wl[3];
@@ -338,6 +365,29 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     g->last_iterations = iters;
     g->last_levels = levels;
     g->last_active_sum = active_sum;
+    return MF_OK;
+}
+
+// One sweep on the heights the previous solve left: worklist, push-relabel,
+// remove-invalid-edges.  Only the loop that follows certifies the value.
+mf_status warm_sweep(mf_graph* g) {
+    hipStream_t st = g->stream;
+    LoopMode m = solve_mode(g);
+    mf::launch_zero_loop_counters(g->ctr, st);
+    timed(g, mf::KC_WL, [&] {
+        mf::launch_build_worklist(m.dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, m.topology, 1, st);
+    });
+    MF_HIP(hipGetLastError());
+    mf_status rc = read_counters(g);
+    if (rc != MF_OK) return rc;
+    int cnt[3] = {g->ctr_h->wl[0], g->ctr_h->wl[1], g->ctr_h->wl[2]};
+    for (int b = 0; b < 3; ++b)
+        if (cnt[b])
+            timed(g, mf::KC_PR, [&] { mf::launch_push_relabel(m.dg, g->wl[b], cnt[b], b, g->kc, false, g->ctr, st); });
+    for (int b = 0; b < 3; ++b)
+        if (cnt[b])
+            timed(g, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, g->wl[b], cnt[b], b, g->ctr, st); });
+    MF_HIP(hipGetLastError());
     return MF_OK;
 }
 
@@ -433,6 +483,10 @@ mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_
         g->pairs += c.new_pairs;
         timed(g, mf::KC_INIT, [&] { mf::launch_saturate_source(g->dg, g->ctr, st); });
         MF_HIP(hipGetLastError());
+        if (g->opt.warm_start) {
+            rc = warm_sweep(g);
+            if (rc != MF_OK) return rc;
+        }
         return run_loop(g, solve_mode(g), value);
     }
     return MF_ERR_OUT_OF_MEMORY;  // slack could not be made to fit
@@ -522,6 +576,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     g->gr_grid = std::max(64, cus * 4);
     if (const char* env = std::getenv("MF_GR_BOTTOM_UP_DIV")) g->bu_div = std::atoi(env);
     if (const char* env = std::getenv("MF_GR_GRID")) g->gr_grid = std::max(1, std::atoi(env));
+    if (o.relabel_mode == 1) g->persistent_grid = mf::persistent_gr_grid(dev);
     g->dg.n = n;
     g->dg.s = s;
     g->dg.t = t;
@@ -777,11 +832,8 @@ mf_status mf_debug_initial_labels(mf_graph* g, int32_t* heights, int64_t* excess
     MF_HIP(hipGetLastError());
     int64_t levels = 0;
     LoopMode m = solve_mode(g);
-    rc = global_relabel(g, m, &levels);
-    if (rc != MF_OK) return rc;
-    mf::launch_build_worklist(g->dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, false, 1, st);
-    MF_HIP(hipGetLastError());
-    rc = read_counters(g);
+    m.topology = false;
+    rc = relabel_and_worklist(g, m, &levels);
     if (rc != MF_OK) return rc;
     settle_events(g);
     const DevCounters c = *g->ctr_h;

@@ -23,8 +23,10 @@
 // a fresh global relabel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <cstdlib>
 
 #include "mf_internal.h"
 
@@ -202,6 +204,9 @@ __global__ void k_zero_counters_front(DevCounters* ctr) {
     if (threadIdx.x == 0) {
         ctr->deficit_sum = 0;
         ctr->e_t = 0;
+        ctr->bar_count = 0;
+        ctr->bar_err = 0;
+        ctr->levels = 0;
     }
 }
 
@@ -221,8 +226,8 @@ __device__ __forceinline__ void append_entries(int add, int v, int2* q, int32_t*
 // seed_deficits, h(v) = 0 for every deficient v outside {root, pinned};
 // every other vertex, the pinned one included, gets |V|.  Level-0 vertices
 // are queued.  The solve uses root = t, pinned = s, deficits seeded.
-__global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr,
-                                                 int seed_deficits) {
+__device__ __forceinline__ void gr_init_body(const DevGraph& g, int2* q0, DevCounters* ctr,
+                                             int seed_deficits) {
     const int N = g.n;
     for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
         int v = base + threadIdx.x;
@@ -237,6 +242,11 @@ __global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounte
     }
     if (blockIdx.x == 0 && threadIdx.x == 0)
         add_bytes(ctr, KC_GR, 12ull * (unsigned long long)N);
+}
+
+__global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr,
+                                                 int seed_deficits) {
+    gr_init_body(g, q0, ctr, seed_deficits);
 }
 
 // One BFS level.  Top-down (small frontier): each block takes 256 frontier
@@ -254,47 +264,94 @@ __global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounte
 // ahead by several levels.
 constexpr int GR_BLOCK = 256;
 
-template <bool FWD>
-__global__ void __launch_bounds__(GR_BLOCK) k_gr_level(DevGraph g, int lv, const int2* qin, int2* qout,
-                                                       DevCounters* ctr, int bu_div) {
-    __shared__ int s_u[GR_BLOCK];
-    __shared__ int s_beg[GR_BLOCK];
-    __shared__ int s_pre[GR_BLOCK + 1];
-    __shared__ int s_wsum[GR_BLOCK / WAVE];
+// The work of one level for a block of BS threads; cnt = the frontier size.
+template <bool FWD, int BS>
+__device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt, const int2* qin,
+                                              int2* qout, DevCounters* ctr, int bu_div) {
+    __shared__ int s_u[BS];
+    __shared__ int s_beg[BS];
+    __shared__ int s_pre[BS + 1];
+    __shared__ int s_wsum[BS / WAVE];
     const int N = g.n;
-    const int cnt = bcast(ctr->front[lv % 3]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
-    if (cnt == 0) return;
     int32_t* out_cnt = &ctr->front[(lv + 1) % 3];
     const int tid = threadIdx.x;
     const int lane = lane_id();
     unsigned long long scanned = 0, found = 0, exam = 0;
     if (bu_div > 0 && cnt > N / bu_div) {
+        // bottom-up: threads check up to BU_THREAD_SLOTS slots of their own
+        // row (four loads in flight); longer rows without a hit go to a
+        // block-local list that the block's waves finish one row at a time
+        __shared__ int s_defer[BS];
+        __shared__ int s_ndefer;
         for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
+            if (tid == 0) s_ndefer = 0;
+            __syncthreads();
             int v = base + tid;
             int add = 0;
             if (v < N) ++exam;
             if (v < N && v != g.pinned && g.h[v] == N) {
-                int beg = g.row_ptr[v], end = beg + g.row_len[v];
+                int beg = g.row_ptr[v], len = g.row_len[v];
+                int end = beg + min(len, BU_THREAD_SLOTS);
                 exam += 2;  // the row bounds
-                for (int j = beg; j < end; ++j) {
-                    int2 cr = g.cr[j];
-                    ++scanned;
-                    int32_t r = FWD ? g.capsum[j] - cr.y : cr.y;
-                    if (r > 0 && g.h[cr.x] == lv) {
-                        g.h[v] = lv + 1;
-                        add = (g.row_len[v] + GR_CHUNK - 1) / GR_CHUNK;
-                        found++;
-                        break;
-                    }
+                bool hit = false;
+                for (int j = beg; j < end && !hit; j += 4) {
+                    int2 c4[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) c4[q] = j + q < end ? g.cr[j + q] : make_int2(0, 0);
+                    int32_t r4[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        r4[q] = j + q < end ? (FWD ? g.capsum[j + q] - c4[q].y : c4[q].y) : 0;
+                    int h4[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) h4[q] = r4[q] > 0 ? g.h[c4[q].x] : -1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) hit = hit || h4[q] == lv;
+                    scanned += (unsigned long long)min(4, end - j);
+                }
+                if (hit) {
+                    g.h[v] = lv + 1;
+                    add = (len + GR_CHUNK - 1) / GR_CHUNK;
+                    found++;
+                } else if (len > BU_THREAD_SLOTS) {
+                    s_defer[atomicAdd(&s_ndefer, 1)] = v;
                 }
             }
             append_entries(add, v, qout, out_cnt);
+            __syncthreads();
+            const int nd = s_ndefer;
+            for (int d = tid / WAVE; d < nd; d += BS / WAVE) {
+                int w = s_defer[d];
+                int beg = g.row_ptr[w] + BU_THREAD_SLOTS, end = g.row_ptr[w] + g.row_len[w];
+                bool hit = false;
+                for (int b = beg; b < end; b += WAVE) {
+                    int j = b + lane;
+                    bool my = false;
+                    if (j < end) {
+                        int2 c = g.cr[j];
+                        int32_t r = FWD ? g.capsum[j] - c.y : c.y;
+                        my = r > 0 && g.h[c.x] == lv;
+                    }
+                    scanned += (unsigned long long)(j < end);
+                    if (__ballot(my)) {
+                        hit = true;
+                        break;
+                    }
+                }
+                int addw = 0;
+                if (hit && lane == 0) {
+                    g.h[w] = lv + 1;
+                    addw = (g.row_len[w] + GR_CHUNK - 1) / GR_CHUNK;
+                    found++;
+                }
+                append_entries(addw, w, qout, out_cnt);
+            }
+            __syncthreads();  // s_defer / s_ndefer are reused next round
         }
     } else {
         // entries per block: spread small frontiers over many blocks, up to
-        // GR_BLOCK entries per block for large ones
-        const int per = min(GR_BLOCK, max(1, (cnt + (int)gridDim.x - 1) / (int)gridDim.x));
+        // BS entries per block for large ones
+        const int per = min(BS, max(1, (cnt + (int)gridDim.x - 1) / (int)gridDim.x));
         for (int eb = blockIdx.x * per; eb < cnt; eb += gridDim.x * per) {
             // stage this block's entries and prefix-sum their slot counts
             int idx = eb + tid;
@@ -312,20 +369,20 @@ __global__ void __launch_bounds__(GR_BLOCK) k_gr_level(DevGraph g, int lv, const
             if (lane == 0) s_wsum[tid / WAVE] = wtot;
             __syncthreads();
             int woff = 0, total = 0;
-            for (int w = 0; w < GR_BLOCK / WAVE; ++w) {
+            for (int w = 0; w < BS / WAVE; ++w) {
                 if (w < tid / WAVE) woff += s_wsum[w];
                 total += s_wsum[w];
             }
             s_pre[tid] = woff + wex;
-            if (tid == GR_BLOCK - 1) s_pre[GR_BLOCK] = total;
+            if (tid == BS - 1) s_pre[BS] = total;
             __syncthreads();
             scanned += (unsigned long long)total;  // counted once per block (thread 0 below)
-            for (int base = 0; base < total; base += GR_BLOCK) {
+            for (int base = 0; base < total; base += BS) {
                 int i = base + tid;
                 int v = -1, add = 0;
                 if (i < total) {
                     // last entry k with s_pre[k] <= i
-                    int lo = 0, hi = GR_BLOCK;
+                    int lo = 0, hi = BS;
                     while (hi - lo > 1) {
                         int mid = (lo + hi) >> 1;
                         if (s_pre[mid] <= i) lo = mid;
@@ -352,13 +409,93 @@ __global__ void __launch_bounds__(GR_BLOCK) k_gr_level(DevGraph g, int lv, const
     if (lane == 0 && b) add_bytes(ctr, KC_GR, b);
 }
 
+template <bool FWD>
+__global__ void __launch_bounds__(GR_BLOCK) k_gr_level(DevGraph g, int lv, const int2* qin, int2* qout,
+                                                       DevCounters* ctr, int bu_div) {
+    const int cnt = bcast(ctr->front[lv % 3]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
+    if (cnt == 0) return;
+    gr_level_body<FWD, GR_BLOCK>(g, lv, cnt, qin, qout, ctr, bu_div);
+}
+
+// Grid-wide barrier for a cooperative launch (all blocks resident).  Block
+// leaders arrive on a counter; the last one resets it and bumps the
+// generation the others wait on.  The spin is bounded: past the limit the
+// leader flags bar_err and stops waiting, and every block leaves its level
+// loop at the next check, so the kernel always ends.
+constexpr unsigned GRID_SYNC_SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ void grid_sync(DevCounters* ctr) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned gen = __hip_atomic_load(&ctr->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned prev = __hip_atomic_fetch_add(&ctr->bar_count, 1u, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            __hip_atomic_store(&ctr->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&ctr->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&ctr->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > GRID_SYNC_SPIN_LIMIT) {
+                    atomicOr(&ctr->bar_err, 1);
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+    }
+    __syncthreads();
+}
+
+template <int BS>
+__device__ __forceinline__ void worklist_body(const DevGraph& g, int32_t* wl0, int32_t* wl1,
+                                              int32_t* wl2, DevCounters* ctr, int topology, int sign);
+
+// Global relabel and worklist build in one cooperative launch: seeds, then
+// one level after another separated by grid barriers (same level work as
+// k_gr_level), then the worklist and value over the fresh heights.
+constexpr int GRP_BLOCK = 1024;
+
+template <bool FWD>
+__global__ void __launch_bounds__(GRP_BLOCK) k_gr_persistent(DevGraph g, int2* q0, int2* q1,
+                                                             DevCounters* ctr, int bu_div,
+                                                             int seed_deficits, int32_t* wl0,
+                                                             int32_t* wl1, int32_t* wl2,
+                                                             int topology, int sign) {
+    __shared__ int s_flag[2];
+    gr_init_body(g, q0, ctr, seed_deficits);
+    grid_sync(ctr);
+    int lv = 0;
+    for (;; ++lv) {
+        // one read per block so that every wave takes the same branch
+        if (threadIdx.x == 0) {
+            s_flag[0] = __hip_atomic_load(&ctr->front[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_flag[1] = __hip_atomic_load(&ctr->bar_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        const int cnt = s_flag[0], bad = s_flag[1];
+        if (cnt == 0 || bad) break;
+        if (lv > g.n) {  // a BFS has at most n levels
+            if (threadIdx.x == 0) atomicOr(&ctr->bar_err, 2);
+            break;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
+        gr_level_body<FWD, GRP_BLOCK>(g, lv, cnt, (lv & 1) ? q1 : q0, (lv & 1) ? q0 : q1, ctr, bu_div);
+        grid_sync(ctr);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->levels = lv;
+    worklist_body<GRP_BLOCK>(g, wl0, wl1, wl2, ctr, topology, sign);
+}
+
 // ---- worklist (Section 5.2, O1) and value (Algorithm 5) --------------------
 
 // sign = +1: active = positive excess below |V| (the solve); sign = -1:
 // active = negative excess below |V| (deficits to fill from t).
-__global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0, int32_t* wl1,
-                                                        int32_t* wl2, DevCounters* ctr,
-                                                        int topology, int sign) {
+template <int BS>
+__device__ __forceinline__ void worklist_body(const DevGraph& g, int32_t* wl0, int32_t* wl1,
+                                              int32_t* wl2, DevCounters* ctr, int topology, int sign) {
     const int N = g.n;
     long long deficit = 0;
     for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
@@ -382,9 +519,15 @@ __global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0
         wave_append(list && bin == 1, v, wl1, &ctr->wl[1]);
         wave_append(list && bin == 2, v, wl2, &ctr->wl[2]);
     }
-    long long tot = block_sum_i64<256>(deficit);
+    long long tot = block_sum_i64<BS>(deficit);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)&ctr->deficit_sum, (unsigned long long)tot);
     if (blockIdx.x == 0 && threadIdx.x == 0) add_bytes(ctr, KC_WL, 16ull * (unsigned long long)N);
+}
+
+__global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0, int32_t* wl1,
+                                                        int32_t* wl2, DevCounters* ctr,
+                                                        int topology, int sign) {
+    worklist_body<256>(g, wl0, wl1, wl2, ctr, topology, sign);
 }
 
 // ---- push-relabel (Algorithm 2) --------------------------------------------
@@ -944,6 +1087,10 @@ void launch_saturate_source(const DevGraph& g, DevCounters* ctr, hipStream_t st)
     k_saturate_source<<<64, 256, 0, st>>>(g);
 }
 
+void launch_zero_loop_counters(DevCounters* ctr, hipStream_t st) {
+    k_zero_counters_front<<<1, 64, 0, st>>>(ctr);
+}
+
 void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, int seed_deficits, hipStream_t st) {
     k_zero_counters_front<<<1, 64, 0, st>>>(ctr);
     k_gr_init<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, q0, ctr, seed_deficits);
@@ -955,6 +1102,37 @@ void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, 
         k_gr_level<true><<<grid, GR_BLOCK, 0, st>>>(g, level, qin, qout, ctr, bu_div);
     else
         k_gr_level<false><<<grid, GR_BLOCK, 0, st>>>(g, level, qin, qout, ctr, bu_div);
+}
+
+int persistent_gr_grid(int device) {
+    int coop = 0, cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop)
+        return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gr_persistent<false>, GRP_BLOCK, 0) !=
+            hipSuccess || per_cu < 1)
+        return 0;
+    int per_cu_f = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_f, k_gr_persistent<true>, GRP_BLOCK, 0) !=
+            hipSuccess || per_cu_f < 1)
+        return 0;
+    int want = 1;  // blocks per CU: one keeps barrier arrivals few; MF_GR_BLOCKS_PER_CU overrides
+    if (const char* env = std::getenv("MF_GR_BLOCKS_PER_CU")) want = std::max(1, std::atoi(env));
+    want = std::min(want, std::min(per_cu, per_cu_f));
+    return cus * want;
+}
+
+hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounters* ctr, int bu_div,
+                                int seed_deficits, bool forward, int32_t* wl0, int32_t* wl1,
+                                int32_t* wl2, bool topology, int sign, int grid, hipStream_t st) {
+    k_zero_counters_front<<<1, 64, 0, st>>>(ctr);
+    DevGraph gg = g;
+    int topo = topology ? 1 : 0;
+    void* args[] = {&gg, &q0, &q1, &ctr, &bu_div, &seed_deficits, &wl0, &wl1, &wl2, &topo, &sign};
+    const void* fn = forward ? reinterpret_cast<const void*>(&k_gr_persistent<true>)
+                             : reinterpret_cast<const void*>(&k_gr_persistent<false>);
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(GRP_BLOCK), args, 0, st);
 }
 
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,

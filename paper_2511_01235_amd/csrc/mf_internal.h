@@ -42,7 +42,10 @@ struct DevCounters {
     int32_t overflow;          // batch: row slack exhausted
     int32_t new_pairs;         // batch: distinct absent pairs
     int32_t cap_overflow;      // batch: c(u,v)+c(v,u) would leave int32
-    int32_t pad[2];
+    int32_t levels;            // levels run by the persistent global relabel
+    int32_t bar_err;           // persistent global relabel: barrier gave up / level bound hit
+    unsigned bar_count;        // grid barrier arrivals
+    unsigned bar_gen;          // grid barrier generation
     long long deficit_sum;     // sum of negative excess outside {s,t}
     long long e_t;             // e(t) at the worklist build
     unsigned long long bytes[8];  // algorithmic bytes per kernel class
@@ -60,7 +63,10 @@ constexpr int GR_CHUNK = 256;
 // A level scans bottom-up (unvisited vertices look for a parent in their own
 // row) when its frontier holds more than n / bu_div entries; bu_div = 0 keeps
 // every level top-down.  Default below; MF_GR_BOTTOM_UP_DIV overrides it.
-constexpr int GR_BOTTOM_UP_DIV = 0;
+constexpr int GR_BOTTOM_UP_DIV = 64;
+// Bottom-up: a thread checks this many slots of its row before handing the
+// rest of a long row to a wave.
+constexpr int BU_THREAD_SLOTS = 32;
 
 // Batch scratch: hash table of absent pairs, keyed by the unordered pair.
 struct BatchTable {
@@ -74,9 +80,14 @@ struct BatchTable {
 void launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t st);
 void launch_reset(const DevGraph& g, int64_t slot_cap, hipStream_t st);
 void launch_saturate_source(const DevGraph& g, DevCounters* ctr, hipStream_t st);
+void launch_zero_loop_counters(DevCounters* ctr, hipStream_t st);
 void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, int seed_deficits, hipStream_t st);
 void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, DevCounters* ctr,
                      int grid, bool forward, int bu_div, hipStream_t st);
+int persistent_gr_grid(int device);
+hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounters* ctr, int bu_div,
+                                int seed_deficits, bool forward, int32_t* wl0, int32_t* wl1,
+                                int32_t* wl2, bool topology, int sign, int grid, hipStream_t st);
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
                            DevCounters* ctr, bool topology, int sign, hipStream_t st);
 void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc, bool pull,

@@ -113,6 +113,23 @@ def test_static_workloads(name, opts):
     _cut_ok(g.n, g.s, g.t, side, cut, got, g.src, g.dst, g.cap)
 
 
+@pytest.mark.parametrize("name", ["er2000", "rmat14", "grid64"])
+def test_persistent_relabel_mode(name):
+    """The cooperative single-launch global relabel gives the same values."""
+    g, stream, k, nb = gen.workload(name)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, relabel_mode=1) as G:
+        assert G.maxflow() == o.static()
+        h, e, active = G.initial_labels()
+        h_want, e_want = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t).initial_labels()
+        assert np.array_equal(h, h_want)
+        G.maxflow()
+        for b in range(3):
+            u, v, c = stream.next_batch(k)
+            say("persistent", name, b)
+            assert G.apply_batch(u, v, c) == o.apply(u, v, c)
+
+
 def test_static_repeatable():
     g, _, _, _ = gen.workload("rmat14")
     want = oracle.max_flow(g.n, g.src, g.dst, g.cap, g.s, g.t)
@@ -175,12 +192,13 @@ def test_dynamic_tiny_adversarial(seed):
             _cut_ok(n, s, t, side, cut, got, ms, md, mc)
 
 
+@pytest.mark.parametrize("warm", [False, True])
 @pytest.mark.parametrize("name,batches", [("er2000", 10), ("rmat12", 8), ("rmat14", 5),
                                           ("grid64", 5), ("grid256", 3)])
-def test_dynamic_workloads(name, batches):
+def test_dynamic_workloads(name, batches, warm):
     g, stream, k, nb = gen.workload(name)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
-    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, warm_start=warm) as G:
         assert G.maxflow() == o.static()
         for b in range(min(batches, nb)):
             u, v, c = stream.next_batch(k)
