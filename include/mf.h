@@ -62,9 +62,10 @@ typedef struct mf_options {
     int32_t insert_slack_min;  /* free slots kept per row for inserted pairs; <= 0: 2 */
     int32_t insert_slack_pct;  /* plus this percentage of the row's length; <= 0: 12 */
     int64_t max_iterations;    /* cap on global relabels per call; <= 0: 4n + 1000 */
-    int32_t warm_start;        /* 1: a repair first runs one push-relabel and remove-invalid-edges
-                                  sweep on the heights left by the previous solve, then the loop;
-                                  0 (default): the loop right away (Algorithm 5) */
+    int32_t cold_start;        /* 0 (default): a repair first runs one push-relabel and remove-
+                                  invalid-edges sweep on the heights left by the previous solve, then
+                                  the loop; 1: the loop right away, global relabel first (Algorithm 5
+                                  as printed).  Both return the same value. */
     int32_t relabel_mode;      /* 0 (default): one launch per BFS level; 1: the whole global
                                   relabel and worklist build in one cooperative launch with a grid
                                   barrier per level (falls back to 0 where unsupported) */
@@ -80,8 +81,8 @@ typedef struct mf_update {
 
 typedef struct mf_stats {
     int64_t n;                 /* vertices */
-    int64_t pairs;             /* merged directed pairs with a slot (cap may be 0) */
-    int64_t slots;             /* Bi-CSR entries in use */
+    int64_t pairs;             /* directed pairs (u,v) with a Bi-CSR entry in row u (cap may be 0) */
+    int64_t slots;             /* Bi-CSR entries in use (one per such pair) */
     int64_t slot_capacity;     /* Bi-CSR entries allocated, including insertion slack */
     int64_t device_bytes;      /* device memory held by the handle */
     int32_t kernel_cycles;     /* KC in use */

@@ -48,7 +48,7 @@ class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("device", C.c_int32), ("stream", C.c_void_p),
                 ("kernel_cycles", C.c_int32), ("topology_driven", C.c_int32),
                 ("insert_slack_min", C.c_int32), ("insert_slack_pct", C.c_int32),
-                ("max_iterations", C.c_int64), ("warm_start", C.c_int32), ("relabel_mode", C.c_int32)]
+                ("max_iterations", C.c_int64), ("cold_start", C.c_int32), ("relabel_mode", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -121,10 +121,10 @@ def mf_default_options() -> Options:
 
 
 def make_options(kernel_cycles=0, topology_driven=False, insert_slack_min=0, insert_slack_pct=0,
-                 max_iterations=0, stream=None, device=-1, warm_start=False,
+                 max_iterations=0, stream=None, device=-1, warm_start=True,
                  relabel_mode=0) -> Options:
     o = mf_default_options()
-    o.warm_start = int(bool(warm_start))
+    o.cold_start = 0 if warm_start else 1
     o.relabel_mode = int(relabel_mode)
     o.kernel_cycles = kernel_cycles
     o.topology_driven = int(bool(topology_driven))

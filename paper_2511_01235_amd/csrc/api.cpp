@@ -65,8 +65,10 @@ struct mf_graph {
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
     int gr_grid = 1024;
-    int bu_div = mf::GR_BOTTOM_UP_DIV;
+    mf::GrBits bits{};
+    mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0};
     int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
+    int first_chunk = 8;      // BFS levels launched before the first frontier check
 };
 
 namespace {
@@ -133,7 +135,14 @@ void settle_events(mf_graph* g) {
     g->ev_pending.clear();
 }
 
+// Profiled calls: sum the kernels' per-block byte partials (one small
+// kernel), read them back and add the selected classes to the totals.
 void fold_bytes(mf_graph* g) {
+    if (!g->prof_mask) return;
+    mf::launch_reduce_bytes(g->dg, g->ctr, g->stream);
+    if (hipMemcpyAsync(g->ctr_h, g->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, g->stream) != hipSuccess ||
+        hipStreamSynchronize(g->stream) != hipSuccess)
+        return;
     for (int c = 0; c < 8; ++c)
         if (g->prof_mask >> c & 1u) g->kernel_bytes[c] += (double)g->ctr_h->bytes[c];
 }
@@ -174,6 +183,8 @@ void free_all(mf_graph* g) {
     dfree(g->tb.slot);
     dfree(g->side);
     dfree(g->cut_acc);
+    dfree(g->bits.visited);
+    dfree(g->dg.bytes_part);
     for (auto& p : g->ev_pending) {
         (void)hipEventDestroy(p.second.first);
         (void)hipEventDestroy(p.second.second);
@@ -275,19 +286,19 @@ LoopMode solve_mode(mf_graph* g) {
 // chunk.  Returns the number of level launches.
 mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
     hipStream_t st = g->stream;
-    timed(g, mf::KC_GR, [&] { mf::launch_gr_init(m.dg, g->q[0], g->ctr, m.seed_deficits, st); });
+    timed(g, mf::KC_GR, [&] { mf::launch_gr_init(m.dg, g->q[0], g->ctr, g->bits, m.seed_deficits, st); });
     int level = 0;
-    int chunk = 2;
+    int chunk = g->first_chunk;
     for (;;) {
         for (int i = 0; i < chunk; ++i, ++level)
             timed(g, mf::KC_GR, [&] {
                 mf::launch_gr_level(m.dg, level, g->q[level & 1], g->q[(level + 1) & 1], g->ctr,
-                                    g->gr_grid, m.forward, g->bu_div, st);
+                                    g->bits, g->tune, g->gr_grid, m.forward, st);
             });
         MF_HIP(hipGetLastError());
         mf_status rc = read_counters(g);
         if (rc != MF_OK) return rc;
-        if (g->ctr_h->front[level % 3] == 0) break;
+        if ((g->ctr_h->front[level % 3] & 0xFFFFFFFFull) == 0) break;
         if (level > g->n + 2) {
             g->poisoned = true;
             return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
@@ -307,7 +318,7 @@ mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) 
     if (g->persistent_grid > 0) {
         hipError_t err = hipSuccess;
         timed(g, mf::KC_GR, [&] {
-            err = mf::launch_gr_persistent(m.dg, g->q[0], g->q[1], g->ctr, g->bu_div, m.seed_deficits,
+            err = mf::launch_gr_persistent(m.dg, g->q[0], g->q[1], g->ctr, g->bits, g->tune, m.seed_deficits,
                                            m.forward, g->wl[0], g->wl[1], g->wl[2], m.topology, m.sign,
                                            g->persistent_grid, st);
         });
@@ -394,6 +405,7 @@ mf_status warm_sweep(mf_graph* g) {
 mf_status check_handle(mf_graph* g) {
     if (!g) return MF_ERR_INVALID;
     if (g->poisoned) return MF_ERR_DEVICE;
+    g->dg.count_bytes = g->prof_mask != 0;
     if (hipSetDevice(g->device) != hipSuccess) {
         g->poisoned = true;
         return MF_ERR_DEVICE;
@@ -480,10 +492,10 @@ mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_
             mf::launch_batch_clamp(g->dg, d_upd, k, g->touched, g->win, g->tb, st);
             mf::launch_batch_cleanup(g->tb, g->need, g->slot_of, g->win, k, st);
         });
-        g->pairs += c.new_pairs;
+        g->dg.used_slots += 2 * (int64_t)c.new_pairs;
         timed(g, mf::KC_INIT, [&] { mf::launch_saturate_source(g->dg, g->ctr, st); });
         MF_HIP(hipGetLastError());
-        if (g->opt.warm_start) {
+        if (!g->opt.cold_start) {
             rc = warm_sweep(g);
             if (rc != MF_OK) return rc;
         }
@@ -573,15 +585,30 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     }
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    g->gr_grid = std::max(64, cus * 4);
-    if (const char* env = std::getenv("MF_GR_BOTTOM_UP_DIV")) g->bu_div = std::atoi(env);
+    g->gr_grid = std::max(32, cus * 4);  // 256-thread level blocks, four per CU
+    if (dalloc(g, &g->dg.bytes_part, (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS) != hipSuccess)
+        return fail(MF_ERR_OUT_OF_MEMORY);
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->dg.bytes_part), 0,
+                        2 * (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS, g->stream);
+    // BFS bitmaps: visited plus a ring of three frontier bitmaps
+    g->bits.nwords = (n + 31) / 32;
+    if (dalloc(g, &g->bits.visited, 4 * (int64_t)g->bits.nwords) != hipSuccess) return fail(MF_ERR_OUT_OF_MEMORY);
+    g->bits.fb = g->bits.visited + g->bits.nwords;
+    g->tune.lds = 0;  // LDS-bitmap level variant: opt-in (MF_GR_LDS=1), slower on rmat20
+    if (const char* env = std::getenv("MF_GR_BU_ALPHA")) g->tune.bu_alpha = std::atoi(env);
+    if (const char* env = std::getenv("MF_GR_BU_BETA")) g->tune.bu_beta = std::max(1, std::atoi(env));
+    if (const char* env = std::getenv("MF_GR_STAGE_MIN")) g->tune.stage_min = std::atoi(env);
+    if (const char* env = std::getenv("MF_GR_LDS"))
+        if (std::atoi(env) != 0) g->tune.lds = mf::gr_level_lds_bytes(g->bits.nwords, dev) > 0 ? 1 : 0;
     if (const char* env = std::getenv("MF_GR_GRID")) g->gr_grid = std::max(1, std::atoi(env));
+    if (const char* env = std::getenv("MF_GR_FIRST_CHUNK")) g->first_chunk = std::max(1, std::atoi(env));
     if (o.relabel_mode == 1) g->persistent_grid = mf::persistent_gr_grid(dev);
     g->dg.n = n;
     g->dg.s = s;
     g->dg.t = t;
     g->dg.root = t;
     g->dg.pinned = s;
+    g->dg.used_slots = b.pairs;
     if (dalloc(g, &g->dg.e, n) != hipSuccess || dalloc(g, &g->dg.h, n) != hipSuccess ||
         dalloc(g, &g->wl[0], n) != hipSuccess || dalloc(g, &g->wl[1], n) != hipSuccess ||
         dalloc(g, &g->wl[2], n) != hipSuccess || dalloc(g, &g->ctr, 1) != hipSuccess ||
@@ -787,9 +814,9 @@ mf_status mf_get_stats(const mf_graph* g, mf_stats* out) {
     if (!g || !out) return MF_ERR_INVALID;
     std::memset(out, 0, sizeof(*out));
     out->n = g->n;
-    out->pairs = g->pairs;
+    out->pairs = g->dg.used_slots;
     out->slot_capacity = g->slot_cap;
-    out->slots = 2 * g->pairs;
+    out->slots = g->dg.used_slots;
     // slot arrays (col+res, rev, cap, capsum, win), two frontier queues, per-vertex arrays
     out->device_bytes = g->slot_cap * 24 + 2 * g->q_cap * 8 + (int64_t)g->n * (4 * 3 + 8 + 4 + 12 + 4 + 1) +
                         g->k_cap * (4 + 4 + 12) + (int64_t)g->tb.capacity * (8 + 8 + 8);

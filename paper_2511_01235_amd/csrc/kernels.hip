@@ -54,8 +54,9 @@ __device__ __forceinline__ int64_t ld_e(const int64_t* e, int v) {
 __device__ __forceinline__ void add_e(int64_t* e, int v, int64_t d) {
     __hip_atomic_fetch_add(&e[v], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void add_bytes(DevCounters* ctr, int cls, unsigned long long b) {
-    if (b) __hip_atomic_fetch_add(&ctr->bytes[cls], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void add_bytes(const DevGraph& g, int cls, unsigned long long b) {
+    if (g.count_bytes && b)
+        atomicAdd(&g.bytes_part[cls * BYTES_SLOTS + (blockIdx.x % BYTES_SLOTS)], b);
 }
 
 // ---- wave primitives ------------------------------------------------------
@@ -199,7 +200,10 @@ __global__ void __launch_bounds__(256) k_saturate_source(DevGraph g) {
 
 // Zero what one global relabel and the worklist build after it accumulate.
 __global__ void k_zero_counters_front(DevCounters* ctr) {
-    if (threadIdx.x < 3) ctr->front[threadIdx.x] = 0;
+    if (threadIdx.x < 3) {
+        ctr->front[threadIdx.x] = 0;
+        ctr->unv[threadIdx.x] = 0;
+    }
     if (threadIdx.x < 4) ctr->wl[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         ctr->deficit_sum = 0;
@@ -211,42 +215,56 @@ __global__ void k_zero_counters_front(DevCounters* ctr) {
 }
 
 // Append the frontier entries of the lanes that discovered a vertex:
-// ceil(row_len / GR_CHUNK) entries {v, offset} per vertex.
-__device__ __forceinline__ void append_entries(int add, int v, int2* q, int32_t* counter) {
+// ceil(row_len / GR_CHUNK) entries {v, offset} per vertex.  One 64-bit atomic
+// per wave both reserves the queue positions (low half) and adds the
+// vertices' slot counts to the frontier's slot total (high half).
+__device__ __forceinline__ void append_entries(int add, int slots, int v, int2* q,
+                                               unsigned long long* counter) {
     int total;
     int off = wave_excl_scan(add, &total);
     if (total == 0) return;
-    int base = 0;
-    if (lane_id() == 0) base = atomicAdd(counter, total);
-    base = __shfl(base, 0, WAVE);
-    for (int k = 0; k < add; ++k) q[base + off + k] = make_int2(v, k * GR_CHUNK);
+    unsigned long long sl = wave_sum_u64((unsigned long long)slots);
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, (sl << 32) | (unsigned long long)total);
+    int b = __shfl((int)(unsigned)(base & 0xFFFFFFFFull), 0, WAVE);
+    for (int k = 0; k < add; ++k) q[b + off + k] = make_int2(v, k * GR_CHUNK);
 }
 
-// Heights before the levels (Algorithms 4 and 6): h(root) = 0 and, with
-// seed_deficits, h(v) = 0 for every deficient v outside {root, pinned};
-// every other vertex, the pinned one included, gets |V|.  Level-0 vertices
-// are queued.  The solve uses root = t, pinned = s, deficits seeded.
+// Visited / frontier bitmaps of a global relabel (one bit per vertex).
+__device__ __forceinline__ bool bit_of(const unsigned* bm, int v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
+__device__ __forceinline__ void set_bit(unsigned* bm, int v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
+
 __device__ __forceinline__ void gr_init_body(const DevGraph& g, int2* q0, DevCounters* ctr,
-                                             int seed_deficits) {
+                                             const GrBits& bits, int seed_deficits) {
     const int N = g.n;
     for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
         int v = base + threadIdx.x;
-        int add = 0;
+        int add = 0, slots = 0;
         if (v < N) {
             bool seed = v == g.root ||
                         (seed_deficits && v != g.pinned && v != g.s && v != g.t && ld_e(g.e, v) < 0);
             g.h[v] = seed ? 0 : N;
-            if (seed) add = (g.row_len[v] + GR_CHUNK - 1) / GR_CHUNK;
+            if (seed) {
+                slots = g.row_len[v];
+                add = (slots + GR_CHUNK - 1) / GR_CHUNK;
+                set_bit(bits.visited, v);
+                set_bit(bits.fb, v);
+            } else if (v == g.pinned) {
+                set_bit(bits.visited, v);  // never labelled
+            }
         }
-        append_entries(add, v, q0, &ctr->front[0]);
+        append_entries(add, slots, v, q0, &ctr->front[0]);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        add_bytes(ctr, KC_GR, 12ull * (unsigned long long)N);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // slots of every row that may be labelled, the seeds' included
+        ctr->unv[2] = (long long)g.used_slots - g.row_len[g.pinned];
+        add_bytes(g, KC_GR, 12ull * (unsigned long long)N);
+    }
 }
 
-__global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr,
+__global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr, GrBits bits,
                                                  int seed_deficits) {
-    gr_init_body(g, q0, ctr, seed_deficits);
+    gr_init_body(g, q0, ctr, bits, seed_deficits);
 }
 
 // One BFS level.  Top-down (small frontier): each block takes 256 frontier
@@ -262,22 +280,41 @@ __global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounte
 // first.  Both produce exactly the BFS levels.  The frontier size is read on
 // the device; an empty frontier makes the launch a no-op, so the host may run
 // ahead by several levels.
-constexpr int GR_BLOCK = 256;
+
+// A vertex gets height lv+1: mark it visited and in the next frontier, queue
+// its entries, and return its slot count for the direction counters.
+__device__ __forceinline__ int discover(const DevGraph& g, const GrBits& bits, int lv, int v, int* add) {
+    set_bit(bits.visited, v);
+    set_bit(bits.fb + (size_t)((lv + 1) % 3) * bits.nwords, v);
+    int len = g.row_len[v];
+    *add = (len + GR_CHUNK - 1) / GR_CHUNK;
+    return len;
+}
 
 // The work of one level for a block of BS threads; cnt = the frontier size.
+// bu selects bottom-up.  s_bm, when not null, is this block's LDS copy of the
+// bitmap the direction needs (visited for top-down, the current frontier for
+// bottom-up), replacing the height gather of every scanned slot by a bit test.
 template <bool FWD, int BS>
 __device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt, const int2* qin,
-                                              int2* qout, DevCounters* ctr, int bu_div) {
+                                              int2* qout, DevCounters* ctr, const GrBits& bits,
+                                              bool bu, const unsigned* s_bm) {
     __shared__ int s_u[BS];
     __shared__ int s_beg[BS];
     __shared__ int s_pre[BS + 1];
     __shared__ int s_wsum[BS / WAVE];
     const int N = g.n;
-    int32_t* out_cnt = &ctr->front[(lv + 1) % 3];
+    unsigned long long* out_cnt = &ctr->front[(lv + 1) % 3];
     const int tid = threadIdx.x;
     const int lane = lane_id();
     unsigned long long scanned = 0, found = 0, exam = 0;
-    if (bu_div > 0 && cnt > N / bu_div) {
+    // is col at height lv (bottom-up)?  The 1-bit-per-vertex bitmaps stay
+    // resident in L2, unlike the 4-byte heights.
+    const unsigned* cur_fb = bits.fb + (size_t)(lv % 3) * bits.nwords;
+    const unsigned* bm_level = s_bm ? s_bm : cur_fb;
+    auto at_level = [&](int c) { return bit_of(bm_level, c); };
+    const unsigned* bm_seen = s_bm ? s_bm : bits.visited;
+    if (bu) {
         // bottom-up: threads check up to BU_THREAD_SLOTS slots of their own
         // row (four loads in flight); longer rows without a hit go to a
         // block-local list that the block's waves finish one row at a time
@@ -287,9 +324,8 @@ __device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt
             if (tid == 0) s_ndefer = 0;
             __syncthreads();
             int v = base + tid;
-            int add = 0;
-            if (v < N) ++exam;
-            if (v < N && v != g.pinned && g.h[v] == N) {
+            int add = 0, slots = 0;
+            if (v < N && !bit_of(bits.visited, v)) {
                 int beg = g.row_ptr[v], len = g.row_len[v];
                 int end = beg + min(len, BU_THREAD_SLOTS);
                 exam += 2;  // the row bounds
@@ -302,22 +338,29 @@ __device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                         r4[q] = j + q < end ? (FWD ? g.capsum[j + q] - c4[q].y : c4[q].y) : 0;
-                    int h4[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) h4[q] = r4[q] > 0 ? g.h[c4[q].x] : -1;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) hit = hit || h4[q] == lv;
+                    for (int q = 0; q < 4; ++q) hit = hit || (r4[q] > 0 && at_level(c4[q].x));
                     scanned += (unsigned long long)min(4, end - j);
                 }
                 if (hit) {
                     g.h[v] = lv + 1;
                     add = (len + GR_CHUNK - 1) / GR_CHUNK;
+                    slots = len;
                     found++;
                 } else if (len > BU_THREAD_SLOTS) {
                     s_defer[atomicAdd(&s_ndefer, 1)] = v;
                 }
             }
-            append_entries(add, v, qout, out_cnt);
+            {   // a wave's 64 vertices are consecutive and 64-aligned: two bitmap
+                // words, one atomic OR each from lanes 0 and 32
+                unsigned long long m = __ballot(add > 0);
+                unsigned half = lane < 32 ? (unsigned)m : (unsigned)(m >> 32);
+                if ((lane & 31) == 0 && half && v < N) {
+                    atomicOr(&bits.visited[v >> 5], half);
+                    atomicOr(&bits.fb[(size_t)((lv + 1) % 3) * bits.nwords + (v >> 5)], half);
+                }
+            }
+            append_entries(add, slots, v, qout, out_cnt);
             __syncthreads();
             const int nd = s_ndefer;
             for (int d = tid / WAVE; d < nd; d += BS / WAVE) {
@@ -330,7 +373,7 @@ __device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt
                     if (j < end) {
                         int2 c = g.cr[j];
                         int32_t r = FWD ? g.capsum[j] - c.y : c.y;
-                        my = r > 0 && g.h[c.x] == lv;
+                        my = r > 0 && at_level(c.x);
                     }
                     scanned += (unsigned long long)(j < end);
                     if (__ballot(my)) {
@@ -338,16 +381,17 @@ __device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt
                         break;
                     }
                 }
-                int addw = 0;
+                int addw = 0, slw = 0;
                 if (hit && lane == 0) {
                     g.h[w] = lv + 1;
-                    addw = (g.row_len[w] + GR_CHUNK - 1) / GR_CHUNK;
+                    slw = discover(g, bits, lv, w, &addw);
                     found++;
                 }
-                append_entries(addw, w, qout, out_cnt);
+                append_entries(addw, slw, w, qout, out_cnt);
             }
             __syncthreads();  // s_defer / s_ndefer are reused next round
         }
+        exam += (unsigned long long)((N + (int)(gridDim.x * blockDim.x) - 1) / (int)(gridDim.x * blockDim.x)) / 8;
     } else {
         // entries per block: spread small frontiers over many blocks, up to
         // BS entries per block for large ones
@@ -379,7 +423,7 @@ __device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt
             scanned += (unsigned long long)total;  // counted once per block (thread 0 below)
             for (int base = 0; base < total; base += BS) {
                 int i = base + tid;
-                int v = -1, add = 0;
+                int v = -1, add = 0, slots = 0;
                 if (i < total) {
                     // last entry k with s_pre[k] <= i
                     int lo = 0, hi = BS;
@@ -392,30 +436,67 @@ __device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt
                     int2 cr = g.cr[j];
                     v = cr.x;
                     int32_t r = FWD ? cr.y : g.capsum[j] - cr.y;
-                    if (r > 0 && v != g.pinned && g.h[v] == N && atomicCAS(&g.h[v], N, lv + 1) == N) {
-                        add = (g.row_len[v] + GR_CHUNK - 1) / GR_CHUNK;
+                    bool open = !bit_of(bm_seen, v);  // pinned is marked visited at init
+                    if (r > 0 && open && atomicCAS(&g.h[v], N, lv + 1) == N) {
+                        slots = discover(g, bits, lv, v, &add);
                         found++;
                     }
                 }
-                append_entries(add, v, qout, out_cnt);
+                append_entries(add, slots, v, qout, out_cnt);
             }
             __syncthreads();  // LDS is restaged next round
         }
         if (tid != 0) scanned = 0;
     }
-    // per scanned slot: col, res, capsum, h[col]; per staged entry or examined
-    // vertex its words; per discovered vertex the CAS and queue entry
-    unsigned long long b = wave_sum_u64(16ull * scanned + 4ull * exam + 16ull * found);
-    if (lane == 0 && b) add_bytes(ctr, KC_GR, b);
+    // per scanned slot: col+res (8), capsum (4), plus h[col] (4) without the
+    // LDS bitmap; per staged entry or unlabelled vertex its words; per
+    // discovered vertex the CAS, two bitmap words and its queue entry
+    unsigned long long per_slot = (s_bm ? 12ull : 16ull) - ((bu && !FWD) ? 4ull : 0ull);
+    if (g.count_bytes) {
+        unsigned long long b = wave_sum_u64(per_slot * scanned + 4ull * exam + 24ull * found);
+        if (lane == 0) add_bytes(g, KC_GR, b);
+    }
 }
 
-template <bool FWD>
-__global__ void __launch_bounds__(GR_BLOCK) k_gr_level(DevGraph g, int lv, const int2* qin, int2* qout,
-                                                       DevCounters* ctr, int bu_div) {
-    const int cnt = bcast(ctr->front[lv % 3]);
+// Direction of level lv (Beamer's rule, decided on the device): bottom-up
+// when the frontier's slots exceed the unvisited slots / alpha and the
+// frontier holds more than n / beta vertices.  Every input was final before
+// the level started (the frontier's slots, and the unvisited slots of the
+// level before minus the frontier's), so all blocks decide alike; block 0
+// records this level's unvisited count for the next one.
+__device__ __forceinline__ bool choose_bottom_up(const DevGraph& g, DevCounters* ctr, int lv,
+                                                 int cnt, const GrTune& tune) {
+    long long fs = (long long)(ctr->front[lv % 3] >> 32);
+    long long mu = ctr->unv[(lv + 2) % 3] - fs;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->unv[lv % 3] = mu;
+    if (tune.bu_alpha <= 0) return false;
+    return fs * (long long)tune.bu_alpha > mu && (long long)cnt * tune.bu_beta > (long long)g.n;
+}
+
+// Level kernel.  BS = 256 (default): four or more blocks per CU, no LDS
+// bitmap.  BS = 1024 with the bitmap staged in LDS: one block per CU.
+constexpr int GRL_BLOCK_LDS = 1024;
+
+template <bool FWD, int BS>
+__global__ void __launch_bounds__(BS) k_gr_level(DevGraph g, int lv, const int2* qin, int2* qout,
+                                                 DevCounters* ctr, GrBits bits, GrTune tune) {
+    extern __shared__ unsigned s_dyn[];
+    const int cnt = bcast((int)(unsigned)(ctr->front[lv % 3] & 0xFFFFFFFFull));
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
     if (cnt == 0) return;
-    gr_level_body<FWD, GR_BLOCK>(g, lv, cnt, qin, qout, ctr, bu_div);
+    {   // the bitmap of level lv+2 (input of level lv-1, consumed) starts empty
+        unsigned* z = bits.fb + (size_t)((lv + 2) % 3) * bits.nwords;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < bits.nwords; i += gridDim.x * blockDim.x)
+            z[i] = 0u;
+    }
+    const bool bu = choose_bottom_up(g, ctr, lv, cnt, tune);
+    const bool stage = tune.lds && (bu || cnt >= tune.stage_min);
+    if (stage) {
+        const unsigned* src = bu ? bits.fb + (size_t)(lv % 3) * bits.nwords : bits.visited;
+        for (int i = threadIdx.x; i < bits.nwords; i += blockDim.x) s_dyn[i] = src[i];
+        __syncthreads();
+    }
+    gr_level_body<FWD, BS>(g, lv, cnt, qin, qout, ctr, bits, bu, stage ? s_dyn : nullptr);
 }
 
 // Grid-wide barrier for a cooperative launch (all blocks resident).  Block
@@ -460,18 +541,19 @@ constexpr int GRP_BLOCK = 1024;
 
 template <bool FWD>
 __global__ void __launch_bounds__(GRP_BLOCK) k_gr_persistent(DevGraph g, int2* q0, int2* q1,
-                                                             DevCounters* ctr, int bu_div,
+                                                             DevCounters* ctr, GrBits bits, GrTune tune,
                                                              int seed_deficits, int32_t* wl0,
                                                              int32_t* wl1, int32_t* wl2,
                                                              int topology, int sign) {
     __shared__ int s_flag[2];
-    gr_init_body(g, q0, ctr, seed_deficits);
+    gr_init_body(g, q0, ctr, bits, seed_deficits);
     grid_sync(ctr);
     int lv = 0;
     for (;; ++lv) {
         // one read per block so that every wave takes the same branch
         if (threadIdx.x == 0) {
-            s_flag[0] = __hip_atomic_load(&ctr->front[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_flag[0] = (int)(unsigned)(__hip_atomic_load(&ctr->front[lv % 3], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT) & 0xFFFFFFFFull);
             s_flag[1] = __hip_atomic_load(&ctr->bar_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
@@ -482,7 +564,12 @@ __global__ void __launch_bounds__(GRP_BLOCK) k_gr_persistent(DevGraph g, int2* q
             break;
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
-        gr_level_body<FWD, GRP_BLOCK>(g, lv, cnt, (lv & 1) ? q1 : q0, (lv & 1) ? q0 : q1, ctr, bu_div);
+        unsigned* z = bits.fb + (size_t)((lv + 2) % 3) * bits.nwords;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < bits.nwords; i += gridDim.x * blockDim.x)
+            z[i] = 0u;
+        const bool bu = choose_bottom_up(g, ctr, lv, cnt, tune);
+        gr_level_body<FWD, GRP_BLOCK>(g, lv, cnt, (lv & 1) ? q1 : q0, (lv & 1) ? q0 : q1, ctr, bits, bu,
+                                      nullptr);
         grid_sync(ctr);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr->levels = lv;
@@ -521,7 +608,7 @@ __device__ __forceinline__ void worklist_body(const DevGraph& g, int32_t* wl0, i
     }
     long long tot = block_sum_i64<BS>(deficit);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)&ctr->deficit_sum, (unsigned long long)tot);
-    if (blockIdx.x == 0 && threadIdx.x == 0) add_bytes(ctr, KC_WL, 16ull * (unsigned long long)N);
+    if (blockIdx.x == 0 && threadIdx.x == 0) add_bytes(g, KC_WL, 16ull * (unsigned long long)N);
 }
 
 __global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0, int32_t* wl1,
@@ -639,7 +726,7 @@ __global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl
         }
     }
     unsigned long long b = wave_sum_u64(bytes);
-    if (lane_id() == 0) add_bytes(ctr, KC_PR, b);
+    if (lane_id() == 0) add_bytes(g, KC_PR, b);
 }
 
 template <bool PULL>
@@ -678,7 +765,7 @@ __global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, 
             bytes += 4;
         }
     }
-    if (lane == 0) add_bytes(ctr, KC_PR, bytes);
+    if (lane == 0) add_bytes(g, KC_PR, bytes);
 }
 
 template <bool PULL>
@@ -728,7 +815,7 @@ __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t
             bytes += 4;
         }
     }
-    if (threadIdx.x == 0) add_bytes(ctr, KC_PR, bytes);
+    if (threadIdx.x == 0) add_bytes(g, KC_PR, bytes);
 }
 
 // ---- remove invalid edges (Algorithm 3) ------------------------------------
@@ -764,7 +851,7 @@ __global__ void __launch_bounds__(256) k_rie_thread(DevGraph g, const int32_t* w
         bytes += 16 + 12ull * (unsigned long long)(end - beg);
     }
     unsigned long long b = wave_sum_u64(bytes);
-    if (lane_id() == 0) add_bytes(ctr, KC_RIE, b);
+    if (lane_id() == 0) add_bytes(g, KC_RIE, b);
 }
 
 template <int GROUP>
@@ -801,7 +888,7 @@ __global__ void __launch_bounds__(256) k_rie_group(DevGraph g, const int32_t* wl
     moved = wave_sum_i64(moved);
     if (lane_id() == 0 && moved && u >= 0) add_e(g.e, u, -moved);
     unsigned long long b = wave_sum_u64(bytes);
-    if (lane_id() == 0) add_bytes(ctr, KC_RIE, b);
+    if (lane_id() == 0) add_bytes(g, KC_RIE, b);
 }
 
 // ---- batch of updates (Algorithm 5, first loops) ---------------------------
@@ -1035,6 +1122,25 @@ __global__ void __launch_bounds__(256) k_flow_slots(DevGraph g, int32_t* flow_sl
     if (threadIdx.x == 0 && tot) atomicAdd(count, (unsigned long long)tot);
 }
 
+// Sum the per-block byte partials of each class into ctr->bytes and clear them.
+__global__ void __launch_bounds__(256) k_reduce_bytes(DevGraph g, DevCounters* ctr) {
+    const int cls = blockIdx.x;
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < BYTES_SLOTS; i += 256) {
+        s += g.bytes_part[cls * BYTES_SLOTS + i];
+        g.bytes_part[cls * BYTES_SLOTS + i] = 0;
+    }
+    __shared__ unsigned long long part[256 / WAVE];
+    s = wave_sum_u64(s);
+    if (lane_id() == 0) part[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 256 / WAVE; ++w) t += part[w];
+        ctr->bytes[cls] = t;
+    }
+}
+
 // ---- self-test of the wave primitives ---------------------------------------
 
 __global__ void k_selftest(int* fails) {
@@ -1091,17 +1197,46 @@ void launch_zero_loop_counters(DevCounters* ctr, hipStream_t st) {
     k_zero_counters_front<<<1, 64, 0, st>>>(ctr);
 }
 
-void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, int seed_deficits, hipStream_t st) {
+void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, const GrBits& bits, int seed_deficits,
+                    hipStream_t st) {
     k_zero_counters_front<<<1, 64, 0, st>>>(ctr);
-    k_gr_init<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, q0, ctr, seed_deficits);
+    launch_fill_i32(reinterpret_cast<int32_t*>(bits.visited), 0, 4 * (int64_t)bits.nwords, st);
+    k_gr_init<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, q0, ctr, bits, seed_deficits);
 }
 
+int gr_level_lds_bytes(int nwords, int device) {
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+        return 0;
+    int bytes = 4 * nwords;
+    // the level kernel's own LDS (entry staging, prefix sums, deferred rows) comes on top
+    const int static_bytes = 4 * (4 * GRL_BLOCK_LDS + 1 + GRL_BLOCK_LDS / WAVE + 1) + 64;
+    if (bytes + static_bytes > max_lds) return 0;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gr_level<false, GRL_BLOCK_LDS>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gr_level<true, GRL_BLOCK_LDS>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+        return 0;
+    return bytes;
+}
+
+// grid: blocks of the 256-thread variant; the LDS variant runs one block per
+// 4 of those (one per CU at the default grid).
 void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, DevCounters* ctr,
-                     int grid, bool forward, int bu_div, hipStream_t st) {
-    if (forward)
-        k_gr_level<true><<<grid, GR_BLOCK, 0, st>>>(g, level, qin, qout, ctr, bu_div);
-    else
-        k_gr_level<false><<<grid, GR_BLOCK, 0, st>>>(g, level, qin, qout, ctr, bu_div);
+                     const GrBits& bits, const GrTune& tune, int grid, bool forward, hipStream_t st) {
+    if (tune.lds) {
+        size_t shm = 4 * (size_t)bits.nwords;
+        int gl = std::max(1, grid / 4);
+        if (forward)
+            k_gr_level<true, GRL_BLOCK_LDS><<<gl, GRL_BLOCK_LDS, shm, st>>>(g, level, qin, qout, ctr, bits, tune);
+        else
+            k_gr_level<false, GRL_BLOCK_LDS><<<gl, GRL_BLOCK_LDS, shm, st>>>(g, level, qin, qout, ctr, bits, tune);
+    } else {
+        if (forward)
+            k_gr_level<true, 256><<<grid, 256, 0, st>>>(g, level, qin, qout, ctr, bits, tune);
+        else
+            k_gr_level<false, 256><<<grid, 256, 0, st>>>(g, level, qin, qout, ctr, bits, tune);
+    }
 }
 
 int persistent_gr_grid(int device) {
@@ -1123,13 +1258,17 @@ int persistent_gr_grid(int device) {
     return cus * want;
 }
 
-hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounters* ctr, int bu_div,
-                                int seed_deficits, bool forward, int32_t* wl0, int32_t* wl1,
-                                int32_t* wl2, bool topology, int sign, int grid, hipStream_t st) {
+hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounters* ctr,
+                                const GrBits& bits, const GrTune& tune, int seed_deficits, bool forward,
+                                int32_t* wl0, int32_t* wl1, int32_t* wl2, bool topology, int sign,
+                                int grid, hipStream_t st) {
     k_zero_counters_front<<<1, 64, 0, st>>>(ctr);
+    launch_fill_i32(reinterpret_cast<int32_t*>(bits.visited), 0, 4 * (int64_t)bits.nwords, st);
     DevGraph gg = g;
+    GrBits bb = bits;
+    GrTune tt = tune;
     int topo = topology ? 1 : 0;
-    void* args[] = {&gg, &q0, &q1, &ctr, &bu_div, &seed_deficits, &wl0, &wl1, &wl2, &topo, &sign};
+    void* args[] = {&gg, &q0, &q1, &ctr, &bb, &tt, &seed_deficits, &wl0, &wl1, &wl2, &topo, &sign};
     const void* fn = forward ? reinterpret_cast<const void*>(&k_gr_persistent<true>)
                              : reinterpret_cast<const void*>(&k_gr_persistent<false>);
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(GRP_BLOCK), args, 0, st);
@@ -1217,6 +1356,10 @@ void launch_batch_cleanup(BatchTable tb, int32_t* need, const int32_t* slot_of, 
 void launch_flow_slots(const DevGraph& g, int32_t* flow_slot, unsigned long long* count,
                        hipStream_t st) {
     k_flow_slots<<<grid_for(g.n, 256, 4096), 256, 0, st>>>(g, flow_slot, count);
+}
+
+void launch_reduce_bytes(const DevGraph& g, DevCounters* ctr, hipStream_t st) {
+    k_reduce_bytes<<<KC_NCLASS, 256, 0, st>>>(g, ctr);
 }
 
 void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipStream_t st) {

@@ -32,11 +32,19 @@ struct DevGraph {
     int32_t* capsum;  // cap[j] + cap[rev[j]]: res[rev[j]] = capsum[j] - res[j] between sweeps
     int64_t* e;
     int32_t* h;
+    int64_t used_slots;                  // sum of row_len
+    unsigned long long* bytes_part;      // KC_NCLASS x BYTES_SLOTS algorithmic-byte partial sums
+    int count_bytes;                     // 1 while kernel classes are being profiled
 };
+
+// Partial sums of algorithmic bytes: a kernel block adds into slot
+// blockIdx % BYTES_SLOTS of its class, so counting contends on no address.
+constexpr int BYTES_SLOTS = 4096;
 
 // Device-side counters, one block of memory read back with a single copy.
 struct DevCounters {
-    int32_t front[3];          // global-relabel frontier sizes, ring over levels
+    unsigned long long front[3];  // per BFS level (ring): entries in the low 32 bits, the
+                                  // frontier's slot count in the high 32 bits
     int32_t wl[4];             // worklist sizes per degree bin
     int32_t err;               // batch: invalid update seen
     int32_t overflow;          // batch: row slack exhausted
@@ -46,6 +54,8 @@ struct DevCounters {
     int32_t bar_err;           // persistent global relabel: barrier gave up / level bound hit
     unsigned bar_count;        // grid barrier arrivals
     unsigned bar_gen;          // grid barrier generation
+    long long unv[3];          // unvisited slots at the start of level lv in unv[lv % 3]; the
+                               // relabel's init leaves the total of all labellable rows in unv[2]
     long long deficit_sum;     // sum of negative excess outside {s,t}
     long long e_t;             // e(t) at the worklist build
     unsigned long long bytes[8];  // algorithmic bytes per kernel class
@@ -60,13 +70,31 @@ constexpr int BIN1_MAX = 512;
 constexpr int BLOCK_PR = 1024;
 // Global-relabel frontier entries cover at most GR_CHUNK slots of a row.
 constexpr int GR_CHUNK = 256;
-// A level scans bottom-up (unvisited vertices look for a parent in their own
-// row) when its frontier holds more than n / bu_div entries; bu_div = 0 keeps
-// every level top-down.  Default below; MF_GR_BOTTOM_UP_DIV overrides it.
-constexpr int GR_BOTTOM_UP_DIV = 64;
+// Direction rule (Beamer, Asanovic, Patterson's direction-optimizing BFS:
+// alpha 14; beta 64 measured best here, their paper uses 24) and the entry
+// count above which a top-down level stages the visited bitmap in LDS.
+constexpr int GR_BU_ALPHA = 14;
+constexpr int GR_BU_BETA = 64;
+constexpr int GR_STAGE_MIN = 1024;
 // Bottom-up: a thread checks this many slots of its row before handing the
 // rest of a long row to a wave.
 constexpr int BU_THREAD_SLOTS = 32;
+
+// Bitmaps of one global relabel: visited (nwords words), then a ring of
+// three frontier bitmaps (fb + r * nwords), all zeroed before each relabel.
+struct GrBits {
+    unsigned* visited;
+    unsigned* fb;
+    int nwords;
+};
+
+// Direction and staging knobs of the BFS levels.
+struct GrTune {
+    int bu_alpha;   // bottom-up when frontier slots * alpha > unvisited slots ...
+    int bu_beta;    // ... and frontier vertices * beta > n; alpha <= 0 disables bottom-up
+    int stage_min;  // top-down levels with at least this many entries stage the visited bitmap
+    int lds;        // the bitmap fits in LDS (dynamic shared memory provided at launch)
+};
 
 // Batch scratch: hash table of absent pairs, keyed by the unordered pair.
 struct BatchTable {
@@ -81,13 +109,16 @@ void launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t st);
 void launch_reset(const DevGraph& g, int64_t slot_cap, hipStream_t st);
 void launch_saturate_source(const DevGraph& g, DevCounters* ctr, hipStream_t st);
 void launch_zero_loop_counters(DevCounters* ctr, hipStream_t st);
-void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, int seed_deficits, hipStream_t st);
+void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, const GrBits& bits, int seed_deficits,
+                    hipStream_t st);
+int gr_level_lds_bytes(int nwords, int device);
 void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, DevCounters* ctr,
-                     int grid, bool forward, int bu_div, hipStream_t st);
+                     const GrBits& bits, const GrTune& tune, int grid, bool forward, hipStream_t st);
 int persistent_gr_grid(int device);
-hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounters* ctr, int bu_div,
-                                int seed_deficits, bool forward, int32_t* wl0, int32_t* wl1,
-                                int32_t* wl2, bool topology, int sign, int grid, hipStream_t st);
+hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounters* ctr,
+                                const GrBits& bits, const GrTune& tune, int seed_deficits, bool forward,
+                                int32_t* wl0, int32_t* wl1, int32_t* wl2, bool topology, int sign,
+                                int grid, hipStream_t st);
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
                            DevCounters* ctr, bool topology, int sign, hipStream_t st);
 void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc, bool pull,
@@ -95,6 +126,7 @@ void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bi
 void launch_remove_invalid(const DevGraph& g, const int32_t* wl, int count, int bin,
                            DevCounters* ctr, hipStream_t st);
 void launch_clear_counters(DevCounters* ctr, hipStream_t st);
+void launch_reduce_bytes(const DevGraph& g, DevCounters* ctr, hipStream_t st);
 void launch_batch_locate(const DevGraph& g, const mf_update* upd, int64_t k, int32_t* slot_of,
                          int32_t* win, BatchTable tb, int32_t* need, DevCounters* ctr,
                          hipStream_t st);
