@@ -199,6 +199,45 @@ mf_status mf_debug_selftest(int32_t device);
 /* Release the handle and its device memory.  NULL is ignored. */
 void mf_graph_free(mf_graph* g);
 
+/* ---- many independent graphs in one launch --------------------------------
+ * A batch holds num_graphs graphs in pooled device memory.  mf_batch_maxflow
+ * solves all of them from zero flow in one launch (one workgroup per graph
+ * runs the whole loop of Algorithm 1, largest graphs first);
+ * mf_batch_apply repairs all of them after their update batches (Algorithm
+ * 5) in two launches.  Each graph's value is exactly what mf_maxflow /
+ * mf_apply_batch return for it alone. */
+typedef struct mf_batch mf_batch;
+
+/* num_graphs >= 1 graphs, graph i with n[i] vertices, edges
+ * [edge_offset[i], edge_offset[i+1]) of the concatenated host arrays src,
+ * dst, cap (vertex ids local to the graph, 0..n[i]-1), source s[i], sink
+ * t[i].  edge_offset has num_graphs + 1 entries, edge_offset[0] = 0.  Every
+ * graph is validated as in mf_graph_load before anything is allocated.
+ * opt (NULL: defaults) applies to every graph. */
+mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edge_offset,
+                        const int32_t* src, const int32_t* dst, const int32_t* cap, const int32_t* s,
+                        const int32_t* t, const mf_options* opt, mf_batch** out);
+
+/* Max-flow value of every graph from zero flow; values: int64[num_graphs].
+ * MF_ERR_NOT_CONVERGED if any graph hit the iteration cap (the other values
+ * are still written). */
+mf_status mf_batch_maxflow(mf_batch* b, int64_t* values);
+
+/* Apply graph i's updates upd[update_offset[i] .. update_offset[i+1]) (host
+ * memory, ids local to the graph, same semantics as mf_apply_batch) to every
+ * graph and return every new value.  All updates of all graphs are validated
+ * first; on MF_ERR_INVALID or MF_ERR_OVERFLOW (a capacity pair above
+ * INT32_MAX, or a row whose insertion slack would be exceeded: load with more
+ * slack) no graph is changed.  Requires a prior mf_batch_maxflow. */
+mf_status mf_batch_apply(mf_batch* b, const int64_t* update_offset, const mf_update* upd,
+                         int64_t* values);
+
+/* Loop iterations (global relabels) of each graph in the last call
+ * (int32[num_graphs], or NULL) and the call's host wall time in ms. */
+mf_status mf_batch_info(const mf_batch* b, int32_t* iterations, double* last_ms);
+
+void mf_batch_free(mf_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,8 @@ MF_ERR_STATE = 6
 EXPORTED = ["mf_default_options", "mf_status_string", "mf_graph_load", "mf_maxflow",
             "mf_apply_batch", "mf_apply_batch_device", "mf_min_cut", "mf_get_flow",
             "mf_get_stats", "mf_profile", "mf_debug_initial_labels", "mf_debug_selftest",
-            "mf_graph_free"]
+            "mf_graph_free", "mf_batch_load", "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info",
+            "mf_batch_free"]
 
 KERNEL_CLASSES = ["global_relabel", "push_relabel", "remove_invalid", "worklist", "batch", "init",
                   "unused6", "unused7"]
@@ -93,9 +94,16 @@ def lib():
         L.mf_debug_selftest.argtypes = [i32]
         L.mf_graph_free.argtypes = [vp]
         L.mf_graph_free.restype = None
+        L.mf_batch_load.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Options), C.POINTER(vp)]
+        L.mf_batch_maxflow.argtypes = [vp, vp]
+        L.mf_batch_apply.argtypes = [vp, vp, vp, vp]
+        L.mf_batch_info.argtypes = [vp, vp, C.POINTER(C.c_double)]
+        L.mf_batch_free.argtypes = [vp]
+        L.mf_batch_free.restype = None
         for name in ["mf_graph_load", "mf_maxflow", "mf_apply_batch", "mf_apply_batch_device",
                      "mf_min_cut", "mf_get_flow", "mf_get_stats", "mf_profile",
-                     "mf_debug_initial_labels", "mf_debug_selftest"]:
+                     "mf_debug_initial_labels", "mf_debug_selftest", "mf_batch_load",
+                     "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info"]:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -273,6 +281,70 @@ class MaxFlowGraph:
     def close(self):
         if self.h:
             mf_graph_free(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MaxFlowBatch:
+    """Many independent graphs solved together (mf_batch_*).  graphs: a list of
+    objects with n, src, dst, cap, s, t (for example gen.Graph)."""
+
+    def __init__(self, graphs, **options):
+        self.G = len(graphs)
+        n = np.array([g.n for g in graphs], np.int32)
+        off = np.zeros(self.G + 1, np.int64)
+        off[1:] = np.cumsum([g.src.size for g in graphs])
+        cat = lambda name: _i32(np.concatenate([getattr(g, name) for g in graphs]) if self.G else [])
+        src, dst, cap = cat("src"), cat("dst"), cat("cap")
+        s = np.array([g.s for g in graphs], np.int32)
+        t = np.array([g.t for g in graphs], np.int32)
+        opt = make_options(**options) if options else None
+        h = C.c_void_p()
+        _check(lib().mf_batch_load(self.G, n.ctypes.data, off.ctypes.data, src.ctypes.data,
+                                   dst.ctypes.data, cap.ctypes.data, s.ctypes.data, t.ctypes.data,
+                                   C.byref(opt) if opt is not None else None, C.byref(h)),
+               "mf_batch_load")
+        self.h = h.value
+
+    def maxflow(self):
+        vals = np.zeros(self.G, np.int64)
+        _check(lib().mf_batch_maxflow(self.h, vals.ctypes.data), "mf_batch_maxflow")
+        return vals
+
+    def apply(self, batches):
+        """batches: one (u, v, c) triple of arrays per graph."""
+        off = np.zeros(self.G + 1, np.int64)
+        off[1:] = np.cumsum([np.asarray(b[0]).size for b in batches])
+        upd = np.zeros((int(off[-1]), 3), np.int32)
+        for i, (u, v, c) in enumerate(batches):
+            upd[off[i]:off[i + 1], 0] = u
+            upd[off[i]:off[i + 1], 1] = v
+            upd[off[i]:off[i + 1], 2] = c
+        vals = np.zeros(self.G, np.int64)
+        _check(lib().mf_batch_apply(self.h, off.ctypes.data, upd.ctypes.data, vals.ctypes.data),
+               "mf_batch_apply")
+        return vals
+
+    def info(self):
+        it = np.zeros(self.G, np.int32)
+        ms = C.c_double()
+        _check(lib().mf_batch_info(self.h, it.ctypes.data, C.byref(ms)), "mf_batch_info")
+        return it, ms.value
+
+    def close(self):
+        if self.h:
+            lib().mf_batch_free(self.h)
             self.h = None
 
     def __enter__(self):

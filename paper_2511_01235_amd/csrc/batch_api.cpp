@@ -1,0 +1,411 @@
+// Batched solve of many independent graphs (C ABI part).
+//
+// All graphs share pooled device arrays; each graph keeps its own rows,
+// residuals, excesses, heights, queues, worklists, bitmaps and counters.  One
+// launch solves every graph (one workgroup per graph running the whole loop
+// of Algorithm 1 on the device), one more pair of launches repairs every
+// graph after its batch of updates (Algorithm 5), so the host synchronises a
+// constant number of times per call however many graphs there are.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "mf.h"
+#include "mf_internal.h"
+
+using mf::DevCounters;
+using mf::GraphSlot;
+using mf::GraphUpdates;
+
+struct mf_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int32_t G = 0;
+    mf_options opt{};
+    mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0};
+    std::vector<int32_t> n, kc;
+    std::vector<int64_t> vbase, rpbase, sbase, slots, bbase, qbase;
+    int64_t total_v = 0, total_rp = 0, total_s = 0, total_b = 0, total_q = 0;
+    // pools
+    int32_t *row_ptr = nullptr, *row_len = nullptr, *row_sorted = nullptr;
+    int2* cr = nullptr;
+    int32_t *rev = nullptr, *cap = nullptr, *capsum = nullptr, *win = nullptr, *need = nullptr;
+    int64_t* e = nullptr;
+    int32_t* h = nullptr;
+    unsigned* bits = nullptr;
+    int2* q = nullptr;
+    int32_t* wl = nullptr;
+    DevCounters* ctr = nullptr;
+    unsigned long long* bytes_part = nullptr;
+    GraphSlot* slots_d = nullptr;
+    int32_t* order_d = nullptr;
+    std::vector<GraphSlot> slots_h;
+    // update scratch, grown on demand
+    GraphUpdates* gu_d = nullptr;
+    mf_update* upd_d = nullptr;
+    int32_t *slot_of = nullptr, *touched = nullptr;
+    unsigned long long* tkey = nullptr;
+    int32_t *twin = nullptr, *tslot = nullptr;
+    int64_t upd_cap = 0, tab_cap = 0;
+    std::vector<DevCounters> ctr_h;
+    bool solved = false, poisoned = false;
+    double last_ms = 0;
+};
+
+namespace {
+
+template <class T>
+hipError_t balloc(T** p, int64_t count) {
+    return hipMalloc((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+}
+
+template <class T>
+void bfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void free_batch(mf_batch* b) {
+    bfree(b->row_ptr); bfree(b->row_len); bfree(b->row_sorted); bfree(b->cr); bfree(b->rev);
+    bfree(b->cap); bfree(b->capsum); bfree(b->win); bfree(b->need); bfree(b->e); bfree(b->h);
+    bfree(b->bits); bfree(b->q); bfree(b->wl); bfree(b->ctr); bfree(b->bytes_part);
+    bfree(b->slots_d); bfree(b->order_d); bfree(b->gu_d); bfree(b->upd_d); bfree(b->slot_of);
+    bfree(b->touched); bfree(b->tkey); bfree(b->twin); bfree(b->tslot);
+}
+
+#define MFB_HIP(call)              \
+    do {                           \
+        if ((call) != hipSuccess) { \
+            b->poisoned = true;    \
+            return MF_ERR_DEVICE;  \
+        }                          \
+    } while (0)
+
+mf_status read_results(mf_batch* b, int64_t* values) {
+    MFB_HIP(hipMemcpyAsync(b->slots_h.data(), b->slots_d, sizeof(GraphSlot) * b->G, hipMemcpyDeviceToHost,
+                           b->stream));
+    MFB_HIP(hipStreamSynchronize(b->stream));
+    mf_status rc = MF_OK;
+    for (int i = 0; i < b->G; ++i) {
+        values[i] = b->slots_h[i].value;
+        if (b->slots_h[i].status != 0) rc = MF_ERR_NOT_CONVERGED;
+    }
+    return rc;
+}
+
+struct Clock {
+    mf_batch* b;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    explicit Clock(mf_batch* bb) : b(bb) {}
+    ~Clock() {
+        b->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edge_offset,
+                        const int32_t* src, const int32_t* dst, const int32_t* cap, const int32_t* s,
+                        const int32_t* t, const mf_options* opt, mf_batch** out) {
+    if (!out) return MF_ERR_INVALID;
+    *out = nullptr;
+    if (num_graphs < 1 || !n || !edge_offset || !s || !t) return MF_ERR_INVALID;
+    mf_options o;
+    mf_default_options(&o);
+    if (opt) {
+        if (opt->struct_size != sizeof(mf_options)) return MF_ERR_INVALID;
+        o = *opt;
+    }
+    if (edge_offset[0] != 0) return MF_ERR_INVALID;
+    for (int i = 0; i < num_graphs; ++i)
+        if (edge_offset[i + 1] < edge_offset[i]) return MF_ERR_INVALID;
+    int32_t slack_min = o.insert_slack_min > 0 ? o.insert_slack_min : 2;
+    int32_t slack_pct = o.insert_slack_pct > 0 ? o.insert_slack_pct : 12;
+    // validate and build every graph on the host first: nothing is allocated on failure
+    std::vector<mf::HostBiCSR> hb((size_t)num_graphs);
+    for (int i = 0; i < num_graphs; ++i) {
+        int64_t e0 = edge_offset[i], m = edge_offset[i + 1] - e0;
+        mf_status rc = mf::build_bicsr(n[i], m, m ? src + e0 : nullptr, m ? dst + e0 : nullptr,
+                                       m ? cap + e0 : nullptr, s[i], t[i], slack_min, slack_pct, &hb[(size_t)i]);
+        if (rc != MF_OK) return rc;
+    }
+    mf_batch* b = new (std::nothrow) mf_batch();
+    if (!b) return MF_ERR_OUT_OF_MEMORY;
+    auto fail = [&](mf_status r) {
+        free_batch(b);
+        if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+        delete b;
+        return r;
+    };
+    b->G = num_graphs;
+    b->opt = o;
+    int dev = o.device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(MF_ERR_DEVICE);
+    if (hipSetDevice(dev) != hipSuccess) return fail(MF_ERR_DEVICE);
+    b->device = dev;
+    if (o.stream) {
+        b->stream = (hipStream_t)o.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) return fail(MF_ERR_DEVICE);
+        b->own_stream = true;
+    }
+    const int G = num_graphs;
+    b->n.resize(G); b->kc.resize(G); b->vbase.resize(G); b->rpbase.resize(G); b->sbase.resize(G);
+    b->slots.resize(G); b->bbase.resize(G); b->qbase.resize(G);
+    for (int i = 0; i < G; ++i) {
+        const mf::HostBiCSR& x = hb[(size_t)i];
+        b->n[i] = n[i];
+        int64_t S = x.row_ptr[(size_t)n[i]];
+        int64_t kc = o.kernel_cycles > 0 ? o.kernel_cycles : (x.m_unique + n[i] / 2) / n[i];
+        b->kc[i] = (int32_t)std::max<int64_t>(1, kc);
+        b->vbase[i] = b->total_v;
+        b->rpbase[i] = b->total_rp;
+        b->sbase[i] = b->total_s;
+        b->slots[i] = S;
+        b->bbase[i] = b->total_b;
+        b->qbase[i] = b->total_q;
+        b->total_v += n[i];
+        b->total_rp += n[i] + 1;
+        b->total_s += S;
+        b->total_b += 4 * (int64_t)((n[i] + 31) / 32);
+        b->total_q += 2 * ((int64_t)n[i] + S / mf::GR_CHUNK + 64);
+    }
+    if (b->total_s > INT_MAX || b->total_v > INT_MAX) return fail(MF_ERR_OVERFLOW);
+    const int64_t V = b->total_v, SS = b->total_s;
+    if (balloc(&b->row_ptr, b->total_rp) || balloc(&b->row_len, V) || balloc(&b->row_sorted, V) ||
+        balloc(&b->cr, SS) || balloc(&b->rev, SS) || balloc(&b->cap, SS) || balloc(&b->capsum, SS) ||
+        balloc(&b->win, SS) || balloc(&b->need, V) || balloc(&b->e, V) || balloc(&b->h, V) ||
+        balloc(&b->bits, b->total_b) || balloc(&b->q, b->total_q) || balloc(&b->wl, 3 * V) ||
+        balloc(&b->ctr, G) || balloc(&b->bytes_part, (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS) ||
+        balloc(&b->slots_d, G) || balloc(&b->order_d, G))
+        return fail(MF_ERR_OUT_OF_MEMORY);
+    // host images of the pools (slot indices made pool-global)
+    {
+        std::vector<int32_t> rp((size_t)b->total_rp), rl((size_t)V), rs((size_t)V), rv((size_t)SS),
+            cp((size_t)SS), cs((size_t)SS, 0);
+        std::vector<int2> crh((size_t)SS);
+        for (int i = 0; i < G; ++i) {
+            const mf::HostBiCSR& x = hb[(size_t)i];
+            int64_t sb = b->sbase[i];
+            for (int32_t v = 0; v <= n[i]; ++v) rp[(size_t)(b->rpbase[i] + v)] = (int32_t)(sb + x.row_ptr[(size_t)v]);
+            for (int32_t v = 0; v < n[i]; ++v) {
+                rl[(size_t)(b->vbase[i] + v)] = x.row_len[(size_t)v];
+                rs[(size_t)(b->vbase[i] + v)] = x.row_sorted[(size_t)v];
+            }
+            for (int64_t j = 0; j < b->slots[i]; ++j) {
+                crh[(size_t)(sb + j)] = make_int2(x.col[(size_t)j], x.cap[(size_t)j]);
+                cp[(size_t)(sb + j)] = x.cap[(size_t)j];
+                int32_t r = x.rev[(size_t)j];
+                rv[(size_t)(sb + j)] = r >= 0 ? (int32_t)(sb + r) : -1;
+                if (r >= 0) cs[(size_t)(sb + j)] = x.cap[(size_t)j] + x.cap[(size_t)r];
+            }
+        }
+        hb.clear();
+        hb.shrink_to_fit();
+        hipStream_t st = b->stream;
+        if (hipMemcpyAsync(b->row_ptr, rp.data(), 4 * rp.size(), hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(b->row_len, rl.data(), 4 * rl.size(), hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(b->row_sorted, rs.data(), 4 * rs.size(), hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(b->cr, crh.data(), 8 * crh.size(), hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(b->rev, rv.data(), 4 * rv.size(), hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(b->cap, cp.data(), 4 * cp.size(), hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(b->capsum, cs.data(), 4 * cs.size(), hipMemcpyHostToDevice, st))
+            return fail(MF_ERR_DEVICE);
+        mf::launch_fill_i32(b->win, -1, SS, st);
+        mf::launch_fill_i32(b->need, 0, V, st);
+        mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->e), 0, 2 * V, st);
+        mf::launch_fill_i32(b->h, 0, V, st);
+        mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->bytes_part), 0,
+                            2 * (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS, st);
+        mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->ctr), 0, (int64_t)G * sizeof(DevCounters) / 4, st);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return fail(MF_ERR_DEVICE);
+    }
+    // per-graph views
+    b->slots_h.resize((size_t)G);
+    for (int i = 0; i < G; ++i) {
+        GraphSlot& S = b->slots_h[(size_t)i];
+        std::memset(&S, 0, sizeof(S));
+        mf::DevGraph& g = S.g;
+        g.n = n[i];
+        g.s = s[i];
+        g.t = t[i];
+        g.root = t[i];
+        g.pinned = s[i];
+        g.row_ptr = b->row_ptr + b->rpbase[i];
+        g.row_len = b->row_len + b->vbase[i];
+        g.row_sorted = b->row_sorted + b->vbase[i];
+        g.cr = b->cr;
+        g.rev = b->rev;
+        g.cap = b->cap;
+        g.capsum = b->capsum;
+        g.e = b->e + b->vbase[i];
+        g.h = b->h + b->vbase[i];
+        g.used_slots = 0;  // set below from the rows
+        g.bytes_part = b->bytes_part;
+        g.count_bytes = 0;
+        int64_t qc = (int64_t)n[i] + b->slots[i] / mf::GR_CHUNK + 64;
+        S.q0 = b->q + b->qbase[i];
+        S.q1 = S.q0 + qc;
+        S.wl0 = b->wl + 3 * b->vbase[i];
+        S.wl1 = S.wl0 + n[i];
+        S.wl2 = S.wl1 + n[i];
+        S.bits.nwords = (n[i] + 31) / 32;
+        S.bits.visited = b->bits + b->bbase[i];
+        S.bits.fb = S.bits.visited + S.bits.nwords;
+        S.ctr = b->ctr + i;
+        S.kc = b->kc[i];
+        S.warm = o.cold_start ? 0 : 1;
+        S.max_iter = o.max_iterations > 0 ? o.max_iterations : 4 * (int64_t)n[i] + 1000;
+    }
+    {
+        // used slots per graph = sum of its row lengths
+        std::vector<int32_t> rl((size_t)V);
+        if (hipMemcpy(rl.data(), b->row_len, 4 * (size_t)V, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(MF_ERR_DEVICE);
+        for (int i = 0; i < G; ++i) {
+            int64_t u = 0;
+            for (int32_t v = 0; v < n[i]; ++v) u += rl[(size_t)(b->vbase[i] + v)];
+            b->slots_h[(size_t)i].g.used_slots = u;
+        }
+    }
+    // largest graphs first, so that the long solves start early
+    std::vector<int32_t> order((size_t)G);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return b->slots[a] > b->slots[c]; });
+    if (hipMemcpy(b->slots_d, b->slots_h.data(), sizeof(GraphSlot) * G, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->order_d, order.data(), 4 * (size_t)G, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(MF_ERR_DEVICE);
+    *out = b;
+    return MF_OK;
+}
+
+mf_status mf_batch_maxflow(mf_batch* b, int64_t* values) {
+    if (!b || !values) return MF_ERR_INVALID;
+    if (b->poisoned) return MF_ERR_DEVICE;
+    if (hipSetDevice(b->device) != hipSuccess) return MF_ERR_DEVICE;
+    Clock clock(b);
+    b->solved = false;
+    mf::launch_batch_solve(b->slots_d, b->order_d, b->G, 0, b->tune, b->stream);
+    MFB_HIP(hipGetLastError());
+    mf_status rc = read_results(b, values);
+    if (rc == MF_OK) b->solved = true;
+    return rc;
+}
+
+mf_status mf_batch_apply(mf_batch* b, const int64_t* update_offset, const mf_update* upd, int64_t* values) {
+    if (!b || !update_offset || !values) return MF_ERR_INVALID;
+    if (b->poisoned) return MF_ERR_DEVICE;
+    if (!b->solved) return MF_ERR_STATE;
+    const int G = b->G;
+    if (update_offset[0] != 0) return MF_ERR_INVALID;
+    for (int i = 0; i < G; ++i)
+        if (update_offset[i + 1] < update_offset[i] || update_offset[i + 1] - update_offset[i] > INT_MAX / 2)
+            return MF_ERR_INVALID;
+    const int64_t K = update_offset[G];
+    if (K > 0 && !upd) return MF_ERR_INVALID;
+    if (hipSetDevice(b->device) != hipSuccess) return MF_ERR_DEVICE;
+    Clock clock(b);
+    hipStream_t st = b->stream;
+    // scratch: updates, per-update slots, one hash table per graph
+    std::vector<int64_t> toff((size_t)G + 1, 0);
+    std::vector<int32_t> tcap((size_t)G);
+    for (int i = 0; i < G; ++i) {
+        int64_t k = update_offset[i + 1] - update_offset[i];
+        int32_t c = 16;
+        while (c < 2 * k) c *= 2;
+        tcap[(size_t)i] = c;
+        toff[(size_t)i + 1] = toff[(size_t)i] + c;
+    }
+    if (K > b->upd_cap) {
+        MFB_HIP(hipStreamSynchronize(st));
+        bfree(b->upd_d); bfree(b->slot_of); bfree(b->touched);
+        if (balloc(&b->upd_d, K) || balloc(&b->slot_of, K) || balloc(&b->touched, K)) {
+            b->upd_cap = 0;
+            return MF_ERR_OUT_OF_MEMORY;
+        }
+        b->upd_cap = K;
+    }
+    if (toff[(size_t)G] > b->tab_cap) {
+        MFB_HIP(hipStreamSynchronize(st));
+        bfree(b->tkey); bfree(b->twin); bfree(b->tslot);
+        int64_t c = toff[(size_t)G];
+        if (balloc(&b->tkey, c) || balloc(&b->twin, 2 * c) || balloc(&b->tslot, 2 * c)) {
+            b->tab_cap = 0;
+            return MF_ERR_OUT_OF_MEMORY;
+        }
+        mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->tkey), -1, 2 * c, st);
+        mf::launch_fill_i32(b->twin, -1, 2 * c, st);
+        b->tab_cap = c;
+    }
+    if (!b->gu_d && balloc(&b->gu_d, G)) return MF_ERR_OUT_OF_MEMORY;
+    std::vector<GraphUpdates> gu((size_t)G);
+    for (int i = 0; i < G; ++i) {
+        GraphUpdates& U = gu[(size_t)i];
+        int64_t o0 = update_offset[i];
+        U.upd = b->upd_d + o0;
+        U.k = (int32_t)(update_offset[i + 1] - o0);
+        U.slot_of = b->slot_of + o0;
+        U.touched = b->touched + o0;
+        U.win = b->win;
+        U.need = b->need + b->vbase[i];
+        U.tb.key = b->tkey + toff[(size_t)i];
+        U.tb.win = b->twin + 2 * toff[(size_t)i];
+        U.tb.slot = b->tslot + 2 * toff[(size_t)i];
+        U.tb.capacity = tcap[(size_t)i];
+    }
+    if (K > 0) MFB_HIP(hipMemcpyAsync(b->upd_d, upd, sizeof(mf_update) * (size_t)K, hipMemcpyHostToDevice, st));
+    MFB_HIP(hipMemcpyAsync(b->gu_d, gu.data(), sizeof(GraphUpdates) * (size_t)G, hipMemcpyHostToDevice, st));
+    mf::launch_batch_locate_multi(b->slots_d, b->gu_d, G, st);
+    MFB_HIP(hipGetLastError());
+    b->ctr_h.resize((size_t)G);
+    MFB_HIP(hipMemcpyAsync(b->ctr_h.data(), b->ctr, sizeof(DevCounters) * (size_t)G, hipMemcpyDeviceToHost, st));
+    MFB_HIP(hipStreamSynchronize(st));
+    bool err = false, ovf = false, slack = false;
+    for (int i = 0; i < G; ++i) {
+        err |= b->ctr_h[(size_t)i].err != 0;
+        ovf |= b->ctr_h[(size_t)i].cap_overflow != 0;
+        slack |= b->ctr_h[(size_t)i].overflow != 0;
+    }
+    if (err || ovf || slack) {
+        // nothing was changed: return the scratch to idle and report
+        mf::launch_batch_cleanup_multi(b->gu_d, G, st);
+        MFB_HIP(hipGetLastError());
+        MFB_HIP(hipStreamSynchronize(st));
+        return err ? MF_ERR_INVALID : MF_ERR_OVERFLOW;
+    }
+    b->solved = false;
+    mf::launch_batch_repair_multi(b->slots_d, b->gu_d, b->order_d, G, b->tune, st);
+    MFB_HIP(hipGetLastError());
+    mf_status rc = read_results(b, values);
+    if (rc == MF_OK) b->solved = true;
+    return rc;
+}
+
+mf_status mf_batch_info(const mf_batch* b, int32_t* iterations, double* last_ms) {
+    if (!b) return MF_ERR_INVALID;
+    if (iterations)
+        for (int i = 0; i < b->G; ++i) iterations[i] = b->slots_h[(size_t)i].iterations;
+    if (last_ms) *last_ms = b->last_ms;
+    return MF_OK;
+}
+
+void mf_batch_free(mf_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    free_batch(b);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+}  // extern "C"

@@ -28,6 +28,7 @@
 #include <cstdint>
 #include <cstdlib>
 
+#include "mf.h"
 #include "mf_internal.h"
 
 namespace mf {
@@ -156,6 +157,14 @@ __device__ __forceinline__ long long block_sum_i64(long long x) {
     return r;  // valid in wave 0
 }
 
+// Which part of the work a block does: block bid of nb.  Ordinary launches
+// use the hardware grid; the per-graph solver gives each graph one block
+// that does everything (bid 0 of 1).
+struct Par {
+    int bid, nb;
+};
+__device__ __forceinline__ Par hw_par() { return Par{(int)blockIdx.x, (int)gridDim.x}; }
+
 // ---- initialisation (Algorithm 1) -----------------------------------------
 
 __global__ void k_fill_i32(int32_t* p, int32_t value, int64_t count) {
@@ -234,10 +243,10 @@ __device__ __forceinline__ void append_entries(int add, int slots, int v, int2* 
 __device__ __forceinline__ bool bit_of(const unsigned* bm, int v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
 __device__ __forceinline__ void set_bit(unsigned* bm, int v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
 
-__device__ __forceinline__ void gr_init_body(const DevGraph& g, int2* q0, DevCounters* ctr,
+__device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, int2* q0, DevCounters* ctr,
                                              const GrBits& bits, int seed_deficits) {
     const int N = g.n;
-    for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
+    for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
         int v = base + threadIdx.x;
         int add = 0, slots = 0;
         if (v < N) {
@@ -255,7 +264,7 @@ __device__ __forceinline__ void gr_init_body(const DevGraph& g, int2* q0, DevCou
         }
         append_entries(add, slots, v, q0, &ctr->front[0]);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (P.bid == 0 && threadIdx.x == 0) {
         // slots of every row that may be labelled, the seeds' included
         ctr->unv[2] = (long long)g.used_slots - g.row_len[g.pinned];
         add_bytes(g, KC_GR, 12ull * (unsigned long long)N);
@@ -264,7 +273,7 @@ __device__ __forceinline__ void gr_init_body(const DevGraph& g, int2* q0, DevCou
 
 __global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr, GrBits bits,
                                                  int seed_deficits) {
-    gr_init_body(g, q0, ctr, bits, seed_deficits);
+    gr_init_body(hw_par(), g, q0, ctr, bits, seed_deficits);
 }
 
 // One BFS level.  Top-down (small frontier): each block takes 256 frontier
@@ -296,7 +305,8 @@ __device__ __forceinline__ int discover(const DevGraph& g, const GrBits& bits, i
 // bitmap the direction needs (visited for top-down, the current frontier for
 // bottom-up), replacing the height gather of every scanned slot by a bit test.
 template <bool FWD, int BS>
-__device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt, const int2* qin,
+__device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, int lv, int cnt,
+                                              const int2* qin,
                                               int2* qout, DevCounters* ctr, const GrBits& bits,
                                               bool bu, const unsigned* s_bm) {
     __shared__ int s_u[BS];
@@ -320,7 +330,7 @@ __device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt
         // block-local list that the block's waves finish one row at a time
         __shared__ int s_defer[BS];
         __shared__ int s_ndefer;
-        for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
+        for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
             if (tid == 0) s_ndefer = 0;
             __syncthreads();
             int v = base + tid;
@@ -391,12 +401,12 @@ __device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt
             }
             __syncthreads();  // s_defer / s_ndefer are reused next round
         }
-        exam += (unsigned long long)((N + (int)(gridDim.x * blockDim.x) - 1) / (int)(gridDim.x * blockDim.x)) / 8;
+        exam += (unsigned long long)((N + (int)(P.nb * blockDim.x) - 1) / (int)(P.nb * blockDim.x)) / 8;
     } else {
         // entries per block: spread small frontiers over many blocks, up to
         // BS entries per block for large ones
-        const int per = min(BS, max(1, (cnt + (int)gridDim.x - 1) / (int)gridDim.x));
-        for (int eb = blockIdx.x * per; eb < cnt; eb += gridDim.x * per) {
+        const int per = min(BS, max(1, (cnt + P.nb - 1) / P.nb));
+        for (int eb = P.bid * per; eb < cnt; eb += P.nb * per) {
             // stage this block's entries and prefix-sum their slot counts
             int idx = eb + tid;
             int len = 0;
@@ -464,13 +474,39 @@ __device__ __forceinline__ void gr_level_body(const DevGraph& g, int lv, int cnt
 // the level started (the frontier's slots, and the unvisited slots of the
 // level before minus the frontier's), so all blocks decide alike; block 0
 // records this level's unvisited count for the next one.
-__device__ __forceinline__ bool choose_bottom_up(const DevGraph& g, DevCounters* ctr, int lv,
+__device__ __forceinline__ bool choose_bottom_up(const Par& P, const DevGraph& g, DevCounters* ctr, int lv,
                                                  int cnt, const GrTune& tune) {
     long long fs = (long long)(ctr->front[lv % 3] >> 32);
     long long mu = ctr->unv[(lv + 2) % 3] - fs;
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->unv[lv % 3] = mu;
+    if (P.bid == 0 && threadIdx.x == 0) ctr->unv[lv % 3] = mu;
     if (tune.bu_alpha <= 0) return false;
     return fs * (long long)tune.bu_alpha > mu && (long long)cnt * tune.bu_beta > (long long)g.n;
+}
+
+// One BFS level including its bookkeeping: read the frontier size, clear the
+// ring slots of level lv+2, choose the direction, optionally stage the
+// bitmap into LDS (s_dyn, when stage_ok), and do the level.  Returns the
+// frontier size (0: the BFS is over and nothing was done).
+template <bool FWD, int BS>
+__device__ __forceinline__ int gr_level_step(const Par& P, const DevGraph& g, int lv, const int2* qin,
+                                             int2* qout, DevCounters* ctr, const GrBits& bits,
+                                             const GrTune& tune, unsigned* s_dyn) {
+    const int cnt = bcast((int)(unsigned)(ctr->front[lv % 3] & 0xFFFFFFFFull));
+    if (P.bid == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
+    if (cnt == 0) return 0;
+    {   // the bitmap of level lv+2 (input of level lv-1, consumed) starts empty
+        unsigned* z = bits.fb + (size_t)((lv + 2) % 3) * bits.nwords;
+        for (int i = P.bid * blockDim.x + threadIdx.x; i < bits.nwords; i += P.nb * blockDim.x) z[i] = 0u;
+    }
+    const bool bu = choose_bottom_up(P, g, ctr, lv, cnt, tune);
+    const bool stage = s_dyn && tune.lds && (bu || cnt >= tune.stage_min);
+    if (stage) {
+        const unsigned* src = bu ? bits.fb + (size_t)(lv % 3) * bits.nwords : bits.visited;
+        for (int i = threadIdx.x; i < bits.nwords; i += blockDim.x) s_dyn[i] = src[i];
+        __syncthreads();
+    }
+    gr_level_body<FWD, BS>(P, g, lv, cnt, qin, qout, ctr, bits, bu, stage ? s_dyn : nullptr);
+    return cnt;
 }
 
 // Level kernel.  BS = 256 (default): four or more blocks per CU, no LDS
@@ -481,22 +517,7 @@ template <bool FWD, int BS>
 __global__ void __launch_bounds__(BS) k_gr_level(DevGraph g, int lv, const int2* qin, int2* qout,
                                                  DevCounters* ctr, GrBits bits, GrTune tune) {
     extern __shared__ unsigned s_dyn[];
-    const int cnt = bcast((int)(unsigned)(ctr->front[lv % 3] & 0xFFFFFFFFull));
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
-    if (cnt == 0) return;
-    {   // the bitmap of level lv+2 (input of level lv-1, consumed) starts empty
-        unsigned* z = bits.fb + (size_t)((lv + 2) % 3) * bits.nwords;
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < bits.nwords; i += gridDim.x * blockDim.x)
-            z[i] = 0u;
-    }
-    const bool bu = choose_bottom_up(g, ctr, lv, cnt, tune);
-    const bool stage = tune.lds && (bu || cnt >= tune.stage_min);
-    if (stage) {
-        const unsigned* src = bu ? bits.fb + (size_t)(lv % 3) * bits.nwords : bits.visited;
-        for (int i = threadIdx.x; i < bits.nwords; i += blockDim.x) s_dyn[i] = src[i];
-        __syncthreads();
-    }
-    gr_level_body<FWD, BS>(g, lv, cnt, qin, qout, ctr, bits, bu, stage ? s_dyn : nullptr);
+    gr_level_step<FWD, BS>(hw_par(), g, lv, qin, qout, ctr, bits, tune, tune.lds ? s_dyn : nullptr);
 }
 
 // Grid-wide barrier for a cooperative launch (all blocks resident).  Block
@@ -531,7 +552,7 @@ __device__ __forceinline__ void grid_sync(DevCounters* ctr) {
 }
 
 template <int BS>
-__device__ __forceinline__ void worklist_body(const DevGraph& g, int32_t* wl0, int32_t* wl1,
+__device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, int32_t* wl0, int32_t* wl1,
                                               int32_t* wl2, DevCounters* ctr, int topology, int sign);
 
 // Global relabel and worklist build in one cooperative launch: seeds, then
@@ -546,7 +567,7 @@ __global__ void __launch_bounds__(GRP_BLOCK) k_gr_persistent(DevGraph g, int2* q
                                                              int32_t* wl1, int32_t* wl2,
                                                              int topology, int sign) {
     __shared__ int s_flag[2];
-    gr_init_body(g, q0, ctr, bits, seed_deficits);
+    gr_init_body(hw_par(), g, q0, ctr, bits, seed_deficits);
     grid_sync(ctr);
     int lv = 0;
     for (;; ++lv) {
@@ -563,17 +584,12 @@ __global__ void __launch_bounds__(GRP_BLOCK) k_gr_persistent(DevGraph g, int2* q
             if (threadIdx.x == 0) atomicOr(&ctr->bar_err, 2);
             break;
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
-        unsigned* z = bits.fb + (size_t)((lv + 2) % 3) * bits.nwords;
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < bits.nwords; i += gridDim.x * blockDim.x)
-            z[i] = 0u;
-        const bool bu = choose_bottom_up(g, ctr, lv, cnt, tune);
-        gr_level_body<FWD, GRP_BLOCK>(g, lv, cnt, (lv & 1) ? q1 : q0, (lv & 1) ? q0 : q1, ctr, bits, bu,
-                                      nullptr);
+        gr_level_step<FWD, GRP_BLOCK>(hw_par(), g, lv, (lv & 1) ? q1 : q0, (lv & 1) ? q0 : q1, ctr, bits,
+                                      tune, nullptr);
         grid_sync(ctr);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr->levels = lv;
-    worklist_body<GRP_BLOCK>(g, wl0, wl1, wl2, ctr, topology, sign);
+    worklist_body<GRP_BLOCK>(hw_par(), g, wl0, wl1, wl2, ctr, topology, sign);
 }
 
 // ---- worklist (Section 5.2, O1) and value (Algorithm 5) --------------------
@@ -581,11 +597,11 @@ __global__ void __launch_bounds__(GRP_BLOCK) k_gr_persistent(DevGraph g, int2* q
 // sign = +1: active = positive excess below |V| (the solve); sign = -1:
 // active = negative excess below |V| (deficits to fill from t).
 template <int BS>
-__device__ __forceinline__ void worklist_body(const DevGraph& g, int32_t* wl0, int32_t* wl1,
+__device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, int32_t* wl0, int32_t* wl1,
                                               int32_t* wl2, DevCounters* ctr, int topology, int sign) {
     const int N = g.n;
     long long deficit = 0;
-    for (int base = blockIdx.x * blockDim.x; base < N; base += gridDim.x * blockDim.x) {
+    for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
         int v = base + threadIdx.x;
         bool act = false, list = false;
         int len = 0;
@@ -608,13 +624,13 @@ __device__ __forceinline__ void worklist_body(const DevGraph& g, int32_t* wl0, i
     }
     long long tot = block_sum_i64<BS>(deficit);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)&ctr->deficit_sum, (unsigned long long)tot);
-    if (blockIdx.x == 0 && threadIdx.x == 0) add_bytes(g, KC_WL, 16ull * (unsigned long long)N);
+    if (P.bid == 0 && threadIdx.x == 0) add_bytes(g, KC_WL, 16ull * (unsigned long long)N);
 }
 
 __global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0, int32_t* wl1,
                                                         int32_t* wl2, DevCounters* ctr,
                                                         int topology, int sign) {
-    worklist_body<256>(g, wl0, wl1, wl2, ctr, topology, sign);
+    worklist_body<256>(hw_par(), g, wl0, wl1, wl2, ctr, topology, sign);
 }
 
 // ---- push-relabel (Algorithm 2) --------------------------------------------
@@ -694,49 +710,45 @@ __device__ __forceinline__ void scan_group(const DevGraph& g, int b, int end, un
 
 constexpr int PR_UNROLL = 4;
 
+// Per-vertex bodies of Algorithm 2; each returns the algorithmic bytes it
+// moved.  Thread: one lane owns u.  Wave: u is wave-uniform.  Block: u is
+// block-uniform and the whole block scans its row.
 template <bool PULL>
-__global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl, int count, int kc,
-                                                   DevCounters* ctr) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long bytes = 0;
-    if (i < count) {
-        const int N = g.n;
-        int u = wl[i];
-        int beg = g.row_ptr[u];
-        int end = beg + g.row_len[u];
-        int hu = g.h[u];
-        bytes += 16;
-        for (int c = 0; c < kc && hu < N; ++c) {
-            int64_t eu = amount<PULL>(g, u);
-            if (eu <= 0) continue;
-            unsigned long long best = ~0ull;
-            for (int b = beg; b < end; b += PR_UNROLL) scan_group<PULL, PR_UNROLL, 1>(g, b, end, best);
-            bytes += 12ull * (unsigned long long)(end - beg);
-            if (best == ~0ull) { hu = N; g.h[u] = N; break; }
-            int bh = (int)(best >> 32);
-            int bj = (int)(unsigned)best;
-            if (hu > bh) {
-                do_push<PULL>(g, u, bj, eu);
-                bytes += 48;
-            } else {
-                hu = bh + 1 < N ? bh + 1 : N;
-                g.h[u] = hu;
-                bytes += 4;
-            }
+__device__ __forceinline__ unsigned long long pr_thread_item(DevGraph& g, int u, int kc) {
+    const int N = g.n;
+    int beg = g.row_ptr[u];
+    int end = beg + g.row_len[u];
+    int hu = g.h[u];
+    unsigned long long bytes = 16;
+    for (int c = 0; c < kc && hu < N; ++c) {
+        int64_t eu = amount<PULL>(g, u);
+        if (eu <= 0) continue;
+        unsigned long long best = ~0ull;
+        for (int b = beg; b < end; b += PR_UNROLL) scan_group<PULL, PR_UNROLL, 1>(g, b, end, best);
+        bytes += 12ull * (unsigned long long)(end - beg);
+        if (best == ~0ull) {
+            hu = N;
+            g.h[u] = N;
+            break;
+        }
+        int bh = (int)(best >> 32);
+        int bj = (int)(unsigned)best;
+        if (hu > bh) {
+            do_push<PULL>(g, u, bj, eu);
+            bytes += 48;
+        } else {
+            hu = bh + 1 < N ? bh + 1 : N;
+            g.h[u] = hu;
+            bytes += 4;
         }
     }
-    unsigned long long b = wave_sum_u64(bytes);
-    if (lane_id() == 0) add_bytes(g, KC_PR, b);
+    return bytes;
 }
 
 template <bool PULL>
-__global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, int count, int kc,
-                                                 DevCounters* ctr) {
-    int w = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    if (w >= count) return;  // whole wave
+__device__ __forceinline__ unsigned long long pr_wave_item(DevGraph& g, int u, int kc) {
     const int N = g.n;
-    int lane = lane_id();
-    int u = bcast(wl[w]);
+    const int lane = lane_id();
     int beg = bcast(g.row_ptr[u]);
     int end = beg + bcast(g.row_len[u]);
     int hu = bcast(g.h[u]);
@@ -765,20 +777,16 @@ __global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, 
             bytes += 4;
         }
     }
-    if (lane == 0) add_bytes(g, KC_PR, bytes);
+    return bytes;
 }
 
-template <bool PULL>
-__global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t* wl, int count,
-                                                       int kc, DevCounters* ctr) {
-    __shared__ unsigned long long part[BLOCK_PR / WAVE];
+template <bool PULL, int BS>
+__device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, int kc) {
+    __shared__ unsigned long long part[BS / WAVE];
     __shared__ int64_t e_sh;
-    int b_id = blockIdx.x;
-    if (b_id >= count) return;
     const int N = g.n;
-    int lane = lane_id();
-    int wv = threadIdx.x / WAVE;
-    int u = wl[b_id];
+    const int lane = lane_id();
+    const int wv = threadIdx.x / WAVE;
     int beg = g.row_ptr[u];
     int end = beg + g.row_len[u];
     int hu = g.h[u];
@@ -790,12 +798,12 @@ __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t
         __syncthreads();
         if (eu <= 0) continue;
         unsigned long long best = ~0ull;
-        for (int b = beg; b < end; b += PR_UNROLL * BLOCK_PR)
-            scan_group<PULL, PR_UNROLL, BLOCK_PR>(g, b + threadIdx.x, end, best);
+        for (int b = beg; b < end; b += PR_UNROLL * BS)
+            scan_group<PULL, PR_UNROLL, BS>(g, b + threadIdx.x, end, best);
         best = wave_min_u64(best);
         if (lane == 0) part[wv] = best;
         __syncthreads();
-        unsigned long long x = lane < BLOCK_PR / WAVE ? part[lane] : ~0ull;
+        unsigned long long x = lane < BS / WAVE ? part[lane] : ~0ull;
         best = wave_min_u64(x);  // every wave computes the same block minimum
         __syncthreads();
         bytes += 12ull * (unsigned long long)(end - beg);
@@ -815,6 +823,38 @@ __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t
             bytes += 4;
         }
     }
+    __syncthreads();  // part / e_sh are reused by the next item
+    return bytes;
+}
+
+template <bool PULL>
+__global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl, int count, int kc,
+                                                   DevCounters* ctr) {
+    (void)ctr;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long bytes = i < count ? pr_thread_item<PULL>(g, wl[i], kc) : 0ull;
+    if (g.count_bytes) {
+        unsigned long long b = wave_sum_u64(bytes);
+        if (lane_id() == 0) add_bytes(g, KC_PR, b);
+    }
+}
+
+template <bool PULL>
+__global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, int count, int kc,
+                                                 DevCounters* ctr) {
+    (void)ctr;
+    int w = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (w >= count) return;  // whole wave
+    unsigned long long bytes = pr_wave_item<PULL>(g, bcast(wl[w]), kc);
+    if (lane_id() == 0) add_bytes(g, KC_PR, bytes);
+}
+
+template <bool PULL>
+__global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t* wl, int count,
+                                                       int kc, DevCounters* ctr) {
+    (void)ctr;
+    if ((int)blockIdx.x >= count) return;
+    unsigned long long bytes = pr_block_item<PULL, BLOCK_PR>(g, wl[blockIdx.x], kc);
     if (threadIdx.x == 0) add_bytes(g, KC_PR, bytes);
 }
 
@@ -823,41 +863,54 @@ __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t
 // Every residual slot u->v with h(u) > h(v) + 1 is saturated: its whole
 // residual moves to v regardless of e(u), so e(u) may turn negative.
 
+// Slots sub, sub + GROUP, ... of u's row; returns the amount that left u
+// (the caller subtracts it from e(u)) and adds its bytes to *bytes.
+template <int GROUP>
+__device__ __forceinline__ long long rie_item(DevGraph& g, int u, int sub, unsigned long long* bytes) {
+    int beg = g.row_ptr[u];
+    int end = beg + g.row_len[u];
+    int hu = g.h[u];
+    long long moved = 0;
+    for (int j = beg + sub; j < end; j += GROUP) {
+        if (ld_res(g.cr, j) > 0) {
+            int v = g.cr[j].x;
+            if (hu > g.h[v] + 1) {
+                int32_t x = xchg_res(g.cr, j, 0);
+                if (x > 0) {
+                    add_res(g.cr, g.rev[j], x);
+                    add_e(g.e, v, x);
+                    moved += x;
+                    *bytes += 32;
+                }
+            }
+        }
+    }
+    if (sub == 0) *bytes += 16 + 12ull * (unsigned long long)(end - beg);
+    return moved;
+}
+
 __global__ void __launch_bounds__(256) k_rie_thread(DevGraph g, const int32_t* wl, int count,
                                                     DevCounters* ctr) {
+    (void)ctr;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long bytes = 0;
     if (i < count) {
         int u = wl[i];
-        int beg = g.row_ptr[u];
-        int end = beg + g.row_len[u];
-        int hu = g.h[u];
-        int64_t moved = 0;
-        for (int j = beg; j < end; ++j) {
-            if (ld_res(g.cr, j) > 0) {
-                int v = g.cr[j].x;
-                if (hu > g.h[v] + 1) {
-                    int32_t x = xchg_res(g.cr, j, 0);
-                    if (x > 0) {
-                        add_res(g.cr, g.rev[j], x);
-                        add_e(g.e, v, x);
-                        moved += x;
-                        bytes += 32;
-                    }
-                }
-            }
-        }
+        long long moved = rie_item<1>(g, u, 0, &bytes);
         if (moved) add_e(g.e, u, -moved);
-        bytes += 16 + 12ull * (unsigned long long)(end - beg);
     }
-    unsigned long long b = wave_sum_u64(bytes);
-    if (lane_id() == 0) add_bytes(g, KC_RIE, b);
+    if (g.count_bytes) {
+        unsigned long long b = wave_sum_u64(bytes);
+        if (lane_id() == 0) add_bytes(g, KC_RIE, b);
+    }
 }
 
+// GROUP = 64: one wave per vertex; GROUP = 256: one block per vertex.  One
+// atomic on e(u) per wave.
 template <int GROUP>
 __global__ void __launch_bounds__(256) k_rie_group(DevGraph g, const int32_t* wl, int count,
                                                    DevCounters* ctr) {
-    // GROUP = 64: one wave per vertex; GROUP = 256: one block per vertex
+    (void)ctr;
     int item = (blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
     int sub = threadIdx.x % GROUP;
     unsigned long long bytes = 0;
@@ -865,30 +918,14 @@ __global__ void __launch_bounds__(256) k_rie_group(DevGraph g, const int32_t* wl
     int u = -1;
     if (item < count) {
         u = wl[item];
-        int beg = g.row_ptr[u];
-        int end = beg + g.row_len[u];
-        int hu = g.h[u];
-        for (int j = beg + sub; j < end; j += GROUP) {
-            if (ld_res(g.cr, j) > 0) {
-                int v = g.cr[j].x;
-                if (hu > g.h[v] + 1) {
-                    int32_t x = xchg_res(g.cr, j, 0);
-                    if (x > 0) {
-                        add_res(g.cr, g.rev[j], x);
-                        add_e(g.e, v, x);
-                        moved += x;
-                        bytes += 32;
-                    }
-                }
-            }
-        }
-        if (sub == 0) bytes += 16 + 12ull * (unsigned long long)(end - beg);
+        moved = rie_item<GROUP>(g, u, sub, &bytes);
     }
-    // one atomic on e(u) per wave
     moved = wave_sum_i64(moved);
     if (lane_id() == 0 && moved && u >= 0) add_e(g.e, u, -moved);
-    unsigned long long b = wave_sum_u64(bytes);
-    if (lane_id() == 0) add_bytes(g, KC_RIE, b);
+    if (g.count_bytes) {
+        unsigned long long b = wave_sum_u64(bytes);
+        if (lane_id() == 0) add_bytes(g, KC_RIE, b);
+    }
 }
 
 // ---- batch of updates (Algorithm 5, first loops) ---------------------------
@@ -902,16 +939,14 @@ __device__ __forceinline__ unsigned long long pair_hash(unsigned long long k) {
     return k;
 }
 
-// Locate the slot of every update (u,v): binary search over the sorted part
+// Locate the slot of update i = (u,v): binary search over the sorted part
 // of row u, then a scan of its inserted tail.  Present: slot_of = j and the
 // update index competes for win[j] (largest index = last update wins).
 // Absent: the unordered pair goes into a hash table; the first thread to
 // claim an entry reserves one slack slot in each of the two rows.
-__global__ void __launch_bounds__(256) k_batch_locate(DevGraph g, const mf_update* upd, int64_t k,
-                                                      int32_t* slot_of, int32_t* win, BatchTable tb,
-                                                      int32_t* need, DevCounters* ctr) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= k) return;
+__device__ __forceinline__ void batch_locate_one(const DevGraph& g, const mf_update* upd, int i,
+                                                 int32_t* slot_of, int32_t* win, const BatchTable& tb,
+                                                 int32_t* need, DevCounters* ctr) {
     mf_update up = upd[i];
     const int N = g.n;
     if (up.u < 0 || up.u >= N || up.v < 0 || up.v >= N || up.u == up.v || up.cap < 0) {
@@ -936,7 +971,7 @@ __global__ void __launch_bounds__(256) k_batch_locate(DevGraph g, const mf_updat
     }
     if (j >= 0) {
         slot_of[i] = j;
-        atomicMax(&win[j], (int)i);
+        atomicMax(&win[j], i);
         return;
     }
     int a = min(up.u, up.v), b = max(up.u, up.v);
@@ -960,7 +995,7 @@ __global__ void __launch_bounds__(256) k_batch_locate(DevGraph g, const mf_updat
         idx = (idx + 1) & mask;
     }
     slot_of[i] = -(int)(idx + 1);
-    atomicMax(&tb.win[2 * idx + (up.u == a ? 0 : 1)], (int)i);
+    atomicMax(&tb.win[2 * idx + (up.u == a ? 0 : 1)], i);
 }
 
 __device__ __forceinline__ int winning_cap(const mf_update* upd, int32_t w, int32_t current) {
@@ -969,16 +1004,14 @@ __device__ __forceinline__ int winning_cap(const mf_update* upd, int32_t w, int3
 
 // Capacity-range check of every pair a winner touches: c(u,v) + c(v,u) must
 // stay within int32 (residuals of the pair sum to it).
-__global__ void __launch_bounds__(256) k_batch_check(DevGraph g, const mf_update* upd, int64_t k,
-                                                     const int32_t* slot_of, const int32_t* win,
-                                                     BatchTable tb, DevCounters* ctr) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= k) return;
+__device__ __forceinline__ void batch_check_one(const DevGraph& g, const mf_update* upd, int i,
+                                                const int32_t* slot_of, const int32_t* win,
+                                                const BatchTable& tb, DevCounters* ctr) {
     int sl = slot_of[i];
     if (sl == INT_MIN) return;
     long long c1, c2;
     if (sl >= 0) {
-        if (win[sl] != (int)i) return;
+        if (win[sl] != i) return;
         int r = g.rev[sl];
         c1 = upd[i].cap;
         c2 = winning_cap(upd, win[r], g.cap[r]);
@@ -990,11 +1023,9 @@ __global__ void __launch_bounds__(256) k_batch_check(DevGraph g, const mf_update
     if (c1 + c2 > (long long)INT_MAX) atomicOr(&ctr->cap_overflow, 1);
 }
 
-// Write both slots of every new pair (capacity 0, residual 0, paired by rev)
+// Write both slots of new pair `idx` (capacity 0, residual 0, paired by rev)
 // and extend the two rows.
-__global__ void __launch_bounds__(256) k_batch_insert(DevGraph g, BatchTable tb) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= tb.capacity) return;
+__device__ __forceinline__ void batch_insert_one(const DevGraph& g, const BatchTable& tb, int idx) {
     unsigned long long key = tb.key[idx];
     if (key == EMPTY_KEY) return;
     int a = (int)(key >> 32), b = (int)(key & 0xFFFFFFFFu);
@@ -1012,19 +1043,17 @@ __global__ void __launch_bounds__(256) k_batch_insert(DevGraph g, BatchTable tb)
 }
 
 // c_f(u,v) += c' - c (Algorithm 5, first loop), by the winning update only.
-__global__ void __launch_bounds__(256) k_batch_apply(DevGraph g, const mf_update* upd, int64_t k,
-                                                     const int32_t* slot_of, const int32_t* win,
-                                                     BatchTable tb, int32_t* touched) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= k) return;
+__device__ __forceinline__ void batch_apply_one(const DevGraph& g, const mf_update* upd, int i,
+                                                const int32_t* slot_of, const int32_t* win,
+                                                const BatchTable& tb, int32_t* touched) {
     int sl = slot_of[i];
     int j = -1;
     if (sl >= 0) {
-        if (win[sl] == (int)i) j = sl;
+        if (win[sl] == i) j = sl;
     } else {
         int idx = -sl - 1;
         int dir = upd[i].u < upd[i].v ? 0 : 1;
-        if (tb.win[2 * idx + dir] == (int)i) j = tb.slot[2 * idx + dir];
+        if (tb.win[2 * idx + dir] == i) j = tb.slot[2 * idx + dir];
     }
     touched[i] = j;
     if (j < 0) return;
@@ -1043,10 +1072,8 @@ __global__ void __launch_bounds__(256) k_batch_apply(DevGraph g, const mf_update
 // falls by the same amount (the excess recomputation of Algorithm 5, kept
 // incrementally).  Of a pair's two slots at most one can be negative, since
 // their residuals sum to c(u,v) + c(v,u) >= 0.
-__global__ void __launch_bounds__(256) k_batch_clamp(DevGraph g, const mf_update* upd, int64_t k,
-                                                     const int32_t* touched) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= k) return;
+__device__ __forceinline__ void batch_clamp_one(const DevGraph& g, const mf_update* upd, int i,
+                                                const int32_t* touched) {
     int j = touched[i];
     if (j < 0) return;
     int32_t r = ld_res(g.cr, j);
@@ -1060,10 +1087,9 @@ __global__ void __launch_bounds__(256) k_batch_clamp(DevGraph g, const mf_update
 }
 
 // Scratch back to its idle state: win[] = -1, table empty, need[] = 0.
-__global__ void __launch_bounds__(256) k_batch_cleanup(BatchTable tb, int32_t* need,
-                                                       const int32_t* slot_of, int32_t* win,
-                                                       int64_t k) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void batch_cleanup_one(const BatchTable& tb, int32_t* need,
+                                                  const int32_t* slot_of, int32_t* win, int64_t i,
+                                                  int64_t k) {
     if (i < k) {
         int sl = slot_of[i];
         if (sl >= 0) win[sl] = -1;
@@ -1078,6 +1104,226 @@ __global__ void __launch_bounds__(256) k_batch_cleanup(BatchTable tb, int32_t* n
         tb.win[2 * i] = -1;
         tb.win[2 * i + 1] = -1;
     }
+}
+
+__global__ void __launch_bounds__(256) k_batch_locate(DevGraph g, const mf_update* upd, int64_t k,
+                                                      int32_t* slot_of, int32_t* win, BatchTable tb,
+                                                      int32_t* need, DevCounters* ctr) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < k) batch_locate_one(g, upd, (int)i, slot_of, win, tb, need, ctr);
+}
+
+__global__ void __launch_bounds__(256) k_batch_check(DevGraph g, const mf_update* upd, int64_t k,
+                                                     const int32_t* slot_of, const int32_t* win,
+                                                     BatchTable tb, DevCounters* ctr) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < k) batch_check_one(g, upd, (int)i, slot_of, win, tb, ctr);
+}
+
+__global__ void __launch_bounds__(256) k_batch_insert(DevGraph g, BatchTable tb) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < tb.capacity) batch_insert_one(g, tb, idx);
+}
+
+__global__ void __launch_bounds__(256) k_batch_apply(DevGraph g, const mf_update* upd, int64_t k,
+                                                     const int32_t* slot_of, const int32_t* win,
+                                                     BatchTable tb, int32_t* touched) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < k) batch_apply_one(g, upd, (int)i, slot_of, win, tb, touched);
+}
+
+__global__ void __launch_bounds__(256) k_batch_clamp(DevGraph g, const mf_update* upd, int64_t k,
+                                                     const int32_t* touched) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < k) batch_clamp_one(g, upd, (int)i, touched);
+}
+
+__global__ void __launch_bounds__(256) k_batch_cleanup(BatchTable tb, int32_t* need,
+                                                       const int32_t* slot_of, int32_t* win,
+                                                       int64_t k) {
+    batch_cleanup_one(tb, need, slot_of, win, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, k);
+}
+
+// ---- batched solve: one block per graph ---------------------------------------
+
+constexpr int BATCH_BLOCK = 512;
+
+// The whole loop of Algorithms 1 and 5 for one graph inside one block: the
+// same level, worklist, push-relabel and remove-invalid-edges bodies as the
+// single-graph kernels, with block barriers where those have launch
+// boundaries (a workgroup barrier orders this block's global memory).
+template <int BS>
+__device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
+    __shared__ int s_cnt[4];
+    __shared__ long long s_val;
+    const Par P{0, 1};
+    DevGraph g = S.g;
+    DevCounters* ctr = S.ctr;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int N = g.n;
+    if (mode == 0) {
+        // Algorithm 1's initialisation: zero flow, then saturate s
+        int sb = g.row_ptr[0], se = g.row_ptr[N];
+        for (int j = sb + tid; j < se; j += BS) g.cr[j].y = g.cap[j];
+        for (int v = tid; v < N; v += BS) {
+            g.e[v] = 0;
+            g.h[v] = 0;
+        }
+        __syncthreads();
+    }
+    if (mode == 0 || mode == 1) {
+        int beg = g.row_ptr[g.s], len = g.row_len[g.s];
+        long long sent = 0;
+        for (int q = tid; q < len; q += BS) {
+            int j = beg + q;
+            int32_t x = g.cr[j].y;
+            if (x > 0) {
+                g.cr[j].y = 0;
+                add_res(g.cr, g.rev[j], x);
+                add_e(g.e, g.cr[j].x, x);
+                sent += x;
+            }
+        }
+        long long tot = block_sum_i64<BS>(sent);
+        if (tid == 0 && tot) add_e(g.e, g.s, -tot);
+        __syncthreads();
+    }
+    bool sweep = mode == 1 && S.warm;  // one push-relabel sweep on the previous heights
+    int iters = 0;
+    int status = 0;
+    for (;;) {
+        if (!sweep) {
+            // global relabel (Algorithm 6), then the worklist and value
+            if (tid < 3) {
+                ctr->front[tid] = 0;
+                ctr->unv[tid] = 0;
+            }
+            if (tid < 4) ctr->wl[tid] = 0;
+            if (tid == 0) {
+                ctr->deficit_sum = 0;
+                ctr->e_t = 0;
+            }
+            for (int i = tid; i < 4 * S.bits.nwords; i += BS) S.bits.visited[i] = 0u;
+            __syncthreads();
+            gr_init_body(P, g, S.q0, ctr, S.bits, 1);
+            __syncthreads();
+            for (int lv = 0; lv <= N; ++lv) {
+                int cnt = gr_level_step<false, BS>(P, g, lv, (lv & 1) ? S.q1 : S.q0, (lv & 1) ? S.q0 : S.q1,
+                                                   ctr, S.bits, tune, nullptr);
+                __syncthreads();
+                if (cnt == 0) break;
+            }
+        } else {
+            if (tid < 4) ctr->wl[tid] = 0;
+            if (tid == 0) {
+                ctr->deficit_sum = 0;
+                ctr->e_t = 0;
+            }
+            __syncthreads();
+        }
+        worklist_body<BS>(P, g, S.wl0, S.wl1, S.wl2, ctr, 0, 1);
+        __syncthreads();
+        if (tid == 0) {
+            for (int b = 0; b < 4; ++b) s_cnt[b] = ctr->wl[b];
+            s_val = ctr->e_t + ctr->deficit_sum;
+        }
+        __syncthreads();
+        const int c0 = s_cnt[0], c1 = s_cnt[1], c2 = s_cnt[2], active = s_cnt[3];
+        if (!sweep) {
+            if (active == 0) break;
+            if (++iters > S.max_iter) {
+                status = MF_ERR_NOT_CONVERGED;
+                break;
+            }
+        }
+        sweep = false;
+        // push-relabel (Algorithm 2) over the three degree bins
+        for (int i = tid; i < c0; i += BS) pr_thread_item<false>(g, S.wl0[i], S.kc);
+        for (int i = tid / WAVE; i < c1; i += BS / WAVE) pr_wave_item<false>(g, bcast(S.wl1[i]), S.kc);
+        for (int i = 0; i < c2; ++i) pr_block_item<false, BS>(g, S.wl2[i], S.kc);
+        __syncthreads();
+        // remove invalid edges (Algorithm 3)
+        unsigned long long nb = 0;
+        for (int i = tid; i < c0; i += BS) {
+            int u = S.wl0[i];
+            long long moved = rie_item<1>(g, u, 0, &nb);
+            if (moved) add_e(g.e, u, -moved);
+        }
+        for (int i = tid / WAVE; i < c1; i += BS / WAVE) {
+            int u = bcast(S.wl1[i]);
+            long long moved = wave_sum_i64(rie_item<WAVE>(g, u, lane, &nb));
+            if (lane == 0 && moved) add_e(g.e, u, -moved);
+        }
+        for (int i = 0; i < c2; ++i) {
+            int u = S.wl2[i];
+            long long moved = wave_sum_i64(rie_item<BS>(g, u, tid, &nb));
+            if (lane == 0 && moved) add_e(g.e, u, -moved);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        S.value = s_val;
+        S.status = status;
+        S.iterations = iters;
+    }
+}
+
+template <int BS>
+__global__ void __launch_bounds__(BS) k_batch_solve(GraphSlot* slots, const int32_t* order, int mode,
+                                                    GrTune tune) {
+    solve_graph<BS>(slots[order[blockIdx.x]], mode, tune);
+}
+
+// Batched repair, step 1 (one block per graph): validate and locate the
+// graph's updates, then check the capacity range of the winners.
+template <int BS>
+__global__ void __launch_bounds__(BS) k_batch_locate_multi(GraphSlot* slots, GraphUpdates* gu) {
+    GraphSlot& S = slots[blockIdx.x];
+    const GraphUpdates U = gu[blockIdx.x];
+    if (threadIdx.x == 0) {
+        S.ctr->err = 0;
+        S.ctr->overflow = 0;
+        S.ctr->new_pairs = 0;
+        S.ctr->cap_overflow = 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < U.k; i += BS)
+        batch_locate_one(S.g, U.upd, i, U.slot_of, U.win, U.tb, U.need, S.ctr);
+    __syncthreads();
+    for (int i = threadIdx.x; i < U.k; i += BS)
+        batch_check_one(S.g, U.upd, i, U.slot_of, U.win, U.tb, S.ctr);
+}
+
+template <int BS>
+__device__ __forceinline__ void cleanup_graph(const GraphUpdates& U) {
+    int64_t items = U.k > U.tb.capacity ? U.k : U.tb.capacity;
+    for (int64_t i = threadIdx.x; i < items; i += BS) batch_cleanup_one(U.tb, U.need, U.slot_of, U.win, i, U.k);
+}
+
+// Batched repair, step 2 (one block per graph, largest first): the rest of
+// Algorithm 5 for this graph, then its loop.
+template <int BS>
+__global__ void __launch_bounds__(BS) k_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu,
+                                                           const int32_t* order, GrTune tune) {
+    const int gi = order[blockIdx.x];
+    GraphSlot& S = slots[gi];
+    const GraphUpdates U = gu[gi];
+    for (int idx = threadIdx.x; idx < U.tb.capacity; idx += BS) batch_insert_one(S.g, U.tb, idx);
+    __syncthreads();
+    for (int i = threadIdx.x; i < U.k; i += BS) batch_apply_one(S.g, U.upd, i, U.slot_of, U.win, U.tb, U.touched);
+    __syncthreads();
+    for (int i = threadIdx.x; i < U.k; i += BS) batch_clamp_one(S.g, U.upd, i, U.touched);
+    __syncthreads();
+    cleanup_graph<BS>(U);
+    if (threadIdx.x == 0) S.g.used_slots += 2 * (int64_t)S.ctr->new_pairs;
+    __syncthreads();
+    solve_graph<BS>(S, 1, tune);
+}
+
+template <int BS>
+__global__ void __launch_bounds__(BS) k_batch_cleanup_multi(GraphUpdates* gu) {
+    cleanup_graph<BS>(gu[blockIdx.x]);
 }
 
 // ---- cut certificate --------------------------------------------------------
@@ -1364,6 +1610,25 @@ void launch_reduce_bytes(const DevGraph& g, DevCounters* ctr, hipStream_t st) {
 
 void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipStream_t st) {
     k_cut<<<grid_for(g.n, 256, 4096), 256, 0, st>>>(g, side, cut);
+}
+
+void launch_batch_solve(GraphSlot* slots, const int32_t* order, int num, int mode, const GrTune& tune,
+                        hipStream_t st) {
+    if (num <= 0) return;
+    k_batch_solve<BATCH_BLOCK><<<num, BATCH_BLOCK, 0, st>>>(slots, order, mode, tune);
+}
+
+void launch_batch_locate_multi(GraphSlot* slots, GraphUpdates* gu, int num, hipStream_t st) {
+    if (num > 0) k_batch_locate_multi<256><<<num, 256, 0, st>>>(slots, gu);
+}
+
+void launch_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu, const int32_t* order, int num,
+                               const GrTune& tune, hipStream_t st) {
+    if (num > 0) k_batch_repair_multi<BATCH_BLOCK><<<num, BATCH_BLOCK, 0, st>>>(slots, gu, order, tune);
+}
+
+void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st) {
+    if (num > 0) k_batch_cleanup_multi<256><<<num, 256, 0, st>>>(gu);
 }
 
 int device_selftest(hipStream_t st) {

@@ -96,12 +96,44 @@ struct GrTune {
     int lds;        // the bitmap fits in LDS (dynamic shared memory provided at launch)
 };
 
+// One graph of a batched solve: views into the pooled device arrays (slot
+// indices and rev are pool-global, vertex arrays are offset to the graph)
+// plus its own scratch and result.
+struct GraphSlot {
+    DevGraph g;
+    int2* q0;
+    int2* q1;
+    int32_t* wl0;
+    int32_t* wl1;
+    int32_t* wl2;
+    GrBits bits;
+    DevCounters* ctr;
+    int32_t kc;
+    int32_t warm;              // repairs: one sweep on the previous heights first
+    int64_t max_iter;
+    // results of the last launch
+    long long value;
+    int32_t status;            // 0 ok, MF_ERR_NOT_CONVERGED
+    int32_t iterations;
+};
+
 // Batch scratch: hash table of absent pairs, keyed by the unordered pair.
 struct BatchTable {
     unsigned long long* key;   // (lo << 32 | hi), ~0 = empty
     int32_t* win;              // 2 per entry: last update index per direction (lo->hi, hi->lo)
     int32_t* slot;             // 2 per entry: reserved slot in row lo, row hi
     int32_t capacity;          // power of two
+};
+
+// One graph's share of a batched repair: its updates and scratch.
+struct GraphUpdates {
+    const mf_update* upd;
+    int32_t k;
+    int32_t* slot_of;
+    int32_t* touched;
+    int32_t* win;              // pool-global, per slot
+    int32_t* need;             // per vertex of this graph
+    BatchTable tb;
 };
 
 // ---- launch wrappers (kernels.hip) ---------------------------------------
@@ -142,6 +174,18 @@ void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipSt
 void launch_flow_slots(const DevGraph& g, int32_t* flow_slot, unsigned long long* count,
                        hipStream_t st);
 int device_selftest(hipStream_t st);
+// Batched solve: one block per graph, graphs taken in `order`; mode 0 solves
+// from zero flow (Algorithm 1), mode 1 resumes after applied updates
+// (Algorithm 5's loop).
+void launch_batch_solve(GraphSlot* slots, const int32_t* order, int num, int mode, const GrTune& tune,
+                        hipStream_t st);
+// Batched repair, first launch: validate and locate every graph's updates.
+void launch_batch_locate_multi(GraphSlot* slots, GraphUpdates* gu, int num, hipStream_t st);
+// Second launch: insert, apply, clamp, clean up and resume each graph.
+void launch_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu, const int32_t* order, int num,
+                               const GrTune& tune, hipStream_t st);
+// After a failed validation: scratch back to idle for every graph.
+void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st);
 
 // ---- host Bi-CSR builder (bicsr.cpp) -------------------------------------
 struct HostBiCSR {

@@ -326,6 +326,41 @@ def random_batch(g_n: int, k: int, cap_max: int, seed: int, pairs: np.ndarray | 
     return u.astype(np.int32), v.astype(np.int32), c.astype(np.int32)
 
 
+def rmat_n(n: int, edge_factor: int, cap_max: int, seed: int, a=0.57, b=0.19, c=0.19,
+           name: str | None = None) -> Graph:
+    """RMAT graph on exactly n vertices: scale = ceil(log2 n), edge_factor * n
+    generated edges, endpoints >= n redrawn."""
+    rng = rng_for(seed)
+    scale = max(1, int(np.ceil(np.log2(n))))
+    count = edge_factor * n
+    u, v = _rmat_sampler(scale, n, a, b, c)(rng, count)
+    cap = rng.integers(1, cap_max + 1, size=count, dtype=np.int64)
+    keep = u != v
+    u, v, cap = u[keep].astype(np.int32), v[keep].astype(np.int32), cap[keep].astype(np.int32)
+    s, t = _pick_source_sink(n, u, v)
+    return Graph(name or f"rmat_n{n}", n, u, v, cap, s, t,
+                 {"family": "rmat", "scale": scale, "seed": seed, "cap_max": cap_max,
+                  "abc": (a, b, c)})
+
+
+def batched_graphs(count: int, seed: int = 41000, n_lo: float = 1e3, n_hi: float = 1e5,
+                   degree: int = 8, cap_max: int = 100):
+    """Independent graphs for a batched solve: alternately Erdos-Renyi and RMAT,
+    n log-uniform in [n_lo, n_hi], average out-degree `degree`, capacities
+    U[1, cap_max]; graph i uses seed + i.  Erdos-Renyi graphs take s = 0,
+    t = n - 1; RMAT graphs the max out-/in-degree rule."""
+    rng = rng_for(seed)
+    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), size=count)).round().astype(np.int64)
+    graphs = []
+    for i in range(count):
+        n = int(max(4, ns[i]))
+        if i % 2 == 0:
+            graphs.append(erdos_renyi(n, degree * n, cap_max, seed=seed + 1 + i, name=f"er_{i}"))
+        else:
+            graphs.append(rmat_n(n, degree, cap_max, seed=seed + 1 + i, name=f"rmat_{i}"))
+    return graphs
+
+
 # ----------------------------------------------------------------------------
 # named workloads
 # ----------------------------------------------------------------------------

@@ -75,3 +75,20 @@ def test_null_handle_calls():
     assert L.mf_min_cut(None, None, mf.C.byref(v)) == mf.MF_ERR_INVALID
     assert L.mf_get_stats(None, None) == mf.MF_ERR_INVALID
     L.mf_graph_free(None)
+
+
+def test_batch_load_rejects_invalid():
+    L = mf.lib()
+    n = np.array([3, 3], np.int32)
+    off = np.array([0, 1, 2], np.int64)
+    src = np.array([0, 0], np.int32)
+    dst = np.array([1, 1], np.int32)
+    cap = np.array([1, -1], np.int32)  # negative capacity in graph 1
+    s = np.array([0, 0], np.int32)
+    t = np.array([2, 2], np.int32)
+    h = mf.C.c_void_p()
+    rc = L.mf_batch_load(2, n.ctypes.data, off.ctypes.data, src.ctypes.data, dst.ctypes.data,
+                         cap.ctypes.data, s.ctypes.data, t.ctypes.data, None, mf.C.byref(h))
+    assert rc == mf.MF_ERR_INVALID and not h.value
+    assert L.mf_batch_maxflow(None, None) == mf.MF_ERR_INVALID
+    L.mf_batch_free(None)

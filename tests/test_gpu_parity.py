@@ -349,3 +349,58 @@ def test_rmat20_full_size():
             cs, cd, cc = stream.current_edges()
             side, cut = G.min_cut()
             _cut_ok(g.n, g.s, g.t, side, cut, got, cs, cd, cc)
+
+
+# --- batched solve: many graphs in one launch -----------------------------------
+
+def _batch_streams(graphs, seed=42000):
+    streams = []
+    for i, g in enumerate(graphs):
+        st = gen.BatchStream(g, seed + i, inc_max=50, new_cap_max=100)
+        streams.append(st)
+    return streams
+
+
+@pytest.mark.parametrize("warm", [True, False])
+def test_batched_matches_oracle(warm):
+    graphs = gen.batched_graphs(24, seed=77000, n_lo=1e3, n_hi=3e4)
+    streams = _batch_streams(graphs)
+    oracles = [oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t) for g in graphs]
+    want = [o.static() for o in oracles]
+    say("batched static", len(graphs))
+    with mf.MaxFlowBatch(graphs, warm_start=warm) as B:
+        got = B.maxflow()
+        assert got.tolist() == want
+        for rnd in range(2):
+            batches = []
+            for g, st in zip(graphs, streams):
+                k = max(1, int(round(0.01 * st.keys.size)))
+                batches.append(st.next_batch(k))
+            want = [o.apply(*b) for o, b in zip(oracles, batches)]
+            say("batched repair", rnd)
+            assert B.apply(batches).tolist() == want
+
+
+def test_batched_equals_single_graph_calls():
+    graphs = gen.batched_graphs(8, seed=78000, n_lo=500, n_hi=5e3)
+    singles = []
+    for g in graphs:
+        with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+            singles.append(G.maxflow())
+    with mf.MaxFlowBatch(graphs) as B:
+        assert B.maxflow().tolist() == singles
+        it, ms = B.info()
+        assert (it > 0).all() and ms > 0
+
+
+def test_batched_errors_change_nothing():
+    graphs = gen.batched_graphs(4, seed=79000, n_lo=200, n_hi=2e3)
+    with mf.MaxFlowBatch(graphs) as B:
+        v0 = B.maxflow().tolist()
+        bad = [(np.array([0]), np.array([1]), np.array([5])) for _ in graphs]
+        bad[2] = (np.array([0]), np.array([graphs[2].n]), np.array([5]))  # out of range
+        with pytest.raises(mf.MFError) as ei:
+            B.apply(bad)
+        assert ei.value.status == mf.MF_ERR_INVALID
+        empty = [(np.zeros(0, np.int32),) * 3 for _ in graphs]
+        assert B.apply(empty).tolist() == v0
