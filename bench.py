@@ -31,11 +31,17 @@ METRIC = ("ms per update batch (incremental vs from-scratch); static edges/s; p9
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
+    "batch512": "512 independent graphs, alternately Erdos-Renyi and RMAT, n log-uniform in "
+                "[1e3,1e5], out-degree 8, caps U[1,100]; one batched static solve, then one batch "
+                "of 1% updates per graph (40/40/20) repaired in one batched launch",
     "rmat20": "RMAT scale 20 (a=.57,b=.19,c=.19), edge factor 16, caps U[1,1000], duplicates "
               "summed; batches of 10,000 updates (40% +U[1,50], 40% to U[0,cap), 20% new U[1,1000])",
     "er2000": "Erdos-Renyi n=2000 m=16000, caps U[1,100]; batches of 200 updates (40/40/20)",
     "grid2048": "2048x2048 4-connected grid, caps U[1,100], source/sink links 1000; batches of "
                 "1,000 updates in random 64x64 patches (40/40/20)",
+    "serve64": "64 resident RMAT graphs, scale uniform in 14..20, edge factor 16, caps U[1,1000]; "
+               "2,000 update batches (size log-uniform 10..10,000, 40/40/20) to uniformly chosen "
+               "graphs with Poisson arrivals; HBM budget 50% of the fleet's footprint",
 }
 
 
@@ -61,11 +67,22 @@ def main():
                          "one sweep on the previous heights")
     ap.add_argument("--profile-all", action="store_true",
                     help="event-time every kernel class (adds event overhead to the steps)")
+    ap.add_argument("--serve-slots", type=int, default=8, help="serve64: concurrent slots")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="serve64: requests per run")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="serve64: offered rate as a fraction of the measured saturation throughput")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each graph or batch "
               "stream runs on one device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    serve_inputs = None
+    if args.workload == "serve64":
+        # generated in worker processes before anything touches the GPU
+        from paper_2511_01235_amd import gen
+        t0 = time.time()
+        serve_inputs = gen.serving_workload(64, args.serve_requests, workers=min(16, os.cpu_count() or 1))
+        log(f"generated serving fleet and {args.serve_requests} requests in {time.time() - t0:.1f}s")
 
     import torch
     import paper_2511_01235_amd as mf
@@ -75,6 +92,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.workload == "batch512":
+        return bench_batched(args, mf, gen, torch, stream)
+    if args.workload == "serve64":
+        return bench_serving(args, mf, serve_inputs)
 
     t0 = time.time()
     g, bstream, k, nb = gen.workload(args.workload)
@@ -160,9 +181,15 @@ def main():
     if cls == "global_relabel" and prof["kernel_launches"]["worklist"] == 0:
         kbytes += prof["kernel_bytes"]["worklist"]  # worklist build fused into the relabel launch
     achieved = (kbytes / (kms * 1e-3)) / 1e9 if kms > 0 else 0.0
+    # HBM bytes per launch from the committed counter summary of this kernel
+    # and workload, while the kernel source is unchanged since it was taken
+    from paper_2511_01235_amd.prof import recorded_traffic
+    traffic = None
+    if cls == "global_relabel" and not args.cold_start and args.relabel_mode == 0:
+        traffic = recorded_traffic(f"k_gr_level_{args.workload}", os.path.join(ROOT, "profiles"))
     roofline = {"bound": "hbm", "kernel_class": cls, "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": None, "launches": launches,
+                "traffic": traffic, "launches": launches,
                 "avg_launch_us": round(kms * 1e3 / launches, 3) if launches else None,
                 "alg_bytes_per_launch": round(kbytes / launches, 1) if launches else None,
                 "share_of_step": round(kms / elapsed_ms, 4) if elapsed_ms > 0 else None}
@@ -199,11 +226,213 @@ def main():
         "static_value": static_val,
         "final_value": values[-1],
         "mean_iterations_per_batch": round(float(np.mean(iters)), 2),
+        "relayouts": prof["relayouts"],
         "updates_per_s": round(k / (ms_per_step * 1e-3), 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(args, mf, gen, torch, stream):
+    """512 graphs: one batched launch per step against one launch sequence per
+    graph (mf_maxflow / mf_apply_batch on each), values required identical."""
+    t0 = time.time()
+    graphs = gen.batched_graphs(512, seed=41000)
+    streams = [gen.BatchStream(g, 42000 + i, inc_max=50, new_cap_max=100) for i, g in enumerate(graphs)]
+    rounds = args.warmup + args.steps
+    batches = [[st.next_batch(max(1, int(round(0.01 * st.keys.size)))) for st in streams]
+               for _ in range(rounds)]
+    log(f"generated 512 graphs (sum n={sum(g.n for g in graphs)}, sum m={sum(g.m for g in graphs)}) "
+        f"and {rounds} update rounds in {time.time() - t0:.1f}s")
+    B = mf.MaxFlowBatch(graphs, stream=stream, device=0, kernel_cycles=args.kc,
+                        warm_start=not args.cold_start)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    static_vals = B.maxflow()
+    torch.cuda.synchronize()
+    static_ms = (time.perf_counter() - a) * 1e3
+    log(f"batched static: {static_ms:.1f} ms")
+    values = []
+    step_ms = []
+    for r in range(rounds):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        values.append(B.apply(batches[r]))
+        torch.cuda.synchronize()
+        if r >= args.warmup:
+            step_ms.append((time.perf_counter() - a) * 1e3)
+    B.close()
+    # the same work one graph at a time
+    single_static_ms, single_step_ms = 0.0, [0.0] * args.steps
+    for i, g in enumerate(graphs):
+        with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0,
+                             kernel_cycles=args.kc, warm_start=not args.cold_start) as G:
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            v = G.maxflow()
+            single_static_ms += (time.perf_counter() - a) * 1e3
+            assert v == static_vals[i], ("static", i, v, static_vals[i])
+            for r in range(rounds):
+                a = time.perf_counter()
+                v = G.apply_batch(*batches[r][i])
+                if r >= args.warmup:
+                    single_step_ms[r - args.warmup] += (time.perf_counter() - a) * 1e3
+                assert v == values[r][i], ("repair", r, i, v, values[r][i])
+    ms_per_step = float(np.mean(step_ms))
+    per_inst = float(np.mean(single_step_ms))
+    log(f"batched repair {ms_per_step:.1f} ms vs per-graph calls {per_inst:.1f} ms; static "
+        f"{static_ms:.1f} vs {single_static_ms:.1f} ms")
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_batched(graphs, batches[0], static_vals, values[0], args.cpu_budget_s)
+    out = {
+        "metric": METRIC, "value": round(ms_per_step, 3), "unit": "ms/batch", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "int32/int64",
+        "data": "synthetic",
+        "config": {"workload": f"batch512: {WORKLOADS['batch512']}", "graphs": 512,
+                   "sum_n": int(sum(g.n for g in graphs)), "sum_m": int(sum(g.m for g in graphs))},
+        "batched_repair_ms": round(ms_per_step, 3),
+        "per_instance_repair_ms": round(per_inst, 3),
+        "batched_speedup_repair": round(per_inst / ms_per_step, 3),
+        "batched_static_ms": round(static_ms, 3),
+        "per_instance_static_ms": round(single_static_ms, 3),
+        "batched_speedup_static": round(single_static_ms / static_ms, 3),
+        "graphs_per_s_static": round(512 / (static_ms * 1e-3), 1),
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args, mf, inputs):
+    """Serving loop over 64 graphs: saturation throughput one slot at a time
+    (per-instance calls) and with overlapping slots, then the Poisson trace at a
+    fraction of that throughput under an HBM budget of half the fleet's
+    footprint.  Every run starts from freshly loaded graphs and must return
+    the same value for every request."""
+    from paper_2511_01235_amd.serve import Server, estimate_device_bytes
+    graphs, reqs = inputs
+    footprint = sum(estimate_device_bytes(g.n, g.m) for g in graphs)
+    unlimited = 4 * footprint
+
+    def run(slots, budget, arrivals, label):
+        trace = [(gi, float(a), u, v, c) for (gi, _, u, v, c), a in zip(reqs, arrivals)]
+        with Server(graphs, budget, slots=slots, device=0) as srv:
+            t0 = time.time()
+            loaded = srv.preload(threads=16)
+            log(f"{label}: preloaded {loaded} graphs in {time.time() - t0:.1f}s")
+            res = srv.run(trace)
+            vals = [r.value for r in srv.requests]
+        log(f"{label}: " + json.dumps({k: (round(x, 3) if isinstance(x, float) else x) for k, x in res.items()}))
+        return res, vals
+
+    zero = np.zeros(len(reqs))
+    seq, v_seq = run(1, unlimited, zero, "saturation, 1 slot")
+    sat, v_sat = run(args.serve_slots, unlimited, zero, f"saturation, {args.serve_slots} slots")
+    assert v_sat == v_seq, "values differ between one slot and overlapping slots"
+    rate = args.serve_load * sat["batches_per_s"]
+    gaps = np.array([r[1] for r in reqs])
+    arrivals = np.cumsum(gaps) / rate
+    pois, v_pois = run(args.serve_slots, footprint // 2, arrivals, f"poisson {rate:.0f}/s, budget 50%")
+    assert v_pois == v_seq, "values differ under the HBM budget"
+    poisu, v_poisu = run(args.serve_slots, unlimited, arrivals, f"poisson {rate:.0f}/s, unlimited budget")
+    assert v_poisu == v_seq
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_serving(graphs, reqs, v_seq, args.cpu_budget_s)
+    out = {
+        "metric": METRIC, "value": round(pois["p99_ms"], 3), "unit": "ms p99 latency", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0, "ms_per_step": round(1e3 / pois["batches_per_s"], 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "int32/int64",
+        "data": "synthetic",
+        "config": {"workload": f"serve64: {WORKLOADS['serve64']}", "graphs": len(graphs),
+                   "sum_n": int(sum(g.n for g in graphs)), "sum_m": int(sum(g.m for g in graphs)),
+                   "slots": args.serve_slots, "offered_rate_per_s": round(rate, 1),
+                   "hbm_budget_bytes": int(footprint // 2), "fleet_footprint_bytes": int(footprint)},
+        "p50_ms": round(pois["p50_ms"], 3), "p99_ms": round(pois["p99_ms"], 3),
+        "batches_per_s": round(pois["batches_per_s"], 1), "evictions": pois["evictions"],
+        "loads": pois["loads"], "unlimited_budget_p50_ms": round(poisu["p50_ms"], 3),
+        "unlimited_budget_p99_ms": round(poisu["p99_ms"], 3),
+        "saturation_batches_per_s_one_slot": round(seq["batches_per_s"], 1),
+        "saturation_batches_per_s_slots": round(sat["batches_per_s"], 1),
+        "overlap_speedup": round(sat["batches_per_s"] / seq["batches_per_s"], 3),
+        "results_identical_across_runs": True,
+        "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_serving(graphs, reqs, gpu_vals, budget_s):
+    """The oracle replays the trace one request at a time (1 core), on the
+    requests of the smallest graphs until the budget is spent; its values are
+    checked against the GPU's."""
+    import oracle
+    order = sorted(range(len(graphs)), key=lambda i: graphs[i].m)
+    spent, done, static_s = 0.0, 0, 0.0
+    for gi in order:
+        g = graphs[gi]
+        mine = [j for j, r in enumerate(reqs) if r[0] == gi]
+        if not mine:
+            continue
+        o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+        a = time.perf_counter()
+        o.static()
+        static_s += time.perf_counter() - a
+        for j in mine:
+            a = time.perf_counter()
+            v = o.apply(*reqs[j][2:])
+            spent += time.perf_counter() - a
+            assert v == gpu_vals[j], ("serving", j, v, gpu_vals[j])
+            done += 1
+        o.close()
+        if spent + static_s > budget_s:
+            break
+    log(f"cpu oracle: {done} requests in {spent:.2f}s (+{static_s:.2f}s static solves)")
+    return {"value": round(done / spent, 2) if spent > 0 else None, "unit": "batches/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"sequential repair of the {done} requests addressed to the smallest graphs of the "
+                      f"fleet, in trace order (values checked equal to the GPU's), after their static solves"}
+
+
+def cpu_baseline_batched(graphs, batches, static_vals, rep_vals, budget_s):
+    """The oracle on the host cores, one graph per worker thread (the ctypes
+    calls release the GIL), static solve then the first update batch, until the
+    budget is spent; values checked against the GPU's."""
+    import concurrent.futures as cf
+    import oracle
+    cores = max(1, min(16, os.cpu_count() or 1))
+    done = []
+
+    def one(i):
+        g = graphs[i]
+        o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+        a = time.perf_counter()
+        v = o.static()
+        v2 = o.apply(*batches[i])
+        dt = time.perf_counter() - a
+        o.close()
+        if v != static_vals[i] or v2 != rep_vals[i]:
+            raise SystemExit(f"oracle mismatch on graph {i}")
+        return dt
+
+    a = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        futs = []
+        for i in range(len(graphs)):
+            futs.append(ex.submit(one, i))
+        for f in futs:
+            if time.perf_counter() - a > budget_s and done:
+                f.cancel()
+                continue
+            done.append(f.result())
+    wall = time.perf_counter() - a
+    n = len(done)
+    return {"value": round(wall * 1e3 * len(graphs) / n, 1), "unit": "ms/(static+1 batch, 512 graphs)",
+            "cores": cores, "kind": "oracle",
+            "sample": f"static solve and first repair of {n} of the 512 graphs on {cores} threads in "
+                      f"{wall:.1f} s, scaled to 512 graphs (values checked equal to the GPU's)"}
 
 
 def cpu_baseline(g, batches_np, static_val, gpu_values, budget_s):

@@ -172,6 +172,13 @@ mf_status mf_min_cut(mf_graph* g, uint8_t* source_side, int64_t* cut_capacity);
  * Errors: MF_ERR_INVALID, MF_ERR_STATE, MF_ERR_NOT_CONVERGED, MF_ERR_DEVICE. */
 mf_status mf_get_flow(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, int32_t* flow);
 
+/* The current capacities: one entry per directed pair with capacity > 0,
+ * sorted by (u, v) (the graph as mf_graph_load would take it back).  With all
+ * three arrays NULL only *count is written; otherwise *count holds the
+ * arrays' length on input (MF_ERR_INVALID if too short) and receives the
+ * number written.  Does not change the solver state. */
+mf_status mf_get_edges(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, int32_t* cap);
+
 /* Counters and sizes; see mf_stats. */
 mf_status mf_get_stats(const mf_graph* g, mf_stats* out);
 

@@ -30,7 +30,7 @@ MF_ERR_STATE = 6
 
 # every symbol include/mf.h declares
 EXPORTED = ["mf_default_options", "mf_status_string", "mf_graph_load", "mf_maxflow",
-            "mf_apply_batch", "mf_apply_batch_device", "mf_min_cut", "mf_get_flow",
+            "mf_apply_batch", "mf_apply_batch_device", "mf_min_cut", "mf_get_flow", "mf_get_edges",
             "mf_get_stats", "mf_profile", "mf_debug_initial_labels", "mf_debug_selftest",
             "mf_graph_free", "mf_batch_load", "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info",
             "mf_batch_free"]
@@ -88,6 +88,7 @@ def lib():
         L.mf_apply_batch_device.argtypes = [vp, vp, i64, C.POINTER(i64)]
         L.mf_min_cut.argtypes = [vp, vp, C.POINTER(i64)]
         L.mf_get_flow.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
+        L.mf_get_edges.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
         L.mf_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.mf_profile.argtypes = [vp, i32]
         L.mf_debug_initial_labels.argtypes = [vp, vp, vp, vp, C.POINTER(i32)]
@@ -101,7 +102,7 @@ def lib():
         L.mf_batch_free.argtypes = [vp]
         L.mf_batch_free.restype = None
         for name in ["mf_graph_load", "mf_maxflow", "mf_apply_batch", "mf_apply_batch_device",
-                     "mf_min_cut", "mf_get_flow", "mf_get_stats", "mf_profile",
+                     "mf_min_cut", "mf_get_flow", "mf_get_edges", "mf_get_stats", "mf_profile",
                      "mf_debug_initial_labels", "mf_debug_selftest", "mf_batch_load",
                      "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info"]:
             getattr(L, name).restype = C.c_int
@@ -211,6 +212,19 @@ def mf_get_flow(g):
     return src[:k], dst[:k], flow[:k]
 
 
+def mf_get_edges(g):
+    """Current (src, dst, cap) of every pair with capacity > 0, sorted by (u, v)."""
+    cnt = C.c_int64()
+    _check(lib().mf_get_edges(g, C.byref(cnt), None, None, None), "mf_get_edges")
+    k = cnt.value
+    src, dst, cap = np.zeros(k, np.int32), np.zeros(k, np.int32), np.zeros(k, np.int32)
+    cnt = C.c_int64(k)
+    _check(lib().mf_get_edges(g, C.byref(cnt), src.ctypes.data, dst.ctypes.data, cap.ctypes.data),
+           "mf_get_edges")
+    k = cnt.value
+    return src[:k], dst[:k], cap[:k]
+
+
 def mf_get_stats(g) -> dict:
     s = Stats()
     _check(lib().mf_get_stats(g, C.byref(s)), "mf_get_stats")
@@ -268,6 +282,9 @@ class MaxFlowGraph:
 
     def get_flow(self):
         return mf_get_flow(self.h)
+
+    def get_edges(self):
+        return mf_get_edges(self.h)
 
     def stats(self) -> dict:
         return mf_get_stats(self.h)

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmf.so")
-SOURCES = ["kernels.hip", "api.cpp", "batch_api.cpp", "bicsr.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "batch_api.cpp", "bicsr.cpp", "relayout.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

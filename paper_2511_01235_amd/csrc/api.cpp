@@ -417,44 +417,38 @@ mf_status check_handle(mf_graph* g) {
 // need[v] more pairs plus fresh slack, upload.  Excess and heights stay.
 mf_status relayout(mf_graph* g) {
     hipStream_t st = g->stream;
-    const int32_t n = g->n;
-    const int64_t S = g->slot_cap;
-    mf::HostBiCSR in;
-    in.n = n;
-    in.row_ptr.resize((size_t)n + 1);
-    in.row_len.resize((size_t)n);
-    in.row_sorted.resize((size_t)n);
-    in.col.resize((size_t)S);
-    in.rev.resize((size_t)S);
-    in.cap.resize((size_t)S);
-    std::vector<int2> cr((size_t)S);
-    std::vector<int32_t> res((size_t)S), extra((size_t)n);
-    MF_HIP(hipMemcpyAsync(in.row_ptr.data(), g->dg.row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
-    MF_HIP(hipMemcpyAsync(in.row_len.data(), g->dg.row_len, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
-    MF_HIP(hipMemcpyAsync(cr.data(), g->dg.cr, sizeof(int2) * S, hipMemcpyDeviceToHost, st));
-    MF_HIP(hipMemcpyAsync(in.rev.data(), g->dg.rev, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
-    MF_HIP(hipMemcpyAsync(in.cap.data(), g->dg.cap, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
-    MF_HIP(hipMemcpyAsync(extra.data(), g->need, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
-    MF_HIP(hipStreamSynchronize(st));
-    for (int64_t j = 0; j < S; ++j) {
-        in.col[(size_t)j] = cr[(size_t)j].x;
-        res[(size_t)j] = cr[(size_t)j].y;
-    }
-    cr.clear();
-    cr.shrink_to_fit();
-    in.pairs = g->pairs;
-    in.m_unique = g->m_unique;
-    mf::HostBiCSR out;
-    std::vector<int32_t> res_out;
-    mf::relayout_bicsr(in, res, extra, g->slack_min, g->slack_pct, &out, &res_out);
-    if (out.row_ptr[(size_t)n] < 0 || (int64_t)out.row_ptr[(size_t)n] > (int64_t)INT_MAX - 1)
-        return MF_ERR_OVERFLOW;
-    free_structure(g);
-    mf_status rc = upload_structure(g, out, res_out);
+    mf::RelayoutPlan p{};
+    p.V = g->n;
+    p.row_ptr = g->dg.row_ptr;
+    p.row_len = g->dg.row_len;
+    p.row_sorted = g->dg.row_sorted;
+    p.need = g->need;
+    p.slack_min = g->slack_min;
+    p.slack_pct = g->slack_pct;
+    mf::SlotArrays a{g->dg.cr, g->dg.rev, g->dg.cap, g->dg.capsum};
+    int64_t S = 0;
+    mf_status rc = mf::relayout_device(p, &a, g->slot_cap, &S, g->dg.row_ptr, g->dg.row_sorted, st);
     if (rc != MF_OK) {
-        g->poisoned = true;
-        return rc == MF_ERR_OUT_OF_MEMORY ? MF_ERR_OUT_OF_MEMORY : rc;
+        if (rc == MF_ERR_DEVICE) g->poisoned = true;
+        return rc;
     }
+    g->dg.cr = a.cr;
+    g->dg.rev = a.rev;
+    g->dg.cap = a.cap;
+    g->dg.capsum = a.capsum;
+    g->slot_cap = S;
+    // arrays whose size follows the slot count
+    dfree(g->win);
+    dfree(g->q[0]);
+    dfree(g->q[1]);
+    g->q_cap = (int64_t)g->n + S / mf::GR_CHUNK + 64;
+    if (dalloc(g, &g->win, S) != hipSuccess || dalloc(g, &g->q[0], g->q_cap) != hipSuccess ||
+        dalloc(g, &g->q[1], g->q_cap) != hipSuccess) {
+        g->poisoned = true;
+        return MF_ERR_OUT_OF_MEMORY;
+    }
+    mf::launch_fill_i32(g->win, -1, S, st);
+    MF_HIP(hipGetLastError());
     g->relayouts++;
     return MF_OK;
 }
@@ -476,11 +470,12 @@ mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_
             if (c.overflow && !c.err && !c.cap_overflow) {
                 // need[] still holds the per-row demand: re-lay, then retry
                 rc = relayout(g);
-                if (rc != MF_OK) return rc;
+                if (g->poisoned) return MF_ERR_DEVICE;
             }
             mf::launch_batch_cleanup(g->tb, g->need, g->slot_of, g->win, k, st);
             MF_HIP(hipGetLastError());
             MF_HIP(hipStreamSynchronize(st));
+            if (rc != MF_OK) return rc;
             if (c.err) return MF_ERR_INVALID;
             if (c.cap_overflow) return MF_ERR_OVERFLOW;
             continue;
@@ -803,6 +798,50 @@ mf_status mf_get_flow(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, i
             src[k] = u;
             dst[k] = p.first;
             flow[k] = p.second;
+            ++k;
+        }
+    }
+    *count = k;
+    return MF_OK;
+}
+
+mf_status mf_get_edges(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, int32_t* cap) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    if (!count) return MF_ERR_INVALID;
+    bool want = src && dst && cap;
+    if ((src || dst || cap) && !want) return MF_ERR_INVALID;
+    hipStream_t st = g->stream;
+    const int32_t n = g->n;
+    const int64_t S = g->slot_cap;
+    std::vector<int32_t> cp((size_t)S), rp((size_t)n + 1), rl((size_t)n);
+    std::vector<int2> cr((size_t)S);
+    MF_HIP(hipMemcpyAsync(cp.data(), g->dg.cap, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(cr.data(), g->dg.cr, sizeof(int2) * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(rp.data(), g->dg.row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(rl.data(), g->dg.row_len, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipStreamSynchronize(st));
+    int64_t total = 0;
+    for (int32_t u = 0; u < n; ++u)
+        for (int32_t q = 0; q < rl[(size_t)u]; ++q) total += cp[(size_t)(rp[(size_t)u] + q)] > 0;
+    if (!want) {
+        *count = total;
+        return MF_OK;
+    }
+    if (total > *count) return MF_ERR_INVALID;
+    int64_t k = 0;
+    std::vector<std::pair<int32_t, int32_t>> row;
+    for (int32_t u = 0; u < n; ++u) {
+        row.clear();
+        for (int32_t q = 0; q < rl[(size_t)u]; ++q) {
+            int32_t j = rp[(size_t)u] + q;
+            if (cp[(size_t)j] > 0) row.push_back({cr[(size_t)j].x, cp[(size_t)j]});
+        }
+        std::sort(row.begin(), row.end());
+        for (auto& p : row) {
+            src[k] = u;
+            dst[k] = p.first;
+            cap[k] = p.second;
             ++k;
         }
     }

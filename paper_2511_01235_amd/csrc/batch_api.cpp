@@ -32,7 +32,10 @@ struct mf_batch {
     mf_options opt{};
     mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0};
     std::vector<int32_t> n, kc;
-    std::vector<int64_t> vbase, rpbase, sbase, slots, bbase, qbase;
+    std::vector<int64_t> vbase, rpbase, sbase, slots, bbase, qbase, used;
+    std::vector<int32_t> s_h, t_h;
+    int32_t slack_min = 2, slack_pct = 12;
+    int32_t relayouts = 0;
     int64_t total_v = 0, total_rp = 0, total_s = 0, total_b = 0, total_q = 0;
     // pools
     int32_t *row_ptr = nullptr, *row_len = nullptr, *row_sorted = nullptr;
@@ -55,6 +58,10 @@ struct mf_batch {
     unsigned long long* tkey = nullptr;
     int32_t *twin = nullptr, *tslot = nullptr;
     int64_t upd_cap = 0, tab_cap = 0;
+    // relayout scratch, made on first use
+    int32_t *gid_d = nullptr, *need_copy = nullptr;
+    int64_t* vbase_d = nullptr;
+    uint8_t* grow_d = nullptr;
     std::vector<DevCounters> ctr_h;
     bool solved = false, poisoned = false;
     double last_ms = 0;
@@ -79,6 +86,7 @@ void free_batch(mf_batch* b) {
     bfree(b->bits); bfree(b->q); bfree(b->wl); bfree(b->ctr); bfree(b->bytes_part);
     bfree(b->slots_d); bfree(b->order_d); bfree(b->gu_d); bfree(b->upd_d); bfree(b->slot_of);
     bfree(b->touched); bfree(b->tkey); bfree(b->twin); bfree(b->tslot);
+    bfree(b->gid_d); bfree(b->need_copy); bfree(b->vbase_d); bfree(b->grow_d);
 }
 
 #define MFB_HIP(call)              \
@@ -109,6 +117,186 @@ struct Clock {
         b->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
 };
+
+
+// Slot and queue bases of every graph for the current slot counts.
+void set_slot_bases(mf_batch* b) {
+    b->total_s = 0;
+    b->total_q = 0;
+    for (int i = 0; i < b->G; ++i) {
+        b->sbase[i] = b->total_s;
+        b->qbase[i] = b->total_q;
+        b->total_s += b->slots[i];
+        b->total_q += 2 * ((int64_t)b->n[i] + b->slots[i] / mf::GR_CHUNK + 64);
+    }
+}
+
+// (Re)allocates the slot-sized pools and the BFS queues, then uploads every
+// graph's rows and slots from hb (slot indices local to each graph, made
+// pool-global here).  res: residual per slot of each graph, or null for
+// res = cap (zero flow).  The vertex-sized pools must exist already.
+mf_status upload_slots(mf_batch* b, const std::vector<mf::HostBiCSR>& hb,
+                       const std::vector<std::vector<int32_t>>* res) {
+    const int G = b->G;
+    const int64_t V = b->total_v, SS = b->total_s;
+    bfree(b->cr); bfree(b->rev); bfree(b->cap); bfree(b->capsum); bfree(b->win); bfree(b->q);
+    if (balloc(&b->cr, SS) || balloc(&b->rev, SS) || balloc(&b->cap, SS) || balloc(&b->capsum, SS) ||
+        balloc(&b->win, SS) || balloc(&b->q, b->total_q))
+        return MF_ERR_OUT_OF_MEMORY;
+    std::vector<int32_t> rp((size_t)b->total_rp), rl((size_t)V), rs((size_t)V), rv((size_t)SS),
+        cp((size_t)SS), cs((size_t)SS, 0);
+    std::vector<int2> crh((size_t)SS);
+    b->used.assign((size_t)G, 0);
+    for (int i = 0; i < G; ++i) {
+        const mf::HostBiCSR& x = hb[(size_t)i];
+        const int32_t ni = b->n[i];
+        const int64_t sb = b->sbase[i];
+        for (int32_t v = 0; v <= ni; ++v) rp[(size_t)(b->rpbase[i] + v)] = (int32_t)(sb + x.row_ptr[(size_t)v]);
+        for (int32_t v = 0; v < ni; ++v) {
+            rl[(size_t)(b->vbase[i] + v)] = x.row_len[(size_t)v];
+            rs[(size_t)(b->vbase[i] + v)] = x.row_sorted[(size_t)v];
+            b->used[(size_t)i] += x.row_len[(size_t)v];
+        }
+        const std::vector<int32_t>* r = res ? &(*res)[(size_t)i] : nullptr;
+        for (int64_t j = 0; j < b->slots[i]; ++j) {
+            int32_t c = x.cap[(size_t)j];
+            crh[(size_t)(sb + j)] = make_int2(x.col[(size_t)j], r ? (*r)[(size_t)j] : c);
+            cp[(size_t)(sb + j)] = c;
+            int32_t rj = x.rev[(size_t)j];
+            rv[(size_t)(sb + j)] = rj >= 0 ? (int32_t)(sb + rj) : -1;
+            if (rj >= 0) cs[(size_t)(sb + j)] = c + x.cap[(size_t)rj];
+        }
+    }
+    hipStream_t st = b->stream;
+    if (hipMemcpyAsync(b->row_ptr, rp.data(), 4 * rp.size(), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(b->row_len, rl.data(), 4 * rl.size(), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(b->row_sorted, rs.data(), 4 * rs.size(), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(b->cr, crh.data(), 8 * crh.size(), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(b->rev, rv.data(), 4 * rv.size(), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(b->cap, cp.data(), 4 * cp.size(), hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(b->capsum, cs.data(), 4 * cs.size(), hipMemcpyHostToDevice, st))
+        return MF_ERR_DEVICE;
+    mf::launch_fill_i32(b->win, -1, SS, st);
+    // the host images are freed on return: wait for the copies
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return MF_ERR_DEVICE;
+    return MF_OK;
+}
+
+// Per-graph views over the pools (results of the last launch are kept), and
+// the solve order (largest graphs first, so that the long solves start
+// early), uploaded.
+mf_status upload_views(mf_batch* b) {
+    const int G = b->G;
+    b->slots_h.resize((size_t)G);
+    for (int i = 0; i < G; ++i) {
+        GraphSlot& S = b->slots_h[(size_t)i];
+        const int32_t ni = b->n[i];
+        mf::DevGraph& g = S.g;
+        g.n = ni;
+        g.s = b->s_h[(size_t)i];
+        g.t = b->t_h[(size_t)i];
+        g.root = g.t;
+        g.pinned = g.s;
+        g.row_ptr = b->row_ptr + b->rpbase[i];
+        g.row_len = b->row_len + b->vbase[i];
+        g.row_sorted = b->row_sorted + b->vbase[i];
+        g.cr = b->cr;
+        g.rev = b->rev;
+        g.cap = b->cap;
+        g.capsum = b->capsum;
+        g.e = b->e + b->vbase[i];
+        g.h = b->h + b->vbase[i];
+        g.used_slots = b->used[(size_t)i];
+        g.bytes_part = b->bytes_part;
+        g.count_bytes = 0;
+        int64_t qc = (int64_t)ni + b->slots[i] / mf::GR_CHUNK + 64;
+        S.q0 = b->q + b->qbase[i];
+        S.q1 = S.q0 + qc;
+        S.wl0 = b->wl + 3 * b->vbase[i];
+        S.wl1 = S.wl0 + ni;
+        S.wl2 = S.wl1 + ni;
+        S.bits.nwords = (ni + 31) / 32;
+        S.bits.visited = b->bits + b->bbase[i];
+        S.bits.fb = S.bits.visited + S.bits.nwords;
+        S.ctr = b->ctr + i;
+        S.kc = b->kc[i];
+        S.warm = b->opt.cold_start ? 0 : 1;
+        S.max_iter = b->opt.max_iterations > 0 ? b->opt.max_iterations : 4 * (int64_t)ni + 1000;
+    }
+    std::vector<int32_t> order((size_t)G);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return b->slots[a] > b->slots[c]; });
+    if (hipMemcpy(b->slots_d, b->slots_h.data(), sizeof(GraphSlot) * G, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->order_d, order.data(), 4 * (size_t)G, hipMemcpyHostToDevice) != hipSuccess)
+        return MF_ERR_DEVICE;
+    return MF_OK;
+}
+
+// A batch's inserts did not fit the free slots of some rows: re-lay the rows
+// of the graphs flagged in `grow` on the device with room for need[] more
+// (residuals, excesses and heights are kept), move every graph to its new
+// place in the pools and rebuild the views.  A device failure leaves the
+// batch poisoned.
+mf_status relayout_pool(mf_batch* b, const int32_t* need_d, const std::vector<char>& grow) {
+    const int G = b->G;
+    const int64_t V = b->total_v;
+    hipStream_t st = b->stream;
+    if (!b->gid_d) {
+        std::vector<int32_t> gid((size_t)V);
+        for (int i = 0; i < G; ++i)
+            std::fill(gid.begin() + b->vbase[i], gid.begin() + b->vbase[i] + b->n[i], i);
+        if (balloc(&b->gid_d, V) || balloc(&b->vbase_d, G) || balloc(&b->grow_d, G)) return MF_ERR_OUT_OF_MEMORY;
+        MFB_HIP(hipMemcpyAsync(b->gid_d, gid.data(), 4 * (size_t)V, hipMemcpyHostToDevice, st));
+        MFB_HIP(hipMemcpyAsync(b->vbase_d, b->vbase.data(), 8 * (size_t)G, hipMemcpyHostToDevice, st));
+        MFB_HIP(hipStreamSynchronize(st));
+    }
+    std::vector<uint8_t> gr(grow.begin(), grow.end());
+    MFB_HIP(hipMemcpyAsync(b->grow_d, gr.data(), (size_t)G, hipMemcpyHostToDevice, st));
+    for (int i = 0; i < G; ++i) b->used[(size_t)i] = b->slots_h[(size_t)i].g.used_slots;
+    mf::RelayoutPlan p{};
+    p.V = (int32_t)V;
+    p.row_ptr = b->row_ptr;
+    p.row_len = b->row_len;
+    p.row_sorted = b->row_sorted;
+    p.need = need_d;
+    p.gid = b->gid_d;
+    p.vbase = b->vbase_d;
+    p.grow = b->grow_d;
+    p.slack_min = b->slack_min;
+    p.slack_pct = b->slack_pct;
+    mf::SlotArrays a{b->cr, b->rev, b->cap, b->capsum};
+    int64_t S = 0;
+    mf_status rc = mf::relayout_device(p, &a, b->total_s, &S, b->row_ptr, b->row_sorted, st);
+    if (rc != MF_OK) {
+        if (rc == MF_ERR_DEVICE) b->poisoned = true;
+        return rc;
+    }
+    b->cr = a.cr;
+    b->rev = a.rev;
+    b->cap = a.cap;
+    b->capsum = a.capsum;
+    // per-graph slot counts from the new row pointers (graphs stay in order)
+    std::vector<int32_t> rp((size_t)b->total_rp);
+    MFB_HIP(hipMemcpyAsync(rp.data(), b->row_ptr, 4 * rp.size(), hipMemcpyDeviceToHost, st));
+    MFB_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < G; ++i) b->slots[i] = (int64_t)rp[(size_t)(b->rpbase[i] + b->n[i])] - rp[(size_t)b->rpbase[i]];
+    set_slot_bases(b);
+    bfree(b->win);
+    bfree(b->q);
+    if (b->total_s != S || balloc(&b->win, S) || balloc(&b->q, b->total_q)) {
+        b->poisoned = true;
+        return MF_ERR_DEVICE;
+    }
+    mf::launch_fill_i32(b->win, -1, S, st);
+    MFB_HIP(hipGetLastError());
+    rc = upload_views(b);
+    if (rc != MF_OK) {
+        b->poisoned = true;
+        return rc;
+    }
+    b->relayouts++;
+    return MF_OK;
+}
 
 }  // namespace
 
@@ -160,131 +348,47 @@ mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edg
         b->own_stream = true;
     }
     const int G = num_graphs;
+    b->slack_min = slack_min;
+    b->slack_pct = slack_pct;
+    b->s_h.assign(s, s + G);
+    b->t_h.assign(t, t + G);
     b->n.resize(G); b->kc.resize(G); b->vbase.resize(G); b->rpbase.resize(G); b->sbase.resize(G);
     b->slots.resize(G); b->bbase.resize(G); b->qbase.resize(G);
     for (int i = 0; i < G; ++i) {
         const mf::HostBiCSR& x = hb[(size_t)i];
         b->n[i] = n[i];
-        int64_t S = x.row_ptr[(size_t)n[i]];
         int64_t kc = o.kernel_cycles > 0 ? o.kernel_cycles : (x.m_unique + n[i] / 2) / n[i];
         b->kc[i] = (int32_t)std::max<int64_t>(1, kc);
         b->vbase[i] = b->total_v;
         b->rpbase[i] = b->total_rp;
-        b->sbase[i] = b->total_s;
-        b->slots[i] = S;
+        b->slots[i] = x.row_ptr[(size_t)n[i]];
         b->bbase[i] = b->total_b;
-        b->qbase[i] = b->total_q;
         b->total_v += n[i];
         b->total_rp += n[i] + 1;
-        b->total_s += S;
         b->total_b += 4 * (int64_t)((n[i] + 31) / 32);
-        b->total_q += 2 * ((int64_t)n[i] + S / mf::GR_CHUNK + 64);
     }
+    set_slot_bases(b);
     if (b->total_s > INT_MAX || b->total_v > INT_MAX) return fail(MF_ERR_OVERFLOW);
-    const int64_t V = b->total_v, SS = b->total_s;
+    const int64_t V = b->total_v;
     if (balloc(&b->row_ptr, b->total_rp) || balloc(&b->row_len, V) || balloc(&b->row_sorted, V) ||
-        balloc(&b->cr, SS) || balloc(&b->rev, SS) || balloc(&b->cap, SS) || balloc(&b->capsum, SS) ||
-        balloc(&b->win, SS) || balloc(&b->need, V) || balloc(&b->e, V) || balloc(&b->h, V) ||
-        balloc(&b->bits, b->total_b) || balloc(&b->q, b->total_q) || balloc(&b->wl, 3 * V) ||
-        balloc(&b->ctr, G) || balloc(&b->bytes_part, (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS) ||
-        balloc(&b->slots_d, G) || balloc(&b->order_d, G))
+        balloc(&b->need, V) || balloc(&b->e, V) || balloc(&b->h, V) || balloc(&b->bits, b->total_b) ||
+        balloc(&b->wl, 3 * V) || balloc(&b->ctr, G) ||
+        balloc(&b->bytes_part, (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS) || balloc(&b->slots_d, G) ||
+        balloc(&b->order_d, G))
         return fail(MF_ERR_OUT_OF_MEMORY);
-    // host images of the pools (slot indices made pool-global)
-    {
-        std::vector<int32_t> rp((size_t)b->total_rp), rl((size_t)V), rs((size_t)V), rv((size_t)SS),
-            cp((size_t)SS), cs((size_t)SS, 0);
-        std::vector<int2> crh((size_t)SS);
-        for (int i = 0; i < G; ++i) {
-            const mf::HostBiCSR& x = hb[(size_t)i];
-            int64_t sb = b->sbase[i];
-            for (int32_t v = 0; v <= n[i]; ++v) rp[(size_t)(b->rpbase[i] + v)] = (int32_t)(sb + x.row_ptr[(size_t)v]);
-            for (int32_t v = 0; v < n[i]; ++v) {
-                rl[(size_t)(b->vbase[i] + v)] = x.row_len[(size_t)v];
-                rs[(size_t)(b->vbase[i] + v)] = x.row_sorted[(size_t)v];
-            }
-            for (int64_t j = 0; j < b->slots[i]; ++j) {
-                crh[(size_t)(sb + j)] = make_int2(x.col[(size_t)j], x.cap[(size_t)j]);
-                cp[(size_t)(sb + j)] = x.cap[(size_t)j];
-                int32_t r = x.rev[(size_t)j];
-                rv[(size_t)(sb + j)] = r >= 0 ? (int32_t)(sb + r) : -1;
-                if (r >= 0) cs[(size_t)(sb + j)] = x.cap[(size_t)j] + x.cap[(size_t)r];
-            }
-        }
-        hb.clear();
-        hb.shrink_to_fit();
-        hipStream_t st = b->stream;
-        if (hipMemcpyAsync(b->row_ptr, rp.data(), 4 * rp.size(), hipMemcpyHostToDevice, st) ||
-            hipMemcpyAsync(b->row_len, rl.data(), 4 * rl.size(), hipMemcpyHostToDevice, st) ||
-            hipMemcpyAsync(b->row_sorted, rs.data(), 4 * rs.size(), hipMemcpyHostToDevice, st) ||
-            hipMemcpyAsync(b->cr, crh.data(), 8 * crh.size(), hipMemcpyHostToDevice, st) ||
-            hipMemcpyAsync(b->rev, rv.data(), 4 * rv.size(), hipMemcpyHostToDevice, st) ||
-            hipMemcpyAsync(b->cap, cp.data(), 4 * cp.size(), hipMemcpyHostToDevice, st) ||
-            hipMemcpyAsync(b->capsum, cs.data(), 4 * cs.size(), hipMemcpyHostToDevice, st))
-            return fail(MF_ERR_DEVICE);
-        mf::launch_fill_i32(b->win, -1, SS, st);
-        mf::launch_fill_i32(b->need, 0, V, st);
-        mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->e), 0, 2 * V, st);
-        mf::launch_fill_i32(b->h, 0, V, st);
-        mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->bytes_part), 0,
-                            2 * (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS, st);
-        mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->ctr), 0, (int64_t)G * sizeof(DevCounters) / 4, st);
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return fail(MF_ERR_DEVICE);
-    }
-    // per-graph views
-    b->slots_h.resize((size_t)G);
-    for (int i = 0; i < G; ++i) {
-        GraphSlot& S = b->slots_h[(size_t)i];
-        std::memset(&S, 0, sizeof(S));
-        mf::DevGraph& g = S.g;
-        g.n = n[i];
-        g.s = s[i];
-        g.t = t[i];
-        g.root = t[i];
-        g.pinned = s[i];
-        g.row_ptr = b->row_ptr + b->rpbase[i];
-        g.row_len = b->row_len + b->vbase[i];
-        g.row_sorted = b->row_sorted + b->vbase[i];
-        g.cr = b->cr;
-        g.rev = b->rev;
-        g.cap = b->cap;
-        g.capsum = b->capsum;
-        g.e = b->e + b->vbase[i];
-        g.h = b->h + b->vbase[i];
-        g.used_slots = 0;  // set below from the rows
-        g.bytes_part = b->bytes_part;
-        g.count_bytes = 0;
-        int64_t qc = (int64_t)n[i] + b->slots[i] / mf::GR_CHUNK + 64;
-        S.q0 = b->q + b->qbase[i];
-        S.q1 = S.q0 + qc;
-        S.wl0 = b->wl + 3 * b->vbase[i];
-        S.wl1 = S.wl0 + n[i];
-        S.wl2 = S.wl1 + n[i];
-        S.bits.nwords = (n[i] + 31) / 32;
-        S.bits.visited = b->bits + b->bbase[i];
-        S.bits.fb = S.bits.visited + S.bits.nwords;
-        S.ctr = b->ctr + i;
-        S.kc = b->kc[i];
-        S.warm = o.cold_start ? 0 : 1;
-        S.max_iter = o.max_iterations > 0 ? o.max_iterations : 4 * (int64_t)n[i] + 1000;
-    }
-    {
-        // used slots per graph = sum of its row lengths
-        std::vector<int32_t> rl((size_t)V);
-        if (hipMemcpy(rl.data(), b->row_len, 4 * (size_t)V, hipMemcpyDeviceToHost) != hipSuccess)
-            return fail(MF_ERR_DEVICE);
-        for (int i = 0; i < G; ++i) {
-            int64_t u = 0;
-            for (int32_t v = 0; v < n[i]; ++v) u += rl[(size_t)(b->vbase[i] + v)];
-            b->slots_h[(size_t)i].g.used_slots = u;
-        }
-    }
-    // largest graphs first, so that the long solves start early
-    std::vector<int32_t> order((size_t)G);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return b->slots[a] > b->slots[c]; });
-    if (hipMemcpy(b->slots_d, b->slots_h.data(), sizeof(GraphSlot) * G, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->order_d, order.data(), 4 * (size_t)G, hipMemcpyHostToDevice) != hipSuccess)
-        return fail(MF_ERR_DEVICE);
+    hipStream_t st = b->stream;
+    mf::launch_fill_i32(b->need, 0, V, st);
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->e), 0, 2 * V, st);
+    mf::launch_fill_i32(b->h, 0, V, st);
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->bytes_part), 0, 2 * (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS,
+                        st);
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->ctr), 0, (int64_t)G * sizeof(DevCounters) / 4, st);
+    mf_status rc = upload_slots(b, hb, nullptr);
+    if (rc != MF_OK) return fail(rc);
+    hb.clear();
+    hb.shrink_to_fit();
+    rc = upload_views(b);
+    if (rc != MF_OK) return fail(rc);
     *out = b;
     return MF_OK;
 }
@@ -348,40 +452,55 @@ mf_status mf_batch_apply(mf_batch* b, const int64_t* update_offset, const mf_upd
         b->tab_cap = c;
     }
     if (!b->gu_d && balloc(&b->gu_d, G)) return MF_ERR_OUT_OF_MEMORY;
-    std::vector<GraphUpdates> gu((size_t)G);
-    for (int i = 0; i < G; ++i) {
-        GraphUpdates& U = gu[(size_t)i];
-        int64_t o0 = update_offset[i];
-        U.upd = b->upd_d + o0;
-        U.k = (int32_t)(update_offset[i + 1] - o0);
-        U.slot_of = b->slot_of + o0;
-        U.touched = b->touched + o0;
-        U.win = b->win;
-        U.need = b->need + b->vbase[i];
-        U.tb.key = b->tkey + toff[(size_t)i];
-        U.tb.win = b->twin + 2 * toff[(size_t)i];
-        U.tb.slot = b->tslot + 2 * toff[(size_t)i];
-        U.tb.capacity = tcap[(size_t)i];
-    }
     if (K > 0) MFB_HIP(hipMemcpyAsync(b->upd_d, upd, sizeof(mf_update) * (size_t)K, hipMemcpyHostToDevice, st));
-    MFB_HIP(hipMemcpyAsync(b->gu_d, gu.data(), sizeof(GraphUpdates) * (size_t)G, hipMemcpyHostToDevice, st));
-    mf::launch_batch_locate_multi(b->slots_d, b->gu_d, G, st);
-    MFB_HIP(hipGetLastError());
     b->ctr_h.resize((size_t)G);
-    MFB_HIP(hipMemcpyAsync(b->ctr_h.data(), b->ctr, sizeof(DevCounters) * (size_t)G, hipMemcpyDeviceToHost, st));
-    MFB_HIP(hipStreamSynchronize(st));
-    bool err = false, ovf = false, slack = false;
-    for (int i = 0; i < G; ++i) {
-        err |= b->ctr_h[(size_t)i].err != 0;
-        ovf |= b->ctr_h[(size_t)i].cap_overflow != 0;
-        slack |= b->ctr_h[(size_t)i].overflow != 0;
-    }
-    if (err || ovf || slack) {
-        // nothing was changed: return the scratch to idle and report
+    for (int attempt = 0;; ++attempt) {
+        bool relay_fail = false;
+        std::vector<GraphUpdates> gu((size_t)G);
+        for (int i = 0; i < G; ++i) {
+            GraphUpdates& U = gu[(size_t)i];
+            int64_t o0 = update_offset[i];
+            U.upd = b->upd_d + o0;
+            U.k = (int32_t)(update_offset[i + 1] - o0);
+            U.slot_of = b->slot_of + o0;
+            U.touched = b->touched + o0;
+            U.win = b->win;
+            U.need = b->need + b->vbase[i];
+            U.tb.key = b->tkey + toff[(size_t)i];
+            U.tb.win = b->twin + 2 * toff[(size_t)i];
+            U.tb.slot = b->tslot + 2 * toff[(size_t)i];
+            U.tb.capacity = tcap[(size_t)i];
+        }
+        MFB_HIP(hipMemcpyAsync(b->gu_d, gu.data(), sizeof(GraphUpdates) * (size_t)G, hipMemcpyHostToDevice, st));
+        mf::launch_batch_locate_multi(b->slots_d, b->gu_d, G, st);
+        MFB_HIP(hipGetLastError());
+        MFB_HIP(hipMemcpyAsync(b->ctr_h.data(), b->ctr, sizeof(DevCounters) * (size_t)G, hipMemcpyDeviceToHost, st));
+        MFB_HIP(hipStreamSynchronize(st));
+        bool err = false, ovf = false, slack = false;
+        std::vector<char> grow((size_t)G, 0);
+        for (int i = 0; i < G; ++i) {
+            err |= b->ctr_h[(size_t)i].err != 0;
+            ovf |= b->ctr_h[(size_t)i].cap_overflow != 0;
+            grow[(size_t)i] = b->ctr_h[(size_t)i].overflow != 0;
+            slack |= grow[(size_t)i] != 0;
+        }
+        if (!err && !ovf && !slack) break;
+        // nothing was changed yet.  Rows without room for their inserts: keep
+        // need[] (the per-row demand), return the scratch to idle, re-lay
+        // those graphs and locate again.
+        const bool relay = !err && !ovf && attempt < 2;
+        if (relay) {
+            if (!b->need_copy && balloc(&b->need_copy, b->total_v)) relay_fail = true;
+            else MFB_HIP(hipMemcpyAsync(b->need_copy, b->need, 4 * (size_t)b->total_v, hipMemcpyDeviceToDevice, st));
+        }
         mf::launch_batch_cleanup_multi(b->gu_d, G, st);
         MFB_HIP(hipGetLastError());
         MFB_HIP(hipStreamSynchronize(st));
-        return err ? MF_ERR_INVALID : MF_ERR_OVERFLOW;
+        if (err) return MF_ERR_INVALID;
+        if (ovf || !relay) return MF_ERR_OVERFLOW;
+        if (relay_fail) return MF_ERR_OUT_OF_MEMORY;
+        mf_status rc = relayout_pool(b, b->need_copy, grow);
+        if (rc != MF_OK) return rc;
     }
     b->solved = false;
     mf::launch_batch_repair_multi(b->slots_d, b->gu_d, b->order_d, G, b->tune, st);

@@ -174,52 +174,4 @@ mf_status build_bicsr(int32_t n, int64_t m, const int32_t* src, const int32_t* d
     return MF_OK;
 }
 
-void relayout_bicsr(const HostBiCSR& in, const std::vector<int32_t>& res_in,
-                    const std::vector<int32_t>& extra, int32_t slack_min, int32_t slack_pct,
-                    HostBiCSR* out, std::vector<int32_t>* res_out) {
-    const int32_t n = in.n;
-    out->n = n;
-    out->row_ptr.assign((size_t)n + 1, 0);
-    out->row_len = in.row_len;
-    out->row_sorted = in.row_len;
-    int64_t total = 0;
-    for (int32_t v = 0; v < n; ++v) {
-        out->row_ptr[(size_t)v] = (int32_t)total;
-        int64_t want = (int64_t)in.row_len[(size_t)v] + extra[(size_t)v];
-        total += want + slack_for(want, slack_min, slack_pct);
-    }
-    out->row_ptr[(size_t)n] = (int32_t)total;
-    out->col.assign((size_t)total, 0);
-    out->cap.assign((size_t)total, 0);
-    out->rev.assign((size_t)total, -1);
-    res_out->assign((size_t)total, 0);
-    std::vector<int32_t> where(in.col.size(), -1);  // old slot -> new slot
-    std::vector<int32_t> order;
-    for (int32_t v = 0; v < n; ++v) {
-        int32_t ob = in.row_ptr[(size_t)v], nb = out->row_ptr[(size_t)v], L = in.row_len[(size_t)v];
-        order.resize((size_t)L);
-        std::iota(order.begin(), order.end(), 0);
-        std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-            return in.col[(size_t)(ob + a)] < in.col[(size_t)(ob + b)];
-        });
-        for (int32_t q = 0; q < L; ++q) {
-            int32_t oj = ob + order[(size_t)q], nj = nb + q;
-            where[(size_t)oj] = nj;
-            out->col[(size_t)nj] = in.col[(size_t)oj];
-            out->cap[(size_t)nj] = in.cap[(size_t)oj];
-            (*res_out)[(size_t)nj] = res_in[(size_t)oj];
-        }
-        for (int32_t q = L; q < out->row_ptr[(size_t)v + 1] - nb; ++q) out->col[(size_t)(nb + q)] = v;
-    }
-    for (int32_t v = 0; v < n; ++v) {
-        int32_t ob = in.row_ptr[(size_t)v];
-        for (int32_t q = 0; q < in.row_len[(size_t)v]; ++q) {
-            int32_t oj = ob + q;
-            out->rev[(size_t)where[(size_t)oj]] = where[(size_t)in.rev[(size_t)oj]];
-        }
-    }
-    out->pairs = in.pairs;
-    out->m_unique = in.m_unique;
-}
-
 }  // namespace mf

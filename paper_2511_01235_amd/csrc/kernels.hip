@@ -1421,6 +1421,199 @@ inline int grid_for(int64_t items, int block, int cap = 4096) {
     return (int)g;
 }
 
+// ---- relayout: rows with room for their pending inserts ---------------------
+//
+// Rows keep their slots in order; each row's new size is its used length plus
+// the inserts it still needs plus fresh slack (rows of graphs that do not grow
+// keep their size).  Vertex gv of graph i = gid[gv] sits at row_ptr[gv + i]
+// (each graph's row_ptr has n_i + 1 entries).  Rows whose inserted tail is
+// unsorted and that fit RL_SORT_MAX slots are sorted by column on the way.
+
+constexpr int RL_BLOCK = 256;
+constexpr int RL_SCAN_ITEMS = 16;                      // per thread
+constexpr int RL_TILE = RL_BLOCK * RL_SCAN_ITEMS;      // per block
+constexpr int RL_SORT_MAX = 4096;
+
+__global__ void __launch_bounds__(RL_BLOCK) k_relayout_sizes(RelayoutPlan p) {
+    int gv = blockIdx.x * RL_BLOCK + threadIdx.x;
+    if (gv >= p.V) return;
+    int i = p.gid ? p.gid[gv] : 0;
+    int rp = gv + i;
+    int len = p.row_len[gv];
+    long long sz;
+    if (!p.grow || p.grow[i]) {
+        long long want = (long long)len + p.need[gv];
+        long long sl = (want * p.slack_pct + 99) / 100;
+        sz = want + (sl < p.slack_min ? p.slack_min : sl);
+    } else {
+        sz = (long long)p.row_ptr[rp + 1] - p.row_ptr[rp];
+    }
+    p.size[gv] = sz;
+    if (p.row_sorted[gv] < len && len <= RL_SORT_MAX) p.sort_rows[atomicAdd(p.sort_count, 1)] = gv;
+}
+
+// exclusive scan of size[0..V) into start[0..V], start[V] = total: tile sums,
+// one block over the tile sums, then each tile with its offset
+__device__ __forceinline__ long long block_excl_scan_i64(long long x, long long* s_w, long long* total) {
+    const int lane = lane_id(), w = threadIdx.x / WAVE;
+    long long inc = x;
+    for (int d = 1; d < WAVE; d <<= 1) {
+        long long y = __shfl_up(inc, d, WAVE);
+        if (lane >= d) inc += y;
+    }
+    if (lane == WAVE - 1) s_w[w] = inc;
+    __syncthreads();
+    long long before = 0, all = 0;
+    for (int q = 0; q < RL_BLOCK / WAVE; ++q) {
+        if (q < w) before += s_w[q];
+        all += s_w[q];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - x;
+}
+
+__global__ void __launch_bounds__(RL_BLOCK) k_relayout_tile_sums(RelayoutPlan p) {
+    __shared__ long long s_w[RL_BLOCK / WAVE];
+    long long base = (long long)blockIdx.x * RL_TILE;
+    long long x = 0;
+    for (int q = 0; q < RL_SCAN_ITEMS; ++q) {
+        long long idx = base + (long long)threadIdx.x * RL_SCAN_ITEMS + q;
+        if (idx < p.V) x += p.size[idx];
+    }
+    long long total;
+    block_excl_scan_i64(x, s_w, &total);
+    if (threadIdx.x == 0) p.tile[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(RL_BLOCK) k_relayout_scan_tiles(RelayoutPlan p, int tiles) {
+    __shared__ long long s_w[RL_BLOCK / WAVE];
+    long long carry = 0;
+    for (int b0 = 0; b0 < tiles; b0 += RL_BLOCK) {
+        int b = b0 + threadIdx.x;
+        long long x = b < tiles ? p.tile[b] : 0;
+        long long total;
+        long long ex = block_excl_scan_i64(x, s_w, &total);
+        if (b < tiles) p.tile[b] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) p.start[p.V] = carry;
+}
+
+__global__ void __launch_bounds__(RL_BLOCK) k_relayout_scan(RelayoutPlan p) {
+    __shared__ long long s_w[RL_BLOCK / WAVE];
+    long long base = (long long)blockIdx.x * RL_TILE + (long long)threadIdx.x * RL_SCAN_ITEMS;
+    long long v[RL_SCAN_ITEMS];
+    long long x = 0;
+    for (int q = 0; q < RL_SCAN_ITEMS; ++q) {
+        v[q] = base + q < p.V ? p.size[base + q] : 0;
+        x += v[q];
+    }
+    long long total;
+    long long run = p.tile[blockIdx.x] + block_excl_scan_i64(x, s_w, &total);
+    for (int q = 0; q < RL_SCAN_ITEMS; ++q) {
+        if (base + q < p.V) p.start[base + q] = run;
+        run += v[q];
+    }
+}
+
+// src_of[j'] = old slot that moves to new slot j', or -1 for free slack
+__global__ void __launch_bounds__(RL_BLOCK) k_relayout_src(RelayoutPlan p, int32_t* src_of, long long S_new) {
+    long long jn = (long long)blockIdx.x * RL_BLOCK + threadIdx.x;
+    if (jn >= S_new) return;
+    int lo = 0, hi = p.V;                   // last row whose start <= jn
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (p.start[mid] <= jn) lo = mid;
+        else hi = mid;
+    }
+    int gv = lo;
+    int i = p.gid ? p.gid[gv] : 0;
+    long long q = jn - p.start[gv];
+    src_of[jn] = q < p.row_len[gv] ? (int32_t)(p.row_ptr[gv + i] + q) : -1;
+}
+
+// sort one listed row's used slots by column (columns in a row are distinct)
+__global__ void __launch_bounds__(RL_BLOCK) k_relayout_sort(RelayoutPlan p, const int2* cr_old, int32_t* src_of,
+                                                           int32_t* row_sorted) {
+    __shared__ unsigned long long s_key[RL_SORT_MAX];
+    const int gv = p.sort_rows[blockIdx.x];
+    const int len = p.row_len[gv];
+    const long long b = p.start[gv];
+    int P2 = 1;
+    while (P2 < len) P2 <<= 1;
+    for (int q = threadIdx.x; q < P2; q += RL_BLOCK) {
+        if (q < len) {
+            int j = src_of[b + q];
+            s_key[q] = ((unsigned long long)(unsigned)cr_old[j].x << 32) | (unsigned)j;
+        } else {
+            s_key[q] = ~0ull;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int d = k >> 1; d > 0; d >>= 1) {
+            for (int q = threadIdx.x; q < P2; q += RL_BLOCK) {
+                int r = q ^ d;
+                if (r > q) {
+                    unsigned long long a = s_key[q], c = s_key[r];
+                    bool up = (q & k) == 0;
+                    if ((a > c) == up) {
+                        s_key[q] = c;
+                        s_key[r] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = threadIdx.x; q < len; q += RL_BLOCK) src_of[b + q] = (int32_t)(unsigned)(s_key[q] & 0xffffffffu);
+    if (threadIdx.x == 0) row_sorted[gv] = len;
+}
+
+__global__ void __launch_bounds__(RL_BLOCK) k_relayout_gather(RelayoutPlan p, const int32_t* src_of, SlotArrays from,
+                                                             SlotArrays to, int32_t* where, long long S_new) {
+    long long jn = (long long)blockIdx.x * RL_BLOCK + threadIdx.x;
+    if (jn >= S_new) return;
+    int j = src_of[jn];
+    if (j >= 0) {
+        to.cr[jn] = from.cr[j];
+        to.cap[jn] = from.cap[j];
+        to.capsum[jn] = from.capsum[j];
+        where[j] = (int32_t)jn;
+    } else {
+        int lo = 0, hi = p.V;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (p.start[mid] <= jn) lo = mid;
+            else hi = mid;
+        }
+        int i = p.gid ? p.gid[lo] : 0;
+        int local = lo - (p.vbase ? (int)p.vbase[i] : 0);
+        to.cr[jn] = make_int2(local, 0);
+        to.cap[jn] = 0;
+        to.capsum[jn] = 0;
+        to.rev[jn] = -1;
+    }
+}
+
+__global__ void __launch_bounds__(RL_BLOCK) k_relayout_rev(const int32_t* src_of, const int32_t* rev_old,
+                                                          const int32_t* where, int32_t* rev_new, long long S_new) {
+    long long jn = (long long)blockIdx.x * RL_BLOCK + threadIdx.x;
+    if (jn >= S_new) return;
+    int j = src_of[jn];
+    if (j >= 0) rev_new[jn] = where[rev_old[j]];
+}
+
+__global__ void __launch_bounds__(RL_BLOCK) k_relayout_row_ptr(RelayoutPlan p, int32_t* row_ptr) {
+    int gv = blockIdx.x * RL_BLOCK + threadIdx.x;
+    if (gv >= p.V) return;
+    int i = p.gid ? p.gid[gv] : 0;
+    row_ptr[gv + i] = (int32_t)p.start[gv];
+    bool last = gv + 1 == p.V || (p.gid && p.gid[gv + 1] != i);
+    if (last) row_ptr[gv + i + 1] = (int32_t)p.start[gv + 1];
+}
+
 }  // namespace
 
 // ---- launch wrappers ----------------------------------------------------------
@@ -1629,6 +1822,27 @@ void launch_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu, const int32_t
 
 void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st) {
     if (num > 0) k_batch_cleanup_multi<256><<<num, 256, 0, st>>>(gu);
+}
+
+int64_t relayout_tiles(int32_t V) { return ((int64_t)V + RL_TILE - 1) / RL_TILE; }
+
+void launch_relayout_plan(const RelayoutPlan& p, hipStream_t st) {
+    const int tiles = (int)relayout_tiles(p.V);
+    k_fill_i32<<<1, 64, 0, st>>>(p.sort_count, 0, 1);
+    k_relayout_sizes<<<(p.V + RL_BLOCK - 1) / RL_BLOCK, RL_BLOCK, 0, st>>>(p);
+    k_relayout_tile_sums<<<tiles, RL_BLOCK, 0, st>>>(p);
+    k_relayout_scan_tiles<<<1, RL_BLOCK, 0, st>>>(p, tiles);
+    k_relayout_scan<<<tiles, RL_BLOCK, 0, st>>>(p);
+}
+
+void launch_relayout_move(const RelayoutPlan& p, int32_t sort_count, int64_t S_new, SlotArrays from, SlotArrays to,
+                          int32_t* src_of, int32_t* where, int32_t* row_ptr, int32_t* row_sorted, hipStream_t st) {
+    const unsigned blocks = (unsigned)((S_new + RL_BLOCK - 1) / RL_BLOCK);
+    k_relayout_src<<<blocks, RL_BLOCK, 0, st>>>(p, src_of, S_new);
+    if (sort_count > 0) k_relayout_sort<<<sort_count, RL_BLOCK, 0, st>>>(p, from.cr, src_of, row_sorted);
+    k_relayout_gather<<<blocks, RL_BLOCK, 0, st>>>(p, src_of, from, to, where, S_new);
+    k_relayout_rev<<<blocks, RL_BLOCK, 0, st>>>(src_of, from.rev, where, to.rev, S_new);
+    k_relayout_row_ptr<<<(p.V + RL_BLOCK - 1) / RL_BLOCK, RL_BLOCK, 0, st>>>(p, row_ptr);
 }
 
 int device_selftest(hipStream_t st) {

@@ -136,6 +136,38 @@ struct GraphUpdates {
     BatchTable tb;
 };
 
+// Slot-sized arrays of a Bi-CSR (one graph, or a pool of graphs).
+struct SlotArrays {
+    int2* cr;
+    int32_t* rev;
+    int32_t* cap;
+    int32_t* capsum;
+};
+
+// Inputs of a device relayout.  Vertex gv (0..V) belongs to graph gid[gv]
+// (gid null: one graph) whose first vertex is vbase[graph] (null: 0); its
+// row starts at row_ptr[gv + graph] (every graph's row_ptr has n + 1
+// entries).  Rows of graphs with grow[graph] == 0 keep their size (grow
+// null: every row grows); a growing row gets room for need[gv] more slots
+// plus fresh slack.
+struct RelayoutPlan {
+    int32_t V;
+    const int32_t* row_ptr;
+    const int32_t* row_len;
+    const int32_t* row_sorted;
+    const int32_t* need;
+    const int32_t* gid;
+    const int64_t* vbase;
+    const uint8_t* grow;
+    int32_t slack_min, slack_pct;
+    // scratch
+    int64_t* size;             // V
+    int64_t* start;            // V + 1
+    int64_t* tile;             // relayout_tiles(V)
+    int32_t* sort_rows;        // V
+    int32_t* sort_count;       // 1
+};
+
 // ---- launch wrappers (kernels.hip) ---------------------------------------
 void launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t st);
 void launch_reset(const DevGraph& g, int64_t slot_cap, hipStream_t st);
@@ -186,6 +218,15 @@ void launch_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu, const int32_t
                                const GrTune& tune, hipStream_t st);
 // After a failed validation: scratch back to idle for every graph.
 void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st);
+int64_t relayout_tiles(int32_t V);
+// sizes, their scan into start[] and the rows to sort; then the caller reads
+// start[V] (the new slot count) and *sort_count
+void launch_relayout_plan(const RelayoutPlan& p, hipStream_t st);
+// moves the slots into `to` (S_new slots), rewrites row_ptr in place and
+// sets row_sorted of the rows it sorted; src_of: S_new, where: old slot count
+void launch_relayout_move(const RelayoutPlan& p, int32_t sort_count, int64_t S_new, SlotArrays from, SlotArrays to,
+                          int32_t* src_of, int32_t* where, int32_t* row_ptr, int32_t* row_sorted, hipStream_t st);
+
 
 // ---- host Bi-CSR builder (bicsr.cpp) -------------------------------------
 struct HostBiCSR {
@@ -200,11 +241,13 @@ mf_status build_bicsr(int32_t n, int64_t m, const int32_t* src, const int32_t* d
                       const int32_t* cap, int32_t s, int32_t t, int32_t slack_min,
                       int32_t slack_pct, HostBiCSR* out);
 
-// Re-lays rows with fresh slack: row v keeps its used slots (sorted by column
-// afterwards) and gets room for extra[v] more plus the usual slack.  Residuals
-// move with their slots.  res is updated in place alongside.
-void relayout_bicsr(const HostBiCSR& in, const std::vector<int32_t>& res_in,
-                    const std::vector<int32_t>& extra, int32_t slack_min, int32_t slack_pct,
-                    HostBiCSR* out, std::vector<int32_t>* res_out);
+// Device relayout (relayout.cpp): runs the plan, allocates the new slot
+// arrays, moves the slots and frees the old arrays; *arrays and *S_new then
+// describe the new layout and row_ptr / row_sorted (device) are rewritten.
+// On error nothing has changed (MF_ERR_OVERFLOW: more than INT32_MAX - 1
+// slots; MF_ERR_OUT_OF_MEMORY; MF_ERR_DEVICE).
+mf_status relayout_device(RelayoutPlan p, SlotArrays* arrays, int64_t S_old, int64_t* S_new, int32_t* row_ptr,
+                          int32_t* row_sorted, hipStream_t st);
+
 
 }  // namespace mf

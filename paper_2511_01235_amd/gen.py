@@ -386,3 +386,87 @@ def workload(name: str):
         return g, BatchStream(g, 31000 if W == 2048 else 31000 + W, inc_max=50, new_cap_max=100,
                               patch=P), k, 50 if W == 2048 else 5
     raise KeyError(name)
+
+
+# ----------------------------------------------------------------------------
+# serving traces
+# ----------------------------------------------------------------------------
+
+def serving_trace(streams, rate: float, count: int, seed: int, k_lo: int = 10, k_hi: int = 10_000):
+    """A request trace for the serving loop: `count` update batches with
+    exponential inter-arrival gaps at `rate` per second (a Poisson process),
+    each addressed to a graph chosen uniformly among `streams`, of size
+    log-uniform in [k_lo, k_hi] but at most half the graph's live edges, and
+    drawn from that graph's BatchStream so it follows the capacities the
+    graph's earlier batches left.  Returns (graph, arrival_s, u, v, c) tuples
+    in arrival order."""
+    rng = rng_for(seed)
+    t = 0.0
+    out = []
+    for _ in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        gi = int(rng.integers(0, len(streams)))
+        k = int(round(float(np.exp(rng.uniform(np.log(k_lo), np.log(k_hi))))))
+        live = int((streams[gi].caps > 0).sum())
+        k = max(1, min(k, live // 2))
+        u, v, c = streams[gi].next_batch(k)
+        out.append((gi, t, u, v, c))
+    return out
+
+
+
+def _serving_graph(spec):
+    """Worker for serving_workload: one graph and its batches, in order."""
+    i, scale, seed, stream_seed, ks, cap_max, edge_factor = spec
+    g = rmat(scale, edge_factor, cap_max, seed=seed, name=f"rmat{scale}_{i}")
+    st = BatchStream(g, stream_seed, inc_max=50, new_cap_max=cap_max)
+    return g, [st.next_batch(k) for k in ks]
+
+
+def serving_workload(graphs: int = 64, requests: int = 2000, seed: int = 51000, arrival_seed: int = 50000,
+                     batch_seed: int = 52000, scale_lo: int = 14, scale_hi: int = 20, edge_factor: int = 16,
+                     cap_max: int = 1000, k_lo: int = 10, k_hi: int = 10_000, workers: int = 1):
+    """Graphs and a request trace for the serving loop.
+
+    Graph i is RMAT with scale uniform in [scale_lo, scale_hi] (drawn from
+    `seed`), the given edge factor, capacities U[1, cap_max] and seed
+    seed + 1 + i.  Request j goes to a graph chosen uniformly, with batch size
+    round(exp(U[ln k_lo, ln k_hi])) capped at a quarter of the graph's edge
+    count, and a unit-rate exponential gap before it (multiply by 1/rate for a
+    Poisson process at that rate); graph, size and gap come from
+    `arrival_seed`.  The batches of graph i are drawn in request order from a
+    BatchStream seeded with batch_seed + 1000 * i, so they depend only on that
+    graph's sizes: graphs are built in `workers` processes.
+
+    Returns (graphs, requests) with requests a list of (graph, gap_s, u, v, c)
+    in arrival order."""
+    rng = rng_for(seed)
+    scales = [int(x) for x in rng.integers(scale_lo, scale_hi + 1, size=graphs)]
+    ar = rng_for(arrival_seed)
+    target = ar.integers(0, graphs, size=requests)
+    size = np.round(np.exp(ar.uniform(np.log(k_lo), np.log(k_hi), size=requests))).astype(np.int64)
+    gaps = ar.exponential(1.0, size=requests)
+    ks = [[] for _ in range(graphs)]
+    for j in range(requests):
+        ks[int(target[j])].append(j)
+    specs = [(i, scales[i], seed + 1 + i, batch_seed + 1000 * i,
+              [int(size[j]) for j in ks[i]], cap_max, edge_factor) for i in range(graphs)]
+    for sp in specs:   # at most a quarter of the generated edges
+        m_gen = edge_factor << sp[1]
+        sp[4][:] = [max(1, min(k, m_gen // 4)) for k in sp[4]]
+    if workers > 1:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            built = list(ex.map(_serving_graph, specs))
+    else:
+        built = [_serving_graph(sp) for sp in specs]
+    out_graphs = [b[0] for b in built]
+    nxt = [0] * graphs
+    reqs = []
+    for j in range(requests):
+        i = int(target[j])
+        u, v, c = built[i][1][nxt[i]]
+        nxt[i] += 1
+        reqs.append((i, float(gaps[j]), u, v, c))
+    return out_graphs, reqs

@@ -1,0 +1,157 @@
+"""Summaries of rocprofv3 output for the benchmark (kernel trace and the
+FETCH_SIZE / WRITE_SIZE counter passes), as markdown.
+
+bench.py runs, in this order: the static solves (each starts with k_reset),
+one plain 256 MiB device copy that calibrates the counters, the warm-up and
+timed update batches, then the from-scratch solves (k_reset again).  The timed
+window is therefore the dispatches after the largest copy and before the
+next k_reset; run the profiled bench with --warmup 0 so that the window holds
+exactly the timed batches.
+
+    python -m paper_2511_01235_amd.prof KT_DIR FETCH_DIR WRITE_DIR --kernel k_gr_level \\
+        --command "..." > profiles/<kernel>_<workload>.md
+
+The last line of the summary records the calibrated HBM bytes per launch of
+the kernel with the SHA-256 of the kernel source it was measured on; bench.py
+reports it as `traffic` only while the source is unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+CAL_BYTES = 256 << 20          # the calibration copy reads and writes this many bytes
+TRAFFIC_TAG = "traffic_bytes_per_launch"
+
+
+def source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def short(name: str) -> str:
+    name = name.replace("mf::(anonymous namespace)::", "").replace("void ", "")
+    return re.sub(r"\(.*", "", name)
+
+
+def _rows(path):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    return rows
+
+
+def _dur_us(r):
+    return (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+
+
+def _name(r):
+    return r.get("Kernel_Name") or r.get("Name")
+
+
+def timed_window(rows):
+    """Indices [a, b) of the timed window (see the module docstring)."""
+    copies = [i for i, r in enumerate(rows) if "copyBuffer" in _name(r)]
+    if not copies:
+        raise ValueError("no calibration copy in the trace")
+    a = max(copies, key=lambda i: _dur_us(rows[i]))
+    later = [i for i, r in enumerate(rows) if i > a and "k_reset" in _name(r)]
+    return a + 1, (later[0] if later else len(rows))
+
+
+def stats_table(path, top=14):
+    rows = list(csv.DictReader(open(path)))
+    out = ["| kernel | calls | total ms | avg us | min us | max us | % |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        out.append(f"| `{short(r['Name'])[:60]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def window_table(rows, a, b, top=10):
+    agg = {}
+    for r in rows[a:b]:
+        k = short(_name(r))
+        agg.setdefault(k, []).append(_dur_us(r))
+    out = ["| kernel | calls | total ms | avg us |", "|---|---:|---:|---:|"]
+    for k, d in sorted(agg.items(), key=lambda x: -sum(x[1]))[:top]:
+        out.append(f"| `{k[:60]}` | {len(d)} | {sum(d) / 1e3:.3f} | {np.mean(d):.2f} |")
+    return "\n".join(out), agg
+
+
+def counter_pass(path, kernel):
+    """(counter name, calibration factor, mean KiB per dispatch of `kernel`
+    in the timed window, dispatches)."""
+    rows = _rows(path)
+    name = rows[0]["Counter_Name"]
+    a, b = timed_window(rows)
+    cal = max((r for r in rows if "copyBuffer" in _name(r)), key=_dur_us)
+    factor = (CAL_BYTES / 1024) / float(cal["Counter_Value"])
+    vals = [float(r["Counter_Value"]) for r in rows[a:b] if kernel in _name(r)]
+    return name, factor, float(np.mean(vals)) if vals else 0.0, len(vals)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("kt_dir")
+    ap.add_argument("fetch_dir")
+    ap.add_argument("write_dir")
+    ap.add_argument("--kernel", default="k_gr_level")
+    ap.add_argument("--command", default="")
+    ap.add_argument("--title", default="")
+    args = ap.parse_args()
+    kt = _rows(os.path.join(args.kt_dir, "run_kernel_trace.csv"))
+    a, b = timed_window(kt)
+    wt, agg = window_table(kt, a, b)
+    mine = [d for k, d in agg.items() if args.kernel in k]
+    durs = [x for d in mine for x in d]
+    print(f"# {args.title or args.kernel}\n")
+    if args.command:
+        print("Commands (each from the repository root):\n\n```\n" + args.command.strip() + "\n```\n")
+    print("## Whole run (rocprofv3 --stats)\n")
+    print(stats_table(os.path.join(args.kt_dir, "run_kernel_stats.csv")) + "\n")
+    print("## Timed window (after the calibration copy, before the first from-scratch solve)\n")
+    print(wt + "\n")
+    print(f"`{args.kernel}` in the window: {len(durs)} launches, average {np.mean(durs):.2f} us\n")
+    total = 0.0
+    lines = []
+    for d in (args.fetch_dir, args.write_dir):
+        name, factor, kib, n = counter_pass(os.path.join(d, "run_counter_collection.csv"), args.kernel)
+        nbytes = kib * 1024 * factor
+        total += nbytes
+        lines.append(f"| {name} | {n} | {kib:.1f} | {factor:.3f} | {nbytes / 1e6:.3f} |")
+    print("## HBM traffic (counter passes, timed window)\n")
+    print("| counter | dispatches | KiB per dispatch (raw) | calibration factor | MB per dispatch |")
+    print("|---|---:|---:|---:|---:|")
+    print("\n".join(lines) + "\n")
+    print("The factor is 256 MiB divided by what the counter reads for the plain 256 MiB copy.\n")
+    print(f"{TRAFFIC_TAG}: {total:.0f} kernels.hip sha256 {source_hash()}")
+
+
+def recorded_traffic(kernel_tag: str, profiles_dir: str):
+    """Bytes per launch recorded for `kernel_tag` (a summary file name prefix)
+    if it was measured on the current kernel source, else None."""
+    if not os.path.isdir(profiles_dir):
+        return None
+    want = source_hash()
+    for fn in sorted(os.listdir(profiles_dir)):
+        if not fn.startswith(kernel_tag) or not fn.endswith(".md"):
+            continue
+        for line in open(os.path.join(profiles_dir, fn)):
+            if line.startswith(TRAFFIC_TAG):
+                parts = line.split()
+                if len(parts) >= 5 and parts[-1] == want:
+                    return float(parts[1])
+    return None
+
+
+if __name__ == "__main__":
+    main()

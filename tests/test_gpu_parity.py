@@ -273,8 +273,36 @@ def test_relayout_when_slack_runs_out():
             u, v, c = gen.random_batch(g.n, 400, 100, seed=77 + b)
             model.apply(u, v, c)
             say("relayout batch", b)
+            val = G.apply_batch(u, v, c)
+            assert val == o.apply(u, v, c)
+        assert G.stats()["relayouts"] >= 1
+        # slots, capacities and pair links survived the moves
+        es, ed, ec = G.get_edges()
+        ms, md, mc = model.arrays()
+        live = mc > 0
+        assert np.array_equal(es, ms[live]) and np.array_equal(ed, md[live]) and np.array_equal(ec, mc[live])
+        _flow_cert(G, g.n, g.s, g.t, val, model)
+
+
+def test_relayout_keeps_long_unsorted_rows():
+    """RMAT scale 16 has rows longer than the in-block sort takes: their
+    inserted tails stay unsorted after a re-layout and must still be found."""
+    g, stream, k, _ = gen.workload("rmat16")
+    model = _CapModel(g.n, g.src, g.dst, g.cap)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, insert_slack_min=1,
+                         insert_slack_pct=1) as G:
+        assert G.maxflow() == o.static()
+        for b in range(4):
+            u, v, c = stream.next_batch(4 * k)
+            model.apply(u, v, c)
+            say("long-row relayout batch", b)
             assert G.apply_batch(u, v, c) == o.apply(u, v, c)
         assert G.stats()["relayouts"] >= 1
+        es, ed, ec = G.get_edges()
+        ms, md, mc = model.arrays()
+        live = mc > 0
+        assert np.array_equal(es, ms[live]) and np.array_equal(ed, md[live]) and np.array_equal(ec, mc[live])
 
 
 # --- flow output (certificate) --------------------------------------------------
@@ -378,6 +406,25 @@ def test_batched_matches_oracle(warm):
                 batches.append(st.next_batch(k))
             want = [o.apply(*b) for o, b in zip(oracles, batches)]
             say("batched repair", rnd)
+            assert B.apply(batches).tolist() == want
+
+
+def test_batched_relayout_on_tight_slack():
+    """One free slot per row: the first batches' inserts overflow rows, the
+    pools are re-laid and the values still match the oracle."""
+    graphs = gen.batched_graphs(12, seed=77500, n_lo=500, n_hi=1e4)
+    streams = _batch_streams(graphs)
+    oracles = [oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t) for g in graphs]
+    want = [o.static() for o in oracles]
+    with mf.MaxFlowBatch(graphs, insert_slack_min=1, insert_slack_pct=1) as B:
+        assert B.maxflow().tolist() == want
+        for rnd in range(3):
+            batches = []
+            for g, st in zip(graphs, streams):
+                k = max(1, int(round(0.05 * st.keys.size)))
+                batches.append(st.next_batch(k))
+            want = [o.apply(*b) for o, b in zip(oracles, batches)]
+            say("batched tight-slack repair", rnd)
             assert B.apply(batches).tolist() == want
 
 
