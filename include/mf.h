@@ -179,7 +179,25 @@ mf_status mf_get_flow(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, i
  * number written.  Does not change the solver state. */
 mf_status mf_get_edges(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, int32_t* cap);
 
-/* Counters and sizes; see mf_stats. */
+/* Move the graph's retained state (the Bi-CSR with its residuals and
+ * capacities, excesses and heights) from device memory into pinned host
+ * memory owned by the handle, and free the device memory it held (a few
+ * hundred bytes of counters stay).  While offloaded every call except
+ * mf_graph_restore, mf_get_stats and mf_graph_free returns MF_ERR_STATE.  The
+ * host buffers are kept for the next offload and released by mf_graph_free.
+ * For callers that keep more graphs than fit in HBM: a restored graph
+ * resumes exactly where it was (Section 4's repair needs the retained state).
+ * Errors: MF_ERR_INVALID, MF_ERR_STATE (already offloaded),
+ * MF_ERR_OUT_OF_MEMORY (host buffers; nothing changed), MF_ERR_DEVICE. */
+mf_status mf_graph_offload(mf_graph* g);
+
+/* Re-allocate device memory and copy the offloaded state back.  Errors:
+ * MF_ERR_INVALID, MF_ERR_STATE (not offloaded), MF_ERR_OUT_OF_MEMORY (device
+ * memory; the graph stays offloaded, nothing lost), MF_ERR_DEVICE. */
+mf_status mf_graph_restore(mf_graph* g);
+
+/* Counters and sizes; see mf_stats (device_bytes is the counters' size while
+ * offloaded). */
 mf_status mf_get_stats(const mf_graph* g, mf_stats* out);
 
 /* Per-kernel event timing.  class_mask selects kernel classes by bit (bit c =

@@ -31,7 +31,7 @@ MF_ERR_STATE = 6
 # every symbol include/mf.h declares
 EXPORTED = ["mf_default_options", "mf_status_string", "mf_graph_load", "mf_maxflow",
             "mf_apply_batch", "mf_apply_batch_device", "mf_min_cut", "mf_get_flow", "mf_get_edges",
-            "mf_get_stats", "mf_profile", "mf_debug_initial_labels", "mf_debug_selftest",
+            "mf_graph_offload", "mf_graph_restore", "mf_get_stats", "mf_profile", "mf_debug_initial_labels", "mf_debug_selftest",
             "mf_graph_free", "mf_batch_load", "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info",
             "mf_batch_free"]
 
@@ -89,6 +89,8 @@ def lib():
         L.mf_min_cut.argtypes = [vp, vp, C.POINTER(i64)]
         L.mf_get_flow.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
         L.mf_get_edges.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
+        L.mf_graph_offload.argtypes = [vp]
+        L.mf_graph_restore.argtypes = [vp]
         L.mf_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.mf_profile.argtypes = [vp, i32]
         L.mf_debug_initial_labels.argtypes = [vp, vp, vp, vp, C.POINTER(i32)]
@@ -102,7 +104,8 @@ def lib():
         L.mf_batch_free.argtypes = [vp]
         L.mf_batch_free.restype = None
         for name in ["mf_graph_load", "mf_maxflow", "mf_apply_batch", "mf_apply_batch_device",
-                     "mf_min_cut", "mf_get_flow", "mf_get_edges", "mf_get_stats", "mf_profile",
+                     "mf_min_cut", "mf_get_flow", "mf_get_edges", "mf_graph_offload", "mf_graph_restore",
+                     "mf_get_stats", "mf_profile",
                      "mf_debug_initial_labels", "mf_debug_selftest", "mf_batch_load",
                      "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info"]:
             getattr(L, name).restype = C.c_int
@@ -225,6 +228,14 @@ def mf_get_edges(g):
     return src[:k], dst[:k], cap[:k]
 
 
+def mf_graph_offload(g):
+    _check(lib().mf_graph_offload(g), "mf_graph_offload")
+
+
+def mf_graph_restore(g):
+    _check(lib().mf_graph_restore(g), "mf_graph_restore")
+
+
 def mf_get_stats(g) -> dict:
     s = Stats()
     _check(lib().mf_get_stats(g, C.byref(s)), "mf_get_stats")
@@ -285,6 +296,12 @@ class MaxFlowGraph:
 
     def get_edges(self):
         return mf_get_edges(self.h)
+
+    def offload(self):
+        mf_graph_offload(self.h)
+
+    def restore(self):
+        mf_graph_restore(self.h)
 
     def stats(self) -> dict:
         return mf_get_stats(self.h)

@@ -69,6 +69,16 @@ struct mf_graph {
     mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0};
     int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
     int first_chunk = 8;      // BFS levels launched before the first frontier check
+    // while offloaded the state lives in these pinned host buffers (kept for
+    // the next offload) and the device holds only the counters
+    bool offloaded = false;
+    struct HostCopy {
+        int2* cr = nullptr;
+        int32_t *rev = nullptr, *cap = nullptr, *capsum = nullptr;
+        int32_t *row_ptr = nullptr, *row_len = nullptr, *row_sorted = nullptr, *h = nullptr;
+        int64_t* e = nullptr;
+        int64_t slots = 0;
+    } hc;
 };
 
 namespace {
@@ -228,6 +238,41 @@ mf_status upload_structure(mf_graph* g, const mf::HostBiCSR& b, const std::vecto
     MF_HIP(hipStreamSynchronize(st));  // host vectors die on return
     g->slot_cap = S;
     return MF_OK;
+}
+
+void free_host_copy(mf_graph* g) {
+    mf_graph::HostCopy& c = g->hc;
+    void* bufs[] = {c.cr, c.rev, c.cap, c.capsum, c.row_ptr, c.row_len, c.row_sorted, c.h, c.e};
+    for (void* p : bufs)
+        if (p) (void)hipHostFree(p);
+    c = mf_graph::HostCopy{};
+}
+
+template <class T>
+hipError_t halloc(T** p, int64_t count) {
+    return hipHostMalloc((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1), hipHostMallocDefault);
+}
+
+// Every device buffer except the counters (the state is elsewhere by then).
+void free_device_state(mf_graph* g) {
+    free_structure(g);
+    dfree(g->dg.e);
+    dfree(g->dg.h);
+    for (auto& w : g->wl) dfree(w);
+    dfree(g->need);
+    dfree(g->slot_of);
+    dfree(g->touched);
+    dfree(g->upd);
+    dfree(g->tb.key);
+    dfree(g->tb.win);
+    dfree(g->tb.slot);
+    dfree(g->side);
+    dfree(g->cut_acc);
+    dfree(g->bits.visited);
+    g->bits.fb = nullptr;
+    dfree(g->dg.bytes_part);
+    g->k_cap = 0;
+    g->tb.capacity = 0;
 }
 
 mf_status ensure_batch_capacity(mf_graph* g, int64_t k) {
@@ -405,6 +450,7 @@ mf_status warm_sweep(mf_graph* g) {
 mf_status check_handle(mf_graph* g) {
     if (!g) return MF_ERR_INVALID;
     if (g->poisoned) return MF_ERR_DEVICE;
+    if (g->offloaded) return MF_ERR_STATE;
     g->dg.count_bytes = g->prof_mask != 0;
     if (hipSetDevice(g->device) != hipSuccess) {
         g->poisoned = true;
@@ -413,8 +459,8 @@ mf_status check_handle(mf_graph* g) {
     return MF_OK;
 }
 
-// Rows ran out of slack: download the structure, re-lay rows with room for
-// need[v] more pairs plus fresh slack, upload.  Excess and heights stay.
+// Rows ran out of slack: re-lay them on the device with room for need[v]
+// more pairs plus fresh slack.  Excess and heights stay.
 mf_status relayout(mf_graph* g) {
     hipStream_t st = g->stream;
     mf::RelayoutPlan p{};
@@ -849,6 +895,78 @@ mf_status mf_get_edges(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, 
     return MF_OK;
 }
 
+mf_status mf_graph_offload(mf_graph* g) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    hipStream_t st = g->stream;
+    const int64_t S = g->slot_cap, n = g->n;
+    mf_graph::HostCopy& c = g->hc;
+    if (c.slots < S) {
+        free_host_copy(g);
+        if (halloc(&c.cr, S) || halloc(&c.rev, S) || halloc(&c.cap, S) || halloc(&c.capsum, S) ||
+            halloc(&c.row_ptr, n + 1) || halloc(&c.row_len, n) || halloc(&c.row_sorted, n) || halloc(&c.h, n) ||
+            halloc(&c.e, n)) {
+            free_host_copy(g);
+            return MF_ERR_OUT_OF_MEMORY;
+        }
+        c.slots = S;
+    }
+    MF_HIP(hipMemcpyAsync(c.cr, g->dg.cr, sizeof(int2) * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(c.rev, g->dg.rev, 4 * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(c.cap, g->dg.cap, 4 * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(c.capsum, g->dg.capsum, 4 * S, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(c.row_ptr, g->dg.row_ptr, 4 * (n + 1), hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(c.row_len, g->dg.row_len, 4 * n, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(c.row_sorted, g->dg.row_sorted, 4 * n, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(c.h, g->dg.h, 4 * n, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipMemcpyAsync(c.e, g->dg.e, 8 * n, hipMemcpyDeviceToHost, st));
+    MF_HIP(hipStreamSynchronize(st));
+    free_device_state(g);
+    g->offloaded = true;
+    return MF_OK;
+}
+
+mf_status mf_graph_restore(mf_graph* g) {
+    if (!g) return MF_ERR_INVALID;
+    if (g->poisoned) return MF_ERR_DEVICE;
+    if (!g->offloaded) return MF_ERR_STATE;
+    if (hipSetDevice(g->device) != hipSuccess) return MF_ERR_DEVICE;
+    hipStream_t st = g->stream;
+    const int64_t S = g->slot_cap, n = g->n;
+    const mf_graph::HostCopy& c = g->hc;
+    g->q_cap = n + S / mf::GR_CHUNK + 64;
+    if (dalloc(g, &g->dg.row_ptr, n + 1) || dalloc(g, &g->dg.row_len, n) || dalloc(g, &g->dg.row_sorted, n) ||
+        dalloc(g, &g->dg.cr, S) || dalloc(g, &g->dg.rev, S) || dalloc(g, &g->dg.cap, S) ||
+        dalloc(g, &g->dg.capsum, S) || dalloc(g, &g->win, S) || dalloc(g, &g->q[0], g->q_cap) ||
+        dalloc(g, &g->q[1], g->q_cap) || dalloc(g, &g->dg.e, n) || dalloc(g, &g->dg.h, n) ||
+        dalloc(g, &g->wl[0], n) || dalloc(g, &g->wl[1], n) || dalloc(g, &g->wl[2], n) || dalloc(g, &g->need, n) ||
+        dalloc(g, &g->side, n) || dalloc(g, &g->cut_acc, 1) ||
+        dalloc(g, &g->bits.visited, 4 * (int64_t)g->bits.nwords) ||
+        dalloc(g, &g->dg.bytes_part, (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS)) {
+        free_device_state(g);
+        return MF_ERR_OUT_OF_MEMORY;  // still offloaded, state intact on the host
+    }
+    g->bits.fb = g->bits.visited + g->bits.nwords;
+    MF_HIP(hipMemcpyAsync(g->dg.cr, c.cr, sizeof(int2) * S, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.rev, c.rev, 4 * S, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.cap, c.cap, 4 * S, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.capsum, c.capsum, 4 * S, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.row_ptr, c.row_ptr, 4 * (n + 1), hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.row_len, c.row_len, 4 * n, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.row_sorted, c.row_sorted, 4 * n, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.h, c.h, 4 * n, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(g->dg.e, c.e, 8 * n, hipMemcpyHostToDevice, st));
+    mf::launch_fill_i32(g->win, -1, S, st);
+    mf::launch_fill_i32(g->need, 0, n, st);
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->dg.bytes_part), 0,
+                        2 * (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS, st);
+    mf::launch_clear_counters(g->ctr, st);
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipStreamSynchronize(st));
+    g->offloaded = false;
+    return MF_OK;
+}
+
 mf_status mf_get_stats(const mf_graph* g, mf_stats* out) {
     if (!g || !out) return MF_ERR_INVALID;
     std::memset(out, 0, sizeof(*out));
@@ -857,8 +975,10 @@ mf_status mf_get_stats(const mf_graph* g, mf_stats* out) {
     out->slot_capacity = g->slot_cap;
     out->slots = g->dg.used_slots;
     // slot arrays (col+res, rev, cap, capsum, win), two frontier queues, per-vertex arrays
-    out->device_bytes = g->slot_cap * 24 + 2 * g->q_cap * 8 + (int64_t)g->n * (4 * 3 + 8 + 4 + 12 + 4 + 1) +
-                        g->k_cap * (4 + 4 + 12) + (int64_t)g->tb.capacity * (8 + 8 + 8);
+    out->device_bytes = g->offloaded ? (int64_t)sizeof(DevCounters)
+                                     : g->slot_cap * 24 + 2 * g->q_cap * 8 +
+                                           (int64_t)g->n * (4 * 3 + 8 + 4 + 12 + 4 + 1) +
+                                           g->k_cap * (4 + 4 + 12) + (int64_t)g->tb.capacity * (8 + 8 + 8);
     out->kernel_cycles = g->kc;
     out->relayouts = g->relayouts;
     out->last_iterations = g->last_iterations;
@@ -932,6 +1052,7 @@ void mf_graph_free(mf_graph* g) {
     (void)hipSetDevice(g->device);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     free_all(g);
+    free_host_copy(g);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }

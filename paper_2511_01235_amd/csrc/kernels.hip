@@ -709,9 +709,12 @@ __device__ __forceinline__ void scan_group(const DevGraph& g, int b, int end, un
 }
 
 constexpr int PR_UNROLL = 4;
+constexpr int PR_UNROLL_BLOCK = 8;   // rows above the wave bin: more loads in flight per lane
 
 // Per-vertex bodies of Algorithm 2; each returns the algorithmic bytes it
-// moved.  Thread: one lane owns u.  Wave: u is wave-uniform.  Block: u is
+// moved.  A relabel is followed by the push of the next cycle on the same
+// scan (the lowest neighbour it found is now admissible), two of the KC
+// cycles for one scan of the row.  Thread: one lane owns u.  Wave: u is wave-uniform.  Block: u is
 // block-uniform and the whole block scans its row.
 template <bool PULL>
 __device__ __forceinline__ unsigned long long pr_thread_item(DevGraph& g, int u, int kc) {
@@ -733,14 +736,14 @@ __device__ __forceinline__ unsigned long long pr_thread_item(DevGraph& g, int u,
         }
         int bh = (int)(best >> 32);
         int bj = (int)(unsigned)best;
-        if (hu > bh) {
-            do_push<PULL>(g, u, bj, eu);
-            bytes += 48;
-        } else {
+        if (hu <= bh) {
             hu = bh + 1 < N ? bh + 1 : N;
             g.h[u] = hu;
             bytes += 4;
+            if (hu >= N || ++c >= kc) break;
         }
+        do_push<PULL>(g, u, bj, eu);
+        bytes += 48;
     }
     return bytes;
 }
@@ -768,14 +771,14 @@ __device__ __forceinline__ unsigned long long pr_wave_item(DevGraph& g, int u, i
         }
         int bh = (int)(best >> 32);
         int bj = (int)(unsigned)best;
-        if (hu > bh) {
-            if (lane == 0) do_push<PULL>(g, u, bj, eu);
-            bytes += 48;
-        } else {
+        if (hu <= bh) {
             hu = bh + 1 < N ? bh + 1 : N;
             if (lane == 0) g.h[u] = hu;
             bytes += 4;
+            if (hu >= N || ++c >= kc) break;
         }
+        if (lane == 0) do_push<PULL>(g, u, bj, eu);
+        bytes += 48;
     }
     return bytes;
 }
@@ -798,8 +801,8 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
         __syncthreads();
         if (eu <= 0) continue;
         unsigned long long best = ~0ull;
-        for (int b = beg; b < end; b += PR_UNROLL * BS)
-            scan_group<PULL, PR_UNROLL, BS>(g, b + threadIdx.x, end, best);
+        for (int b = beg; b < end; b += PR_UNROLL_BLOCK * BS)
+            scan_group<PULL, PR_UNROLL_BLOCK, BS>(g, b + threadIdx.x, end, best);
         best = wave_min_u64(best);
         if (lane == 0) part[wv] = best;
         __syncthreads();
@@ -814,14 +817,14 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
         }
         int bh = (int)(best >> 32);
         int bj = (int)(unsigned)best;
-        if (hu > bh) {
-            if (threadIdx.x == 0) do_push<PULL>(g, u, bj, eu);
-            bytes += 48;
-        } else {
+        if (hu <= bh) {
             hu = bh + 1 < N ? bh + 1 : N;
             if (threadIdx.x == 0) g.h[u] = hu;
             bytes += 4;
+            if (hu >= N || ++c >= kc) break;
         }
+        if (threadIdx.x == 0) do_push<PULL>(g, u, bj, eu);
+        bytes += 48;
     }
     __syncthreads();  // part / e_sh are reused by the next item
     return bytes;
@@ -864,24 +867,37 @@ __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t
 // residual moves to v regardless of e(u), so e(u) may turn negative.
 
 // Slots sub, sub + GROUP, ... of u's row; returns the amount that left u
-// (the caller subtracts it from e(u)) and adds its bytes to *bytes.
+// (the caller subtracts it from e(u)) and adds its bytes to *bytes.  RIE_UNROLL
+// slot loads per lane are issued before their height gathers.
+constexpr int RIE_UNROLL = 4;
+
 template <int GROUP>
 __device__ __forceinline__ long long rie_item(DevGraph& g, int u, int sub, unsigned long long* bytes) {
     int beg = g.row_ptr[u];
     int end = beg + g.row_len[u];
     int hu = g.h[u];
     long long moved = 0;
-    for (int j = beg + sub; j < end; j += GROUP) {
-        if (ld_res(g.cr, j) > 0) {
-            int v = g.cr[j].x;
-            if (hu > g.h[v] + 1) {
-                int32_t x = xchg_res(g.cr, j, 0);
-                if (x > 0) {
-                    add_res(g.cr, g.rev[j], x);
-                    add_e(g.e, v, x);
-                    moved += x;
-                    *bytes += 32;
-                }
+    for (int j0 = beg + sub; j0 < end; j0 += GROUP * RIE_UNROLL) {
+        unsigned long long sv[RIE_UNROLL];
+#pragma unroll
+        for (int q = 0; q < RIE_UNROLL; ++q) {
+            int j = j0 + q * GROUP;
+            sv[q] = j < end ? ld_slot(g.cr, j) : 0ull;
+        }
+        int hv[RIE_UNROLL];
+#pragma unroll
+        for (int q = 0; q < RIE_UNROLL; ++q)
+            hv[q] = (int32_t)(sv[q] >> 32) > 0 ? g.h[(int)(unsigned)sv[q]] : INT_MAX;
+#pragma unroll
+        for (int q = 0; q < RIE_UNROLL; ++q) {
+            if (hv[q] == INT_MAX || hu <= hv[q] + 1) continue;
+            int j = j0 + q * GROUP;
+            int32_t x = xchg_res(g.cr, j, 0);
+            if (x > 0) {
+                add_res(g.cr, g.rev[j], x);
+                add_e(g.e, (int)(unsigned)sv[q], x);
+                moved += x;
+                *bytes += 32;
             }
         }
     }

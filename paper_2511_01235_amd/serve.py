@@ -10,10 +10,13 @@ every answer equals that of applying the graph's batches one after another.
 
 A graph is resident while its handle holds device memory.  Admission keeps the
 device bytes of the resident graphs within an HBM budget by evicting the
-least recently used idle graph: its current capacities are read back
-(mf_get_edges) and the handle is freed.  Re-admission loads those
-capacities and solves from zero flow, which reaches the same maximum flow
-value as the evicted state, before the waiting batch is applied.
+least recently used idle graph.  By default eviction offloads the graph's
+retained state to pinned host memory (mf_graph_offload) and re-admission
+copies it back (mf_graph_restore), so the repair resumes exactly where it
+stopped.  With evict="rebuild" the graph's current capacities are read back
+(mf_get_edges), the handle is freed, and re-admission loads those
+capacities and solves from zero flow (the same maximum flow value), which
+needs no host copy of the state but costs a full solve.
 
 Every step of the computation runs in the HIP library behind the C ABI; this
 module only schedules calls into it (ctypes drops the GIL for the length of
@@ -51,6 +54,7 @@ class _Graph:
     t: int
     edges: tuple                   # (src, dst, cap) while not resident
     handle: object = None
+    resident: bool = False         # handle holds device memory
     device_bytes: int = 0
     busy: bool = False
     last_use: float = 0.0
@@ -72,13 +76,18 @@ class Server:
     stats()["device_bytes"] and close(); the default builds a MaxFlowGraph with
     `options`."""
 
-    def __init__(self, graphs, hbm_budget: int, slots: int = 4, factory=None, **options):
+    def __init__(self, graphs, hbm_budget: int, slots: int = 4, factory=None, evict: str = "offload",
+                 **options):
         if factory is None:
             from . import MaxFlowGraph
 
             def factory(n, src, dst, cap, s, t):
                 return MaxFlowGraph(n, src, dst, cap, s, t, **options)
+        if evict not in ("offload", "rebuild"):
+            raise ValueError("evict must be 'offload' or 'rebuild'")
         self.factory = factory
+        self.evict = evict
+        self.restores = 0
         self.budget = int(hbm_budget)
         self.slots = int(slots)
         self.g = [_Graph(int(x.n), int(x.s), int(x.t), (x.src, x.dst, x.cap)) for x in graphs]
@@ -96,10 +105,12 @@ class Server:
     # -- accounting (lock held) -------------------------------------------------
     def _need(self, gi: int) -> int:
         x = self.g[gi]
-        return x.device_bytes or estimate_device_bytes(x.n, int(np.asarray(x.edges[0]).size))
+        if x.device_bytes:
+            return x.device_bytes
+        return estimate_device_bytes(x.n, int(np.asarray(x.edges[0]).size))
 
     def _idle_resident(self, exclude: int):
-        return [i for i, x in enumerate(self.g) if x.handle is not None and not x.busy and i != exclude]
+        return [i for i, x in enumerate(self.g) if x.resident and not x.busy and i != exclude]
 
     def _committed(self) -> int:
         """Bytes that resident graphs hold or loads have reserved, less what
@@ -125,10 +136,14 @@ class Server:
         capacities, free their device memory, then account for it."""
         for v in victims:
             x = self.g[v]
-            edges = x.handle.get_edges()
-            x.handle.close()
+            if self.evict == "offload":
+                x.handle.offload()
+                edges, handle = x.edges, x.handle
+            else:
+                edges, handle = x.handle.get_edges(), None
+                x.handle.close()
             with self.cv:
-                x.edges, x.handle = edges, None
+                x.edges, x.handle, x.resident = edges, handle, False
                 self.resident_bytes -= x.device_bytes
                 self.releasing -= x.device_bytes
                 self.evictions += 1
@@ -142,7 +157,7 @@ class Server:
         self._release([gi])
 
     def _admissible(self, gi: int) -> bool:
-        if self.g[gi].handle is not None:
+        if self.g[gi].resident:
             return True
         free = self.budget - self._committed()
         evictable = sum(self.g[i].device_bytes for i in self._idle_resident(gi))
@@ -178,14 +193,18 @@ class Server:
                 x.busy = True
                 x.pending.popleft()
                 reserved, victims = 0, []
-                if x.handle is None:
+                if not x.resident:
                     reserved = self._need(r.graph)
                     victims = self._claim(r.graph, reserved)
                     self.reserved += reserved
             try:
                 # device memory is given back before this graph takes its share
                 self._release(victims)
-                if reserved:
+                restored = False
+                if reserved and x.handle is not None:
+                    x.handle.restore()
+                    h, dev_bytes, restored = x.handle, x.device_bytes, True
+                elif reserved:
                     h = self.factory(x.n, *x.edges, x.s, x.t)
                     h.maxflow()
                     dev_bytes = int(h.stats()["device_bytes"])
@@ -200,10 +219,13 @@ class Server:
                 return
             with self.cv:
                 if reserved:
-                    x.handle = h
-                    x.edges = None
+                    x.handle, x.resident = h, True
                     x.device_bytes = dev_bytes
-                    x.loads += 1
+                    if restored:
+                        self.restores += 1
+                    else:
+                        x.edges = None
+                        x.loads += 1
                     self.reserved -= reserved
                     self.resident_bytes += dev_bytes
                 self.peak_bytes = max(self.peak_bytes, self.resident_bytes)
@@ -242,18 +264,16 @@ class Server:
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "service_mean_ms": float(svc.mean()),
                 "span_s": span, "evictions": self.evictions,
-                "loads": sum(x.loads for x in self.g), "peak_resident_bytes": self.peak_bytes}
+                "loads": sum(x.loads for x in self.g), "restores": self.restores,
+                "peak_resident_bytes": self.peak_bytes}
 
     def preload(self, threads: int = 8):
-        """Make graphs resident in index order while the budget allows (not
-        timed by run); loads run in `threads` host threads."""
+        """Load every graph before run (not timed) and solve it, in groups
+        that fit the free budget, `threads` loads at a time.  With offload
+        eviction every graph ends up loaded (the earlier ones offloaded to host
+        memory as later ones need the room); with rebuild eviction loading
+        stops when the budget is full.  Returns the number of graphs loaded."""
         import concurrent.futures as cf
-        picked, used = [], 0
-        for gi in range(len(self.g)):
-            need = self._need(gi)
-            if self.g[gi].handle is None and used + need <= self.budget:
-                picked.append(gi)
-                used += need
 
         def load(gi):
             x = self.g[gi]
@@ -261,15 +281,33 @@ class Server:
             h.maxflow()
             return gi, h, int(h.stats()["device_bytes"])
 
+        pending = [gi for gi, x in enumerate(self.g) if x.handle is None]
+        loaded, order = 0, []
         with cf.ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
-            for gi, h, nbytes in ex.map(load, picked):
-                x = self.g[gi]
-                x.handle, x.edges, x.device_bytes = h, None, nbytes
-                self.resident_bytes += nbytes
-        while self.resident_bytes > self.budget and self._idle_resident(-1):
-            self._evict(max(self._idle_resident(-1)))
+            while pending:
+                free = self.budget - self.resident_bytes
+                group, room = [], free
+                for gi in pending:
+                    if self._need(gi) <= room:
+                        group.append(gi)
+                        room -= self._need(gi)
+                if not group:
+                    if self.evict != "offload" or not order:
+                        break
+                    self._evict(order.pop(0))
+                    continue
+                for gi, h, nbytes in ex.map(load, group):
+                    x = self.g[gi]
+                    x.handle, x.resident, x.edges, x.device_bytes = h, True, None, nbytes
+                    self.resident_bytes += nbytes
+                    order.append(gi)
+                    loaded += 1
+                pending = [gi for gi in pending if gi not in set(group)]
+                while self.resident_bytes > self.budget and order:
+                    self._evict(order.pop(0))
         self.peak_bytes = max(self.peak_bytes, self.resident_bytes)
-        return len(picked)
+        self.evictions = 0
+        return loaded
 
     def close(self):
         for x in self.g:

@@ -305,6 +305,35 @@ def test_relayout_keeps_long_unsorted_rows():
         assert np.array_equal(es, ms[live]) and np.array_equal(ed, md[live]) and np.array_equal(ec, mc[live])
 
 
+def test_offload_restore_resumes_exactly():
+    """Offload the retained state to host memory and back between batches
+    (also across a re-layout that grows the slot arrays): every value still
+    matches the oracle and calls on an offloaded handle are refused."""
+    g, stream, k, _ = gen.workload("rmat12")
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, insert_slack_min=1,
+                         insert_slack_pct=1) as G:
+        assert G.maxflow() == o.static()
+        full = G.stats()["device_bytes"]
+        for b in range(4):
+            G.offload()
+            assert G.stats()["device_bytes"] < full // 100
+            with pytest.raises(mf.MFError) as ei:
+                G.apply_batch(np.array([0]), np.array([1]), np.array([1]))
+            assert ei.value.status == mf.MF_ERR_STATE
+            with pytest.raises(mf.MFError) as ei:
+                G.offload()
+            assert ei.value.status == mf.MF_ERR_STATE
+            G.restore()
+            u, v, c = stream.next_batch(4 * k)
+            say("offload/restore batch", b)
+            assert G.apply_batch(u, v, c) == o.apply(u, v, c)
+        assert G.stats()["relayouts"] >= 1
+        with pytest.raises(mf.MFError) as ei:
+            G.restore()
+        assert ei.value.status == mf.MF_ERR_STATE
+
+
 # --- flow output (certificate) --------------------------------------------------
 
 def _flow_cert(G, n, s, t, value, model):

@@ -28,12 +28,21 @@ class OracleHandle:
         self.o = oracle.DynOracle(n, src, dst, cap, s, t)
         self.n = n
         self.closed = False
+        self.offloaded = False
+
+    def offload(self):
+        assert not self.offloaded
+        self.offloaded = True
+
+    def restore(self):
+        assert self.offloaded
+        self.offloaded = False
 
     def maxflow(self):
         return self.o.static()
 
     def apply_batch(self, u, v, c):
-        assert not self.closed
+        assert not self.closed and not self.offloaded
         time.sleep(0.002)
         for a, b, x in zip(u.tolist(), v.tolist(), c.tolist()):
             self.caps[(a, b)] = x
@@ -89,32 +98,40 @@ def _check_order(server):
             assert a.done <= b.start, "a graph's requests overlapped or ran out of order"
 
 
+@pytest.mark.parametrize("evict", ["offload", "rebuild"])
 @pytest.mark.parametrize("slots,budget_graphs", [(1, 2), (3, 2), (4, 100)])
-def test_serving_matches_sequential_oracle(slots, budget_graphs):
+def test_serving_matches_sequential_oracle(slots, budget_graphs, evict):
     graphs = _fleet(6, 7100)
     trace = _trace(graphs, 7200, count=50, rate=2000.0, k_hi=40)
     want = _expected(graphs, trace)
     biggest = max(estimate_device_bytes(g.n, g.m) for g in graphs)
     budget = budget_graphs * biggest + biggest // 2
-    with Server(graphs, budget, slots=slots, factory=OracleHandle) as srv:
+    with Server(graphs, budget, slots=slots, factory=OracleHandle, evict=evict) as srv:
         res = srv.run(trace)
         got = [r.value for r in srv.requests]
         assert got == want
         _check_order(srv)
         assert res["peak_resident_bytes"] <= budget
+        touched = len({t[0] for t in trace})
         if budget_graphs < len(graphs):
-            assert res["evictions"] > 0 and res["loads"] > len(graphs)
+            assert res["evictions"] > 0
+            if evict == "offload":
+                assert res["loads"] == touched and res["restores"] > 0
+            else:
+                assert res["loads"] > touched and res["restores"] == 0
         else:
-            assert res["evictions"] == 0 and res["loads"] == len({t[0] for t in trace})
+            assert res["evictions"] == 0 and res["loads"] == touched
 
 
-def test_serving_after_preload():
+@pytest.mark.parametrize("evict", ["offload", "rebuild"])
+def test_serving_after_preload(evict):
     graphs = _fleet(5, 7050)
     trace = _trace(graphs, 7060, count=30, rate=3000.0, k_hi=30)
     want = _expected(graphs, trace)
     biggest = max(estimate_device_bytes(g.n, g.m) for g in graphs)
-    with Server(graphs, 2 * biggest, slots=3, factory=OracleHandle) as srv:
-        assert srv.preload(threads=2) >= 1
+    with Server(graphs, 2 * biggest, slots=3, factory=OracleHandle, evict=evict) as srv:
+        loaded = srv.preload(threads=2)
+        assert loaded == len(graphs) if evict == "offload" else 1 <= loaded < len(graphs)
         assert srv.resident_bytes <= srv.budget
         res = srv.run(trace)
         assert [r.value for r in srv.requests] == want
@@ -146,7 +163,8 @@ def test_serving_surfaces_errors():
 
 
 @pytest.mark.gpu
-def test_serving_gpu_matches_oracle():
+@pytest.mark.parametrize("evict", ["offload", "rebuild"])
+def test_serving_gpu_matches_oracle(evict):
     import torch
     assert torch.cuda.is_available()
     graphs = gen.batched_graphs(8, seed=7700, n_lo=500, n_hi=20000, degree=8)
@@ -155,7 +173,7 @@ def test_serving_gpu_matches_oracle():
     sizes = sorted(estimate_device_bytes(g.n, g.m) for g in graphs)
     budget = sum(sizes[-3:])          # room for about three graphs at a time
     print("[gpu] serving", len(graphs), "graphs", len(trace), "requests budget", budget, flush=True)
-    with Server(graphs, budget, slots=4) as srv:
+    with Server(graphs, budget, slots=4, evict=evict) as srv:
         res = srv.run(trace)
         print("[gpu] serving", res, flush=True)
         assert [r.value for r in srv.requests] == want
