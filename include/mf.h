@@ -101,6 +101,7 @@ typedef struct mf_stats {
     /* algorithmic bytes the kernels of each class had to move over the same calls,
      * from device-side counters (Bi-CSR slots and vertex words actually visited) */
     double kernel_bytes[8];
+    int64_t last_rounds;       /* push-relabel rounds of the last call (one or more per global relabel) */
 } mf_stats;
 
 /* Fill *opt with the defaults. */

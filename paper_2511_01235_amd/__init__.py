@@ -59,7 +59,8 @@ class Stats(C.Structure):
                 ("last_iterations", C.c_int64), ("last_bfs_levels", C.c_int64),
                 ("last_active_sum", C.c_int64), ("last_new_pairs", C.c_int64),
                 ("last_ms", C.c_double), ("kernel_ms", C.c_double * 8),
-                ("kernel_launches", C.c_int64 * 8), ("kernel_bytes", C.c_double * 8)]
+                ("kernel_launches", C.c_int64 * 8), ("kernel_bytes", C.c_double * 8),
+                ("last_rounds", C.c_int64)]
 
 
 class Update(C.Structure):

@@ -56,7 +56,7 @@ struct mf_graph {
     int64_t last_value = 0;
     // stats
     int32_t relayouts = 0;
-    int64_t last_iterations = 0, last_levels = 0, last_active_sum = 0, last_new_pairs = 0;
+    int64_t last_iterations = 0, last_levels = 0, last_active_sum = 0, last_new_pairs = 0, last_rounds = 0;
     double last_ms = 0;
     uint32_t prof_mask = 0;
     double kernel_ms[8] = {0};
@@ -66,9 +66,11 @@ struct mf_graph {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
     int gr_grid = 1024;
     mf::GrBits bits{};
-    mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0};
+    mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0};
     int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
     int first_chunk = 8;      // BFS levels launched before the first frontier check
+    int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
+    int32_t round_max = 4096; // ... at most this many
     // while offloaded the state lives in these pinned host buffers (kept for
     // the next offload) and the device holds only the counters
     bool offloaded = false;
@@ -386,13 +388,37 @@ mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) 
     return read_counters(g);
 }
 
-// Loop {global relabel; worklist; stop if no active vertex; push-relabel;
-// remove invalid edges}.  The stop test is taken right after a fresh global
+// Loop {global relabel; worklist; stop if no active vertex; R rounds of
+// push-relabel, remove invalid edges and worklist on the current heights}.
+// The stop test that ends the loop is taken right after a fresh global
 // relabel, so at exit A = {h = |V|} is a cut whose capacity is the value.
+// Between relabels the heights stay a valid labelling (push-relabel lifts by
+// the lowest neighbour + 1, remove-invalid-edges saturates every steep
+// residual slot), so further rounds need no relabel; a vertex activated by a
+// push waits for the next worklist, so each round moves excess about one
+// more hop.  R is the relabel's depth divided by round_div (at least 1): a
+// deep BFS (long augmenting paths) buys many cheap rounds, a shallow one
+// keeps the paper's one sweep per relabel.
+mf_status push_round(mf_graph* g, const LoopMode& m, const int cnt[3]) {
+    hipStream_t st = g->stream;
+    for (int b = 0; b < 3; ++b)
+        if (cnt[b])
+            timed(g, mf::KC_PR, [&] {
+                mf::launch_push_relabel(m.dg, g->wl[b], cnt[b], b, g->kc, m.pull, g->ctr, st);
+            });
+    if (m.rie)
+        for (int b = 0; b < 3; ++b)
+            if (cnt[b])
+                timed(g, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, g->wl[b], cnt[b], b, g->ctr, st); });
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
 mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     hipStream_t st = g->stream;
-    int64_t iters = 0, levels = 0, active_sum = 0;
+    int64_t iters = 0, levels = 0, active_sum = 0, rounds = 0;
     for (;;) {
+        const int64_t levels_before = levels;
         mf_status rc = relabel_and_worklist(g, m, &levels);
         if (rc != MF_OK) return rc;
         const DevCounters& c = *g->ctr_h;
@@ -406,21 +432,32 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             g->last_iterations = iters;
             return MF_ERR_NOT_CONVERGED;
         }
+        const int64_t depth = levels - levels_before;
+        const int64_t R = std::min<int64_t>(g->round_max, std::max<int64_t>(1, depth / g->round_div));
         int cnt[3] = {c.wl[0], c.wl[1], c.wl[2]};
-        for (int b = 0; b < 3; ++b)
-            if (cnt[b])
-                timed(g, mf::KC_PR, [&] {
-                    mf::launch_push_relabel(m.dg, g->wl[b], cnt[b], b, g->kc, m.pull, g->ctr, st);
-                });
-        if (m.rie)
-            for (int b = 0; b < 3; ++b)
-                if (cnt[b])
-                    timed(g, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, g->wl[b], cnt[b], b, g->ctr, st); });
-        MF_HIP(hipGetLastError());
+        for (int64_t r = 0;; ++r) {
+            rc = push_round(g, m, cnt);
+            if (rc != MF_OK) return rc;
+            ++rounds;
+            if (r + 1 >= R) break;
+            mf::launch_zero_loop_counters(g->ctr, st);
+            timed(g, mf::KC_WL, [&] {
+                mf::launch_build_worklist(m.dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, m.topology, m.sign, st);
+            });
+            MF_HIP(hipGetLastError());
+            rc = read_counters(g);
+            if (rc != MF_OK) return rc;
+            if (c.wl[3] == 0) break;  // certified by the next relabel
+            active_sum += c.wl[3];
+            cnt[0] = c.wl[0];
+            cnt[1] = c.wl[1];
+            cnt[2] = c.wl[2];
+        }
     }
     g->last_iterations = iters;
     g->last_levels = levels;
     g->last_active_sum = active_sum;
+    g->last_rounds = rounds;
     return MF_OK;
 }
 
@@ -639,10 +676,13 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     if (const char* env = std::getenv("MF_GR_BU_ALPHA")) g->tune.bu_alpha = std::atoi(env);
     if (const char* env = std::getenv("MF_GR_BU_BETA")) g->tune.bu_beta = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_GR_STAGE_MIN")) g->tune.stage_min = std::atoi(env);
+    if (const char* env = std::getenv("MF_GR_BU_LB")) g->tune.bu_lb = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_GR_LDS"))
         if (std::atoi(env) != 0) g->tune.lds = mf::gr_level_lds_bytes(g->bits.nwords, dev) > 0 ? 1 : 0;
     if (const char* env = std::getenv("MF_GR_GRID")) g->gr_grid = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_GR_FIRST_CHUNK")) g->first_chunk = std::max(1, std::atoi(env));
+    if (const char* env = std::getenv("MF_ROUND_DIV")) g->round_div = std::max(1, std::atoi(env));
+    if (const char* env = std::getenv("MF_ROUND_MAX")) g->round_max = std::max(1, std::atoi(env));
     if (o.relabel_mode == 1) g->persistent_grid = mf::persistent_gr_grid(dev);
     g->dg.n = n;
     g->dg.s = s;
@@ -985,6 +1025,7 @@ mf_status mf_get_stats(const mf_graph* g, mf_stats* out) {
     out->last_bfs_levels = g->last_levels;
     out->last_active_sum = g->last_active_sum;
     out->last_new_pairs = g->last_new_pairs;
+    out->last_rounds = g->last_rounds;
     out->last_ms = g->last_ms;
     for (int c = 0; c < 8; ++c) {
         out->kernel_ms[c] = g->kernel_ms[c];

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <climits>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -30,12 +31,13 @@ struct mf_batch {
     bool own_stream = false;
     int32_t G = 0;
     mf_options opt{};
-    mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0};
+    mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0};
     std::vector<int32_t> n, kc;
     std::vector<int64_t> vbase, rpbase, sbase, slots, bbase, qbase, used;
     std::vector<int32_t> s_h, t_h;
     int32_t slack_min = 2, slack_pct = 12;
     int32_t relayouts = 0;
+    int32_t round_div = 8;
     int64_t total_v = 0, total_rp = 0, total_s = 0, total_b = 0, total_q = 0;
     // pools
     int32_t *row_ptr = nullptr, *row_len = nullptr, *row_sorted = nullptr;
@@ -221,6 +223,7 @@ mf_status upload_views(mf_batch* b) {
         S.ctr = b->ctr + i;
         S.kc = b->kc[i];
         S.warm = b->opt.cold_start ? 0 : 1;
+        S.round_div = b->round_div;
         S.max_iter = b->opt.max_iterations > 0 ? b->opt.max_iterations : 4 * (int64_t)ni + 1000;
     }
     std::vector<int32_t> order((size_t)G);
@@ -350,6 +353,7 @@ mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edg
     const int G = num_graphs;
     b->slack_min = slack_min;
     b->slack_pct = slack_pct;
+    if (const char* env = std::getenv("MF_ROUND_DIV")) b->round_div = std::max(1, std::atoi(env));
     b->s_h.assign(s, s + G);
     b->t_h.assign(t, t + G);
     b->n.resize(G); b->kc.resize(G); b->vbase.resize(G); b->rpbase.resize(G); b->sbase.resize(G);

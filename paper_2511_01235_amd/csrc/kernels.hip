@@ -125,6 +125,18 @@ __device__ __forceinline__ int wave_excl_scan(int x, int* total) {
     return v - x;
 }
 
+__device__ __forceinline__ long long wave_excl_scan64(long long x, long long* total) {
+    int lane = lane_id();
+    long long v = x;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        long long y = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += y;
+    }
+    *total = __shfl(v, WAVE - 1, WAVE);
+    return v - x;
+}
+
 // Append one item per lane with pred set to list[*counter ...] using one
 // atomic per wave (ballot + lane rank).  Must be called by the whole wave.
 __device__ __forceinline__ void wave_append(bool pred, int32_t item, int32_t* list, int32_t* counter) {
@@ -308,11 +320,37 @@ template <bool FWD, int BS>
 __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, int lv, int cnt,
                                               const int2* qin,
                                               int2* qout, DevCounters* ctr, const GrBits& bits,
-                                              bool bu, const unsigned* s_bm) {
+                                              bool bu, bool bu_lb, const unsigned* s_bm) {
     __shared__ int s_u[BS];
     __shared__ int s_beg[BS];
     __shared__ int s_pre[BS + 1];
     __shared__ int s_wsum[BS / WAVE];
+    // exclusive prefix sum of len over the block into s_pre[0..BS], total in s_pre[BS]
+    auto block_prefix = [&](int len) {
+        int wtot;
+        int wex = wave_excl_scan(len, &wtot);
+        if (lane_id() == 0) s_wsum[threadIdx.x / WAVE] = wtot;
+        __syncthreads();
+        int woff = 0, total = 0;
+        for (int w = 0; w < BS / WAVE; ++w) {
+            if (w < (int)threadIdx.x / WAVE) woff += s_wsum[w];
+            total += s_wsum[w];
+        }
+        s_pre[threadIdx.x] = woff + wex;
+        if (threadIdx.x == BS - 1) s_pre[BS] = total;
+        __syncthreads();
+        return s_pre[BS];
+    };
+    // last staged entry k with s_pre[k] <= i
+    auto owner = [&](int i) {
+        int lo = 0, hi = BS;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (s_pre[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        return lo;
+    };
     const int N = g.n;
     unsigned long long* out_cnt = &ctr->front[(lv + 1) % 3];
     const int tid = threadIdx.x;
@@ -324,7 +362,55 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
     const unsigned* bm_level = s_bm ? s_bm : cur_fb;
     auto at_level = [&](int c) { return bit_of(bm_level, c); };
     const unsigned* bm_seen = s_bm ? s_bm : bits.visited;
-    if (bu) {
+    if (bu && bu_lb) {
+        // bottom-up, slot-parallel: the block stages BS consecutive vertices,
+        // prefix-sums the row lengths of the unlabelled ones and streams
+        // their slots with consecutive threads on consecutive slots; a hit
+        // flags the row in LDS
+        __shared__ int s_hit[BS];
+        for (int base = P.bid * BS; base < N; base += P.nb * BS) {
+            const int v = base + tid;
+            int len = 0;
+            if (v < N && !bit_of(bits.visited, v)) {
+                len = g.row_len[v];
+                s_beg[tid] = g.row_ptr[v];
+                exam += 2;
+            }
+            s_hit[tid] = 0;
+            const int total = block_prefix(len);
+            for (int b0 = 0; b0 < total; b0 += BS) {
+                const int i = b0 + tid;
+                if (i < total) {
+                    const int k = owner(i);
+                    if (!s_hit[k]) {
+                        const int j = s_beg[k] + (i - s_pre[k]);
+                        const int2 c = g.cr[j];
+                        const int32_t r = FWD ? g.capsum[j] - c.y : c.y;
+                        if (r > 0 && at_level(c.x)) s_hit[k] = 1;
+                        scanned++;
+                    }
+                }
+            }
+            __syncthreads();
+            int add = 0, slots = 0;
+            if (s_hit[tid]) {
+                g.h[v] = lv + 1;
+                add = (len + GR_CHUNK - 1) / GR_CHUNK;
+                slots = len;
+                found++;
+            }
+            {
+                unsigned long long m = __ballot(add > 0);
+                unsigned half = lane < 32 ? (unsigned)m : (unsigned)(m >> 32);
+                if ((lane & 31) == 0 && half && v < N) {
+                    atomicOr(&bits.visited[v >> 5], half);
+                    atomicOr(&bits.fb[(size_t)((lv + 1) % 3) * bits.nwords + (v >> 5)], half);
+                }
+            }
+            append_entries(add, slots, v, qout, out_cnt);
+            __syncthreads();  // s_hit / s_pre are restaged next round
+        }
+    } else if (bu) {
         // bottom-up: threads check up to BU_THREAD_SLOTS slots of their own
         // row (four loads in flight); longer rows without a hit go to a
         // block-local list that the block's waves finish one row at a time
@@ -418,30 +504,13 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
                 len = min(rl - ent.y, GR_CHUNK);
                 exam += 3;
             }
-            int wtot;
-            int wex = wave_excl_scan(len, &wtot);
-            if (lane == 0) s_wsum[tid / WAVE] = wtot;
-            __syncthreads();
-            int woff = 0, total = 0;
-            for (int w = 0; w < BS / WAVE; ++w) {
-                if (w < tid / WAVE) woff += s_wsum[w];
-                total += s_wsum[w];
-            }
-            s_pre[tid] = woff + wex;
-            if (tid == BS - 1) s_pre[BS] = total;
-            __syncthreads();
+            const int total = block_prefix(len);
             scanned += (unsigned long long)total;  // counted once per block (thread 0 below)
             for (int base = 0; base < total; base += BS) {
                 int i = base + tid;
                 int v = -1, add = 0, slots = 0;
                 if (i < total) {
-                    // last entry k with s_pre[k] <= i
-                    int lo = 0, hi = BS;
-                    while (hi - lo > 1) {
-                        int mid = (lo + hi) >> 1;
-                        if (s_pre[mid] <= i) lo = mid;
-                        else hi = mid;
-                    }
+                    const int lo = owner(i);
                     int j = s_beg[lo] + (i - s_pre[lo]);
                     int2 cr = g.cr[j];
                     v = cr.x;
@@ -505,7 +574,7 @@ __device__ __forceinline__ int gr_level_step(const Par& P, const DevGraph& g, in
         for (int i = threadIdx.x; i < bits.nwords; i += blockDim.x) s_dyn[i] = src[i];
         __syncthreads();
     }
-    gr_level_body<FWD, BS>(P, g, lv, cnt, qin, qout, ctr, bits, bu, stage ? s_dyn : nullptr);
+    gr_level_body<FWD, BS>(P, g, lv, cnt, qin, qout, ctr, bits, bu, tune.bu_lb != 0, stage ? s_dyn : nullptr);
     return cnt;
 }
 
@@ -670,6 +739,18 @@ __device__ __forceinline__ void do_push(DevGraph& g, int u, int j, int64_t eu) {
     add_e(g.e, PULL ? u : w, d);
 }
 
+// Move d along slot j of u without touching e(u) (the caller settles u's
+// excess once for all the moves of a cycle): the residual the move uses
+// shrinks, its reverse grows, and the neighbour's excess changes by d.
+template <bool PULL>
+__device__ __forceinline__ void move_along(DevGraph& g, int j, int32_t d) {
+    int jo = PULL ? g.rev[j] : j;
+    int ji = PULL ? j : g.rev[j];
+    add_res(g.cr, jo, -d);
+    add_res(g.cr, ji, d);
+    add_e(g.e, g.cr[j].x, PULL ? -(int64_t)d : (int64_t)d);
+}
+
 // Key of slot j for the lowest-neighbour search: (h(col) << 32 | j) when the
 // residual the move would use is positive, else ~0.  The slot's col and res
 // come from one coherent 64-bit load.
@@ -714,7 +795,12 @@ constexpr int PR_UNROLL_BLOCK = 8;   // rows above the wave bin: more loads in f
 // Per-vertex bodies of Algorithm 2; each returns the algorithmic bytes it
 // moved.  A relabel is followed by the push of the next cycle on the same
 // scan (the lowest neighbour it found is now admissible), two of the KC
-// cycles for one scan of the row.  Thread: one lane owns u.  Wave: u is wave-uniform.  Block: u is
+// cycles for one scan of the row.  A push goes to the lowest neighbour the
+// scan found and then on to every other residual slot whose neighbour is
+// still at that height, until the excess is gone: the cycles Algorithm 2
+// would spend saturating one lowest neighbour after another under the same
+// heights, done in one pass (heights only rise during push-relabel, so a
+// neighbour still at the scanned minimum is still admissible).  Thread: one lane owns u.  Wave: u is wave-uniform.  Block: u is
 // block-uniform and the whole block scans its row.
 template <bool PULL>
 __device__ __forceinline__ unsigned long long pr_thread_item(DevGraph& g, int u, int kc) {
@@ -742,8 +828,19 @@ __device__ __forceinline__ unsigned long long pr_thread_item(DevGraph& g, int u,
             bytes += 4;
             if (hu >= N || ++c >= kc) break;
         }
-        do_push<PULL>(g, u, bj, eu);
-        bytes += 48;
+        // push to bj, then to the following slots still at height bh, in
+        // slot order, until the excess is gone
+        int64_t left = eu;
+        for (int j = bj; j < end && left > 0; ++j) {
+            int32_t r = scan_res<PULL>(g, j);
+            if (r <= 0 || (j != bj && g.h[g.cr[j].x] != bh)) continue;
+            int32_t d = left < (int64_t)r ? (int32_t)left : r;
+            move_along<PULL>(g, j, d);
+            left -= d;
+            bytes += 48;
+        }
+        if (left != eu) add_e(g.e, u, PULL ? eu - left : left - eu);
+        bytes += 12ull * (unsigned long long)(end - bj);
     }
     return bytes;
 }
@@ -777,8 +874,25 @@ __device__ __forceinline__ unsigned long long pr_wave_item(DevGraph& g, int u, i
             bytes += 4;
             if (hu >= N || ++c >= kc) break;
         }
-        if (lane == 0) do_push<PULL>(g, u, bj, eu);
-        bytes += 48;
+        // push to bj, then to the following slots still at height bh, in
+        // slot order (a wave prefix sum hands out the excess), until the
+        // excess is gone
+        int64_t left = eu;
+        for (int b = bj; b < end && left > 0; b += WAVE) {
+            int j = b + lane;
+            int32_t r = j < end ? scan_res<PULL>(g, j) : 0;
+            bool cand = r > 0 && (j == bj || g.h[g.cr[j].x] == bh);
+            long long tot;
+            long long ex = wave_excl_scan64(cand ? (long long)r : 0ll, &tot);
+            if (cand && ex < left) {
+                int64_t room = left - ex;
+                move_along<PULL>(g, j, room < (int64_t)r ? (int32_t)room : r);
+                bytes += 48;
+            }
+            left -= tot < left ? tot : left;
+            bytes += 12ull * (unsigned long long)(j < end);
+        }
+        if (lane == 0 && left != eu) add_e(g.e, u, PULL ? eu - left : left - eu);
     }
     return bytes;
 }
@@ -787,6 +901,7 @@ template <bool PULL, int BS>
 __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, int kc) {
     __shared__ unsigned long long part[BS / WAVE];
     __shared__ int64_t e_sh;
+    __shared__ unsigned long long taken;   // excess handed out by the current cycle
     const int N = g.n;
     const int lane = lane_id();
     const int wv = threadIdx.x / WAVE;
@@ -823,10 +938,47 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
             bytes += 4;
             if (hu >= N || ++c >= kc) break;
         }
-        if (threadIdx.x == 0) do_push<PULL>(g, u, bj, eu);
-        bytes += 48;
+        // push to bj first, then every other slot of the row still at height
+        // bh takes what is left in the order the threads claim it (an LDS
+        // running total), until the excess is gone
+        if (threadIdx.x == 0) {
+            int32_t r = scan_res<PULL>(g, bj);
+            int32_t d = eu < (int64_t)r ? (int32_t)eu : r;
+            if (d > 0) move_along<PULL>(g, bj, d);
+            taken = d > 0 ? (unsigned long long)d : 0ull;
+            bytes += 48;
+        }
+        __syncthreads();
+        for (int b = beg + threadIdx.x; b < end && (int64_t)taken < eu; b += PR_UNROLL_BLOCK * BS) {
+            unsigned long long sv[PR_UNROLL_BLOCK];
+#pragma unroll
+            for (int q = 0; q < PR_UNROLL_BLOCK; ++q) {
+                int j = b + q * BS;
+                sv[q] = j < end && j != bj ? ld_slot(g.cr, j) : 0ull;
+            }
+#pragma unroll
+            for (int q = 0; q < PR_UNROLL_BLOCK; ++q) {
+                int j = b + q * BS;
+                if (j >= end || j == bj) continue;
+                int32_t r = PULL ? ld_res(g.cr, g.rev[j]) : (int32_t)(sv[q] >> 32);
+                if (r <= 0 || g.h[(int)(unsigned)sv[q]] != bh) continue;
+                int64_t before = (int64_t)atomicAdd(&taken, (unsigned long long)r);
+                if (before < eu) {
+                    int64_t room = eu - before;
+                    move_along<PULL>(g, j, room < (int64_t)r ? (int32_t)room : r);
+                    bytes += 48;
+                }
+            }
+            bytes += 12ull * PR_UNROLL_BLOCK;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t moved = (int64_t)taken < eu ? (int64_t)taken : eu;
+            if (moved) add_e(g.e, u, PULL ? moved : -moved);
+        }
+        __syncthreads();
     }
-    __syncthreads();  // part / e_sh are reused by the next item
+    __syncthreads();  // part / e_sh / taken are reused by the next item
     return bytes;
 }
 
@@ -1208,8 +1360,11 @@ __device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
     bool sweep = mode == 1 && S.warm;  // one push-relabel sweep on the previous heights
     int iters = 0;
     int status = 0;
+    int rounds_left = 0;               // push-relabel rounds still due before the next relabel
     for (;;) {
-        if (!sweep) {
+        const bool relabel = !sweep && rounds_left == 0;
+        int depth = 0;
+        if (relabel) {
             // global relabel (Algorithm 6), then the worklist and value
             if (tid < 3) {
                 ctr->front[tid] = 0;
@@ -1229,6 +1384,7 @@ __device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
                                                    ctr, S.bits, tune, nullptr);
                 __syncthreads();
                 if (cnt == 0) break;
+                depth = lv + 1;
             }
         } else {
             if (tid < 4) ctr->wl[tid] = 0;
@@ -1246,14 +1402,19 @@ __device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
         }
         __syncthreads();
         const int c0 = s_cnt[0], c1 = s_cnt[1], c2 = s_cnt[2], active = s_cnt[3];
-        if (!sweep) {
+        if (relabel) {
             if (active == 0) break;
             if (++iters > S.max_iter) {
                 status = MF_ERR_NOT_CONVERGED;
                 break;
             }
+            rounds_left = depth / S.round_div > 1 ? depth / S.round_div : 1;
+        } else if (!sweep && active == 0) {
+            rounds_left = 0;  // the next relabel certifies (or finds more work)
+            continue;
         }
         sweep = false;
+        if (rounds_left > 0) --rounds_left;
         // push-relabel (Algorithm 2) over the three degree bins
         for (int i = tid; i < c0; i += BS) pr_thread_item<false>(g, S.wl0[i], S.kc);
         for (int i = tid / WAVE; i < c1; i += BS / WAVE) pr_wave_item<false>(g, bcast(S.wl1[i]), S.kc);

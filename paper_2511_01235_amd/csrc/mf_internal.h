@@ -94,6 +94,7 @@ struct GrTune {
     int bu_beta;    // ... and frontier vertices * beta > n; alpha <= 0 disables bottom-up
     int stage_min;  // top-down levels with at least this many entries stage the visited bitmap
     int lds;        // the bitmap fits in LDS (dynamic shared memory provided at launch)
+    int bu_lb;      // bottom-up levels stream the unvisited rows slot-parallel (no per-row early exit)
 };
 
 // One graph of a batched solve: views into the pooled device arrays (slot
@@ -110,6 +111,7 @@ struct GraphSlot {
     DevCounters* ctr;
     int32_t kc;
     int32_t warm;              // repairs: one sweep on the previous heights first
+    int32_t round_div;         // push-relabel rounds per relabel: BFS depth / round_div, at least 1
     int64_t max_iter;
     // results of the last launch
     long long value;

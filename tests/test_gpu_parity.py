@@ -71,6 +71,50 @@ def test_initial_labels_bit_exact(name):
     assert np.unique(active).size == active.size
 
 
+@pytest.mark.parametrize("lb", [0, 1])
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+def test_bottom_up_levels_bit_exact(name, lb, monkeypatch):
+    """Every BFS level bottom-up (per-row early exit, or slot-parallel rows):
+    heights bit-exact to the oracle's BFS, and the dynamic values too."""
+    monkeypatch.setenv("MF_GR_BU_ALPHA", "1000000")
+    monkeypatch.setenv("MF_GR_BU_BETA", "1000000")
+    monkeypatch.setenv("MF_GR_BU_LB", str(lb))
+    g, stream, k, _ = gen.workload(name)
+    say("bottom-up levels", name, "lb", lb)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    h_want, _ = o.initial_labels()
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        h, _, _ = G.initial_labels()
+        assert np.array_equal(h, h_want)
+        assert G.maxflow() == o.static()
+        for _ in range(3):
+            u, v, c = stream.next_batch(k)
+            assert G.apply_batch(u, v, c) == o.apply(u, v, c)
+
+
+@pytest.mark.parametrize("div", [1, 8, 1000000])
+@pytest.mark.parametrize("name", ["grid64", "rmat12"])
+def test_push_rounds_between_relabels(name, div, monkeypatch):
+    """Push-relabel rounds on the current heights between global relabels
+    (one per relabel up to one per BFS level): values equal the oracle's in
+    the single-graph and the batched loops."""
+    monkeypatch.setenv("MF_ROUND_DIV", str(div))
+    g, stream, k, _ = gen.workload(name)
+    say("push rounds", name, "div", div)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    want = [o.static()]
+    batches = [stream.next_batch(k) for _ in range(3)]
+    want += [o.apply(*b) for b in batches]
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        got = [G.maxflow()] + [G.apply_batch(*b) for b in batches]
+        if div == 1 and name == "grid64":
+            assert G.stats()["last_rounds"] > G.stats()["last_iterations"]
+    assert got == want
+    with mf.MaxFlowBatch([g]) as B:
+        got_b = [int(B.maxflow()[0])] + [int(B.apply([b])[0]) for b in batches]
+    assert got_b == want
+
+
 # --- static value ---------------------------------------------------------------
 
 def test_golden_static_gpu():
