@@ -39,6 +39,10 @@ WORKLOADS = {
     "er2000": "Erdos-Renyi n=2000 m=16000, caps U[1,100]; batches of 200 updates (40/40/20)",
     "grid2048": "2048x2048 4-connected grid, caps U[1,100], source/sink links 1000; batches of "
                 "1,000 updates in random 64x64 patches (40/40/20)",
+    "sweep": "update-batch sweep in the shape of the paper's experiments (Section 6.2): RMAT scale 20 "
+             "(or --sweep-graph), batches of x% of |E| existing edges, source/sink edges 10x as likely, "
+             "all increases / all decreases / mixed, each applied to the freshly solved graph; "
+             "incremental vs from-scratch time",
     "serve64": "64 resident RMAT graphs, scale uniform in 14..20, edge factor 16, caps U[1,1000]; "
                "2,000 update batches (size log-uniform 10..10,000, 40/40/20) to uniformly chosen "
                "graphs with Poisson arrivals; HBM budget 50% of the fleet's footprint",
@@ -69,6 +73,11 @@ def main():
                          "one sweep on the previous heights")
     ap.add_argument("--profile-all", action="store_true",
                     help="event-time every kernel class (adds event overhead to the steps)")
+    ap.add_argument("--tune", action="store_true",
+                    help="single-graph workloads: autotune the handle (untimed) before the timed batches")
+    ap.add_argument("--no-tune", action="store_true", help="batch512: skip the autotuner")
+    ap.add_argument("--sweep-graph", default="rmat20", help="sweep: generator workload of the graph")
+    ap.add_argument("--sweep-pcts", default="0.01,0.1,1,5,10", help="sweep: batch sizes in %% of |E|")
     ap.add_argument("--serve-slots", type=int, default=8, help="serve64: concurrent slots")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serve64: requests per run")
     ap.add_argument("--serve-load", type=float, default=0.7,
@@ -98,6 +107,8 @@ def main():
         return bench_batched(args, mf, gen, torch, stream)
     if args.workload == "serve64":
         return bench_serving(args, mf, serve_inputs)
+    if args.workload == "sweep":
+        return bench_sweep(args, mf, gen, torch, stream)
 
     t0 = time.time()
     g, bstream, k, nb = gen.workload(args.workload)
@@ -143,6 +154,11 @@ def main():
     for i in range(args.warmup):
         values.append(G.apply_batch_device(dev_batches[i]))
         log(f"warm-up batch {i} done")
+    tuned = None
+    if args.tune:
+        from paper_2511_01235_amd.tune import tune_graph
+        tuned = tune_graph(G, k, sync=torch.cuda.synchronize)
+        log(f"tuned: {tuned}")
 
     # dominant kernel: timed live over the whole timed region (HIP events on the library's stream)
     G.profile(0xFF if args.profile_all else (1 << 0))
@@ -233,6 +249,7 @@ def main():
         "final_value": values[-1],
         "mean_iterations_per_batch": round(float(np.mean(iters)), 2),
         "relayouts": prof["relayouts"],
+        "tuned": tuned,
         "updates_per_s": round(k / (ms_per_step * 1e-3), 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -253,6 +270,12 @@ def bench_batched(args, mf, gen, torch, stream):
         f"and {rounds} update rounds in {time.time() - t0:.1f}s")
     B = mf.MaxFlowBatch(graphs, stream=stream, device=0, kernel_cycles=args.kc,
                         warm_start=not args.cold_start)
+    tuned = None
+    if not args.no_tune:
+        from paper_2511_01235_amd.tune import tune_batch
+        B.maxflow()
+        tuned = tune_batch(B, graphs, sample=24, sync=torch.cuda.synchronize)
+        log(f"tuned: {tuned}")
     torch.cuda.synchronize()
     a = time.perf_counter()
     static_vals = B.maxflow()
@@ -306,9 +329,58 @@ def bench_batched(args, mf, gen, torch, stream):
         "per_instance_static_ms": round(single_static_ms, 3),
         "batched_speedup_static": round(single_static_ms / static_ms, 3),
         "graphs_per_s_static": round(512 / (static_ms * 1e-3), 1),
+        "tuned": tuned,
+        "per_instance_options": "defaults",
         "roofline": None,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args, mf, gen, torch, stream):
+    """Incremental repair against a from-scratch solve of the same updated
+    graph, for increase-only, decrease-only and mixed batches of growing size
+    (x% of |E|); each batch hits the graph as first solved (reloaded and
+    re-solved before each point, outside the timing)."""
+    g, _, _, _ = gen.workload(args.sweep_graph)
+    pcts = [float(x) for x in args.sweep_pcts.split(",")]
+    rows = []
+    for kind in ("inc", "dec", "mixed"):
+        for pct in pcts:
+            st = gen.BatchStream(g, 61000 + int(pct * 1000) + {"inc": 0, "dec": 1, "mixed": 2}[kind],
+                                 inc_max=50)
+            k = max(1, int(round(pct / 100 * st.keys.size)))
+            u, v, c = st.paper_batch(k, kind)
+            dev_upd = torch.from_numpy(np.ascontiguousarray(np.stack([u, v, c], 1))).to("cuda:0")
+            with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0) as G:
+                v0 = G.maxflow()
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                v1 = G.apply_batch_device(dev_upd)
+                torch.cuda.synchronize()
+                inc_ms = (time.perf_counter() - a) * 1e3
+                it = G.stats()["last_iterations"]
+                a = time.perf_counter()
+                v2 = G.maxflow()
+                torch.cuda.synchronize()
+                scratch_ms = (time.perf_counter() - a) * 1e3
+            assert v1 == v2, (kind, pct, v1, v2)
+            rows.append({"kind": kind, "pct_of_E": pct, "updates": k, "value_before": v0, "value_after": v1,
+                         "incremental_ms": round(inc_ms, 3), "from_scratch_ms": round(scratch_ms, 3),
+                         "speedup": round(scratch_ms / inc_ms, 3), "iterations": it})
+            log(json.dumps(rows[-1]))
+    crossover = {}
+    for kind in ("inc", "dec", "mixed"):
+        slower = [r["pct_of_E"] for r in rows if r["kind"] == kind and r["speedup"] < 1.0]
+        crossover[kind] = min(slower) if slower else None
+    mean_ms = float(np.mean([r["incremental_ms"] for r in rows]))
+    out = {"metric": METRIC, "value": round(mean_ms, 3), "unit": "ms/batch (mean over the sweep)", "n_gpus": 1,
+           "steps": len(rows), "warmup": 0, "ms_per_step": round(mean_ms, 3), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32/int64", "data": "synthetic",
+           "config": {"workload": f"sweep: {WORKLOADS['sweep']}", "graph": args.sweep_graph, "n": g.n,
+                      "m_edges_generated": g.m, "pcts": pcts},
+           "sweep": rows, "first_pct_where_from_scratch_wins": crossover,
+           "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 

@@ -69,6 +69,17 @@ typedef struct mf_options {
     int32_t relabel_mode;      /* 0 (default): one launch per BFS level; 1: the whole global
                                   relabel and worklist build in one cooperative launch with a grid
                                   barrier per level (falls back to 0 where unsupported) */
+    /* tuning (mf_graph_tune / mf_batch_tune change them on a live handle); none
+     * changes a result */
+    int32_t bfs_alpha;         /* a BFS level goes bottom-up when its frontier's slots times alpha
+                                  exceed the unvisited slots ...; 0: 14, < 0: never bottom-up */
+    int32_t bfs_beta;          /* ... and its frontier vertices times beta exceed n; <= 0: 64 */
+    int32_t round_div;         /* push-relabel rounds per global relabel: BFS depth / round_div,
+                                  at least 1; <= 0: 8 */
+    int32_t bin_thread_max;    /* active rows up to this many slots get one thread ...; <= 0: 16 */
+    int32_t bin_wave_max;      /* ... up to this many one 64-lane wave, longer ones a workgroup;
+                                  <= 0: 512 */
+    int32_t batch_block;       /* mf_batch_*: threads per graph, 256, 512 or 1024; 0: 512 */
 } mf_options;
 
 /* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its
@@ -197,6 +208,13 @@ mf_status mf_graph_offload(mf_graph* g);
  * memory; the graph stays offloaded, nothing lost), MF_ERR_DEVICE. */
 mf_status mf_graph_restore(mf_graph* g);
 
+/* Apply the tuning fields of *opt (kernel_cycles, bfs_alpha, bfs_beta,
+ * round_div, bin_thread_max, bin_wave_max; others ignored, 0 = default) to a
+ * live handle, for autotuners that time one handle under several settings.
+ * Results never depend on them.  Errors: MF_ERR_INVALID (NULL, struct_size,
+ * bin_wave_max below bin_thread_max), MF_ERR_STATE (offloaded). */
+mf_status mf_graph_tune(mf_graph* g, const mf_options* opt);
+
 /* Counters and sizes; see mf_stats (device_bytes is the counters' size while
  * offloaded). */
 mf_status mf_get_stats(const mf_graph* g, mf_stats* out);
@@ -261,6 +279,10 @@ mf_status mf_batch_apply(mf_batch* b, const int64_t* update_offset, const mf_upd
 /* Loop iterations (global relabels) of each graph in the last call
  * (int32[num_graphs], or NULL) and the call's host wall time in ms. */
 mf_status mf_batch_info(const mf_batch* b, int32_t* iterations, double* last_ms);
+
+/* mf_graph_tune for a batch: the same fields plus batch_block (threads per
+ * graph: 256, 512 or 1024).  Errors: MF_ERR_INVALID, MF_ERR_DEVICE. */
+mf_status mf_batch_tune(mf_batch* b, const mf_options* opt);
 
 void mf_batch_free(mf_batch* b);
 

@@ -31,9 +31,9 @@ MF_ERR_STATE = 6
 # every symbol include/mf.h declares
 EXPORTED = ["mf_default_options", "mf_status_string", "mf_graph_load", "mf_maxflow",
             "mf_apply_batch", "mf_apply_batch_device", "mf_min_cut", "mf_get_flow", "mf_get_edges",
-            "mf_graph_offload", "mf_graph_restore", "mf_get_stats", "mf_profile", "mf_debug_initial_labels", "mf_debug_selftest",
+            "mf_graph_offload", "mf_graph_restore", "mf_graph_tune", "mf_get_stats", "mf_profile", "mf_debug_initial_labels", "mf_debug_selftest",
             "mf_graph_free", "mf_batch_load", "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info",
-            "mf_batch_free"]
+            "mf_batch_tune", "mf_batch_free"]
 
 KERNEL_CLASSES = ["global_relabel", "push_relabel", "remove_invalid", "worklist", "batch", "init",
                   "unused6", "unused7"]
@@ -49,7 +49,13 @@ class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("device", C.c_int32), ("stream", C.c_void_p),
                 ("kernel_cycles", C.c_int32), ("topology_driven", C.c_int32),
                 ("insert_slack_min", C.c_int32), ("insert_slack_pct", C.c_int32),
-                ("max_iterations", C.c_int64), ("cold_start", C.c_int32), ("relabel_mode", C.c_int32)]
+                ("max_iterations", C.c_int64), ("cold_start", C.c_int32), ("relabel_mode", C.c_int32),
+                ("bfs_alpha", C.c_int32), ("bfs_beta", C.c_int32), ("round_div", C.c_int32),
+                ("bin_thread_max", C.c_int32), ("bin_wave_max", C.c_int32), ("batch_block", C.c_int32)]
+
+# fields mf_graph_tune / mf_batch_tune apply to a live handle
+TUNING_FIELDS = ("kernel_cycles", "bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max",
+                 "batch_block")
 
 
 class Stats(C.Structure):
@@ -91,6 +97,8 @@ def lib():
         L.mf_get_flow.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
         L.mf_get_edges.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
         L.mf_graph_offload.argtypes = [vp]
+        L.mf_graph_tune.argtypes = [vp, C.POINTER(Options)]
+        L.mf_batch_tune.argtypes = [vp, C.POINTER(Options)]
         L.mf_graph_restore.argtypes = [vp]
         L.mf_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.mf_profile.argtypes = [vp, i32]
@@ -106,6 +114,7 @@ def lib():
         L.mf_batch_free.restype = None
         for name in ["mf_graph_load", "mf_maxflow", "mf_apply_batch", "mf_apply_batch_device",
                      "mf_min_cut", "mf_get_flow", "mf_get_edges", "mf_graph_offload", "mf_graph_restore",
+                     "mf_graph_tune", "mf_batch_tune",
                      "mf_get_stats", "mf_profile",
                      "mf_debug_initial_labels", "mf_debug_selftest", "mf_batch_load",
                      "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info"]:
@@ -135,8 +144,11 @@ def mf_default_options() -> Options:
 
 def make_options(kernel_cycles=0, topology_driven=False, insert_slack_min=0, insert_slack_pct=0,
                  max_iterations=0, stream=None, device=-1, warm_start=True,
-                 relabel_mode=0) -> Options:
+                 relabel_mode=0, bfs_alpha=0, bfs_beta=0, round_div=0, bin_thread_max=0, bin_wave_max=0,
+                 batch_block=0) -> Options:
     o = mf_default_options()
+    o.bfs_alpha, o.bfs_beta, o.round_div = int(bfs_alpha), int(bfs_beta), int(round_div)
+    o.bin_thread_max, o.bin_wave_max, o.batch_block = int(bin_thread_max), int(bin_wave_max), int(batch_block)
     o.cold_start = 0 if warm_start else 1
     o.relabel_mode = int(relabel_mode)
     o.kernel_cycles = kernel_cycles
@@ -229,6 +241,14 @@ def mf_get_edges(g):
     return src[:k], dst[:k], cap[:k]
 
 
+def mf_graph_tune(g, **tuning):
+    """Apply tuning fields (see TUNING_FIELDS; 0 = default) to a live handle."""
+    bad = set(tuning) - set(TUNING_FIELDS)
+    if bad:
+        raise TypeError(f"not tuning fields: {sorted(bad)}")
+    _check(lib().mf_graph_tune(g, C.byref(make_options(**tuning))), "mf_graph_tune")
+
+
 def mf_graph_offload(g):
     _check(lib().mf_graph_offload(g), "mf_graph_offload")
 
@@ -297,6 +317,9 @@ class MaxFlowGraph:
 
     def get_edges(self):
         return mf_get_edges(self.h)
+
+    def tune(self, **tuning):
+        mf_graph_tune(self.h, **tuning)
 
     def offload(self):
         mf_graph_offload(self.h)
@@ -370,6 +393,12 @@ class MaxFlowBatch:
         _check(lib().mf_batch_apply(self.h, off.ctypes.data, upd.ctypes.data, vals.ctypes.data),
                "mf_batch_apply")
         return vals
+
+    def tune(self, **tuning):
+        bad = set(tuning) - set(TUNING_FIELDS)
+        if bad:
+            raise TypeError(f"not tuning fields: {sorted(bad)}")
+        _check(lib().mf_batch_tune(self.h, C.byref(make_options(**tuning))), "mf_batch_tune")
 
     def info(self):
         it = np.zeros(self.G, np.int32)

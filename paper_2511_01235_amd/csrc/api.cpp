@@ -83,6 +83,34 @@ struct mf_graph {
     } hc;
 };
 
+namespace mf {
+
+mf_status resolve_tuning(const mf_options& o, Tuning* t) {
+    Tuning r{};
+    r.kc_option = o.kernel_cycles > 0 ? o.kernel_cycles : 0;
+    r.gr = GrTune{GR_BU_ALPHA, GR_BU_BETA, GR_STAGE_MIN, 0, 0};
+    r.round_div = 8;
+    // environment overrides for experiments, where the option is left 0
+    if (const char* env = std::getenv("MF_GR_BU_ALPHA")) r.gr.bu_alpha = std::atoi(env);
+    if (const char* env = std::getenv("MF_GR_BU_BETA")) r.gr.bu_beta = std::max(1, std::atoi(env));
+    if (const char* env = std::getenv("MF_GR_STAGE_MIN")) r.gr.stage_min = std::atoi(env);
+    if (const char* env = std::getenv("MF_GR_BU_LB")) r.gr.bu_lb = std::atoi(env) != 0;
+    if (const char* env = std::getenv("MF_ROUND_DIV")) r.round_div = std::max(1, std::atoi(env));
+    if (o.bfs_alpha > 0) r.gr.bu_alpha = o.bfs_alpha;
+    if (o.bfs_alpha < 0) r.gr.bu_alpha = 0;
+    if (o.bfs_beta > 0) r.gr.bu_beta = o.bfs_beta;
+    if (o.round_div > 0) r.round_div = o.round_div;
+    r.bin0 = o.bin_thread_max > 0 ? o.bin_thread_max : BIN0_MAX;
+    r.bin1 = o.bin_wave_max > 0 ? o.bin_wave_max : BIN1_MAX;
+    if (r.bin1 < r.bin0) return MF_ERR_INVALID;
+    r.batch_block = o.batch_block == 0 ? 512 : o.batch_block;
+    if (r.batch_block != 256 && r.batch_block != 512 && r.batch_block != 1024) return MF_ERR_INVALID;
+    *t = r;
+    return MF_OK;
+}
+
+}  // namespace mf
+
 namespace {
 
 #define MF_HIP(call)                                   \
@@ -275,6 +303,19 @@ void free_device_state(mf_graph* g) {
     dfree(g->dg.bytes_part);
     g->k_cap = 0;
     g->tb.capacity = 0;
+}
+
+// Tuning fields of a handle from resolved options; KC defaults to round(m/n)
+// (at least 1).  The LDS-staging flag is the device's and stays.
+void apply_tuning(mf_graph* g, const mf::Tuning& t) {
+    int64_t kc = t.kc_option > 0 ? t.kc_option : (g->m_unique + g->n / 2) / g->n;
+    g->kc = (int32_t)std::max<int64_t>(1, kc);
+    int lds = g->tune.lds;
+    g->tune = t.gr;
+    g->tune.lds = lds;
+    g->round_div = t.round_div;
+    g->dg.bin0_max = t.bin0;
+    g->dg.bin1_max = t.bin1;
 }
 
 mf_status ensure_batch_capacity(mf_graph* g, int64_t k) {
@@ -628,6 +669,8 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     }
     int32_t slack_min = o.insert_slack_min > 0 ? o.insert_slack_min : 2;
     int32_t slack_pct = o.insert_slack_pct > 0 ? o.insert_slack_pct : 12;
+    mf::Tuning tuning;
+    if (mf::resolve_tuning(o, &tuning) != MF_OK) return MF_ERR_INVALID;
     mf::HostBiCSR b;
     mf_status rc = mf::build_bicsr(n, m, src, dst, cap, s, t, slack_min, slack_pct, &b);
     if (rc != MF_OK) return rc;
@@ -642,8 +685,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     g->slack_pct = slack_pct;
     g->pairs = b.pairs;
     g->m_unique = b.m_unique;
-    int64_t kc = o.kernel_cycles > 0 ? o.kernel_cycles : (b.m_unique + n / 2) / n;
-    g->kc = (int32_t)std::max<int64_t>(1, kc);
+    apply_tuning(g, tuning);
     g->max_iter = o.max_iterations > 0 ? o.max_iterations : 4 * (int64_t)n + 1000;
     auto fail = [&](mf_status r) {
         free_all(g);
@@ -673,15 +715,10 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     if (dalloc(g, &g->bits.visited, 4 * (int64_t)g->bits.nwords) != hipSuccess) return fail(MF_ERR_OUT_OF_MEMORY);
     g->bits.fb = g->bits.visited + g->bits.nwords;
     g->tune.lds = 0;  // LDS-bitmap level variant: opt-in (MF_GR_LDS=1), slower on rmat20
-    if (const char* env = std::getenv("MF_GR_BU_ALPHA")) g->tune.bu_alpha = std::atoi(env);
-    if (const char* env = std::getenv("MF_GR_BU_BETA")) g->tune.bu_beta = std::max(1, std::atoi(env));
-    if (const char* env = std::getenv("MF_GR_STAGE_MIN")) g->tune.stage_min = std::atoi(env);
-    if (const char* env = std::getenv("MF_GR_BU_LB")) g->tune.bu_lb = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_GR_LDS"))
         if (std::atoi(env) != 0) g->tune.lds = mf::gr_level_lds_bytes(g->bits.nwords, dev) > 0 ? 1 : 0;
     if (const char* env = std::getenv("MF_GR_GRID")) g->gr_grid = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_GR_FIRST_CHUNK")) g->first_chunk = std::max(1, std::atoi(env));
-    if (const char* env = std::getenv("MF_ROUND_DIV")) g->round_div = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_ROUND_MAX")) g->round_max = std::max(1, std::atoi(env));
     if (o.relabel_mode == 1) g->persistent_grid = mf::persistent_gr_grid(dev);
     g->dg.n = n;
@@ -1004,6 +1041,16 @@ mf_status mf_graph_restore(mf_graph* g) {
     MF_HIP(hipGetLastError());
     MF_HIP(hipStreamSynchronize(st));
     g->offloaded = false;
+    return MF_OK;
+}
+
+mf_status mf_graph_tune(mf_graph* g, const mf_options* opt) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    if (!opt || opt->struct_size != sizeof(mf_options)) return MF_ERR_INVALID;
+    mf::Tuning t;
+    if (mf::resolve_tuning(*opt, &t) != MF_OK) return MF_ERR_INVALID;
+    apply_tuning(g, t);
     return MF_OK;
 }
 

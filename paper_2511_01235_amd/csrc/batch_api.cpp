@@ -38,6 +38,10 @@ struct mf_batch {
     int32_t slack_min = 2, slack_pct = 12;
     int32_t relayouts = 0;
     int32_t round_div = 8;
+    int32_t bin0 = mf::BIN0_MAX, bin1 = mf::BIN1_MAX;
+    int32_t block = 512;                 // threads per graph
+    int32_t kc_option = 0;               // 0: round(m/n) per graph
+    std::vector<int64_t> m_unique;
     int64_t total_v = 0, total_rp = 0, total_s = 0, total_b = 0, total_q = 0;
     // pools
     int32_t *row_ptr = nullptr, *row_len = nullptr, *row_sorted = nullptr;
@@ -120,6 +124,21 @@ struct Clock {
     }
 };
 
+
+// Tuning fields from resolved options; KC per graph defaults to round(m/n).
+void apply_tuning(mf_batch* b, const mf::Tuning& t) {
+    b->tune = t.gr;
+    b->tune.lds = 0;
+    b->round_div = t.round_div;
+    b->bin0 = t.bin0;
+    b->bin1 = t.bin1;
+    b->block = t.batch_block;
+    b->kc_option = t.kc_option;
+    for (int i = 0; i < b->G; ++i) {
+        int64_t kc = t.kc_option > 0 ? t.kc_option : (b->m_unique[i] + b->n[i] / 2) / b->n[i];
+        b->kc[i] = (int32_t)std::max<int64_t>(1, kc);
+    }
+}
 
 // Slot and queue bases of every graph for the current slot counts.
 void set_slot_bases(mf_batch* b) {
@@ -211,6 +230,8 @@ mf_status upload_views(mf_batch* b) {
         g.used_slots = b->used[(size_t)i];
         g.bytes_part = b->bytes_part;
         g.count_bytes = 0;
+        g.bin0_max = b->bin0;
+        g.bin1_max = b->bin1;
         int64_t qc = (int64_t)ni + b->slots[i] / mf::GR_CHUNK + 64;
         S.q0 = b->q + b->qbase[i];
         S.q1 = S.q0 + qc;
@@ -322,6 +343,8 @@ mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edg
         if (edge_offset[i + 1] < edge_offset[i]) return MF_ERR_INVALID;
     int32_t slack_min = o.insert_slack_min > 0 ? o.insert_slack_min : 2;
     int32_t slack_pct = o.insert_slack_pct > 0 ? o.insert_slack_pct : 12;
+    mf::Tuning tuning;
+    if (mf::resolve_tuning(o, &tuning) != MF_OK) return MF_ERR_INVALID;
     // validate and build every graph on the host first: nothing is allocated on failure
     std::vector<mf::HostBiCSR> hb((size_t)num_graphs);
     for (int i = 0; i < num_graphs; ++i) {
@@ -353,16 +376,14 @@ mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edg
     const int G = num_graphs;
     b->slack_min = slack_min;
     b->slack_pct = slack_pct;
-    if (const char* env = std::getenv("MF_ROUND_DIV")) b->round_div = std::max(1, std::atoi(env));
     b->s_h.assign(s, s + G);
     b->t_h.assign(t, t + G);
     b->n.resize(G); b->kc.resize(G); b->vbase.resize(G); b->rpbase.resize(G); b->sbase.resize(G);
-    b->slots.resize(G); b->bbase.resize(G); b->qbase.resize(G);
+    b->slots.resize(G); b->bbase.resize(G); b->qbase.resize(G); b->m_unique.resize(G);
     for (int i = 0; i < G; ++i) {
         const mf::HostBiCSR& x = hb[(size_t)i];
         b->n[i] = n[i];
-        int64_t kc = o.kernel_cycles > 0 ? o.kernel_cycles : (x.m_unique + n[i] / 2) / n[i];
-        b->kc[i] = (int32_t)std::max<int64_t>(1, kc);
+        b->m_unique[i] = x.m_unique;
         b->vbase[i] = b->total_v;
         b->rpbase[i] = b->total_rp;
         b->slots[i] = x.row_ptr[(size_t)n[i]];
@@ -371,6 +392,7 @@ mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edg
         b->total_rp += n[i] + 1;
         b->total_b += 4 * (int64_t)((n[i] + 31) / 32);
     }
+    apply_tuning(b, tuning);
     set_slot_bases(b);
     if (b->total_s > INT_MAX || b->total_v > INT_MAX) return fail(MF_ERR_OVERFLOW);
     const int64_t V = b->total_v;
@@ -403,7 +425,7 @@ mf_status mf_batch_maxflow(mf_batch* b, int64_t* values) {
     if (hipSetDevice(b->device) != hipSuccess) return MF_ERR_DEVICE;
     Clock clock(b);
     b->solved = false;
-    mf::launch_batch_solve(b->slots_d, b->order_d, b->G, 0, b->tune, b->stream);
+    mf::launch_batch_solve(b->slots_d, b->order_d, b->G, 0, b->tune, b->block, b->stream);
     MFB_HIP(hipGetLastError());
     mf_status rc = read_results(b, values);
     if (rc == MF_OK) b->solved = true;
@@ -507,11 +529,22 @@ mf_status mf_batch_apply(mf_batch* b, const int64_t* update_offset, const mf_upd
         if (rc != MF_OK) return rc;
     }
     b->solved = false;
-    mf::launch_batch_repair_multi(b->slots_d, b->gu_d, b->order_d, G, b->tune, st);
+    mf::launch_batch_repair_multi(b->slots_d, b->gu_d, b->order_d, G, b->tune, b->block, st);
     MFB_HIP(hipGetLastError());
     mf_status rc = read_results(b, values);
     if (rc == MF_OK) b->solved = true;
     return rc;
+}
+
+mf_status mf_batch_tune(mf_batch* b, const mf_options* opt) {
+    if (!b || !opt || opt->struct_size != sizeof(mf_options)) return MF_ERR_INVALID;
+    if (b->poisoned) return MF_ERR_DEVICE;
+    mf::Tuning t;
+    if (mf::resolve_tuning(*opt, &t) != MF_OK) return MF_ERR_INVALID;
+    if (hipSetDevice(b->device) != hipSuccess) return MF_ERR_DEVICE;
+    MFB_HIP(hipStreamSynchronize(b->stream));
+    apply_tuning(b, t);
+    return upload_views(b);
 }
 
 mf_status mf_batch_info(const mf_batch* b, int32_t* iterations, double* last_ms) {

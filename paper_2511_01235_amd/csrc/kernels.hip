@@ -686,7 +686,7 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
         }
         unsigned long long am = __ballot(act);
         if (lane_id() == 0 && am) atomicAdd(&ctr->wl[3], __popcll(am));
-        int bin = len <= BIN0_MAX ? 0 : (len <= BIN1_MAX ? 1 : 2);
+        int bin = len <= g.bin0_max ? 0 : (len <= g.bin1_max ? 1 : 2);
         wave_append(list && bin == 0, v, wl0, &ctr->wl[0]);
         wave_append(list && bin == 1, v, wl1, &ctr->wl[1]);
         wave_append(list && bin == 2, v, wl2, &ctr->wl[2]);
@@ -1313,8 +1313,7 @@ __global__ void __launch_bounds__(256) k_batch_cleanup(BatchTable tb, int32_t* n
 }
 
 // ---- batched solve: one block per graph ---------------------------------------
-
-constexpr int BATCH_BLOCK = 512;
+// (256, 512 or 1024 threads per graph, a tuning choice)
 
 // The whole loop of Algorithms 1 and 5 for one graph inside one block: the
 // same level, worklist, push-relabel and remove-invalid-edges bodies as the
@@ -1983,9 +1982,11 @@ void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipSt
 }
 
 void launch_batch_solve(GraphSlot* slots, const int32_t* order, int num, int mode, const GrTune& tune,
-                        hipStream_t st) {
+                        int block, hipStream_t st) {
     if (num <= 0) return;
-    k_batch_solve<BATCH_BLOCK><<<num, BATCH_BLOCK, 0, st>>>(slots, order, mode, tune);
+    if (block == 256) k_batch_solve<256><<<num, 256, 0, st>>>(slots, order, mode, tune);
+    else if (block == 1024) k_batch_solve<1024><<<num, 1024, 0, st>>>(slots, order, mode, tune);
+    else k_batch_solve<512><<<num, 512, 0, st>>>(slots, order, mode, tune);
 }
 
 void launch_batch_locate_multi(GraphSlot* slots, GraphUpdates* gu, int num, hipStream_t st) {
@@ -1993,8 +1994,11 @@ void launch_batch_locate_multi(GraphSlot* slots, GraphUpdates* gu, int num, hipS
 }
 
 void launch_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu, const int32_t* order, int num,
-                               const GrTune& tune, hipStream_t st) {
-    if (num > 0) k_batch_repair_multi<BATCH_BLOCK><<<num, BATCH_BLOCK, 0, st>>>(slots, gu, order, tune);
+                               const GrTune& tune, int block, hipStream_t st) {
+    if (num <= 0) return;
+    if (block == 256) k_batch_repair_multi<256><<<num, 256, 0, st>>>(slots, gu, order, tune);
+    else if (block == 1024) k_batch_repair_multi<1024><<<num, 1024, 0, st>>>(slots, gu, order, tune);
+    else k_batch_repair_multi<512><<<num, 512, 0, st>>>(slots, gu, order, tune);
 }
 
 void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st) {

@@ -35,6 +35,7 @@ struct DevGraph {
     int64_t used_slots;                  // sum of row_len
     unsigned long long* bytes_part;      // KC_NCLASS x BYTES_SLOTS algorithmic-byte partial sums
     int count_bytes;                     // 1 while kernel classes are being profiled
+    int bin0_max, bin1_max;              // worklist degree bins: thread up to bin0_max slots, wave up to bin1_max
 };
 
 // Partial sums of algorithmic bytes: a kernel block adds into slot
@@ -63,8 +64,8 @@ struct DevCounters {
 
 enum KernelClass { KC_GR = 0, KC_PR = 1, KC_RIE = 2, KC_WL = 3, KC_BATCH = 4, KC_INIT = 5, KC_NCLASS = 8 };
 
-// Degree bins for the worklist: rows up to BIN0_MAX slots get one thread,
-// up to BIN1_MAX one wave, longer rows one 1024-thread block.
+// Default degree bins for the worklist: rows up to BIN0_MAX slots get one
+// thread, up to BIN1_MAX one wave, longer rows one 1024-thread block.
 constexpr int BIN0_MAX = 16;
 constexpr int BIN1_MAX = 512;
 constexpr int BLOCK_PR = 1024;
@@ -170,6 +171,18 @@ struct RelayoutPlan {
     int32_t* sort_count;       // 1
 };
 
+// Tuning of a handle resolved from mf_options (0 = default).
+struct Tuning {
+    int32_t kc_option;   // 0: round(m/n) per graph
+    GrTune gr;
+    int32_t round_div;
+    int32_t bin0, bin1;
+    int32_t batch_block;
+};
+// MF_ERR_INVALID for inconsistent fields; environment overrides (MF_GR_*,
+// MF_ROUND_DIV) apply where the option is left 0.
+mf_status resolve_tuning(const mf_options& o, Tuning* t);
+
 // ---- launch wrappers (kernels.hip) ---------------------------------------
 void launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t st);
 void launch_reset(const DevGraph& g, int64_t slot_cap, hipStream_t st);
@@ -212,12 +225,12 @@ int device_selftest(hipStream_t st);
 // from zero flow (Algorithm 1), mode 1 resumes after applied updates
 // (Algorithm 5's loop).
 void launch_batch_solve(GraphSlot* slots, const int32_t* order, int num, int mode, const GrTune& tune,
-                        hipStream_t st);
+                        int block, hipStream_t st);
 // Batched repair, first launch: validate and locate every graph's updates.
 void launch_batch_locate_multi(GraphSlot* slots, GraphUpdates* gu, int num, hipStream_t st);
 // Second launch: insert, apply, clamp, clean up and resume each graph.
 void launch_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu, const int32_t* order, int num,
-                               const GrTune& tune, hipStream_t st);
+                               const GrTune& tune, int block, hipStream_t st);
 // After a failed validation: scratch back to idle for every graph.
 void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st);
 int64_t relayout_tiles(int32_t V);

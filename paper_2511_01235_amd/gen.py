@@ -283,6 +283,35 @@ class BatchStream:
         order = rng.permutation(k)
         return (u[order].astype(np.int32), v[order].astype(np.int32), c[order].astype(np.int32))
 
+    def paper_batch(self, k: int, kind: str, st_bias: float = 10.0, inc_max: int | None = None):
+        """A batch shaped like the paper's update files (Section 6.2): k
+        distinct existing edges (capacity > 0), edges out of s and into t
+        drawn st_bias times as likely as the others; kind "inc" raises each
+        capacity by U[1, inc_max], "dec" lowers it to U[0, cap - 1], "mixed"
+        does one or the other with equal probability.  No new edges."""
+        if kind not in ("inc", "dec", "mixed"):
+            raise ValueError(kind)
+        rng = rng_for(self.seed_base + self.count)
+        self.count += 1
+        live = np.flatnonzero(self.caps > 0)
+        if live.size < k:
+            raise ValueError("not enough existing edges for the requested batch")
+        src = self.keys[live] // self.n
+        dst = self.keys[live] % self.n
+        w = np.where((src == self.g.s) | (dst == self.g.t), float(st_bias), 1.0)
+        pick = live[rng.choice(live.size, size=k, replace=False, p=w / w.sum())]
+        cur = self.caps[pick]
+        up = np.ones(k, bool) if kind == "inc" else (np.zeros(k, bool) if kind == "dec"
+                                                     else rng.random(k) < 0.5)
+        inc = rng.integers(1, (inc_max or self.inc_max) + 1, size=k)
+        dec = rng.integers(0, cur)                      # cur >= 1
+        new = np.where(up, cur + inc, dec)
+        if (new > INT32_MAX).any():
+            raise OverflowError("capacity increase leaves int32 range")
+        self.caps[pick] = new
+        u, v = self.keys[pick] // self.n, self.keys[pick] % self.n
+        return u.astype(np.int32), v.astype(np.int32), new.astype(np.int32)
+
     def _new_pairs(self, rng, want, sampler):
         if want == 0:
             return np.empty(0, np.int32), np.empty(0, np.int32)

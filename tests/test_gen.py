@@ -1,5 +1,6 @@
 """Seeded generators: determinism, shapes, and update-mix bookkeeping."""
 import numpy as np
+import pytest
 
 from paper_2511_01235_amd import gen
 
@@ -67,3 +68,27 @@ def test_grid_patch_batches_stay_in_patch():
     rows = np.concatenate([u // W, v // W])
     cols = np.concatenate([u % W, v % W])
     assert rows.max() - rows.min() < 64 and cols.max() - cols.min() < 64
+
+
+@pytest.mark.parametrize("kind", ["inc", "dec", "mixed"])
+def test_paper_batch_shapes(kind):
+    """Section 6.2's update files: existing edges only, distinct, direction of
+    the change as requested, source/sink edges favoured, caps tracked."""
+    g, st, _, _ = gen.workload("er2000")
+    before = dict(zip(st.keys.tolist(), st.caps.tolist()))
+    u, v, c = st.paper_batch(400, kind, st_bias=50.0)
+    keys = u.astype(np.int64) * g.n + v
+    assert np.unique(keys).size == keys.size
+    old = np.array([before[k] for k in keys.tolist()])
+    assert (old > 0).all()
+    if kind == "inc":
+        assert (c > old).all()
+    elif kind == "dec":
+        assert (c < old).all() and (c >= 0).all()
+    else:
+        assert ((c > old) | (c < old)).all() and (c > old).any() and (c < old).any()
+    st_edges = np.mean((u == g.s) | (v == g.t))
+    base = np.mean((g.src == g.s) | (g.dst == g.t))
+    assert st_edges > 5 * base
+    after = dict(zip(st.keys.tolist(), st.caps.tolist()))
+    assert all(after[k] == x for k, x in zip(keys.tolist(), c.tolist()))

@@ -452,6 +452,52 @@ def test_rmat20_full_size():
             _cut_ok(g.n, g.s, g.t, side, cut, got, cs, cd, cc)
 
 
+@pytest.mark.parametrize("kind", ["inc", "dec", "mixed"])
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+def test_paper_shaped_batches(name, kind):
+    """Section 6.2's update files (existing edges, source/sink edges favoured,
+    all increases / all decreases / mixed) at 0.1%, 1% and 10% of |E|."""
+    g, stream, _, _ = gen.workload(name)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        prev = o.static()
+        assert G.maxflow() == prev
+        for frac in (0.001, 0.01, 0.1):
+            k = max(1, int(round(frac * stream.keys.size)))
+            u, v, c = stream.paper_batch(k, kind)
+            say("paper batch", name, kind, k)
+            want = o.apply(u, v, c)
+            assert G.apply_batch(u, v, c) == want
+            # raising capacities cannot lower the maximum flow, lowering cannot raise it
+            assert want >= prev if kind == "inc" else (want <= prev if kind == "dec" else True)
+            prev = want
+
+
+def test_grid2048_full_size():
+    """The 2048 x 2048 grid at full size: the static value and the first
+    batches' values equal the oracle's (stored by
+    tests/golden/make_full_size_values.py: the CPU oracle takes minutes on
+    this graph), and every cut is a certificate."""
+    import json
+    ref = json.load(open(os.path.join(HERE, "golden", "grid2048_values.json")))
+    g, stream, k, _ = gen.workload("grid2048")
+    assert ref["batch_size"] == k
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        say("grid2048 gpu static")
+        got = G.maxflow()
+        assert got == ref["values"][0]
+        side, cut = G.min_cut()
+        _cut_ok(g.n, g.s, g.t, side, cut, got, g.src, g.dst, g.cap)
+        for b, want in enumerate(ref["values"][1:]):
+            u, v, c = stream.next_batch(k)
+            say("grid2048 batch", b)
+            got = G.apply_batch(u, v, c)
+            assert got == want
+        cs, cd, cc = stream.current_edges()
+        side, cut = G.min_cut()
+        _cut_ok(g.n, g.s, g.t, side, cut, got, cs, cd, cc)
+
+
 # --- batched solve: many graphs in one launch -----------------------------------
 
 def _batch_streams(graphs, seed=42000):
