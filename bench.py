@@ -73,6 +73,8 @@ def main():
                          "one sweep on the previous heights")
     ap.add_argument("--profile-all", action="store_true",
                     help="event-time every kernel class (adds event overhead to the steps)")
+    ap.add_argument("--push-pull", action="store_true",
+                    help="Section 5.2's O2: static push-pull and parallel push-pull repairs")
     ap.add_argument("--tune", action="store_true",
                     help="single-graph workloads: autotune the handle (untimed) before the timed batches")
     ap.add_argument("--no-tune", action="store_true", help="batch512: skip the autotuner")
@@ -120,7 +122,7 @@ def main():
 
     G = mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0,
                         kernel_cycles=args.kc, warm_start=not args.cold_start,
-                        relabel_mode=args.relabel_mode)
+                        relabel_mode=args.relabel_mode, push_pull=args.push_pull)
     st = G.stats()
     m_unique = None
     # static solve: median of a few from-zero runs on the loaded graph
@@ -237,7 +239,8 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOADS.get(args.workload, 'generator workload')}", "n": g.n,
                    "m_edges_generated": g.m, "m_pairs": m_unique, "s": g.s, "t": g.t,
                    "batch_size": k, "kernel_cycles": st["kernel_cycles"],
-                   "warm_start": not args.cold_start, "relabel_mode": args.relabel_mode},
+                   "warm_start": not args.cold_start, "relabel_mode": args.relabel_mode,
+                   "push_pull": args.push_pull},
         "incremental_ms_p50": round(float(np.percentile(arr, 50)), 4),
         "incremental_ms_p90": round(float(np.percentile(arr, 90)), 4),
         "incremental_ms_p99": round(float(np.percentile(arr, 99)), 4),
@@ -352,7 +355,8 @@ def bench_sweep(args, mf, gen, torch, stream):
             k = max(1, int(round(pct / 100 * st.keys.size)))
             u, v, c = st.paper_batch(k, kind)
             dev_upd = torch.from_numpy(np.ascontiguousarray(np.stack([u, v, c], 1))).to("cuda:0")
-            with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0) as G:
+            with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0,
+                                 push_pull=args.push_pull) as G:
                 v0 = G.maxflow()
                 torch.cuda.synchronize()
                 a = time.perf_counter()

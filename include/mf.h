@@ -80,6 +80,11 @@ typedef struct mf_options {
     int32_t bin_wave_max;      /* ... up to this many one 64-lane wave, longer ones a workgroup;
                                   <= 0: 512 */
     int32_t batch_block;       /* mf_batch_*: threads per graph, 256, 512 or 1024; 0: 512 */
+    int32_t push_pull;         /* 1: Section 5.2's O2 -- mf_maxflow also saturates the sink's
+                                  in-edges first (static push-pull); a repair saturates the previous
+                                  min cut again and runs push-relabel on its sink side and pull-
+                                  relabel on its source side at the same time on two streams,
+                                  before the ordinary loop.  0 (default): off.  Same values. */
 } mf_options;
 
 /* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its

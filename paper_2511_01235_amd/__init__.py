@@ -51,7 +51,8 @@ class Options(C.Structure):
                 ("insert_slack_min", C.c_int32), ("insert_slack_pct", C.c_int32),
                 ("max_iterations", C.c_int64), ("cold_start", C.c_int32), ("relabel_mode", C.c_int32),
                 ("bfs_alpha", C.c_int32), ("bfs_beta", C.c_int32), ("round_div", C.c_int32),
-                ("bin_thread_max", C.c_int32), ("bin_wave_max", C.c_int32), ("batch_block", C.c_int32)]
+                ("bin_thread_max", C.c_int32), ("bin_wave_max", C.c_int32), ("batch_block", C.c_int32),
+                ("push_pull", C.c_int32)]
 
 # fields mf_graph_tune / mf_batch_tune apply to a live handle
 TUNING_FIELDS = ("kernel_cycles", "bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max",
@@ -145,8 +146,9 @@ def mf_default_options() -> Options:
 def make_options(kernel_cycles=0, topology_driven=False, insert_slack_min=0, insert_slack_pct=0,
                  max_iterations=0, stream=None, device=-1, warm_start=True,
                  relabel_mode=0, bfs_alpha=0, bfs_beta=0, round_div=0, bin_thread_max=0, bin_wave_max=0,
-                 batch_block=0) -> Options:
+                 batch_block=0, push_pull=False) -> Options:
     o = mf_default_options()
+    o.push_pull = int(bool(push_pull))
     o.bfs_alpha, o.bfs_beta, o.round_div = int(bfs_alpha), int(bfs_beta), int(round_div)
     o.bin_thread_max, o.bin_wave_max, o.batch_block = int(bin_thread_max), int(bin_wave_max), int(batch_block)
     o.cold_start = 0 if warm_start else 1

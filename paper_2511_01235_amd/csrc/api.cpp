@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <utility>
+#include <thread>
 #include <vector>
 
 #include "mf.h"
@@ -71,6 +72,17 @@ struct mf_graph {
     int first_chunk = 8;      // BFS levels launched before the first frontier check
     int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
     int32_t round_max = 4096; // ... at most this many
+    // parallel push-pull repair (Section 5.2, O2): the pull side's lane and
+    // heights, made on first use
+    int32_t push_pull = 0;
+    hipStream_t stream2 = nullptr;
+    int2* q2[2] = {nullptr, nullptr};
+    int64_t q2_cap = 0;
+    int32_t* wl2[3] = {nullptr, nullptr, nullptr};
+    mf::GrBits bits2{};
+    DevCounters* ctr2 = nullptr;
+    DevCounters* ctr2_h = nullptr;  // pinned
+    int32_t* h2 = nullptr;
     // while offloaded the state lives in these pinned host buffers (kept for
     // the next offload) and the device holds only the counters
     bool offloaded = false;
@@ -206,7 +218,21 @@ void free_structure(mf_graph* g) {
     dfree(g->q[1]);
 }
 
+void free_lane2(mf_graph* g) {
+    dfree(g->q2[0]);
+    dfree(g->q2[1]);
+    g->q2_cap = 0;
+    for (auto& w : g->wl2) dfree(w);
+    dfree(g->bits2.visited);
+    g->bits2.fb = nullptr;
+    dfree(g->ctr2);
+    dfree(g->h2);
+}
+
 void free_all(mf_graph* g) {
+    free_lane2(g);
+    if (g->ctr2_h) (void)hipHostFree(g->ctr2_h);
+    g->ctr2_h = nullptr;
     free_structure(g);
     dfree(g->dg.e);
     dfree(g->dg.h);
@@ -285,6 +311,7 @@ hipError_t halloc(T** p, int64_t count) {
 
 // Every device buffer except the counters (the state is elsewhere by then).
 void free_device_state(mf_graph* g) {
+    free_lane2(g);
     free_structure(g);
     dfree(g->dg.e);
     dfree(g->dg.h);
@@ -352,8 +379,34 @@ mf_status ensure_batch_capacity(mf_graph* g, int64_t k) {
 // edges.  Completing a preflow into a flow reuses the loop twice on a copy of
 // the state: pushes toward s (root s, t pinned), then pulls from t (forward
 // BFS, negative-excess worklist, s pinned).
+// The scratch one loop runs on: a stream, BFS queues, worklists, bitmaps and
+// counters.  The handle's own lane is the main one (timed when profiling);
+// the parallel push-pull repair runs a second lane on a stream of its own.
+struct Lane {
+    hipStream_t stream = nullptr;
+    int2* q[2] = {nullptr, nullptr};
+    int32_t* wl[3] = {nullptr, nullptr, nullptr};
+    mf::GrBits bits{};
+    DevCounters* ctr = nullptr;
+    DevCounters* ctr_h = nullptr;
+    bool main = true;
+};
+
+Lane main_lane(mf_graph* g) {
+    Lane L;
+    L.stream = g->stream;
+    L.q[0] = g->q[0];
+    L.q[1] = g->q[1];
+    for (int b = 0; b < 3; ++b) L.wl[b] = g->wl[b];
+    L.bits = g->bits;
+    L.ctr = g->ctr;
+    L.ctr_h = g->ctr_h;
+    return L;
+}
+
 struct LoopMode {
     DevGraph dg;
+    Lane L;
     int seed_deficits = 1;
     bool forward = false;
     int sign = 1;
@@ -365,28 +418,43 @@ struct LoopMode {
 LoopMode solve_mode(mf_graph* g) {
     LoopMode m;
     m.dg = g->dg;
+    m.L = main_lane(g);
     m.topology = g->opt.topology_driven != 0;
     return m;
+}
+
+// Event timing on the main lane only (the host bookkeeping is not shared
+// across threads).
+template <class F>
+void timed(mf_graph* g, const Lane& L, int cls, F&& launch) {
+    if (L.main) timed(g, cls, launch);
+    else launch();
+}
+
+mf_status read_lane(mf_graph* g, const Lane& L) {
+    MF_HIP(hipMemcpyAsync(L.ctr_h, L.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, L.stream));
+    MF_HIP(hipStreamSynchronize(L.stream));
+    return MF_OK;
 }
 
 // Global relabel: seeds, then levels in growing chunks; each level launch
 // reads the frontier size on the device, so the host checks only after a
 // chunk.  Returns the number of level launches.
 mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
-    hipStream_t st = g->stream;
-    timed(g, mf::KC_GR, [&] { mf::launch_gr_init(m.dg, g->q[0], g->ctr, g->bits, m.seed_deficits, st); });
+    hipStream_t st = m.L.stream;
+    timed(g, m.L, mf::KC_GR, [&] { mf::launch_gr_init(m.dg, m.L.q[0], m.L.ctr, m.L.bits, m.seed_deficits, st); });
     int level = 0;
     int chunk = g->first_chunk;
     for (;;) {
         for (int i = 0; i < chunk; ++i, ++level)
-            timed(g, mf::KC_GR, [&] {
-                mf::launch_gr_level(m.dg, level, g->q[level & 1], g->q[(level + 1) & 1], g->ctr,
-                                    g->bits, g->tune, g->gr_grid, m.forward, st);
+            timed(g, m.L, mf::KC_GR, [&] {
+                mf::launch_gr_level(m.dg, level, m.L.q[level & 1], m.L.q[(level + 1) & 1], m.L.ctr,
+                                    m.L.bits, g->tune, g->gr_grid, m.forward, st);
             });
         MF_HIP(hipGetLastError());
-        mf_status rc = read_counters(g);
+        mf_status rc = read_lane(g, m.L);
         if (rc != MF_OK) return rc;
-        if ((g->ctr_h->front[level % 3] & 0xFFFFFFFFull) == 0) break;
+        if ((m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull) == 0) break;
         if (level > g->n + 2) {
             g->poisoned = true;
             return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
@@ -402,31 +470,31 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
 // kernel (every BFS level behind a grid barrier); otherwise one launch per
 // level plus one for the worklist.
 mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) {
-    hipStream_t st = g->stream;
+    hipStream_t st = m.L.stream;
     if (g->persistent_grid > 0) {
         hipError_t err = hipSuccess;
-        timed(g, mf::KC_GR, [&] {
-            err = mf::launch_gr_persistent(m.dg, g->q[0], g->q[1], g->ctr, g->bits, g->tune, m.seed_deficits,
-                                           m.forward, g->wl[0], g->wl[1], g->wl[2], m.topology, m.sign,
+        timed(g, m.L, mf::KC_GR, [&] {
+            err = mf::launch_gr_persistent(m.dg, m.L.q[0], m.L.q[1], m.L.ctr, m.L.bits, g->tune, m.seed_deficits,
+                                           m.forward, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.topology, m.sign,
                                            g->persistent_grid, st);
         });
         MF_HIP(err);
-        mf_status rc = read_counters(g);
+        mf_status rc = read_lane(g, m.L);
         if (rc != MF_OK) return rc;
-        if (g->ctr_h->bar_err) {
+        if (m.L.ctr_h->bar_err) {
             g->poisoned = true;
             return MF_ERR_DEVICE;
         }
-        *levels += g->ctr_h->levels;
+        *levels += m.L.ctr_h->levels;
         return MF_OK;
     }
     mf_status rc = global_relabel(g, m, levels);
     if (rc != MF_OK) return rc;
-    timed(g, mf::KC_WL, [&] {
-        mf::launch_build_worklist(m.dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, m.topology, m.sign, st);
+    timed(g, m.L, mf::KC_WL, [&] {
+        mf::launch_build_worklist(m.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology, m.sign, st);
     });
     MF_HIP(hipGetLastError());
-    return read_counters(g);
+    return read_lane(g, m.L);
 }
 
 // Loop {global relabel; worklist; stop if no active vertex; R rounds of
@@ -441,28 +509,34 @@ mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) 
 // deep BFS (long augmenting paths) buys many cheap rounds, a shallow one
 // keeps the paper's one sweep per relabel.
 mf_status push_round(mf_graph* g, const LoopMode& m, const int cnt[3]) {
-    hipStream_t st = g->stream;
+    hipStream_t st = m.L.stream;
     for (int b = 0; b < 3; ++b)
         if (cnt[b])
-            timed(g, mf::KC_PR, [&] {
-                mf::launch_push_relabel(m.dg, g->wl[b], cnt[b], b, g->kc, m.pull, g->ctr, st);
+            timed(g, m.L, mf::KC_PR, [&] {
+                mf::launch_push_relabel(m.dg, m.L.wl[b], cnt[b], b, g->kc, m.pull, m.L.ctr, st);
             });
     if (m.rie)
         for (int b = 0; b < 3; ++b)
             if (cnt[b])
-                timed(g, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, g->wl[b], cnt[b], b, g->ctr, st); });
+                timed(g, m.L, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, m.L.wl[b], cnt[b], b, m.L.ctr, st); });
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
 
 mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
-    hipStream_t st = g->stream;
+    // every buffer a loop launches on must be set (a mode built by hand
+    // without a lane would hand the kernels null pointers)
+    const Lane& L = m.L;
+    if (!L.stream || !L.q[0] || !L.q[1] || !L.wl[0] || !L.wl[1] || !L.wl[2] || !L.bits.visited ||
+        !L.bits.fb || !L.ctr || !L.ctr_h || !m.dg.h || !m.dg.e || !m.dg.cr)
+        return MF_ERR_INVALID;
+    hipStream_t st = m.L.stream;
     int64_t iters = 0, levels = 0, active_sum = 0, rounds = 0;
     for (;;) {
         const int64_t levels_before = levels;
         mf_status rc = relabel_and_worklist(g, m, &levels);
         if (rc != MF_OK) return rc;
-        const DevCounters& c = *g->ctr_h;
+        const DevCounters& c = *m.L.ctr_h;
         int active = c.wl[3];
         active_sum += active;
         if (active == 0) {
@@ -470,7 +544,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             break;
         }
         if (++iters > g->max_iter) {
-            g->last_iterations = iters;
+            if (m.L.main) g->last_iterations = iters;
             return MF_ERR_NOT_CONVERGED;
         }
         const int64_t depth = levels - levels_before;
@@ -481,12 +555,12 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             if (rc != MF_OK) return rc;
             ++rounds;
             if (r + 1 >= R) break;
-            mf::launch_zero_loop_counters(g->ctr, st);
-            timed(g, mf::KC_WL, [&] {
-                mf::launch_build_worklist(m.dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, m.topology, m.sign, st);
+            mf::launch_zero_loop_counters(m.L.ctr, st);
+            timed(g, m.L, mf::KC_WL, [&] {
+                mf::launch_build_worklist(m.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology, m.sign, st);
             });
             MF_HIP(hipGetLastError());
-            rc = read_counters(g);
+            rc = read_lane(g, m.L);
             if (rc != MF_OK) return rc;
             if (c.wl[3] == 0) break;  // certified by the next relabel
             active_sum += c.wl[3];
@@ -495,10 +569,12 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             cnt[2] = c.wl[2];
         }
     }
-    g->last_iterations = iters;
-    g->last_levels = levels;
-    g->last_active_sum = active_sum;
-    g->last_rounds = rounds;
+    if (m.L.main) {
+        g->last_iterations = iters;
+        g->last_levels = levels;
+        g->last_active_sum = active_sum;
+        g->last_rounds = rounds;
+    }
     return MF_OK;
 }
 
@@ -577,6 +653,8 @@ mf_status relayout(mf_graph* g) {
     return MF_OK;
 }
 
+mf_status push_pull_phase(mf_graph* g);
+
 // Algorithm 5 after the updates are on the device.
 mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value) {
     hipStream_t st = g->stream;
@@ -614,13 +692,121 @@ mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_
         g->dg.used_slots += 2 * (int64_t)c.new_pairs;
         timed(g, mf::KC_INIT, [&] { mf::launch_saturate_source(g->dg, g->ctr, st); });
         MF_HIP(hipGetLastError());
-        if (!g->opt.cold_start) {
+        if (g->push_pull) {
+            rc = push_pull_phase(g);
+            if (rc != MF_OK) return rc;
+        } else if (!g->opt.cold_start) {
             rc = warm_sweep(g);
             if (rc != MF_OK) return rc;
         }
         return run_loop(g, solve_mode(g), value);
     }
     return MF_ERR_OUT_OF_MEMORY;  // slack could not be made to fit
+}
+
+// The pull side's lane: its own stream (default priority), queues sized like
+// the main lane's, worklists, bitmaps, counters and heights.
+mf_status ensure_lane2(mf_graph* g) {
+    const int64_t n = g->n;
+    if (!g->stream2 && hipStreamCreateWithFlags(&g->stream2, hipStreamNonBlocking) != hipSuccess)
+        return MF_ERR_DEVICE;
+    if (!g->ctr2_h && hipHostMalloc((void**)&g->ctr2_h, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess)
+        return MF_ERR_OUT_OF_MEMORY;
+    if (g->q2_cap < g->q_cap) {
+        dfree(g->q2[0]);
+        dfree(g->q2[1]);
+        g->q2_cap = 0;
+        if (dalloc(g, &g->q2[0], g->q_cap) != hipSuccess || dalloc(g, &g->q2[1], g->q_cap) != hipSuccess)
+            return MF_ERR_OUT_OF_MEMORY;
+        g->q2_cap = g->q_cap;
+    }
+    if (!g->h2) {
+        g->bits2.nwords = g->bits.nwords;
+        if (dalloc(g, &g->wl2[0], n) != hipSuccess || dalloc(g, &g->wl2[1], n) != hipSuccess ||
+            dalloc(g, &g->wl2[2], n) != hipSuccess ||
+            dalloc(g, &g->bits2.visited, 4 * (int64_t)g->bits2.nwords) != hipSuccess ||
+            dalloc(g, &g->ctr2, 1) != hipSuccess || dalloc(g, &g->h2, n) != hipSuccess) {
+            free_lane2(g);
+            return MF_ERR_OUT_OF_MEMORY;
+        }
+        g->bits2.fb = g->bits2.visited + g->bits2.nwords;
+        mf::launch_clear_counters(g->ctr2, g->stream2);
+        MF_HIP(hipStreamSynchronize(g->stream2));
+    }
+    return MF_OK;
+}
+
+// Section 5.2's O2 after a batch: the source side S of the last terminating
+// relabel (h = |V|) and the rest T were separated by a saturated cut; the
+// batch may have opened it.  Saturate every residual S -> T slot again, then
+// run at the same time, on two streams, push-relabel inside T (excess flows
+// to t and T's deficits, relabels seeded only in T) and pull-relabel inside S
+// (deficits pull from s and S's excess, forward relabels seeded only in S).
+// No residual path leads from S to T, so the two never touch the same vertex
+// or slot.  The caller then runs the ordinary loop over the whole graph,
+// whose fresh relabel certifies the value.
+mf_status push_pull_phase(mf_graph* g) {
+    hipStream_t st = g->stream;
+    mf_status rc = ensure_lane2(g);
+    if (rc != MF_OK) return rc;
+    mf::launch_mark_side(g->dg, g->side, st);
+    mf::launch_saturate_cut(g->dg, g->side, g->slot_cap, st);
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipStreamSynchronize(st));
+    LoopMode push_t = solve_mode(g);
+    push_t.dg.side = g->side;
+    push_t.dg.side_keep = 0;
+    LoopMode pull_s = push_t;
+    pull_s.dg.side_keep = 1;
+    pull_s.dg.h = g->h2;
+    pull_s.dg.root = g->s;
+    pull_s.dg.pinned = g->t;
+    pull_s.seed_deficits = -1;  // overflowing vertices of S are bases of the pull heights
+    pull_s.forward = true;
+    pull_s.sign = -1;
+    pull_s.pull = true;
+    pull_s.rie = false;
+    Lane& L2 = pull_s.L;
+    L2.stream = g->stream2;
+    L2.q[0] = g->q2[0];
+    L2.q[1] = g->q2[1];
+    for (int b = 0; b < 3; ++b) L2.wl[b] = g->wl2[b];
+    L2.bits = g->bits2;
+    L2.ctr = g->ctr2;
+    L2.ctr_h = g->ctr2_h;
+    L2.main = false;
+    int64_t v1 = 0, v2 = 0;
+    mf_status rc2 = MF_OK;
+    if (g->persistent_grid > 0) {
+        // two cooperative launches must not wait on each other: one side after the other
+        mf::launch_zero_loop_counters(g->ctr, st);
+        rc = run_loop(g, push_t, &v1);
+        if (rc != MF_OK) return rc;
+        mf::launch_zero_loop_counters(g->ctr2, g->stream2);
+        return run_loop(g, pull_s, &v2);
+    }
+    std::thread pull_thread;
+    try {
+        pull_thread = std::thread([&] {
+            if (hipSetDevice(g->device) != hipSuccess) {
+                rc2 = MF_ERR_DEVICE;
+                return;
+            }
+            mf::launch_zero_loop_counters(g->ctr2, g->stream2);
+            rc2 = run_loop(g, pull_s, &v2);
+        });
+    } catch (...) {
+        return MF_ERR_OUT_OF_MEMORY;  // no thread: nothing was launched
+    }
+    mf::launch_zero_loop_counters(g->ctr, st);
+    rc = run_loop(g, push_t, &v1);
+    pull_thread.join();
+    if (rc != MF_OK) return rc;
+    if (rc2 != MF_OK) {
+        if (rc2 == MF_ERR_DEVICE) g->poisoned = true;
+        return rc2;
+    }
+    return MF_OK;
 }
 
 struct CallTimer {
@@ -686,6 +872,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     g->pairs = b.pairs;
     g->m_unique = b.m_unique;
     apply_tuning(g, tuning);
+    g->push_pull = o.push_pull != 0;
     g->max_iter = o.max_iterations > 0 ? o.max_iterations : 4 * (int64_t)n + 1000;
     auto fail = [&](mf_status r) {
         free_all(g);
@@ -758,6 +945,7 @@ mf_status mf_maxflow(mf_graph* g, int64_t* value) {
     timed(g, mf::KC_INIT, [&] {
         mf::launch_reset(g->dg, g->slot_cap, st);
         mf::launch_saturate_source(g->dg, g->ctr, st);
+        if (g->push_pull) mf::launch_saturate_sink(g->dg, st);  // static push-pull (Section 5.2)
     });
     MF_HIP(hipGetLastError());
     int64_t v = 0;
@@ -868,8 +1056,8 @@ mf_status mf_get_flow(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, i
     // work on a copy: the retained preflow stays as it is
     MF_HIP(hipMemcpyAsync(cr2, g->dg.cr, sizeof(int2) * S, hipMemcpyDeviceToDevice, st));
     MF_HIP(hipMemcpyAsync(e2, g->dg.e, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
-    LoopMode to_source;
-    to_source.dg = g->dg;
+    LoopMode to_source = solve_mode(g);  // the handle's lane; the graph arrays are the copies
+    to_source.topology = false;
     to_source.dg.cr = cr2;
     to_source.dg.e = e2;
     to_source.dg.h = h2;
@@ -1141,6 +1329,7 @@ void mf_graph_free(mf_graph* g) {
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     free_all(g);
     free_host_copy(g);
+    if (g->stream2) (void)hipStreamDestroy(g->stream2);
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }

@@ -232,6 +232,8 @@ mf_status upload_views(mf_batch* b) {
         g.count_bytes = 0;
         g.bin0_max = b->bin0;
         g.bin1_max = b->bin1;
+        g.side = nullptr;
+        g.side_keep = 0;
         int64_t qc = (int64_t)ni + b->slots[i] / mf::GR_CHUNK + 64;
         S.q0 = b->q + b->qbase[i];
         S.q1 = S.q0 + qc;

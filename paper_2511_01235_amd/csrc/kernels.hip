@@ -217,6 +217,53 @@ __global__ void __launch_bounds__(256) k_saturate_source(DevGraph g) {
     if (threadIdx.x == 0 && tot) add_e(g.e, g.s, -tot);
 }
 
+// Static push-pull: the sink pulls every residual in-edge w->t full; w may
+// turn deficient and is then an extra root of the next relabel.
+__global__ void __launch_bounds__(256) k_saturate_sink(DevGraph g) {
+    int beg = g.row_ptr[g.t];
+    int len = g.row_len[g.t];
+    long long got = 0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < len; k += gridDim.x * blockDim.x) {
+        int j = beg + k;            // slot t->w; the in-edge w->t is its reverse
+        int w = g.cr[j].x;
+        if (w == g.s) continue;     // the source's edges are the source's to saturate
+        int r = g.rev[j];
+        int32_t x = xchg_res(g.cr, r, 0);
+        if (x > 0) {
+            add_res(g.cr, j, x);
+            add_e(g.e, w, -(int64_t)x);
+            got += x;
+        }
+    }
+    long long tot = block_sum_i64<256>(got);
+    if (threadIdx.x == 0 && tot) add_e(g.e, g.t, tot);
+}
+
+__global__ void __launch_bounds__(256) k_mark_side(DevGraph g, uint8_t* side) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += gridDim.x * blockDim.x)
+        side[v] = g.h[v] == g.n ? 1 : 0;
+}
+
+// Saturate every residual slot from side 1 to side 0 (a slot's owner is the
+// column of its reverse slot; free slack slots have no reverse).
+__global__ void __launch_bounds__(256) k_saturate_cut(DevGraph g, const uint8_t* side, int64_t slot_cap) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < slot_cap;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int2 c = g.cr[j];
+        if (c.y <= 0 || side[c.x] != 0) continue;
+        int r = g.rev[j];
+        if (r < 0) continue;
+        int u = g.cr[r].x;
+        if (side[u] != 1) continue;
+        int32_t x = xchg_res(g.cr, (int)j, 0);
+        if (x > 0) {
+            add_res(g.cr, r, x);
+            add_e(g.e, u, -(int64_t)x);
+            add_e(g.e, c.x, (int64_t)x);
+        }
+    }
+}
+
 // ---- global relabel (Algorithms 4 and 6) ----------------------------------
 
 // Zero what one global relabel and the worklist build after it accumulate.
@@ -261,9 +308,17 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
     for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
         int v = base + threadIdx.x;
         int add = 0, slots = 0;
-        if (v < N) {
-            bool seed = v == g.root ||
-                        (seed_deficits && v != g.pinned && v != g.s && v != g.t && ld_e(g.e, v) < 0);
+        if (v < N && g.side && g.side[v] != g.side_keep) {
+            g.h[v] = N;                 // the other side: never labelled by this relabel
+            set_bit(bits.visited, v);
+        } else if (v < N) {
+            // seed_deficits 1: deficient vertices are extra roots; -1: overflowing ones
+            bool extra = false;
+            if (seed_deficits && v != g.pinned && v != g.s && v != g.t) {
+                int64_t ev = ld_e(g.e, v);
+                extra = seed_deficits > 0 ? ev < 0 : ev > 0;
+            }
+            bool seed = v == g.root || extra;
             g.h[v] = seed ? 0 : N;
             if (seed) {
                 slots = g.row_len[v];
@@ -1806,6 +1861,18 @@ void launch_reset(const DevGraph& g, int64_t slot_cap, hipStream_t st) {
 void launch_saturate_source(const DevGraph& g, DevCounters* ctr, hipStream_t st) {
     (void)ctr;
     k_saturate_source<<<64, 256, 0, st>>>(g);
+}
+
+void launch_saturate_sink(const DevGraph& g, hipStream_t st) {
+    k_saturate_sink<<<64, 256, 0, st>>>(g);
+}
+
+void launch_mark_side(const DevGraph& g, uint8_t* side, hipStream_t st) {
+    k_mark_side<<<grid_for(g.n, 256), 256, 0, st>>>(g, side);
+}
+
+void launch_saturate_cut(const DevGraph& g, const uint8_t* side, int64_t slot_cap, hipStream_t st) {
+    k_saturate_cut<<<grid_for(slot_cap, 256, 8192), 256, 0, st>>>(g, side, slot_cap);
 }
 
 void launch_zero_loop_counters(DevCounters* ctr, hipStream_t st) {

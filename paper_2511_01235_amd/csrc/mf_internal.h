@@ -36,6 +36,8 @@ struct DevGraph {
     unsigned long long* bytes_part;      // KC_NCLASS x BYTES_SLOTS algorithmic-byte partial sums
     int count_bytes;                     // 1 while kernel classes are being profiled
     int bin0_max, bin1_max;              // worklist degree bins: thread up to bin0_max slots, wave up to bin1_max
+    const uint8_t* side;                 // not null: a relabel only labels vertices with side[v] == side_keep
+    int side_keep;
 };
 
 // Partial sums of algorithmic bytes: a kernel block adds into slot
@@ -187,6 +189,12 @@ mf_status resolve_tuning(const mf_options& o, Tuning* t);
 void launch_fill_i32(int32_t* p, int32_t value, int64_t count, hipStream_t st);
 void launch_reset(const DevGraph& g, int64_t slot_cap, hipStream_t st);
 void launch_saturate_source(const DevGraph& g, DevCounters* ctr, hipStream_t st);
+// static push-pull: every residual in-slot w->t of the sink is saturated (w may turn deficient)
+void launch_saturate_sink(const DevGraph& g, hipStream_t st);
+// side[v] = 1 where h[v] == n (the source side of the last terminating relabel), else 0
+void launch_mark_side(const DevGraph& g, uint8_t* side, hipStream_t st);
+// every residual slot u->v with side[u] == 1 and side[v] == 0 is saturated
+void launch_saturate_cut(const DevGraph& g, const uint8_t* side, int64_t slot_cap, hipStream_t st);
 void launch_zero_loop_counters(DevCounters* ctr, hipStream_t st);
 void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, const GrBits& bits, int seed_deficits,
                     hipStream_t st);

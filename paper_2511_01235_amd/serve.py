@@ -2,8 +2,9 @@
 
 Requests (one batch of capacity updates for one graph) arrive over time.  A
 fixed number of slots (host threads) serve them.  A free slot takes the
-earliest-arrived request whose graph no other slot is working on and whose
-graph is resident or can be made resident, and runs the repair
+earliest-arrived request of an idle resident graph, or -- when none waits,
+or when a request to a graph that is not resident has waited max_wait
+seconds -- one whose graph can be made resident, and runs the repair
 (mf_apply_batch) on that graph's own HIP stream: repairs of different graphs
 overlap on the device, and each graph sees its requests in arrival order, so
 every answer equals that of applying the graph's batches one after another.
@@ -77,7 +78,7 @@ class Server:
     `options`."""
 
     def __init__(self, graphs, hbm_budget: int, slots: int = 4, factory=None, evict: str = "offload",
-                 **options):
+                 max_wait: float = 0.25, **options):
         if factory is None:
             from . import MaxFlowGraph
 
@@ -87,6 +88,7 @@ class Server:
             raise ValueError("evict must be 'offload' or 'rebuild'")
         self.factory = factory
         self.evict = evict
+        self.max_wait = float(max_wait)
         self.restores = 0
         self.budget = int(hbm_budget)
         self.slots = int(slots)
@@ -164,14 +166,23 @@ class Server:
         return self._need(gi) <= free + evictable
 
     def _pick(self, now: float):
-        best = None
+        """Residency first, with aging: the earliest-arrived request of a
+        resident idle graph, unless none waits or the earliest request of a
+        graph that must be admitted has waited max_wait seconds; requests to
+        a graph coming in meanwhile share its one admission."""
+        best_res = best_new = None
         for gi, x in enumerate(self.g):
             if x.busy or not x.pending or x.pending[0].arrival > now:
                 continue
             r = x.pending[0]
-            if (best is None or r.arrival < best.arrival) and self._admissible(gi):
-                best = r
-        return best
+            if x.resident:
+                if best_res is None or r.arrival < best_res.arrival:
+                    best_res = r
+            elif (best_new is None or r.arrival < best_new.arrival) and self._admissible(gi):
+                best_new = r
+        if best_new is not None and (best_res is None or now - best_new.arrival >= self.max_wait):
+            return best_new
+        return best_res
 
     def _next_arrival(self, now: float) -> float:
         later = [x.pending[0].arrival for x in self.g if x.pending and x.pending[0].arrival > now]

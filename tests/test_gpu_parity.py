@@ -498,6 +498,37 @@ def test_grid2048_full_size():
         _cut_ok(g.n, g.s, g.t, side, cut, got, cs, cd, cc)
 
 
+@pytest.mark.parametrize("relabel_mode", [0, 1])
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+def test_push_pull_matches_oracle(name, relabel_mode):
+    """Section 5.2's O2: static push-pull (sink in-edges saturated first) and
+    the parallel push-pull repair (old min cut saturated again, push inside
+    T and pull inside S on two streams, then the ordinary loop) give the
+    oracle's values, with cut certificates, on mixed, increase-only and
+    decrease-only batches."""
+    g, stream, k, _ = gen.workload(name)
+    model = _CapModel(g.n, g.src, g.dst, g.cap)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, push_pull=True,
+                         relabel_mode=relabel_mode) as G:
+        got = G.maxflow()
+        assert got == o.static()
+        side, cut = G.min_cut()
+        _cut_ok(g.n, g.s, g.t, side, cut, got, g.src, g.dst, g.cap)
+        for b, kind in enumerate(["mix", "inc", "dec", "mix", "dec"]):
+            if kind == "mix":
+                u, v, c = stream.next_batch(k)
+            else:
+                u, v, c = stream.paper_batch(max(1, k // 2), kind)
+            model.apply(u, v, c)
+            say("push-pull batch", name, b, kind)
+            got = G.apply_batch(u, v, c)
+            assert got == o.apply(u, v, c)
+            ms, md, mc = model.arrays()
+            side, cut = G.min_cut()
+            _cut_ok(g.n, g.s, g.t, side, cut, got, ms, md, mc)
+
+
 # --- batched solve: many graphs in one launch -----------------------------------
 
 def _batch_streams(graphs, seed=42000):
