@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--sweep-pcts", default="0.01,0.1,1,5,10", help="sweep: batch sizes in %% of |E|")
     ap.add_argument("--serve-slots", type=int, default=8, help="serve64: concurrent slots")
     ap.add_argument("--serve-requests", type=int, default=2000, help="serve64: requests per run")
-    ap.add_argument("--serve-load", type=float, default=0.7,
+    ap.add_argument("--serve-load", type=float, default=0.5,
                     help="serve64: offered rate as a fraction of the measured saturation throughput")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -425,6 +425,10 @@ def bench_serving(args, mf, inputs):
     arrivals = np.cumsum(gaps) / rate
     pois, v_pois = run(args.serve_slots, budget, arrivals, f"poisson {rate:.0f}/s, budget 50%")
     assert v_pois == v_seq, "values differ under the HBM budget"
+    light_rate = rate / 2
+    light, v_light = run(args.serve_slots, budget, np.cumsum(gaps) / light_rate,
+                         f"poisson {light_rate:.0f}/s, budget 50%")
+    assert v_light == v_seq
     poisu, v_poisu = run(args.serve_slots, unlimited, arrivals, f"poisson {rate:.0f}/s, unlimited budget")
     assert v_poisu == v_seq
     cpu = None
@@ -443,6 +447,9 @@ def bench_serving(args, mf, inputs):
         "batches_per_s": round(pois["batches_per_s"], 1), "evictions": pois["evictions"],
         "restores": pois["restores"], "eviction": "offload to pinned host memory",
         "saturation_batches_per_s_budget": round(satb["batches_per_s"], 1),
+        "half_rate": {"offered_rate_per_s": round(light_rate, 1), "p50_ms": round(light["p50_ms"], 3),
+                      "p99_ms": round(light["p99_ms"], 3), "batches_per_s": round(light["batches_per_s"], 1),
+                      "evictions": light["evictions"]},
         "unlimited_budget_p50_ms": round(poisu["p50_ms"], 3),
         "unlimited_budget_p99_ms": round(poisu["p99_ms"], 3),
         "saturation_batches_per_s_one_slot": round(seq["batches_per_s"], 1),

@@ -67,7 +67,7 @@ struct mf_graph {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
     int gr_grid = 1024;
     mf::GrBits bits{};
-    mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0};
+    mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0, 0};
     int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
     int first_chunk = 8;      // BFS levels launched before the first frontier check
     int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
@@ -100,13 +100,14 @@ namespace mf {
 mf_status resolve_tuning(const mf_options& o, Tuning* t) {
     Tuning r{};
     r.kc_option = o.kernel_cycles > 0 ? o.kernel_cycles : 0;
-    r.gr = GrTune{GR_BU_ALPHA, GR_BU_BETA, GR_STAGE_MIN, 0, 0};
+    r.gr = GrTune{GR_BU_ALPHA, GR_BU_BETA, GR_STAGE_MIN, 0, 0, 0};
     r.round_div = 8;
     // environment overrides for experiments, where the option is left 0
     if (const char* env = std::getenv("MF_GR_BU_ALPHA")) r.gr.bu_alpha = std::atoi(env);
     if (const char* env = std::getenv("MF_GR_BU_BETA")) r.gr.bu_beta = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_GR_STAGE_MIN")) r.gr.stage_min = std::atoi(env);
     if (const char* env = std::getenv("MF_GR_BU_LB")) r.gr.bu_lb = std::atoi(env) != 0;
+    if (const char* env = std::getenv("MF_GR_BU_WIDE")) r.gr.bu_wide = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_ROUND_DIV")) r.round_div = std::max(1, std::atoi(env));
     if (o.bfs_alpha > 0) r.gr.bu_alpha = o.bfs_alpha;
     if (o.bfs_alpha < 0) r.gr.bu_alpha = 0;

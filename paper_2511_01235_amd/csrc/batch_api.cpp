@@ -31,7 +31,7 @@ struct mf_batch {
     bool own_stream = false;
     int32_t G = 0;
     mf_options opt{};
-    mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0};
+    mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0, 0};
     std::vector<int32_t> n, kc;
     std::vector<int64_t> vbase, rpbase, sbase, slots, bbase, qbase, used;
     std::vector<int32_t> s_h, t_h;

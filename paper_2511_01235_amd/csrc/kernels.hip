@@ -375,7 +375,7 @@ template <bool FWD, int BS>
 __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, int lv, int cnt,
                                               const int2* qin,
                                               int2* qout, DevCounters* ctr, const GrBits& bits,
-                                              bool bu, bool bu_lb, const unsigned* s_bm) {
+                                              bool bu, bool bu_lb, bool bu_wide, const unsigned* s_bm) {
     __shared__ int s_u[BS];
     __shared__ int s_beg[BS];
     __shared__ int s_pre[BS + 1];
@@ -481,17 +481,32 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
                 int end = beg + min(len, BU_THREAD_SLOTS);
                 exam += 2;  // the row bounds
                 bool hit = false;
-                for (int j = beg; j < end && !hit; j += 4) {
-                    int2 c4[4];
+                if (bu_wide) {
+                    for (int j = beg; j < end && !hit; j += 8) {
+                        int2 c8[8];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) c4[q] = j + q < end ? g.cr[j + q] : make_int2(0, 0);
-                    int32_t r4[4];
+                        for (int q = 0; q < 8; ++q) c8[q] = j + q < end ? g.cr[j + q] : make_int2(0, 0);
+                        int32_t r8[8];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        r4[q] = j + q < end ? (FWD ? g.capsum[j + q] - c4[q].y : c4[q].y) : 0;
+                        for (int q = 0; q < 8; ++q)
+                            r8[q] = j + q < end ? (FWD ? g.capsum[j + q] - c8[q].y : c8[q].y) : 0;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) hit = hit || (r4[q] > 0 && at_level(c4[q].x));
-                    scanned += (unsigned long long)min(4, end - j);
+                        for (int q = 0; q < 8; ++q) hit = hit || (r8[q] > 0 && at_level(c8[q].x));
+                        scanned += (unsigned long long)min(8, end - j);
+                    }
+                } else {
+                    for (int j = beg; j < end && !hit; j += 4) {
+                        int2 c4[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) c4[q] = j + q < end ? g.cr[j + q] : make_int2(0, 0);
+                        int32_t r4[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            r4[q] = j + q < end ? (FWD ? g.capsum[j + q] - c4[q].y : c4[q].y) : 0;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) hit = hit || (r4[q] > 0 && at_level(c4[q].x));
+                        scanned += (unsigned long long)min(4, end - j);
+                    }
                 }
                 if (hit) {
                     g.h[v] = lv + 1;
@@ -629,7 +644,8 @@ __device__ __forceinline__ int gr_level_step(const Par& P, const DevGraph& g, in
         for (int i = threadIdx.x; i < bits.nwords; i += blockDim.x) s_dyn[i] = src[i];
         __syncthreads();
     }
-    gr_level_body<FWD, BS>(P, g, lv, cnt, qin, qout, ctr, bits, bu, tune.bu_lb != 0, stage ? s_dyn : nullptr);
+    gr_level_body<FWD, BS>(P, g, lv, cnt, qin, qout, ctr, bits, bu, tune.bu_lb != 0, tune.bu_wide != 0,
+                           stage ? s_dyn : nullptr);
     return cnt;
 }
 

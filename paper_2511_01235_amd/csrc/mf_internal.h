@@ -98,6 +98,7 @@ struct GrTune {
     int stage_min;  // top-down levels with at least this many entries stage the visited bitmap
     int lds;        // the bitmap fits in LDS (dynamic shared memory provided at launch)
     int bu_lb;      // bottom-up levels stream the unvisited rows slot-parallel (no per-row early exit)
+    int bu_wide;    // bottom-up threads keep eight slot loads in flight instead of four
 };
 
 // One graph of a batched solve: views into the pooled device arrays (slot

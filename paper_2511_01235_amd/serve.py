@@ -100,6 +100,7 @@ class Server:
         self.resident_bytes = 0
         self.reserved = 0
         self.releasing = 0
+        self.now = 0.0
         self.peak_bytes = 0
         self.evictions = 0
         self.errors: list[BaseException] = []
@@ -119,15 +120,24 @@ class Server:
         graphs claimed for eviction are about to give back."""
         return self.resident_bytes + self.reserved - self.releasing
 
+    def _victim_key(self, i: int):
+        """Eviction order: graphs with the fewest requests already waiting,
+        then the least recently used (under load the least recently used
+        graph is the one whose queue has grown longest)."""
+        x = self.g[i]
+        waiting = sum(1 for r in x.pending if r.arrival <= self.now)
+        return waiting, x.last_use
+
     def _claim(self, gi: int, need: int):
-        """Claim least recently used idle graphs for eviction until `need`
-        more bytes fit; they stay busy until _release."""
+        """Claim idle resident graphs for eviction (fewest waiting requests
+        first, then least recently used) until `need` more bytes fit; they
+        stay busy until _release."""
         victims = []
         while self._committed() + need > self.budget:
             idle = self._idle_resident(gi)
             if not idle:
                 break
-            v = min(idle, key=lambda i: self.g[i].last_use)
+            v = min(idle, key=self._victim_key)
             self.g[v].busy = True
             self.releasing += self.g[v].device_bytes
             victims.append(v)
@@ -196,6 +206,7 @@ class Server:
                     if self.remaining == 0 or self.errors:
                         return
                     now = time.perf_counter() - t0
+                    self.now = now
                     r = self._pick(now)
                     if r is not None:
                         break

@@ -71,14 +71,17 @@ def test_initial_labels_bit_exact(name):
     assert np.unique(active).size == active.size
 
 
-@pytest.mark.parametrize("lb", [0, 1])
+@pytest.mark.parametrize("variant", ["rows4", "rows8", "slots"])
 @pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
-def test_bottom_up_levels_bit_exact(name, lb, monkeypatch):
-    """Every BFS level bottom-up (per-row early exit, or slot-parallel rows):
-    heights bit-exact to the oracle's BFS, and the dynamic values too."""
+def test_bottom_up_levels_bit_exact(name, variant, monkeypatch):
+    """Every BFS level bottom-up (per-row early exit with four or eight loads
+    in flight, or slot-parallel rows): heights bit-exact to the oracle's BFS,
+    and the dynamic values too."""
     monkeypatch.setenv("MF_GR_BU_ALPHA", "1000000")
     monkeypatch.setenv("MF_GR_BU_BETA", "1000000")
-    monkeypatch.setenv("MF_GR_BU_LB", str(lb))
+    monkeypatch.setenv("MF_GR_BU_LB", "1" if variant == "slots" else "0")
+    monkeypatch.setenv("MF_GR_BU_WIDE", "1" if variant == "rows8" else "0")
+    lb = variant
     g, stream, k, _ = gen.workload(name)
     say("bottom-up levels", name, "lb", lb)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
