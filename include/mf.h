@@ -85,6 +85,14 @@ typedef struct mf_options {
                                   min cut again and runs push-relabel on its sink side and pull-
                                   relabel on its source side at the same time on two streams,
                                   before the ordinary loop.  0 (default): off.  Same values. */
+    /* Device memory: every buffer a handle (or batch) owns is taken from
+     * alloc(bytes, alloc_ctx) and given back with free(ptr, alloc_ctx), e.g. a
+     * framework's caching allocator (launch the handle on that framework's
+     * stream then).  Both NULL (default): hipMalloc / hipFree.  Setting only
+     * one is MF_ERR_INVALID.  alloc returns NULL when it has no memory. */
+    void* (*alloc)(size_t bytes, void* ctx);
+    void (*free)(void* ptr, void* ctx);
+    void* alloc_ctx;
 } mf_options;
 
 /* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its

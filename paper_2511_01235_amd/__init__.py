@@ -52,7 +52,34 @@ class Options(C.Structure):
                 ("max_iterations", C.c_int64), ("cold_start", C.c_int32), ("relabel_mode", C.c_int32),
                 ("bfs_alpha", C.c_int32), ("bfs_beta", C.c_int32), ("round_div", C.c_int32),
                 ("bin_thread_max", C.c_int32), ("bin_wave_max", C.c_int32), ("batch_block", C.c_int32),
-                ("push_pull", C.c_int32)]
+                ("push_pull", C.c_int32), ("alloc", C.c_void_p), ("free", C.c_void_p),
+                ("alloc_ctx", C.c_void_p)]
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory for a handle from torch's caching allocator (launch the
+    handle on `stream`, e.g. torch.cuda.current_stream()).  Pass as
+    allocator=...; keep the object alive as long as the handle (the handle
+    classes do)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device, self.stream = device, stream
+
+        def _alloc(nbytes, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+            except Exception:
+                return None
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc_fn = ALLOC_FN(_alloc)
+        self.free_fn = FREE_FN(_free)
 
 # fields mf_graph_tune / mf_batch_tune apply to a live handle
 TUNING_FIELDS = ("kernel_cycles", "bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max",
@@ -146,9 +173,12 @@ def mf_default_options() -> Options:
 def make_options(kernel_cycles=0, topology_driven=False, insert_slack_min=0, insert_slack_pct=0,
                  max_iterations=0, stream=None, device=-1, warm_start=True,
                  relabel_mode=0, bfs_alpha=0, bfs_beta=0, round_div=0, bin_thread_max=0, bin_wave_max=0,
-                 batch_block=0, push_pull=False) -> Options:
+                 batch_block=0, push_pull=False, allocator=None) -> Options:
     o = mf_default_options()
     o.push_pull = int(bool(push_pull))
+    if allocator is not None:
+        o.alloc = C.cast(allocator.alloc_fn, C.c_void_p).value
+        o.free = C.cast(allocator.free_fn, C.c_void_p).value
     o.bfs_alpha, o.bfs_beta, o.round_div = int(bfs_alpha), int(bfs_beta), int(round_div)
     o.bin_thread_max, o.bin_wave_max, o.batch_block = int(bin_thread_max), int(bin_wave_max), int(batch_block)
     o.cold_start = 0 if warm_start else 1
@@ -299,6 +329,7 @@ class MaxFlowGraph:
 
     def __init__(self, n, src, dst, cap, s, t, **options):
         self.n, self.s, self.t = int(n), int(s), int(t)
+        self._allocator = options.get("allocator")   # the callbacks must outlive the handle
         opt = make_options(**options) if options else None
         self.h = mf_graph_load(n, src, dst, cap, s, t, opt)
 
@@ -362,6 +393,7 @@ class MaxFlowBatch:
 
     def __init__(self, graphs, **options):
         self.G = len(graphs)
+        self._allocator = options.get("allocator")
         n = np.array([g.n for g in graphs], np.int32)
         off = np.zeros(self.G + 1, np.int64)
         off[1:] = np.cumsum([g.src.size for g in graphs])

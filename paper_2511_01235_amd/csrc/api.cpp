@@ -26,6 +26,7 @@ using mf::DevGraph;
 
 struct mf_graph {
     int device = 0;
+    mf::DeviceAllocator mem;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     mf_options opt{};
@@ -138,13 +139,12 @@ namespace {
 template <class T>
 hipError_t dalloc(mf_graph* g, T** p, int64_t count) {
     size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
-    (void)g;
-    return hipMalloc((void**)p, bytes);
+    return g->mem.allocate((void**)p, bytes);
 }
 
 template <class T>
-void dfree(T*& p) {
-    if (p) (void)hipFree((void*)p);
+void dfree(mf_graph* g, T*& p) {
+    g->mem.release((void*)p);
     p = nullptr;
 }
 
@@ -207,27 +207,27 @@ mf_status read_counters(mf_graph* g) {
 }
 
 void free_structure(mf_graph* g) {
-    dfree(g->dg.row_ptr);
-    dfree(g->dg.row_len);
-    dfree(g->dg.row_sorted);
-    dfree(g->dg.cr);
-    dfree(g->dg.rev);
-    dfree(g->dg.cap);
-    dfree(g->dg.capsum);
-    dfree(g->win);
-    dfree(g->q[0]);
-    dfree(g->q[1]);
+    dfree(g, g->dg.row_ptr);
+    dfree(g, g->dg.row_len);
+    dfree(g, g->dg.row_sorted);
+    dfree(g, g->dg.cr);
+    dfree(g, g->dg.rev);
+    dfree(g, g->dg.cap);
+    dfree(g, g->dg.capsum);
+    dfree(g, g->win);
+    dfree(g, g->q[0]);
+    dfree(g, g->q[1]);
 }
 
 void free_lane2(mf_graph* g) {
-    dfree(g->q2[0]);
-    dfree(g->q2[1]);
+    dfree(g, g->q2[0]);
+    dfree(g, g->q2[1]);
     g->q2_cap = 0;
-    for (auto& w : g->wl2) dfree(w);
-    dfree(g->bits2.visited);
+    for (auto& w : g->wl2) dfree(g, w);
+    dfree(g, g->bits2.visited);
     g->bits2.fb = nullptr;
-    dfree(g->ctr2);
-    dfree(g->h2);
+    dfree(g, g->ctr2);
+    dfree(g, g->h2);
 }
 
 void free_all(mf_graph* g) {
@@ -235,23 +235,23 @@ void free_all(mf_graph* g) {
     if (g->ctr2_h) (void)hipHostFree(g->ctr2_h);
     g->ctr2_h = nullptr;
     free_structure(g);
-    dfree(g->dg.e);
-    dfree(g->dg.h);
-    for (auto& w : g->wl) dfree(w);
-    dfree(g->ctr);
+    dfree(g, g->dg.e);
+    dfree(g, g->dg.h);
+    for (auto& w : g->wl) dfree(g, w);
+    dfree(g, g->ctr);
     if (g->ctr_h) (void)hipHostFree(g->ctr_h);
     g->ctr_h = nullptr;
-    dfree(g->need);
-    dfree(g->slot_of);
-    dfree(g->touched);
-    dfree(g->upd);
-    dfree(g->tb.key);
-    dfree(g->tb.win);
-    dfree(g->tb.slot);
-    dfree(g->side);
-    dfree(g->cut_acc);
-    dfree(g->bits.visited);
-    dfree(g->dg.bytes_part);
+    dfree(g, g->need);
+    dfree(g, g->slot_of);
+    dfree(g, g->touched);
+    dfree(g, g->upd);
+    dfree(g, g->tb.key);
+    dfree(g, g->tb.win);
+    dfree(g, g->tb.slot);
+    dfree(g, g->side);
+    dfree(g, g->cut_acc);
+    dfree(g, g->bits.visited);
+    dfree(g, g->dg.bytes_part);
     for (auto& p : g->ev_pending) {
         (void)hipEventDestroy(p.second.first);
         (void)hipEventDestroy(p.second.second);
@@ -314,21 +314,21 @@ hipError_t halloc(T** p, int64_t count) {
 void free_device_state(mf_graph* g) {
     free_lane2(g);
     free_structure(g);
-    dfree(g->dg.e);
-    dfree(g->dg.h);
-    for (auto& w : g->wl) dfree(w);
-    dfree(g->need);
-    dfree(g->slot_of);
-    dfree(g->touched);
-    dfree(g->upd);
-    dfree(g->tb.key);
-    dfree(g->tb.win);
-    dfree(g->tb.slot);
-    dfree(g->side);
-    dfree(g->cut_acc);
-    dfree(g->bits.visited);
+    dfree(g, g->dg.e);
+    dfree(g, g->dg.h);
+    for (auto& w : g->wl) dfree(g, w);
+    dfree(g, g->need);
+    dfree(g, g->slot_of);
+    dfree(g, g->touched);
+    dfree(g, g->upd);
+    dfree(g, g->tb.key);
+    dfree(g, g->tb.win);
+    dfree(g, g->tb.slot);
+    dfree(g, g->side);
+    dfree(g, g->cut_acc);
+    dfree(g, g->bits.visited);
     g->bits.fb = nullptr;
-    dfree(g->dg.bytes_part);
+    dfree(g, g->dg.bytes_part);
     g->k_cap = 0;
     g->tb.capacity = 0;
 }
@@ -352,12 +352,12 @@ mf_status ensure_batch_capacity(mf_graph* g, int64_t k) {
     int32_t tcap = 64;
     while (tcap < 2 * cap) tcap *= 2;
     MF_HIP(hipStreamSynchronize(g->stream));
-    dfree(g->slot_of);
-    dfree(g->touched);
-    dfree(g->upd);
-    dfree(g->tb.key);
-    dfree(g->tb.win);
-    dfree(g->tb.slot);
+    dfree(g, g->slot_of);
+    dfree(g, g->touched);
+    dfree(g, g->upd);
+    dfree(g, g->tb.key);
+    dfree(g, g->tb.win);
+    dfree(g, g->tb.slot);
     if (dalloc(g, &g->slot_of, cap) != hipSuccess || dalloc(g, &g->touched, cap) != hipSuccess ||
         dalloc(g, &g->upd, cap) != hipSuccess || dalloc(g, &g->tb.key, tcap) != hipSuccess ||
         dalloc(g, &g->tb.win, 2 * (int64_t)tcap) != hipSuccess ||
@@ -628,7 +628,7 @@ mf_status relayout(mf_graph* g) {
     p.slack_pct = g->slack_pct;
     mf::SlotArrays a{g->dg.cr, g->dg.rev, g->dg.cap, g->dg.capsum};
     int64_t S = 0;
-    mf_status rc = mf::relayout_device(p, &a, g->slot_cap, &S, g->dg.row_ptr, g->dg.row_sorted, st);
+    mf_status rc = mf::relayout_device(p, &a, g->slot_cap, &S, g->dg.row_ptr, g->dg.row_sorted, st, g->mem);
     if (rc != MF_OK) {
         if (rc == MF_ERR_DEVICE) g->poisoned = true;
         return rc;
@@ -639,9 +639,9 @@ mf_status relayout(mf_graph* g) {
     g->dg.capsum = a.capsum;
     g->slot_cap = S;
     // arrays whose size follows the slot count
-    dfree(g->win);
-    dfree(g->q[0]);
-    dfree(g->q[1]);
+    dfree(g, g->win);
+    dfree(g, g->q[0]);
+    dfree(g, g->q[1]);
     g->q_cap = (int64_t)g->n + S / mf::GR_CHUNK + 64;
     if (dalloc(g, &g->win, S) != hipSuccess || dalloc(g, &g->q[0], g->q_cap) != hipSuccess ||
         dalloc(g, &g->q[1], g->q_cap) != hipSuccess) {
@@ -714,8 +714,8 @@ mf_status ensure_lane2(mf_graph* g) {
     if (!g->ctr2_h && hipHostMalloc((void**)&g->ctr2_h, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess)
         return MF_ERR_OUT_OF_MEMORY;
     if (g->q2_cap < g->q_cap) {
-        dfree(g->q2[0]);
-        dfree(g->q2[1]);
+        dfree(g, g->q2[0]);
+        dfree(g, g->q2[1]);
         g->q2_cap = 0;
         if (dalloc(g, &g->q2[0], g->q_cap) != hipSuccess || dalloc(g, &g->q2[1], g->q_cap) != hipSuccess)
             return MF_ERR_OUT_OF_MEMORY;
@@ -858,12 +858,16 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     int32_t slack_pct = o.insert_slack_pct > 0 ? o.insert_slack_pct : 12;
     mf::Tuning tuning;
     if (mf::resolve_tuning(o, &tuning) != MF_OK) return MF_ERR_INVALID;
+    if ((o.alloc == nullptr) != (o.free == nullptr)) return MF_ERR_INVALID;
     mf::HostBiCSR b;
     mf_status rc = mf::build_bicsr(n, m, src, dst, cap, s, t, slack_min, slack_pct, &b);
     if (rc != MF_OK) return rc;
 
     mf_graph* g = new (std::nothrow) mf_graph();
     if (!g) return MF_ERR_OUT_OF_MEMORY;
+    g->mem.alloc_fn = o.alloc;
+    g->mem.free_fn = o.free;
+    g->mem.ctx = o.alloc_ctx;
     g->opt = o;
     g->n = n;
     g->s = s;
@@ -1044,10 +1048,10 @@ mf_status mf_get_flow(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, i
     int32_t* h2 = nullptr;
     int32_t* fslot = nullptr;
     auto release = [&] {
-        dfree(cr2);
-        dfree(e2);
-        dfree(h2);
-        dfree(fslot);
+        dfree(g, cr2);
+        dfree(g, e2);
+        dfree(g, h2);
+        dfree(g, fslot);
     };
     if (dalloc(g, &cr2, S) != hipSuccess || dalloc(g, &e2, n) != hipSuccess ||
         dalloc(g, &h2, n) != hipSuccess || dalloc(g, &fslot, S) != hipSuccess) {

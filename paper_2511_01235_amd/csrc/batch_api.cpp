@@ -27,6 +27,7 @@ using mf::GraphUpdates;
 
 struct mf_batch {
     int device = 0;
+    mf::DeviceAllocator mem;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int32_t G = 0;
@@ -75,14 +76,26 @@ struct mf_batch {
 
 namespace {
 
+// The batch being built or freed: its allocator serves every pool.
+thread_local const mf::DeviceAllocator* t_mem = nullptr;
+
+struct UseAllocator {
+    const mf::DeviceAllocator* prev;
+    explicit UseAllocator(const mf::DeviceAllocator& m) : prev(t_mem) { t_mem = &m; }
+    ~UseAllocator() { t_mem = prev; }
+};
+
 template <class T>
 hipError_t balloc(T** p, int64_t count) {
-    return hipMalloc((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+    size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    if (t_mem) return t_mem->allocate((void**)p, bytes);
+    return hipMalloc((void**)p, bytes);
 }
 
 template <class T>
 void bfree(T*& p) {
-    if (p) (void)hipFree((void*)p);
+    if (t_mem) t_mem->release((void*)p);
+    else if (p) (void)hipFree((void*)p);
     p = nullptr;
 }
 
@@ -292,7 +305,7 @@ mf_status relayout_pool(mf_batch* b, const int32_t* need_d, const std::vector<ch
     p.slack_pct = b->slack_pct;
     mf::SlotArrays a{b->cr, b->rev, b->cap, b->capsum};
     int64_t S = 0;
-    mf_status rc = mf::relayout_device(p, &a, b->total_s, &S, b->row_ptr, b->row_sorted, st);
+    mf_status rc = mf::relayout_device(p, &a, b->total_s, &S, b->row_ptr, b->row_sorted, st, b->mem);
     if (rc != MF_OK) {
         if (rc == MF_ERR_DEVICE) b->poisoned = true;
         return rc;
@@ -355,8 +368,13 @@ mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edg
                                        m ? cap + e0 : nullptr, s[i], t[i], slack_min, slack_pct, &hb[(size_t)i]);
         if (rc != MF_OK) return rc;
     }
+    if ((o.alloc == nullptr) != (o.free == nullptr)) return MF_ERR_INVALID;
     mf_batch* b = new (std::nothrow) mf_batch();
     if (!b) return MF_ERR_OUT_OF_MEMORY;
+    b->mem.alloc_fn = o.alloc;
+    b->mem.free_fn = o.free;
+    b->mem.ctx = o.alloc_ctx;
+    UseAllocator use(b->mem);
     auto fail = [&](mf_status r) {
         free_batch(b);
         if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -447,6 +465,7 @@ mf_status mf_batch_apply(mf_batch* b, const int64_t* update_offset, const mf_upd
     if (K > 0 && !upd) return MF_ERR_INVALID;
     if (hipSetDevice(b->device) != hipSuccess) return MF_ERR_DEVICE;
     Clock clock(b);
+    UseAllocator use(b->mem);
     hipStream_t st = b->stream;
     // scratch: updates, per-update slots, one hash table per graph
     std::vector<int64_t> toff((size_t)G + 1, 0);
@@ -559,6 +578,7 @@ mf_status mf_batch_info(const mf_batch* b, int32_t* iterations, double* last_ms)
 
 void mf_batch_free(mf_batch* b) {
     if (!b) return;
+    UseAllocator use(b->mem);
     (void)hipSetDevice(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     free_batch(b);

@@ -174,6 +174,24 @@ struct RelayoutPlan {
     int32_t* sort_count;       // 1
 };
 
+// Where a handle's device buffers come from: the caller's allocator when
+// mf_options sets one, else hipMalloc / hipFree.
+struct DeviceAllocator {
+    void* (*alloc_fn)(size_t, void*) = nullptr;
+    void (*free_fn)(void*, void*) = nullptr;
+    void* ctx = nullptr;
+    hipError_t allocate(void** p, size_t bytes) const {
+        if (!alloc_fn) return hipMalloc(p, bytes);
+        *p = alloc_fn(bytes, ctx);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    void release(void* p) const {
+        if (!p) return;
+        if (free_fn) free_fn(p, ctx);
+        else (void)hipFree(p);
+    }
+};
+
 // Tuning of a handle resolved from mf_options (0 = default).
 struct Tuning {
     int32_t kc_option;   // 0: round(m/n) per graph
@@ -271,7 +289,7 @@ mf_status build_bicsr(int32_t n, int64_t m, const int32_t* src, const int32_t* d
 // On error nothing has changed (MF_ERR_OVERFLOW: more than INT32_MAX - 1
 // slots; MF_ERR_OUT_OF_MEMORY; MF_ERR_DEVICE).
 mf_status relayout_device(RelayoutPlan p, SlotArrays* arrays, int64_t S_old, int64_t* S_new, int32_t* row_ptr,
-                          int32_t* row_sorted, hipStream_t st);
+                          int32_t* row_sorted, hipStream_t st, const DeviceAllocator& mem);
 
 
 }  // namespace mf

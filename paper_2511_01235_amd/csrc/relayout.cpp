@@ -15,21 +15,21 @@ namespace mf {
 
 namespace {
 
-template <class T>
-hipError_t alloc(T** p, int64_t count) {
-    return hipMalloc((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
-}
-
-template <class T>
-void release(T*& p) {
-    if (p) (void)hipFree((void*)p);
-    p = nullptr;
-}
-
 struct Scratch {
+    const DeviceAllocator& mem;
     int64_t *size = nullptr, *start = nullptr, *tile = nullptr;
     int32_t *sort_rows = nullptr, *sort_count = nullptr, *src_of = nullptr, *where = nullptr;
     SlotArrays to{nullptr, nullptr, nullptr, nullptr};
+    explicit Scratch(const DeviceAllocator& m) : mem(m) {}
+    template <class T>
+    hipError_t alloc(T** p, int64_t count) {
+        return mem.allocate((void**)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+    }
+    template <class T>
+    void release(T*& p) {
+        mem.release((void*)p);
+        p = nullptr;
+    }
     ~Scratch() {
         release(size); release(start); release(tile); release(sort_rows); release(sort_count);
         release(src_of); release(where);
@@ -40,10 +40,10 @@ struct Scratch {
 }  // namespace
 
 mf_status relayout_device(RelayoutPlan p, SlotArrays* arrays, int64_t S_old, int64_t* S_new, int32_t* row_ptr,
-                          int32_t* row_sorted, hipStream_t st) {
-    Scratch x;
-    if (alloc(&x.size, p.V) || alloc(&x.start, (int64_t)p.V + 1) || alloc(&x.tile, relayout_tiles(p.V)) ||
-        alloc(&x.sort_rows, p.V) || alloc(&x.sort_count, 1))
+                          int32_t* row_sorted, hipStream_t st, const DeviceAllocator& mem) {
+    Scratch x(mem);
+    if (x.alloc(&x.size, p.V) || x.alloc(&x.start, (int64_t)p.V + 1) || x.alloc(&x.tile, relayout_tiles(p.V)) ||
+        x.alloc(&x.sort_rows, p.V) || x.alloc(&x.sort_count, 1))
         return MF_ERR_OUT_OF_MEMORY;
     p.size = x.size;
     p.start = x.start;
@@ -59,8 +59,8 @@ mf_status relayout_device(RelayoutPlan p, SlotArrays* arrays, int64_t S_old, int
         hipStreamSynchronize(st) != hipSuccess)
         return MF_ERR_DEVICE;
     if (total < S_old || total > (int64_t)INT_MAX - 1) return MF_ERR_OVERFLOW;
-    if (alloc(&x.src_of, total) || alloc(&x.where, S_old) || alloc(&x.to.cr, total) || alloc(&x.to.rev, total) ||
-        alloc(&x.to.cap, total) || alloc(&x.to.capsum, total))
+    if (x.alloc(&x.src_of, total) || x.alloc(&x.where, S_old) || x.alloc(&x.to.cr, total) ||
+        x.alloc(&x.to.rev, total) || x.alloc(&x.to.cap, total) || x.alloc(&x.to.capsum, total))
         return MF_ERR_OUT_OF_MEMORY;
     launch_relayout_move(p, sorts, total, *arrays, x.to, x.src_of, x.where, row_ptr, row_sorted, st);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return MF_ERR_DEVICE;

@@ -102,22 +102,26 @@ def counter_pass(path, kernel):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("kt_dir")
-    ap.add_argument("fetch_dir")
-    ap.add_argument("write_dir")
+    ap.add_argument("fetch_dir", nargs="?")
+    ap.add_argument("write_dir", nargs="?")
     ap.add_argument("--kernel", default="k_gr_level")
     ap.add_argument("--command", default="")
     ap.add_argument("--title", default="")
     args = ap.parse_args()
     kt = _rows(os.path.join(args.kt_dir, "run_kernel_trace.csv"))
-    a, b = timed_window(kt)
-    wt, agg = window_table(kt, a, b)
-    mine = [d for k, d in agg.items() if args.kernel in k]
-    durs = [x for d in mine for x in d]
     print(f"# {args.title or args.kernel}\n")
     if args.command:
         print("Commands (each from the repository root):\n\n```\n" + args.command.strip() + "\n```\n")
     print("## Whole run (rocprofv3 --stats)\n")
     print(stats_table(os.path.join(args.kt_dir, "run_kernel_stats.csv")) + "\n")
+    if not args.fetch_dir:
+        durs = [_dur_us(r) for r in kt if args.kernel in _name(r)]
+        print(f"`{args.kernel}` over the whole run: {len(durs)} launches, average {np.mean(durs):.2f} us")
+        return
+    a, b = timed_window(kt)
+    wt, agg = window_table(kt, a, b)
+    mine = [d for k, d in agg.items() if args.kernel in k]
+    durs = [x for d in mine for x in d]
     print("## Timed window (after the calibration copy, before the first from-scratch solve)\n")
     print(wt + "\n")
     print(f"`{args.kernel}` in the window: {len(durs)} launches, average {np.mean(durs):.2f} us\n")

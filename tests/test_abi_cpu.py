@@ -92,3 +92,34 @@ def test_batch_load_rejects_invalid():
     assert rc == mf.MF_ERR_INVALID and not h.value
     assert L.mf_batch_maxflow(None, None) == mf.MF_ERR_INVALID
     L.mf_batch_free(None)
+
+
+def test_half_an_allocator_is_rejected():
+    """mf_options.alloc without .free (or the reverse) is refused before any
+    device work, for graphs and batches."""
+    import ctypes as C
+    o = mf.mf_default_options()
+    cb = mf.ALLOC_FN(lambda n, ctx: None)
+    o.alloc = C.cast(cb, C.c_void_p).value
+    src, dst, cap = (np.array([0], np.int32), np.array([1], np.int32), np.array([5], np.int32))
+    with pytest.raises(mf.MFError) as ei:
+        mf.mf_graph_load(3, src, dst, cap, 0, 2, o)
+    assert ei.value.status == mf.MF_ERR_INVALID
+    h = C.c_void_p()
+    n = np.array([3], np.int32)
+    off = np.array([0, 1], np.int64)
+    s = np.array([0], np.int32)
+    t = np.array([2], np.int32)
+    st = mf.lib().mf_batch_load(1, n.ctypes.data, off.ctypes.data, src.ctypes.data, dst.ctypes.data,
+                                cap.ctypes.data, s.ctypes.data, t.ctypes.data, C.byref(o), C.byref(h))
+    assert st == mf.MF_ERR_INVALID and not h.value
+
+
+def test_bad_tuning_is_rejected():
+    o = mf.make_options(bin_thread_max=64, bin_wave_max=32)
+    src, dst, cap = (np.array([0], np.int32), np.array([1], np.int32), np.array([5], np.int32))
+    with pytest.raises(mf.MFError) as ei:
+        mf.mf_graph_load(3, src, dst, cap, 0, 2, o)
+    assert ei.value.status == mf.MF_ERR_INVALID
+    with pytest.raises(mf.MFError):
+        mf.mf_graph_load(3, src, dst, cap, 0, 2, mf.make_options(batch_block=300))

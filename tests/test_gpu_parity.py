@@ -532,6 +532,40 @@ def test_push_pull_matches_oracle(name, relabel_mode):
             _cut_ok(g.n, g.s, g.t, side, cut, got, ms, md, mc)
 
 
+def test_caller_allocator_torch():
+    """Device memory from torch's caching allocator: values unchanged, the
+    memory shows up in torch's accounting while the handle lives (also
+    across a re-layout) and is given back when it is freed."""
+    import torch
+    g, stream, k, _ = gen.workload("rmat12")
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    st = torch.cuda.current_stream()
+    alloc = mf.TorchAllocator(device=0, stream=st)
+    G = mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=st, device=0, allocator=alloc,
+                        insert_slack_min=1, insert_slack_pct=1)
+    try:
+        held = torch.cuda.memory_allocated() - base
+        assert held >= G.stats()["slot_capacity"] * 16
+        assert G.maxflow() == o.static()
+        for _ in range(3):
+            b = stream.next_batch(4 * k)
+            assert G.apply_batch(*b) == o.apply(*b)
+        assert G.stats()["relayouts"] >= 1
+    finally:
+        G.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base
+    graphs = gen.batched_graphs(4, seed=79900, n_lo=500, n_hi=3e3)
+    want = [oracle.max_flow(x.n, x.src, x.dst, x.cap, x.s, x.t) for x in graphs]
+    with mf.MaxFlowBatch(graphs, stream=st, device=0, allocator=alloc) as B:
+        assert torch.cuda.memory_allocated() > base
+        assert B.maxflow().tolist() == want
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base
+
+
 # --- batched solve: many graphs in one launch -----------------------------------
 
 def _batch_streams(graphs, seed=42000):
