@@ -145,9 +145,16 @@ def main():
     # `rocprofv3 --pmc FETCH_SIZE` / `WRITE_SIZE` it calibrates the counters' units
     cal_src = torch.ones(64 << 20, dtype=torch.int32, device=dev)
     cal_dst = torch.empty_like(cal_src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
     cal_dst.copy_(cal_src)
+    ev1.record()
     torch.cuda.synchronize()
+    copy_gbs = 2 * cal_src.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del cal_src, cal_dst
+    # scattered-atomic reference rates for the push and relabel kernels
+    atomic_rates = {f"int{8 * w}_ops_per_s": round(mf.mf_debug_atomic_probe(1 << 26, w, 0), 1) for w in (4, 8)}
+    log(f"copy probe {copy_gbs:.0f} GB/s; atomics {atomic_rates}")
 
     dev_batches = [torch.from_numpy(np.ascontiguousarray(np.stack(b, 1).astype(np.int32))).to(dev)
                    for b in batches_np]
@@ -216,7 +223,8 @@ def main():
                 "traffic": traffic, "launches": launches,
                 "avg_launch_us": round(kms * 1e3 / launches, 3) if launches else None,
                 "alg_bytes_per_launch": round(kbytes / launches, 1) if launches else None,
-                "share_of_step": round(kms / elapsed_ms, 4) if elapsed_ms > 0 else None}
+                "share_of_step": round(kms / elapsed_ms, 4) if elapsed_ms > 0 else None,
+                "copy_probe_gbs": round(copy_gbs, 1), "atomic_probe": atomic_rates}
 
     cpu = None
     if not args.no_cpu:

@@ -253,6 +253,14 @@ mf_status mf_debug_initial_labels(mf_graph* g, int32_t* heights, int64_t* excess
  * MF_ERR_DEVICE otherwise. */
 mf_status mf_debug_selftest(int32_t device);
 
+/* Diagnostic: atomic throughput on `device` (-1: current): n atomicAdds of
+ * `width` bytes (4 or 8) spread over n distinct addresses in a scattered
+ * order (n below 2^31), timed with HIP events after one warm-up
+ * launch; *ops_per_s receives the rate.  The reference point for the push and
+ * relabel kernels, whose updates are scattered atomics.  Errors:
+ * MF_ERR_INVALID, MF_ERR_DEVICE. */
+mf_status mf_debug_atomic_probe(int32_t device, int64_t n, int32_t width, double* ops_per_s);
+
 /* Release the handle and its device memory.  NULL is ignored. */
 void mf_graph_free(mf_graph* g);
 

@@ -31,7 +31,7 @@ MF_ERR_STATE = 6
 # every symbol include/mf.h declares
 EXPORTED = ["mf_default_options", "mf_status_string", "mf_graph_load", "mf_maxflow",
             "mf_apply_batch", "mf_apply_batch_device", "mf_min_cut", "mf_get_flow", "mf_get_edges",
-            "mf_graph_offload", "mf_graph_restore", "mf_graph_tune", "mf_get_stats", "mf_profile", "mf_debug_initial_labels", "mf_debug_selftest",
+            "mf_graph_offload", "mf_graph_restore", "mf_graph_tune", "mf_get_stats", "mf_profile", "mf_debug_initial_labels", "mf_debug_selftest", "mf_debug_atomic_probe",
             "mf_graph_free", "mf_batch_load", "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info",
             "mf_batch_tune", "mf_batch_free"]
 
@@ -132,6 +132,7 @@ def lib():
         L.mf_profile.argtypes = [vp, i32]
         L.mf_debug_initial_labels.argtypes = [vp, vp, vp, vp, C.POINTER(i32)]
         L.mf_debug_selftest.argtypes = [i32]
+        L.mf_debug_atomic_probe.argtypes = [i32, i64, i32, C.POINTER(C.c_double)]
         L.mf_graph_free.argtypes = [vp]
         L.mf_graph_free.restype = None
         L.mf_batch_load.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Options), C.POINTER(vp)]
@@ -144,7 +145,7 @@ def lib():
                      "mf_min_cut", "mf_get_flow", "mf_get_edges", "mf_graph_offload", "mf_graph_restore",
                      "mf_graph_tune", "mf_batch_tune",
                      "mf_get_stats", "mf_profile",
-                     "mf_debug_initial_labels", "mf_debug_selftest", "mf_batch_load",
+                     "mf_debug_initial_labels", "mf_debug_selftest", "mf_debug_atomic_probe", "mf_batch_load",
                      "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info"]:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -317,6 +318,13 @@ def mf_debug_initial_labels(g, n: int):
 
 def mf_debug_selftest(device: int = -1) -> int:
     return int(lib().mf_debug_selftest(int(device)))
+
+
+def mf_debug_atomic_probe(n: int = 1 << 26, width: int = 4, device: int = -1) -> float:
+    """Scattered atomicAdd throughput (ops/s) on n distinct addresses."""
+    r = C.c_double()
+    _check(lib().mf_debug_atomic_probe(int(device), int(n), int(width), C.byref(r)), "mf_debug_atomic_probe")
+    return r.value
 
 
 def mf_graph_free(g):

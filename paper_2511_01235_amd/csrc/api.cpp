@@ -1319,6 +1319,19 @@ mf_status mf_debug_initial_labels(mf_graph* g, int32_t* heights, int64_t* excess
     return MF_OK;
 }
 
+mf_status mf_debug_atomic_probe(int32_t device, int64_t n, int32_t width, double* ops_per_s) {
+    if (!ops_per_s || n < 1 || n > INT_MAX || (width != 4 && width != 8)) return MF_ERR_INVALID;
+    if (device >= 0 && hipSetDevice(device) != hipSuccess) return MF_ERR_DEVICE;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return MF_ERR_DEVICE;
+    double r = mf::atomic_probe(n, width, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    if (r < 0) return MF_ERR_DEVICE;
+    *ops_per_s = r;
+    return MF_OK;
+}
+
 mf_status mf_debug_selftest(int32_t device) {
     if (device >= 0 && hipSetDevice(device) != hipSuccess) return MF_ERR_DEVICE;
     hipStream_t st = nullptr;

@@ -970,9 +970,16 @@ __device__ __forceinline__ unsigned long long pr_wave_item(DevGraph& g, int u, i
 
 template <bool PULL, int BS>
 __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, int kc) {
+    // Long rows: one pass per cycle.  While it looks for the lowest
+    // neighbour, the pass already pushes to every residual slot whose
+    // neighbour is at h(u) - 1 -- under a valid labelling the lowest height a
+    // neighbour can have, so these are the pushes Algorithm 2's next cycles
+    // would make -- until the excess is gone.  Excess left over: the minimum
+    // of the pass decides as in Algorithm 2 (relabel to it + 1, or a push to
+    // a lower slot left by stale heights).
     __shared__ unsigned long long part[BS / WAVE];
     __shared__ int64_t e_sh;
-    __shared__ unsigned long long taken;   // excess handed out by the current cycle
+    __shared__ unsigned long long taken;   // excess handed out by the current pass
     const int N = g.n;
     const int lane = lane_id();
     const int wv = threadIdx.x / WAVE;
@@ -981,73 +988,84 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
     int hu = g.h[u];
     unsigned long long bytes = 16;
     for (int c = 0; c < kc && hu < N; ++c) {
-        if (threadIdx.x == 0) e_sh = amount<PULL>(g, u);
+        if (threadIdx.x == 0) {
+            e_sh = amount<PULL>(g, u);
+            taken = 0ull;
+        }
         __syncthreads();
-        int64_t eu = e_sh;
+        const int64_t eu = e_sh;
         __syncthreads();
         if (eu <= 0) continue;
+        const unsigned target = (unsigned)(hu - 1);
         unsigned long long best = ~0ull;
-        for (int b = beg; b < end; b += PR_UNROLL_BLOCK * BS)
-            scan_group<PULL, PR_UNROLL_BLOCK, BS>(g, b + threadIdx.x, end, best);
+        bool done = false;
+        for (int b0 = beg; b0 < end && !done; b0 += PR_UNROLL_BLOCK * BS) {
+            const int b = b0 + threadIdx.x;
+            unsigned long long sv[PR_UNROLL_BLOCK];
+#pragma unroll
+            for (int q = 0; q < PR_UNROLL_BLOCK; ++q) {
+                int j = b + q * BS;
+                sv[q] = j < end ? ld_slot(g.cr, j) : 0ull;
+            }
+            int32_t r[PR_UNROLL_BLOCK];
+#pragma unroll
+            for (int q = 0; q < PR_UNROLL_BLOCK; ++q) {
+                int j = b + q * BS;
+                r[q] = j < end ? (PULL ? ld_res(g.cr, g.rev[j]) : (int32_t)(sv[q] >> 32)) : 0;
+            }
+            unsigned hv[PR_UNROLL_BLOCK];
+#pragma unroll
+            for (int q = 0; q < PR_UNROLL_BLOCK; ++q) hv[q] = r[q] > 0 ? (unsigned)g.h[(int)(unsigned)sv[q]] : 0u;
+#pragma unroll
+            for (int q = 0; q < PR_UNROLL_BLOCK; ++q) {
+                const int j = b + q * BS;
+                const bool cand = r[q] > 0 && hv[q] == target;
+                if (r[q] > 0) {
+                    unsigned long long key = ((unsigned long long)hv[q] << 32) | (unsigned)j;
+                    if (key < best) best = key;
+                }
+                long long tot;
+                long long ex = wave_excl_scan64(cand ? (long long)r[q] : 0ll, &tot);
+                if (tot == 0) continue;  // wave-uniform
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(&taken, (unsigned long long)tot);
+                const int64_t before = (int64_t)bcast64((long long)base) + ex;
+                if (cand && before < eu) {
+                    int64_t room = eu - before;
+                    move_along<PULL>(g, j, room < (int64_t)r[q] ? (int32_t)room : r[q]);
+                    bytes += 48;
+                }
+            }
+            bytes += 12ull * PR_UNROLL_BLOCK;
+            done = (int64_t)bcast64((long long)taken) >= eu;  // wave-uniform: this wave stops
+        }
         best = wave_min_u64(best);
         if (lane == 0) part[wv] = best;
         __syncthreads();
         unsigned long long x = lane < BS / WAVE ? part[lane] : ~0ull;
         best = wave_min_u64(x);  // every wave computes the same block minimum
+        const int64_t moved = (int64_t)taken < eu ? (int64_t)taken : eu;
         __syncthreads();
-        bytes += 12ull * (unsigned long long)(end - beg);
+        if (threadIdx.x == 0 && moved) add_e(g.e, u, PULL ? moved : -moved);
+        if (moved >= eu) continue;  // the excess is gone (more may arrive)
+        // excess left: the scan saw the whole row
         if (best == ~0ull) {
             hu = N;
             if (threadIdx.x == 0) g.h[u] = N;
             break;
         }
-        int bh = (int)(best >> 32);
-        int bj = (int)(unsigned)best;
-        if (hu <= bh) {
+        const int bh = (int)(best >> 32);
+        const int bj = (int)(unsigned)best;
+        if (bh < hu - 1) {
+            // a neighbour below h(u) - 1 (heights moved meanwhile): push there
+            if (threadIdx.x == 0) do_push<PULL>(g, u, bj, eu - moved);
+            bytes += 48;
+        } else if (bh >= hu) {
             hu = bh + 1 < N ? bh + 1 : N;
             if (threadIdx.x == 0) g.h[u] = hu;
             bytes += 4;
-            if (hu >= N || ++c >= kc) break;
         }
-        // push to bj first, then every other slot of the row still at height
-        // bh takes what is left in the order the threads claim it (an LDS
-        // running total), until the excess is gone
-        if (threadIdx.x == 0) {
-            int32_t r = scan_res<PULL>(g, bj);
-            int32_t d = eu < (int64_t)r ? (int32_t)eu : r;
-            if (d > 0) move_along<PULL>(g, bj, d);
-            taken = d > 0 ? (unsigned long long)d : 0ull;
-            bytes += 48;
-        }
-        __syncthreads();
-        for (int b = beg + threadIdx.x; b < end && (int64_t)taken < eu; b += PR_UNROLL_BLOCK * BS) {
-            unsigned long long sv[PR_UNROLL_BLOCK];
-#pragma unroll
-            for (int q = 0; q < PR_UNROLL_BLOCK; ++q) {
-                int j = b + q * BS;
-                sv[q] = j < end && j != bj ? ld_slot(g.cr, j) : 0ull;
-            }
-#pragma unroll
-            for (int q = 0; q < PR_UNROLL_BLOCK; ++q) {
-                int j = b + q * BS;
-                if (j >= end || j == bj) continue;
-                int32_t r = PULL ? ld_res(g.cr, g.rev[j]) : (int32_t)(sv[q] >> 32);
-                if (r <= 0 || g.h[(int)(unsigned)sv[q]] != bh) continue;
-                int64_t before = (int64_t)atomicAdd(&taken, (unsigned long long)r);
-                if (before < eu) {
-                    int64_t room = eu - before;
-                    move_along<PULL>(g, j, room < (int64_t)r ? (int32_t)room : r);
-                    bytes += 48;
-                }
-            }
-            bytes += 12ull * PR_UNROLL_BLOCK;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int64_t moved = (int64_t)taken < eu ? (int64_t)taken : eu;
-            if (moved) add_e(g.e, u, PULL ? moved : -moved);
-        }
-        __syncthreads();
+        // bh == hu - 1: those slots were saturated by this pass; the next pass rescans
     }
     __syncthreads();  // part / e_sh / taken are reused by the next item
     return bytes;
@@ -1861,6 +1879,17 @@ __global__ void __launch_bounds__(RL_BLOCK) k_relayout_row_ptr(RelayoutPlan p, i
     if (last) row_ptr[gv + i + 1] = (int32_t)p.start[gv + 1];
 }
 
+// Atomic-throughput probe: op i adds 1 at address (i * 2654435761) mod n.
+// 2654435761 is prime, so for n below it the map is a permutation of
+// 0..n-1: n ops hit n distinct addresses in a scattered order.
+template <class T>
+__global__ void __launch_bounds__(256) k_atomic_probe(T* buf, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t a = (int64_t)(((unsigned long long)i * 2654435761ull) % (unsigned long long)n);
+        atomicAdd(&buf[a], (T)1);
+    }
+}
+
 }  // namespace
 
 // ---- launch wrappers ----------------------------------------------------------
@@ -2107,6 +2136,33 @@ void launch_relayout_move(const RelayoutPlan& p, int32_t sort_count, int64_t S_n
     k_relayout_gather<<<blocks, RL_BLOCK, 0, st>>>(p, src_of, from, to, where, S_new);
     k_relayout_rev<<<blocks, RL_BLOCK, 0, st>>>(src_of, from.rev, where, to.rev, S_new);
     k_relayout_row_ptr<<<(p.V + RL_BLOCK - 1) / RL_BLOCK, RL_BLOCK, 0, st>>>(p, row_ptr);
+}
+
+double atomic_probe(int64_t n, int width, hipStream_t st) {
+    if (n >= 2654435761ll) return -1.0;
+    void* buf = nullptr;
+    size_t bytes = (size_t)n * (width == 8 ? 8 : 4);
+    if (hipMalloc(&buf, bytes) != hipSuccess) return -1.0;
+    hipEvent_t a = nullptr, b = nullptr;
+    double rate = -1.0;
+    if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
+        hipMemsetAsync(buf, 0, bytes, st) == hipSuccess) {
+        const int grid = 4096;
+        for (int rep = 0; rep < 2; ++rep) {  // the first launch warms up
+            (void)hipEventRecord(a, st);
+            if (width == 8) k_atomic_probe<unsigned long long><<<grid, 256, 0, st>>>((unsigned long long*)buf, n);
+            else k_atomic_probe<unsigned><<<grid, 256, 0, st>>>((unsigned*)buf, n);
+            (void)hipEventRecord(b, st);
+        }
+        float ms = 0.f;
+        if (hipGetLastError() == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+            hipEventElapsedTime(&ms, a, b) == hipSuccess && ms > 0.f)
+            rate = (double)n / (ms * 1e-3);
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipFree(buf);
+    return rate;
 }
 
 int device_selftest(hipStream_t st) {

@@ -261,6 +261,8 @@ void launch_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu, const int32_t
 // After a failed validation: scratch back to idle for every graph.
 void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st);
 int64_t relayout_tiles(int32_t V);
+// n scattered atomicAdds of `width` bytes (4 or 8) on n distinct addresses; ops/s, < 0 on failure
+double atomic_probe(int64_t n, int width, hipStream_t st);
 // sizes, their scan into start[] and the rows to sort; then the caller reads
 // start[V] (the new slot count) and *sort_count
 void launch_relayout_plan(const RelayoutPlan& p, hipStream_t st);

@@ -52,6 +52,14 @@ def test_selftest():
     assert mf.mf_debug_selftest(0) == mf.MF_OK
 
 
+def test_atomic_probe_runs():
+    for width in (4, 8):
+        rate = mf.mf_debug_atomic_probe(1 << 20, width, 0)
+        assert rate > 1e8, (width, rate)
+    with pytest.raises(mf.MFError):
+        mf.mf_debug_atomic_probe(0, 4, 0)
+
+
 # --- global relabel and worklist, bit-exact -------------------------------------
 
 @pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
