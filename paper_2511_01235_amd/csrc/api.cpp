@@ -73,6 +73,13 @@ struct mf_graph {
     int first_chunk = 8;      // BFS levels launched before the first frontier check
     int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
     int32_t round_max = 4096; // ... at most this many
+    bool incremental_rounds = true;  // rounds take their worklist from the previous one plus activations
+    int32_t narrow_max = 4096;       // BFS frontiers up to this many entries run in one workgroup (0: never)
+    // incremental worklists between relabels (made on first use)
+    int32_t* act_list = nullptr;   // vertices whose excess turned positive in a round
+    int32_t* mark = nullptr;       // per vertex: the round that last listed it
+    int32_t* wlb[3] = {nullptr, nullptr, nullptr};  // second set of degree-bin worklists
+    int32_t epoch = 0;
     // parallel push-pull repair (Section 5.2, O2): the pull side's lane and
     // heights, made on first use
     int32_t push_pull = 0;
@@ -219,7 +226,15 @@ void free_structure(mf_graph* g) {
     dfree(g, g->q[1]);
 }
 
+void free_round_lists(mf_graph* g) {
+    dfree(g, g->act_list);
+    dfree(g, g->mark);
+    for (auto& w : g->wlb) dfree(g, w);
+    g->epoch = 0;
+}
+
 void free_lane2(mf_graph* g) {
+    free_round_lists(g);
     dfree(g, g->q2[0]);
     dfree(g, g->q2[1]);
     g->q2_cap = 0;
@@ -446,7 +461,30 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
     timed(g, m.L, mf::KC_GR, [&] { mf::launch_gr_init(m.dg, m.L.q[0], m.L.ctr, m.L.bits, m.seed_deficits, st); });
     int level = 0;
     int chunk = g->first_chunk;
+    // thin frontiers run in one workgroup, several levels per launch; the
+    // first frontier is tried that way, later ones when a chunk leaves one
+    // small enough
+    bool narrow = g->narrow_max > 0;
     for (;;) {
+        if (narrow) {
+            timed(g, m.L, mf::KC_GR, [&] {
+                mf::launch_gr_narrow(m.dg, level, m.L.q[0], m.L.q[1], m.L.ctr, m.L.bits, g->narrow_max, m.forward,
+                                     st);
+            });
+            MF_HIP(hipGetLastError());
+            mf_status rc = read_lane(g, m.L);
+            if (rc != MF_OK) return rc;
+            level = m.L.ctr_h->levels;
+            const int cnt = (int)(unsigned)(m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull);
+            if (cnt == 0) break;
+            if (level > g->n + 2) {
+                g->poisoned = true;
+                return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
+            }
+            // the multi-block levels read the current frontier's bitmap
+            mf::launch_frontier_bitmap(m.L.q[level & 1], cnt, m.L.bits, level, st);
+            chunk = g->first_chunk;
+        }
         for (int i = 0; i < chunk; ++i, ++level)
             timed(g, m.L, mf::KC_GR, [&] {
                 mf::launch_gr_level(m.dg, level, m.L.q[level & 1], m.L.q[(level + 1) & 1], m.L.ctr,
@@ -455,12 +493,14 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
         MF_HIP(hipGetLastError());
         mf_status rc = read_lane(g, m.L);
         if (rc != MF_OK) return rc;
-        if ((m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull) == 0) break;
+        const int cnt = (int)(unsigned)(m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull);
+        if (cnt == 0) break;
         if (level > g->n + 2) {
             g->poisoned = true;
             return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
         }
         chunk = std::min(chunk * 2, 64);
+        narrow = g->narrow_max > 0 && cnt <= g->narrow_max;
     }
     *levels_out += level;
     return MF_OK;
@@ -509,17 +549,33 @@ mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) 
 // more hop.  R is the relabel's depth divided by round_div (at least 1): a
 // deep BFS (long augmenting paths) buys many cheap rounds, a shallow one
 // keeps the paper's one sweep per relabel.
-mf_status push_round(mf_graph* g, const LoopMode& m, const int cnt[3]) {
+mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const int cnt[3]) {
     hipStream_t st = m.L.stream;
     for (int b = 0; b < 3; ++b)
         if (cnt[b])
             timed(g, m.L, mf::KC_PR, [&] {
-                mf::launch_push_relabel(m.dg, m.L.wl[b], cnt[b], b, g->kc, m.pull, m.L.ctr, st);
+                mf::launch_push_relabel(m.dg, wl[b], cnt[b], b, g->kc, m.pull, m.L.ctr, st);
             });
     if (m.rie)
         for (int b = 0; b < 3; ++b)
             if (cnt[b])
-                timed(g, m.L, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, m.L.wl[b], cnt[b], b, m.L.ctr, st); });
+                timed(g, m.L, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, wl[b], cnt[b], b, m.L.ctr, st); });
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+// Buffers of the incremental worklists between relabels.
+mf_status ensure_round_lists(mf_graph* g) {
+    if (g->act_list) return MF_OK;
+    const int64_t n = g->n;
+    if (dalloc(g, &g->act_list, n) != hipSuccess || dalloc(g, &g->mark, n) != hipSuccess ||
+        dalloc(g, &g->wlb[0], n) != hipSuccess || dalloc(g, &g->wlb[1], n) != hipSuccess ||
+        dalloc(g, &g->wlb[2], n) != hipSuccess) {
+        free_round_lists(g);
+        return MF_ERR_OUT_OF_MEMORY;
+    }
+    mf::launch_fill_i32(g->mark, 0, n, g->stream);
+    g->epoch = 0;
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
@@ -551,18 +607,59 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         const int64_t depth = levels - levels_before;
         const int64_t R = std::min<int64_t>(g->round_max, std::max<int64_t>(1, depth / g->round_div));
         int cnt[3] = {c.wl[0], c.wl[1], c.wl[2]};
+        int32_t* cur[3] = {m.L.wl[0], m.L.wl[1], m.L.wl[2]};
+        // several rounds on the main lane: later worklists come from the
+        // previous one plus the vertices the round activated, not a scan of
+        // every vertex
+        const bool incremental = R > 1 && m.L.main && !m.pull && !m.topology && g->incremental_rounds;
+        LoopMode rm = m;
+        if (incremental) {
+            rc = ensure_round_lists(g);
+            if (rc != MF_OK) return rc;
+            rm.dg.act = g->act_list;
+            rm.dg.act_cnt = &m.L.ctr->act;
+            rm.dg.act_cap = g->n;
+            mf::launch_zero_act(m.L.ctr, st);
+        }
         for (int64_t r = 0;; ++r) {
-            rc = push_round(g, m, cnt);
+            rc = push_round(g, rm, cur, cnt);
             if (rc != MF_OK) return rc;
             ++rounds;
             if (r + 1 >= R) break;
-            mf::launch_zero_loop_counters(m.L.ctr, st);
-            timed(g, m.L, mf::KC_WL, [&] {
-                mf::launch_build_worklist(m.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology, m.sign, st);
-            });
-            MF_HIP(hipGetLastError());
-            rc = read_lane(g, m.L);
-            if (rc != MF_OK) return rc;
+            bool rebuilt = false;
+            if (incremental) {
+                if (++g->epoch == INT_MAX) {
+                    mf::launch_fill_i32(g->mark, 0, g->n, st);
+                    g->epoch = 1;
+                }
+                int32_t* nxt[3];
+                for (int b = 0; b < 3; ++b) nxt[b] = cur[b] == m.L.wl[b] ? g->wlb[b] : m.L.wl[b];
+                timed(g, m.L, mf::KC_WL, [&] {
+                    mf::launch_next_worklist(rm.dg, cur, cnt, nxt[0], nxt[1], nxt[2], g->mark, g->epoch, m.L.ctr,
+                                             st);
+                });
+                MF_HIP(hipGetLastError());
+                rc = read_lane(g, m.L);
+                if (rc != MF_OK) return rc;
+                if (c.act <= g->n) {
+                    for (int b = 0; b < 3; ++b) cur[b] = nxt[b];
+                    rebuilt = true;
+                    mf::launch_zero_act(m.L.ctr, st);
+                }
+                // else activations were dropped: scan every vertex instead
+            }
+            if (!rebuilt) {
+                mf::launch_zero_loop_counters(m.L.ctr, st);
+                timed(g, m.L, mf::KC_WL, [&] {
+                    mf::launch_build_worklist(m.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology, m.sign,
+                                              st);
+                });
+                MF_HIP(hipGetLastError());
+                rc = read_lane(g, m.L);
+                if (rc != MF_OK) return rc;
+                for (int b = 0; b < 3; ++b) cur[b] = m.L.wl[b];
+                if (incremental) mf::launch_zero_act(m.L.ctr, st);
+            }
             if (c.wl[3] == 0) break;  // certified by the next relabel
             active_sum += c.wl[3];
             cnt[0] = c.wl[0];
@@ -911,6 +1008,8 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
         if (std::atoi(env) != 0) g->tune.lds = mf::gr_level_lds_bytes(g->bits.nwords, dev) > 0 ? 1 : 0;
     if (const char* env = std::getenv("MF_GR_GRID")) g->gr_grid = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_GR_FIRST_CHUNK")) g->first_chunk = std::max(1, std::atoi(env));
+    if (const char* env = std::getenv("MF_ROUND_SCAN")) g->incremental_rounds = std::atoi(env) == 0;
+    if (const char* env = std::getenv("MF_GR_NARROW")) g->narrow_max = std::max(0, std::atoi(env));
     if (const char* env = std::getenv("MF_ROUND_MAX")) g->round_max = std::max(1, std::atoi(env));
     if (o.relabel_mode == 1) g->persistent_grid = mf::persistent_gr_grid(dev);
     g->dg.n = n;

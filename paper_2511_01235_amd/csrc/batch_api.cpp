@@ -247,6 +247,9 @@ mf_status upload_views(mf_batch* b) {
         g.bin1_max = b->bin1;
         g.side = nullptr;
         g.side_keep = 0;
+        g.act = nullptr;
+        g.act_cnt = nullptr;
+        g.act_cap = 0;
         int64_t qc = (int64_t)ni + b->slots[i] / mf::GR_CHUNK + 64;
         S.q0 = b->q + b->qbase[i];
         S.q1 = S.q0 + qc;

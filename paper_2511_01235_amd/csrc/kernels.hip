@@ -55,6 +55,15 @@ __device__ __forceinline__ int64_t ld_e(const int64_t* e, int v) {
 __device__ __forceinline__ void add_e(int64_t* e, int v, int64_t d) {
     __hip_atomic_fetch_add(&e[v], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// v receives d > 0; when activations are tracked and v's excess turns
+// positive, v goes on the activation list
+__device__ __forceinline__ void gain_e(const DevGraph& g, int v, int64_t d) {
+    int64_t old = __hip_atomic_fetch_add(&g.e[v], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (g.act && old <= 0 && old + d > 0) {
+        int k = atomicAdd(g.act_cnt, 1);
+        if (k < g.act_cap) g.act[k] = v;
+    }
+}
 __device__ __forceinline__ void add_bytes(const DevGraph& g, int cls, unsigned long long b) {
     if (g.count_bytes && b)
         atomicAdd(&g.bytes_part[cls * BYTES_SLOTS + (blockIdx.x % BYTES_SLOTS)], b);
@@ -280,6 +289,13 @@ __global__ void k_zero_counters_front(DevCounters* ctr) {
         ctr->bar_err = 0;
         ctr->levels = 0;
     }
+}
+
+// Between push-relabel rounds: clear the worklist counts (before the next
+// worklist) or the activation count (before the next push-relabel).
+__global__ void k_zero_counts(DevCounters* ctr, int wl, int act) {
+    if (wl && threadIdx.x < 4) ctr->wl[threadIdx.x] = 0;
+    if (act && threadIdx.x == 0) ctr->act = 0;
 }
 
 // Append the frontier entries of the lanes that discovered a vertex:
@@ -660,6 +676,54 @@ __global__ void __launch_bounds__(BS) k_gr_level(DevGraph g, int lv, const int2*
     gr_level_step<FWD, BS>(hw_par(), g, lv, qin, qout, ctr, bits, tune, tune.lds ? s_dyn : nullptr);
 }
 
+// Thin frontiers (deep BFS, e.g. grids): one workgroup runs top-down levels
+// back to back with workgroup barriers only, from level lv0 while each
+// frontier holds at most max_entries entries.  It stops at the first empty
+// level (the BFS is over) or at a level whose frontier is larger (not
+// processed), and leaves in ctr->levels the level to continue from.  The frontier bitmaps are
+// not kept up to date here (top-down needs only the visited bitmap); the host
+// rebuilds the current one before multi-block levels continue.
+constexpr int NARROW_BLOCK = 1024;
+
+template <bool FWD>
+__global__ void __launch_bounds__(NARROW_BLOCK) k_gr_narrow(DevGraph g, int lv0, int2* q0, int2* q1,
+                                                            DevCounters* ctr, GrBits bits, int max_entries) {
+    __shared__ int s_cnt;
+    const Par P{0, 1};
+    int lv = lv0;
+    if (threadIdx.x == 0)
+        s_cnt = (int)(unsigned)(__hip_atomic_load(&ctr->front[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                                0xFFFFFFFFull);
+    __syncthreads();
+    for (; lv <= g.n; ++lv) {
+        const int2* qin = (lv & 1) ? q1 : q0;
+        int2* qout = (lv & 1) ? q0 : q1;
+        const int cnt = s_cnt;
+        // over (empty frontier), or a frontier for the multi-block levels
+        if (cnt == 0 || cnt > max_entries) break;
+        __syncthreads();  // s_cnt is rewritten below
+        if (threadIdx.x == 0) {
+            ctr->front[(lv + 2) % 3] = 0;
+            // unvisited slots after this level's frontier, as the direction rule keeps them
+            long long fs = (long long)(ctr->front[lv % 3] >> 32);
+            ctr->unv[lv % 3] = ctr->unv[(lv + 2) % 3] - fs;
+        }
+        __syncthreads();
+        gr_level_body<FWD, NARROW_BLOCK>(P, g, lv, cnt, qin, qout, ctr, bits, false, false, false, nullptr);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_cnt = (int)(unsigned)(__hip_atomic_load(&ctr->front[(lv + 1) % 3], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT) & 0xFFFFFFFFull);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctr->levels = lv;
+}
+
+// The frontier bitmap of the current level from its queue entries.
+__global__ void __launch_bounds__(256) k_mark_frontier(const int2* q, int cnt, unsigned* fb) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) set_bit(fb, q[i].x);
+}
+
 // Grid-wide barrier for a cooperative launch (all blocks resident).  Block
 // leaders arrive on a counter; the last one resets it and bumps the
 // generation the others wait on.  The spin is bounded: past the limit the
@@ -807,7 +871,8 @@ __device__ __forceinline__ void do_push(DevGraph& g, int u, int j, int64_t eu) {
     add_res(g.cr, ji, (int32_t)d);
     int w = g.cr[j].x;
     add_e(g.e, PULL ? w : u, -d);
-    add_e(g.e, PULL ? u : w, d);
+    if (PULL) add_e(g.e, u, d);
+    else gain_e(g, w, d);
 }
 
 // Move d along slot j of u without touching e(u) (the caller settles u's
@@ -819,7 +884,8 @@ __device__ __forceinline__ void move_along(DevGraph& g, int j, int32_t d) {
     int ji = PULL ? j : g.rev[j];
     add_res(g.cr, jo, -d);
     add_res(g.cr, ji, d);
-    add_e(g.e, g.cr[j].x, PULL ? -(int64_t)d : (int64_t)d);
+    if (PULL) add_e(g.e, g.cr[j].x, -(int64_t)d);
+    else gain_e(g, g.cr[j].x, d);
 }
 
 // Key of slot j for the lowest-neighbour search: (h(col) << 32 | j) when the
@@ -1136,7 +1202,7 @@ __device__ __forceinline__ long long rie_item(DevGraph& g, int u, int sub, unsig
             int32_t x = xchg_res(g.cr, j, 0);
             if (x > 0) {
                 add_res(g.cr, g.rev[j], x);
-                add_e(g.e, (int)(unsigned)sv[q], x);
+                gain_e(g, (int)(unsigned)sv[q], x);
                 moved += x;
                 *bytes += 32;
             }
@@ -1686,6 +1752,43 @@ inline int grid_for(int64_t items, int block, int cap = 4096) {
     return (int)g;
 }
 
+// ---- worklist of a round without a relabel ------------------------------------
+//
+// The previous worklist's vertices and the ones activated by the round's
+// pushes and saturations (DevGraph::act), kept when active (e > 0, h < n),
+// each once (mark[v] == epoch), binned by row length.
+__global__ void __launch_bounds__(256) k_next_worklist(DevGraph g, const int32_t* in0, const int32_t* in1,
+                                                       const int32_t* in2, int c0, int c1, int c2, int32_t* out0,
+                                                       int32_t* out1, int32_t* out2, int32_t* mark, int32_t epoch,
+                                                       DevCounters* ctr) {
+    const int na = min(*g.act_cnt, g.act_cap);
+    const long long total = (long long)c0 + c1 + c2 + na;
+    for (long long base = (long long)blockIdx.x * blockDim.x; base < total;
+         base += (long long)gridDim.x * blockDim.x) {
+        const long long i = base + threadIdx.x;
+        int v = -1;
+        if (i < total) {
+            if (i < c0) v = in0[i];
+            else if (i < (long long)c0 + c1) v = in1[i - c0];
+            else if (i < (long long)c0 + c1 + c2) v = in2[i - c0 - c1];
+            else v = g.act[i - c0 - c1 - c2];
+        }
+        bool act = false;
+        int bin = 0;
+        if (v >= 0 && v != g.s && v != g.t && v != g.pinned && ld_e(g.e, v) > 0 && g.h[v] < g.n &&
+            atomicExch(&mark[v], epoch) != epoch) {
+            act = true;
+            int len = g.row_len[v];
+            bin = len <= g.bin0_max ? 0 : (len <= g.bin1_max ? 1 : 2);
+        }
+        wave_append(act && bin == 0, v, out0, &ctr->wl[0]);
+        wave_append(act && bin == 1, v, out1, &ctr->wl[1]);
+        wave_append(act && bin == 2, v, out2, &ctr->wl[2]);
+        unsigned long long m = __ballot(act);
+        if (lane_id() == 0 && m) atomicAdd(&ctr->wl[3], (int)__popcll(m));
+    }
+}
+
 // ---- relayout: rows with room for their pending inserts ---------------------
 //
 // Rows keep their slots in order; each row's new size is its used length plus
@@ -1966,6 +2069,18 @@ void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, 
     }
 }
 
+void launch_gr_narrow(const DevGraph& g, int lv0, int2* q0, int2* q1, DevCounters* ctr, const GrBits& bits,
+                      int max_entries, bool forward, hipStream_t st) {
+    if (forward) k_gr_narrow<true><<<1, NARROW_BLOCK, 0, st>>>(g, lv0, q0, q1, ctr, bits, max_entries);
+    else k_gr_narrow<false><<<1, NARROW_BLOCK, 0, st>>>(g, lv0, q0, q1, ctr, bits, max_entries);
+}
+
+void launch_frontier_bitmap(const int2* q, int cnt, const GrBits& bits, int level, hipStream_t st) {
+    launch_fill_i32(reinterpret_cast<int32_t*>(bits.fb), 0, 3 * (int64_t)bits.nwords, st);
+    if (cnt > 0)
+        k_mark_frontier<<<grid_for(cnt, 256), 256, 0, st>>>(q, cnt, bits.fb + (size_t)(level % 3) * bits.nwords);
+}
+
 int persistent_gr_grid(int device) {
     int coop = 0, cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop)
@@ -2115,6 +2230,19 @@ void launch_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu, const int32_t
 
 void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st) {
     if (num > 0) k_batch_cleanup_multi<256><<<num, 256, 0, st>>>(gu);
+}
+
+void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const int cnt[3], int32_t* out0,
+                          int32_t* out1, int32_t* out2, int32_t* mark, int32_t epoch, DevCounters* ctr,
+                          hipStream_t st) {
+    k_zero_counts<<<1, 64, 0, st>>>(ctr, 1, 0);
+    const int64_t most = (int64_t)cnt[0] + cnt[1] + cnt[2] + g.act_cap;
+    k_next_worklist<<<grid_for(most, 256, 2048), 256, 0, st>>>(g, in[0], in[1], in[2], cnt[0], cnt[1], cnt[2],
+                                                              out0, out1, out2, mark, epoch, ctr);
+}
+
+void launch_zero_act(DevCounters* ctr, hipStream_t st) {
+    k_zero_counts<<<1, 64, 0, st>>>(ctr, 0, 1);
 }
 
 int64_t relayout_tiles(int32_t V) { return ((int64_t)V + RL_TILE - 1) / RL_TILE; }

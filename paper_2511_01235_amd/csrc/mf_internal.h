@@ -38,6 +38,9 @@ struct DevGraph {
     int bin0_max, bin1_max;              // worklist degree bins: thread up to bin0_max slots, wave up to bin1_max
     const uint8_t* side;                 // not null: a relabel only labels vertices with side[v] == side_keep
     int side_keep;
+    int32_t* act;                        // not null: push-relabel / remove-invalid-edges append every vertex
+    int32_t* act_cnt;                    // whose excess turns positive, counting in *act_cnt (which may
+    int32_t act_cap;                     // pass act_cap: the extra ones are dropped)
 };
 
 // Partial sums of algorithmic bytes: a kernel block adds into slot
@@ -62,6 +65,8 @@ struct DevCounters {
     long long deficit_sum;     // sum of negative excess outside {s,t}
     long long e_t;             // e(t) at the worklist build
     unsigned long long bytes[8];  // algorithmic bytes per kernel class
+    int32_t act;               // vertices appended to DevGraph::act (may exceed act_cap: then some were dropped)
+    int32_t act_pad;
 };
 
 enum KernelClass { KC_GR = 0, KC_PR = 1, KC_RIE = 2, KC_WL = 3, KC_BATCH = 4, KC_INIT = 5, KC_NCLASS = 8 };
@@ -260,9 +265,21 @@ void launch_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu, const int32_t
                                const GrTune& tune, int block, hipStream_t st);
 // After a failed validation: scratch back to idle for every graph.
 void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st);
+// thin-frontier BFS levels in one workgroup; ctr->levels = the level to continue from
+void launch_gr_narrow(const DevGraph& g, int lv0, int2* q0, int2* q1, DevCounters* ctr, const GrBits& bits,
+                      int max_entries, bool forward, hipStream_t st);
+// zero the three frontier bitmaps, then set the current level's from its queue
+void launch_frontier_bitmap(const int2* q, int cnt, const GrBits& bits, int level, hipStream_t st);
 int64_t relayout_tiles(int32_t V);
 // n scattered atomicAdds of `width` bytes (4 or 8) on n distinct addresses; ops/s, < 0 on failure
 double atomic_probe(int64_t n, int width, hipStream_t st);
+// next worklist of a push-relabel round without a relabel: the previous
+// worklist's bins (counts c0..c2) and the activation list, filtered to
+// active vertices (e > 0, h < n), deduplicated with mark[v] == epoch, binned
+void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const int cnt[3], int32_t* out0,
+                          int32_t* out1, int32_t* out2, int32_t* mark, int32_t epoch, DevCounters* ctr,
+                          hipStream_t st);
+void launch_zero_act(DevCounters* ctr, hipStream_t st);
 // sizes, their scan into start[] and the rows to sort; then the caller reads
 // start[V] (the new slot count) and *sort_count
 void launch_relayout_plan(const RelayoutPlan& p, hipStream_t st);

@@ -89,6 +89,7 @@ def test_bottom_up_levels_bit_exact(name, variant, monkeypatch):
     monkeypatch.setenv("MF_GR_BU_BETA", "1000000")
     monkeypatch.setenv("MF_GR_BU_LB", "1" if variant == "slots" else "0")
     monkeypatch.setenv("MF_GR_BU_WIDE", "1" if variant == "rows8" else "0")
+    monkeypatch.setenv("MF_GR_NARROW", "0")   # every level through the multi-block kernels
     lb = variant
     g, stream, k, _ = gen.workload(name)
     say("bottom-up levels", name, "lb", lb)
@@ -103,13 +104,16 @@ def test_bottom_up_levels_bit_exact(name, variant, monkeypatch):
             assert G.apply_batch(u, v, c) == o.apply(u, v, c)
 
 
+@pytest.mark.parametrize("scan", [0, 1])
 @pytest.mark.parametrize("div", [1, 8, 1000000])
 @pytest.mark.parametrize("name", ["grid64", "rmat12"])
-def test_push_rounds_between_relabels(name, div, monkeypatch):
+def test_push_rounds_between_relabels(name, div, scan, monkeypatch):
     """Push-relabel rounds on the current heights between global relabels
-    (one per relabel up to one per BFS level): values equal the oracle's in
-    the single-graph and the batched loops."""
+    (one per relabel up to one per BFS level), their worklists built from the
+    previous one plus the activated vertices or by scanning every vertex:
+    values equal the oracle's in the single-graph and the batched loops."""
     monkeypatch.setenv("MF_ROUND_DIV", str(div))
+    monkeypatch.setenv("MF_ROUND_SCAN", str(scan))
     g, stream, k, _ = gen.workload(name)
     say("push rounds", name, "div", div)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
@@ -124,6 +128,26 @@ def test_push_rounds_between_relabels(name, div, monkeypatch):
     with mf.MaxFlowBatch([g]) as B:
         got_b = [int(B.maxflow()[0])] + [int(B.apply([b])[0]) for b in batches]
     assert got_b == want
+
+
+@pytest.mark.parametrize("narrow", [0, 16, 4096, 1 << 30])
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+def test_thin_frontier_levels_bit_exact(name, narrow, monkeypatch):
+    """BFS levels with frontiers up to `narrow` entries run in one workgroup
+    (0: never, 1 << 30: every level), handing larger ones to the multi-block
+    kernels and taking them back: heights bit-exact, values equal."""
+    monkeypatch.setenv("MF_GR_NARROW", str(narrow))
+    g, stream, k, _ = gen.workload(name)
+    say("thin frontiers", name, narrow)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    h_want, _ = o.initial_labels()
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        h, _, _ = G.initial_labels()
+        assert np.array_equal(h, h_want)
+        assert G.maxflow() == o.static()
+        for _ in range(3):
+            u, v, c = stream.next_batch(k)
+            assert G.apply_batch(u, v, c) == o.apply(u, v, c)
 
 
 # --- static value ---------------------------------------------------------------
