@@ -74,7 +74,7 @@ struct mf_graph {
     int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
     int32_t round_max = 4096; // ... at most this many
     bool incremental_rounds = true;  // rounds take their worklist from the previous one plus activations
-    int32_t narrow_max = 4096;       // BFS frontiers up to this many entries run in one workgroup (0: never)
+    int64_t narrow_max = 4096;       // BFS frontiers of up to this many slots run in one workgroup (0: never)
     // incremental worklists between relabels (made on first use)
     int32_t* act_list = nullptr;   // vertices whose excess turned positive in a round
     int32_t* mark = nullptr;       // per vertex: the round that last listed it
@@ -500,7 +500,7 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
             return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
         }
         chunk = std::min(chunk * 2, 64);
-        narrow = g->narrow_max > 0 && cnt <= g->narrow_max;
+        narrow = g->narrow_max > 0 && (int64_t)(m.L.ctr_h->front[level % 3] >> 32) <= g->narrow_max;
     }
     *levels_out += level;
     return MF_OK;
@@ -1009,7 +1009,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     if (const char* env = std::getenv("MF_GR_GRID")) g->gr_grid = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_GR_FIRST_CHUNK")) g->first_chunk = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_ROUND_SCAN")) g->incremental_rounds = std::atoi(env) == 0;
-    if (const char* env = std::getenv("MF_GR_NARROW")) g->narrow_max = std::max(0, std::atoi(env));
+    if (const char* env = std::getenv("MF_GR_NARROW")) g->narrow_max = std::max(0LL, std::atoll(env));
     if (const char* env = std::getenv("MF_ROUND_MAX")) g->round_max = std::max(1, std::atoi(env));
     if (o.relabel_mode == 1) g->persistent_grid = mf::persistent_gr_grid(dev);
     g->dg.n = n;

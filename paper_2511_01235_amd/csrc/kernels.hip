@@ -678,30 +678,31 @@ __global__ void __launch_bounds__(BS) k_gr_level(DevGraph g, int lv, const int2*
 
 // Thin frontiers (deep BFS, e.g. grids): one workgroup runs top-down levels
 // back to back with workgroup barriers only, from level lv0 while each
-// frontier holds at most max_entries entries.  It stops at the first empty
-// level (the BFS is over) or at a level whose frontier is larger (not
-// processed), and leaves in ctr->levels the level to continue from.  The frontier bitmaps are
-// not kept up to date here (top-down needs only the visited bitmap); the host
+// frontier covers at most max_slots slots.  It stops at the first empty level
+// (the BFS is over) or at a level whose frontier is larger (not processed),
+// and leaves in ctr->levels the level to continue from.  The frontier bitmaps
+// are not kept up to date here (top-down needs only the visited bitmap); the host
 // rebuilds the current one before multi-block levels continue.
 constexpr int NARROW_BLOCK = 1024;
 
 template <bool FWD>
 __global__ void __launch_bounds__(NARROW_BLOCK) k_gr_narrow(DevGraph g, int lv0, int2* q0, int2* q1,
-                                                            DevCounters* ctr, GrBits bits, int max_entries) {
-    __shared__ int s_cnt;
+                                                            DevCounters* ctr, GrBits bits, long long max_slots) {
+    __shared__ unsigned long long s_front;
     const Par P{0, 1};
     int lv = lv0;
     if (threadIdx.x == 0)
-        s_cnt = (int)(unsigned)(__hip_atomic_load(&ctr->front[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-                                0xFFFFFFFFull);
+        s_front = __hip_atomic_load(&ctr->front[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     for (; lv <= g.n; ++lv) {
         const int2* qin = (lv & 1) ? q1 : q0;
         int2* qout = (lv & 1) ? q0 : q1;
-        const int cnt = s_cnt;
-        // over (empty frontier), or a frontier for the multi-block levels
-        if (cnt == 0 || cnt > max_entries) break;
-        __syncthreads();  // s_cnt is rewritten below
+        const unsigned long long front = s_front;
+        const int cnt = (int)(unsigned)(front & 0xFFFFFFFFull);
+        // over (empty frontier), or a frontier with too many slots for one
+        // workgroup: the multi-block levels take it
+        if (cnt == 0 || (long long)(front >> 32) > max_slots) break;
+        __syncthreads();  // s_front is rewritten below
         if (threadIdx.x == 0) {
             ctr->front[(lv + 2) % 3] = 0;
             // unvisited slots after this level's frontier, as the direction rule keeps them
@@ -712,8 +713,7 @@ __global__ void __launch_bounds__(NARROW_BLOCK) k_gr_narrow(DevGraph g, int lv0,
         gr_level_body<FWD, NARROW_BLOCK>(P, g, lv, cnt, qin, qout, ctr, bits, false, false, false, nullptr);
         __syncthreads();
         if (threadIdx.x == 0)
-            s_cnt = (int)(unsigned)(__hip_atomic_load(&ctr->front[(lv + 1) % 3], __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT) & 0xFFFFFFFFull);
+            s_front = __hip_atomic_load(&ctr->front[(lv + 1) % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
     }
     if (threadIdx.x == 0) ctr->levels = lv;
@@ -2070,9 +2070,9 @@ void launch_gr_level(const DevGraph& g, int level, const int2* qin, int2* qout, 
 }
 
 void launch_gr_narrow(const DevGraph& g, int lv0, int2* q0, int2* q1, DevCounters* ctr, const GrBits& bits,
-                      int max_entries, bool forward, hipStream_t st) {
-    if (forward) k_gr_narrow<true><<<1, NARROW_BLOCK, 0, st>>>(g, lv0, q0, q1, ctr, bits, max_entries);
-    else k_gr_narrow<false><<<1, NARROW_BLOCK, 0, st>>>(g, lv0, q0, q1, ctr, bits, max_entries);
+                      long long max_slots, bool forward, hipStream_t st) {
+    if (forward) k_gr_narrow<true><<<1, NARROW_BLOCK, 0, st>>>(g, lv0, q0, q1, ctr, bits, max_slots);
+    else k_gr_narrow<false><<<1, NARROW_BLOCK, 0, st>>>(g, lv0, q0, q1, ctr, bits, max_slots);
 }
 
 void launch_frontier_bitmap(const int2* q, int cnt, const GrBits& bits, int level, hipStream_t st) {

@@ -267,7 +267,7 @@ void launch_batch_repair_multi(GraphSlot* slots, GraphUpdates* gu, const int32_t
 void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st);
 // thin-frontier BFS levels in one workgroup; ctr->levels = the level to continue from
 void launch_gr_narrow(const DevGraph& g, int lv0, int2* q0, int2* q1, DevCounters* ctr, const GrBits& bits,
-                      int max_entries, bool forward, hipStream_t st);
+                      long long max_slots, bool forward, hipStream_t st);
 // zero the three frontier bitmaps, then set the current level's from its queue
 void launch_frontier_bitmap(const int2* q, int cnt, const GrBits& bits, int level, hipStream_t st);
 int64_t relayout_tiles(int32_t V);

@@ -133,7 +133,7 @@ def test_push_rounds_between_relabels(name, div, scan, monkeypatch):
 @pytest.mark.parametrize("narrow", [0, 16, 4096, 1 << 30])
 @pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
 def test_thin_frontier_levels_bit_exact(name, narrow, monkeypatch):
-    """BFS levels with frontiers up to `narrow` entries run in one workgroup
+    """BFS levels with frontiers of up to `narrow` slots run in one workgroup
     (0: never, 1 << 30: every level), handing larger ones to the multi-block
     kernels and taking them back: heights bit-exact, values equal."""
     monkeypatch.setenv("MF_GR_NARROW", str(narrow))
