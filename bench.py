@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="single-graph workloads: autotune the handle (untimed) before the timed batches")
     ap.add_argument("--no-tune", action="store_true", help="batch512: skip the autotuner")
+    ap.add_argument("--opt", action="append", default=[], metavar="KEY=INT",
+                    help="graph workloads: a loop setting (bfs_alpha, bfs_beta, round_div, "
+                         "bin_thread_max, bin_wave_max); repeatable")
     ap.add_argument("--sweep-graph", default="rmat20", help="sweep: generator workload of the graph")
     ap.add_argument("--sweep-pcts", default="0.01,0.1,1,5,10", help="sweep: batch sizes in %% of |E|")
     ap.add_argument("--serve-slots", type=int, default=8, help="serve64: concurrent slots")
@@ -120,9 +123,15 @@ def main():
     batches_np = [bstream.next_batch(k) for _ in range(total)]
     log(f"generated {g.name}: n={g.n} m={g.m} batches={total}x{k} in {time.time() - t0:.1f}s")
 
+    extra = {}
+    for kv in args.opt:
+        key, _, val = kv.partition("=")
+        if key not in ("bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max"):
+            raise SystemExit(f"--opt: unknown setting {key!r}")
+        extra[key] = int(val)
     G = mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0,
                         kernel_cycles=args.kc, warm_start=not args.cold_start,
-                        relabel_mode=args.relabel_mode, push_pull=args.push_pull)
+                        relabel_mode=args.relabel_mode, push_pull=args.push_pull, **extra)
     st = G.stats()
     m_unique = None
     # static solve: median of a few from-zero runs on the loaded graph
@@ -248,7 +257,7 @@ def main():
                    "m_edges_generated": g.m, "m_pairs": m_unique, "s": g.s, "t": g.t,
                    "batch_size": k, "kernel_cycles": st["kernel_cycles"],
                    "warm_start": not args.cold_start, "relabel_mode": args.relabel_mode,
-                   "push_pull": args.push_pull},
+                   "push_pull": args.push_pull, **extra},
         "incremental_ms_p50": round(float(np.percentile(arr, 50)), 4),
         "incremental_ms_p90": round(float(np.percentile(arr, 90)), 4),
         "incremental_ms_p99": round(float(np.percentile(arr, 99)), 4),

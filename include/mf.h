@@ -118,8 +118,9 @@ typedef struct mf_stats {
     int64_t last_new_pairs;    /* pairs inserted by the last batch */
     double last_ms;            /* host wall time of the call */
     /* per-kernel device time over the calls since mf_profile (HIP events on the
-     * library's stream); index: 0 global-relabel level, 1 push-relabel, 2 remove-invalid-
-     * edges, 3 worklist build, 4 batch kernels, 5 reset and source saturation */
+     * library's stream); index: 0 global-relabel multi-block BFS level, 1 push-relabel,
+     * 2 remove-invalid-edges, 3 worklist build, 4 batch kernels, 5 reset and source
+     * saturation, 6 global-relabel seeding and one-workgroup thin-frontier levels */
     double kernel_ms[8];
     int64_t kernel_launches[8];
     /* algorithmic bytes the kernels of each class had to move over the same calls,

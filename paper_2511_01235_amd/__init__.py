@@ -36,7 +36,7 @@ EXPORTED = ["mf_default_options", "mf_status_string", "mf_graph_load", "mf_maxfl
             "mf_batch_tune", "mf_batch_free"]
 
 KERNEL_CLASSES = ["global_relabel", "push_relabel", "remove_invalid", "worklist", "batch", "init",
-                  "unused6", "unused7"]
+                  "relabel_seed_narrow", "unused7"]
 
 
 class MFError(RuntimeError):

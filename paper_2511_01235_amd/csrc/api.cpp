@@ -11,6 +11,7 @@
 #include <chrono>
 #include <climits>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -71,6 +72,7 @@ struct mf_graph {
     mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0, 0};
     int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
     int first_chunk = 8;      // BFS levels launched before the first frontier check
+    bool trace_gr = false;    // MF_GR_TRACE: one level per launch, each printed to stderr
     int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
     int32_t round_max = 4096; // ... at most this many
     bool incremental_rounds = true;  // rounds take their worklist from the previous one plus activations
@@ -458,16 +460,24 @@ mf_status read_lane(mf_graph* g, const Lane& L) {
 // chunk.  Returns the number of level launches.
 mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
     hipStream_t st = m.L.stream;
-    timed(g, m.L, mf::KC_GR, [&] { mf::launch_gr_init(m.dg, m.L.q[0], m.L.ctr, m.L.bits, m.seed_deficits, st); });
+    timed(g, m.L, mf::KC_GRS, [&] { mf::launch_gr_init(m.dg, m.L.q[0], m.L.ctr, m.L.bits, m.seed_deficits, st); });
     int level = 0;
-    int chunk = g->first_chunk;
+    int chunk = g->trace_gr ? 1 : g->first_chunk;
     // thin frontiers run in one workgroup, several levels per launch; the
     // first frontier is tried that way, later ones when a chunk leaves one
     // small enough
-    bool narrow = g->narrow_max > 0;
+    bool narrow = g->narrow_max > 0 && !g->trace_gr;
+    auto t_last = std::chrono::steady_clock::now();
+    if (g->trace_gr) {
+        mf_status rc = read_lane(g, m.L);
+        if (rc != MF_OK) return rc;
+        const unsigned long long f = m.L.ctr_h->front[0];
+        std::fprintf(stderr, "[gr] seeds %u slots %llu\n", (unsigned)(f & 0xFFFFFFFFull), f >> 32);
+        t_last = std::chrono::steady_clock::now();
+    }
     for (;;) {
         if (narrow) {
-            timed(g, m.L, mf::KC_GR, [&] {
+            timed(g, m.L, mf::KC_GRS, [&] {
                 mf::launch_gr_narrow(m.dg, level, m.L.q[0], m.L.q[1], m.L.ctr, m.L.bits, g->narrow_max, m.forward,
                                      st);
             });
@@ -482,7 +492,8 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
                 return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
             }
             // the multi-block levels read the current frontier's bitmap
-            mf::launch_frontier_bitmap(m.L.q[level & 1], cnt, m.L.bits, level, st);
+            timed(g, m.L, mf::KC_GRS,
+                  [&] { mf::launch_frontier_bitmap(m.L.q[level & 1], cnt, m.L.bits, level, st); });
             chunk = g->first_chunk;
         }
         for (int i = 0; i < chunk; ++i, ++level)
@@ -494,11 +505,27 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
         mf_status rc = read_lane(g, m.L);
         if (rc != MF_OK) return rc;
         const int cnt = (int)(unsigned)(m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull);
+        if (g->trace_gr) {
+            // the level just done: its frontier, the unvisited slots before it,
+            // the direction rule's choice, its next frontier, host wall time
+            const DevCounters& c = *m.L.ctr_h;
+            const int lv = level - 1;
+            const unsigned long long f = c.front[lv % 3];
+            const long long fs = (long long)(f >> 32), cin = (long long)(f & 0xFFFFFFFFull);
+            const long long mu = c.unv[lv % 3];
+            const bool bu = g->tune.bu_alpha > 0 && fs * g->tune.bu_alpha > mu && cin * g->tune.bu_beta > g->n;
+            const auto now = std::chrono::steady_clock::now();
+            std::fprintf(stderr, "[gr] level %d frontier %lld slots %lld unvisited %lld %s next %d us %.1f\n", lv,
+                         cin, fs, mu, bu ? "bu" : "td", cnt,
+                         std::chrono::duration<double, std::micro>(now - t_last).count());
+            t_last = now;
+        }
         if (cnt == 0) break;
         if (level > g->n + 2) {
             g->poisoned = true;
             return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
         }
+        if (g->trace_gr) continue;  // one level per launch
         chunk = std::min(chunk * 2, 64);
         narrow = g->narrow_max > 0 && (int64_t)(m.L.ctr_h->front[level % 3] >> 32) <= g->narrow_max;
     }
@@ -608,6 +635,9 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         const int64_t R = std::min<int64_t>(g->round_max, std::max<int64_t>(1, depth / g->round_div));
         int cnt[3] = {c.wl[0], c.wl[1], c.wl[2]};
         int32_t* cur[3] = {m.L.wl[0], m.L.wl[1], m.L.wl[2]};
+        if (g->trace_gr)
+            std::fprintf(stderr, "[loop] relabel %lld depth %lld active %d (rows by bin %d %d %d) rounds %lld\n",
+                         (long long)iters, (long long)depth, active, cnt[0], cnt[1], cnt[2], (long long)R);
         // several rounds on the main lane: later worklists come from the
         // previous one plus the vertices the round activated, not a scan of
         // every vertex
@@ -660,6 +690,9 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
                 for (int b = 0; b < 3; ++b) cur[b] = m.L.wl[b];
                 if (incremental) mf::launch_zero_act(m.L.ctr, st);
             }
+            if (g->trace_gr)
+                std::fprintf(stderr, "[loop]   round %lld active %d (rows by bin %d %d %d)\n", (long long)r + 1,
+                             c.wl[3], c.wl[0], c.wl[1], c.wl[2]);
             if (c.wl[3] == 0) break;  // certified by the next relabel
             active_sum += c.wl[3];
             cnt[0] = c.wl[0];
@@ -1008,6 +1041,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
         if (std::atoi(env) != 0) g->tune.lds = mf::gr_level_lds_bytes(g->bits.nwords, dev) > 0 ? 1 : 0;
     if (const char* env = std::getenv("MF_GR_GRID")) g->gr_grid = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_GR_FIRST_CHUNK")) g->first_chunk = std::max(1, std::atoi(env));
+    if (const char* env = std::getenv("MF_GR_TRACE")) g->trace_gr = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_ROUND_SCAN")) g->incremental_rounds = std::atoi(env) == 0;
     if (const char* env = std::getenv("MF_GR_NARROW")) g->narrow_max = std::max(0LL, std::atoll(env));
     if (const char* env = std::getenv("MF_ROUND_MAX")) g->round_max = std::max(1, std::atoi(env));

@@ -314,12 +314,50 @@ __device__ __forceinline__ void append_entries(int add, int slots, int v, int2* 
     for (int k = 0; k < add; ++k) q[b + off + k] = make_int2(v, k * GR_CHUNK);
 }
 
+// The same for a whole block with one atomic: thread t queues the entries of
+// up to U vertices (vs[k] with adds[k] entries and lens[k] slots).  Every
+// level-counter atomic goes to the same address from all CUs and XCDs, so
+// one per block instead of one per wave is what keeps levels that discover
+// hundreds of thousands of vertices short.  Every thread of the block calls
+// it (two barriers); s_agg holds BS / WAVE + 1 words.
+template <int BS, int U>
+__device__ __forceinline__ void block_append(const int (&vs)[U], const int (&adds)[U], const int (&lens)[U],
+                                             int2* q, unsigned long long* counter, unsigned long long* s_agg) {
+    int add = 0;
+    unsigned long long sl = 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        add += adds[k];
+        sl += adds[k] > 0 ? (unsigned long long)lens[k] : 0ull;
+    }
+    int wtot;
+    const int off = wave_excl_scan(add, &wtot);
+    const unsigned long long wsl = wave_sum_u64(sl);
+    const int w = threadIdx.x / WAVE;
+    if (lane_id() == 0) s_agg[w] = (wsl << 32) | (unsigned)wtot;
+    __syncthreads();
+    unsigned long long tot = 0;
+    int woff = 0;
+#pragma unroll
+    for (int i = 0; i < BS / WAVE; ++i) {
+        const unsigned long long x = s_agg[i];
+        if (i < w) woff += (int)(unsigned)(x & 0xFFFFFFFFull);
+        tot += x;
+    }
+    if (threadIdx.x == 0) s_agg[BS / WAVE] = (tot & 0xFFFFFFFFull) ? atomicAdd(counter, tot) : 0ull;
+    __syncthreads();
+    int p = (int)(unsigned)(s_agg[BS / WAVE] & 0xFFFFFFFFull) + woff + off;
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+        for (int a = 0; a < adds[k]; ++a) q[p++] = make_int2(vs[k], a * GR_CHUNK);
+}
+
 // Visited / frontier bitmaps of a global relabel (one bit per vertex).
 __device__ __forceinline__ bool bit_of(const unsigned* bm, int v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
 __device__ __forceinline__ void set_bit(unsigned* bm, int v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
 
 __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, int2* q0, DevCounters* ctr,
-                                             const GrBits& bits, int seed_deficits) {
+                                             const GrBits& bits, int seed_deficits, int cls = KC_GR) {
     const int N = g.n;
     for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
         int v = base + threadIdx.x;
@@ -350,13 +388,13 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
     if (P.bid == 0 && threadIdx.x == 0) {
         // slots of every row that may be labelled, the seeds' included
         ctr->unv[2] = (long long)g.used_slots - g.row_len[g.pinned];
-        add_bytes(g, KC_GR, 12ull * (unsigned long long)N);
+        add_bytes(g, cls, 12ull * (unsigned long long)N);
     }
 }
 
 __global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr, GrBits bits,
                                                  int seed_deficits) {
-    gr_init_body(hw_par(), g, q0, ctr, bits, seed_deficits);
+    gr_init_body(hw_par(), g, q0, ctr, bits, seed_deficits, KC_GRS);
 }
 
 // One BFS level.  Top-down (small frontier): each block takes 256 frontier
@@ -372,6 +410,10 @@ __global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounte
 // first.  Both produce exactly the BFS levels.  The frontier size is read on
 // the device; an empty frontier makes the launch a no-op, so the host may run
 // ahead by several levels.
+
+// Top-down slots per thread per round (loads in flight, and one queue atomic
+// per block per GR_TD_U * BS slots).
+constexpr int GR_TD_U = 4;
 
 // A vertex gets height lv+1: mark it visited and in the next frontier, queue
 // its entries, and return its slot count for the direction counters.
@@ -391,11 +433,13 @@ template <bool FWD, int BS>
 __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, int lv, int cnt,
                                               const int2* qin,
                                               int2* qout, DevCounters* ctr, const GrBits& bits,
-                                              bool bu, bool bu_lb, bool bu_wide, const unsigned* s_bm) {
+                                              bool bu, bool bu_lb, bool bu_wide, const unsigned* s_bm,
+                                              int cls = KC_GR) {
     __shared__ int s_u[BS];
     __shared__ int s_beg[BS];
     __shared__ int s_pre[BS + 1];
     __shared__ int s_wsum[BS / WAVE];
+    __shared__ unsigned long long s_agg[BS / WAVE + 1];
     // exclusive prefix sum of len over the block into s_pre[0..BS], total in s_pre[BS]
     auto block_prefix = [&](int len) {
         int wtot;
@@ -478,7 +522,10 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
                     atomicOr(&bits.fb[(size_t)((lv + 1) % 3) * bits.nwords + (v >> 5)], half);
                 }
             }
-            append_entries(add, slots, v, qout, out_cnt);
+            {
+                const int vs[1] = {v}, adds[1] = {add}, lens[1] = {slots};
+                block_append<BS, 1>(vs, adds, lens, qout, out_cnt, s_agg);
+            }
             __syncthreads();  // s_hit / s_pre are restaged next round
         }
     } else if (bu) {
@@ -486,9 +533,13 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
         // row (four loads in flight); longer rows without a hit go to a
         // block-local list that the block's waves finish one row at a time
         __shared__ int s_defer[BS];
-        __shared__ int s_ndefer;
+        __shared__ int s_dhit[BS];
+        __shared__ int s_ndefer, s_ndhit;
         for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
-            if (tid == 0) s_ndefer = 0;
+            if (tid == 0) {
+                s_ndefer = 0;
+                s_ndhit = 0;
+            }
             __syncthreads();
             int v = base + tid;
             int add = 0, slots = 0;
@@ -542,8 +593,10 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
                     atomicOr(&bits.fb[(size_t)((lv + 1) % 3) * bits.nwords + (v >> 5)], half);
                 }
             }
-            append_entries(add, slots, v, qout, out_cnt);
-            __syncthreads();
+            {   // block_append's barriers also publish s_defer / s_ndefer
+                const int vs[1] = {v}, adds[1] = {add}, lens[1] = {slots};
+                block_append<BS, 1>(vs, adds, lens, qout, out_cnt, s_agg);
+            }
             const int nd = s_ndefer;
             for (int d = tid / WAVE; d < nd; d += BS / WAVE) {
                 int w = s_defer[d];
@@ -563,15 +616,26 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
                         break;
                     }
                 }
-                int addw = 0, slw = 0;
                 if (hit && lane == 0) {
                     g.h[w] = lv + 1;
-                    slw = discover(g, bits, lv, w, &addw);
+                    int addw;
+                    discover(g, bits, lv, w, &addw);
+                    s_dhit[atomicAdd(&s_ndhit, 1)] = w;
                     found++;
                 }
-                append_entries(addw, slw, w, qout, out_cnt);
             }
-            __syncthreads();  // s_defer / s_ndefer are reused next round
+            __syncthreads();
+            {   // the long rows that found a parent, queued by the whole block
+                const int nh = s_ndhit;
+                int vs[1] = {-1}, adds[1] = {0}, lens[1] = {0};
+                if (tid < nh) {
+                    vs[0] = s_dhit[tid];
+                    lens[0] = g.row_len[vs[0]];
+                    adds[0] = (lens[0] + GR_CHUNK - 1) / GR_CHUNK;
+                }
+                block_append<BS, 1>(vs, adds, lens, qout, out_cnt, s_agg);
+            }
+            __syncthreads();  // s_defer / s_dhit and their counts are reused next round
         }
         exam += (unsigned long long)((N + (int)(P.nb * blockDim.x) - 1) / (int)(P.nb * blockDim.x)) / 8;
     } else {
@@ -592,22 +656,35 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
             }
             const int total = block_prefix(len);
             scanned += (unsigned long long)total;  // counted once per block (thread 0 below)
-            for (int base = 0; base < total; base += BS) {
-                int i = base + tid;
-                int v = -1, add = 0, slots = 0;
-                if (i < total) {
-                    const int lo = owner(i);
-                    int j = s_beg[lo] + (i - s_pre[lo]);
-                    int2 cr = g.cr[j];
-                    v = cr.x;
-                    int32_t r = FWD ? cr.y : g.capsum[j] - cr.y;
-                    bool open = !bit_of(bm_seen, v);  // pinned is marked visited at init
-                    if (r > 0 && open && atomicCAS(&g.h[v], N, lv + 1) == N) {
-                        slots = discover(g, bits, lv, v, &add);
+            for (int base = 0; base < total; base += GR_TD_U * BS) {
+                int vs[GR_TD_U], adds[GR_TD_U], lens[GR_TD_U];
+                int2 cr[GR_TD_U];
+                int32_t r[GR_TD_U];
+#pragma unroll
+                for (int k = 0; k < GR_TD_U; ++k) {  // the loads of all U slots first
+                    const int i = base + k * BS + tid;
+                    cr[k] = make_int2(-1, 0);
+                    r[k] = 0;
+                    if (i < total) {
+                        const int lo = owner(i);
+                        const int j = s_beg[lo] + (i - s_pre[lo]);
+                        cr[k] = g.cr[j];
+                        r[k] = FWD ? cr[k].y : g.capsum[j] - cr[k].y;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < GR_TD_U; ++k) {
+                    const int v = cr[k].x;
+                    vs[k] = v;
+                    adds[k] = 0;
+                    lens[k] = 0;
+                    // pinned is marked visited at init
+                    if (r[k] > 0 && !bit_of(bm_seen, v) && atomicCAS(&g.h[v], N, lv + 1) == N) {
+                        lens[k] = discover(g, bits, lv, v, &adds[k]);
                         found++;
                     }
                 }
-                append_entries(add, slots, v, qout, out_cnt);
+                block_append<BS, GR_TD_U>(vs, adds, lens, qout, out_cnt, s_agg);
             }
             __syncthreads();  // LDS is restaged next round
         }
@@ -619,7 +696,7 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
     unsigned long long per_slot = (s_bm ? 12ull : 16ull) - ((bu && !FWD) ? 4ull : 0ull);
     if (g.count_bytes) {
         unsigned long long b = wave_sum_u64(per_slot * scanned + 4ull * exam + 24ull * found);
-        if (lane == 0) add_bytes(g, KC_GR, b);
+        if (lane == 0) add_bytes(g, cls, b);
     }
 }
 
@@ -710,7 +787,7 @@ __global__ void __launch_bounds__(NARROW_BLOCK) k_gr_narrow(DevGraph g, int lv0,
             ctr->unv[lv % 3] = ctr->unv[(lv + 2) % 3] - fs;
         }
         __syncthreads();
-        gr_level_body<FWD, NARROW_BLOCK>(P, g, lv, cnt, qin, qout, ctr, bits, false, false, false, nullptr);
+        gr_level_body<FWD, NARROW_BLOCK>(P, g, lv, cnt, qin, qout, ctr, bits, false, false, false, nullptr, KC_GRS);
         __syncthreads();
         if (threadIdx.x == 0)
             s_front = __hip_atomic_load(&ctr->front[(lv + 1) % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -69,7 +69,9 @@ struct DevCounters {
     int32_t act_pad;
 };
 
-enum KernelClass { KC_GR = 0, KC_PR = 1, KC_RIE = 2, KC_WL = 3, KC_BATCH = 4, KC_INIT = 5, KC_NCLASS = 8 };
+// KC_GR: multi-block BFS level launches; KC_GRS: the relabel's seeding and its
+// one-workgroup thin-frontier levels
+enum KernelClass { KC_GR = 0, KC_PR = 1, KC_RIE = 2, KC_WL = 3, KC_BATCH = 4, KC_INIT = 5, KC_GRS = 6, KC_NCLASS = 8 };
 
 // Default degree bins for the worklist: rows up to BIN0_MAX slots get one
 // thread, up to BIN1_MAX one wave, longer rows one 1024-thread block.
