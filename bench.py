@@ -80,7 +80,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="batch512: skip the autotuner")
     ap.add_argument("--opt", action="append", default=[], metavar="KEY=INT",
                     help="graph workloads: a loop setting (bfs_alpha, bfs_beta, round_div, "
-                         "bin_thread_max, bin_wave_max); repeatable")
+                         "bin_thread_max, bin_wave_max, long_row_cycles); repeatable")
     ap.add_argument("--sweep-graph", default="rmat20", help="sweep: generator workload of the graph")
     ap.add_argument("--sweep-pcts", default="0.01,0.1,1,5,10", help="sweep: batch sizes in %% of |E|")
     ap.add_argument("--serve-slots", type=int, default=8, help="serve64: concurrent slots")
@@ -126,7 +126,7 @@ def main():
     extra = {}
     for kv in args.opt:
         key, _, val = kv.partition("=")
-        if key not in ("bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max"):
+        if key not in ("bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max", "long_row_cycles"):
             raise SystemExit(f"--opt: unknown setting {key!r}")
         extra[key] = int(val)
     G = mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0,

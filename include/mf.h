@@ -93,6 +93,11 @@ typedef struct mf_options {
     void* (*alloc)(size_t bytes, void* ctx);
     void (*free)(void* ptr, void* ctx);
     void* alloc_ctx;
+    int32_t long_row_cycles;   /* tuning: push/relabel cycles per launch for the rows a workgroup
+                                  takes (longer than bin_wave_max slots), at most kernel_cycles;
+                                  <= 0: 1.  Their excess left over waits for the next round, so a
+                                  hub's repeated full-row passes do not hold up the launch.
+                                  Single-graph handles (mf_batch_* use kernel_cycles). */
 } mf_options;
 
 /* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its
@@ -223,7 +228,8 @@ mf_status mf_graph_offload(mf_graph* g);
 mf_status mf_graph_restore(mf_graph* g);
 
 /* Apply the tuning fields of *opt (kernel_cycles, bfs_alpha, bfs_beta,
- * round_div, bin_thread_max, bin_wave_max; others ignored, 0 = default) to a
+ * round_div, bin_thread_max, bin_wave_max, long_row_cycles; others ignored, 0 =
+ * default) to a
  * live handle, for autotuners that time one handle under several settings.
  * Results never depend on them.  Errors: MF_ERR_INVALID (NULL, struct_size,
  * bin_wave_max below bin_thread_max), MF_ERR_STATE (offloaded). */

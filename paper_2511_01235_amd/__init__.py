@@ -53,7 +53,7 @@ class Options(C.Structure):
                 ("bfs_alpha", C.c_int32), ("bfs_beta", C.c_int32), ("round_div", C.c_int32),
                 ("bin_thread_max", C.c_int32), ("bin_wave_max", C.c_int32), ("batch_block", C.c_int32),
                 ("push_pull", C.c_int32), ("alloc", C.c_void_p), ("free", C.c_void_p),
-                ("alloc_ctx", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("long_row_cycles", C.c_int32)]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -83,7 +83,7 @@ class TorchAllocator:
 
 # fields mf_graph_tune / mf_batch_tune apply to a live handle
 TUNING_FIELDS = ("kernel_cycles", "bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max",
-                 "batch_block")
+                 "batch_block", "long_row_cycles")
 
 
 class Stats(C.Structure):
@@ -174,7 +174,7 @@ def mf_default_options() -> Options:
 def make_options(kernel_cycles=0, topology_driven=False, insert_slack_min=0, insert_slack_pct=0,
                  max_iterations=0, stream=None, device=-1, warm_start=True,
                  relabel_mode=0, bfs_alpha=0, bfs_beta=0, round_div=0, bin_thread_max=0, bin_wave_max=0,
-                 batch_block=0, push_pull=False, allocator=None) -> Options:
+                 batch_block=0, push_pull=False, allocator=None, long_row_cycles=0) -> Options:
     o = mf_default_options()
     o.push_pull = int(bool(push_pull))
     if allocator is not None:
@@ -182,6 +182,7 @@ def make_options(kernel_cycles=0, topology_driven=False, insert_slack_min=0, ins
         o.free = C.cast(allocator.free_fn, C.c_void_p).value
     o.bfs_alpha, o.bfs_beta, o.round_div = int(bfs_alpha), int(bfs_beta), int(round_div)
     o.bin_thread_max, o.bin_wave_max, o.batch_block = int(bin_thread_max), int(bin_wave_max), int(batch_block)
+    o.long_row_cycles = int(long_row_cycles)
     o.cold_start = 0 if warm_start else 1
     o.relabel_mode = int(relabel_mode)
     o.kernel_cycles = kernel_cycles

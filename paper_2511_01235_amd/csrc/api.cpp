@@ -73,6 +73,7 @@ struct mf_graph {
     int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
     int first_chunk = 8;      // BFS levels launched before the first frontier check
     bool trace_gr = false;    // MF_GR_TRACE: one level per launch, each printed to stderr
+    int32_t kc_block = 1;     // push/relabel cycles of the workgroup bin (capped at kc)
     int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
     int32_t round_max = 4096; // ... at most this many
     bool incremental_rounds = true;  // rounds take their worklist from the previous one plus activations
@@ -119,6 +120,9 @@ mf_status resolve_tuning(const mf_options& o, Tuning* t) {
     if (const char* env = std::getenv("MF_GR_BU_LB")) r.gr.bu_lb = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_GR_BU_WIDE")) r.gr.bu_wide = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_ROUND_DIV")) r.round_div = std::max(1, std::atoi(env));
+    r.long_cycles = 1;
+    if (const char* env = std::getenv("MF_KC_BLOCK")) r.long_cycles = std::max(1, std::atoi(env));
+    if (o.long_row_cycles > 0) r.long_cycles = o.long_row_cycles;
     if (o.bfs_alpha > 0) r.gr.bu_alpha = o.bfs_alpha;
     if (o.bfs_alpha < 0) r.gr.bu_alpha = 0;
     if (o.bfs_beta > 0) r.gr.bu_beta = o.bfs_beta;
@@ -361,7 +365,11 @@ void apply_tuning(mf_graph* g, const mf::Tuning& t) {
     g->round_div = t.round_div;
     g->dg.bin0_max = t.bin0;
     g->dg.bin1_max = t.bin1;
+    g->kc_block = t.long_cycles;
 }
+
+// Push/relabel cycles per launch for worklist bin b (2: rows a workgroup takes).
+int32_t kc_for_bin(const mf_graph* g, int b) { return b == 2 ? std::min(g->kc, g->kc_block) : g->kc; }
 
 mf_status ensure_batch_capacity(mf_graph* g, int64_t k) {
     if (k <= g->k_cap) return MF_OK;
@@ -578,11 +586,19 @@ mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) 
 // keeps the paper's one sweep per relabel.
 mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const int cnt[3]) {
     hipStream_t st = m.L.stream;
-    for (int b = 0; b < 3; ++b)
-        if (cnt[b])
-            timed(g, m.L, mf::KC_PR, [&] {
-                mf::launch_push_relabel(m.dg, wl[b], cnt[b], b, g->kc, m.pull, m.L.ctr, st);
-            });
+    for (int b = 0; b < 3; ++b) {
+        if (!cnt[b]) continue;
+        const int kc = kc_for_bin(g, b);
+        const auto t0 = std::chrono::steady_clock::now();
+        timed(g, m.L, mf::KC_PR, [&] {
+            mf::launch_push_relabel(m.dg, wl[b], cnt[b], b, kc, m.pull, m.L.ctr, st);
+        });
+        if (g->trace_gr) {
+            MF_HIP(hipStreamSynchronize(st));
+            std::fprintf(stderr, "[loop]   push bin %d rows %d us %.1f\n", b, cnt[b],
+                         std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count());
+        }
+    }
     if (m.rie)
         for (int b = 0; b < 3; ++b)
             if (cnt[b])
@@ -724,7 +740,9 @@ mf_status warm_sweep(mf_graph* g) {
     int cnt[3] = {g->ctr_h->wl[0], g->ctr_h->wl[1], g->ctr_h->wl[2]};
     for (int b = 0; b < 3; ++b)
         if (cnt[b])
-            timed(g, mf::KC_PR, [&] { mf::launch_push_relabel(m.dg, g->wl[b], cnt[b], b, g->kc, false, g->ctr, st); });
+            timed(g, mf::KC_PR, [&] {
+                mf::launch_push_relabel(m.dg, g->wl[b], cnt[b], b, kc_for_bin(g, b), false, g->ctr, st);
+            });
     for (int b = 0; b < 3; ++b)
         if (cnt[b])
             timed(g, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, g->wl[b], cnt[b], b, g->ctr, st); });

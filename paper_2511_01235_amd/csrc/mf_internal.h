@@ -206,9 +206,10 @@ struct Tuning {
     int32_t round_div;
     int32_t bin0, bin1;
     int32_t batch_block;
+    int32_t long_cycles;  // push/relabel cycles of the workgroup bin (capped at kc)
 };
 // MF_ERR_INVALID for inconsistent fields; environment overrides (MF_GR_*,
-// MF_ROUND_DIV) apply where the option is left 0.
+// MF_ROUND_DIV, MF_KC_BLOCK) apply where the option is left 0.
 mf_status resolve_tuning(const mf_options& o, Tuning* t);
 
 // ---- launch wrappers (kernels.hip) ---------------------------------------

@@ -32,9 +32,12 @@ GRAPH_SPACE = {
     "round_div": [4, 8, 16],
     "bin_thread_max": [8, 16, 32],
     "bin_wave_max": [256, 512, 1024],
+    "long_row_cycles": [1, 2, 4],
 }
-BATCH_SPACE = dict(GRAPH_SPACE, batch_block=[256, 512, 1024])
+# batched solves take long rows with kernel_cycles (one workgroup per graph)
+BATCH_SPACE = dict({k: v for k, v in GRAPH_SPACE.items() if k != "long_row_cycles"}, batch_block=[256, 512, 1024])
 DEFAULTS = {"kc_scale": 1.0, "bfs_alpha": 14, "round_div": 8, "bin_thread_max": 16, "bin_wave_max": 512,
+            "long_row_cycles": 1,
             "batch_block": 512}
 
 

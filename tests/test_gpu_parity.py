@@ -150,6 +150,23 @@ def test_thin_frontier_levels_bit_exact(name, narrow, monkeypatch):
             assert G.apply_batch(u, v, c) == o.apply(u, v, c)
 
 
+@pytest.mark.parametrize("cycles", [1, 2, 1000])
+@pytest.mark.parametrize("name", ["rmat12", "er2000"])
+def test_long_row_cycles_same_values(name, cycles):
+    """Rows above bin_wave_max slots run `cycles` push/relabel cycles per
+    launch (1000: capped at kernel_cycles); with bins of 4 and 8 slots most
+    rows take that path.  Static value and repairs equal the oracle's."""
+    g, stream, k, _ = gen.workload(name)
+    say("long-row cycles", name, cycles)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, long_row_cycles=cycles,
+                         bin_thread_max=4, bin_wave_max=8) as G:
+        assert G.maxflow() == o.static()
+        for _ in range(3):
+            u, v, c = stream.next_batch(k)
+            assert G.apply_batch(u, v, c) == o.apply(u, v, c)
+
+
 # --- static value ---------------------------------------------------------------
 
 def test_golden_static_gpu():
