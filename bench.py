@@ -150,6 +150,9 @@ def main():
     static_med = float(np.median(static_ms))
     log(f"static value {static_val}: {static_ms} ms; iterations {G.stats()['last_iterations']}")
 
+    # scattered-atomic reference rates for the push and relabel kernels (before
+    # the copy below, which opens the profiled window)
+    atomic_rates = {f"int{8 * w}_ops_per_s": round(mf.mf_debug_atomic_probe(1 << 26, w, 0), 1) for w in (4, 8)}
     # a plain copy of known size (64 Mi int32 = 256 MiB read + 256 MiB written): under
     # `rocprofv3 --pmc FETCH_SIZE` / `WRITE_SIZE` it calibrates the counters' units
     cal_src = torch.ones(64 << 20, dtype=torch.int32, device=dev)
@@ -161,8 +164,6 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 2 * cal_src.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del cal_src, cal_dst
-    # scattered-atomic reference rates for the push and relabel kernels
-    atomic_rates = {f"int{8 * w}_ops_per_s": round(mf.mf_debug_atomic_probe(1 << 26, w, 0), 1) for w in (4, 8)}
     log(f"copy probe {copy_gbs:.0f} GB/s; atomics {atomic_rates}")
 
     dev_batches = [torch.from_numpy(np.ascontiguousarray(np.stack(b, 1).astype(np.int32))).to(dev)

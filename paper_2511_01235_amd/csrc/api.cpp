@@ -73,9 +73,11 @@ struct mf_graph {
     int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
     int first_chunk = 8;      // BFS levels launched before the first frontier check
     bool trace_gr = false;    // MF_GR_TRACE: one level per launch, each printed to stderr
+    bool narrow_seed = true;  // start relabels in one workgroup (the last one's seeds were few enough)
     int32_t kc_block = 1;     // push/relabel cycles of the workgroup bin (capped at kc)
     int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
     int32_t round_max = 4096; // ... at most this many
+    int32_t round_min = 2;    // ... and at least this many (MF_ROUND_MIN)
     bool incremental_rounds = true;  // rounds take their worklist from the previous one plus activations
     int64_t narrow_max = 4096;       // BFS frontiers of up to this many slots run in one workgroup (0: never)
     // incremental worklists between relabels (made on first use)
@@ -474,7 +476,7 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
     // thin frontiers run in one workgroup, several levels per launch; the
     // first frontier is tried that way, later ones when a chunk leaves one
     // small enough
-    bool narrow = g->narrow_max > 0 && !g->trace_gr;
+    bool narrow = g->narrow_max > 0 && !g->trace_gr && g->narrow_seed;
     auto t_last = std::chrono::steady_clock::now();
     if (g->trace_gr) {
         mf_status rc = read_lane(g, m.L);
@@ -492,16 +494,20 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
             MF_HIP(hipGetLastError());
             mf_status rc = read_lane(g, m.L);
             if (rc != MF_OK) return rc;
+            const int level_before = level;
             level = m.L.ctr_h->levels;
+            if (level_before == 0) g->narrow_seed = (int64_t)(m.L.ctr_h->seed_front >> 32) <= g->narrow_max;
             const int cnt = (int)(unsigned)(m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull);
             if (cnt == 0) break;
             if (level > g->n + 2) {
                 g->poisoned = true;
                 return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
             }
-            // the multi-block levels read the current frontier's bitmap
-            timed(g, m.L, mf::KC_GRS,
-                  [&] { mf::launch_frontier_bitmap(m.L.q[level & 1], cnt, m.L.bits, level, st); });
+            // the multi-block levels read the current frontier's bitmap (the
+            // one-workgroup levels do not keep it; untouched if none ran)
+            if (level != level_before)
+                timed(g, m.L, mf::KC_GRS,
+                      [&] { mf::launch_frontier_bitmap(m.L.q[level & 1], cnt, m.L.bits, level, st); });
             chunk = g->first_chunk;
         }
         for (int i = 0; i < chunk; ++i, ++level)
@@ -512,6 +518,8 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
         MF_HIP(hipGetLastError());
         mf_status rc = read_lane(g, m.L);
         if (rc != MF_OK) return rc;
+        // seeds of the next relabel: like this one's, as its level 0 recorded them
+        g->narrow_seed = (int64_t)(m.L.ctr_h->seed_front >> 32) <= g->narrow_max;
         const int cnt = (int)(unsigned)(m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull);
         if (g->trace_gr) {
             // the level just done: its frontier, the unvisited slots before it,
@@ -581,9 +589,11 @@ mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) 
 // the lowest neighbour + 1, remove-invalid-edges saturates every steep
 // residual slot), so further rounds need no relabel; a vertex activated by a
 // push waits for the next worklist, so each round moves excess about one
-// more hop.  R is the relabel's depth divided by round_div (at least 1): a
-// deep BFS (long augmenting paths) buys many cheap rounds, a shallow one
-// keeps the paper's one sweep per relabel.
+// more hop.  R is the relabel's depth divided by round_div, at least
+// round_min (2): a deep BFS (long augmenting paths) buys many cheap rounds; on
+// a shallow one (RMAT, random graphs: depth under 10) a second round, which
+// starts from the activations of the first instead of a scan, still costs
+// well under a relabel and saves about a third of them.
 mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const int cnt[3]) {
     hipStream_t st = m.L.stream;
     for (int b = 0; b < 3; ++b) {
@@ -648,7 +658,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             return MF_ERR_NOT_CONVERGED;
         }
         const int64_t depth = levels - levels_before;
-        const int64_t R = std::min<int64_t>(g->round_max, std::max<int64_t>(1, depth / g->round_div));
+        const int64_t R = std::min<int64_t>(g->round_max, std::max<int64_t>(g->round_min, depth / g->round_div));
         int cnt[3] = {c.wl[0], c.wl[1], c.wl[2]};
         int32_t* cur[3] = {m.L.wl[0], m.L.wl[1], m.L.wl[2]};
         if (g->trace_gr)
@@ -1063,6 +1073,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     if (const char* env = std::getenv("MF_ROUND_SCAN")) g->incremental_rounds = std::atoi(env) == 0;
     if (const char* env = std::getenv("MF_GR_NARROW")) g->narrow_max = std::max(0LL, std::atoll(env));
     if (const char* env = std::getenv("MF_ROUND_MAX")) g->round_max = std::max(1, std::atoi(env));
+    if (const char* env = std::getenv("MF_ROUND_MIN")) g->round_min = std::max(1, std::atoi(env));
     if (o.relabel_mode == 1) g->persistent_grid = mf::persistent_gr_grid(dev);
     g->dg.n = n;
     g->dg.s = s;

@@ -724,7 +724,10 @@ __device__ __forceinline__ int gr_level_step(const Par& P, const DevGraph& g, in
                                              int2* qout, DevCounters* ctr, const GrBits& bits,
                                              const GrTune& tune, unsigned* s_dyn) {
     const int cnt = bcast((int)(unsigned)(ctr->front[lv % 3] & 0xFFFFFFFFull));
-    if (P.bid == 0 && threadIdx.x == 0) ctr->front[(lv + 2) % 3] = 0;
+    if (P.bid == 0 && threadIdx.x == 0) {
+        ctr->front[(lv + 2) % 3] = 0;
+        if (lv == 0) ctr->seed_front = ctr->front[0];
+    }
     if (cnt == 0) return 0;
     {   // the bitmap of level lv+2 (input of level lv-1, consumed) starts empty
         unsigned* z = bits.fb + (size_t)((lv + 2) % 3) * bits.nwords;
@@ -768,8 +771,10 @@ __global__ void __launch_bounds__(NARROW_BLOCK) k_gr_narrow(DevGraph g, int lv0,
     __shared__ unsigned long long s_front;
     const Par P{0, 1};
     int lv = lv0;
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         s_front = __hip_atomic_load(&ctr->front[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lv == 0) ctr->seed_front = s_front;
+    }
     __syncthreads();
     for (; lv <= g.n; ++lv) {
         const int2* qin = (lv & 1) ? q1 : q0;

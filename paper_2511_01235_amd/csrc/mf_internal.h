@@ -67,6 +67,7 @@ struct DevCounters {
     unsigned long long bytes[8];  // algorithmic bytes per kernel class
     int32_t act;               // vertices appended to DevGraph::act (may exceed act_cap: then some were dropped)
     int32_t act_pad;
+    unsigned long long seed_front;  // the last relabel's level-0 frontier (front[] format)
 };
 
 // KC_GR: multi-block BFS level launches; KC_GRS: the relabel's seeding and its

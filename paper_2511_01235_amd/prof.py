@@ -1,9 +1,10 @@
 """Summaries of rocprofv3 output for the benchmark (kernel trace and the
 FETCH_SIZE / WRITE_SIZE counter passes), as markdown.
 
-bench.py runs, in this order: the static solves (each starts with k_reset),
-one plain 256 MiB device copy that calibrates the counters, the warm-up and
-timed update batches, then the from-scratch solves (k_reset again).  The timed
+bench.py runs, in this order: the static solves (each starts with k_reset), the
+atomic probes, one plain 256 MiB device copy that calibrates the counters, the
+warm-up and timed update batches, then the from-scratch solves (k_reset
+again).  The timed
 window is therefore the dispatches after the largest copy and before the
 next k_reset; run the profiled bench with --warmup 0 so that the window holds
 exactly the timed batches.
@@ -87,6 +88,24 @@ def window_table(rows, a, b, top=10):
     return "\n".join(out), agg
 
 
+def busy_split(rows, a, b):
+    """(wall us, kernel-busy us) of dispatches a..b-1: the window from the
+    first start to the last end, and the union of the kernel intervals in it
+    (the rest is the device waiting on the host: launches and syncs)."""
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows[a:b])
+    if not iv:
+        return 0.0, 0.0
+    busy, cs, ce = 0, iv[0][0], iv[0][1]
+    for s, e in iv[1:]:
+        if s > ce:
+            busy += ce - cs
+            cs, ce = s, e
+        else:
+            ce = max(ce, e)
+    busy += ce - cs
+    return (max(e for _, e in iv) - iv[0][0]) / 1e3, busy / 1e3
+
+
 def counter_pass(path, kernel):
     """(counter name, calibration factor, mean KiB per dispatch of `kernel`
     in the timed window, dispatches)."""
@@ -114,17 +133,27 @@ def main():
         print("Commands (each from the repository root):\n\n```\n" + args.command.strip() + "\n```\n")
     print("## Whole run (rocprofv3 --stats)\n")
     print(stats_table(os.path.join(args.kt_dir, "run_kernel_stats.csv")) + "\n")
-    if not args.fetch_dir:
+    try:
+        a, b = timed_window(kt)
+    except ValueError:
+        a = b = None
+    if a is None or not args.fetch_dir:
         durs = [_dur_us(r) for r in kt if args.kernel in _name(r)]
-        print(f"`{args.kernel}` over the whole run: {len(durs)} launches, average {np.mean(durs):.2f} us")
+        print(f"`{args.kernel}` over the whole run: {len(durs)} launches, average {np.mean(durs):.2f} us\n")
+    if a is not None:
+        wt, agg = window_table(kt, a, b)
+        mine = [d for k, d in agg.items() if args.kernel in k]
+        durs = [x for d in mine for x in d]
+        print("## Timed window (after the calibration copy, before the first from-scratch solve)\n")
+        print(wt + "\n")
+        print(f"`{args.kernel}` in the window: {len(durs)} launches, average {np.mean(durs):.2f} us\n")
+        wall, busy = busy_split(kt, a, b)
+        if wall > 0:
+            print(f"Window: {wall / 1e3:.3f} ms from the first dispatch to the last, kernels busy "
+                  f"{busy / 1e3:.3f} ms ({100 * busy / wall:.1f}%); the rest is the device waiting on "
+                  f"host launches and synchronisations.\n")
+    if not args.fetch_dir:
         return
-    a, b = timed_window(kt)
-    wt, agg = window_table(kt, a, b)
-    mine = [d for k, d in agg.items() if args.kernel in k]
-    durs = [x for d in mine for x in d]
-    print("## Timed window (after the calibration copy, before the first from-scratch solve)\n")
-    print(wt + "\n")
-    print(f"`{args.kernel}` in the window: {len(durs)} launches, average {np.mean(durs):.2f} us\n")
     total = 0.0
     lines = []
     for d in (args.fetch_dir, args.write_dir):
