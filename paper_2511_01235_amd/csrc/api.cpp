@@ -784,6 +784,10 @@ mf_status relayout(mf_graph* g) {
     p.need = g->need;
     p.slack_min = g->slack_min;
     p.slack_pct = g->slack_pct;
+    // a stream of inserts that outgrew the slack once will again: each
+    // relayout doubles the fresh slack (up to 8x), so relayouts get rarer
+    // geometrically; slots past a row's length are never scanned
+    p.slack_shift = std::min(g->relayouts + 1, 3);
     mf::SlotArrays a{g->dg.cr, g->dg.rev, g->dg.cap, g->dg.capsum};
     int64_t S = 0;
     mf_status rc = mf::relayout_device(p, &a, g->slot_cap, &S, g->dg.row_ptr, g->dg.row_sorted, st, g->mem);

@@ -306,6 +306,7 @@ mf_status relayout_pool(mf_batch* b, const int32_t* need_d, const std::vector<ch
     p.grow = b->grow_d;
     p.slack_min = b->slack_min;
     p.slack_pct = b->slack_pct;
+    p.slack_shift = std::min(b->relayouts + 1, 3);  // as for single graphs
     mf::SlotArrays a{b->cr, b->rev, b->cap, b->capsum};
     int64_t S = 0;
     mf_status rc = mf::relayout_device(p, &a, b->total_s, &S, b->row_ptr, b->row_sorted, st, b->mem);

@@ -1894,7 +1894,7 @@ __global__ void __launch_bounds__(RL_BLOCK) k_relayout_sizes(RelayoutPlan p) {
     if (!p.grow || p.grow[i]) {
         long long want = (long long)len + p.need[gv];
         long long sl = (want * p.slack_pct + 99) / 100;
-        sz = want + (sl < p.slack_min ? p.slack_min : sl);
+        sz = want + ((sl < p.slack_min ? p.slack_min : sl) << p.slack_shift);
     } else {
         sz = (long long)p.row_ptr[rp + 1] - p.row_ptr[rp];
     }

@@ -174,6 +174,7 @@ struct RelayoutPlan {
     const int64_t* vbase;
     const uint8_t* grow;
     int32_t slack_min, slack_pct;
+    int32_t slack_shift;       // the fresh slack is scaled by 2^slack_shift (grows with each relayout)
     // scratch
     int64_t* size;             // V
     int64_t* start;            // V + 1
