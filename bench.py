@@ -62,6 +62,9 @@ def main():
                     help="one of " + ", ".join(sorted(WORKLOADS)) + ", or a scaled generator workload "
                          "(rmat<scale>, grid<width>)")
     ap.add_argument("--static-runs", type=int, default=3)
+    ap.add_argument("--roofline-steps", type=int, default=10,
+                    help="batches applied after the timed ones with per-launch event timing of the "
+                         "relabel's level kernel (the roofline); the timed batches run without events")
     ap.add_argument("--scratch-runs", type=int, default=3)
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -118,9 +121,10 @@ def main():
     t0 = time.time()
     g, bstream, k, nb = gen.workload(args.workload)
     total = args.warmup + args.steps
+    n_roof = 0 if args.profile_all else max(1, args.roofline_steps)
     if total > nb:
         log(f"note: {total} batches requested; the workload's stream continues past its nominal {nb}")
-    batches_np = [bstream.next_batch(k) for _ in range(total)]
+    batches_np = [bstream.next_batch(k) for _ in range(total + n_roof)]
     log(f"generated {g.name}: n={g.n} m={g.m} batches={total}x{k} in {time.time() - t0:.1f}s")
 
     extra = {}
@@ -179,8 +183,9 @@ def main():
         tuned = tune_graph(G, k, sync=torch.cuda.synchronize)
         log(f"tuned: {tuned}")
 
-    # dominant kernel: timed live over the whole timed region (HIP events on the library's stream)
-    G.profile(0xFF if args.profile_all else (1 << 0))
+    # no per-launch events in the timed region (they would split the chained
+    # BFS level launches); --profile-all times every class here instead
+    G.profile(0xFF if args.profile_all else 0)
     per_batch, iters = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -196,6 +201,7 @@ def main():
     prof = G.stats()
     G.profile(0)
     ms_per_step = elapsed_ms / args.steps
+    roof_elapsed_ms = elapsed_ms
 
     # from-scratch recompute of the same (final) graph on the GPU
     scratch_ms, scratch_val = [], None
@@ -208,6 +214,18 @@ def main():
         scratch_val = v
     assert scratch_val == values[-1], (scratch_val, values[-1])
     scratch_med = float(np.median(scratch_ms))
+    if n_roof:
+        # the relabel's level kernel, timed with HIP events on the library's
+        # stream over further batches of the same stream
+        G.profile(1 << 0)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for i in range(total, total + n_roof):
+            G.apply_batch_device(dev_batches[i])
+        torch.cuda.synchronize()
+        roof_elapsed_ms = (time.perf_counter() - a) * 1e3
+        prof = G.stats()
+        G.profile(0)
     G.close()
 
     # roofline of the dominant kernel class
@@ -233,7 +251,9 @@ def main():
                 "traffic": traffic, "launches": launches,
                 "avg_launch_us": round(kms * 1e3 / launches, 3) if launches else None,
                 "alg_bytes_per_launch": round(kbytes / launches, 1) if launches else None,
-                "share_of_step": round(kms / elapsed_ms, 4) if elapsed_ms > 0 else None,
+                "share_of_step": round(kms / roof_elapsed_ms, 4) if roof_elapsed_ms > 0 else None,
+                "timed_over": "every batch of the timed region" if not n_roof else
+                              f"{n_roof} batches after the timed region (per-launch events)",
                 "copy_probe_gbs": round(copy_gbs, 1), "atomic_probe": atomic_rates}
 
     cpu = None

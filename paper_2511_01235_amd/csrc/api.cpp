@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <utility>
 #include <thread>
@@ -74,6 +75,8 @@ struct mf_graph {
     int first_chunk = 8;      // BFS levels launched before the first frontier check
     bool trace_gr = false;    // MF_GR_TRACE: one level per launch, each printed to stderr
     bool narrow_seed = true;  // start relabels in one workgroup (the last one's seeds were few enough)
+    int32_t last_depth = 0;   // BFS levels of the last global relabel
+    bool queue_rounds = true; // MF_QUEUE_ROUNDS=0: no worklist build and rounds queued behind the relabel
     int32_t kc_block = 1;     // push/relabel cycles of the workgroup bin (capped at kc)
     int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
     int32_t round_max = 4096; // ... at most this many
@@ -468,15 +471,30 @@ mf_status read_lane(mf_graph* g, const Lane& L) {
 // Global relabel: seeds, then levels in growing chunks; each level launch
 // reads the frontier size on the device, so the host checks only after a
 // chunk.  Returns the number of level launches.
-mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
+//
+// tail (optional): launches queued right behind the first multi-block chunk,
+// before the host reads the counters -- the guarded worklist build and the
+// rounds after it.  *tail_valid tells whether the BFS ended within that
+// chunk, i.e. whether the tail did its work (else it was a no-op).
+mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out, int* depth_out,
+                         const std::function<void(int)>* tail = nullptr, bool* tail_valid = nullptr) {
+    // *levels_out counts level launches (a chunk's last ones may find the BFS
+    // over); *depth_out is the BFS's depth as the level kernels recorded it.
+    // The seed and depth hints kept on the handle are the main lane's (the
+    // pull lane of a push-pull repair runs on another thread).
     hipStream_t st = m.L.stream;
+    bool tail_queued = false;
+    if (tail_valid) *tail_valid = false;
     timed(g, m.L, mf::KC_GRS, [&] { mf::launch_gr_init(m.dg, m.L.q[0], m.L.ctr, m.L.bits, m.seed_deficits, st); });
     int level = 0;
-    int chunk = g->trace_gr ? 1 : g->first_chunk;
+    // the first chunk covers the last relabel's depth, so that a tail queued
+    // behind it usually finds the BFS over
+    int chunk = g->trace_gr ? 1 : (tail ? std::min(64, std::max(g->first_chunk, g->last_depth + 1)) : g->first_chunk);
+    const bool main = m.L.main;
     // thin frontiers run in one workgroup, several levels per launch; the
     // first frontier is tried that way, later ones when a chunk leaves one
     // small enough
-    bool narrow = g->narrow_max > 0 && !g->trace_gr && g->narrow_seed;
+    bool narrow = g->narrow_max > 0 && !g->trace_gr && (g->narrow_seed || !m.L.main);
     auto t_last = std::chrono::steady_clock::now();
     if (g->trace_gr) {
         mf_status rc = read_lane(g, m.L);
@@ -496,7 +514,8 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
             if (rc != MF_OK) return rc;
             const int level_before = level;
             level = m.L.ctr_h->levels;
-            if (level_before == 0) g->narrow_seed = (int64_t)(m.L.ctr_h->seed_front >> 32) <= g->narrow_max;
+            if (level_before == 0 && main)
+                g->narrow_seed = (int64_t)(m.L.ctr_h->seed_front >> 32) <= g->narrow_max;
             const int cnt = (int)(unsigned)(m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull);
             if (cnt == 0) break;
             if (level > g->n + 2) {
@@ -515,11 +534,16 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
                 mf::launch_gr_level(m.dg, level, m.L.q[level & 1], m.L.q[(level + 1) & 1], m.L.ctr,
                                     m.L.bits, g->tune, g->gr_grid, m.forward, st);
             });
+        const bool tail_now = tail && !tail_queued;
+        if (tail_now) {
+            (*tail)(level);
+            tail_queued = true;
+        }
         MF_HIP(hipGetLastError());
         mf_status rc = read_lane(g, m.L);
         if (rc != MF_OK) return rc;
         // seeds of the next relabel: like this one's, as its level 0 recorded them
-        g->narrow_seed = (int64_t)(m.L.ctr_h->seed_front >> 32) <= g->narrow_max;
+        if (main) g->narrow_seed = (int64_t)(m.L.ctr_h->seed_front >> 32) <= g->narrow_max;
         const int cnt = (int)(unsigned)(m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull);
         if (g->trace_gr) {
             // the level just done: its frontier, the unvisited slots before it,
@@ -536,7 +560,10 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
                          std::chrono::duration<double, std::micro>(now - t_last).count());
             t_last = now;
         }
-        if (cnt == 0) break;
+        if (cnt == 0) {
+            if (tail_now && tail_valid) *tail_valid = true;
+            break;
+        }
         if (level > g->n + 2) {
             g->poisoned = true;
             return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
@@ -546,6 +573,8 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
         narrow = g->narrow_max > 0 && (int64_t)(m.L.ctr_h->front[level % 3] >> 32) <= g->narrow_max;
     }
     *levels_out += level;
+    *depth_out = m.L.ctr_h->levels;
+    if (main) g->last_depth = *depth_out;
     return MF_OK;
 }
 
@@ -553,7 +582,8 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out) {
 // counters in ctr_h.  With cooperative launch support this is one persistent
 // kernel (every BFS level behind a grid barrier); otherwise one launch per
 // level plus one for the worklist.
-mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) {
+mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels, int* depth,
+                               const std::function<void(int)>* tail = nullptr, bool* tail_valid = nullptr) {
     hipStream_t st = m.L.stream;
     if (g->persistent_grid > 0) {
         hipError_t err = hipSuccess;
@@ -570,10 +600,12 @@ mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) 
             return MF_ERR_DEVICE;
         }
         *levels += m.L.ctr_h->levels;
+        *depth = m.L.ctr_h->levels;
         return MF_OK;
     }
-    mf_status rc = global_relabel(g, m, levels);
+    mf_status rc = global_relabel(g, m, levels, depth, tail, tail_valid);
     if (rc != MF_OK) return rc;
+    if (tail_valid && *tail_valid) return MF_OK;  // the tail built the worklist; counters read
     timed(g, m.L, mf::KC_WL, [&] {
         mf::launch_build_worklist(m.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology, m.sign, st);
     });
@@ -594,25 +626,21 @@ mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels) 
 // a shallow one (RMAT, random graphs: depth under 10) a second round, which
 // starts from the activations of the first instead of a scan, still costs
 // well under a relabel and saves about a third of them.
-mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const int cnt[3]) {
+// dev: the bins' sizes are the worklist counts on the device when the
+// kernels run, cnt[] only upper bounds for their grids.
+mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const int cnt[3], bool dev = false) {
     hipStream_t st = m.L.stream;
-    for (int b = 0; b < 3; ++b) {
-        if (!cnt[b]) continue;
-        const int kc = kc_for_bin(g, b);
-        const auto t0 = std::chrono::steady_clock::now();
-        timed(g, m.L, mf::KC_PR, [&] {
-            mf::launch_push_relabel(m.dg, wl[b], cnt[b], b, kc, m.pull, m.L.ctr, st);
-        });
-        if (g->trace_gr) {
-            MF_HIP(hipStreamSynchronize(st));
-            std::fprintf(stderr, "[loop]   push bin %d rows %d us %.1f\n", b, cnt[b],
-                         std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count());
-        }
+    const int32_t* dcount = dev ? m.L.ctr->wl : nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    timed(g, m.L, mf::KC_PR, [&] {
+        mf::launch_pr_fused(m.dg, wl, cnt, kc_for_bin(g, 0), kc_for_bin(g, 2), m.pull, st, dcount);
+    });
+    if (g->trace_gr) {
+        MF_HIP(hipStreamSynchronize(st));
+        std::fprintf(stderr, "[loop]   push rows by bin %d %d %d us %.1f\n", cnt[0], cnt[1], cnt[2],
+                     std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count());
     }
-    if (m.rie)
-        for (int b = 0; b < 3; ++b)
-            if (cnt[b])
-                timed(g, m.L, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, wl[b], cnt[b], b, m.L.ctr, st); });
+    if (m.rie) timed(g, m.L, mf::KC_RIE, [&] { mf::launch_rie_fused(m.dg, wl, cnt, m.L.ctr, st, dcount); });
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
@@ -642,12 +670,53 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         return MF_ERR_INVALID;
     hipStream_t st = m.L.stream;
     int64_t iters = 0, levels = 0, active_sum = 0, rounds = 0;
-    for (;;) {
-        const int64_t levels_before = levels;
-        mf_status rc = relabel_and_worklist(g, m, &levels);
+    // The main lane queues the worklist build and the first two rounds right
+    // behind the relabel's first chunk of BFS levels, sized on the device:
+    // an iteration whose BFS ends within that chunk reads the counters back
+    // once instead of three times.  (Rounds run on the worklist of a finished
+    // relabel only: the build is guarded on the device.)
+    const bool queue = g->queue_rounds && m.L.main && !m.pull && !m.topology && g->incremental_rounds &&
+                       g->round_min >= 2 && !g->trace_gr && g->persistent_grid == 0;
+    LoopMode qm = m;
+    if (queue) {
+        mf_status rc = ensure_round_lists(g);
         if (rc != MF_OK) return rc;
+        qm.dg.act = g->act_list;
+        qm.dg.act_cnt = &m.L.ctr->act;
+        qm.dg.act_cap = g->n;
+    }
+    const int bounds[3] = {(int)g->n, (int)g->n, (int)g->n};
+    mf_status tail_rc = MF_OK;
+    const std::function<void(int)> tail = [&](int level_end) {
+        timed(g, m.L, mf::KC_WL, [&] {
+            mf::launch_build_worklist(m.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology, m.sign, st,
+                                      level_end);
+        });
+        // the build cleared the activation count; the next-worklist build
+        // sets the worklist counts aside in wl_in (the host reads the
+        // relabel's there), round 2 keeps its own in wl
+        mf_status rc = push_round(g, qm, m.L.wl, bounds, true);
+        if (++g->epoch == INT_MAX) {
+            mf::launch_fill_i32(g->mark, 0, g->n, st);
+            g->epoch = 1;
+        }
+        timed(g, m.L, mf::KC_WL, [&] {
+            mf::launch_next_worklist(qm.dg, m.L.wl, nullptr, g->wlb[0], g->wlb[1], g->wlb[2], g->mark, g->epoch,
+                                     m.L.ctr, st);
+        });
+        mf::launch_zero_act(m.L.ctr, st);
+        if (rc == MF_OK) rc = push_round(g, qm, g->wlb, bounds, true);
+        if (tail_rc == MF_OK) tail_rc = rc;
+    };
+    for (;;) {
+        bool queued = false;
+        int depth = 0;
+        mf_status rc = relabel_and_worklist(g, m, &levels, &depth, queue ? &tail : nullptr, &queued);
+        if (rc != MF_OK) return rc;
+        if (tail_rc != MF_OK) return tail_rc;
         const DevCounters& c = *m.L.ctr_h;
-        int active = c.wl[3];
+        // the relabel's worklist (after queued rounds, the first round set its sizes aside)
+        const int active = queued ? c.wl_in[3] : c.wl[3];  // (set aside by the next-worklist build)
         active_sum += active;
         if (active == 0) {
             *value = (int64_t)c.e_t + (int64_t)c.deficit_sum;
@@ -657,13 +726,12 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             if (m.L.main) g->last_iterations = iters;
             return MF_ERR_NOT_CONVERGED;
         }
-        const int64_t depth = levels - levels_before;
         const int64_t R = std::min<int64_t>(g->round_max, std::max<int64_t>(g->round_min, depth / g->round_div));
-        int cnt[3] = {c.wl[0], c.wl[1], c.wl[2]};
-        int32_t* cur[3] = {m.L.wl[0], m.L.wl[1], m.L.wl[2]};
+        int cnt[3];
+        int32_t* cur[3];
         if (g->trace_gr)
             std::fprintf(stderr, "[loop] relabel %lld depth %lld active %d (rows by bin %d %d %d) rounds %lld\n",
-                         (long long)iters, (long long)depth, active, cnt[0], cnt[1], cnt[2], (long long)R);
+                         (long long)iters, (long long)depth, active, c.wl[0], c.wl[1], c.wl[2], (long long)R);
         // several rounds on the main lane: later worklists come from the
         // previous one plus the vertices the round activated, not a scan of
         // every vertex
@@ -675,55 +743,76 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             rm.dg.act = g->act_list;
             rm.dg.act_cnt = &m.L.ctr->act;
             rm.dg.act_cap = g->n;
-            mf::launch_zero_act(m.L.ctr, st);
         }
-        for (int64_t r = 0;; ++r) {
+        int64_t done = 0;  // rounds run on this relabel
+        if (queued) {
+            // two rounds ran; the second one's worklist and activations are on the device
+            done = 2;
+            rounds += 2;
+            for (int b = 0; b < 3; ++b) {
+                cur[b] = g->wlb[b];
+                cnt[b] = c.wl[b];
+            }
+            if (c.wl[3] == 0 || R <= 2) continue;  // certified by the next relabel
+            active_sum += c.wl[3];
+        } else {
+            for (int b = 0; b < 3; ++b) {
+                cur[b] = m.L.wl[b];
+                cnt[b] = c.wl[b];
+            }
+            // k_build_worklist cleared the activation count; the persistent
+            // relabel's worklist did not
+            if (incremental && g->persistent_grid > 0) mf::launch_zero_act(m.L.ctr, st);
+        }
+        for (;;) {
+            if (done > 0) {
+                if (done >= R) break;
+                bool rebuilt = false;
+                if (incremental) {
+                    if (++g->epoch == INT_MAX) {
+                        mf::launch_fill_i32(g->mark, 0, g->n, st);
+                        g->epoch = 1;
+                    }
+                    int32_t* nxt[3];
+                    for (int b = 0; b < 3; ++b) nxt[b] = cur[b] == m.L.wl[b] ? g->wlb[b] : m.L.wl[b];
+                    timed(g, m.L, mf::KC_WL, [&] {
+                        mf::launch_next_worklist(rm.dg, cur, cnt, nxt[0], nxt[1], nxt[2], g->mark, g->epoch,
+                                                 m.L.ctr, st);
+                    });
+                    MF_HIP(hipGetLastError());
+                    rc = read_lane(g, m.L);
+                    if (rc != MF_OK) return rc;
+                    if (c.act <= g->n) {
+                        for (int b = 0; b < 3; ++b) cur[b] = nxt[b];
+                        rebuilt = true;
+                        mf::launch_zero_act(m.L.ctr, st);
+                    }
+                    // else activations were dropped: scan every vertex instead
+                }
+                if (!rebuilt) {
+                    mf::launch_zero_loop_counters(m.L.ctr, st);
+                    timed(g, m.L, mf::KC_WL, [&] {
+                        mf::launch_build_worklist(m.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology,
+                                                  m.sign, st);
+                    });
+                    MF_HIP(hipGetLastError());
+                    rc = read_lane(g, m.L);
+                    if (rc != MF_OK) return rc;
+                    for (int b = 0; b < 3; ++b) cur[b] = m.L.wl[b];
+                }
+                if (g->trace_gr)
+                    std::fprintf(stderr, "[loop]   round %lld active %d (rows by bin %d %d %d)\n", (long long)done,
+                                 c.wl[3], c.wl[0], c.wl[1], c.wl[2]);
+                if (c.wl[3] == 0) break;  // certified by the next relabel
+                active_sum += c.wl[3];
+                cnt[0] = c.wl[0];
+                cnt[1] = c.wl[1];
+                cnt[2] = c.wl[2];
+            }
             rc = push_round(g, rm, cur, cnt);
             if (rc != MF_OK) return rc;
             ++rounds;
-            if (r + 1 >= R) break;
-            bool rebuilt = false;
-            if (incremental) {
-                if (++g->epoch == INT_MAX) {
-                    mf::launch_fill_i32(g->mark, 0, g->n, st);
-                    g->epoch = 1;
-                }
-                int32_t* nxt[3];
-                for (int b = 0; b < 3; ++b) nxt[b] = cur[b] == m.L.wl[b] ? g->wlb[b] : m.L.wl[b];
-                timed(g, m.L, mf::KC_WL, [&] {
-                    mf::launch_next_worklist(rm.dg, cur, cnt, nxt[0], nxt[1], nxt[2], g->mark, g->epoch, m.L.ctr,
-                                             st);
-                });
-                MF_HIP(hipGetLastError());
-                rc = read_lane(g, m.L);
-                if (rc != MF_OK) return rc;
-                if (c.act <= g->n) {
-                    for (int b = 0; b < 3; ++b) cur[b] = nxt[b];
-                    rebuilt = true;
-                    mf::launch_zero_act(m.L.ctr, st);
-                }
-                // else activations were dropped: scan every vertex instead
-            }
-            if (!rebuilt) {
-                mf::launch_zero_loop_counters(m.L.ctr, st);
-                timed(g, m.L, mf::KC_WL, [&] {
-                    mf::launch_build_worklist(m.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology, m.sign,
-                                              st);
-                });
-                MF_HIP(hipGetLastError());
-                rc = read_lane(g, m.L);
-                if (rc != MF_OK) return rc;
-                for (int b = 0; b < 3; ++b) cur[b] = m.L.wl[b];
-                if (incremental) mf::launch_zero_act(m.L.ctr, st);
-            }
-            if (g->trace_gr)
-                std::fprintf(stderr, "[loop]   round %lld active %d (rows by bin %d %d %d)\n", (long long)r + 1,
-                             c.wl[3], c.wl[0], c.wl[1], c.wl[2]);
-            if (c.wl[3] == 0) break;  // certified by the next relabel
-            active_sum += c.wl[3];
-            cnt[0] = c.wl[0];
-            cnt[1] = c.wl[1];
-            cnt[2] = c.wl[2];
+            ++done;
         }
     }
     if (m.L.main) {
@@ -744,18 +833,12 @@ mf_status warm_sweep(mf_graph* g) {
     timed(g, mf::KC_WL, [&] {
         mf::launch_build_worklist(m.dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, m.topology, 1, st);
     });
-    MF_HIP(hipGetLastError());
-    mf_status rc = read_counters(g);
-    if (rc != MF_OK) return rc;
-    int cnt[3] = {g->ctr_h->wl[0], g->ctr_h->wl[1], g->ctr_h->wl[2]};
-    for (int b = 0; b < 3; ++b)
-        if (cnt[b])
-            timed(g, mf::KC_PR, [&] {
-                mf::launch_push_relabel(m.dg, g->wl[b], cnt[b], b, kc_for_bin(g, b), false, g->ctr, st);
-            });
-    for (int b = 0; b < 3; ++b)
-        if (cnt[b])
-            timed(g, mf::KC_RIE, [&] { mf::launch_remove_invalid(m.dg, g->wl[b], cnt[b], b, g->ctr, st); });
+    // sized on the device: no read-back between the build and the sweep
+    const int bounds[3] = {(int)g->n, (int)g->n, (int)g->n};
+    timed(g, mf::KC_PR, [&] {
+        mf::launch_pr_fused(m.dg, g->wl, bounds, kc_for_bin(g, 0), kc_for_bin(g, 2), false, st, g->ctr->wl);
+    });
+    timed(g, mf::KC_RIE, [&] { mf::launch_rie_fused(m.dg, g->wl, bounds, g->ctr, st, g->ctr->wl); });
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
@@ -1074,6 +1157,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     if (const char* env = std::getenv("MF_GR_GRID")) g->gr_grid = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_GR_FIRST_CHUNK")) g->first_chunk = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_GR_TRACE")) g->trace_gr = std::atoi(env) != 0;
+    if (const char* env = std::getenv("MF_QUEUE_ROUNDS")) g->queue_rounds = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_ROUND_SCAN")) g->incremental_rounds = std::atoi(env) == 0;
     if (const char* env = std::getenv("MF_GR_NARROW")) g->narrow_max = std::max(0LL, std::atoll(env));
     if (const char* env = std::getenv("MF_ROUND_MAX")) g->round_max = std::max(1, std::atoi(env));
@@ -1464,9 +1548,10 @@ mf_status mf_debug_initial_labels(mf_graph* g, int32_t* heights, int64_t* excess
     mf::launch_saturate_source(g->dg, g->ctr, st);
     MF_HIP(hipGetLastError());
     int64_t levels = 0;
+    int depth = 0;
     LoopMode m = solve_mode(g);
     m.topology = false;
-    rc = relabel_and_worklist(g, m, &levels);
+    rc = relabel_and_worklist(g, m, &levels, &depth);
     if (rc != MF_OK) return rc;
     settle_events(g);
     const DevCounters c = *g->ctr_h;

@@ -294,7 +294,10 @@ __global__ void k_zero_counters_front(DevCounters* ctr) {
 // Between push-relabel rounds: clear the worklist counts (before the next
 // worklist) or the activation count (before the next push-relabel).
 __global__ void k_zero_counts(DevCounters* ctr, int wl, int act) {
-    if (wl && threadIdx.x < 4) ctr->wl[threadIdx.x] = 0;
+    if (wl && threadIdx.x < 4) {
+        ctr->wl_in[threadIdx.x] = ctr->wl[threadIdx.x];  // the lists the next build reads
+        ctr->wl[threadIdx.x] = 0;
+    }
     if (act && threadIdx.x == 0) ctr->act = 0;
 }
 
@@ -356,15 +359,20 @@ __device__ __forceinline__ void block_append(const int (&vs)[U], const int (&add
 __device__ __forceinline__ bool bit_of(const unsigned* bm, int v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
 __device__ __forceinline__ void set_bit(unsigned* bm, int v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
 
+// WORDS: the bitmaps are written a whole word at a time (a wave's 64
+// vertices are consecutive and 64-aligned: two words per bitmap), so they
+// need no clearing beforehand; else single bits are set into cleared maps.
+template <bool WORDS = false>
 __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, int2* q0, DevCounters* ctr,
                                              const GrBits& bits, int seed_deficits, int cls = KC_GR) {
     const int N = g.n;
     for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
         int v = base + threadIdx.x;
         int add = 0, slots = 0;
+        bool vis = false, front = false;
         if (v < N && g.side && g.side[v] != g.side_keep) {
             g.h[v] = N;                 // the other side: never labelled by this relabel
-            set_bit(bits.visited, v);
+            vis = true;
         } else if (v < N) {
             // seed_deficits 1: deficient vertices are extra roots; -1: overflowing ones
             bool extra = false;
@@ -377,11 +385,25 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
             if (seed) {
                 slots = g.row_len[v];
                 add = (slots + GR_CHUNK - 1) / GR_CHUNK;
-                set_bit(bits.visited, v);
-                set_bit(bits.fb, v);
-            } else if (v == g.pinned) {
-                set_bit(bits.visited, v);  // never labelled
             }
+            vis = seed || v == g.pinned;  // the pinned vertex is never labelled
+            front = seed;
+        }
+        if (WORDS) {
+            const unsigned long long mv = __ballot(vis), mf = __ballot(front);
+            const int lane = lane_id();
+            const int w = (v >> 5);
+            if ((lane & 31) == 0 && w < bits.nwords) {
+                const unsigned hv = lane < 32 ? (unsigned)mv : (unsigned)(mv >> 32);
+                const unsigned hf = lane < 32 ? (unsigned)mf : (unsigned)(mf >> 32);
+                bits.visited[w] = hv;
+                bits.fb[w] = hf;
+                bits.fb[(size_t)bits.nwords + w] = 0u;
+                bits.fb[2 * (size_t)bits.nwords + w] = 0u;
+            }
+        } else {
+            if (vis) set_bit(bits.visited, v);
+            if (front) set_bit(bits.fb, v);
         }
         append_entries(add, slots, v, q0, &ctr->front[0]);
     }
@@ -394,7 +416,7 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
 
 __global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr, GrBits bits,
                                                  int seed_deficits) {
-    gr_init_body(hw_par(), g, q0, ctr, bits, seed_deficits, KC_GRS);
+    gr_init_body<true>(hw_par(), g, q0, ctr, bits, seed_deficits, KC_GRS);
 }
 
 // One BFS level.  Top-down (small frontier): each block takes 256 frontier
@@ -727,6 +749,7 @@ __device__ __forceinline__ int gr_level_step(const Par& P, const DevGraph& g, in
     if (P.bid == 0 && threadIdx.x == 0) {
         ctr->front[(lv + 2) % 3] = 0;
         if (lv == 0) ctr->seed_front = ctr->front[0];
+        if (cnt) ctr->levels = lv + 1;  // the BFS's depth so far (levels are launched in order)
     }
     if (cnt == 0) return 0;
     {   // the bitmap of level lv+2 (input of level lv-1, consumed) starts empty
@@ -915,7 +938,16 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
 
 __global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0, int32_t* wl1,
                                                         int32_t* wl2, DevCounters* ctr,
-                                                        int topology, int sign) {
+                                                        int topology, int sign, int guard_level) {
+    // The first round's activations start here -- also when the build is
+    // skipped below, so that nothing queued behind it finds work: neither
+    // the rounds (worklist sizes zero) nor the next-worklist build after the
+    // first of them (no activations either).
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->act = 0;
+    // guard_level >= 0: queued behind BFS levels up to guard_level - 1 before
+    // the host knew whether the BFS ends there; a frontier still waiting at
+    // guard_level means it did not, and this build is skipped
+    if (guard_level >= 0 && (ctr->front[guard_level % 3] & 0xFFFFFFFFull) != 0) return;
     worklist_body<256>(hw_par(), g, wl0, wl1, wl2, ctr, topology, sign);
 }
 
@@ -1221,10 +1253,12 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
 
 template <bool PULL>
 __global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl, int count, int kc,
-                                                   DevCounters* ctr) {
+                                                   DevCounters* ctr, const int32_t* dcount) {
     (void)ctr;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long bytes = i < count ? pr_thread_item<PULL>(g, wl[i], kc) : 0ull;
+    const int cnt = dcount ? *dcount : count;
+    unsigned long long bytes = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x)
+        bytes += pr_thread_item<PULL>(g, wl[i], kc);
     if (g.count_bytes) {
         unsigned long long b = wave_sum_u64(bytes);
         if (lane_id() == 0) add_bytes(g, KC_PR, b);
@@ -1233,21 +1267,66 @@ __global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl
 
 template <bool PULL>
 __global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, int count, int kc,
-                                                 DevCounters* ctr) {
+                                                 DevCounters* ctr, const int32_t* dcount) {
     (void)ctr;
-    int w = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    if (w >= count) return;  // whole wave
-    unsigned long long bytes = pr_wave_item<PULL>(g, bcast(wl[w]), kc);
-    if (lane_id() == 0) add_bytes(g, KC_PR, bytes);
+    const int cnt = dcount ? *dcount : count;
+    const int waves = (int)(gridDim.x * blockDim.x / WAVE);
+    unsigned long long bytes = 0;
+    for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE; w < cnt; w += waves)  // whole waves
+        bytes += pr_wave_item<PULL>(g, bcast(wl[w]), kc);
+    if (lane_id() == 0 && bytes) add_bytes(g, KC_PR, bytes);
 }
 
 template <bool PULL>
 __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t* wl, int count,
-                                                       int kc, DevCounters* ctr) {
+                                                       int kc, DevCounters* ctr, const int32_t* dcount) {
     (void)ctr;
-    if ((int)blockIdx.x >= count) return;
-    unsigned long long bytes = pr_block_item<PULL, BLOCK_PR>(g, wl[blockIdx.x], kc);
-    if (threadIdx.x == 0) add_bytes(g, KC_PR, bytes);
+    const int cnt = dcount ? *dcount : count;
+    unsigned long long bytes = 0;
+    for (int it = blockIdx.x; it < cnt; it += gridDim.x)  // whole blocks
+        bytes += pr_block_item<PULL, BLOCK_PR>(g, wl[it], kc);
+    if (threadIdx.x == 0 && bytes) add_bytes(g, KC_PR, bytes);
+}
+
+// One launch for a round's thread and wave bins (the workgroup bin has its
+// own 1024-thread launch: in one kernel with these its registers would halve
+// their occupancy).  The 256-thread workgroups take virtual blocks in turn:
+// first BS / WAVE rows of the wave bin per block, then BS rows of the thread
+// bin.  Bin sizes: dcount[0..1] on the device when dcount is set, else c0, c1.
+struct BinSizes {
+    int c0, c1, c2;
+};
+__device__ __forceinline__ BinSizes bin_sizes(const int32_t* dcount, int c0, int c1, int c2) {
+    if (dcount) return BinSizes{dcount[0], dcount[1], dcount[2]};
+    return BinSizes{c0, c1, c2};
+}
+
+constexpr int PR_SMALL_BLOCK = 256;
+
+template <bool PULL>
+__global__ void __launch_bounds__(PR_SMALL_BLOCK) k_pr_small(DevGraph g, const int32_t* wl0, const int32_t* wl1,
+                                                             int c0, int c1, int kc, const int32_t* dcount) {
+    constexpr int BS = PR_SMALL_BLOCK, WPB = BS / WAVE;
+    const BinSizes c = bin_sizes(dcount, c0, c1, 0);
+    const int nb1 = (c.c1 + WPB - 1) / WPB, nb0 = (c.c0 + BS - 1) / BS;
+    const int total = nb1 + nb0;
+    unsigned long long bytes = 0;  // thread items per thread, wave items on lane 0
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {  // block-uniform roles
+        if (vb < nb1) {
+            const int w = vb * WPB + (int)threadIdx.x / WAVE;
+            if (w < c.c1) {  // whole waves
+                const unsigned long long b = pr_wave_item<PULL>(g, bcast(wl1[w]), kc);
+                if (lane_id() == 0) bytes += b;
+            }
+        } else {
+            const int i = (vb - nb1) * BS + (int)threadIdx.x;
+            if (i < c.c0) bytes += pr_thread_item<PULL>(g, wl0[i], kc);
+        }
+    }
+    if (g.count_bytes) {
+        const unsigned long long b = wave_sum_u64(bytes);
+        if (lane_id() == 0 && b) add_bytes(g, KC_PR, b);
+    }
 }
 
 // ---- remove invalid edges (Algorithm 3) ------------------------------------
@@ -1295,11 +1374,11 @@ __device__ __forceinline__ long long rie_item(DevGraph& g, int u, int sub, unsig
 }
 
 __global__ void __launch_bounds__(256) k_rie_thread(DevGraph g, const int32_t* wl, int count,
-                                                    DevCounters* ctr) {
+                                                    DevCounters* ctr, const int32_t* dcount) {
     (void)ctr;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cnt = dcount ? *dcount : count;
     unsigned long long bytes = 0;
-    if (i < count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
         int u = wl[i];
         long long moved = rie_item<1>(g, u, 0, &bytes);
         if (moved) add_e(g.e, u, -moved);
@@ -1314,22 +1393,60 @@ __global__ void __launch_bounds__(256) k_rie_thread(DevGraph g, const int32_t* w
 // atomic on e(u) per wave.
 template <int GROUP>
 __global__ void __launch_bounds__(256) k_rie_group(DevGraph g, const int32_t* wl, int count,
-                                                   DevCounters* ctr) {
+                                                   DevCounters* ctr, const int32_t* dcount) {
     (void)ctr;
-    int item = (blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
-    int sub = threadIdx.x % GROUP;
+    const int cnt = dcount ? *dcount : count;
+    const int groups = (int)(gridDim.x * blockDim.x / GROUP);
+    const int sub = threadIdx.x % GROUP;
     unsigned long long bytes = 0;
-    long long moved = 0;
-    int u = -1;
-    if (item < count) {
-        u = wl[item];
-        moved = rie_item<GROUP>(g, u, sub, &bytes);
+    // whole groups (waves or blocks) take the same items
+    for (int item = (blockIdx.x * blockDim.x + threadIdx.x) / GROUP; item < cnt; item += groups) {
+        const int u = wl[item];
+        long long moved = wave_sum_i64(rie_item<GROUP>(g, u, sub, &bytes));
+        if (lane_id() == 0 && moved) add_e(g.e, u, -moved);
     }
-    moved = wave_sum_i64(moved);
-    if (lane_id() == 0 && moved && u >= 0) add_e(g.e, u, -moved);
     if (g.count_bytes) {
         unsigned long long b = wave_sum_u64(bytes);
         if (lane_id() == 0) add_bytes(g, KC_RIE, b);
+    }
+}
+
+// Remove-invalid-edges for a round's three bins in one launch (256-thread
+// workgroups taking virtual blocks as in k_pr_small, the workgroup bin's
+// rows first, one per block).
+__global__ void __launch_bounds__(256) k_rie_fused(DevGraph g, const int32_t* wl0, const int32_t* wl1,
+                                                   const int32_t* wl2, int c0, int c1, int c2,
+                                                   DevCounters* ctr, const int32_t* dcount) {
+    (void)ctr;
+    constexpr int BS = 256, WPB = BS / WAVE;
+    const BinSizes c = bin_sizes(dcount, c0, c1, c2);
+    const int nb2 = c.c2, nb1 = (c.c1 + WPB - 1) / WPB, nb0 = (c.c0 + BS - 1) / BS;
+    const int total = nb2 + nb1 + nb0;
+    unsigned long long bytes = 0;
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {  // block-uniform roles
+        if (vb < nb2) {
+            const int u = wl2[vb];
+            const long long moved = wave_sum_i64(rie_item<BS>(g, u, (int)threadIdx.x, &bytes));
+            if (lane_id() == 0 && moved) add_e(g.e, u, -moved);
+        } else if (vb < nb2 + nb1) {
+            const int item = (vb - nb2) * WPB + (int)threadIdx.x / WAVE;
+            if (item < c.c1) {  // whole waves
+                const int u = wl1[item];
+                const long long moved = wave_sum_i64(rie_item<WAVE>(g, u, lane_id(), &bytes));
+                if (lane_id() == 0 && moved) add_e(g.e, u, -moved);
+            }
+        } else {
+            const int i = (vb - nb2 - nb1) * BS + (int)threadIdx.x;
+            if (i < c.c0) {
+                const int u = wl0[i];
+                const long long moved = rie_item<1>(g, u, 0, &bytes);
+                if (moved) add_e(g.e, u, -moved);
+            }
+        }
+    }
+    if (g.count_bytes) {
+        const unsigned long long b = wave_sum_u64(bytes);
+        if (lane_id() == 0 && b) add_bytes(g, KC_RIE, b);
     }
 }
 
@@ -1843,6 +1960,11 @@ __global__ void __launch_bounds__(256) k_next_worklist(DevGraph g, const int32_t
                                                        const int32_t* in2, int c0, int c1, int c2, int32_t* out0,
                                                        int32_t* out1, int32_t* out2, int32_t* mark, int32_t epoch,
                                                        DevCounters* ctr) {
+    if (c0 < 0) {  // the input lists' sizes on the device (set aside by k_zero_counts)
+        c0 = ctr->wl_in[0];
+        c1 = ctr->wl_in[1];
+        c2 = ctr->wl_in[2];
+    }
     const int na = min(*g.act_cnt, g.act_cap);
     const long long total = (long long)c0 + c1 + c2 + na;
     for (long long base = (long long)blockIdx.x * blockDim.x; base < total;
@@ -2112,7 +2234,7 @@ void launch_zero_loop_counters(DevCounters* ctr, hipStream_t st) {
 void launch_gr_init(const DevGraph& g, int2* q0, DevCounters* ctr, const GrBits& bits, int seed_deficits,
                     hipStream_t st) {
     k_zero_counters_front<<<1, 64, 0, st>>>(ctr);
-    launch_fill_i32(reinterpret_cast<int32_t*>(bits.visited), 0, 4 * (int64_t)bits.nwords, st);
+    // k_gr_init writes the four bitmaps whole (no clearing launch)
     k_gr_init<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, q0, ctr, bits, seed_deficits);
 }
 
@@ -2199,40 +2321,84 @@ hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounte
 }
 
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
-                           DevCounters* ctr, bool topology, int sign, hipStream_t st) {
+                           DevCounters* ctr, bool topology, int sign, hipStream_t st, int guard_level) {
     k_build_worklist<<<grid_for(g.n, 256, 8192), 256, 0, st>>>(g, wl0, wl1, wl2, ctr, topology ? 1 : 0,
-                                                              sign);
+                                                              sign, guard_level);
 }
+
+// Grids of the push-relabel and remove-invalid-edges launches.  With the
+// size known on the host (dcount null) one worker per item; with the size on
+// the device (dcount, a worklist counter) `count` is only an upper bound and
+// the grid is capped: the kernels loop over their items.
+constexpr int DEV_COUNT_BLOCKS = 2048;   // thread and wave bins
+constexpr int DEV_COUNT_ITEMS = 1024;    // workgroup bin: workgroups in flight
 
 template <bool PULL>
 static void launch_pr_bins(const DevGraph& g, const int32_t* wl, int count, int bin, int kc,
-                           DevCounters* ctr, hipStream_t st) {
+                           DevCounters* ctr, hipStream_t st, const int32_t* dcount) {
+    const bool dev = dcount != nullptr;
     if (bin == 0)
-        k_pr_thread<PULL><<<grid_for(count, 256, 1 << 30), 256, 0, st>>>(g, wl, count, kc, ctr);
+        k_pr_thread<PULL><<<grid_for(count, 256, dev ? DEV_COUNT_BLOCKS : 1 << 30), 256, 0, st>>>(
+            g, wl, count, kc, ctr, dcount);
     else if (bin == 1)
-        k_pr_wave<PULL><<<grid_for((int64_t)count * WAVE, 256, 1 << 30), 256, 0, st>>>(g, wl, count, kc, ctr);
+        k_pr_wave<PULL><<<grid_for((int64_t)count * WAVE, 256, dev ? DEV_COUNT_BLOCKS : 1 << 30), 256, 0, st>>>(
+            g, wl, count, kc, ctr, dcount);
     else
-        k_pr_block<PULL><<<count, BLOCK_PR, 0, st>>>(g, wl, count, kc, ctr);
+        k_pr_block<PULL><<<dev ? std::min(count, DEV_COUNT_ITEMS) : count, BLOCK_PR, 0, st>>>(g, wl, count, kc,
+                                                                                          ctr, dcount);
 }
 
 void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc, bool pull,
-                         DevCounters* ctr, hipStream_t st) {
+                         DevCounters* ctr, hipStream_t st, const int32_t* dcount) {
     if (count <= 0) return;
     if (pull)
-        launch_pr_bins<true>(g, wl, count, bin, kc, ctr, st);
+        launch_pr_bins<true>(g, wl, count, bin, kc, ctr, st, dcount);
     else
-        launch_pr_bins<false>(g, wl, count, bin, kc, ctr, st);
+        launch_pr_bins<false>(g, wl, count, bin, kc, ctr, st, dcount);
 }
 
 void launch_remove_invalid(const DevGraph& g, const int32_t* wl, int count, int bin,
-                           DevCounters* ctr, hipStream_t st) {
+                           DevCounters* ctr, hipStream_t st, const int32_t* dcount) {
     if (count <= 0) return;
+    const bool dev = dcount != nullptr;
     if (bin == 0)
-        k_rie_thread<<<grid_for(count, 256, 1 << 30), 256, 0, st>>>(g, wl, count, ctr);
+        k_rie_thread<<<grid_for(count, 256, dev ? DEV_COUNT_BLOCKS : 1 << 30), 256, 0, st>>>(g, wl, count, ctr,
+                                                                                          dcount);
     else if (bin == 1)
-        k_rie_group<64><<<grid_for((int64_t)count * 64, 256, 1 << 30), 256, 0, st>>>(g, wl, count, ctr);
+        k_rie_group<64><<<grid_for((int64_t)count * 64, 256, dev ? DEV_COUNT_BLOCKS : 1 << 30), 256, 0, st>>>(
+            g, wl, count, ctr, dcount);
     else
-        k_rie_group<256><<<count, 256, 0, st>>>(g, wl, count, ctr);
+        k_rie_group<256><<<dev ? std::min(count, DEV_COUNT_ITEMS) : count, 256, 0, st>>>(g, wl, count, ctr,
+                                                                                      dcount);
+}
+
+constexpr int PR_SMALL_GRID = 4096;   // 256-thread workgroups: 16 per CU
+constexpr int PR_BLOCK_GRID = 1024;   // 1024-thread workgroups
+constexpr int RIE_FUSED_GRID = 2048;  // 256-thread workgroups
+
+void launch_pr_fused(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], int kc, int kc_long,
+                     bool pull, hipStream_t st, const int32_t* dcount) {
+    // the workgroup bin first: its rows are the longest
+    if (cnt[2] > 0) {
+        const int grid = dcount ? std::min(cnt[2], PR_BLOCK_GRID) : cnt[2];
+        const int32_t* d2 = dcount ? dcount + 2 : nullptr;
+        if (pull) k_pr_block<true><<<grid, BLOCK_PR, 0, st>>>(g, wl[2], cnt[2], kc_long, nullptr, d2);
+        else k_pr_block<false><<<grid, BLOCK_PR, 0, st>>>(g, wl[2], cnt[2], kc_long, nullptr, d2);
+    }
+    const int64_t total = (int64_t)(cnt[1] + PR_SMALL_BLOCK / WAVE - 1) / (PR_SMALL_BLOCK / WAVE) +
+                          (cnt[0] + PR_SMALL_BLOCK - 1) / PR_SMALL_BLOCK;
+    if (total <= 0) return;
+    const int grid = (int)std::min<int64_t>(total, dcount ? PR_SMALL_GRID : 1 << 30);
+    if (pull) k_pr_small<true><<<grid, PR_SMALL_BLOCK, 0, st>>>(g, wl[0], wl[1], cnt[0], cnt[1], kc, dcount);
+    else k_pr_small<false><<<grid, PR_SMALL_BLOCK, 0, st>>>(g, wl[0], wl[1], cnt[0], cnt[1], kc, dcount);
+}
+
+void launch_rie_fused(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], DevCounters* ctr,
+                      hipStream_t st, const int32_t* dcount) {
+    const int64_t total = (int64_t)cnt[2] + (cnt[1] + 3) / 4 + (cnt[0] + 255) / 256;
+    if (total <= 0) return;
+    const int grid = (int)std::min<int64_t>(total, dcount ? RIE_FUSED_GRID : 1 << 30);
+    k_rie_fused<<<grid, 256, 0, st>>>(g, wl[0], wl[1], wl[2], cnt[0], cnt[1], cnt[2], ctr, dcount);
 }
 
 void launch_clear_counters(DevCounters* ctr, hipStream_t st) {
@@ -2317,10 +2483,13 @@ void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st) {
 void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const int cnt[3], int32_t* out0,
                           int32_t* out1, int32_t* out2, int32_t* mark, int32_t epoch, DevCounters* ctr,
                           hipStream_t st) {
+    // cnt null: the input sizes are the worklist counts, which k_zero_counts
+    // sets aside in wl_in before it clears them
     k_zero_counts<<<1, 64, 0, st>>>(ctr, 1, 0);
-    const int64_t most = (int64_t)cnt[0] + cnt[1] + cnt[2] + g.act_cap;
-    k_next_worklist<<<grid_for(most, 256, 2048), 256, 0, st>>>(g, in[0], in[1], in[2], cnt[0], cnt[1], cnt[2],
-                                                              out0, out1, out2, mark, epoch, ctr);
+    const int64_t most = cnt ? (int64_t)cnt[0] + cnt[1] + cnt[2] + g.act_cap : (int64_t)g.n + g.act_cap;
+    k_next_worklist<<<grid_for(most, 256, 2048), 256, 0, st>>>(g, in[0], in[1], in[2], cnt ? cnt[0] : -1,
+                                                              cnt ? cnt[1] : 0, cnt ? cnt[2] : 0, out0, out1,
+                                                              out2, mark, epoch, ctr);
 }
 
 void launch_zero_act(DevCounters* ctr, hipStream_t st) {

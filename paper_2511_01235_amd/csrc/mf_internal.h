@@ -56,7 +56,9 @@ struct DevCounters {
     int32_t overflow;          // batch: row slack exhausted
     int32_t new_pairs;         // batch: distinct absent pairs
     int32_t cap_overflow;      // batch: c(u,v)+c(v,u) would leave int32
-    int32_t levels;            // levels run by the persistent global relabel
+    int32_t levels;            // global relabel: the level after the last non-empty one so far (the
+                               // BFS depth once it is over; the one-workgroup levels leave the
+                               // level to continue from)
     int32_t bar_err;           // persistent global relabel: barrier gave up / level bound hit
     unsigned bar_count;        // grid barrier arrivals
     unsigned bar_gen;          // grid barrier generation
@@ -68,6 +70,7 @@ struct DevCounters {
     int32_t act;               // vertices appended to DevGraph::act (may exceed act_cap: then some were dropped)
     int32_t act_pad;
     unsigned long long seed_front;  // the last relabel's level-0 frontier (front[] format)
+    int32_t wl_in[4];          // worklist sizes as the last next-worklist build found them (its input)
 };
 
 // KC_GR: multi-block BFS level launches; KC_GRS: the relabel's seeding and its
@@ -235,12 +238,16 @@ hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounte
                                 const GrBits& bits, const GrTune& tune, int seed_deficits, bool forward,
                                 int32_t* wl0, int32_t* wl1, int32_t* wl2, bool topology, int sign,
                                 int grid, hipStream_t st);
+// guard_level >= 0: a build queued behind BFS levels up to guard_level - 1
+// does nothing unless the BFS ended there
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
-                           DevCounters* ctr, bool topology, int sign, hipStream_t st);
+                           DevCounters* ctr, bool topology, int sign, hipStream_t st, int guard_level = -1);
+// dcount null: `count` items; else the item count is *dcount on the device
+// (read when the kernel runs) and `count` an upper bound for the grid
 void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc, bool pull,
-                         DevCounters* ctr, hipStream_t st);
+                         DevCounters* ctr, hipStream_t st, const int32_t* dcount = nullptr);
 void launch_remove_invalid(const DevGraph& g, const int32_t* wl, int count, int bin,
-                           DevCounters* ctr, hipStream_t st);
+                           DevCounters* ctr, hipStream_t st, const int32_t* dcount = nullptr);
 void launch_clear_counters(DevCounters* ctr, hipStream_t st);
 void launch_reduce_bytes(const DevGraph& g, DevCounters* ctr, hipStream_t st);
 void launch_batch_locate(const DevGraph& g, const mf_update* upd, int64_t k, int32_t* slot_of,
@@ -278,8 +285,17 @@ void launch_frontier_bitmap(const int2* q, int cnt, const GrBits& bits, int leve
 int64_t relayout_tiles(int32_t V);
 // n scattered atomicAdds of `width` bytes (4 or 8) on n distinct addresses; ops/s, < 0 on failure
 double atomic_probe(int64_t n, int width, hipStream_t st);
+// A push-relabel round in two launches (the workgroup bin with kc_long
+// cycles, then the thread and wave bins with kc) and a remove-invalid-edges
+// round in one.  dcount null: the bins hold cnt[0..2] rows; else their
+// sizes are dcount[0..2] on the device and cnt[] upper bounds for the grid.
+void launch_pr_fused(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], int kc, int kc_long,
+                     bool pull, hipStream_t st, const int32_t* dcount = nullptr);
+void launch_rie_fused(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], DevCounters* ctr,
+                      hipStream_t st, const int32_t* dcount = nullptr);
 // next worklist of a push-relabel round without a relabel: the previous
-// worklist's bins (counts c0..c2) and the activation list, filtered to
+// worklist's bins (counts cnt[0..2], or with cnt null the worklist counts on
+// the device, set aside in wl_in first) and the activation list, filtered to
 // active vertices (e > 0, h < n), deduplicated with mark[v] == epoch, binned
 void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const int cnt[3], int32_t* out0,
                           int32_t* out1, int32_t* out2, int32_t* mark, int32_t epoch, DevCounters* ctr,
