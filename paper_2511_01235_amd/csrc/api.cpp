@@ -633,14 +633,14 @@ mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const
     const int32_t* dcount = dev ? m.L.ctr->wl : nullptr;
     const auto t0 = std::chrono::steady_clock::now();
     timed(g, m.L, mf::KC_PR, [&] {
-        mf::launch_pr_fused(m.dg, wl, cnt, kc_for_bin(g, 0), kc_for_bin(g, 2), m.pull, st, dcount);
+        mf::launch_push_relabel_round(m.dg, wl, cnt, kc_for_bin(g, 0), kc_for_bin(g, 2), m.pull, st, dcount);
     });
     if (g->trace_gr) {
         MF_HIP(hipStreamSynchronize(st));
         std::fprintf(stderr, "[loop]   push rows by bin %d %d %d us %.1f\n", cnt[0], cnt[1], cnt[2],
                      std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count());
     }
-    if (m.rie) timed(g, m.L, mf::KC_RIE, [&] { mf::launch_rie_fused(m.dg, wl, cnt, m.L.ctr, st, dcount); });
+    if (m.rie) timed(g, m.L, mf::KC_RIE, [&] { mf::launch_remove_invalid_round(m.dg, wl, cnt, m.L.ctr, st, dcount); });
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
@@ -836,9 +836,9 @@ mf_status warm_sweep(mf_graph* g) {
     // sized on the device: no read-back between the build and the sweep
     const int bounds[3] = {(int)g->n, (int)g->n, (int)g->n};
     timed(g, mf::KC_PR, [&] {
-        mf::launch_pr_fused(m.dg, g->wl, bounds, kc_for_bin(g, 0), kc_for_bin(g, 2), false, st, g->ctr->wl);
+        mf::launch_push_relabel_round(m.dg, g->wl, bounds, kc_for_bin(g, 0), kc_for_bin(g, 2), false, st, g->ctr->wl);
     });
-    timed(g, mf::KC_RIE, [&] { mf::launch_rie_fused(m.dg, g->wl, bounds, g->ctr, st, g->ctr->wl); });
+    timed(g, mf::KC_RIE, [&] { mf::launch_remove_invalid_round(m.dg, g->wl, bounds, g->ctr, st, g->ctr->wl); });
     MF_HIP(hipGetLastError());
     return MF_OK;
 }

@@ -1252,32 +1252,6 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
 }
 
 template <bool PULL>
-__global__ void __launch_bounds__(256) k_pr_thread(DevGraph g, const int32_t* wl, int count, int kc,
-                                                   DevCounters* ctr, const int32_t* dcount) {
-    (void)ctr;
-    const int cnt = dcount ? *dcount : count;
-    unsigned long long bytes = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x)
-        bytes += pr_thread_item<PULL>(g, wl[i], kc);
-    if (g.count_bytes) {
-        unsigned long long b = wave_sum_u64(bytes);
-        if (lane_id() == 0) add_bytes(g, KC_PR, b);
-    }
-}
-
-template <bool PULL>
-__global__ void __launch_bounds__(256) k_pr_wave(DevGraph g, const int32_t* wl, int count, int kc,
-                                                 DevCounters* ctr, const int32_t* dcount) {
-    (void)ctr;
-    const int cnt = dcount ? *dcount : count;
-    const int waves = (int)(gridDim.x * blockDim.x / WAVE);
-    unsigned long long bytes = 0;
-    for (int w = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE; w < cnt; w += waves)  // whole waves
-        bytes += pr_wave_item<PULL>(g, bcast(wl[w]), kc);
-    if (lane_id() == 0 && bytes) add_bytes(g, KC_PR, bytes);
-}
-
-template <bool PULL>
 __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t* wl, int count,
                                                        int kc, DevCounters* ctr, const int32_t* dcount) {
     (void)ctr;
@@ -1373,48 +1347,11 @@ __device__ __forceinline__ long long rie_item(DevGraph& g, int u, int sub, unsig
     return moved;
 }
 
-__global__ void __launch_bounds__(256) k_rie_thread(DevGraph g, const int32_t* wl, int count,
-                                                    DevCounters* ctr, const int32_t* dcount) {
-    (void)ctr;
-    const int cnt = dcount ? *dcount : count;
-    unsigned long long bytes = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
-        int u = wl[i];
-        long long moved = rie_item<1>(g, u, 0, &bytes);
-        if (moved) add_e(g.e, u, -moved);
-    }
-    if (g.count_bytes) {
-        unsigned long long b = wave_sum_u64(bytes);
-        if (lane_id() == 0) add_bytes(g, KC_RIE, b);
-    }
-}
-
-// GROUP = 64: one wave per vertex; GROUP = 256: one block per vertex.  One
-// atomic on e(u) per wave.
-template <int GROUP>
-__global__ void __launch_bounds__(256) k_rie_group(DevGraph g, const int32_t* wl, int count,
-                                                   DevCounters* ctr, const int32_t* dcount) {
-    (void)ctr;
-    const int cnt = dcount ? *dcount : count;
-    const int groups = (int)(gridDim.x * blockDim.x / GROUP);
-    const int sub = threadIdx.x % GROUP;
-    unsigned long long bytes = 0;
-    // whole groups (waves or blocks) take the same items
-    for (int item = (blockIdx.x * blockDim.x + threadIdx.x) / GROUP; item < cnt; item += groups) {
-        const int u = wl[item];
-        long long moved = wave_sum_i64(rie_item<GROUP>(g, u, sub, &bytes));
-        if (lane_id() == 0 && moved) add_e(g.e, u, -moved);
-    }
-    if (g.count_bytes) {
-        unsigned long long b = wave_sum_u64(bytes);
-        if (lane_id() == 0) add_bytes(g, KC_RIE, b);
-    }
-}
 
 // Remove-invalid-edges for a round's three bins in one launch (256-thread
 // workgroups taking virtual blocks as in k_pr_small, the workgroup bin's
 // rows first, one per block).
-__global__ void __launch_bounds__(256) k_rie_fused(DevGraph g, const int32_t* wl0, const int32_t* wl1,
+__global__ void __launch_bounds__(256) k_rie_round(DevGraph g, const int32_t* wl0, const int32_t* wl1,
                                                    const int32_t* wl2, int c0, int c1, int c2,
                                                    DevCounters* ctr, const int32_t* dcount) {
     (void)ctr;
@@ -2326,57 +2263,11 @@ void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_
                                                               sign, guard_level);
 }
 
-// Grids of the push-relabel and remove-invalid-edges launches.  With the
-// size known on the host (dcount null) one worker per item; with the size on
-// the device (dcount, a worklist counter) `count` is only an upper bound and
-// the grid is capped: the kernels loop over their items.
-constexpr int DEV_COUNT_BLOCKS = 2048;   // thread and wave bins
-constexpr int DEV_COUNT_ITEMS = 1024;    // workgroup bin: workgroups in flight
-
-template <bool PULL>
-static void launch_pr_bins(const DevGraph& g, const int32_t* wl, int count, int bin, int kc,
-                           DevCounters* ctr, hipStream_t st, const int32_t* dcount) {
-    const bool dev = dcount != nullptr;
-    if (bin == 0)
-        k_pr_thread<PULL><<<grid_for(count, 256, dev ? DEV_COUNT_BLOCKS : 1 << 30), 256, 0, st>>>(
-            g, wl, count, kc, ctr, dcount);
-    else if (bin == 1)
-        k_pr_wave<PULL><<<grid_for((int64_t)count * WAVE, 256, dev ? DEV_COUNT_BLOCKS : 1 << 30), 256, 0, st>>>(
-            g, wl, count, kc, ctr, dcount);
-    else
-        k_pr_block<PULL><<<dev ? std::min(count, DEV_COUNT_ITEMS) : count, BLOCK_PR, 0, st>>>(g, wl, count, kc,
-                                                                                          ctr, dcount);
-}
-
-void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc, bool pull,
-                         DevCounters* ctr, hipStream_t st, const int32_t* dcount) {
-    if (count <= 0) return;
-    if (pull)
-        launch_pr_bins<true>(g, wl, count, bin, kc, ctr, st, dcount);
-    else
-        launch_pr_bins<false>(g, wl, count, bin, kc, ctr, st, dcount);
-}
-
-void launch_remove_invalid(const DevGraph& g, const int32_t* wl, int count, int bin,
-                           DevCounters* ctr, hipStream_t st, const int32_t* dcount) {
-    if (count <= 0) return;
-    const bool dev = dcount != nullptr;
-    if (bin == 0)
-        k_rie_thread<<<grid_for(count, 256, dev ? DEV_COUNT_BLOCKS : 1 << 30), 256, 0, st>>>(g, wl, count, ctr,
-                                                                                          dcount);
-    else if (bin == 1)
-        k_rie_group<64><<<grid_for((int64_t)count * 64, 256, dev ? DEV_COUNT_BLOCKS : 1 << 30), 256, 0, st>>>(
-            g, wl, count, ctr, dcount);
-    else
-        k_rie_group<256><<<dev ? std::min(count, DEV_COUNT_ITEMS) : count, 256, 0, st>>>(g, wl, count, ctr,
-                                                                                      dcount);
-}
-
 constexpr int PR_SMALL_GRID = 4096;   // 256-thread workgroups: 16 per CU
 constexpr int PR_BLOCK_GRID = 1024;   // 1024-thread workgroups
-constexpr int RIE_FUSED_GRID = 2048;  // 256-thread workgroups
+constexpr int RIE_ROUND_GRID = 2048;  // 256-thread workgroups
 
-void launch_pr_fused(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], int kc, int kc_long,
+void launch_push_relabel_round(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], int kc, int kc_long,
                      bool pull, hipStream_t st, const int32_t* dcount) {
     // the workgroup bin first: its rows are the longest
     if (cnt[2] > 0) {
@@ -2393,12 +2284,12 @@ void launch_pr_fused(const DevGraph& g, const int32_t* const wl[3], const int cn
     else k_pr_small<false><<<grid, PR_SMALL_BLOCK, 0, st>>>(g, wl[0], wl[1], cnt[0], cnt[1], kc, dcount);
 }
 
-void launch_rie_fused(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], DevCounters* ctr,
+void launch_remove_invalid_round(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], DevCounters* ctr,
                       hipStream_t st, const int32_t* dcount) {
     const int64_t total = (int64_t)cnt[2] + (cnt[1] + 3) / 4 + (cnt[0] + 255) / 256;
     if (total <= 0) return;
-    const int grid = (int)std::min<int64_t>(total, dcount ? RIE_FUSED_GRID : 1 << 30);
-    k_rie_fused<<<grid, 256, 0, st>>>(g, wl[0], wl[1], wl[2], cnt[0], cnt[1], cnt[2], ctr, dcount);
+    const int grid = (int)std::min<int64_t>(total, dcount ? RIE_ROUND_GRID : 1 << 30);
+    k_rie_round<<<grid, 256, 0, st>>>(g, wl[0], wl[1], wl[2], cnt[0], cnt[1], cnt[2], ctr, dcount);
 }
 
 void launch_clear_counters(DevCounters* ctr, hipStream_t st) {

@@ -242,12 +242,6 @@ hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounte
 // does nothing unless the BFS ended there
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,
                            DevCounters* ctr, bool topology, int sign, hipStream_t st, int guard_level = -1);
-// dcount null: `count` items; else the item count is *dcount on the device
-// (read when the kernel runs) and `count` an upper bound for the grid
-void launch_push_relabel(const DevGraph& g, const int32_t* wl, int count, int bin, int kc, bool pull,
-                         DevCounters* ctr, hipStream_t st, const int32_t* dcount = nullptr);
-void launch_remove_invalid(const DevGraph& g, const int32_t* wl, int count, int bin,
-                           DevCounters* ctr, hipStream_t st, const int32_t* dcount = nullptr);
 void launch_clear_counters(DevCounters* ctr, hipStream_t st);
 void launch_reduce_bytes(const DevGraph& g, DevCounters* ctr, hipStream_t st);
 void launch_batch_locate(const DevGraph& g, const mf_update* upd, int64_t k, int32_t* slot_of,
@@ -289,9 +283,9 @@ double atomic_probe(int64_t n, int width, hipStream_t st);
 // cycles, then the thread and wave bins with kc) and a remove-invalid-edges
 // round in one.  dcount null: the bins hold cnt[0..2] rows; else their
 // sizes are dcount[0..2] on the device and cnt[] upper bounds for the grid.
-void launch_pr_fused(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], int kc, int kc_long,
+void launch_push_relabel_round(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], int kc, int kc_long,
                      bool pull, hipStream_t st, const int32_t* dcount = nullptr);
-void launch_rie_fused(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], DevCounters* ctr,
+void launch_remove_invalid_round(const DevGraph& g, const int32_t* const wl[3], const int cnt[3], DevCounters* ctr,
                       hipStream_t st, const int32_t* dcount = nullptr);
 // next worklist of a push-relabel round without a relabel: the previous
 // worklist's bins (counts cnt[0..2], or with cnt null the worklist counts on
