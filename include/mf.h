@@ -96,8 +96,8 @@ typedef struct mf_options {
     int32_t long_row_cycles;   /* tuning: push/relabel cycles per launch for the rows a workgroup
                                   takes (longer than bin_wave_max slots), at most kernel_cycles;
                                   <= 0: 1.  Their excess left over waits for the next round, so a
-                                  hub's repeated full-row passes do not hold up the launch.
-                                  Single-graph handles (mf_batch_* use kernel_cycles). */
+                                  hub's repeated full-row passes do not hold up the launch
+                                  (in mf_batch_*, the graph's other rows). */
 } mf_options;
 
 /* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its

@@ -34,6 +34,7 @@ struct mf_batch {
     mf_options opt{};
     mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0, 0};
     std::vector<int32_t> n, kc;
+    int32_t long_cycles = 1;      // push/relabel cycles of the rows a graph's workgroup takes whole
     std::vector<int64_t> vbase, rpbase, sbase, slots, bbase, qbase, used;
     std::vector<int32_t> s_h, t_h;
     int32_t slack_min = 2, slack_pct = 12;
@@ -147,6 +148,7 @@ void apply_tuning(mf_batch* b, const mf::Tuning& t) {
     b->bin1 = t.bin1;
     b->block = t.batch_block;
     b->kc_option = t.kc_option;
+    b->long_cycles = t.long_cycles;
     for (int i = 0; i < b->G; ++i) {
         int64_t kc = t.kc_option > 0 ? t.kc_option : (b->m_unique[i] + b->n[i] / 2) / b->n[i];
         b->kc[i] = (int32_t)std::max<int64_t>(1, kc);
@@ -261,6 +263,7 @@ mf_status upload_views(mf_batch* b) {
         S.bits.fb = S.bits.visited + S.bits.nwords;
         S.ctr = b->ctr + i;
         S.kc = b->kc[i];
+        S.kc_long = std::min(b->kc[i], b->long_cycles);
         S.warm = b->opt.cold_start ? 0 : 1;
         S.round_div = b->round_div;
         S.max_iter = b->opt.max_iterations > 0 ? b->opt.max_iterations : 4 * (int64_t)ni + 1000;

@@ -317,6 +317,31 @@ __device__ __forceinline__ void append_entries(int add, int slots, int v, int2* 
     for (int k = 0; k < add; ++k) q[b + off + k] = make_int2(v, k * GR_CHUNK);
 }
 
+// Thread t queues the entries of up to U vertices with one atomic per wave:
+// for BFS levels that one workgroup runs alone (no other CU contends for the
+// counter, and block_append's barriers would only cost).
+template <int U>
+__device__ __forceinline__ void wave_append(const int (&vs)[U], const int (&adds)[U], const int (&lens)[U],
+                                            int2* q, unsigned long long* counter) {
+    int add = 0;
+    unsigned long long sl = 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        add += adds[k];
+        sl += adds[k] > 0 ? (unsigned long long)lens[k] : 0ull;
+    }
+    int tot;
+    const int off = wave_excl_scan(add, &tot);
+    const unsigned long long wsl = wave_sum_u64(sl);
+    if (tot == 0) return;  // wave-uniform
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, (wsl << 32) | (unsigned)tot);
+    int p = __shfl((int)(unsigned)(base & 0xFFFFFFFFull), 0, WAVE) + off;
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+        for (int a = 0; a < adds[k]; ++a) q[p++] = make_int2(vs[k], a * GR_CHUNK);
+}
+
 // The same for a whole block with one atomic: thread t queues the entries of
 // up to U vertices (vs[k] with adds[k] entries and lens[k] slots).  Every
 // level-counter atomic goes to the same address from all CUs and XCDs, so
@@ -451,7 +476,9 @@ __device__ __forceinline__ int discover(const DevGraph& g, const GrBits& bits, i
 // bu selects bottom-up.  s_bm, when not null, is this block's LDS copy of the
 // bitmap the direction needs (visited for top-down, the current frontier for
 // bottom-up), replacing the height gather of every scanned slot by a bit test.
-template <bool FWD, int BS>
+// AGG: one frontier-counter atomic per block round (launches of many
+// workgroups); else one per wave (a workgroup that runs the level alone).
+template <bool FWD, int BS, bool AGG = true>
 __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, int lv, int cnt,
                                               const int2* qin,
                                               int2* qout, DevCounters* ctr, const GrBits& bits,
@@ -546,7 +573,8 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
             }
             {
                 const int vs[1] = {v}, adds[1] = {add}, lens[1] = {slots};
-                block_append<BS, 1>(vs, adds, lens, qout, out_cnt, s_agg);
+                if (AGG) block_append<BS, 1>(vs, adds, lens, qout, out_cnt, s_agg);
+                else wave_append<1>(vs, adds, lens, qout, out_cnt);
             }
             __syncthreads();  // s_hit / s_pre are restaged next round
         }
@@ -617,7 +645,8 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
             }
             {   // block_append's barriers also publish s_defer / s_ndefer
                 const int vs[1] = {v}, adds[1] = {add}, lens[1] = {slots};
-                block_append<BS, 1>(vs, adds, lens, qout, out_cnt, s_agg);
+                if (AGG) block_append<BS, 1>(vs, adds, lens, qout, out_cnt, s_agg);
+                else wave_append<1>(vs, adds, lens, qout, out_cnt);
             }
             const int nd = s_ndefer;
             for (int d = tid / WAVE; d < nd; d += BS / WAVE) {
@@ -655,7 +684,8 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
                     lens[0] = g.row_len[vs[0]];
                     adds[0] = (lens[0] + GR_CHUNK - 1) / GR_CHUNK;
                 }
-                block_append<BS, 1>(vs, adds, lens, qout, out_cnt, s_agg);
+                if (AGG) block_append<BS, 1>(vs, adds, lens, qout, out_cnt, s_agg);
+                else wave_append<1>(vs, adds, lens, qout, out_cnt);
             }
             __syncthreads();  // s_defer / s_dhit and their counts are reused next round
         }
@@ -706,7 +736,8 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
                         found++;
                     }
                 }
-                block_append<BS, GR_TD_U>(vs, adds, lens, qout, out_cnt, s_agg);
+                if (AGG) block_append<BS, GR_TD_U>(vs, adds, lens, qout, out_cnt, s_agg);
+                else wave_append<GR_TD_U>(vs, adds, lens, qout, out_cnt);
             }
             __syncthreads();  // LDS is restaged next round
         }
@@ -741,7 +772,7 @@ __device__ __forceinline__ bool choose_bottom_up(const Par& P, const DevGraph& g
 // ring slots of level lv+2, choose the direction, optionally stage the
 // bitmap into LDS (s_dyn, when stage_ok), and do the level.  Returns the
 // frontier size (0: the BFS is over and nothing was done).
-template <bool FWD, int BS>
+template <bool FWD, int BS, bool AGG = true>
 __device__ __forceinline__ int gr_level_step(const Par& P, const DevGraph& g, int lv, const int2* qin,
                                              int2* qout, DevCounters* ctr, const GrBits& bits,
                                              const GrTune& tune, unsigned* s_dyn) {
@@ -763,7 +794,7 @@ __device__ __forceinline__ int gr_level_step(const Par& P, const DevGraph& g, in
         for (int i = threadIdx.x; i < bits.nwords; i += blockDim.x) s_dyn[i] = src[i];
         __syncthreads();
     }
-    gr_level_body<FWD, BS>(P, g, lv, cnt, qin, qout, ctr, bits, bu, tune.bu_lb != 0, tune.bu_wide != 0,
+    gr_level_body<FWD, BS, AGG>(P, g, lv, cnt, qin, qout, ctr, bits, bu, tune.bu_lb != 0, tune.bu_wide != 0,
                            stage ? s_dyn : nullptr);
     return cnt;
 }
@@ -815,7 +846,8 @@ __global__ void __launch_bounds__(NARROW_BLOCK) k_gr_narrow(DevGraph g, int lv0,
             ctr->unv[lv % 3] = ctr->unv[(lv + 2) % 3] - fs;
         }
         __syncthreads();
-        gr_level_body<FWD, NARROW_BLOCK>(P, g, lv, cnt, qin, qout, ctr, bits, false, false, false, nullptr, KC_GRS);
+        gr_level_body<FWD, NARROW_BLOCK, false>(P, g, lv, cnt, qin, qout, ctr, bits, false, false, false, nullptr,
+                                                KC_GRS);
         __syncthreads();
         if (threadIdx.x == 0)
             s_front = __hip_atomic_load(&ctr->front[(lv + 1) % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1670,7 +1702,7 @@ __device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
             gr_init_body(P, g, S.q0, ctr, S.bits, 1);
             __syncthreads();
             for (int lv = 0; lv <= N; ++lv) {
-                int cnt = gr_level_step<false, BS>(P, g, lv, (lv & 1) ? S.q1 : S.q0, (lv & 1) ? S.q0 : S.q1,
+                int cnt = gr_level_step<false, BS, false>(P, g, lv, (lv & 1) ? S.q1 : S.q0, (lv & 1) ? S.q0 : S.q1,
                                                    ctr, S.bits, tune, nullptr);
                 __syncthreads();
                 if (cnt == 0) break;
@@ -1708,7 +1740,7 @@ __device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
         // push-relabel (Algorithm 2) over the three degree bins
         for (int i = tid; i < c0; i += BS) pr_thread_item<false>(g, S.wl0[i], S.kc);
         for (int i = tid / WAVE; i < c1; i += BS / WAVE) pr_wave_item<false>(g, bcast(S.wl1[i]), S.kc);
-        for (int i = 0; i < c2; ++i) pr_block_item<false, BS>(g, S.wl2[i], S.kc);
+        for (int i = 0; i < c2; ++i) pr_block_item<false, BS>(g, S.wl2[i], S.kc_long);
         __syncthreads();
         // remove invalid edges (Algorithm 3)
         unsigned long long nb = 0;

@@ -125,6 +125,7 @@ struct GraphSlot {
     GrBits bits;
     DevCounters* ctr;
     int32_t kc;
+    int32_t kc_long;           // cycles for rows the workgroup takes whole (at most kc)
     int32_t warm;              // repairs: one sweep on the previous heights first
     int32_t round_div;         // push-relabel rounds per relabel: BFS depth / round_div, at least 1
     int64_t max_iter;

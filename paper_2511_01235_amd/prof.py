@@ -2,11 +2,11 @@
 FETCH_SIZE / WRITE_SIZE counter passes), as markdown.
 
 bench.py runs, in this order: the static solves (each starts with k_reset), the
-atomic probes, one plain 256 MiB device copy that calibrates the counters, the
-warm-up and timed update batches, then the from-scratch solves (k_reset
-again).  The timed
-window is therefore the dispatches after the largest copy and before the
-next k_reset; run the profiled bench with --warmup 0 so that the window holds
+atomic probes, a plain 256 MiB device copy done twice (the second one
+calibrates the counters), the warm-up and timed update batches, then the
+from-scratch solves (k_reset again).  The timed
+window is therefore the dispatches after the calibration copy and before
+the next k_reset; run the profiled bench with --warmup 0 so that the window holds
 exactly the timed batches.
 
     python -m paper_2511_01235_amd.prof KT_DIR FETCH_DIR WRITE_DIR --kernel k_gr_level \\
@@ -56,12 +56,20 @@ def _name(r):
     return r.get("Kernel_Name") or r.get("Name")
 
 
-def timed_window(rows):
-    """Indices [a, b) of the timed window (see the module docstring)."""
+def calibration_copy(rows):
+    """Index of the calibration copy: bench.py copies the 256 MiB twice (the
+    first touches fresh pages); the last copy at least half as long as the
+    longest is the timed one."""
     copies = [i for i, r in enumerate(rows) if "copyBuffer" in _name(r)]
     if not copies:
         raise ValueError("no calibration copy in the trace")
-    a = max(copies, key=lambda i: _dur_us(rows[i]))
+    longest = max(_dur_us(rows[i]) for i in copies)
+    return max(i for i in copies if _dur_us(rows[i]) >= 0.5 * longest)
+
+
+def timed_window(rows):
+    """Indices [a, b) of the timed window (see the module docstring)."""
+    a = calibration_copy(rows)
     later = [i for i, r in enumerate(rows) if i > a and "k_reset" in _name(r)]
     return a + 1, (later[0] if later else len(rows))
 
@@ -112,7 +120,7 @@ def counter_pass(path, kernel):
     rows = _rows(path)
     name = rows[0]["Counter_Name"]
     a, b = timed_window(rows)
-    cal = max((r for r in rows if "copyBuffer" in _name(r)), key=_dur_us)
+    cal = rows[calibration_copy(rows)]
     factor = (CAL_BYTES / 1024) / float(cal["Counter_Value"])
     vals = [float(r["Counter_Value"]) for r in rows[a:b] if kernel in _name(r)]
     return name, factor, float(np.mean(vals)) if vals else 0.0, len(vals)

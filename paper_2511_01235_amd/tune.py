@@ -34,8 +34,7 @@ GRAPH_SPACE = {
     "bin_wave_max": [256, 512, 1024],
     "long_row_cycles": [1, 2, 4],
 }
-# batched solves take long rows with kernel_cycles (one workgroup per graph)
-BATCH_SPACE = dict({k: v for k, v in GRAPH_SPACE.items() if k != "long_row_cycles"}, batch_block=[256, 512, 1024])
+BATCH_SPACE = dict(GRAPH_SPACE, batch_block=[256, 512, 1024])
 DEFAULTS = {"kc_scale": 1.0, "bfs_alpha": 14, "round_div": 8, "bin_thread_max": 16, "bin_wave_max": 512,
             "long_row_cycles": 1,
             "batch_block": 512}
