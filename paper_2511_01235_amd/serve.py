@@ -46,6 +46,7 @@ class Request:
     value: int | None = None
     slot: int = -1
     loaded: bool = False           # the graph was (re-)admitted for this request
+    seq: int = 0                   # position in the trace (breaks ties between equal arrivals)
 
 
 @dataclass
@@ -78,7 +79,7 @@ class Server:
     `options`."""
 
     def __init__(self, graphs, hbm_budget: int, slots: int = 4, factory=None, evict: str = "offload",
-                 max_wait: float = 0.25, **options):
+                 max_wait: float = 0.25, policy: str = "residency", **options):
         if factory is None:
             from . import MaxFlowGraph
 
@@ -86,6 +87,9 @@ class Server:
                 return MaxFlowGraph(n, src, dst, cap, s, t, **options)
         if evict not in ("offload", "rebuild"):
             raise ValueError("evict must be 'offload' or 'rebuild'")
+        if policy not in ("residency", "fifo"):
+            raise ValueError("policy must be 'residency' or 'fifo'")
+        self.policy = policy
         self.factory = factory
         self.evict = evict
         self.max_wait = float(max_wait)
@@ -185,6 +189,11 @@ class Server:
             if x.busy or not x.pending or x.pending[0].arrival > now:
                 continue
             r = x.pending[0]
+            if self.policy == "fifo":  # the earliest request of any idle graph that can run
+                if (x.resident or self._admissible(gi)) and \
+                        (best_res is None or (r.arrival, r.seq) < (best_res.arrival, best_res.seq)):
+                    best_res = r
+                continue
             if x.resident:
                 if best_res is None or r.arrival < best_res.arrival:
                     best_res = r
@@ -264,7 +273,9 @@ class Server:
         tuples; arrivals in seconds after the call) and return throughput and
         latency figures.  Each Request gets value, start, done, slot."""
         reqs = [r if isinstance(r, Request) else Request(*r) for r in requests]
-        for r in sorted(reqs, key=lambda q: q.arrival):
+        for i, r in enumerate(reqs):
+            r.seq = i
+        for r in sorted(reqs, key=lambda q: (q.arrival, q.seq)):
             self.g[r.graph].pending.append(r)
         self.remaining = len(reqs)
         t0 = time.perf_counter()

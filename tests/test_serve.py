@@ -162,6 +162,24 @@ def test_residency_first_with_aging(max_wait):
         _check_order(srv)
 
 
+def test_fifo_policy_serves_in_arrival_order():
+    """policy="fifo": with room for one graph and one slot, requests that
+    alternate between two graphs run in arrival order (each one evicting the
+    other graph), where residency-first would group them by graph."""
+    graphs = _fleet(2, 7960)
+    streams = [gen.BatchStream(g, 7970 + i, inc_max=30, new_cap_max=50) for i, g in enumerate(graphs)]
+    sizes = [estimate_device_bytes(g.n, g.m) for g in graphs]
+    trace = [(i % 2, 0.0, *streams[i % 2].next_batch(5)) for i in range(6)]
+    want = _expected(graphs, trace)
+    with Server(graphs, max(sizes) + min(sizes) // 2, slots=1, factory=OracleHandle, policy="fifo") as srv:
+        srv.run(trace)
+        assert [r.value for r in srv.requests] == want
+        order = sorted(range(len(srv.requests)), key=lambda i: srv.requests[i].start)
+        assert order == list(range(6))
+    with pytest.raises(ValueError):
+        Server(graphs, 1 << 40, factory=OracleHandle, policy="lifo")
+
+
 def test_serving_honours_arrival_times():
     graphs = _fleet(2, 7300)
     trace = _trace(graphs, 7400, count=6, rate=50.0, k_hi=10)
