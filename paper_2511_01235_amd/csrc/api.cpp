@@ -77,6 +77,9 @@ struct mf_graph {
     bool narrow_seed = true;  // start relabels in one workgroup (the last one's seeds were few enough)
     int32_t last_depth = 0;   // BFS levels of the last global relabel
     bool queue_rounds = true; // MF_QUEUE_ROUNDS=0: no worklist build and rounds queued behind the relabel
+    bool pipeline = true;     // MF_PIPELINE=0: no relabel iteration queued ahead of the host's read
+    DevCounters* snap_h[2] = {nullptr, nullptr};  // pinned: counters of the iterations in flight
+    hipEvent_t snap_ev[2] = {nullptr, nullptr};
     int32_t kc_block = 1;     // push/relabel cycles of the workgroup bin (capped at kc)
     int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
     int32_t round_max = 4096; // ... at most this many
@@ -285,6 +288,24 @@ void free_all(mf_graph* g) {
     for (auto e : g->ev_pool) (void)hipEventDestroy(e);
     g->ev_pending.clear();
     g->ev_pool.clear();
+    for (int k = 0; k < 2; ++k) {
+        if (g->snap_ev[k]) (void)hipEventSynchronize(g->snap_ev[k]);
+        if (g->snap_ev[k]) (void)hipEventDestroy(g->snap_ev[k]);
+        if (g->snap_h[k]) (void)hipHostFree(g->snap_h[k]);
+        g->snap_ev[k] = nullptr;
+        g->snap_h[k] = nullptr;
+    }
+}
+
+// Pinned counter snapshots and their events for pipelined iterations.
+mf_status ensure_snapshots(mf_graph* g) {
+    for (int k = 0; k < 2; ++k) {
+        if (!g->snap_h[k] && hipHostMalloc((void**)&g->snap_h[k], sizeof(DevCounters), hipHostMallocDefault) != hipSuccess)
+            return MF_ERR_OUT_OF_MEMORY;
+        if (!g->snap_ev[k] && hipEventCreateWithFlags(&g->snap_ev[k], hipEventDisableTiming) != hipSuccess)
+            return MF_ERR_DEVICE;
+    }
+    return MF_OK;
 }
 
 // Allocate and upload the slot arrays of a Bi-CSR (plus the arrays whose size
@@ -708,7 +729,67 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         if (rc == MF_OK) rc = push_round(g, qm, g->wlb, bounds, true);
         if (tail_rc == MF_OK) tail_rc = rc;
     };
-    for (;;) {
+    // Shallow relabels (depth under 16: at most two rounds each), no thin-
+    // frontier start, no event timing: the next iteration -- relabel init,
+    // its first chunk of levels, the queued tail and a copy of the counters
+    // to a pinned snapshot -- is queued before the host waits for the
+    // previous one's snapshot, so the device never idles on that read.  When
+    // the previous iteration turns out to be the last (empty worklist), the
+    // one queued behind it relabels the same residual graph to the same
+    // heights and finds the same empty worklist: it changes nothing.  A BFS
+    // that outlasts its chunk (or grows deep) sends the loop back to the
+    // ordinary iterations below, which start with a fresh relabel.
+    bool finished = false;
+    if (queue && g->pipeline && !g->prof_mask && !g->narrow_seed && g->last_depth > 0 && g->last_depth < 16) {
+        mf_status rc = ensure_snapshots(g);
+        if (rc != MF_OK) return rc;
+        auto queue_iteration = [&](int slot) -> int {
+            timed(g, m.L, mf::KC_GRS,
+                  [&] { mf::launch_gr_init(m.dg, m.L.q[0], m.L.ctr, m.L.bits, m.seed_deficits, st); });
+            const int C = std::min(64, std::max(g->first_chunk, g->last_depth + 1));
+            for (int lv = 0; lv < C; ++lv)
+                timed(g, m.L, mf::KC_GR, [&] {
+                    mf::launch_gr_level(m.dg, lv, m.L.q[lv & 1], m.L.q[(lv + 1) & 1], m.L.ctr, m.L.bits, g->tune,
+                                        g->gr_grid, m.forward, st);
+                });
+            tail(C);
+            (void)hipMemcpyAsync(g->snap_h[slot], m.L.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, st);
+            (void)hipEventRecord(g->snap_ev[slot], st);
+            return C;
+        };
+        int chunk[2];
+        int k = 0;
+        chunk[0] = queue_iteration(0);
+        for (;;) {
+            chunk[1 - k] = queue_iteration(1 - k);
+            MF_HIP(hipGetLastError());
+            if (tail_rc != MF_OK) return tail_rc;
+            MF_HIP(hipEventSynchronize(g->snap_ev[k]));
+            const DevCounters& c = *g->snap_h[k];
+            levels += chunk[k];
+            // the BFS outlasted the chunk: the tail did nothing
+            if ((c.front[chunk[k] % 3] & 0xFFFFFFFFull) != 0) break;
+            g->last_depth = c.levels;
+            const int active = c.wl_in[3];  // the relabel's worklist (set aside before round 2's)
+            active_sum += active;
+            if (active == 0) {
+                *value = (int64_t)c.e_t + (int64_t)c.deficit_sum;
+                *m.L.ctr_h = c;
+                finished = true;
+                break;
+            }
+            if (++iters > g->max_iter) {
+                g->last_iterations = iters;
+                return MF_ERR_NOT_CONVERGED;
+            }
+            rounds += 2;
+            if (g->last_depth >= 16) break;  // deep now: the ordinary loop runs more rounds per relabel
+            k = 1 - k;
+        }
+        // leaving early: the iteration still queued runs to its end first
+        if (!finished) MF_HIP(hipStreamSynchronize(st));
+    }
+    while (!finished) {
         bool queued = false;
         int depth = 0;
         mf_status rc = relabel_and_worklist(g, m, &levels, &depth, queue ? &tail : nullptr, &queued);
@@ -1158,6 +1239,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     if (const char* env = std::getenv("MF_GR_FIRST_CHUNK")) g->first_chunk = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_GR_TRACE")) g->trace_gr = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_QUEUE_ROUNDS")) g->queue_rounds = std::atoi(env) != 0;
+    if (const char* env = std::getenv("MF_PIPELINE")) g->pipeline = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_ROUND_SCAN")) g->incremental_rounds = std::atoi(env) == 0;
     if (const char* env = std::getenv("MF_GR_NARROW")) g->narrow_max = std::max(0LL, std::atoll(env));
     if (const char* env = std::getenv("MF_ROUND_MAX")) g->round_max = std::max(1, std::atoi(env));

@@ -167,6 +167,31 @@ def test_long_row_cycles_same_values(name, cycles):
             assert G.apply_batch(u, v, c) == o.apply(u, v, c)
 
 
+@pytest.mark.parametrize("mode", ["ordinary", "queued", "pipelined"])
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+def test_queued_rounds_same_values(name, mode, monkeypatch):
+    """The worklist build and first two rounds queued behind the relabel's
+    first chunk of levels (device-sized, guarded on the BFS having ended;
+    grid64's BFS outlasts the first chunk, so its queued launches must do
+    nothing), also with the next iteration queued before the host reads the
+    last one's counters (shallow graphs), or everything launched after the
+    host read the counters: static value and repairs equal the oracle's in
+    every mode, cut certified."""
+    monkeypatch.setenv("MF_QUEUE_ROUNDS", "0" if mode == "ordinary" else "1")
+    monkeypatch.setenv("MF_PIPELINE", "1" if mode == "pipelined" else "0")
+    g, stream, k, _ = gen.workload(name)
+    say("queued rounds", name, mode)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        assert G.maxflow() == o.static()
+        for _ in range(4):
+            u, v, c = stream.next_batch(k)
+            want = o.apply(u, v, c)
+            assert G.apply_batch(u, v, c) == want
+            side, cut = G.min_cut()
+            assert cut == want
+
+
 # --- static value ---------------------------------------------------------------
 
 def test_golden_static_gpu():
