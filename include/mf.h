@@ -131,7 +131,8 @@ typedef struct mf_stats {
     /* algorithmic bytes the kernels of each class had to move over the same calls,
      * from device-side counters (Bi-CSR slots and vertex words actually visited) */
     double kernel_bytes[8];
-    int64_t last_rounds;       /* push-relabel rounds of the last call (one or more per global relabel) */
+    int64_t last_rounds;       /* push-relabel rounds of the last call (two or more per global relabel
+                                  that leaves active vertices, unless a round empties the worklist) */
 } mf_stats;
 
 /* Fill *opt with the defaults. */
@@ -162,6 +163,10 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
  * only when a freshly computed global relabel leaves no active vertex, and
  * *value = e(t) plus the (non-positive) excess of every deficient vertex.
  * Leaves the residual graph, excesses and heights on the device for repairs.
+ * The value is final on return; the handle's stream may still be running one
+ * more global relabel and worklist build that change nothing (the next
+ * iteration, queued before the last one's counters were read).  Every later
+ * call on the handle is ordered after it on that stream.
  * Errors: MF_ERR_INVALID (NULL), MF_ERR_NOT_CONVERGED, MF_ERR_DEVICE. */
 mf_status mf_maxflow(mf_graph* g, int64_t* value);
 
@@ -171,6 +176,7 @@ mf_status mf_maxflow(mf_graph* g, int64_t* value);
  * (changing the two endpoints' excesses), saturate the source again, then
  * run the loop with t and every deficient vertex as sinks (Algorithm 6) and
  * *value = sum of the excesses at height 0.  Requires a prior mf_maxflow.
+ * On return, as for mf_maxflow.
  * Errors: MF_ERR_INVALID (any update out of range, u == v, cap < 0; nothing
  * is applied), MF_ERR_OVERFLOW (an updated pair's c(u,v)+c(v,u) above
  * INT32_MAX; nothing is applied), MF_ERR_STATE, MF_ERR_NOT_CONVERGED,
