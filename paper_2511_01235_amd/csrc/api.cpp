@@ -743,6 +743,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     if (queue && g->pipeline && !g->prof_mask && !g->narrow_seed && g->last_depth > 0 && g->last_depth < 16) {
         mf_status rc = ensure_snapshots(g);
         if (rc != MF_OK) return rc;
+        hipError_t queue_err = hipSuccess;
         auto queue_iteration = [&](int slot) -> int {
             timed(g, m.L, mf::KC_GRS,
                   [&] { mf::launch_gr_init(m.dg, m.L.q[0], m.L.ctr, m.L.bits, m.seed_deficits, st); });
@@ -753,8 +754,9 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
                                         g->gr_grid, m.forward, st);
                 });
             tail(C);
-            (void)hipMemcpyAsync(g->snap_h[slot], m.L.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, st);
-            (void)hipEventRecord(g->snap_ev[slot], st);
+            hipError_t e = hipMemcpyAsync(g->snap_h[slot], m.L.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipEventRecord(g->snap_ev[slot], st);
+            if (queue_err == hipSuccess) queue_err = e;
             return C;
         };
         int chunk[2];
@@ -763,6 +765,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         for (;;) {
             chunk[1 - k] = queue_iteration(1 - k);
             MF_HIP(hipGetLastError());
+            MF_HIP(queue_err);
             if (tail_rc != MF_OK) return tail_rc;
             MF_HIP(hipEventSynchronize(g->snap_ev[k]));
             const DevCounters& c = *g->snap_h[k];
