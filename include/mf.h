@@ -79,7 +79,7 @@ typedef struct mf_options {
     int32_t bin_thread_max;    /* active rows up to this many slots get one thread ...; <= 0: 16 */
     int32_t bin_wave_max;      /* ... up to this many one 64-lane wave, longer ones a workgroup;
                                   <= 0: 512 */
-    int32_t batch_block;       /* mf_batch_*: threads per graph, 256, 512 or 1024; 0: 512 */
+    int32_t batch_block;       /* mf_batch_*: threads per graph, 256, 512 or 1024; 0: 1024 */
     int32_t push_pull;         /* 1: Section 5.2's O2 -- mf_maxflow also saturates the sink's
                                   in-edges first (static push-pull); a repair saturates the previous
                                   min cut again and runs push-relabel on its sink side and pull-

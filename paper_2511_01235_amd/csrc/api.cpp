@@ -138,7 +138,7 @@ mf_status resolve_tuning(const mf_options& o, Tuning* t) {
     r.bin0 = o.bin_thread_max > 0 ? o.bin_thread_max : BIN0_MAX;
     r.bin1 = o.bin_wave_max > 0 ? o.bin_wave_max : BIN1_MAX;
     if (r.bin1 < r.bin0) return MF_ERR_INVALID;
-    r.batch_block = o.batch_block == 0 ? 512 : o.batch_block;
+    r.batch_block = o.batch_block == 0 ? 1024 : o.batch_block;
     if (r.batch_block != 256 && r.batch_block != 512 && r.batch_block != 1024) return MF_ERR_INVALID;
     *t = r;
     return MF_OK;

@@ -37,7 +37,7 @@ GRAPH_SPACE = {
 BATCH_SPACE = dict(GRAPH_SPACE, batch_block=[256, 512, 1024])
 DEFAULTS = {"kc_scale": 1.0, "bfs_alpha": 14, "round_div": 8, "bin_thread_max": 16, "bin_wave_max": 512,
             "long_row_cycles": 1,
-            "batch_block": 512}
+            "batch_block": 1024}
 
 
 def _configs(space, sample, seed):
