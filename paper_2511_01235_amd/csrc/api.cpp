@@ -705,12 +705,18 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         qm.dg.act = g->act_list;
         qm.dg.act_cnt = &m.L.ctr->act;
         qm.dg.act_cap = g->n;
+        // rounds right after a fresh relabel (whose heights are exact BFS
+        // distances, a valid labelling): an out-slot can only turn steep at
+        // a vertex whose height push-relabel raised, so remove-invalid-edges
+        // visits just those rows.  The marks live in the first frontier
+        // bitmap, free until the next relabel rewrites it.
+        qm.dg.relab = m.L.bits.fb;
     }
     const int bounds[3] = {(int)g->n, (int)g->n, (int)g->n};
     mf_status tail_rc = MF_OK;
     const std::function<void(int)> tail = [&](int level_end) {
         timed(g, m.L, mf::KC_WL, [&] {
-            mf::launch_build_worklist(m.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology, m.sign, st,
+            mf::launch_build_worklist(qm.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology, m.sign, st,
                                       level_end);
         });
         // the build cleared the activation count; the next-worklist build

@@ -251,6 +251,7 @@ mf_status upload_views(mf_batch* b) {
         g.side_keep = 0;
         g.act = nullptr;
         g.act_cnt = nullptr;
+        g.relab = nullptr;
         g.act_cap = 0;
         int64_t qc = (int64_t)ni + b->slots[i] / mf::GR_CHUNK + 64;
         S.q0 = b->q + b->qbase[i];

@@ -384,6 +384,11 @@ __device__ __forceinline__ void block_append(const int (&vs)[U], const int (&add
 __device__ __forceinline__ bool bit_of(const unsigned* bm, int v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
 __device__ __forceinline__ void set_bit(unsigned* bm, int v) { atomicOr(&bm[v >> 5], 1u << (v & 31)); }
 
+// h(u) was raised by push-relabel (rounds that track it: DevGraph::relab).
+__device__ __forceinline__ void mark_relabel(const DevGraph& g, int u) {
+    if (g.relab) set_bit(g.relab, u);
+}
+
 // WORDS: the bitmaps are written a whole word at a time (a wave's 64
 // vertices are consecutive and 64-aligned: two words per bitmap), so they
 // need no clearing beforehand; else single bits are set into cleared maps.
@@ -980,6 +985,10 @@ __global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0
     // the host knew whether the BFS ends there; a frontier still waiting at
     // guard_level means it did not, and this build is skipped
     if (guard_level >= 0 && (ctr->front[guard_level % 3] & 0xFFFFFFFFull) != 0) return;
+    if (g.relab) {  // the rounds after this build start with no vertex marked as raised
+        const int nw = (g.n + 31) >> 5;
+        for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x) g.relab[w] = 0u;
+    }
     worklist_body<256>(hw_par(), g, wl0, wl1, wl2, ctr, topology, sign);
 }
 
@@ -1101,6 +1110,7 @@ __device__ __forceinline__ unsigned long long pr_thread_item(DevGraph& g, int u,
         if (best == ~0ull) {
             hu = N;
             g.h[u] = N;
+            mark_relabel(g, u);
             break;
         }
         int bh = (int)(best >> 32);
@@ -1108,6 +1118,7 @@ __device__ __forceinline__ unsigned long long pr_thread_item(DevGraph& g, int u,
         if (hu <= bh) {
             hu = bh + 1 < N ? bh + 1 : N;
             g.h[u] = hu;
+            mark_relabel(g, u);
             bytes += 4;
             if (hu >= N || ++c >= kc) break;
         }
@@ -1146,14 +1157,20 @@ __device__ __forceinline__ unsigned long long pr_wave_item(DevGraph& g, int u, i
         bytes += 12ull * (unsigned long long)(end - beg);
         if (best == ~0ull) {
             hu = N;
-            if (lane == 0) g.h[u] = N;
+            if (lane == 0) {
+                g.h[u] = N;
+                mark_relabel(g, u);
+            }
             break;
         }
         int bh = (int)(best >> 32);
         int bj = (int)(unsigned)best;
         if (hu <= bh) {
             hu = bh + 1 < N ? bh + 1 : N;
-            if (lane == 0) g.h[u] = hu;
+            if (lane == 0) {
+                g.h[u] = hu;
+                mark_relabel(g, u);
+            }
             bytes += 4;
             if (hu >= N || ++c >= kc) break;
         }
@@ -1263,7 +1280,10 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
         // excess left: the scan saw the whole row
         if (best == ~0ull) {
             hu = N;
-            if (threadIdx.x == 0) g.h[u] = N;
+            if (threadIdx.x == 0) {
+                g.h[u] = N;
+                mark_relabel(g, u);
+            }
             break;
         }
         const int bh = (int)(best >> 32);
@@ -1274,7 +1294,10 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
             bytes += 48;
         } else if (bh >= hu) {
             hu = bh + 1 < N ? bh + 1 : N;
-            if (threadIdx.x == 0) g.h[u] = hu;
+            if (threadIdx.x == 0) {
+                g.h[u] = hu;
+                mark_relabel(g, u);
+            }
             bytes += 4;
         }
         // bh == hu - 1: those slots were saturated by this pass; the next pass rescans
@@ -1395,21 +1418,26 @@ __global__ void __launch_bounds__(256) k_rie_round(DevGraph g, const int32_t* wl
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {  // block-uniform roles
         if (vb < nb2) {
             const int u = wl2[vb];
+            if (g.relab && !bit_of(g.relab, u)) continue;  // block-uniform: h(u) kept, no invalid out-slot
             const long long moved = wave_sum_i64(rie_item<BS>(g, u, (int)threadIdx.x, &bytes));
             if (lane_id() == 0 && moved) add_e(g.e, u, -moved);
         } else if (vb < nb2 + nb1) {
             const int item = (vb - nb2) * WPB + (int)threadIdx.x / WAVE;
             if (item < c.c1) {  // whole waves
                 const int u = wl1[item];
-                const long long moved = wave_sum_i64(rie_item<WAVE>(g, u, lane_id(), &bytes));
-                if (lane_id() == 0 && moved) add_e(g.e, u, -moved);
+                if (!g.relab || bit_of(g.relab, u)) {
+                    const long long moved = wave_sum_i64(rie_item<WAVE>(g, u, lane_id(), &bytes));
+                    if (lane_id() == 0 && moved) add_e(g.e, u, -moved);
+                }
             }
         } else {
             const int i = (vb - nb2 - nb1) * BS + (int)threadIdx.x;
             if (i < c.c0) {
                 const int u = wl0[i];
-                const long long moved = rie_item<1>(g, u, 0, &bytes);
-                if (moved) add_e(g.e, u, -moved);
+                if (!g.relab || bit_of(g.relab, u)) {
+                    const long long moved = rie_item<1>(g, u, 0, &bytes);
+                    if (moved) add_e(g.e, u, -moved);
+                }
             }
         }
     }

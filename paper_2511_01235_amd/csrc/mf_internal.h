@@ -41,6 +41,8 @@ struct DevGraph {
     int32_t* act;                        // not null: push-relabel / remove-invalid-edges append every vertex
     int32_t* act_cnt;                    // whose excess turns positive, counting in *act_cnt (which may
     int32_t act_cap;                     // pass act_cap: the extra ones are dropped)
+    unsigned* relab;                     // not null: push-relabel sets bit u when it raises h(u); the
+                                         // worklist build clears it; remove-invalid-edges skips unset rows
 };
 
 // Partial sums of algorithmic bytes: a kernel block adds into slot
