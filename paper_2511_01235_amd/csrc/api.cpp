@@ -86,6 +86,8 @@ struct mf_graph {
     int32_t round_min = 2;    // ... and at least this many (MF_ROUND_MIN)
     bool incremental_rounds = true;  // rounds take their worklist from the previous one plus activations
     int64_t narrow_max = 4096;       // BFS frontiers of up to this many slots run in one workgroup (0: never)
+    int64_t medium_max = 65536;      // ... up to this many in one cooperative launch of a few workgroups
+    int32_t medium_blocks = 32;      //     of this many 1024-thread blocks (0 where unsupported)
     // incremental worklists between relabels (made on first use)
     int32_t* act_list = nullptr;   // vertices whose excess turned positive in a round
     int32_t* mark = nullptr;       // per vertex: the round that last listed it
@@ -516,6 +518,11 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out, in
     // first frontier is tried that way, later ones when a chunk leaves one
     // small enough
     bool narrow = g->narrow_max > 0 && !g->trace_gr && (g->narrow_seed || !m.L.main);
+    bool medium = false;  // set when a read finds a mid-size frontier waiting
+    auto mid_size = [&](int lv) {
+        const int64_t slots = (int64_t)(m.L.ctr_h->front[lv % 3] >> 32);
+        return g->medium_blocks > 0 && !g->trace_gr && slots > g->narrow_max && slots <= g->medium_max;
+    };
     auto t_last = std::chrono::steady_clock::now();
     if (g->trace_gr) {
         mf_status rc = read_lane(g, m.L);
@@ -549,6 +556,34 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out, in
                 timed(g, m.L, mf::KC_GRS,
                       [&] { mf::launch_frontier_bitmap(m.L.q[level & 1], cnt, m.L.bits, level, st); });
             chunk = g->first_chunk;
+            medium = mid_size(level);
+        }
+        if (medium) {
+            hipError_t err = hipSuccess;
+            timed(g, m.L, mf::KC_GRS, [&] {
+                err = mf::launch_gr_medium(m.dg, level, m.L.q[0], m.L.q[1], m.L.ctr, m.L.bits, g->tune,
+                                           g->medium_max, m.forward, g->medium_blocks, st);
+            });
+            if (err != hipSuccess) {
+                (void)hipGetLastError();
+                g->medium_blocks = 0;  // no cooperative launch here: multi-block levels only
+            } else {
+                mf_status rc = read_lane(g, m.L);
+                if (rc != MF_OK) return rc;
+                if (m.L.ctr_h->bar_err) {
+                    g->poisoned = true;
+                    return MF_ERR_DEVICE;
+                }
+                level = m.L.ctr_h->levels;
+                const int cnt = (int)(unsigned)(m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull);
+                if (cnt == 0) break;
+                if (level > g->n + 2) {
+                    g->poisoned = true;
+                    return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
+                }
+                chunk = g->first_chunk;
+            }
+            medium = false;  // a larger frontier waits: multi-block levels
         }
         for (int i = 0; i < chunk; ++i, ++level)
             timed(g, m.L, mf::KC_GR, [&] {
@@ -592,6 +627,7 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out, in
         if (g->trace_gr) continue;  // one level per launch
         chunk = std::min(chunk * 2, 64);
         narrow = g->narrow_max > 0 && (int64_t)(m.L.ctr_h->front[level % 3] >> 32) <= g->narrow_max;
+        medium = !narrow && mid_size(level);
     }
     *levels_out += level;
     *depth_out = m.L.ctr_h->levels;
@@ -1249,11 +1285,19 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     if (const char* env = std::getenv("MF_GR_TRACE")) g->trace_gr = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_QUEUE_ROUNDS")) g->queue_rounds = std::atoi(env) != 0;
     if (const char* env = std::getenv("MF_PIPELINE")) g->pipeline = std::atoi(env) != 0;
+    if (const char* env = std::getenv("MF_GR_MEDIUM")) g->medium_max = std::max(0LL, std::atoll(env));
+    if (const char* env = std::getenv("MF_GR_MEDIUM_BLOCKS")) g->medium_blocks = std::max(0, std::atoi(env));
     if (const char* env = std::getenv("MF_ROUND_SCAN")) g->incremental_rounds = std::atoi(env) == 0;
     if (const char* env = std::getenv("MF_GR_NARROW")) g->narrow_max = std::max(0LL, std::atoll(env));
     if (const char* env = std::getenv("MF_ROUND_MAX")) g->round_max = std::max(1, std::atoi(env));
     if (const char* env = std::getenv("MF_ROUND_MIN")) g->round_min = std::max(1, std::atoi(env));
     if (o.relabel_mode == 1) g->persistent_grid = mf::persistent_gr_grid(dev);
+    {   // mid-size frontiers need cooperative launch (all blocks resident)
+        int coop = 0;
+        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
+            g->medium_blocks = 0;
+        if (g->medium_max <= g->narrow_max) g->medium_blocks = 0;
+    }
     g->dg.n = n;
     g->dg.s = s;
     g->dg.t = t;

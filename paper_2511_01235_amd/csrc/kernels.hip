@@ -901,6 +901,46 @@ template <int BS>
 __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, int32_t* wl0, int32_t* wl1,
                                               int32_t* wl2, DevCounters* ctr, int topology, int sign);
 
+// Mid-size frontiers (deep BFS of grid-like graphs, a few thousand to tens
+// of thousands of slots per level): a cooperative launch of a few 1024-thread
+// workgroups runs level after level of the multi-block level step (frontier
+// bitmaps kept up to date), separated by grid barriers -- a barrier of a few
+// arrivals costs less than a launch.  From level lv0 while the frontier
+// covers at most max_slots slots and the level goes top-down; stops at an
+// empty frontier, a larger one or a bottom-up level (not processed) or a
+// barrier error, and leaves the level to continue from in ctr->levels.  Every block reads the same counters after the barrier,
+// so all take the same exit.
+constexpr int GRM_BLOCK = 1024;
+
+template <bool FWD>
+__global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, int2* q0, int2* q1,
+                                                         DevCounters* ctr, GrBits bits, GrTune tune,
+                                                         long long max_slots) {
+    __shared__ unsigned long long s_front;
+    __shared__ int s_bad;
+    int lv = lv0;
+    for (; lv <= g.n; ++lv) {
+        if (threadIdx.x == 0) {
+            s_front = __hip_atomic_load(&ctr->front[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_bad = __hip_atomic_load(&ctr->bar_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        const unsigned long long front = s_front;
+        const int bad = s_bad;
+        __syncthreads();  // s_front / s_bad are rewritten next level
+        const long long cnt = (long long)(front & 0xFFFFFFFFull), fs = (long long)(front >> 32);
+        if (cnt == 0 || bad || fs > max_slots) break;
+        // a bottom-up level scans every unvisited vertex: the multi-block
+        // kernel's work (the direction rule as gr_level_step applies it)
+        const long long mu = ctr->unv[(lv + 2) % 3] - fs;
+        if (tune.bu_alpha > 0 && fs * tune.bu_alpha > mu && cnt * tune.bu_beta > (long long)g.n) break;
+        gr_level_step<FWD, GRM_BLOCK>(hw_par(), g, lv, (lv & 1) ? q1 : q0, (lv & 1) ? q0 : q1, ctr, bits, tune,
+                                      nullptr);
+        grid_sync(ctr);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->levels = lv;
+}
+
 // Global relabel and worklist build in one cooperative launch: seeds, then
 // one level after another separated by grid barriers (same level work as
 // k_gr_level), then the worklist and value over the fresh heights.
@@ -2315,6 +2355,18 @@ hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounte
     const void* fn = forward ? reinterpret_cast<const void*>(&k_gr_persistent<true>)
                              : reinterpret_cast<const void*>(&k_gr_persistent<false>);
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(GRP_BLOCK), args, 0, st);
+}
+
+hipError_t launch_gr_medium(const DevGraph& g, int lv0, int2* q0, int2* q1, DevCounters* ctr, const GrBits& bits,
+                            const GrTune& tune, long long max_slots, bool forward, int grid, hipStream_t st) {
+    DevGraph gg = g;
+    GrBits bb = bits;
+    GrTune tt = tune;
+    tt.lds = 0;
+    void* args[] = {&gg, &lv0, &q0, &q1, &ctr, &bb, &tt, &max_slots};
+    const void* fn = forward ? reinterpret_cast<const void*>(&k_gr_medium<true>)
+                             : reinterpret_cast<const void*>(&k_gr_medium<false>);
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(GRM_BLOCK), args, 0, st);
 }
 
 void launch_build_worklist(const DevGraph& g, int32_t* wl0, int32_t* wl1, int32_t* wl2,

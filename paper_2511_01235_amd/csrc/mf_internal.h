@@ -277,6 +277,11 @@ void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st);
 // thin-frontier BFS levels in one workgroup; ctr->levels = the level to continue from
 void launch_gr_narrow(const DevGraph& g, int lv0, int2* q0, int2* q1, DevCounters* ctr, const GrBits& bits,
                       long long max_slots, bool forward, hipStream_t st);
+// BFS levels from lv0 in one cooperative launch of `grid` 1024-thread blocks
+// while the frontier covers at most max_slots slots (ctr->levels: where to
+// continue; ctr->bar_err set if a grid barrier gave up)
+hipError_t launch_gr_medium(const DevGraph& g, int lv0, int2* q0, int2* q1, DevCounters* ctr, const GrBits& bits,
+                            const GrTune& tune, long long max_slots, bool forward, int grid, hipStream_t st);
 // zero the three frontier bitmaps, then set the current level's from its queue
 void launch_frontier_bitmap(const int2* q, int cnt, const GrBits& bits, int level, hipStream_t st);
 int64_t relayout_tiles(int32_t V);

@@ -90,6 +90,7 @@ def test_bottom_up_levels_bit_exact(name, variant, monkeypatch):
     monkeypatch.setenv("MF_GR_BU_LB", "1" if variant == "slots" else "0")
     monkeypatch.setenv("MF_GR_BU_WIDE", "1" if variant == "rows8" else "0")
     monkeypatch.setenv("MF_GR_NARROW", "0")   # every level through the multi-block kernels
+    monkeypatch.setenv("MF_GR_MEDIUM", "0")
     lb = variant
     g, stream, k, _ = gen.workload(name)
     say("bottom-up levels", name, "lb", lb)
@@ -190,6 +191,28 @@ def test_queued_rounds_same_values(name, mode, monkeypatch):
             assert G.apply_batch(u, v, c) == want
             side, cut = G.min_cut()
             assert cut == want
+
+
+@pytest.mark.parametrize("medium", ["0", "65536", str(1 << 30)])
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+def test_mid_frontier_levels_bit_exact(name, medium, monkeypatch):
+    """Frontiers above the one-workgroup threshold and up to MF_GR_MEDIUM
+    slots run in one cooperative launch of a few workgroups with grid
+    barriers (0: never; 1 << 30: every level that is not thin), handing
+    larger frontiers to the multi-block levels: heights bit-exact, static
+    value and repairs equal the oracle's."""
+    monkeypatch.setenv("MF_GR_MEDIUM", medium)
+    g, stream, k, _ = gen.workload(name)
+    say("mid-size frontiers", name, medium)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    h_want, _ = o.initial_labels()
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        h, _, _ = G.initial_labels()
+        assert np.array_equal(h, h_want)
+        assert G.maxflow() == o.static()
+        for _ in range(3):
+            u, v, c = stream.next_batch(k)
+            assert G.apply_batch(u, v, c) == o.apply(u, v, c)
 
 
 # --- static value ---------------------------------------------------------------
