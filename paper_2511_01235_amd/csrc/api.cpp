@@ -72,7 +72,7 @@ struct mf_graph {
     mf::GrBits bits{};
     mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0, 0};
     int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
-    int first_chunk = 8;      // BFS levels launched before the first frontier check
+    int first_chunk = 10;     // BFS levels launched before the first frontier check (at least)
     bool trace_gr = false;    // MF_GR_TRACE: one level per launch, each printed to stderr
     bool narrow_seed = true;  // start relabels in one workgroup (the last one's seeds were few enough)
     int32_t last_depth = 0;   // BFS levels of the last global relabel
@@ -1318,6 +1318,17 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     mf::launch_fill_i32(g->dg.h, 0, n, g->stream);
     mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->dg.e), 0, 2 * (int64_t)n, g->stream);
     mf::launch_clear_counters(g->ctr, g->stream);
+    if (g->medium_blocks > 0) {
+        // the process's first cooperative launch carries a one-time setup of
+        // several ms: pay it here rather than in the first solve (limit -1:
+        // the kernel leaves at its first frontier check, changing nothing but
+        // the level counter, which every relabel resets)
+        if (mf::launch_gr_medium(g->dg, 0, g->q[0], g->q[1], g->ctr, g->bits, g->tune, -1, false, g->medium_blocks,
+                                 g->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            g->medium_blocks = 0;
+        }
+    }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(g->stream) != hipSuccess)
         return fail(MF_ERR_DEVICE);
     *out = g;
