@@ -683,6 +683,8 @@ mf_status relabel_and_worklist(mf_graph* g, const LoopMode& m, int64_t* levels, 
 // a shallow one (RMAT, random graphs: depth under 10) a second round, which
 // starts from the activations of the first instead of a scan, still costs
 // well under a relabel and saves about a third of them.
+//
+// One round: push-relabel (two launches) and remove-invalid-edges (one).
 // dev: the bins' sizes are the worklist counts on the device when the
 // kernels run, cnt[] only upper bounds for their grids.
 mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const int cnt[3], bool dev = false) {
