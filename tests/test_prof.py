@@ -83,3 +83,14 @@ def test_recorded_traffic_only_for_the_current_source(tmp_path):
     stale.write_text(f"{prof.TRAFFIC_TAG}: 999 kernels.hip sha256 {'0' * 64}\n")
     assert prof.recorded_traffic("k_gr_level_old", str(tmp_path)) is None
     assert prof.recorded_traffic("k_gr_level_demo", os.path.join(str(tmp_path), "missing")) is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N above 1 exits with a message (one GPU here)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
