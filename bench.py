@@ -132,7 +132,8 @@ def main():
     extra = {}
     for kv in args.opt:
         key, _, val = kv.partition("=")
-        if key not in ("bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max", "long_row_cycles"):
+        if key not in ("bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max",
+                       "long_row_cycles") + mf.LOOP_FIELDS:
             raise SystemExit(f"--opt: unknown setting {key!r}")
         extra[key] = int(val)
     G = mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0,

@@ -98,6 +98,41 @@ typedef struct mf_options {
                                   <= 0: 1.  Their excess left over waits for the next round, so a
                                   hub's repeated full-row passes do not hold up the launch
                                   (in mf_batch_*, the graph's other rows). */
+    /* Loop and relabel settings of a single-graph handle (mf_graph_tune changes
+     * them on a live handle too).  None changes a result.  0 takes the
+     * default; on/off switches take 1 = on, -1 = off. */
+    int32_t bfs_first_chunk;   /* BFS levels launched before the host first checks whether the
+                                  BFS is over (a relabel of depth d launches max(this, d + 1));
+                                  <= 0: 10 */
+    int32_t bfs_narrow_slots;  /* frontiers of at most this many slots run in one workgroup, many
+                                  levels per launch; 0: 4096, < 0: never */
+    int32_t bfs_medium_slots;  /* larger frontiers up to this many slots run in one cooperative
+                                  launch of bfs_medium_blocks workgroups with a grid barrier per
+                                  level; 0: 65536, < 0: never (also where cooperative launch is
+                                  unsupported) */
+    int32_t bfs_medium_blocks; /* 0: 32 */
+    int32_t bfs_level_blocks;  /* workgroups of one multi-block BFS level launch; 0: four per
+                                  compute unit */
+    int32_t bfs_bottom_up;     /* bottom-up level variant: 0 a thread per unvisited row, four slot
+                                  loads in flight; 1 the same with eight; 2 slot-parallel over
+                                  the unvisited rows (no early exit per row) */
+    int32_t bfs_lds_bitmap;    /* 1: top-down levels of at least bfs_stage_min frontier entries read
+                                  the visited bitmap from a copy in LDS, where it fits */
+    int32_t bfs_stage_min;     /* 0: 1024 */
+    int32_t round_min;         /* push-relabel rounds per global relabel: at least this many
+                                  (and BFS depth / round_div); 0: 2 */
+    int32_t round_max;         /* ... and at most this many; 0: 4096 */
+    int32_t round_scan;        /* 1: every round's worklist comes from a scan of every vertex;
+                                  0: from the last worklist plus the round's activations */
+    int32_t queue_rounds;      /* -1: the worklist build and the first two rounds are not queued
+                                  behind the relabel's first chunk of levels (three read-backs
+                                  per iteration instead of one) */
+    int32_t pipeline;          /* -1: on shallow graphs the next iteration is not queued before
+                                  the host reads the last one's counters */
+    int32_t graph_capture;     /* -1: pipelined iterations are launched kernel by kernel instead
+                                  of replayed from a HIP graph captured once per handle */
+    int32_t trace;             /* 1: every BFS level (one per launch) and every round printed on
+                                  stderr, for diagnosis; slow */
 } mf_options;
 
 /* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its
@@ -234,11 +269,13 @@ mf_status mf_graph_offload(mf_graph* g);
 mf_status mf_graph_restore(mf_graph* g);
 
 /* Apply the tuning fields of *opt (kernel_cycles, bfs_alpha, bfs_beta,
- * round_div, bin_thread_max, bin_wave_max, long_row_cycles; others ignored, 0 =
- * default) to a
- * live handle, for autotuners that time one handle under several settings.
- * Results never depend on them.  Errors: MF_ERR_INVALID (NULL, struct_size,
- * bin_wave_max below bin_thread_max), MF_ERR_STATE (offloaded). */
+ * round_div, bin_thread_max, bin_wave_max, long_row_cycles), its loop and
+ * relabel settings (bfs_first_chunk ... trace) and max_iterations to a live
+ * handle, for autotuners that time one handle under several settings; other
+ * fields are ignored and every field left 0 takes its default.  Results never
+ * depend on them (max_iterations only decides MF_ERR_NOT_CONVERGED).
+ * Errors: MF_ERR_INVALID (NULL, struct_size, bin_wave_max below
+ * bin_thread_max, bfs_bottom_up outside 0..2), MF_ERR_STATE (offloaded). */
 mf_status mf_graph_tune(mf_graph* g, const mf_options* opt);
 
 /* Counters and sizes; see mf_stats (device_bytes is the counters' size while
@@ -259,6 +296,36 @@ mf_status mf_profile(mf_graph* g, int32_t class_mask);
  * the handle needing a new mf_maxflow before repairs. */
 mf_status mf_debug_initial_labels(mf_graph* g, int32_t* heights, int64_t* excess,
                                   int32_t* active, int32_t* n_active);
+
+/* Diagnostic: one round of the loop on the current heights, as a solve runs
+ * it between global relabels: the active-vertex worklist (Section 5.2), then
+ * with parts bit 0 the push-relabel kernel over it (Algorithm 2) and with bit 1
+ * the remove-invalid-edges kernel over the same rows (Algorithm 3).  For
+ * checking the invariants between kernels (mf_debug_check_invariants), for
+ * example after mf_debug_initial_labels.  Afterwards the handle needs a new
+ * mf_maxflow before repairs, cuts and flows (its heights are no longer a
+ * terminating relabel's).
+ * Errors: MF_ERR_INVALID (parts outside 0..3), MF_ERR_STATE (offloaded),
+ * MF_ERR_DEVICE. */
+mf_status mf_debug_round(mf_graph* g, int32_t parts);
+
+/* Diagnostic: check on the device what Section 3.1 states for the residual
+ * state between kernels, over every used slot and vertex.  counts: int64[8]
+ * host buffer receiving
+ *   [0] slots with a negative residual (c_f >= 0 must hold)
+ *   [1] slots whose pair's two residuals do not sum to its two capacities
+ *   [2] slots whose pairing is broken (rev[rev[j]] != j, the reverse slot's
+ *       column is not the row's vertex, or capsum != cap + cap of the reverse)
+ *   [3] vertices whose excess differs from their net inflow, the sum over
+ *       their row of (c_f - c)
+ *   [4] the sum of all excesses (0 when no flow is lost or created)
+ *   [5] vertices with a height outside [0, |V|]
+ *   [6] residual slots u->v with h(u) < |V| and h(u) > h(v) + 1 (none after a
+ *       fresh relabel or a remove-invalid-edges round)
+ *   [7] active vertices (outside {s, t}, e > 0, h < |V|; none when a solve ends)
+ * Does not change the state.  Errors: MF_ERR_INVALID, MF_ERR_STATE
+ * (offloaded), MF_ERR_DEVICE. */
+mf_status mf_debug_check_invariants(mf_graph* g, int64_t* counts);
 
 /* Diagnostic: run the device self-test of the wave primitives the kernels
  * rely on (64-lane DPP minimum, wave prefix sum) on `device` (-1: current)

@@ -31,9 +31,10 @@ MF_ERR_STATE = 6
 # every symbol include/mf.h declares
 EXPORTED = ["mf_default_options", "mf_status_string", "mf_graph_load", "mf_maxflow",
             "mf_apply_batch", "mf_apply_batch_device", "mf_min_cut", "mf_get_flow", "mf_get_edges",
-            "mf_graph_offload", "mf_graph_restore", "mf_graph_tune", "mf_get_stats", "mf_profile", "mf_debug_initial_labels", "mf_debug_selftest", "mf_debug_atomic_probe",
-            "mf_graph_free", "mf_batch_load", "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info",
-            "mf_batch_tune", "mf_batch_free"]
+            "mf_graph_offload", "mf_graph_restore", "mf_graph_tune", "mf_get_stats", "mf_profile",
+            "mf_debug_initial_labels", "mf_debug_selftest", "mf_debug_atomic_probe", "mf_debug_round",
+            "mf_debug_check_invariants", "mf_graph_free", "mf_batch_load", "mf_batch_maxflow",
+            "mf_batch_apply", "mf_batch_info", "mf_batch_tune", "mf_batch_free"]
 
 KERNEL_CLASSES = ["global_relabel", "push_relabel", "remove_invalid", "worklist", "batch", "init",
                   "relabel_seed_narrow", "unused7"]
@@ -53,7 +54,11 @@ class Options(C.Structure):
                 ("bfs_alpha", C.c_int32), ("bfs_beta", C.c_int32), ("round_div", C.c_int32),
                 ("bin_thread_max", C.c_int32), ("bin_wave_max", C.c_int32), ("batch_block", C.c_int32),
                 ("push_pull", C.c_int32), ("alloc", C.c_void_p), ("free", C.c_void_p),
-                ("alloc_ctx", C.c_void_p), ("long_row_cycles", C.c_int32)]
+                ("alloc_ctx", C.c_void_p), ("long_row_cycles", C.c_int32)] + \
+        [(name, C.c_int32) for name in ("bfs_first_chunk", "bfs_narrow_slots", "bfs_medium_slots",
+                                        "bfs_medium_blocks", "bfs_level_blocks", "bfs_bottom_up",
+                                        "bfs_lds_bitmap", "bfs_stage_min", "round_min", "round_max",
+                                        "round_scan", "queue_rounds", "pipeline", "graph_capture", "trace")]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -81,9 +86,13 @@ class TorchAllocator:
         self.alloc_fn = ALLOC_FN(_alloc)
         self.free_fn = FREE_FN(_free)
 
-# fields mf_graph_tune / mf_batch_tune apply to a live handle
+# loop and relabel settings of a single-graph handle (0 = default; switches 1 on, -1 off)
+LOOP_FIELDS = ("bfs_first_chunk", "bfs_narrow_slots", "bfs_medium_slots", "bfs_medium_blocks",
+               "bfs_level_blocks", "bfs_bottom_up", "bfs_lds_bitmap", "bfs_stage_min", "round_min",
+               "round_max", "round_scan", "queue_rounds", "pipeline", "graph_capture", "trace")
+# fields mf_graph_tune / mf_batch_tune apply to a live handle (mf_graph_tune also the loop fields)
 TUNING_FIELDS = ("kernel_cycles", "bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max",
-                 "batch_block", "long_row_cycles")
+                 "batch_block", "long_row_cycles", "max_iterations") + LOOP_FIELDS
 
 
 class Stats(C.Structure):
@@ -133,6 +142,8 @@ def lib():
         L.mf_debug_initial_labels.argtypes = [vp, vp, vp, vp, C.POINTER(i32)]
         L.mf_debug_selftest.argtypes = [i32]
         L.mf_debug_atomic_probe.argtypes = [i32, i64, i32, C.POINTER(C.c_double)]
+        L.mf_debug_round.argtypes = [vp, i32]
+        L.mf_debug_check_invariants.argtypes = [vp, vp]
         L.mf_graph_free.argtypes = [vp]
         L.mf_graph_free.restype = None
         L.mf_batch_load.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Options), C.POINTER(vp)]
@@ -145,7 +156,8 @@ def lib():
                      "mf_min_cut", "mf_get_flow", "mf_get_edges", "mf_graph_offload", "mf_graph_restore",
                      "mf_graph_tune", "mf_batch_tune",
                      "mf_get_stats", "mf_profile",
-                     "mf_debug_initial_labels", "mf_debug_selftest", "mf_debug_atomic_probe", "mf_batch_load",
+                     "mf_debug_initial_labels", "mf_debug_selftest", "mf_debug_atomic_probe", "mf_debug_round",
+                     "mf_debug_check_invariants", "mf_batch_load",
                      "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info"]:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -174,8 +186,14 @@ def mf_default_options() -> Options:
 def make_options(kernel_cycles=0, topology_driven=False, insert_slack_min=0, insert_slack_pct=0,
                  max_iterations=0, stream=None, device=-1, warm_start=True,
                  relabel_mode=0, bfs_alpha=0, bfs_beta=0, round_div=0, bin_thread_max=0, bin_wave_max=0,
-                 batch_block=0, push_pull=False, allocator=None, long_row_cycles=0) -> Options:
+                 batch_block=0, push_pull=False, allocator=None, long_row_cycles=0, **loop) -> Options:
+    """Options for a handle; `loop` takes any of LOOP_FIELDS."""
+    bad = set(loop) - set(LOOP_FIELDS)
+    if bad:
+        raise TypeError(f"unknown options: {sorted(bad)}")
     o = mf_default_options()
+    for name, val in loop.items():
+        setattr(o, name, int(val))
     o.push_pull = int(bool(push_pull))
     if allocator is not None:
         o.alloc = C.cast(allocator.alloc_fn, C.c_void_p).value
@@ -328,6 +346,21 @@ def mf_debug_atomic_probe(n: int = 1 << 26, width: int = 4, device: int = -1) ->
     return r.value
 
 
+INVARIANT_NAMES = ("negative_residuals", "pair_sums", "pair_links", "excess_mismatches", "excess_total",
+                   "heights_out_of_range", "steep_slots", "active")
+
+
+def mf_debug_round(g, parts: int = 3):
+    """parts bit 0: push-relabel round, bit 1: remove-invalid-edges round, over a fresh worklist."""
+    _check(lib().mf_debug_round(g, int(parts)), "mf_debug_round")
+
+
+def mf_debug_check_invariants(g) -> dict:
+    out = np.zeros(8, np.int64)
+    _check(lib().mf_debug_check_invariants(g, out.ctypes.data), "mf_debug_check_invariants")
+    return dict(zip(INVARIANT_NAMES, out.tolist()))
+
+
 def mf_graph_free(g):
     if g:
         lib().mf_graph_free(g)
@@ -377,6 +410,12 @@ class MaxFlowGraph:
 
     def initial_labels(self):
         return mf_debug_initial_labels(self.h, self.n)
+
+    def debug_round(self, parts=3):
+        mf_debug_round(self.h, parts)
+
+    def invariants(self) -> dict:
+        return mf_debug_check_invariants(self.h)
 
     def close(self):
         if self.h:

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cstdint>
@@ -53,7 +54,7 @@ struct mf_graph {
     int64_t k_cap = 0;
     mf::BatchTable tb{};
     uint8_t* side = nullptr;
-    unsigned long long* cut_acc = nullptr;
+    unsigned long long* cut_acc = nullptr;  // 8 words: cut / flow-slot sums, invariant counts
     // state
     bool solved = false;
     bool poisoned = false;
@@ -88,6 +89,16 @@ struct mf_graph {
     int64_t narrow_max = 4096;       // BFS frontiers of up to this many slots run in one workgroup (0: never)
     int64_t medium_max = 65536;      // ... up to this many in one cooperative launch of a few workgroups
     int32_t medium_blocks = 32;      //     of this many 1024-thread blocks (0 where unsupported)
+    bool coop_ok = false;            // the device supports cooperative launch
+    std::atomic<bool> coop_broken{false};  // a cooperative launch failed: multi-block levels only
+                                     // (set by either lane of a push-pull repair)
+    int cus = 256;                   // compute units of the device
+    bool graph_capture = true;       // pipelined iterations replayed from a captured HIP graph
+    bool capture_failed = false;     // capture or instantiation failed once: launch kernel by kernel
+    hipStream_t cap_stream = nullptr;  // stream the iteration is captured on (never launched on)
+    hipGraphExec_t it_exec = nullptr;  // the captured pipelined iteration
+    std::vector<long long> it_key;   // what it was captured with
+    long long* nslots_d = nullptr;   // the used slot count in device memory (kept while offloaded)
     // incremental worklists between relabels (made on first use)
     int32_t* act_list = nullptr;   // vertices whose excess turned positive in a round
     int32_t* mark = nullptr;       // per vertex: the round that last listed it
@@ -123,15 +134,11 @@ mf_status resolve_tuning(const mf_options& o, Tuning* t) {
     r.kc_option = o.kernel_cycles > 0 ? o.kernel_cycles : 0;
     r.gr = GrTune{GR_BU_ALPHA, GR_BU_BETA, GR_STAGE_MIN, 0, 0, 0};
     r.round_div = 8;
-    // environment overrides for experiments, where the option is left 0
-    if (const char* env = std::getenv("MF_GR_BU_ALPHA")) r.gr.bu_alpha = std::atoi(env);
-    if (const char* env = std::getenv("MF_GR_BU_BETA")) r.gr.bu_beta = std::max(1, std::atoi(env));
-    if (const char* env = std::getenv("MF_GR_STAGE_MIN")) r.gr.stage_min = std::atoi(env);
-    if (const char* env = std::getenv("MF_GR_BU_LB")) r.gr.bu_lb = std::atoi(env) != 0;
-    if (const char* env = std::getenv("MF_GR_BU_WIDE")) r.gr.bu_wide = std::atoi(env) != 0;
-    if (const char* env = std::getenv("MF_ROUND_DIV")) r.round_div = std::max(1, std::atoi(env));
+    if (o.bfs_stage_min > 0) r.gr.stage_min = o.bfs_stage_min;
+    if (o.bfs_bottom_up < 0 || o.bfs_bottom_up > 2) return MF_ERR_INVALID;
+    r.gr.bu_wide = o.bfs_bottom_up == 1;
+    r.gr.bu_lb = o.bfs_bottom_up == 2;
     r.long_cycles = 1;
-    if (const char* env = std::getenv("MF_KC_BLOCK")) r.long_cycles = std::max(1, std::atoi(env));
     if (o.long_row_cycles > 0) r.long_cycles = o.long_row_cycles;
     if (o.bfs_alpha > 0) r.gr.bu_alpha = o.bfs_alpha;
     if (o.bfs_alpha < 0) r.gr.bu_alpha = 0;
@@ -262,6 +269,13 @@ void free_lane2(mf_graph* g) {
 }
 
 void free_all(mf_graph* g) {
+    if (g->it_exec) {
+        (void)hipStreamSynchronize(g->stream);
+        (void)hipGraphExecDestroy(g->it_exec);
+        g->it_exec = nullptr;
+    }
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    g->cap_stream = nullptr;
     free_lane2(g);
     if (g->ctr2_h) (void)hipHostFree(g->ctr2_h);
     g->ctr2_h = nullptr;
@@ -270,6 +284,7 @@ void free_all(mf_graph* g) {
     dfree(g, g->dg.h);
     for (auto& w : g->wl) dfree(g, w);
     dfree(g, g->ctr);
+    dfree(g, g->nslots_d);
     if (g->ctr_h) (void)hipHostFree(g->ctr_h);
     g->ctr_h = nullptr;
     dfree(g, g->need);
@@ -394,6 +409,26 @@ void apply_tuning(mf_graph* g, const mf::Tuning& t) {
     g->dg.bin0_max = t.bin0;
     g->dg.bin1_max = t.bin1;
     g->kc_block = t.long_cycles;
+}
+
+// Loop and relabel settings of a handle from its options (0 = default).
+void apply_loop_options(mf_graph* g, const mf_options& o) {
+    auto on = [](int32_t v, bool dflt) { return v > 0 ? true : v < 0 ? false : dflt; };
+    g->first_chunk = o.bfs_first_chunk > 0 ? o.bfs_first_chunk : 10;
+    g->narrow_max = o.bfs_narrow_slots < 0 ? 0 : o.bfs_narrow_slots > 0 ? o.bfs_narrow_slots : 4096;
+    g->medium_max = o.bfs_medium_slots < 0 ? 0 : o.bfs_medium_slots > 0 ? o.bfs_medium_slots : 65536;
+    g->medium_blocks = o.bfs_medium_blocks > 0 ? o.bfs_medium_blocks : 32;
+    // mid-size frontiers need cooperative launch (every block resident)
+    if (!g->coop_ok || g->medium_max <= g->narrow_max) g->medium_blocks = 0;
+    g->gr_grid = o.bfs_level_blocks > 0 ? o.bfs_level_blocks : std::max(32, g->cus * 4);
+    g->tune.lds = on(o.bfs_lds_bitmap, false) && mf::gr_level_lds_bytes(g->bits.nwords, g->device) > 0 ? 1 : 0;
+    g->round_min = o.round_min > 0 ? o.round_min : 2;
+    g->round_max = o.round_max > 0 ? o.round_max : 4096;
+    g->incremental_rounds = !on(o.round_scan, false);
+    g->queue_rounds = on(o.queue_rounds, true);
+    g->pipeline = on(o.pipeline, true);
+    g->graph_capture = on(o.graph_capture, true);
+    g->trace_gr = on(o.trace, false);
 }
 
 // Push/relabel cycles per launch for worklist bin b (2: rows a workgroup takes).
@@ -521,7 +556,8 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out, in
     bool medium = false;  // set when a read finds a mid-size frontier waiting
     auto mid_size = [&](int lv) {
         const int64_t slots = (int64_t)(m.L.ctr_h->front[lv % 3] >> 32);
-        return g->medium_blocks > 0 && !g->trace_gr && slots > g->narrow_max && slots <= g->medium_max;
+        return g->medium_blocks > 0 && !g->coop_broken && !g->trace_gr && slots > g->narrow_max &&
+               slots <= g->medium_max;
     };
     auto t_last = std::chrono::steady_clock::now();
     if (g->trace_gr) {
@@ -566,7 +602,7 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out, in
             });
             if (err != hipSuccess) {
                 (void)hipGetLastError();
-                g->medium_blocks = 0;  // no cooperative launch here: multi-block levels only
+                g->coop_broken = true;  // no cooperative launch here: multi-block levels only
             } else {
                 mf_status rc = read_lane(g, m.L);
                 if (rc != MF_OK) return rc;
@@ -708,16 +744,107 @@ mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const
 mf_status ensure_round_lists(mf_graph* g) {
     if (g->act_list) return MF_OK;
     const int64_t n = g->n;
-    if (dalloc(g, &g->act_list, n) != hipSuccess || dalloc(g, &g->mark, n) != hipSuccess ||
+    if (dalloc(g, &g->act_list, n) != hipSuccess || dalloc(g, &g->mark, n + 1) != hipSuccess ||
         dalloc(g, &g->wlb[0], n) != hipSuccess || dalloc(g, &g->wlb[1], n) != hipSuccess ||
         dalloc(g, &g->wlb[2], n) != hipSuccess) {
         free_round_lists(g);
         return MF_ERR_OUT_OF_MEMORY;
     }
-    mf::launch_fill_i32(g->mark, 0, n, g->stream);
+    mf::launch_fill_i32(g->mark, 0, n + 1, g->stream);
     g->epoch = 0;
     MF_HIP(hipGetLastError());
     return MF_OK;
+}
+
+// BFS levels launched by every pipelined iteration.  The pipeline runs only
+// while the last relabel was shallower than PIPELINE_DEPTH levels, so with
+// at least that many every queued iteration -- the surplus one queued behind
+// the last, which relabels the same residual graph -- finishes its BFS within
+// its chunk and leaves exact heights (a cut read after the call depends on
+// them).  Levels past the BFS's end find an empty frontier and exit at once.
+constexpr int PIPELINE_DEPTH = 16;
+int pipelined_chunk(const mf_graph* g) { return std::min(64, std::max(g->first_chunk, PIPELINE_DEPTH)); }
+
+// The next-worklist marks compare with an epoch word in device memory
+// (mark[n]) that every next-worklist build moves on by one before it runs.
+// The host counts the builds it queues; before the word could wrap it clears
+// every mark and the word (stale marks of an old epoch only ever cost a
+// vertex one round's delay: the loop stops on a full scan after a relabel).
+void count_epochs(mf_graph* g, hipStream_t st, int builds) {
+    if (g->epoch > INT_MAX - 1024 - builds) {
+        mf::launch_fill_i32(g->mark, 0, (int64_t)g->n + 1, st);
+        g->epoch = 0;
+    }
+    g->epoch += builds;
+}
+
+// Everything a captured pipelined iteration bakes into its launches: the
+// graph and lane buffers, the loop mode, the tuning and the chunk.  The slot
+// count is left out (the relabel reads it from device memory).
+std::vector<long long> capture_key(const mf_graph* g, const LoopMode& m, const LoopMode& qm, int C) {
+    std::vector<long long> k;
+    auto P = [&](const void* p) { k.push_back((long long)(intptr_t)p); };
+    for (const DevGraph* d : {&m.dg, &qm.dg}) {
+        k.insert(k.end(), {d->n, d->s, d->t, d->root, d->pinned, d->count_bytes, d->bin0_max, d->bin1_max,
+                           d->side_keep, d->act_cap});
+        for (const void* p : {(const void*)d->row_ptr, (const void*)d->row_len, (const void*)d->row_sorted,
+                              (const void*)d->cr, (const void*)d->rev, (const void*)d->cap, (const void*)d->capsum,
+                              (const void*)d->e, (const void*)d->h, (const void*)d->nslots,
+                              (const void*)d->bytes_part, (const void*)d->side, (const void*)d->act,
+                              (const void*)d->act_cnt, (const void*)d->relab})
+            P(p);
+    }
+    const Lane& L = m.L;
+    for (const void* p : {(const void*)L.q[0], (const void*)L.q[1], (const void*)L.wl[0], (const void*)L.wl[1],
+                          (const void*)L.wl[2], (const void*)L.bits.visited, (const void*)L.bits.fb,
+                          (const void*)L.ctr, (const void*)g->mark, (const void*)g->wlb[0], (const void*)g->wlb[1],
+                          (const void*)g->wlb[2]})
+        P(p);
+    const mf::GrTune& t = g->tune;
+    k.insert(k.end(), {L.bits.nwords, t.bu_alpha, t.bu_beta, t.stage_min, t.lds, t.bu_lb, t.bu_wide, g->gr_grid,
+                       kc_for_bin(g, 0), kc_for_bin(g, 2), C, m.seed_deficits, m.sign, m.forward, m.topology,
+                       m.pull, m.rie, qm.rie});
+    return k;
+}
+
+// The pipelined iteration as an instantiated HIP graph: captured on the
+// handle's capture stream the first time, and again whenever something it
+// bakes in changed (a relayout, a restore, new tuning).  nullptr when capture
+// is unavailable: the caller launches the kernels one by one.
+template <class F>
+hipGraphExec_t iteration_graph(mf_graph* g, const LoopMode& m, const LoopMode& qm, int C, F&& enqueue) {
+    std::vector<long long> key = capture_key(g, m, qm, C);
+    if (g->it_exec && key == g->it_key) return g->it_exec;
+    if (g->it_exec) {
+        // an older graph may still be running on the stream
+        if (hipStreamSynchronize(g->stream) != hipSuccess) return nullptr;
+        (void)hipGraphExecDestroy(g->it_exec);
+        g->it_exec = nullptr;
+    }
+    if (g->capture_failed) return nullptr;
+    if (!g->cap_stream && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        g->capture_failed = true;
+        return nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    mf_status rc = MF_OK;
+    hipError_t e = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = enqueue(g->cap_stream);
+        e = hipStreamEndCapture(g->cap_stream, &graph);
+    }
+    if (e == hipSuccess && rc == MF_OK && graph) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess || rc != MF_OK || !exec) {
+        (void)hipGetLastError();
+        if (exec) (void)hipGraphExecDestroy(exec);
+        g->capture_failed = true;  // launch kernel by kernel from now on
+        return nullptr;
+    }
+    g->it_exec = exec;
+    g->it_key = std::move(key);
+    return exec;
 }
 
 mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
@@ -752,25 +879,30 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     }
     const int bounds[3] = {(int)g->n, (int)g->n, (int)g->n};
     mf_status tail_rc = MF_OK;
-    const std::function<void(int)> tail = [&](int level_end) {
-        timed(g, m.L, mf::KC_WL, [&] {
-            mf::launch_build_worklist(qm.dg, m.L.wl[0], m.L.wl[1], m.L.wl[2], m.L.ctr, m.topology, m.sign, st,
-                                      level_end);
+    // The launches queued behind the relabel's first chunk of levels on
+    // stream `sm`'s lane: the guarded worklist build, round 1, round 2's
+    // worklist from round 1's (one next-worklist build: one epoch), round 2.
+    auto enqueue_tail = [&](const LoopMode& mm, const LoopMode& qq, int level_end) -> mf_status {
+        hipStream_t s2 = mm.L.stream;
+        timed(g, mm.L, mf::KC_WL, [&] {
+            mf::launch_build_worklist(qq.dg, mm.L.wl[0], mm.L.wl[1], mm.L.wl[2], mm.L.ctr, mm.topology, mm.sign,
+                                      s2, level_end);
         });
         // the build cleared the activation count; the next-worklist build
         // sets the worklist counts aside in wl_in (the host reads the
         // relabel's there), round 2 keeps its own in wl
-        mf_status rc = push_round(g, qm, m.L.wl, bounds, true);
-        if (++g->epoch == INT_MAX) {
-            mf::launch_fill_i32(g->mark, 0, g->n, st);
-            g->epoch = 1;
-        }
-        timed(g, m.L, mf::KC_WL, [&] {
-            mf::launch_next_worklist(qm.dg, m.L.wl, nullptr, g->wlb[0], g->wlb[1], g->wlb[2], g->mark, g->epoch,
-                                     m.L.ctr, st);
+        mf_status rc = push_round(g, qq, mm.L.wl, bounds, true);
+        timed(g, mm.L, mf::KC_WL, [&] {
+            mf::launch_next_worklist(qq.dg, mm.L.wl, nullptr, g->wlb[0], g->wlb[1], g->wlb[2], g->mark,
+                                     g->mark + g->n, mm.L.ctr, s2);
         });
-        mf::launch_zero_act(m.L.ctr, st);
-        if (rc == MF_OK) rc = push_round(g, qm, g->wlb, bounds, true);
+        mf::launch_zero_act(mm.L.ctr, s2);
+        if (rc == MF_OK) rc = push_round(g, qq, g->wlb, bounds, true);
+        return rc;
+    };
+    const std::function<void(int)> tail = [&](int level_end) {
+        count_epochs(g, st, 1);
+        mf_status rc = enqueue_tail(m, qm, level_end);
         if (tail_rc == MF_OK) tail_rc = rc;
     };
     // Shallow relabels (depth under 16: at most two rounds each), no thin-
@@ -783,22 +915,41 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     // heights and finds the same empty worklist: it changes nothing.  A BFS
     // that outlasts its chunk (or grows deep) sends the loop back to the
     // ordinary iterations below, which start with a fresh relabel.
+    //
+    // Every pipelined iteration launches the same kernels with the same
+    // arguments (the chunk is fixed; the epoch and the slot count are read
+    // from device memory), so by default the iteration is captured once
+    // into a HIP graph and each later one is a single graph launch.
     bool finished = false;
-    if (queue && g->pipeline && !g->prof_mask && !g->narrow_seed && g->last_depth > 0 && g->last_depth < 16) {
+    if (queue && g->pipeline && !g->prof_mask && !g->narrow_seed && g->last_depth > 0 &&
+        g->last_depth < PIPELINE_DEPTH) {
         mf_status rc = ensure_snapshots(g);
         if (rc != MF_OK) return rc;
+        const int C = pipelined_chunk(g);
+        // the relabel init, C levels and the tail, on stream s3 (st, or the
+        // capture stream)
+        auto enqueue_iteration = [&](hipStream_t s3) -> mf_status {
+            LoopMode mm = m, qq = qm;
+            mm.L.stream = qq.L.stream = s3;
+            mf::launch_gr_init(mm.dg, mm.L.q[0], mm.L.ctr, mm.L.bits, mm.seed_deficits, s3);
+            for (int lv = 0; lv < C; ++lv)
+                mf::launch_gr_level(mm.dg, lv, mm.L.q[lv & 1], mm.L.q[(lv + 1) & 1], mm.L.ctr, mm.L.bits, g->tune,
+                                    g->gr_grid, mm.forward, s3);
+            return enqueue_tail(mm, qq, C);
+        };
+        hipGraphExec_t exec = g->graph_capture ? iteration_graph(g, m, qm, C, enqueue_iteration) : nullptr;
         hipError_t queue_err = hipSuccess;
         auto queue_iteration = [&](int slot) -> int {
-            timed(g, m.L, mf::KC_GRS,
-                  [&] { mf::launch_gr_init(m.dg, m.L.q[0], m.L.ctr, m.L.bits, m.seed_deficits, st); });
-            const int C = std::min(64, std::max(g->first_chunk, g->last_depth + 1));
-            for (int lv = 0; lv < C; ++lv)
-                timed(g, m.L, mf::KC_GR, [&] {
-                    mf::launch_gr_level(m.dg, lv, m.L.q[lv & 1], m.L.q[(lv + 1) & 1], m.L.ctr, m.L.bits, g->tune,
-                                        g->gr_grid, m.forward, st);
-                });
-            tail(C);
-            hipError_t e = hipMemcpyAsync(g->snap_h[slot], m.L.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, st);
+            count_epochs(g, st, 1);
+            hipError_t e = hipSuccess;
+            if (exec) {
+                e = hipGraphLaunch(exec, st);
+            } else {
+                mf_status r2 = enqueue_iteration(st);
+                if (tail_rc == MF_OK) tail_rc = r2;
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(g->snap_h[slot], m.L.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipEventRecord(g->snap_ev[slot], st);
             if (queue_err == hipSuccess) queue_err = e;
             return C;
@@ -830,7 +981,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
                 return MF_ERR_NOT_CONVERGED;
             }
             rounds += 2;
-            if (g->last_depth >= 16) break;  // deep now: the ordinary loop runs more rounds per relabel
+            if (g->last_depth >= PIPELINE_DEPTH) break;  // deep now: the ordinary loop runs more rounds per relabel
             k = 1 - k;
         }
         // leaving early: the iteration still queued runs to its end first
@@ -897,14 +1048,11 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
                 if (done >= R) break;
                 bool rebuilt = false;
                 if (incremental) {
-                    if (++g->epoch == INT_MAX) {
-                        mf::launch_fill_i32(g->mark, 0, g->n, st);
-                        g->epoch = 1;
-                    }
+                    count_epochs(g, st, 1);
                     int32_t* nxt[3];
                     for (int b = 0; b < 3; ++b) nxt[b] = cur[b] == m.L.wl[b] ? g->wlb[b] : m.L.wl[b];
                     timed(g, m.L, mf::KC_WL, [&] {
-                        mf::launch_next_worklist(rm.dg, cur, cnt, nxt[0], nxt[1], nxt[2], g->mark, g->epoch,
+                        mf::launch_next_worklist(rm.dg, cur, cnt, nxt[0], nxt[1], nxt[2], g->mark, g->mark + g->n,
                                                  m.L.ctr, st);
                     });
                     MF_HIP(hipGetLastError());
@@ -1064,6 +1212,7 @@ mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_
             mf::launch_batch_cleanup(g->tb, g->need, g->slot_of, g->win, k, st);
         });
         g->dg.used_slots += 2 * (int64_t)c.new_pairs;
+        if (c.new_pairs) mf::launch_set_i64(g->nslots_d, g->dg.used_slots, st);
         timed(g, mf::KC_INIT, [&] { mf::launch_saturate_source(g->dg, g->ctr, st); });
         MF_HIP(hipGetLastError());
         if (g->push_pull) {
@@ -1183,6 +1332,15 @@ mf_status push_pull_phase(mf_graph* g) {
     return MF_OK;
 }
 
+// Everything a solve or repair may allocate, taken before it changes any
+// state: a failed allocation then leaves the graph as it was.
+mf_status prepare_loop(mf_graph* g) {
+    mf_status rc = ensure_round_lists(g);
+    if (rc == MF_OK) rc = ensure_snapshots(g);
+    if (rc == MF_OK && g->push_pull) rc = ensure_lane2(g);
+    return rc;
+}
+
 struct CallTimer {
     mf_graph* g;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -1270,7 +1428,6 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     }
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    g->gr_grid = std::max(32, cus * 4);  // 256-thread level blocks, four per CU
     if (dalloc(g, &g->dg.bytes_part, (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS) != hipSuccess)
         return fail(MF_ERR_OUT_OF_MEMORY);
     mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->dg.bytes_part), 0,
@@ -1279,38 +1436,26 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     g->bits.nwords = (n + 31) / 32;
     if (dalloc(g, &g->bits.visited, 4 * (int64_t)g->bits.nwords) != hipSuccess) return fail(MF_ERR_OUT_OF_MEMORY);
     g->bits.fb = g->bits.visited + g->bits.nwords;
-    g->tune.lds = 0;  // LDS-bitmap level variant: opt-in (MF_GR_LDS=1), slower on rmat20
-    if (const char* env = std::getenv("MF_GR_LDS"))
-        if (std::atoi(env) != 0) g->tune.lds = mf::gr_level_lds_bytes(g->bits.nwords, dev) > 0 ? 1 : 0;
-    if (const char* env = std::getenv("MF_GR_GRID")) g->gr_grid = std::max(1, std::atoi(env));
-    if (const char* env = std::getenv("MF_GR_FIRST_CHUNK")) g->first_chunk = std::max(1, std::atoi(env));
-    if (const char* env = std::getenv("MF_GR_TRACE")) g->trace_gr = std::atoi(env) != 0;
-    if (const char* env = std::getenv("MF_QUEUE_ROUNDS")) g->queue_rounds = std::atoi(env) != 0;
-    if (const char* env = std::getenv("MF_PIPELINE")) g->pipeline = std::atoi(env) != 0;
-    if (const char* env = std::getenv("MF_GR_MEDIUM")) g->medium_max = std::max(0LL, std::atoll(env));
-    if (const char* env = std::getenv("MF_GR_MEDIUM_BLOCKS")) g->medium_blocks = std::max(0, std::atoi(env));
-    if (const char* env = std::getenv("MF_ROUND_SCAN")) g->incremental_rounds = std::atoi(env) == 0;
-    if (const char* env = std::getenv("MF_GR_NARROW")) g->narrow_max = std::max(0LL, std::atoll(env));
-    if (const char* env = std::getenv("MF_ROUND_MAX")) g->round_max = std::max(1, std::atoi(env));
-    if (const char* env = std::getenv("MF_ROUND_MIN")) g->round_min = std::max(1, std::atoi(env));
-    if (o.relabel_mode == 1) g->persistent_grid = mf::persistent_gr_grid(dev);
-    {   // mid-size frontiers need cooperative launch (all blocks resident)
+    {
         int coop = 0;
-        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
-            g->medium_blocks = 0;
-        if (g->medium_max <= g->narrow_max) g->medium_blocks = 0;
+        g->coop_ok = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop;
     }
+    g->cus = cus;
+    apply_loop_options(g, o);
     g->dg.n = n;
     g->dg.s = s;
     g->dg.t = t;
     g->dg.root = t;
     g->dg.pinned = s;
     g->dg.used_slots = b.pairs;
+    if (dalloc(g, &g->nslots_d, 1) != hipSuccess) return fail(MF_ERR_OUT_OF_MEMORY);
+    g->dg.nslots = g->nslots_d;
+    mf::launch_set_i64(g->nslots_d, g->dg.used_slots, g->stream);
     if (dalloc(g, &g->dg.e, n) != hipSuccess || dalloc(g, &g->dg.h, n) != hipSuccess ||
         dalloc(g, &g->wl[0], n) != hipSuccess || dalloc(g, &g->wl[1], n) != hipSuccess ||
         dalloc(g, &g->wl[2], n) != hipSuccess || dalloc(g, &g->ctr, 1) != hipSuccess ||
         dalloc(g, &g->need, n) != hipSuccess || dalloc(g, &g->side, n) != hipSuccess ||
-        dalloc(g, &g->cut_acc, 1) != hipSuccess)
+        dalloc(g, &g->cut_acc, 8) != hipSuccess)
         return fail(MF_ERR_OUT_OF_MEMORY);
     if (hipHostMalloc((void**)&g->ctr_h, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess)
         return fail(MF_ERR_OUT_OF_MEMORY);
@@ -1328,7 +1473,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
         if (mf::launch_gr_medium(g->dg, 0, g->q[0], g->q[1], g->ctr, g->bits, g->tune, -1, false, g->medium_blocks,
                                  g->stream) != hipSuccess) {
             (void)hipGetLastError();
-            g->medium_blocks = 0;
+            g->coop_broken = true;
         }
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(g->stream) != hipSuccess)
@@ -1343,6 +1488,8 @@ mf_status mf_maxflow(mf_graph* g, int64_t* value) {
     if (!value) return MF_ERR_INVALID;
     CallTimer timer(g);
     hipStream_t st = g->stream;
+    rc = prepare_loop(g);
+    if (rc != MF_OK) return rc;
     g->solved = false;
     mf::launch_clear_counters(g->ctr, st);
     timed(g, mf::KC_INIT, [&] {
@@ -1374,6 +1521,7 @@ static mf_status apply_common(mf_graph* g, const mf_update* upd, int64_t k, int6
         return MF_OK;
     }
     rc = ensure_batch_capacity(g, k);
+    if (rc == MF_OK) rc = prepare_loop(g);
     if (rc != MF_OK) return rc;
     const mf_update* d_upd = upd;
     if (!on_device) {
@@ -1451,6 +1599,11 @@ mf_status mf_get_flow(mf_graph* g, int64_t* count, int32_t* src, int32_t* dst, i
         dfree(g, h2);
         dfree(g, fslot);
     };
+    // every exit, the early error returns of MF_HIP included, releases the copies
+    struct Guard {
+        std::function<void()> f;
+        ~Guard() { f(); }
+    } guard{release};
     if (dalloc(g, &cr2, S) != hipSuccess || dalloc(g, &e2, n) != hipSuccess ||
         dalloc(g, &h2, n) != hipSuccess || dalloc(g, &fslot, S) != hipSuccess) {
         release();
@@ -1608,7 +1761,7 @@ mf_status mf_graph_restore(mf_graph* g) {
         dalloc(g, &g->dg.capsum, S) || dalloc(g, &g->win, S) || dalloc(g, &g->q[0], g->q_cap) ||
         dalloc(g, &g->q[1], g->q_cap) || dalloc(g, &g->dg.e, n) || dalloc(g, &g->dg.h, n) ||
         dalloc(g, &g->wl[0], n) || dalloc(g, &g->wl[1], n) || dalloc(g, &g->wl[2], n) || dalloc(g, &g->need, n) ||
-        dalloc(g, &g->side, n) || dalloc(g, &g->cut_acc, 1) ||
+        dalloc(g, &g->side, n) || dalloc(g, &g->cut_acc, 8) ||
         dalloc(g, &g->bits.visited, 4 * (int64_t)g->bits.nwords) ||
         dalloc(g, &g->dg.bytes_part, (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS)) {
         free_device_state(g);
@@ -1642,6 +1795,8 @@ mf_status mf_graph_tune(mf_graph* g, const mf_options* opt) {
     mf::Tuning t;
     if (mf::resolve_tuning(*opt, &t) != MF_OK) return MF_ERR_INVALID;
     apply_tuning(g, t);
+    apply_loop_options(g, *opt);
+    g->max_iter = opt->max_iterations > 0 ? opt->max_iterations : 4 * (int64_t)g->n + 1000;
     return MF_OK;
 }
 
@@ -1715,6 +1870,38 @@ mf_status mf_debug_initial_labels(mf_graph* g, int32_t* heights, int64_t* excess
     MF_HIP(hipStreamSynchronize(st));
     if (n_active) *n_active = c.wl[0] + c.wl[1] + c.wl[2];
     g->last_levels = levels;
+    return MF_OK;
+}
+
+mf_status mf_debug_round(mf_graph* g, int32_t parts) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    if (parts < 0 || parts > 3) return MF_ERR_INVALID;
+    hipStream_t st = g->stream;
+    const LoopMode m = solve_mode(g);
+    mf::launch_zero_loop_counters(g->ctr, st);
+    mf::launch_build_worklist(m.dg, g->wl[0], g->wl[1], g->wl[2], g->ctr, false, 1, st);
+    const int bounds[3] = {(int)g->n, (int)g->n, (int)g->n};
+    if (parts & 1)
+        mf::launch_push_relabel_round(m.dg, g->wl, bounds, kc_for_bin(g, 0), kc_for_bin(g, 2), false, st,
+                                      g->ctr->wl);
+    if (parts & 2) mf::launch_remove_invalid_round(m.dg, g->wl, bounds, g->ctr, st, g->ctr->wl);
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipStreamSynchronize(st));
+    // the heights are no longer those of a terminating relabel
+    g->solved = false;
+    return MF_OK;
+}
+
+mf_status mf_debug_check_invariants(mf_graph* g, int64_t* counts) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    if (!counts) return MF_ERR_INVALID;
+    hipStream_t st = g->stream;
+    mf::launch_check_invariants(g->dg, g->cut_acc, st);
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipMemcpyAsync(counts, g->cut_acc, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    MF_HIP(hipStreamSynchronize(st));
     return MF_OK;
 }
 

@@ -293,12 +293,17 @@ __global__ void k_zero_counters_front(DevCounters* ctr) {
 
 // Between push-relabel rounds: clear the worklist counts (before the next
 // worklist) or the activation count (before the next push-relabel).
-__global__ void k_zero_counts(DevCounters* ctr, int wl, int act) {
+__global__ void k_zero_counts(DevCounters* ctr, int wl, int act, int32_t* bump) {
     if (wl && threadIdx.x < 4) {
         ctr->wl_in[threadIdx.x] = ctr->wl[threadIdx.x];  // the lists the next build reads
         ctr->wl[threadIdx.x] = 0;
     }
     if (act && threadIdx.x == 0) ctr->act = 0;
+    if (bump && threadIdx.x == 0) *bump += 1;  // a fresh epoch for the next-worklist marks
+}
+
+__global__ void k_set_i64(long long* p, long long value) {
+    if (threadIdx.x == 0) *p = value;
 }
 
 // Append the frontier entries of the lanes that discovered a vertex:
@@ -439,7 +444,7 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
     }
     if (P.bid == 0 && threadIdx.x == 0) {
         // slots of every row that may be labelled, the seeds' included
-        ctr->unv[2] = (long long)g.used_slots - g.row_len[g.pinned];
+        ctr->unv[2] = (g.nslots ? *g.nslots : (long long)g.used_slots) - g.row_len[g.pinned];
         add_bytes(g, cls, 12ull * (unsigned long long)N);
     }
 }
@@ -1910,6 +1915,48 @@ __global__ void __launch_bounds__(256) k_cut(DevGraph g, uint8_t* side, unsigned
     if (threadIdx.x == 0 && tot) atomicAdd(cut, (unsigned long long)tot);
 }
 
+// ---- invariants of the residual state (diagnostics) ----------------------------
+//
+// Counts, over every used slot and vertex, the violations of what Section 3.1
+// states for every moment between kernels: c_f >= 0; the two residuals of a
+// pair sum to its two capacities; the excess of v is its net inflow,
+// sum over row v of (c_f - c); the excesses sum to zero.  Also the height
+// range, the residual slots that are steep (h(u) > h(v) + 1 with h(u) < |V|:
+// a labelling Algorithm 3 and a fresh relabel leave valid) and the active
+// vertices.  out[] as in launch_check_invariants.
+__global__ void __launch_bounds__(256) k_check_invariants(DevGraph g, unsigned long long* out) {
+    const int N = g.n;
+    long long neg = 0, pair = 0, link = 0, exc = 0, hr = 0, steep = 0, act = 0, esum = 0;
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < N; u += gridDim.x * blockDim.x) {
+        const int beg = g.row_ptr[u], end = beg + g.row_len[u];
+        const int hu = g.h[u];
+        if (hu < 0 || hu > N) ++hr;
+        long long net = 0;
+        for (int j = beg; j < end; ++j) {
+            const int2 cr = g.cr[j];
+            const int r = g.rev[j];
+            if (cr.y < 0) ++neg;
+            if (r < 0 || cr.x < 0 || cr.x >= N) {
+                ++link;
+                continue;
+            }
+            if (g.rev[r] != j || g.cr[r].x != u || g.capsum[j] != g.cap[j] + g.cap[r]) ++link;
+            if ((long long)cr.y + g.cr[r].y != (long long)g.capsum[j]) ++pair;
+            net += (long long)cr.y - g.cap[j];
+            if (cr.y > 0 && hu < N && hu > g.h[cr.x] + 1) ++steep;
+        }
+        const long long e = g.e[u];
+        if (e != net) ++exc;
+        esum += e;
+        if (u != g.s && u != g.t && e > 0 && hu < N) ++act;
+    }
+    const long long vals[8] = {neg, pair, link, exc, esum, hr, steep, act};
+    for (int i = 0; i < 8; ++i) {
+        const long long tot = block_sum_i64<256>(vals[i]);
+        if (threadIdx.x == 0 && tot) atomicAdd(&out[i], (unsigned long long)tot);
+    }
+}
+
 // ---- flow from residuals (Section 3.1, the three cases per pair) --------------
 
 // For a completed flow: f(u,v) = c(u,v) - c_f(u,v) when positive, else 0.
@@ -1995,8 +2042,9 @@ inline int grid_for(int64_t items, int block, int cap = 4096) {
 // each once (mark[v] == epoch), binned by row length.
 __global__ void __launch_bounds__(256) k_next_worklist(DevGraph g, const int32_t* in0, const int32_t* in1,
                                                        const int32_t* in2, int c0, int c1, int c2, int32_t* out0,
-                                                       int32_t* out1, int32_t* out2, int32_t* mark, int32_t epoch,
-                                                       DevCounters* ctr) {
+                                                       int32_t* out1, int32_t* out2, int32_t* mark,
+                                                       const int32_t* epoch_p, DevCounters* ctr) {
+    const int32_t epoch = *epoch_p;
     if (c0 < 0) {  // the input lists' sizes on the device (set aside by k_zero_counts)
         c0 = ctr->wl_in[0];
         c1 = ctr->wl_in[1];
@@ -2335,10 +2383,10 @@ int persistent_gr_grid(int device) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_f, k_gr_persistent<true>, GRP_BLOCK, 0) !=
             hipSuccess || per_cu_f < 1)
         return 0;
-    int want = 1;  // blocks per CU: one keeps barrier arrivals few; MF_GR_BLOCKS_PER_CU overrides
-    if (const char* env = std::getenv("MF_GR_BLOCKS_PER_CU")) want = std::max(1, std::atoi(env));
-    want = std::min(want, std::min(per_cu, per_cu_f));
-    return cus * want;
+    // one block per CU keeps the barrier's arrivals few
+    (void)per_cu;
+    (void)per_cu_f;
+    return cus;
 }
 
 hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounters* ctr,
@@ -2455,6 +2503,11 @@ void launch_reduce_bytes(const DevGraph& g, DevCounters* ctr, hipStream_t st) {
     k_reduce_bytes<<<KC_NCLASS, 256, 0, st>>>(g, ctr);
 }
 
+void launch_check_invariants(const DevGraph& g, unsigned long long* out, hipStream_t st) {
+    launch_fill_i32(reinterpret_cast<int32_t*>(out), 0, 16, st);
+    k_check_invariants<<<grid_for(g.n, 256, 4096), 256, 0, st>>>(g, out);
+}
+
 void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipStream_t st) {
     k_cut<<<grid_for(g.n, 256, 4096), 256, 0, st>>>(g, side, cut);
 }
@@ -2484,11 +2537,11 @@ void launch_batch_cleanup_multi(GraphUpdates* gu, int num, hipStream_t st) {
 }
 
 void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const int cnt[3], int32_t* out0,
-                          int32_t* out1, int32_t* out2, int32_t* mark, int32_t epoch, DevCounters* ctr,
+                          int32_t* out1, int32_t* out2, int32_t* mark, int32_t* epoch, DevCounters* ctr,
                           hipStream_t st) {
     // cnt null: the input sizes are the worklist counts, which k_zero_counts
-    // sets aside in wl_in before it clears them
-    k_zero_counts<<<1, 64, 0, st>>>(ctr, 1, 0);
+    // sets aside in wl_in before it clears them; it also moves the epoch on
+    k_zero_counts<<<1, 64, 0, st>>>(ctr, 1, 0, epoch);
     const int64_t most = cnt ? (int64_t)cnt[0] + cnt[1] + cnt[2] + g.act_cap : (int64_t)g.n + g.act_cap;
     k_next_worklist<<<grid_for(most, 256, 2048), 256, 0, st>>>(g, in[0], in[1], in[2], cnt ? cnt[0] : -1,
                                                               cnt ? cnt[1] : 0, cnt ? cnt[2] : 0, out0, out1,
@@ -2496,7 +2549,11 @@ void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const i
 }
 
 void launch_zero_act(DevCounters* ctr, hipStream_t st) {
-    k_zero_counts<<<1, 64, 0, st>>>(ctr, 0, 1);
+    k_zero_counts<<<1, 64, 0, st>>>(ctr, 0, 1, nullptr);
+}
+
+void launch_set_i64(long long* p, long long value, hipStream_t st) {
+    k_set_i64<<<1, 64, 0, st>>>(p, value);
 }
 
 int64_t relayout_tiles(int32_t V) { return ((int64_t)V + RL_TILE - 1) / RL_TILE; }

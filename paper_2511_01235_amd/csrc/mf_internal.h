@@ -33,6 +33,8 @@ struct DevGraph {
     int64_t* e;
     int32_t* h;
     int64_t used_slots;                  // sum of row_len
+    const long long* nslots;             // not null: the same count in device memory, which the kernels
+                                         // read instead (a captured launch keeps its arguments)
     unsigned long long* bytes_part;      // KC_NCLASS x BYTES_SLOTS algorithmic-byte partial sums
     int count_bytes;                     // 1 while kernel classes are being profiled
     int bin0_max, bin1_max;              // worklist degree bins: thread up to bin0_max slots, wave up to bin1_max
@@ -259,6 +261,10 @@ void launch_batch_clamp(const DevGraph& g, const mf_update* upd, int64_t k,
 void launch_batch_cleanup(BatchTable tb, int32_t* need, const int32_t* slot_of, int32_t* win,
                           int64_t k, hipStream_t st);
 void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipStream_t st);
+// out[8] (device): negative residuals, broken pair sums, broken pair links,
+// excess mismatches, sum of excesses, heights out of range, steep residual
+// slots, active vertices
+void launch_check_invariants(const DevGraph& g, unsigned long long* out, hipStream_t st);
 void launch_flow_slots(const DevGraph& g, int32_t* flow_slot, unsigned long long* count,
                        hipStream_t st);
 int device_selftest(hipStream_t st);
@@ -298,10 +304,12 @@ void launch_remove_invalid_round(const DevGraph& g, const int32_t* const wl[3], 
 // next worklist of a push-relabel round without a relabel: the previous
 // worklist's bins (counts cnt[0..2], or with cnt null the worklist counts on
 // the device, set aside in wl_in first) and the activation list, filtered to
-// active vertices (e > 0, h < n), deduplicated with mark[v] == epoch, binned
+// active vertices (e > 0, h < n), deduplicated with mark[v] == *epoch (a
+// device word the launch increments first), binned
 void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const int cnt[3], int32_t* out0,
-                          int32_t* out1, int32_t* out2, int32_t* mark, int32_t epoch, DevCounters* ctr,
+                          int32_t* out1, int32_t* out2, int32_t* mark, int32_t* epoch, DevCounters* ctr,
                           hipStream_t st);
+void launch_set_i64(long long* p, long long value, hipStream_t st);
 void launch_zero_act(DevCounters* ctr, hipStream_t st);
 // sizes, their scan into start[] and the rows to sort; then the caller reads
 // start[V] (the new slot count) and *sort_count

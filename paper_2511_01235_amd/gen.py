@@ -454,7 +454,8 @@ def _serving_graph(spec):
 
 def serving_workload(graphs: int = 64, requests: int = 2000, seed: int = 51000, arrival_seed: int = 50000,
                      batch_seed: int = 52000, scale_lo: int = 14, scale_hi: int = 20, edge_factor: int = 16,
-                     cap_max: int = 1000, k_lo: int = 10, k_hi: int = 10_000, workers: int = 1):
+                     cap_max: int = 1000, k_lo: int = 10, k_hi: int = 10_000, workers: int = 1,
+                     scales=None):
     """Graphs and a request trace for the serving loop.
 
     Graph i is RMAT with scale uniform in [scale_lo, scale_hi] (drawn from
@@ -467,10 +468,15 @@ def serving_workload(graphs: int = 64, requests: int = 2000, seed: int = 51000, 
     BatchStream seeded with batch_seed + 1000 * i, so they depend only on that
     graph's sizes: graphs are built in `workers` processes.
 
+    `scales` (a list of `graphs` ints) fixes the scales instead of drawing them.
+
     Returns (graphs, requests) with requests a list of (graph, gap_s, u, v, c)
     in arrival order."""
     rng = rng_for(seed)
-    scales = [int(x) for x in rng.integers(scale_lo, scale_hi + 1, size=graphs)]
+    drawn = [int(x) for x in rng.integers(scale_lo, scale_hi + 1, size=graphs)]
+    scales = drawn if scales is None else [int(x) for x in scales]
+    if len(scales) != graphs:
+        raise ValueError("one scale per graph")
     ar = rng_for(arrival_seed)
     target = ar.integers(0, graphs, size=requests)
     size = np.round(np.exp(ar.uniform(np.log(k_lo), np.log(k_hi), size=requests))).astype(np.int64)

@@ -123,3 +123,24 @@ def test_bad_tuning_is_rejected():
     assert ei.value.status == mf.MF_ERR_INVALID
     with pytest.raises(mf.MFError):
         mf.mf_graph_load(3, src, dst, cap, 0, 2, mf.make_options(batch_block=300))
+
+
+def test_loop_options_validated_before_the_device():
+    """Loop and relabel settings travel in mf_options (no environment
+    switches); an out-of-range variant is rejected before any device work."""
+    o = mf.make_options(bfs_first_chunk=4, pipeline=-1, graph_capture=1, bfs_narrow_slots=-1)
+    assert (o.bfs_first_chunk, o.pipeline, o.graph_capture, o.bfs_narrow_slots) == (4, -1, 1, -1)
+    with pytest.raises(TypeError):
+        mf.make_options(no_such_setting=1)
+    bad = mf.make_options(bfs_bottom_up=3)
+    with pytest.raises(mf.MFError) as ei:
+        mf.mf_graph_load(3, [0], [1], [1], 0, 2, bad)
+    assert ei.value.status == mf.MF_ERR_INVALID
+
+
+def test_library_reads_no_environment_switches():
+    """The product library takes every setting from mf_options: its sources
+    call no getenv."""
+    import glob
+    for path in glob.glob(os.path.join(ROOT, "paper_2511_01235_amd", "csrc", "*")):
+        assert "getenv" not in open(path).read(), path

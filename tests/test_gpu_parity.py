@@ -81,22 +81,18 @@ def test_initial_labels_bit_exact(name):
 
 @pytest.mark.parametrize("variant", ["rows4", "rows8", "slots"])
 @pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
-def test_bottom_up_levels_bit_exact(name, variant, monkeypatch):
+def test_bottom_up_levels_bit_exact(name, variant):
     """Every BFS level bottom-up (per-row early exit with four or eight loads
     in flight, or slot-parallel rows): heights bit-exact to the oracle's BFS,
     and the dynamic values too."""
-    monkeypatch.setenv("MF_GR_BU_ALPHA", "1000000")
-    monkeypatch.setenv("MF_GR_BU_BETA", "1000000")
-    monkeypatch.setenv("MF_GR_BU_LB", "1" if variant == "slots" else "0")
-    monkeypatch.setenv("MF_GR_BU_WIDE", "1" if variant == "rows8" else "0")
-    monkeypatch.setenv("MF_GR_NARROW", "0")   # every level through the multi-block kernels
-    monkeypatch.setenv("MF_GR_MEDIUM", "0")
-    lb = variant
+    opts = dict(bfs_alpha=1000000, bfs_beta=1000000,
+                bfs_bottom_up={"rows4": 0, "rows8": 1, "slots": 2}[variant],
+                bfs_narrow_slots=-1, bfs_medium_slots=-1)   # every level through the multi-block kernels
     g, stream, k, _ = gen.workload(name)
-    say("bottom-up levels", name, "lb", lb)
+    say("bottom-up levels", name, variant)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
     h_want, _ = o.initial_labels()
-    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, **opts) as G:
         h, _, _ = G.initial_labels()
         assert np.array_equal(h, h_want)
         assert G.maxflow() == o.static()
@@ -108,41 +104,38 @@ def test_bottom_up_levels_bit_exact(name, variant, monkeypatch):
 @pytest.mark.parametrize("scan", [0, 1])
 @pytest.mark.parametrize("div", [1, 8, 1000000])
 @pytest.mark.parametrize("name", ["grid64", "rmat12"])
-def test_push_rounds_between_relabels(name, div, scan, monkeypatch):
+def test_push_rounds_between_relabels(name, div, scan):
     """Push-relabel rounds on the current heights between global relabels
     (one per relabel up to one per BFS level), their worklists built from the
     previous one plus the activated vertices or by scanning every vertex:
     values equal the oracle's in the single-graph and the batched loops."""
-    monkeypatch.setenv("MF_ROUND_DIV", str(div))
-    monkeypatch.setenv("MF_ROUND_SCAN", str(scan))
     g, stream, k, _ = gen.workload(name)
-    say("push rounds", name, "div", div)
+    say("push rounds", name, "div", div, "scan", scan)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
     want = [o.static()]
     batches = [stream.next_batch(k) for _ in range(3)]
     want += [o.apply(*b) for b in batches]
-    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, round_div=div, round_scan=scan) as G:
         got = [G.maxflow()] + [G.apply_batch(*b) for b in batches]
         if div == 1 and name == "grid64":
             assert G.stats()["last_rounds"] > G.stats()["last_iterations"]
     assert got == want
-    with mf.MaxFlowBatch([g]) as B:
+    with mf.MaxFlowBatch([g], round_div=div) as B:
         got_b = [int(B.maxflow()[0])] + [int(B.apply([b])[0]) for b in batches]
     assert got_b == want
 
 
 @pytest.mark.parametrize("narrow", [0, 16, 4096, 1 << 30])
 @pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
-def test_thin_frontier_levels_bit_exact(name, narrow, monkeypatch):
+def test_thin_frontier_levels_bit_exact(name, narrow):
     """BFS levels with frontiers of up to `narrow` slots run in one workgroup
     (0: never, 1 << 30: every level), handing larger ones to the multi-block
     kernels and taking them back: heights bit-exact, values equal."""
-    monkeypatch.setenv("MF_GR_NARROW", str(narrow))
     g, stream, k, _ = gen.workload(name)
     say("thin frontiers", name, narrow)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
     h_want, _ = o.initial_labels()
-    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, bfs_narrow_slots=narrow or -1) as G:
         h, _, _ = G.initial_labels()
         assert np.array_equal(h, h_want)
         assert G.maxflow() == o.static()
@@ -170,7 +163,7 @@ def test_long_row_cycles_same_values(name, cycles):
 
 @pytest.mark.parametrize("mode", ["ordinary", "queued", "pipelined"])
 @pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
-def test_queued_rounds_same_values(name, mode, monkeypatch):
+def test_queued_rounds_same_values(name, mode):
     """The worklist build and first two rounds queued behind the relabel's
     first chunk of levels (device-sized, guarded on the BFS having ended;
     grid64's BFS outlasts the first chunk, so its queued launches must do
@@ -178,12 +171,12 @@ def test_queued_rounds_same_values(name, mode, monkeypatch):
     last one's counters (shallow graphs), or everything launched after the
     host read the counters: static value and repairs equal the oracle's in
     every mode, cut certified."""
-    monkeypatch.setenv("MF_QUEUE_ROUNDS", "0" if mode == "ordinary" else "1")
-    monkeypatch.setenv("MF_PIPELINE", "1" if mode == "pipelined" else "0")
+    opts = dict(queue_rounds=-1 if mode == "ordinary" else 1,
+                pipeline=1 if mode == "pipelined" else -1)
     g, stream, k, _ = gen.workload(name)
     say("queued rounds", name, mode)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
-    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, **opts) as G:
         assert G.maxflow() == o.static()
         for _ in range(4):
             u, v, c = stream.next_batch(k)
@@ -193,20 +186,48 @@ def test_queued_rounds_same_values(name, mode, monkeypatch):
             assert cut == want
 
 
-@pytest.mark.parametrize("medium", ["0", "65536", str(1 << 30)])
+@pytest.mark.parametrize("capture", [1, -1])
+@pytest.mark.parametrize("name", ["er2000", "rmat12"])
+def test_pipelined_surplus_iteration_leaves_exact_cut(name, capture):
+    """Pipelined iterations with a first chunk of one BFS level: the surplus
+    iteration queued behind the last one must still finish its BFS (every
+    pipelined iteration launches at least as many levels as the pipeline's
+    depth limit), so the cut read after each call is the certified one:
+    capacity equal to the value and a valid certificate, after the static
+    solve and after every repair, replayed from a captured graph or launched
+    kernel by kernel."""
+    g, stream, k, _ = gen.workload(name)
+    say("pipelined surplus", name, "capture", capture)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    cur = _CapModel(g.n, g.src, g.dst, g.cap)
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, bfs_first_chunk=1, pipeline=1,
+                         graph_capture=capture) as G:
+        val = G.maxflow()
+        assert val == o.static()
+        for i in range(6):
+            side, cut = G.min_cut()
+            assert cut == val
+            src, dst, cap = cur.arrays()
+            _cut_ok(g.n, g.s, g.t, side, cut, val, src, dst, cap)
+            u, v, c = stream.next_batch(k)
+            cur.apply(u, v, c)
+            val = G.apply_batch(u, v, c)
+            assert val == o.apply(u, v, c), i
+
+
+@pytest.mark.parametrize("medium", [-1, 65536, 1 << 30])
 @pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
-def test_mid_frontier_levels_bit_exact(name, medium, monkeypatch):
-    """Frontiers above the one-workgroup threshold and up to MF_GR_MEDIUM
+def test_mid_frontier_levels_bit_exact(name, medium):
+    """Frontiers above the one-workgroup threshold and up to bfs_medium_slots
     slots run in one cooperative launch of a few workgroups with grid
-    barriers (0: never; 1 << 30: every level that is not thin), handing
+    barriers (-1: never; 1 << 30: every level that is not thin), handing
     larger frontiers to the multi-block levels: heights bit-exact, static
     value and repairs equal the oracle's."""
-    monkeypatch.setenv("MF_GR_MEDIUM", medium)
     g, stream, k, _ = gen.workload(name)
     say("mid-size frontiers", name, medium)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
     h_want, _ = o.initial_labels()
-    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, bfs_medium_slots=medium) as G:
         h, _, _ = G.initial_labels()
         assert np.array_equal(h, h_want)
         assert G.maxflow() == o.static()
