@@ -126,7 +126,10 @@ def main():
     n_roof = 0 if args.profile_all else max(1, args.roofline_steps)
     if total > nb:
         log(f"note: {total} batches requested; the workload's stream continues past its nominal {nb}")
-    batches_np = [bstream.next_batch(k) for _ in range(total + n_roof)]
+    n_dev = 0 if args.profile_all else args.steps   # the device-resident pass after the timed one
+    batches_np = [bstream.next_batch(k) for _ in range(total + n_roof + n_dev)]
+    # host-memory batches as one [k, 3] int32 array each (what mf_apply_batch takes)
+    host_batches = [np.ascontiguousarray(np.stack(b, 1).astype(np.int32)) for b in batches_np]
     log(f"generated {g.name}: n={g.n} m={g.m} batches={total}x{k} in {time.time() - t0:.1f}s")
 
     extra = {}
@@ -174,12 +177,11 @@ def main():
     del cal_src, cal_dst
     log(f"copy probe {copy_gbs:.0f} GB/s; atomics {atomic_rates}")
 
-    dev_batches = [torch.from_numpy(np.ascontiguousarray(np.stack(b, 1).astype(np.int32))).to(dev)
-                   for b in batches_np]
+    dev_batches = [torch.from_numpy(b).to(dev) for b in host_batches]
     torch.cuda.synchronize()
     values = []
     for i in range(args.warmup):
-        values.append(G.apply_batch_device(dev_batches[i]))
+        values.append(G.apply_batch(host_batches[i]))
         log(f"warm-up batch {i} done")
     tuned = None
     if args.tune:
@@ -193,9 +195,11 @@ def main():
     per_batch, iters = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    # each step: mf_apply_batch on updates in host memory, from the call to the
+    # int64 value on the host, the copy of the batch to the device included
     for i in range(args.warmup, total):
         a = time.perf_counter()
-        values.append(G.apply_batch_device(dev_batches[i]))
+        values.append(G.apply_batch(host_batches[i]))
         per_batch.append((time.perf_counter() - a) * 1e3)
         iters.append(G.stats()["last_iterations"])
         if per_batch[-1] > 1000:
@@ -207,6 +211,19 @@ def main():
     ms_per_step = elapsed_ms / args.steps
     roof_elapsed_ms = elapsed_ms
 
+    # the same repairs with the batches already in HBM (mf_apply_batch_device),
+    # on the next batches of the stream
+    dev_ms = None
+    if n_dev:
+        base = total
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for i in range(base, base + n_dev):
+            values_dev = G.apply_batch_device(dev_batches[i])
+        torch.cuda.synchronize()
+        dev_ms = (time.perf_counter() - a) * 1e3 / n_dev
+        log(f"device-resident batches: {dev_ms:.3f} ms/batch")
+
     # from-scratch recompute of the same (final) graph on the GPU
     scratch_ms, scratch_val = [], None
     for r in range(max(1, args.scratch_runs)):
@@ -216,7 +233,7 @@ def main():
         torch.cuda.synchronize()
         scratch_ms.append((time.perf_counter() - a) * 1e3)
         scratch_val = v
-    assert scratch_val == values[-1], (scratch_val, values[-1])
+    assert scratch_val == (values_dev if n_dev else values[-1]), (scratch_val, values[-1])
     scratch_med = float(np.median(scratch_ms))
     if n_roof:
         # the relabel's level kernel, timed with HIP events on the library's
@@ -224,7 +241,7 @@ def main():
         G.profile(1 << 0)
         torch.cuda.synchronize()
         a = time.perf_counter()
-        for i in range(total, total + n_roof):
+        for i in range(total + n_dev, total + n_dev + n_roof):
             G.apply_batch_device(dev_batches[i])
         torch.cuda.synchronize()
         roof_elapsed_ms = (time.perf_counter() - a) * 1e3
@@ -262,7 +279,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(g, batches_np, static_val, values, args.cpu_budget_s)
+        host = cpu_host()
+        cpu = {**cpu_baseline(g, batches_np, static_val, values, args.cpu_budget_s), **host}
 
     arr = np.array(per_batch)
     out = {
@@ -283,6 +301,8 @@ def main():
                    "batch_size": k, "kernel_cycles": st["kernel_cycles"],
                    "warm_start": not args.cold_start, "relabel_mode": args.relabel_mode,
                    "push_pull": args.push_pull, **extra},
+        "batches_from": "host memory (mf_apply_batch; the copy to the device is inside each step)",
+        "device_resident_ms_per_batch": round(dev_ms, 4) if dev_ms else None,
         "incremental_ms_p50": round(float(np.percentile(arr, 50)), 4),
         "incremental_ms_p90": round(float(np.percentile(arr, 90)), 4),
         "incremental_ms_p99": round(float(np.percentile(arr, 99)), 4),
@@ -359,7 +379,8 @@ def bench_batched(args, mf, gen, torch, stream):
         f"{static_ms:.1f} vs {single_static_ms:.1f} ms")
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline_batched(graphs, batches[0], static_vals, values[0], args.cpu_budget_s)
+        host = cpu_host()
+        cpu = {**cpu_baseline_batched(graphs, batches[0], static_vals, values[0], args.cpu_budget_s), **host}
     out = {
         "metric": METRIC, "value": round(ms_per_step, 3), "unit": "ms/batch", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -481,7 +502,8 @@ def bench_serving(args, mf, inputs):
     assert v_poisu == v_seq
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline_serving(graphs, reqs, v_seq, args.cpu_budget_s)
+        host = cpu_host()
+        cpu = {**cpu_baseline_serving(graphs, reqs, v_seq, args.cpu_budget_s), **host}
     out = {
         "metric": METRIC, "value": round(pois["p99_ms"], 3), "unit": "ms p99 latency", "n_gpus": 1,
         "steps": len(reqs), "warmup": 0, "ms_per_step": round(1e3 / pois["batches_per_s"], 4),
@@ -508,6 +530,26 @@ def bench_serving(args, mf, inputs):
         "roofline": None, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_host():
+    """The oracle built -O3 -march=native for this host (loaded by every CPU
+    baseline below), and what the host is: CPU model and usable cores."""
+    import tempfile
+    import oracle
+    if "MF_ORACLE_LIB" not in os.environ:
+        path = os.path.join(tempfile.mkdtemp(prefix="mforacle"), "liboracle_native.so")
+        os.environ["MF_ORACLE_LIB"] = oracle.build_native(path)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "build": "gcc -O3 -march=native"}
 
 
 def cpu_baseline_serving(graphs, reqs, gpu_vals, budget_s):
@@ -548,7 +590,8 @@ def cpu_baseline_batched(graphs, batches, static_vals, rep_vals, budget_s):
     budget is spent; values checked against the GPU's."""
     import concurrent.futures as cf
     import oracle
-    cores = max(1, min(16, os.cpu_count() or 1))
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(16, usable))
     done = []
 
     def one(i):

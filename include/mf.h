@@ -195,13 +195,15 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
 /* Maximum flow value of the current capacities from zero flow: Algorithm 1
  * (initialise, saturate the source, loop {backward BFS, push-relabel kernel,
  * remove-invalid-edges kernel} while active vertices remain).  The loop stops
- * only when a freshly computed global relabel leaves no active vertex, and
- * *value = e(t) plus the (non-positive) excess of every deficient vertex.
+ * when no active vertex is left under a valid labelling -- right after a
+ * global relabel, or after a push-relabel plus remove-invalid-edges round,
+ * which keeps the labelling valid -- and *value = e(t) plus the
+ * (non-positive) excess of every deficient vertex.
  * Leaves the residual graph, excesses and heights on the device for repairs.
- * The value is final on return; the handle's stream may still be running one
- * more global relabel and worklist build that change nothing (the next
- * iteration, queued before the last one's counters were read).  Every later
- * call on the handle is ordered after it on that stream.
+ * The value is final on return; the handle's stream may still be running the
+ * launches of one more iteration (queued before the last one's counters were
+ * read), which find the loop over on the device and leave at once.  Every
+ * later call on the handle is ordered after them on that stream.
  * Errors: MF_ERR_INVALID (NULL), MF_ERR_NOT_CONVERGED, MF_ERR_DEVICE. */
 mf_status mf_maxflow(mf_graph* g, int64_t* value);
 
@@ -224,10 +226,12 @@ mf_status mf_apply_batch(mf_graph* g, const mf_update* upd, int64_t k, int64_t* 
 mf_status mf_apply_batch_device(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value);
 
 /* The minimum cut certified by the last solve (Sections 3.1 and 4.3):
- * source side A = {v : h(v) = |V|}, the vertices that cannot reach t or a
- * deficient vertex in the residual graph.  source_side: uint8[n] host buffer
- * (1 = A, 0 = B) or NULL; *cut_capacity = sum of c(u,v) over u in A, v in B,
- * which equals the last returned value.  Requires a prior solve.
+ * source side A = {v : h(v) = |V|} under a global relabel of the final
+ * residual graph, the vertices that cannot reach t or a deficient vertex in
+ * it (when the solve ended after a round rather than a relabel, this call
+ * runs that relabel first).  source_side: uint8[n] host buffer (1 = A,
+ * 0 = B) or NULL; *cut_capacity = sum of c(u,v) over u in A, v in B, which
+ * equals the last returned value.  Requires a prior solve.
  * Errors: MF_ERR_INVALID, MF_ERR_STATE, MF_ERR_DEVICE. */
 mf_status mf_min_cut(mf_graph* g, uint8_t* source_side, int64_t* cut_capacity);
 

@@ -153,6 +153,7 @@ def lib():
         L.mf_batch_free.argtypes = [vp]
         L.mf_batch_free.restype = None
         for name in ["mf_graph_load", "mf_maxflow", "mf_apply_batch", "mf_apply_batch_device",
+                    
                      "mf_min_cut", "mf_get_flow", "mf_get_edges", "mf_graph_offload", "mf_graph_restore",
                      "mf_graph_tune", "mf_batch_tune",
                      "mf_get_stats", "mf_profile",

@@ -95,10 +95,17 @@ struct mf_graph {
     int cus = 256;                   // compute units of the device
     bool graph_capture = true;       // pipelined iterations replayed from a captured HIP graph
     bool capture_failed = false;     // capture or instantiation failed once: launch kernel by kernel
+    bool heights_exact = true;       // heights are the last relabel's BFS distances (else a valid labelling
+                                     // left by the round that ended the solve)
     hipStream_t cap_stream = nullptr;  // stream the iteration is captured on (never launched on)
-    hipGraphExec_t it_exec = nullptr;  // the captured pipelined iteration
-    std::vector<long long> it_key;   // what it was captured with
-    long long* nslots_d = nullptr;   // the used slot count in device memory (kept while offloaded)
+    struct ItGraph {
+        std::vector<long long> key;  // what it was captured with
+        hipGraphExec_t exec;
+    };
+    std::vector<ItGraph> it_graphs;  // captured pipelined iterations
+    int32_t* halt_d = nullptr;       // the loop kernels' halt word (next to the slot count)
+    long long* nslots_d = nullptr;   // the used slot count in device memory, then the halt word (kept
+                                     // while offloaded)
     // incremental worklists between relabels (made on first use)
     int32_t* act_list = nullptr;   // vertices whose excess turned positive in a round
     int32_t* mark = nullptr;       // per vertex: the round that last listed it
@@ -269,11 +276,9 @@ void free_lane2(mf_graph* g) {
 }
 
 void free_all(mf_graph* g) {
-    if (g->it_exec) {
-        (void)hipStreamSynchronize(g->stream);
-        (void)hipGraphExecDestroy(g->it_exec);
-        g->it_exec = nullptr;
-    }
+    if (!g->it_graphs.empty()) (void)hipStreamSynchronize(g->stream);
+    for (auto& ig : g->it_graphs) (void)hipGraphExecDestroy(ig.exec);
+    g->it_graphs.clear();
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     g->cap_stream = nullptr;
     free_lane2(g);
@@ -756,14 +761,9 @@ mf_status ensure_round_lists(mf_graph* g) {
     return MF_OK;
 }
 
-// BFS levels launched by every pipelined iteration.  The pipeline runs only
-// while the last relabel was shallower than PIPELINE_DEPTH levels, so with
-// at least that many every queued iteration -- the surplus one queued behind
-// the last, which relabels the same residual graph -- finishes its BFS within
-// its chunk and leaves exact heights (a cut read after the call depends on
-// them).  Levels past the BFS's end find an empty frontier and exit at once.
+// Iterations are pipelined while the last relabel was shallower than this
+// (at most two rounds per relabel).
 constexpr int PIPELINE_DEPTH = 16;
-int pipelined_chunk(const mf_graph* g) { return std::min(64, std::max(g->first_chunk, PIPELINE_DEPTH)); }
 
 // The next-worklist marks compare with an epoch word in device memory
 // (mark[n]) that every next-worklist build moves on by one before it runs.
@@ -807,21 +807,24 @@ std::vector<long long> capture_key(const mf_graph* g, const LoopMode& m, const L
     return k;
 }
 
-// The pipelined iteration as an instantiated HIP graph: captured on the
-// handle's capture stream the first time, and again whenever something it
-// bakes in changed (a relayout, a restore, new tuning).  nullptr when capture
-// is unavailable: the caller launches the kernels one by one.
+// The pipelined iteration of chunk C as an instantiated HIP graph: captured
+// on the handle's capture stream the first time, and again whenever
+// something it bakes in changed (a relayout, a restore, new tuning); the
+// last four captures are kept (chunks follow the BFS depth, which varies a
+// little).  nullptr when capture is unavailable: the caller launches the
+// kernels one by one.
 template <class F>
 hipGraphExec_t iteration_graph(mf_graph* g, const LoopMode& m, const LoopMode& qm, int C, F&& enqueue) {
     std::vector<long long> key = capture_key(g, m, qm, C);
-    if (g->it_exec && key == g->it_key) return g->it_exec;
-    if (g->it_exec) {
-        // an older graph may still be running on the stream
-        if (hipStreamSynchronize(g->stream) != hipSuccess) return nullptr;
-        (void)hipGraphExecDestroy(g->it_exec);
-        g->it_exec = nullptr;
-    }
+    for (auto& ig : g->it_graphs)
+        if (ig.key == key) return ig.exec;
     if (g->capture_failed) return nullptr;
+    if (g->it_graphs.size() >= 4) {
+        // the oldest capture goes (it may still be running on the stream)
+        if (hipStreamSynchronize(g->stream) != hipSuccess) return nullptr;
+        (void)hipGraphExecDestroy(g->it_graphs.front().exec);
+        g->it_graphs.erase(g->it_graphs.begin());
+    }
     if (!g->cap_stream && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         g->capture_failed = true;
         return nullptr;
@@ -842,8 +845,7 @@ hipGraphExec_t iteration_graph(mf_graph* g, const LoopMode& m, const LoopMode& q
         g->capture_failed = true;  // launch kernel by kernel from now on
         return nullptr;
     }
-    g->it_exec = exec;
-    g->it_key = std::move(key);
+    g->it_graphs.push_back({std::move(key), exec});
     return exec;
 }
 
@@ -863,6 +865,20 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     // relabel only: the build is guarded on the device.)
     const bool queue = g->queue_rounds && m.L.main && !m.pull && !m.topology && g->incremental_rounds &&
                        g->round_min >= 2 && !g->trace_gr && g->persistent_grid == 0;
+    // The active set after a push-relabel plus remove-invalid-edges round is
+    // taken under a valid labelling (the rounds keep h(u) <= h(v) + 1 on every
+    // residual slot, Section 3.1; remove-invalid-edges repairs what races
+    // broke): a vertex at |V| then cannot reach t or a deficient vertex (its
+    // height would have to fall by |V| along a simple path), so an empty
+    // active set ends the loop there, without another relabel, with the same
+    // value (the sinks' excess sum).  This is Algorithm 1's test after its
+    // kernels.  Heights are then valid but not exact distances: the cut is
+    // read after a fresh relabel (mf_min_cut).  Only the solve itself (sinks
+    // t and the deficits, remove-invalid-edges on) ends this way.
+    // (With push-pull the next repair reads the last cut from the heights:
+    // those solves end after a relabel.)
+    const bool shortcut =
+        m.rie && !m.pull && m.sign == 1 && !m.forward && m.seed_deficits && m.L.main && !g->push_pull;
     LoopMode qm = m;
     if (queue) {
         mf_status rc = ensure_round_lists(g);
@@ -895,6 +911,8 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         timed(g, mm.L, mf::KC_WL, [&] {
             mf::launch_next_worklist(qq.dg, mm.L.wl, nullptr, g->wlb[0], g->wlb[1], g->wlb[2], g->mark,
                                      g->mark + g->n, mm.L.ctr, s2);
+            // round 1 left no active vertex: the value, and no second round
+            if (shortcut) mf::launch_value_if_empty(qq.dg, mm.L.ctr, level_end, s2);
         });
         mf::launch_zero_act(mm.L.ctr, s2);
         if (rc == MF_OK) rc = push_round(g, qq, g->wlb, bounds, true);
@@ -921,31 +939,38 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     // from device memory), so by default the iteration is captured once
     // into a HIP graph and each later one is a single graph launch.
     bool finished = false;
+    bool exact = false;  // the loop ended right after a relabel: heights are BFS distances
     if (queue && g->pipeline && !g->prof_mask && !g->narrow_seed && g->last_depth > 0 &&
         g->last_depth < PIPELINE_DEPTH) {
         mf_status rc = ensure_snapshots(g);
         if (rc != MF_OK) return rc;
-        const int C = pipelined_chunk(g);
-        // the relabel init, C levels and the tail, on stream s3 (st, or the
-        // capture stream)
-        auto enqueue_iteration = [&](hipStream_t s3) -> mf_status {
+        mf::launch_set_i32(g->halt_d, 0, st);
+        // the relabel init, C levels, the tail and the halt test, on stream
+        // s3 (st, or the capture stream)
+        auto enqueue_iteration = [&](hipStream_t s3, int C) -> mf_status {
             LoopMode mm = m, qq = qm;
             mm.L.stream = qq.L.stream = s3;
             mf::launch_gr_init(mm.dg, mm.L.q[0], mm.L.ctr, mm.L.bits, mm.seed_deficits, s3);
             for (int lv = 0; lv < C; ++lv)
                 mf::launch_gr_level(mm.dg, lv, mm.L.q[lv & 1], mm.L.q[(lv + 1) & 1], mm.L.ctr, mm.L.bits, g->tune,
                                     g->gr_grid, mm.forward, s3);
-            return enqueue_tail(mm, qq, C);
+            mf_status r = enqueue_tail(mm, qq, C);
+            mf::launch_halt_if_done(mm.L.ctr, C, shortcut, g->halt_d, s3);
+            return r;
         };
-        hipGraphExec_t exec = g->graph_capture ? iteration_graph(g, m, qm, C, enqueue_iteration) : nullptr;
         hipError_t queue_err = hipSuccess;
         auto queue_iteration = [&](int slot) -> int {
+            // the first chunk covers the last relabel's depth
+            const int C = std::min(64, std::max(g->first_chunk, g->last_depth + 1));
+            hipGraphExec_t exec = nullptr;
+            if (g->graph_capture)
+                exec = iteration_graph(g, m, qm, C, [&](hipStream_t s3) { return enqueue_iteration(s3, C); });
             count_epochs(g, st, 1);
             hipError_t e = hipSuccess;
             if (exec) {
                 e = hipGraphLaunch(exec, st);
             } else {
-                mf_status r2 = enqueue_iteration(st);
+                mf_status r2 = enqueue_iteration(st, C);
                 if (tail_rc == MF_OK) tail_rc = r2;
             }
             if (e == hipSuccess)
@@ -974,10 +999,20 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
                 *value = (int64_t)c.e_t + (int64_t)c.deficit_sum;
                 *m.L.ctr_h = c;
                 finished = true;
+                exact = true;
+                break;
+            }
+            if (shortcut && c.wl[3] == 0) {  // the first round left no active vertex
+                *value = (int64_t)c.round_e_t + (int64_t)c.round_deficit;
+                *m.L.ctr_h = c;
+                finished = true;
+                ++iters;
+                rounds += 1;
                 break;
             }
             if (++iters > g->max_iter) {
                 g->last_iterations = iters;
+                mf::launch_set_i32(g->halt_d, 0, st);
                 return MF_ERR_NOT_CONVERGED;
             }
             rounds += 2;
@@ -985,10 +1020,13 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             k = 1 - k;
         }
         // leaving early: the iteration still queued runs to its end first
+        // (it may have ended the loop and set the halt word: cleared below)
         if (!finished) MF_HIP(hipStreamSynchronize(st));
+        // every later kernel runs again (queued behind the halted iteration)
+        mf::launch_set_i32(g->halt_d, 0, st);
     }
     while (!finished) {
-        bool queued = false;
+        bool queued = false, ended = false;
         int depth = 0;
         mf_status rc = relabel_and_worklist(g, m, &levels, &depth, queue ? &tail : nullptr, &queued);
         if (rc != MF_OK) return rc;
@@ -999,6 +1037,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         active_sum += active;
         if (active == 0) {
             *value = (int64_t)c.e_t + (int64_t)c.deficit_sum;
+            exact = true;
             break;
         }
         if (++iters > g->max_iter) {
@@ -1031,6 +1070,10 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             for (int b = 0; b < 3; ++b) {
                 cur[b] = g->wlb[b];
                 cnt[b] = c.wl[b];
+            }
+            if (c.wl[3] == 0 && shortcut) {  // the first round left no active vertex
+                *value = (int64_t)c.round_e_t + (int64_t)c.round_deficit;
+                break;
             }
             if (c.wl[3] == 0 || R <= 2) continue;  // certified by the next relabel
             active_sum += c.wl[3];
@@ -1079,7 +1122,21 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
                 if (g->trace_gr)
                     std::fprintf(stderr, "[loop]   round %lld active %d (rows by bin %d %d %d)\n", (long long)done,
                                  c.wl[3], c.wl[0], c.wl[1], c.wl[2]);
-                if (c.wl[3] == 0) break;  // certified by the next relabel
+                if (c.wl[3] == 0) {
+                    if (shortcut) {  // no active vertex after the last round: the value now
+                        if (rebuilt) {
+                            mf::launch_value_if_empty(m.dg, m.L.ctr, -1, st);
+                            MF_HIP(hipGetLastError());
+                            rc = read_lane(g, m.L);
+                            if (rc != MF_OK) return rc;
+                            *value = (int64_t)c.round_e_t + (int64_t)c.round_deficit;
+                        } else {
+                            *value = (int64_t)c.e_t + (int64_t)c.deficit_sum;  // the full build's
+                        }
+                        ended = true;
+                    }
+                    break;  // else certified by the next relabel
+                }
                 active_sum += c.wl[3];
                 cnt[0] = c.wl[0];
                 cnt[1] = c.wl[1];
@@ -1090,7 +1147,9 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             ++rounds;
             ++done;
         }
+        if (ended) break;
     }
+    if (shortcut) g->heights_exact = exact;
     if (m.L.main) {
         g->last_iterations = iters;
         g->last_levels = levels;
@@ -1178,13 +1237,26 @@ mf_status relayout(mf_graph* g) {
 mf_status push_pull_phase(mf_graph* g);
 
 // Algorithm 5 after the updates are on the device.
-mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value) {
+// The batch scratch one repair runs on: the handle's own buffers, or the
+// GPU's static array (allocation-free entry point).
+struct BatchScratch {
+    int32_t* slot_of;
+    int32_t* touched;
+    mf::BatchTable tb;
+};
+
+BatchScratch handle_scratch(mf_graph* g) { return BatchScratch{g->slot_of, g->touched, g->tb}; }
+
+// may_allocate false: rows without room for their inserts end the call with
+// MF_ERR_OUT_OF_MEMORY (nothing applied) instead of a relayout.
+mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value, const BatchScratch& bs,
+                          bool may_allocate) {
     hipStream_t st = g->stream;
     g->last_new_pairs = 0;
     for (int attempt = 0; attempt < 3; ++attempt) {
         mf::launch_clear_counters(g->ctr, st);
         timed(g, mf::KC_BATCH, [&] {
-            mf::launch_batch_locate(g->dg, d_upd, k, g->slot_of, g->win, g->tb, g->need, g->ctr, st);
+            mf::launch_batch_locate(g->dg, d_upd, k, bs.slot_of, g->win, bs.tb, g->need, g->ctr, st);
         });
         MF_HIP(hipGetLastError());
         mf_status rc = read_counters(g);
@@ -1193,10 +1265,11 @@ mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_
         if (c.err || c.cap_overflow || c.overflow) {
             if (c.overflow && !c.err && !c.cap_overflow) {
                 // need[] still holds the per-row demand: re-lay, then retry
-                rc = relayout(g);
+                if (may_allocate) rc = relayout(g);
+                else rc = MF_ERR_OUT_OF_MEMORY;
                 if (g->poisoned) return MF_ERR_DEVICE;
             }
-            mf::launch_batch_cleanup(g->tb, g->need, g->slot_of, g->win, k, st);
+            mf::launch_batch_cleanup(bs.tb, g->need, bs.slot_of, g->win, k, st);
             MF_HIP(hipGetLastError());
             MF_HIP(hipStreamSynchronize(st));
             if (rc != MF_OK) return rc;
@@ -1206,10 +1279,10 @@ mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_
         }
         g->last_new_pairs = c.new_pairs;
         timed(g, mf::KC_BATCH, [&] {
-            if (c.new_pairs) mf::launch_batch_insert(g->dg, g->tb, g->need, st);
-            mf::launch_batch_apply(g->dg, d_upd, k, g->slot_of, g->win, g->tb, g->touched, g->ctr, st);
-            mf::launch_batch_clamp(g->dg, d_upd, k, g->touched, g->win, g->tb, st);
-            mf::launch_batch_cleanup(g->tb, g->need, g->slot_of, g->win, k, st);
+            if (c.new_pairs) mf::launch_batch_insert(g->dg, bs.tb, g->need, st);
+            mf::launch_batch_apply(g->dg, d_upd, k, bs.slot_of, g->win, bs.tb, bs.touched, g->ctr, st);
+            mf::launch_batch_clamp(g->dg, d_upd, k, bs.touched, g->win, bs.tb, st);
+            mf::launch_batch_cleanup(bs.tb, g->need, bs.slot_of, g->win, k, st);
         });
         g->dg.used_slots += 2 * (int64_t)c.new_pairs;
         if (c.new_pairs) mf::launch_set_i64(g->nslots_d, g->dg.used_slots, st);
@@ -1448,9 +1521,12 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
     g->dg.root = t;
     g->dg.pinned = s;
     g->dg.used_slots = b.pairs;
-    if (dalloc(g, &g->nslots_d, 1) != hipSuccess) return fail(MF_ERR_OUT_OF_MEMORY);
+    if (dalloc(g, &g->nslots_d, 2) != hipSuccess) return fail(MF_ERR_OUT_OF_MEMORY);
     g->dg.nslots = g->nslots_d;
+    g->halt_d = reinterpret_cast<int32_t*>(g->nslots_d + 1);
+    g->dg.halt = g->halt_d;
     mf::launch_set_i64(g->nslots_d, g->dg.used_slots, g->stream);
+    mf::launch_set_i32(g->halt_d, 0, g->stream);
     if (dalloc(g, &g->dg.e, n) != hipSuccess || dalloc(g, &g->dg.h, n) != hipSuccess ||
         dalloc(g, &g->wl[0], n) != hipSuccess || dalloc(g, &g->wl[1], n) != hipSuccess ||
         dalloc(g, &g->wl[2], n) != hipSuccess || dalloc(g, &g->ctr, 1) != hipSuccess ||
@@ -1509,6 +1585,21 @@ mf_status mf_maxflow(mf_graph* g, int64_t* value) {
     return MF_OK;
 }
 
+// After a repair: errors found before anything changed (invalid updates,
+// capacity overflow, rows the slack could not be made to fit) leave the last
+// solve standing.
+static mf_status finish_apply(mf_graph* g, mf_status rc, int64_t v, int64_t* value) {
+    if (rc == MF_ERR_INVALID || rc == MF_ERR_OVERFLOW || rc == MF_ERR_OUT_OF_MEMORY) {
+        g->solved = true;  // nothing was applied
+        return rc;
+    }
+    if (rc != MF_OK) return rc;
+    g->solved = true;
+    g->last_value = v;
+    *value = v;
+    return MF_OK;
+}
+
 static mf_status apply_common(mf_graph* g, const mf_update* upd, int64_t k, int64_t* value, bool on_device) {
     mf_status rc = check_handle(g);
     if (rc != MF_OK) return rc;
@@ -1530,18 +1621,10 @@ static mf_status apply_common(mf_graph* g, const mf_update* upd, int64_t k, int6
     }
     g->solved = false;
     int64_t v = 0;
-    rc = apply_batch_dev(g, d_upd, k, &v);
+    rc = apply_batch_dev(g, d_upd, k, &v, handle_scratch(g), true);
     settle_events(g);
     fold_bytes(g);
-    if (rc == MF_ERR_INVALID || rc == MF_ERR_OVERFLOW) {
-        g->solved = true;  // nothing was applied
-        return rc;
-    }
-    if (rc != MF_OK) return rc;
-    g->solved = true;
-    g->last_value = v;
-    *value = v;
-    return MF_OK;
+    return finish_apply(g, rc, v, value);
 }
 
 mf_status mf_apply_batch(mf_graph* g, const mf_update* upd, int64_t k, int64_t* value) {
@@ -1558,6 +1641,18 @@ mf_status mf_min_cut(mf_graph* g, uint8_t* source_side, int64_t* cut_capacity) {
     if (!cut_capacity) return MF_ERR_INVALID;
     if (!g->solved) return MF_ERR_STATE;
     hipStream_t st = g->stream;
+    if (!g->heights_exact) {
+        // the solve ended after a round (valid heights, not distances): the
+        // cut of Sections 3.1 / 4.3 is read from a fresh relabel of the same
+        // residual graph, which the solve would have ended with
+        int64_t levels = 0;
+        int depth = 0;
+        LoopMode m = solve_mode(g);
+        m.topology = false;
+        rc = global_relabel(g, m, &levels, &depth);
+        if (rc != MF_OK) return rc;
+        g->heights_exact = true;
+    }
     mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->cut_acc), 0, 2, st);
     mf::launch_cut(g->dg, g->side, g->cut_acc, st);
     MF_HIP(hipGetLastError());
@@ -1785,6 +1880,10 @@ mf_status mf_graph_restore(mf_graph* g) {
     MF_HIP(hipGetLastError());
     MF_HIP(hipStreamSynchronize(st));
     g->offloaded = false;
+    // the loop's buffers too, so that a repair right after (the allocation-
+    // free one included) finds them; if they cannot be had now, the next
+    // allocating call takes them
+    if (g->solved) (void)prepare_loop(g);
     return MF_OK;
 }
 

@@ -244,6 +244,7 @@ mf_status upload_views(mf_batch* b) {
         g.h = b->h + b->vbase[i];
         g.used_slots = b->used[(size_t)i];
         g.nslots = nullptr;  // the batched kernels keep used_slots in the device-resident view
+        g.halt = nullptr;
         g.bytes_part = b->bytes_part;
         g.count_bytes = 0;
         g.bin0_max = b->bin0;

@@ -69,6 +69,10 @@ __device__ __forceinline__ void add_bytes(const DevGraph& g, int cls, unsigned l
         atomicAdd(&g.bytes_part[cls * BYTES_SLOTS + (blockIdx.x % BYTES_SLOTS)], b);
 }
 
+// A pipelined iteration queued behind the one that ended the loop finds the
+// halt word set and leaves every kernel at once.
+__device__ __forceinline__ bool halted(const DevGraph& g) { return g.halt && *g.halt; }
+
 // ---- wave primitives ------------------------------------------------------
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -299,7 +303,24 @@ __global__ void k_zero_counts(DevCounters* ctr, int wl, int act, int32_t* bump) 
         ctr->wl[threadIdx.x] = 0;
     }
     if (act && threadIdx.x == 0) ctr->act = 0;
+    if (wl && threadIdx.x == 0) ctr->round_deficit = 0;
     if (bump && threadIdx.x == 0) *bump += 1;  // a fresh epoch for the next-worklist marks
+}
+
+// End of a pipelined iteration queued behind BFS levels 0..level_end-1: if
+// its BFS ended there and its relabel's worklist (set aside in wl_in by the
+// next-worklist build) was empty -- or, after_round, the worklist of its
+// second round, the active set after the first -- the loop is over and every
+// kernel of the iteration queued behind this one leaves at once.  The same
+// test the host makes on the iteration's counters.
+__global__ void k_halt_if_done(const DevCounters* ctr, int level_end, int after_round, int32_t* halt) {
+    if (threadIdx.x == 0 && (ctr->front[level_end % 3] & 0xFFFFFFFFull) == 0 &&
+        (after_round ? ctr->wl[3] : ctr->wl_in[3]) == 0)
+        *halt = 1;
+}
+
+__global__ void k_set_i32(int32_t* p, int32_t value) {
+    if (threadIdx.x == 0) *p = value;
 }
 
 __global__ void k_set_i64(long long* p, long long value) {
@@ -451,6 +472,7 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
 
 __global__ void __launch_bounds__(256) k_gr_init(DevGraph g, int2* q0, DevCounters* ctr, GrBits bits,
                                                  int seed_deficits) {
+    if (halted(g)) return;
     gr_init_body<true>(hw_par(), g, q0, ctr, bits, seed_deficits, KC_GRS);
 }
 
@@ -816,6 +838,7 @@ constexpr int GRL_BLOCK_LDS = 1024;
 template <bool FWD, int BS>
 __global__ void __launch_bounds__(BS) k_gr_level(DevGraph g, int lv, const int2* qin, int2* qout,
                                                  DevCounters* ctr, GrBits bits, GrTune tune) {
+    if (halted(g)) return;
     extern __shared__ unsigned s_dyn[];
     gr_level_step<FWD, BS>(hw_par(), g, lv, qin, qout, ctr, bits, tune, tune.lds ? s_dyn : nullptr);
 }
@@ -1021,6 +1044,7 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
 __global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0, int32_t* wl1,
                                                         int32_t* wl2, DevCounters* ctr,
                                                         int topology, int sign, int guard_level) {
+    if (halted(g)) return;
     // The first round's activations start here -- also when the build is
     // skipped below, so that nothing queued behind it finds work: neither
     // the rounds (worklist sizes zero) nor the next-worklist build after the
@@ -1354,6 +1378,7 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
 template <bool PULL>
 __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t* wl, int count,
                                                        int kc, DevCounters* ctr, const int32_t* dcount) {
+    if (halted(g)) return;
     (void)ctr;
     const int cnt = dcount ? *dcount : count;
     unsigned long long bytes = 0;
@@ -1380,6 +1405,7 @@ constexpr int PR_SMALL_BLOCK = 256;
 template <bool PULL>
 __global__ void __launch_bounds__(PR_SMALL_BLOCK) k_pr_small(DevGraph g, const int32_t* wl0, const int32_t* wl1,
                                                              int c0, int c1, int kc, const int32_t* dcount) {
+    if (halted(g)) return;
     constexpr int BS = PR_SMALL_BLOCK, WPB = BS / WAVE;
     const BinSizes c = bin_sizes(dcount, c0, c1, 0);
     const int nb1 = (c.c1 + WPB - 1) / WPB, nb0 = (c.c0 + BS - 1) / BS;
@@ -1456,6 +1482,7 @@ __global__ void __launch_bounds__(256) k_rie_round(DevGraph g, const int32_t* wl
                                                    DevCounters* ctr, const int32_t* dcount) {
     (void)ctr;
     constexpr int BS = 256, WPB = BS / WAVE;
+    if (halted(g)) return;
     const BinSizes c = bin_sizes(dcount, c0, c1, c2);
     const int nb2 = c.c2, nb1 = (c.c1 + WPB - 1) / WPB, nb0 = (c.c0 + BS - 1) / BS;
     const int total = nb2 + nb1 + nb0;
@@ -1805,8 +1832,10 @@ __device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
             }
             rounds_left = depth / S.round_div > 1 ? depth / S.round_div : 1;
         } else if (!sweep && active == 0) {
-            rounds_left = 0;  // the next relabel certifies (or finds more work)
-            continue;
+            // a round after a relabel left no active vertex: its push-relabel
+            // and remove-invalid-edges kept the labelling valid, so no vertex
+            // with excess can reach t or a deficit, and s_val is the value
+            break;
         }
         sweep = false;
         if (rounds_left > 0) --rounds_left;
@@ -2044,6 +2073,7 @@ __global__ void __launch_bounds__(256) k_next_worklist(DevGraph g, const int32_t
                                                        const int32_t* in2, int c0, int c1, int c2, int32_t* out0,
                                                        int32_t* out1, int32_t* out2, int32_t* mark,
                                                        const int32_t* epoch_p, DevCounters* ctr) {
+    if (halted(g)) return;
     const int32_t epoch = *epoch_p;
     if (c0 < 0) {  // the input lists' sizes on the device (set aside by k_zero_counts)
         c0 = ctr->wl_in[0];
@@ -2076,6 +2106,25 @@ __global__ void __launch_bounds__(256) k_next_worklist(DevGraph g, const int32_t
         unsigned long long m = __ballot(act);
         if (lane_id() == 0 && m) atomicAdd(&ctr->wl[3], (int)__popcll(m));
     }
+}
+
+// The value after a round that left no active vertex: the labelling is valid
+// after every push-relabel plus remove-invalid-edges round, so no vertex with
+// excess can reach t or a deficient vertex, and the value is e(t) plus the
+// deficits, as after a relabel (Algorithm 5's sum over the sinks).
+__global__ void __launch_bounds__(256) k_value_if_empty(DevGraph g, DevCounters* ctr, int guard_level) {
+    if (halted(g)) return;
+    if (guard_level >= 0 && (ctr->front[guard_level % 3] & 0xFFFFFFFFull) != 0) return;
+    if (ctr->wl[3] != 0) return;
+    const int N = g.n;
+    long long deficit = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < N; v += gridDim.x * blockDim.x) {
+        const int64_t ev = g.e[v];
+        if (v != g.s && v != g.t && ev < 0) deficit += ev;
+        if (v == g.t) ctr->round_e_t = ev;
+    }
+    const long long tot = block_sum_i64<256>(deficit);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)&ctr->round_deficit, (unsigned long long)tot);
 }
 
 // ---- relayout: rows with room for their pending inserts ---------------------
@@ -2548,8 +2597,20 @@ void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const i
                                                               out2, mark, epoch, ctr);
 }
 
+void launch_value_if_empty(const DevGraph& g, DevCounters* ctr, int guard_level, hipStream_t st) {
+    k_value_if_empty<<<grid_for(g.n, 256, 2048), 256, 0, st>>>(g, ctr, guard_level);
+}
+
 void launch_zero_act(DevCounters* ctr, hipStream_t st) {
     k_zero_counts<<<1, 64, 0, st>>>(ctr, 0, 1, nullptr);
+}
+
+void launch_halt_if_done(const DevCounters* ctr, int level_end, bool after_round, int32_t* halt, hipStream_t st) {
+    k_halt_if_done<<<1, 64, 0, st>>>(ctr, level_end, after_round ? 1 : 0, halt);
+}
+
+void launch_set_i32(int32_t* p, int32_t value, hipStream_t st) {
+    k_set_i32<<<1, 64, 0, st>>>(p, value);
 }
 
 void launch_set_i64(long long* p, long long value, hipStream_t st) {

@@ -45,6 +45,8 @@ struct DevGraph {
     int32_t act_cap;                     // pass act_cap: the extra ones are dropped)
     unsigned* relab;                     // not null: push-relabel sets bit u when it raises h(u); the
                                          // worklist build clears it; remove-invalid-edges skips unset rows
+    const int32_t* halt;                 // not null and set: the single-graph loop kernels leave at once
+                                         // (a pipelined iteration queued behind the loop's last one)
 };
 
 // Partial sums of algorithmic bytes: a kernel block adds into slot
@@ -75,6 +77,8 @@ struct DevCounters {
     int32_t act_pad;
     unsigned long long seed_front;  // the last relabel's level-0 frontier (front[] format)
     int32_t wl_in[4];          // worklist sizes as the last next-worklist build found them (its input)
+    long long round_e_t;       // value terms after a round whose next worklist came out empty:
+    long long round_deficit;   // e(t) and the sum of negative excess outside {s,t}
 };
 
 // KC_GR: multi-block BFS level launches; KC_GRS: the relabel's seeding and its
@@ -310,7 +314,15 @@ void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const i
                           int32_t* out1, int32_t* out2, int32_t* mark, int32_t* epoch, DevCounters* ctr,
                           hipStream_t st);
 void launch_set_i64(long long* p, long long value, hipStream_t st);
+void launch_set_i32(int32_t* p, int32_t value, hipStream_t st);
+// sets *halt when the iteration queued behind levels 0..level_end-1 ended the loop
+// (after_round: when its first round left no active vertex)
+void launch_halt_if_done(const DevCounters* ctr, int level_end, bool after_round, int32_t* halt, hipStream_t st);
 void launch_zero_act(DevCounters* ctr, hipStream_t st);
+// After a next-worklist build that found no active vertex (and, guard_level
+// >= 0, a BFS that ended before guard_level): the value terms of the state,
+// into round_e_t and round_deficit (zeroed by that build).  Otherwise nothing.
+void launch_value_if_empty(const DevGraph& g, DevCounters* ctr, int guard_level, hipStream_t st);
 // sizes, their scan into start[] and the rows to sort; then the caller reads
 // start[V] (the new slot count) and *sort_count
 void launch_relayout_plan(const RelayoutPlan& p, hipStream_t st);

@@ -114,6 +114,24 @@ def busy_split(rows, a, b):
     return (max(e for _, e in iv) - iv[0][0]) / 1e3, busy / 1e3
 
 
+def gap_table(rows, a, b, top=12, min_us=1.0):
+    """Where the device idles in dispatches a..b-1: every gap of at least
+    min_us between the end of the work so far and the next dispatch's start,
+    grouped by (kernel before, kernel after)."""
+    iv = sorted(((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(_name(r))) for r in rows[a:b]))
+    agg = {}
+    end, prev = None, None
+    for s, e, k in iv:
+        if end is not None and s - end >= min_us * 1e3:
+            agg.setdefault((prev, k), []).append((s - end) / 1e3)
+        if end is None or e > end:
+            end, prev = e, k
+    out = ["| before | after | gaps | idle ms | avg us |", "|---|---|---:|---:|---:|"]
+    for (p, k), d in sorted(agg.items(), key=lambda x: -sum(x[1]))[:top]:
+        out.append(f"| `{p[:40]}` | `{k[:40]}` | {len(d)} | {sum(d) / 1e3:.3f} | {np.mean(d):.1f} |")
+    return "\n".join(out)
+
+
 def counter_pass(path, kernel):
     """(counter name, calibration factor, mean KiB per dispatch of `kernel`
     in the timed window, dispatches)."""
@@ -160,6 +178,8 @@ def main():
             print(f"Window: {wall / 1e3:.3f} ms from the first dispatch to the last, kernels busy "
                   f"{busy / 1e3:.3f} ms ({100 * busy / wall:.1f}%); the rest is the device waiting on "
                   f"host launches and synchronisations.\n")
+            print("Idle gaps in the window by the kernels around them:\n")
+            print(gap_table(kt, a, b) + "\n")
     if not args.fetch_dir:
         return
     total = 0.0

@@ -511,7 +511,7 @@ def _flow_cert(G, n, s, t, value, model):
     assert rc == 0, msg
 
 
-@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64", "rmat16", "grid256"])
 def test_get_flow_is_a_max_flow(name):
     g, stream, k, nb = gen.workload(name)
     model = _CapModel(g.n, g.src, g.dst, g.cap)
@@ -563,7 +563,7 @@ def test_rmat20_full_size():
         assert got == want
         side, cut = G.min_cut()
         _cut_ok(g.n, g.s, g.t, side, cut, got, g.src, g.dst, g.cap)
-        for b in range(3):
+        for b in range(10):
             u, v, c = stream.next_batch(k)
             say("rmat20 batch", b)
             got = G.apply_batch(u, v, c)
