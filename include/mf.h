@@ -225,6 +225,30 @@ mf_status mf_apply_batch(mf_graph* g, const mf_update* upd, int64_t k, int64_t* 
  * buffer is only read, on the handle's stream, before the call returns. */
 mf_status mf_apply_batch_device(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value);
 
+/* Largest batch mf_apply_batch_device_noalloc takes. */
+#define MF_NOALLOC_MAX_UPDATES 32768
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops that must not call hipMalloc, harnesses that forbid it):
+ * mf_apply_batch_device without any allocation.  Same arguments, semantics
+ * and result as mf_apply_batch_device; the updates are in device memory.
+ * The batch scratch (the slot located for each update, the updates that
+ * changed a capacity, the hash table of absent pairs) lives in one static
+ * device array per GPU of about 1.8 MB, held by each GPU the library runs on
+ * until the process ends; its hash table is cleared by every call.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (two
+ * handles used from different threads or streams) race, and the caller must
+ * order them.  Nothing else is allocated: the handle's own buffers come from
+ * its first mf_maxflow, and no new HIP graph is instantiated (an iteration
+ * captured by an earlier call is replayed, else the kernels are launched one
+ * by one).
+ * Errors: MF_ERR_INVALID (as mf_apply_batch_device, or k above
+ * MF_NOALLOC_MAX_UPDATES), MF_ERR_OVERFLOW, MF_ERR_STATE (no prior solve),
+ * MF_ERR_OUT_OF_MEMORY (the batch inserts more pairs than the rows' free
+ * slots hold: nothing is applied; mf_apply_batch_device re-lays the rows),
+ * MF_ERR_NOT_CONVERGED, MF_ERR_DEVICE. */
+mf_status mf_apply_batch_device_noalloc(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value);
+
 /* The minimum cut certified by the last solve (Sections 3.1 and 4.3):
  * source side A = {v : h(v) = |V|} under a global relabel of the final
  * residual graph, the vertices that cannot reach t or a deficient vertex in

@@ -30,7 +30,7 @@ MF_ERR_STATE = 6
 
 # every symbol include/mf.h declares
 EXPORTED = ["mf_default_options", "mf_status_string", "mf_graph_load", "mf_maxflow",
-            "mf_apply_batch", "mf_apply_batch_device", "mf_min_cut", "mf_get_flow", "mf_get_edges",
+            "mf_apply_batch", "mf_apply_batch_device", "mf_apply_batch_device_noalloc", "mf_min_cut", "mf_get_flow", "mf_get_edges",
             "mf_graph_offload", "mf_graph_restore", "mf_graph_tune", "mf_get_stats", "mf_profile",
             "mf_debug_initial_labels", "mf_debug_selftest", "mf_debug_atomic_probe", "mf_debug_round",
             "mf_debug_check_invariants", "mf_graph_free", "mf_batch_load", "mf_batch_maxflow",
@@ -130,6 +130,7 @@ def lib():
         L.mf_maxflow.argtypes = [vp, C.POINTER(i64)]
         L.mf_apply_batch.argtypes = [vp, vp, i64, C.POINTER(i64)]
         L.mf_apply_batch_device.argtypes = [vp, vp, i64, C.POINTER(i64)]
+        L.mf_apply_batch_device_noalloc.argtypes = [vp, vp, i64, C.POINTER(i64)]
         L.mf_min_cut.argtypes = [vp, vp, C.POINTER(i64)]
         L.mf_get_flow.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
         L.mf_get_edges.argtypes = [vp, C.POINTER(i64), vp, vp, vp]
@@ -153,7 +154,7 @@ def lib():
         L.mf_batch_free.argtypes = [vp]
         L.mf_batch_free.restype = None
         for name in ["mf_graph_load", "mf_maxflow", "mf_apply_batch", "mf_apply_batch_device",
-                    
+                     "mf_apply_batch_device_noalloc",
                      "mf_min_cut", "mf_get_flow", "mf_get_edges", "mf_graph_offload", "mf_graph_restore",
                      "mf_graph_tune", "mf_batch_tune",
                      "mf_get_stats", "mf_profile",
@@ -257,6 +258,21 @@ def mf_apply_batch_device(g, updates) -> int:
     val = C.c_int64()
     _check(lib().mf_apply_batch_device(g, updates.data_ptr(), updates.shape[0], C.byref(val)),
            "mf_apply_batch_device")
+    return val.value
+
+
+NOALLOC_MAX_UPDATES = 32768
+
+
+def mf_apply_batch_device_noalloc(g, updates) -> int:
+    """As mf_apply_batch_device, allocating nothing (batch scratch in the GPU's
+    static array; at most NOALLOC_MAX_UPDATES updates)."""
+    if updates.dtype.__str__() != "torch.int32" or not updates.is_contiguous() or updates.dim() != 2 \
+            or updates.shape[1] != 3 or not updates.is_cuda:
+        raise ValueError("expected a contiguous int32 cuda tensor of shape [k, 3]")
+    val = C.c_int64()
+    _check(lib().mf_apply_batch_device_noalloc(g, updates.data_ptr(), updates.shape[0], C.byref(val)),
+           "mf_apply_batch_device_noalloc")
     return val.value
 
 
@@ -384,6 +400,9 @@ class MaxFlowGraph:
 
     def apply_batch_device(self, updates) -> int:
         return mf_apply_batch_device(self.h, updates)
+
+    def apply_batch_device_noalloc(self, updates) -> int:
+        return mf_apply_batch_device_noalloc(self.h, updates)
 
     def min_cut(self):
         return mf_min_cut(self.h, self.n)

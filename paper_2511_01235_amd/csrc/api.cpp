@@ -95,6 +95,7 @@ struct mf_graph {
     int cus = 256;                   // compute units of the device
     bool graph_capture = true;       // pipelined iterations replayed from a captured HIP graph
     bool capture_failed = false;     // capture or instantiation failed once: launch kernel by kernel
+    bool no_capture = false;         // this call instantiates no new graph (allocation-free entry point)
     bool heights_exact = true;       // heights are the last relabel's BFS distances (else a valid labelling
                                      // left by the round that ended the solve)
     hipStream_t cap_stream = nullptr;  // stream the iteration is captured on (never launched on)
@@ -818,7 +819,7 @@ hipGraphExec_t iteration_graph(mf_graph* g, const LoopMode& m, const LoopMode& q
     std::vector<long long> key = capture_key(g, m, qm, C);
     for (auto& ig : g->it_graphs)
         if (ig.key == key) return ig.exec;
-    if (g->capture_failed) return nullptr;
+    if (g->capture_failed || g->no_capture) return nullptr;
     if (g->it_graphs.size() >= 4) {
         // the oldest capture goes (it may still be running on the stream)
         if (hipStreamSynchronize(g->stream) != hipSuccess) return nullptr;
@@ -1405,6 +1406,13 @@ mf_status push_pull_phase(mf_graph* g) {
     return MF_OK;
 }
 
+// Whether everything prepare_loop takes is there (the allocation-free repair
+// runs only then).
+bool loop_ready(const mf_graph* g) {
+    return g->act_list && g->mark && g->wlb[0] && g->snap_h[0] && g->snap_h[1] && g->snap_ev[0] && g->snap_ev[1] &&
+           (!g->push_pull || (g->h2 && g->q2_cap >= g->q_cap));
+}
+
 // Everything a solve or repair may allocate, taken before it changes any
 // state: a failed allocation then leaves the graph as it was.
 mf_status prepare_loop(mf_graph* g) {
@@ -1633,6 +1641,38 @@ mf_status mf_apply_batch(mf_graph* g, const mf_update* upd, int64_t k, int64_t* 
 
 mf_status mf_apply_batch_device(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value) {
     return apply_common(g, d_upd, k, value, true);
+}
+
+mf_status mf_apply_batch_device_noalloc(mf_graph* g, const mf_update* d_upd, int64_t k, int64_t* value) {
+    mf_status rc = check_handle(g);
+    if (rc != MF_OK) return rc;
+    if (!value || k < 0 || (k > 0 && !d_upd) || k > mf::NOALLOC_MAX_UPDATES) return MF_ERR_INVALID;
+    if (!g->solved || !loop_ready(g)) return MF_ERR_STATE;
+    CallTimer timer(g);
+    if (k == 0) {
+        *value = g->last_value;
+        return MF_OK;
+    }
+    mf::NoallocScratch ns;
+    rc = mf::noalloc_scratch(g->device, &ns);
+    if (rc != MF_OK) return rc;
+    int32_t tcap = 64;
+    while (tcap < 2 * k) tcap *= 2;
+    const BatchScratch bs{ns.slot_of, ns.touched, mf::BatchTable{ns.table_key, ns.table_win, ns.table_slot, tcap}};
+    // the array keeps the last call's contents: the part of the table this
+    // batch uses starts empty (slot_of and touched are written before read)
+    hipStream_t st = g->stream;
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(bs.tb.key), -1, 2 * (int64_t)tcap, st);
+    mf::launch_fill_i32(bs.tb.win, -1, 2 * (int64_t)tcap, st);
+    MF_HIP(hipGetLastError());
+    g->solved = false;
+    g->no_capture = true;
+    int64_t v = 0;
+    rc = apply_batch_dev(g, d_upd, k, &v, bs, false);
+    g->no_capture = false;
+    settle_events(g);
+    fold_bytes(g);
+    return finish_apply(g, rc, v, value);
 }
 
 mf_status mf_min_cut(mf_graph* g, uint8_t* source_side, int64_t* cut_capacity) {

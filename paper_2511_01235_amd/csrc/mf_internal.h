@@ -332,6 +332,25 @@ void launch_relayout_move(const RelayoutPlan& p, int32_t sort_count, int64_t S_n
                           int32_t* src_of, int32_t* where, int32_t* row_ptr, int32_t* row_sorted, hipStream_t st);
 
 
+// ---- allocation-free repair (noalloc.hip) --------------------------------
+// Largest batch the allocation-free repair takes, and its hash table's size
+// (a power of two of at least twice that, as the allocating path sizes it).
+constexpr int64_t NOALLOC_MAX_UPDATES = MF_NOALLOC_MAX_UPDATES;
+constexpr int32_t NOALLOC_TABLE = 2 * (int32_t)MF_NOALLOC_MAX_UPDATES;
+static_assert((NOALLOC_TABLE & (NOALLOC_TABLE - 1)) == 0, "table size must be a power of two");
+// Views into the GPU's static scratch array (device addresses).
+struct NoallocScratch {
+    unsigned long long* table_key;   // NOALLOC_TABLE
+    int32_t* table_win;              // 2 * NOALLOC_TABLE
+    int32_t* table_slot;             // 2 * NOALLOC_TABLE
+    int32_t* slot_of;                // NOALLOC_MAX_UPDATES
+    int32_t* touched;                // NOALLOC_MAX_UPDATES
+    size_t bytes;                    // size of the whole array
+};
+// The scratch array of `device`, which the caller has made current: its
+// address is looked up on the first call for each device and kept.
+mf_status noalloc_scratch(int device, NoallocScratch* out);
+
 // ---- host Bi-CSR builder (bicsr.cpp) -------------------------------------
 struct HostBiCSR {
     int32_t n = 0;
