@@ -236,9 +236,10 @@ def main():
     assert scratch_val == (values_dev if n_dev else values[-1]), (scratch_val, values[-1])
     scratch_med = float(np.median(scratch_ms))
     if n_roof:
-        # the relabel's level kernel, timed with HIP events on the library's
-        # stream over further batches of the same stream
-        G.profile(1 << 0)
+        # every kernel class timed with HIP events on the library's stream
+        # (the relabel's level kernel is the roofline's) over further batches
+        # of the same stream
+        G.profile(0xFF)
         torch.cuda.synchronize()
         a = time.perf_counter()
         for i in range(total + n_dev, total + n_dev + n_roof):
@@ -275,7 +276,13 @@ def main():
                 "share_of_step": round(kms / roof_elapsed_ms, 4) if roof_elapsed_ms > 0 else None,
                 "timed_over": "every batch of the timed region" if not n_roof else
                               f"{n_roof} batches after the timed region (per-launch events)",
-                "copy_probe_gbs": round(copy_gbs, 1), "atomic_probe": atomic_rates}
+                "copy_probe_gbs": round(copy_gbs, 1), "atomic_probe": atomic_rates,
+                "classes": {c: {"launches": prof["kernel_launches"][c],
+                                "avg_launch_us": round(prof["kernel_ms"][c] * 1e3 / prof["kernel_launches"][c], 3),
+                                "alg_bytes_per_launch": round(prof["kernel_bytes"][c] / prof["kernel_launches"][c], 1),
+                                "achieved_gbs": round(prof["kernel_bytes"][c] / (prof["kernel_ms"][c] * 1e-3) / 1e9, 2)
+                                if prof["kernel_ms"][c] > 0 else None}
+                            for c in prof["kernel_launches"] if prof["kernel_launches"][c]}}
 
     cpu = None
     if not args.no_cpu:

@@ -129,8 +129,10 @@ typedef struct mf_options {
                                   per iteration instead of one) */
     int32_t pipeline;          /* -1: on shallow graphs the next iteration is not queued before
                                   the host reads the last one's counters */
-    int32_t graph_capture;     /* -1: pipelined iterations are launched kernel by kernel instead
-                                  of replayed from a HIP graph captured once per handle */
+    int32_t graph_capture;     /* 1: every pipelined iteration is one launch of a HIP graph
+                                  captured once per handle (and again when a relayout, restore
+                                  or tuning changes what it bakes in); 0 (default) or -1: its
+                                  kernels are launched one by one, which measured faster */
     int32_t trace;             /* 1: every BFS level (one per launch) and every round printed on
                                   stderr, for diagnosis; slow */
 } mf_options;

@@ -51,6 +51,7 @@ struct mf_graph {
     int32_t* slot_of = nullptr;
     int32_t* touched = nullptr;
     mf_update* upd = nullptr;
+    mf_update* upd_h = nullptr;      // pinned staging of host-memory batches (k_cap entries)
     int64_t k_cap = 0;
     mf::BatchTable tb{};
     uint8_t* side = nullptr;
@@ -93,7 +94,7 @@ struct mf_graph {
     std::atomic<bool> coop_broken{false};  // a cooperative launch failed: multi-block levels only
                                      // (set by either lane of a push-pull repair)
     int cus = 256;                   // compute units of the device
-    bool graph_capture = true;       // pipelined iterations replayed from a captured HIP graph
+    bool graph_capture = false;      // pipelined iterations replayed from a captured HIP graph
     bool capture_failed = false;     // capture or instantiation failed once: launch kernel by kernel
     bool no_capture = false;         // this call instantiates no new graph (allocation-free entry point)
     bool heights_exact = true;       // heights are the last relabel's BFS distances (else a valid labelling
@@ -297,6 +298,8 @@ void free_all(mf_graph* g) {
     dfree(g, g->slot_of);
     dfree(g, g->touched);
     dfree(g, g->upd);
+    if (g->upd_h) (void)hipHostFree(g->upd_h);
+    g->upd_h = nullptr;
     dfree(g, g->tb.key);
     dfree(g, g->tb.win);
     dfree(g, g->tb.slot);
@@ -391,6 +394,8 @@ void free_device_state(mf_graph* g) {
     dfree(g, g->slot_of);
     dfree(g, g->touched);
     dfree(g, g->upd);
+    if (g->upd_h) (void)hipHostFree(g->upd_h);
+    g->upd_h = nullptr;
     dfree(g, g->tb.key);
     dfree(g, g->tb.win);
     dfree(g, g->tb.slot);
@@ -433,7 +438,7 @@ void apply_loop_options(mf_graph* g, const mf_options& o) {
     g->incremental_rounds = !on(o.round_scan, false);
     g->queue_rounds = on(o.queue_rounds, true);
     g->pipeline = on(o.pipeline, true);
-    g->graph_capture = on(o.graph_capture, true);
+    g->graph_capture = on(o.graph_capture, false);
     g->trace_gr = on(o.trace, false);
 }
 
@@ -452,6 +457,13 @@ mf_status ensure_batch_capacity(mf_graph* g, int64_t k) {
     dfree(g, g->tb.key);
     dfree(g, g->tb.win);
     dfree(g, g->tb.slot);
+    if (g->upd_h) (void)hipHostFree(g->upd_h);
+    g->upd_h = nullptr;
+    if (hipHostMalloc((void**)&g->upd_h, sizeof(mf_update) * (size_t)cap, hipHostMallocDefault) != hipSuccess) {
+        g->upd_h = nullptr;
+        g->k_cap = 0;
+        return MF_ERR_OUT_OF_MEMORY;
+    }
     if (dalloc(g, &g->slot_of, cap) != hipSuccess || dalloc(g, &g->touched, cap) != hipSuccess ||
         dalloc(g, &g->upd, cap) != hipSuccess || dalloc(g, &g->tb.key, tcap) != hipSuccess ||
         dalloc(g, &g->tb.win, 2 * (int64_t)tcap) != hipSuccess ||
@@ -811,16 +823,19 @@ std::vector<long long> capture_key(const mf_graph* g, const LoopMode& m, const L
 // The pipelined iteration of chunk C as an instantiated HIP graph: captured
 // on the handle's capture stream the first time, and again whenever
 // something it bakes in changed (a relayout, a restore, new tuning); the
-// last four captures are kept (chunks follow the BFS depth, which varies a
-// little).  nullptr when capture is unavailable: the caller launches the
-// kernels one by one.
+// last eight captures are kept (chunks follow the BFS depth, which varies a
+// little).  Consecutive iterations use two instantiations (`copy` 0 and 1),
+// so that queuing the next one never waits for the launch of the same
+// executable still in flight.  nullptr when capture is unavailable: the
+// caller launches the kernels one by one.
 template <class F>
-hipGraphExec_t iteration_graph(mf_graph* g, const LoopMode& m, const LoopMode& qm, int C, F&& enqueue) {
+hipGraphExec_t iteration_graph(mf_graph* g, const LoopMode& m, const LoopMode& qm, int C, int copy, F&& enqueue) {
     std::vector<long long> key = capture_key(g, m, qm, C);
+    key.push_back(copy);
     for (auto& ig : g->it_graphs)
         if (ig.key == key) return ig.exec;
     if (g->capture_failed || g->no_capture) return nullptr;
-    if (g->it_graphs.size() >= 4) {
+    if (g->it_graphs.size() >= 8) {
         // the oldest capture goes (it may still be running on the stream)
         if (hipStreamSynchronize(g->stream) != hipSuccess) return nullptr;
         (void)hipGraphExecDestroy(g->it_graphs.front().exec);
@@ -869,13 +884,16 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     // The active set after a push-relabel plus remove-invalid-edges round is
     // taken under a valid labelling (the rounds keep h(u) <= h(v) + 1 on every
     // residual slot, Section 3.1; remove-invalid-edges repairs what races
-    // broke): a vertex at |V| then cannot reach t or a deficient vertex (its
-    // height would have to fall by |V| along a simple path), so an empty
-    // active set ends the loop there, without another relabel, with the same
-    // value (the sinks' excess sum).  This is Algorithm 1's test after its
-    // kernels.  Heights are then valid but not exact distances: the cut is
-    // read after a fresh relabel (mf_min_cut).  Only the solve itself (sinks
-    // t and the deficits, remove-invalid-edges on) ends this way.
+    // broke).  While every sink -- t and each deficient vertex -- is at height
+    // 0, a vertex at |V| cannot reach one (its height would have to fall by
+    // |V| along a simple path), so an empty active set ends the loop there,
+    // without another relabel, with the same value (the sinks' excess sum).
+    // This is Algorithm 1's test after its kernels.  A vertex that remove-
+    // invalid-edges made deficient sits at its own height: then the next
+    // relabel decides, as before.  Heights at such an end are valid but not
+    // exact distances: the cut is read after a fresh relabel (mf_min_cut).
+    // Only the solve itself (sinks t and the deficits, remove-invalid-edges
+    // on) ends this way.
     // (With push-pull the next repair reads the last cut from the heights:
     // those solves end after a relabel.)
     const bool shortcut =
@@ -965,7 +983,8 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             const int C = std::min(64, std::max(g->first_chunk, g->last_depth + 1));
             hipGraphExec_t exec = nullptr;
             if (g->graph_capture)
-                exec = iteration_graph(g, m, qm, C, [&](hipStream_t s3) { return enqueue_iteration(s3, C); });
+                exec = iteration_graph(g, m, qm, C, slot,
+                                       [&](hipStream_t s3) { return enqueue_iteration(s3, C); });
             count_epochs(g, st, 1);
             hipError_t e = hipSuccess;
             if (exec) {
@@ -1003,7 +1022,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
                 exact = true;
                 break;
             }
-            if (shortcut && c.wl[3] == 0) {  // the first round left no active vertex
+            if (shortcut && c.wl[3] == 0 && c.round_raised == 0) {  // the first round left no active vertex
                 *value = (int64_t)c.round_e_t + (int64_t)c.round_deficit;
                 *m.L.ctr_h = c;
                 finished = true;
@@ -1072,7 +1091,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
                 cur[b] = g->wlb[b];
                 cnt[b] = c.wl[b];
             }
-            if (c.wl[3] == 0 && shortcut) {  // the first round left no active vertex
+            if (c.wl[3] == 0 && shortcut && c.round_raised == 0) {  // the first round left no active vertex
                 *value = (int64_t)c.round_e_t + (int64_t)c.round_deficit;
                 break;
             }
@@ -1125,16 +1144,15 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
                                  c.wl[3], c.wl[0], c.wl[1], c.wl[2]);
                 if (c.wl[3] == 0) {
                     if (shortcut) {  // no active vertex after the last round: the value now
-                        if (rebuilt) {
-                            mf::launch_value_if_empty(m.dg, m.L.ctr, -1, st);
-                            MF_HIP(hipGetLastError());
-                            rc = read_lane(g, m.L);
-                            if (rc != MF_OK) return rc;
+                        if (!rebuilt) mf::launch_round_terms_clear(m.L.ctr, st);  // (the full build's)
+                        mf::launch_value_if_empty(m.dg, m.L.ctr, -1, st);
+                        MF_HIP(hipGetLastError());
+                        rc = read_lane(g, m.L);
+                        if (rc != MF_OK) return rc;
+                        if (c.round_raised == 0) {  // every sink still at height 0
                             *value = (int64_t)c.round_e_t + (int64_t)c.round_deficit;
-                        } else {
-                            *value = (int64_t)c.e_t + (int64_t)c.deficit_sum;  // the full build's
+                            ended = true;
                         }
-                        ended = true;
                     }
                     break;  // else certified by the next relabel
                 }
@@ -1624,7 +1642,11 @@ static mf_status apply_common(mf_graph* g, const mf_update* upd, int64_t k, int6
     if (rc != MF_OK) return rc;
     const mf_update* d_upd = upd;
     if (!on_device) {
-        MF_HIP(hipMemcpyAsync(g->upd, upd, sizeof(mf_update) * (size_t)k, hipMemcpyHostToDevice, g->stream));
+        // through pinned staging, so that the copy is a plain asynchronous DMA
+        // queued behind the work still on the stream (the last call's copy out
+        // of the staging buffer finished before that call returned)
+        std::memcpy(g->upd_h, upd, sizeof(mf_update) * (size_t)k);
+        MF_HIP(hipMemcpyAsync(g->upd, g->upd_h, sizeof(mf_update) * (size_t)k, hipMemcpyHostToDevice, g->stream));
         d_upd = g->upd;
     }
     g->solved = false;

@@ -303,19 +303,23 @@ __global__ void k_zero_counts(DevCounters* ctr, int wl, int act, int32_t* bump) 
         ctr->wl[threadIdx.x] = 0;
     }
     if (act && threadIdx.x == 0) ctr->act = 0;
-    if (wl && threadIdx.x == 0) ctr->round_deficit = 0;
+    if (wl && threadIdx.x == 0) {
+        ctr->round_deficit = 0;
+        ctr->round_raised = 0;
+    }
     if (bump && threadIdx.x == 0) *bump += 1;  // a fresh epoch for the next-worklist marks
 }
 
 // End of a pipelined iteration queued behind BFS levels 0..level_end-1: if
 // its BFS ended there and its relabel's worklist (set aside in wl_in by the
 // next-worklist build) was empty -- or, after_round, the worklist of its
-// second round, the active set after the first -- the loop is over and every
+// second round, the active set after the first, with every sink at height 0
+// -- the loop is over and every
 // kernel of the iteration queued behind this one leaves at once.  The same
 // test the host makes on the iteration's counters.
 __global__ void k_halt_if_done(const DevCounters* ctr, int level_end, int after_round, int32_t* halt) {
     if (threadIdx.x == 0 && (ctr->front[level_end % 3] & 0xFFFFFFFFull) == 0 &&
-        (after_round ? ctr->wl[3] : ctr->wl_in[3]) == 0)
+        (ctr->wl_in[3] == 0 || (after_round && ctr->wl[3] == 0 && ctr->round_raised == 0)))
         *halt = 1;
 }
 
@@ -1833,9 +1837,21 @@ __device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
             rounds_left = depth / S.round_div > 1 ? depth / S.round_div : 1;
         } else if (!sweep && active == 0) {
             // a round after a relabel left no active vertex: its push-relabel
-            // and remove-invalid-edges kept the labelling valid, so no vertex
-            // with excess can reach t or a deficit, and s_val is the value
-            break;
+            // and remove-invalid-edges kept the labelling valid, so if every
+            // deficient vertex is still at height 0 no vertex with excess can
+            // reach t or a deficit and s_val is the value; else the next
+            // relabel decides
+            long long raised = 0;
+            for (int v = tid; v < N; v += BS)
+                raised += v != g.s && v != g.t && g.e[v] < 0 && g.h[v] != 0;
+            raised = block_sum_i64<BS>(raised);
+            if (tid == 0) s_cnt[0] = raised != 0;
+            __syncthreads();
+            const bool stop = s_cnt[0] == 0;
+            __syncthreads();
+            if (stop) break;
+            rounds_left = 0;
+            continue;
         }
         sweep = false;
         if (rounds_left > 0) --rounds_left;
@@ -2080,14 +2096,19 @@ __global__ void __launch_bounds__(256) k_next_worklist(DevGraph g, const int32_t
         c1 = ctr->wl_in[1];
         c2 = ctr->wl_in[2];
     }
+    // more activations than the list holds: some were dropped, so every
+    // vertex is examined instead (the result must be the exact active set: an
+    // empty one ends the loop)
+    const bool all = *g.act_cnt > g.act_cap;
     const int na = min(*g.act_cnt, g.act_cap);
-    const long long total = (long long)c0 + c1 + c2 + na;
+    const long long total = all ? (long long)g.n : (long long)c0 + c1 + c2 + na;
     for (long long base = (long long)blockIdx.x * blockDim.x; base < total;
          base += (long long)gridDim.x * blockDim.x) {
         const long long i = base + threadIdx.x;
         int v = -1;
         if (i < total) {
-            if (i < c0) v = in0[i];
+            if (all) v = (int)i;
+            else if (i < c0) v = in0[i];
             else if (i < (long long)c0 + c1) v = in1[i - c0];
             else if (i < (long long)c0 + c1 + c2) v = in2[i - c0 - c1];
             else v = g.act[i - c0 - c1 - c2];
@@ -2108,23 +2129,31 @@ __global__ void __launch_bounds__(256) k_next_worklist(DevGraph g, const int32_t
     }
 }
 
-// The value after a round that left no active vertex: the labelling is valid
-// after every push-relabel plus remove-invalid-edges round, so no vertex with
-// excess can reach t or a deficient vertex, and the value is e(t) plus the
-// deficits, as after a relabel (Algorithm 5's sum over the sinks).
+// The value after a round that left no active vertex.  The labelling is
+// valid after every push-relabel plus remove-invalid-edges round; if every
+// sink (t and each deficient vertex) is still at height 0 -- remove-invalid-
+// edges can make a vertex deficient at its own height, counted here in
+// round_raised -- then a vertex at |V| cannot reach a sink, no vertex with
+// excess is below |V|, and the value is e(t) plus the deficits, as after a
+// relabel (Algorithm 5's sum over the sinks).
 __global__ void __launch_bounds__(256) k_value_if_empty(DevGraph g, DevCounters* ctr, int guard_level) {
     if (halted(g)) return;
     if (guard_level >= 0 && (ctr->front[guard_level % 3] & 0xFFFFFFFFull) != 0) return;
     if (ctr->wl[3] != 0) return;
     const int N = g.n;
-    long long deficit = 0;
+    long long deficit = 0, raised = 0;
     for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < N; v += gridDim.x * blockDim.x) {
         const int64_t ev = g.e[v];
-        if (v != g.s && v != g.t && ev < 0) deficit += ev;
+        if (v != g.s && v != g.t && ev < 0) {
+            deficit += ev;
+            raised += g.h[v] != 0;
+        }
         if (v == g.t) ctr->round_e_t = ev;
     }
     const long long tot = block_sum_i64<256>(deficit);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)&ctr->round_deficit, (unsigned long long)tot);
+    const long long nr = block_sum_i64<256>(raised);
+    if (threadIdx.x == 0 && nr) atomicAdd(&ctr->round_raised, (int)nr);
 }
 
 // ---- relayout: rows with room for their pending inserts ---------------------
@@ -2599,6 +2628,10 @@ void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const i
 
 void launch_value_if_empty(const DevGraph& g, DevCounters* ctr, int guard_level, hipStream_t st) {
     k_value_if_empty<<<grid_for(g.n, 256, 2048), 256, 0, st>>>(g, ctr, guard_level);
+}
+
+void launch_round_terms_clear(DevCounters* ctr, hipStream_t st) {
+    k_zero_counts<<<1, 64, 0, st>>>(ctr, 1, 0, nullptr);
 }
 
 void launch_zero_act(DevCounters* ctr, hipStream_t st) {

@@ -79,6 +79,8 @@ struct DevCounters {
     int32_t wl_in[4];          // worklist sizes as the last next-worklist build found them (its input)
     long long round_e_t;       // value terms after a round whose next worklist came out empty:
     long long round_deficit;   // e(t) and the sum of negative excess outside {s,t}
+    int32_t round_raised;      // ... and the deficient vertices above height 0 (made by remove-invalid-
+    int32_t round_pad;         //     edges after the relabel); the loop may end there only if none
 };
 
 // KC_GR: multi-block BFS level launches; KC_GRS: the relabel's seeding and its
@@ -319,9 +321,12 @@ void launch_set_i32(int32_t* p, int32_t value, hipStream_t st);
 // (after_round: when its first round left no active vertex)
 void launch_halt_if_done(const DevCounters* ctr, int level_end, bool after_round, int32_t* halt, hipStream_t st);
 void launch_zero_act(DevCounters* ctr, hipStream_t st);
+// the round value terms to zero (as a next-worklist build leaves them)
+void launch_round_terms_clear(DevCounters* ctr, hipStream_t st);
 // After a next-worklist build that found no active vertex (and, guard_level
 // >= 0, a BFS that ended before guard_level): the value terms of the state,
-// into round_e_t and round_deficit (zeroed by that build).  Otherwise nothing.
+// into round_e_t and round_deficit, and the deficient vertices above height
+// 0 into round_raised (all zeroed by that build).  Otherwise nothing.
 void launch_value_if_empty(const DevGraph& g, DevCounters* ctr, int guard_level, hipStream_t st);
 // sizes, their scan into start[] and the rows to sort; then the caller reads
 // start[V] (the new slot count) and *sort_count

@@ -144,6 +144,59 @@ def counter_pass(path, kernel):
     return name, factor, float(np.mean(vals)) if vals else 0.0, len(vals)
 
 
+# the library's kernel classes (mf_stats index order) and, for each, the
+# kernels one class launch dispatches; the first is counted as the launch
+CLASS_KERNELS = {
+    "global_relabel": ["k_gr_level"],
+    "push_relabel": ["k_pr_small", "k_pr_block"],
+    "remove_invalid": ["k_rie_round"],
+}
+
+
+def counter_values(path, kernels):
+    """{kernel: (counter name, factor, [KiB per dispatch in the timed window])}."""
+    rows = _rows(path)
+    name = rows[0]["Counter_Name"]
+    a, b = timed_window(rows)
+    cal = rows[calibration_copy(rows)]
+    factor = (CAL_BYTES / 1024) / float(cal["Counter_Value"])
+    out = {}
+    for k in kernels:
+        out[k] = (name, factor, [float(r["Counter_Value"]) for r in rows[a:b] if short(_name(r)) == k or
+                                 short(_name(r)).startswith(k + "<")])
+    return out
+
+
+def traffic_table(fetch_dir, write_dir, kernels, classes):
+    """Per kernel: calibrated HBM bytes per dispatch; per class: bytes per
+    class launch against the algorithmic bytes the bench counted."""
+    f = counter_values(os.path.join(fetch_dir, "run_counter_collection.csv"), kernels)
+    w = counter_values(os.path.join(write_dir, "run_counter_collection.csv"), kernels)
+    lines = ["| kernel | dispatches | FETCH MB | WRITE MB | HBM MB per dispatch |", "|---|---:|---:|---:|---:|"]
+    per = {}
+    for k in kernels:
+        fv, wv = f[k][2], w[k][2]
+        if not fv or not wv:
+            continue
+        fm = np.mean(fv) * 1024 * f[k][1] / 1e6
+        wm = np.mean(wv) * 1024 * w[k][1] / 1e6
+        per[k] = (len(fv), fm + wm)
+        lines.append(f"| `{k}` | {len(fv)} | {fm:.3f} | {wm:.3f} | {fm + wm:.3f} |")
+    out = "\n".join(lines) + "\n"
+    if classes:
+        out += ("\n| class | HBM MB per class launch | algorithmic MB per launch | HBM / algorithmic |\n"
+                "|---|---:|---:|---:|\n")
+        for cls, ks in CLASS_KERNELS.items():
+            if cls not in classes or ks[0] not in per:
+                continue
+            launches = per[ks[0]][0]
+            total = sum(per[k][0] * per[k][1] for k in ks if k in per)
+            alg = classes[cls]["alg_bytes_per_launch"] / 1e6
+            hbm = total / launches
+            out += f"| {cls} | {hbm:.3f} | {alg:.3f} | {hbm / alg:.2f} |\n"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("kt_dir")
@@ -152,6 +205,9 @@ def main():
     ap.add_argument("--kernel", default="k_gr_level")
     ap.add_argument("--command", default="")
     ap.add_argument("--title", default="")
+    ap.add_argument("--kernels", default="",
+                    help="comma-separated kernels for a per-kernel traffic table (with --bench-json: per class)")
+    ap.add_argument("--bench-json", default="", help="file whose last line is the bench's JSON result")
     args = ap.parse_args()
     kt = _rows(os.path.join(args.kt_dir, "run_kernel_trace.csv"))
     print(f"# {args.title or args.kernel}\n")
@@ -182,6 +238,14 @@ def main():
             print(gap_table(kt, a, b) + "\n")
     if not args.fetch_dir:
         return
+    if args.kernels:
+        classes = None
+        if args.bench_json:
+            import json
+            last = [ln for ln in open(args.bench_json) if ln.startswith("{")][-1]
+            classes = json.loads(last)["roofline"].get("classes")
+        print("## HBM traffic of each kernel (counter passes, timed window)\n")
+        print(traffic_table(args.fetch_dir, args.write_dir, args.kernels.split(","), classes))
     total = 0.0
     lines = []
     for d in (args.fetch_dir, args.write_dir):
