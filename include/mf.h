@@ -135,6 +135,9 @@ typedef struct mf_options {
                                   kernels are launched one by one, which measured faster */
     int32_t trace;             /* 1: every BFS level (one per launch) and every round printed on
                                   stderr, for diagnosis; slow */
+    int32_t round_narrow;      /* rounds between relabels whose worklist holds at most this many
+                                  vertices (none above bin_wave_max slots) run in one workgroup,
+                                  many rounds per launch; 0: 2048, < 0: never */
 } mf_options;
 
 /* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its

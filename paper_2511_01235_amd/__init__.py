@@ -58,7 +58,8 @@ class Options(C.Structure):
         [(name, C.c_int32) for name in ("bfs_first_chunk", "bfs_narrow_slots", "bfs_medium_slots",
                                         "bfs_medium_blocks", "bfs_level_blocks", "bfs_bottom_up",
                                         "bfs_lds_bitmap", "bfs_stage_min", "round_min", "round_max",
-                                        "round_scan", "queue_rounds", "pipeline", "graph_capture", "trace")]
+                                        "round_scan", "queue_rounds", "pipeline", "graph_capture", "trace",
+                                        "round_narrow")]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -89,7 +90,7 @@ class TorchAllocator:
 # loop and relabel settings of a single-graph handle (0 = default; switches 1 on, -1 off)
 LOOP_FIELDS = ("bfs_first_chunk", "bfs_narrow_slots", "bfs_medium_slots", "bfs_medium_blocks",
                "bfs_level_blocks", "bfs_bottom_up", "bfs_lds_bitmap", "bfs_stage_min", "round_min",
-               "round_max", "round_scan", "queue_rounds", "pipeline", "graph_capture", "trace")
+               "round_max", "round_scan", "queue_rounds", "pipeline", "graph_capture", "trace", "round_narrow")
 # fields mf_graph_tune / mf_batch_tune apply to a live handle (mf_graph_tune also the loop fields)
 TUNING_FIELDS = ("kernel_cycles", "bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max",
                  "batch_block", "long_row_cycles", "max_iterations") + LOOP_FIELDS

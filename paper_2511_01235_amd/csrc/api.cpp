@@ -89,6 +89,7 @@ struct mf_graph {
     bool incremental_rounds = true;  // rounds take their worklist from the previous one plus activations
     int64_t narrow_max = 4096;       // BFS frontiers of up to this many slots run in one workgroup (0: never)
     int64_t medium_max = 65536;      // ... up to this many in one cooperative launch of a few workgroups
+    int32_t rn_limit = 2048;         // worklists of up to this many vertices run rounds in one workgroup
     int32_t medium_blocks = 32;      //     of this many 1024-thread blocks (0 where unsupported)
     bool coop_ok = false;            // the device supports cooperative launch
     std::atomic<bool> coop_broken{false};  // a cooperative launch failed: multi-block levels only
@@ -435,6 +436,7 @@ void apply_loop_options(mf_graph* g, const mf_options& o) {
     g->tune.lds = on(o.bfs_lds_bitmap, false) && mf::gr_level_lds_bytes(g->bits.nwords, g->device) > 0 ? 1 : 0;
     g->round_min = o.round_min > 0 ? o.round_min : 2;
     g->round_max = o.round_max > 0 ? o.round_max : 4096;
+    g->rn_limit = o.round_narrow < 0 ? 0 : o.round_narrow > 0 ? o.round_narrow : 2048;
     g->incremental_rounds = !on(o.round_scan, false);
     g->queue_rounds = on(o.queue_rounds, true);
     g->pipeline = on(o.pipeline, true);
@@ -1083,6 +1085,21 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             rm.dg.act_cap = g->n;
         }
         int64_t done = 0;  // rounds run on this relabel
+        // the last round left no active vertex (round terms cleared): the
+        // value, if every sink is still at height 0 (else the next relabel
+        // certifies)
+        auto end_after_round = [&]() -> mf_status {
+            if (!shortcut) return MF_OK;
+            mf::launch_value_if_empty(m.dg, m.L.ctr, -1, st);
+            MF_HIP(hipGetLastError());
+            mf_status r2 = read_lane(g, m.L);
+            if (r2 != MF_OK) return r2;
+            if (c.round_raised == 0) {
+                *value = (int64_t)c.round_e_t + (int64_t)c.round_deficit;
+                ended = true;
+            }
+            return MF_OK;
+        };
         if (queued) {
             // two rounds ran; the second one's worklist and activations are on the device
             done = 2;
@@ -1143,23 +1160,46 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
                     std::fprintf(stderr, "[loop]   round %lld active %d (rows by bin %d %d %d)\n", (long long)done,
                                  c.wl[3], c.wl[0], c.wl[1], c.wl[2]);
                 if (c.wl[3] == 0) {
-                    if (shortcut) {  // no active vertex after the last round: the value now
-                        if (!rebuilt) mf::launch_round_terms_clear(m.L.ctr, st);  // (the full build's)
-                        mf::launch_value_if_empty(m.dg, m.L.ctr, -1, st);
-                        MF_HIP(hipGetLastError());
-                        rc = read_lane(g, m.L);
-                        if (rc != MF_OK) return rc;
-                        if (c.round_raised == 0) {  // every sink still at height 0
-                            *value = (int64_t)c.round_e_t + (int64_t)c.round_deficit;
-                            ended = true;
-                        }
-                    }
+                    if (!rebuilt) mf::launch_round_terms_clear(m.L.ctr, st);  // (the full build's)
+                    rc = end_after_round();
+                    if (rc != MF_OK) return rc;
                     break;  // else certified by the next relabel
                 }
                 active_sum += c.wl[3];
                 cnt[0] = c.wl[0];
                 cnt[1] = c.wl[1];
                 cnt[2] = c.wl[2];
+            }
+            // a short list without workgroup-bin rows: rounds in one workgroup,
+            // many per launch, until the list grows or empties
+            if (incremental && g->rn_limit > 0 && cnt[2] == 0 && cnt[0] + cnt[1] <= g->rn_limit && R - done >= 4) {
+                int32_t* other[3];
+                for (int b = 0; b < 3; ++b) other[b] = cur[b] == m.L.wl[b] ? g->wlb[b] : m.L.wl[b];
+                const int most = (int)std::min<int64_t>(R - done, INT_MAX / 2);
+                count_epochs(g, st, most);
+                mf::launch_rounds_narrow(rm.dg, cur, other, g->mark, g->mark + g->n, m.L.ctr, kc_for_bin(g, 0), most,
+                                         g->rn_limit, st);
+                mf::launch_zero_act(m.L.ctr, st);  // the last round's activations are in the new list
+                MF_HIP(hipGetLastError());
+                rc = read_lane(g, m.L);
+                if (rc != MF_OK) return rc;
+                if (c.rn_rounds > 0) {
+                    if (c.rn_set)
+                        for (int b = 0; b < 3; ++b) cur[b] = other[b];
+                    done += c.rn_rounds;
+                    rounds += c.rn_rounds;
+                    if (c.wl[3] == 0) {
+                        mf::launch_round_terms_clear(m.L.ctr, st);
+                        rc = end_after_round();
+                        if (rc != MF_OK) return rc;
+                        break;
+                    }
+                    if (done >= R) break;
+                    active_sum += c.wl[3];
+                    cnt[0] = c.wl[0];
+                    cnt[1] = c.wl[1];
+                    cnt[2] = c.wl[2];
+                }
             }
             rc = push_round(g, rm, cur, cnt);
             if (rc != MF_OK) return rc;

@@ -2156,6 +2156,102 @@ __global__ void __launch_bounds__(256) k_value_if_empty(DevGraph g, DevCounters*
     if (threadIdx.x == 0 && nr) atomicAdd(&ctr->round_raised, (int)nr);
 }
 
+// ---- rounds on a small worklist in one workgroup ----------------------------
+//
+// Deep graphs (grids) run thousands of push-relabel rounds between relabels,
+// each over a few hundred active vertices: as separate launches per round
+// (push-relabel, remove-invalid-edges, next worklist) with a read-back each,
+// the rounds cost more in launches and host round trips than in work.  Here
+// one 1024-thread workgroup runs round after round with workgroup barriers
+// only: push-relabel over the list (Algorithm 2), remove-invalid-edges over
+// the same rows (Algorithm 3), then the next list from this one plus the
+// round's activations, each vertex once (mark == epoch), binned by row
+// length.  It stops after max_rounds rounds, or before a round whose list is
+// empty, longer than `limit` vertices or holds a workgroup-bin row (the
+// multi-block kernels take those).  Lists alternate between set a and set b
+// (input in a, counts in ctr->wl); on exit ctr->wl holds the counts of the
+// list to run next, ctr->rn_set which set holds it (0 a, 1 b) and
+// ctr->rn_rounds the rounds run.  Activations of the last round are already
+// in that list (the caller clears the activation count).
+constexpr int RN_BLOCK = 1024;
+
+__global__ void __launch_bounds__(RN_BLOCK) k_rounds_narrow(DevGraph g, int32_t* a0, int32_t* a1, int32_t* a2,
+                                                           int32_t* b0, int32_t* b1, int32_t* b2, int32_t* mark,
+                                                           int32_t* epoch, DevCounters* ctr, int kc, int max_rounds,
+                                                           int limit) {
+    if (halted(g)) return;
+    constexpr int BS = RN_BLOCK;
+    __shared__ int s_c[3];
+    __shared__ int s_n[3];
+    __shared__ int s_ep;
+    __shared__ int s_na;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    if (tid < 3) s_c[tid] = ctr->wl[tid];
+    __syncthreads();
+    int set = 0, r = 0;
+    for (; r < max_rounds; ++r) {
+        const int c0 = s_c[0], c1 = s_c[1], c2 = s_c[2];
+        if (c2 != 0 || c0 + c1 == 0 || c0 + c1 > limit) break;
+        const int32_t* in0 = set ? b0 : a0;
+        const int32_t* in1 = set ? b1 : a1;
+        int32_t* out[3] = {set ? a0 : b0, set ? a1 : b1, set ? a2 : b2};
+        if (tid == 0) *g.act_cnt = 0;
+        __syncthreads();
+        // push-relabel (Algorithm 2): one thread per short row, one wave per longer row
+        for (int i = tid; i < c0; i += BS) pr_thread_item<false>(g, in0[i], kc);
+        for (int w = tid / WAVE; w < c1; w += BS / WAVE) pr_wave_item<false>(g, bcast(in1[w]), kc);
+        __syncthreads();
+        // remove invalid edges (Algorithm 3) over the same rows
+        unsigned long long nb = 0;
+        for (int i = tid; i < c0; i += BS) {
+            const int u = in0[i];
+            const long long moved = rie_item<1>(g, u, 0, &nb);
+            if (moved) add_e(g.e, u, -moved);
+        }
+        for (int w = tid / WAVE; w < c1; w += BS / WAVE) {
+            const int u = bcast(in1[w]);
+            const long long moved = wave_sum_i64(rie_item<WAVE>(g, u, lane, &nb));
+            if (lane == 0 && moved) add_e(g.e, u, -moved);
+        }
+        if (tid == 0) {
+            s_ep = *epoch + 1;
+            *epoch = s_ep;
+            s_na = __hip_atomic_load(g.act_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // counted by atomics
+        }
+        if (tid < 3) s_n[tid] = 0;
+        __syncthreads();
+        // the next list: this one and the round's activations, still active,
+        // each once; every vertex when activations overflowed the list
+        const int ep = s_ep;
+        const bool all = s_na > g.act_cap;
+        const long long total = all ? (long long)g.n : (long long)c0 + c1 + s_na;
+        for (long long i = tid; i < total; i += BS) {
+            int v;
+            if (all) v = (int)i;
+            else if (i < c0) v = in0[i];
+            else if (i < (long long)c0 + c1) v = in1[i - c0];
+            else v = g.act[i - c0 - c1];
+            if (v != g.s && v != g.t && v != g.pinned && ld_e(g.e, v) > 0 && g.h[v] < g.n &&
+                atomicExch(&mark[v], ep) != ep) {
+                const int len = g.row_len[v];
+                const int bin = len <= g.bin0_max ? 0 : (len <= g.bin1_max ? 1 : 2);
+                out[bin][atomicAdd(&s_n[bin], 1)] = v;
+            }
+        }
+        __syncthreads();
+        if (tid < 3) s_c[tid] = s_n[tid];
+        set ^= 1;
+        __syncthreads();
+    }
+    if (tid < 3) ctr->wl[tid] = s_c[tid];
+    if (tid == 0) {
+        ctr->wl[3] = s_c[0] + s_c[1] + s_c[2];
+        ctr->rn_set = set;
+        ctr->rn_rounds = r;
+    }
+}
+
 // ---- relayout: rows with room for their pending inserts ---------------------
 //
 // Rows keep their slots in order; each row's new size is its used length plus
@@ -2632,6 +2728,12 @@ void launch_value_if_empty(const DevGraph& g, DevCounters* ctr, int guard_level,
 
 void launch_round_terms_clear(DevCounters* ctr, hipStream_t st) {
     k_zero_counts<<<1, 64, 0, st>>>(ctr, 1, 0, nullptr);
+}
+
+void launch_rounds_narrow(const DevGraph& g, int32_t* const a[3], int32_t* const b[3], int32_t* mark,
+                          int32_t* epoch, DevCounters* ctr, int kc, int max_rounds, int limit, hipStream_t st) {
+    k_rounds_narrow<<<1, RN_BLOCK, 0, st>>>(g, a[0], a[1], a[2], b[0], b[1], b[2], mark, epoch, ctr, kc, max_rounds,
+                                           limit);
 }
 
 void launch_zero_act(DevCounters* ctr, hipStream_t st) {

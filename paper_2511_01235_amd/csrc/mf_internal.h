@@ -80,7 +80,10 @@ struct DevCounters {
     long long round_e_t;       // value terms after a round whose next worklist came out empty:
     long long round_deficit;   // e(t) and the sum of negative excess outside {s,t}
     int32_t round_raised;      // ... and the deficient vertices above height 0 (made by remove-invalid-
-    int32_t round_pad;         //     edges after the relabel); the loop may end there only if none
+                               //     edges after the relabel); the loop may end there only if none
+    int32_t rn_set;            // one-workgroup rounds: which list set holds the next list (0 in, 1 other)
+    int32_t rn_rounds;         // ... and how many rounds they ran
+    int32_t rn_pad;
 };
 
 // KC_GR: multi-block BFS level launches; KC_GRS: the relabel's seeding and its
@@ -321,6 +324,13 @@ void launch_set_i32(int32_t* p, int32_t value, hipStream_t st);
 // (after_round: when its first round left no active vertex)
 void launch_halt_if_done(const DevCounters* ctr, int level_end, bool after_round, int32_t* halt, hipStream_t st);
 void launch_zero_act(DevCounters* ctr, hipStream_t st);
+// Up to max_rounds push-relabel + remove-invalid-edges rounds in one
+// workgroup while the worklist holds at most `limit` vertices and no
+// workgroup-bin row (input lists a with counts in ctr->wl; lists alternate
+// with b; ctr->wl, rn_set and rn_rounds say where it stopped).  dg.act must be
+// set, dg.relab null; epoch: the device epoch word (one per round).
+void launch_rounds_narrow(const DevGraph& g, int32_t* const a[3], int32_t* const b[3], int32_t* mark,
+                          int32_t* epoch, DevCounters* ctr, int kc, int max_rounds, int limit, hipStream_t st);
 // the round value terms to zero (as a next-worklist build leaves them)
 void launch_round_terms_clear(DevCounters* ctr, hipStream_t st);
 // After a next-worklist build that found no active vertex (and, guard_level

@@ -74,10 +74,15 @@ def test_invariants_between_kernels(name):
         assert inv["active"] == 0 and inv["steep_slots"] == 0
         for _ in range(3):
             u, v, c = stream.next_batch(k)
-            assert G.apply_batch(u, v, c) == o.apply(u, v, c)
+            want = o.apply(u, v, c)
+            assert G.apply_batch(u, v, c) == want
             inv = G.invariants()
             _safe(inv)
             assert inv["active"] == 0 and inv["steep_slots"] == 0
+            # the cut (after a relabel of its own when the repair ended after a round)
+            side, cut = G.min_cut()
+            assert cut == want and side[g.s] == 1 and side[g.t] == 0
+            _safe(G.invariants())
 
 
 class FailingAllocator:

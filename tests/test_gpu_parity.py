@@ -101,25 +101,31 @@ def test_bottom_up_levels_bit_exact(name, variant):
             assert G.apply_batch(u, v, c) == o.apply(u, v, c)
 
 
+@pytest.mark.parametrize("narrow", [0, -1, 16])
 @pytest.mark.parametrize("scan", [0, 1])
 @pytest.mark.parametrize("div", [1, 8, 1000000])
 @pytest.mark.parametrize("name", ["grid64", "rmat12"])
-def test_push_rounds_between_relabels(name, div, scan):
+def test_push_rounds_between_relabels(name, div, scan, narrow):
     """Push-relabel rounds on the current heights between global relabels
     (one per relabel up to one per BFS level), their worklists built from the
-    previous one plus the activated vertices or by scanning every vertex:
-    values equal the oracle's in the single-graph and the batched loops."""
+    previous one plus the activated vertices or by scanning every vertex,
+    short lists run many rounds per launch in one workgroup (up to 2048 or 16
+    vertices, or never): values equal the oracle's in the single-graph and
+    the batched loops."""
     g, stream, k, _ = gen.workload(name)
-    say("push rounds", name, "div", div, "scan", scan)
+    say("push rounds", name, "div", div, "scan", scan, "narrow", narrow)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
     want = [o.static()]
     batches = [stream.next_batch(k) for _ in range(3)]
     want += [o.apply(*b) for b in batches]
-    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, round_div=div, round_scan=scan) as G:
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, round_div=div, round_scan=scan,
+                         round_narrow=narrow) as G:
         got = [G.maxflow()] + [G.apply_batch(*b) for b in batches]
         if div == 1 and name == "grid64":
             assert G.stats()["last_rounds"] > G.stats()["last_iterations"]
     assert got == want
+    if narrow:
+        return  # the batched loop has no one-workgroup rounds
     with mf.MaxFlowBatch([g], round_div=div) as B:
         got_b = [int(B.maxflow()[0])] + [int(B.apply([b])[0]) for b in batches]
     assert got_b == want
