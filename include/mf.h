@@ -110,7 +110,7 @@ typedef struct mf_options {
                                   launch of bfs_medium_blocks workgroups with a grid barrier per
                                   level; 0: 65536, < 0: never (also where cooperative launch is
                                   unsupported) */
-    int32_t bfs_medium_blocks; /* 0: 32 */
+    int32_t bfs_medium_blocks; /* 0: 16 */
     int32_t bfs_level_blocks;  /* workgroups of one multi-block BFS level launch; 0: four per
                                   compute unit */
     int32_t bfs_bottom_up;     /* bottom-up level variant: 0 a thread per unvisited row, four slot
@@ -417,6 +417,18 @@ mf_status mf_batch_info(const mf_batch* b, int32_t* iterations, double* last_ms)
 /* mf_graph_tune for a batch: the same fields plus batch_block (threads per
  * graph: 256, 512 or 1024).  Errors: MF_ERR_INVALID, MF_ERR_DEVICE. */
 mf_status mf_batch_tune(mf_batch* b, const mf_options* opt);
+
+/* Profiling of the batched solve: with on != 0 every later mf_batch_maxflow
+ * and mf_batch_apply times its solve launch (the one that runs every graph's
+ * loop) with HIP events on the batch's stream and counts the algorithmic
+ * bytes its kernels move on the device (Bi-CSR slots and vertex words
+ * visited, as mf_stats.kernel_bytes counts them for one graph); on == 0
+ * turns it off.  Errors: MF_ERR_INVALID, MF_ERR_DEVICE. */
+mf_status mf_batch_profile(mf_batch* b, int32_t on);
+
+/* The last profiled call's solve launch: its event time in ms and the
+ * algorithmic bytes its kernels moved (0 when not profiling). */
+mf_status mf_batch_kernel_stats(const mf_batch* b, double* kernel_ms, double* alg_bytes);
 
 void mf_batch_free(mf_batch* b);
 

@@ -34,7 +34,8 @@ EXPORTED = ["mf_default_options", "mf_status_string", "mf_graph_load", "mf_maxfl
             "mf_graph_offload", "mf_graph_restore", "mf_graph_tune", "mf_get_stats", "mf_profile",
             "mf_debug_initial_labels", "mf_debug_selftest", "mf_debug_atomic_probe", "mf_debug_round",
             "mf_debug_check_invariants", "mf_graph_free", "mf_batch_load", "mf_batch_maxflow",
-            "mf_batch_apply", "mf_batch_info", "mf_batch_tune", "mf_batch_free"]
+            "mf_batch_apply", "mf_batch_info", "mf_batch_tune", "mf_batch_profile", "mf_batch_kernel_stats",
+            "mf_batch_free"]
 
 KERNEL_CLASSES = ["global_relabel", "push_relabel", "remove_invalid", "worklist", "batch", "init",
                   "relabel_seed_narrow", "unused7"]
@@ -152,6 +153,8 @@ def lib():
         L.mf_batch_maxflow.argtypes = [vp, vp]
         L.mf_batch_apply.argtypes = [vp, vp, vp, vp]
         L.mf_batch_info.argtypes = [vp, vp, C.POINTER(C.c_double)]
+        L.mf_batch_profile.argtypes = [vp, i32]
+        L.mf_batch_kernel_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.mf_batch_free.argtypes = [vp]
         L.mf_batch_free.restype = None
         for name in ["mf_graph_load", "mf_maxflow", "mf_apply_batch", "mf_apply_batch_device",
@@ -161,7 +164,8 @@ def lib():
                      "mf_get_stats", "mf_profile",
                      "mf_debug_initial_labels", "mf_debug_selftest", "mf_debug_atomic_probe", "mf_debug_round",
                      "mf_debug_check_invariants", "mf_batch_load",
-                     "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info"]:
+                     "mf_batch_maxflow", "mf_batch_apply", "mf_batch_info", "mf_batch_profile",
+                     "mf_batch_kernel_stats"]:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -502,6 +506,16 @@ class MaxFlowBatch:
         if bad:
             raise TypeError(f"not tuning fields: {sorted(bad)}")
         _check(lib().mf_batch_tune(self.h, C.byref(make_options(**tuning))), "mf_batch_tune")
+
+    def profile(self, on=True):
+        """Time each call's solve launch and count its algorithmic bytes."""
+        _check(lib().mf_batch_profile(self.h, int(bool(on))), "mf_batch_profile")
+
+    def kernel_stats(self):
+        """(ms, algorithmic bytes) of the last profiled call's solve launch."""
+        ms, nb = C.c_double(), C.c_double()
+        _check(lib().mf_batch_kernel_stats(self.h, C.byref(ms), C.byref(nb)), "mf_batch_kernel_stats")
+        return ms.value, nb.value
 
     def info(self):
         it = np.zeros(self.G, np.int32)

@@ -90,7 +90,7 @@ struct mf_graph {
     int64_t narrow_max = 4096;       // BFS frontiers of up to this many slots run in one workgroup (0: never)
     int64_t medium_max = 65536;      // ... up to this many in one cooperative launch of a few workgroups
     int32_t rn_limit = 2048;         // worklists of up to this many vertices run rounds in one workgroup
-    int32_t medium_blocks = 32;      //     of this many 1024-thread blocks (0 where unsupported)
+    int32_t medium_blocks = 16;      //     of this many 1024-thread blocks (0 where unsupported)
     bool coop_ok = false;            // the device supports cooperative launch
     std::atomic<bool> coop_broken{false};  // a cooperative launch failed: multi-block levels only
                                      // (set by either lane of a push-pull repair)
@@ -429,7 +429,7 @@ void apply_loop_options(mf_graph* g, const mf_options& o) {
     g->first_chunk = o.bfs_first_chunk > 0 ? o.bfs_first_chunk : 10;
     g->narrow_max = o.bfs_narrow_slots < 0 ? 0 : o.bfs_narrow_slots > 0 ? o.bfs_narrow_slots : 4096;
     g->medium_max = o.bfs_medium_slots < 0 ? 0 : o.bfs_medium_slots > 0 ? o.bfs_medium_slots : 65536;
-    g->medium_blocks = o.bfs_medium_blocks > 0 ? o.bfs_medium_blocks : 32;
+    g->medium_blocks = o.bfs_medium_blocks > 0 ? o.bfs_medium_blocks : 16;
     // mid-size frontiers need cooperative launch (every block resident)
     if (!g->coop_ok || g->medium_max <= g->narrow_max) g->medium_blocks = 0;
     g->gr_grid = o.bfs_level_blocks > 0 ? o.bfs_level_blocks : std::max(32, g->cus * 4);

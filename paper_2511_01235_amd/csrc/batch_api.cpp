@@ -73,6 +73,12 @@ struct mf_batch {
     std::vector<DevCounters> ctr_h;
     bool solved = false, poisoned = false;
     double last_ms = 0;
+    // profiling (mf_batch_profile): the solve launch of each call timed with
+    // events and its algorithmic bytes counted on the device
+    bool prof = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    double kernel_ms = 0, kernel_bytes = 0;
+    std::vector<unsigned long long> bytes_h;
 };
 
 namespace {
@@ -127,6 +133,32 @@ mf_status read_results(mf_batch* b, int64_t* values) {
         if (b->slots_h[i].status != 0) rc = MF_ERR_NOT_CONVERGED;
     }
     return rc;
+}
+
+// Around the solve launch of a call: while profiling, the partial byte sums
+// start at zero and events bracket the launch.
+mf_status prof_begin(mf_batch* b) {
+    if (!b->prof) return MF_OK;
+    mf::launch_fill_i32(reinterpret_cast<int32_t*>(b->bytes_part), 0, 2 * (int64_t)mf::KC_NCLASS * mf::BYTES_SLOTS,
+                        b->stream);
+    MFB_HIP(hipEventRecord(b->ev[0], b->stream));
+    return MF_OK;
+}
+
+mf_status prof_end(mf_batch* b) {
+    if (!b->prof) return MF_OK;
+    MFB_HIP(hipEventRecord(b->ev[1], b->stream));
+    b->bytes_h.resize((size_t)mf::KC_NCLASS * mf::BYTES_SLOTS);
+    MFB_HIP(hipMemcpyAsync(b->bytes_h.data(), b->bytes_part, sizeof(unsigned long long) * b->bytes_h.size(),
+                           hipMemcpyDeviceToHost, b->stream));
+    MFB_HIP(hipStreamSynchronize(b->stream));
+    float ms = 0;
+    MFB_HIP(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+    b->kernel_ms = ms;
+    double sum = 0;
+    for (unsigned long long x : b->bytes_h) sum += (double)x;
+    b->kernel_bytes = sum;
+    return MF_OK;
 }
 
 struct Clock {
@@ -246,7 +278,7 @@ mf_status upload_views(mf_batch* b) {
         g.nslots = nullptr;  // the batched kernels keep used_slots in the device-resident view
         g.halt = nullptr;
         g.bytes_part = b->bytes_part;
-        g.count_bytes = 0;
+        g.count_bytes = b->prof ? 1 : 0;
         g.bin0_max = b->bin0;
         g.bin1_max = b->bin1;
         g.side = nullptr;
@@ -455,9 +487,13 @@ mf_status mf_batch_maxflow(mf_batch* b, int64_t* values) {
     if (hipSetDevice(b->device) != hipSuccess) return MF_ERR_DEVICE;
     Clock clock(b);
     b->solved = false;
+    mf_status rc = prof_begin(b);
+    if (rc != MF_OK) return rc;
     mf::launch_batch_solve(b->slots_d, b->order_d, b->G, 0, b->tune, b->block, b->stream);
     MFB_HIP(hipGetLastError());
-    mf_status rc = read_results(b, values);
+    rc = prof_end(b);
+    if (rc != MF_OK) return rc;
+    rc = read_results(b, values);
     if (rc == MF_OK) b->solved = true;
     return rc;
 }
@@ -560,9 +596,13 @@ mf_status mf_batch_apply(mf_batch* b, const int64_t* update_offset, const mf_upd
         if (rc != MF_OK) return rc;
     }
     b->solved = false;
+    mf_status rc = prof_begin(b);
+    if (rc != MF_OK) return rc;
     mf::launch_batch_repair_multi(b->slots_d, b->gu_d, b->order_d, G, b->tune, b->block, st);
     MFB_HIP(hipGetLastError());
-    mf_status rc = read_results(b, values);
+    rc = prof_end(b);
+    if (rc != MF_OK) return rc;
+    rc = read_results(b, values);
     if (rc == MF_OK) b->solved = true;
     return rc;
 }
@@ -586,12 +626,33 @@ mf_status mf_batch_info(const mf_batch* b, int32_t* iterations, double* last_ms)
     return MF_OK;
 }
 
+mf_status mf_batch_profile(mf_batch* b, int32_t on) {
+    if (!b) return MF_ERR_INVALID;
+    if (b->poisoned) return MF_ERR_DEVICE;
+    if (hipSetDevice(b->device) != hipSuccess) return MF_ERR_DEVICE;
+    MFB_HIP(hipStreamSynchronize(b->stream));
+    for (auto& e : b->ev)
+        if (!e) MFB_HIP(hipEventCreate(&e));
+    b->prof = on != 0;
+    b->kernel_ms = b->kernel_bytes = 0;
+    return upload_views(b);
+}
+
+mf_status mf_batch_kernel_stats(const mf_batch* b, double* kernel_ms, double* alg_bytes) {
+    if (!b) return MF_ERR_INVALID;
+    if (kernel_ms) *kernel_ms = b->kernel_ms;
+    if (alg_bytes) *alg_bytes = b->kernel_bytes;
+    return MF_OK;
+}
+
 void mf_batch_free(mf_batch* b) {
     if (!b) return;
     UseAllocator use(b->mem);
     (void)hipSetDevice(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     free_batch(b);
+    for (auto e : b->ev)
+        if (e) (void)hipEventDestroy(e);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }

@@ -1856,9 +1856,20 @@ __device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
         sweep = false;
         if (rounds_left > 0) --rounds_left;
         // push-relabel (Algorithm 2) over the three degree bins
-        for (int i = tid; i < c0; i += BS) pr_thread_item<false>(g, S.wl0[i], S.kc);
-        for (int i = tid / WAVE; i < c1; i += BS / WAVE) pr_wave_item<false>(g, bcast(S.wl1[i]), S.kc);
-        for (int i = 0; i < c2; ++i) pr_block_item<false, BS>(g, S.wl2[i], S.kc_long);
+        unsigned long long pb = 0;  // algorithmic bytes (counted while profiling)
+        for (int i = tid; i < c0; i += BS) pb += pr_thread_item<false>(g, S.wl0[i], S.kc);
+        for (int i = tid / WAVE; i < c1; i += BS / WAVE) {
+            const unsigned long long b = pr_wave_item<false>(g, bcast(S.wl1[i]), S.kc);
+            if (lane == 0) pb += b;
+        }
+        for (int i = 0; i < c2; ++i) {
+            const unsigned long long b = pr_block_item<false, BS>(g, S.wl2[i], S.kc_long);
+            if (tid == 0) pb += b;
+        }
+        if (g.count_bytes) {
+            const unsigned long long b = wave_sum_u64(pb);
+            if (lane == 0 && b) add_bytes(g, KC_PR, b);
+        }
         __syncthreads();
         // remove invalid edges (Algorithm 3)
         unsigned long long nb = 0;
@@ -1876,6 +1887,10 @@ __device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
             int u = S.wl2[i];
             long long moved = wave_sum_i64(rie_item<BS>(g, u, tid, &nb));
             if (lane == 0 && moved) add_e(g.e, u, -moved);
+        }
+        if (g.count_bytes) {
+            const unsigned long long b = wave_sum_u64(nb);
+            if (lane == 0 && b) add_bytes(g, KC_RIE, b);
         }
         __syncthreads();
     }

@@ -197,6 +197,41 @@ def traffic_table(fetch_dir, write_dir, kernels, classes):
     return out
 
 
+def atomic_table(kt_rows, atomic_dir, kernels):
+    """Atomic requests at L2 (TCC_ATOMIC_sum) per dispatch of each kernel in
+    the timed window, over the kernel's average duration in the kernel-trace
+    run: the rate its pushes and relabels drive, next to the scattered-atomic
+    probe's own rate measured the same way (its dispatches run before the
+    window)."""
+    rows = _rows(os.path.join(atomic_dir, "run_counter_collection.csv"))
+    a, b = timed_window(rows)
+    ka, kb = timed_window(kt_rows)
+    dur = {}
+    for r in kt_rows[ka:kb]:
+        dur.setdefault(short(_name(r)), []).append(_dur_us(r))
+    probe_dur = {}
+    for r in kt_rows:
+        k = short(_name(r))
+        if k.startswith("k_atomic_probe"):
+            probe_dur.setdefault(k, []).append(_dur_us(r))
+    out = ["| kernel | dispatches | atomic requests per dispatch | avg us | G requests/s |",
+           "|---|---:|---:|---:|---:|"]
+    for k, d in sorted(probe_dur.items()):
+        vals = [float(r["Counter_Value"]) for r in rows if short(_name(r)) == k]
+        if vals:
+            rate = np.mean(vals) / (np.mean(d) * 1e-6) / 1e9
+            out.append(f"| `{k}` (probe) | {len(vals)} | {np.mean(vals):.0f} | {np.mean(d):.1f} | {rate:.2f} |")
+    for k in kernels:
+        vals = [float(r["Counter_Value"]) for r in rows[a:b] if short(_name(r)) == k or
+                short(_name(r)).startswith(k + "<")]
+        ds = [x for name, d in dur.items() if name == k or name.startswith(k + "<") for x in d]
+        if not vals or not ds:
+            continue
+        rate = np.mean(vals) / (np.mean(ds) * 1e-6) / 1e9
+        out.append(f"| `{k}` | {len(vals)} | {np.mean(vals):.0f} | {np.mean(ds):.1f} | {rate:.2f} |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("kt_dir")
@@ -208,6 +243,7 @@ def main():
     ap.add_argument("--kernels", default="",
                     help="comma-separated kernels for a per-kernel traffic table (with --bench-json: per class)")
     ap.add_argument("--bench-json", default="", help="file whose last line is the bench's JSON result")
+    ap.add_argument("--atomic-dir", default="", help="counter pass of TCC_ATOMIC_sum (same bench command)")
     args = ap.parse_args()
     kt = _rows(os.path.join(args.kt_dir, "run_kernel_trace.csv"))
     print(f"# {args.title or args.kernel}\n")
@@ -246,6 +282,9 @@ def main():
             classes = json.loads(last)["roofline"].get("classes")
         print("## HBM traffic of each kernel (counter passes, timed window)\n")
         print(traffic_table(args.fetch_dir, args.write_dir, args.kernels.split(","), classes))
+        if args.atomic_dir:
+            print("## Atomics (TCC_ATOMIC_sum pass, timed window)\n")
+            print(atomic_table(kt, args.atomic_dir, args.kernels.split(",")))
     total = 0.0
     lines = []
     for d in (args.fetch_dir, args.write_dir):
