@@ -1219,7 +1219,9 @@ __device__ __forceinline__ unsigned long long pr_wave_item(DevGraph& g, int u, i
     int beg = bcast(g.row_ptr[u]);
     int end = beg + bcast(g.row_len[u]);
     int hu = bcast(g.h[u]);
-    unsigned long long bytes = 16;
+    // wave-uniform terms on lane 0, per-lane terms on each lane: the caller
+    // sums the wave
+    unsigned long long bytes = lane == 0 ? 16 : 0;
     for (int c = 0; c < kc && hu < N; ++c) {
         int64_t eu = bcast64(amount<PULL>(g, u));
         if (eu <= 0) continue;
@@ -1227,7 +1229,7 @@ __device__ __forceinline__ unsigned long long pr_wave_item(DevGraph& g, int u, i
         for (int b = beg; b < end; b += PR_UNROLL * WAVE)
             scan_group<PULL, PR_UNROLL, WAVE>(g, b + lane, end, best);
         best = wave_min_u64(best);
-        bytes += 12ull * (unsigned long long)(end - beg);
+        if (lane == 0) bytes += 12ull * (unsigned long long)(end - beg);
         if (best == ~0ull) {
             hu = N;
             if (lane == 0) {
@@ -1243,8 +1245,8 @@ __device__ __forceinline__ unsigned long long pr_wave_item(DevGraph& g, int u, i
             if (lane == 0) {
                 g.h[u] = hu;
                 mark_relabel(g, u);
+                bytes += 4;
             }
-            bytes += 4;
             if (hu >= N || ++c >= kc) break;
         }
         // push to bj, then to the following slots still at height bh, in
@@ -1288,7 +1290,9 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
     int beg = g.row_ptr[u];
     int end = beg + g.row_len[u];
     int hu = g.h[u];
-    unsigned long long bytes = 16;
+    // block-uniform terms on thread 0, per-thread terms on each thread: the
+    // caller sums the block
+    unsigned long long bytes = threadIdx.x == 0 ? 16 : 0;
     for (int c = 0; c < kc && hu < N; ++c) {
         if (threadIdx.x == 0) {
             e_sh = amount<PULL>(g, u);
@@ -1338,7 +1342,8 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
                     bytes += 48;
                 }
             }
-            bytes += 12ull * PR_UNROLL_BLOCK;
+#pragma unroll
+            for (int q = 0; q < PR_UNROLL_BLOCK; ++q) bytes += b + q * BS < end ? 12ull : 0ull;
             done = (int64_t)bcast64((long long)taken) >= eu;  // wave-uniform: this wave stops
         }
         best = wave_min_u64(best);
@@ -1363,15 +1368,17 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
         const int bj = (int)(unsigned)best;
         if (bh < hu - 1) {
             // a neighbour below h(u) - 1 (heights moved meanwhile): push there
-            if (threadIdx.x == 0) do_push<PULL>(g, u, bj, eu - moved);
-            bytes += 48;
+            if (threadIdx.x == 0) {
+                do_push<PULL>(g, u, bj, eu - moved);
+                bytes += 48;
+            }
         } else if (bh >= hu) {
             hu = bh + 1 < N ? bh + 1 : N;
             if (threadIdx.x == 0) {
                 g.h[u] = hu;
                 mark_relabel(g, u);
+                bytes += 4;
             }
-            bytes += 4;
         }
         // bh == hu - 1: those slots were saturated by this pass; the next pass rescans
     }
@@ -1388,7 +1395,10 @@ __global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t
     unsigned long long bytes = 0;
     for (int it = blockIdx.x; it < cnt; it += gridDim.x)  // whole blocks
         bytes += pr_block_item<PULL, BLOCK_PR>(g, wl[it], kc);
-    if (threadIdx.x == 0 && bytes) add_bytes(g, KC_PR, bytes);
+    if (g.count_bytes) {
+        const unsigned long long b = wave_sum_u64(bytes);
+        if (lane_id() == 0 && b) add_bytes(g, KC_PR, b);
+    }
 }
 
 // One launch for a round's thread and wave bins (the workgroup bin has its
@@ -1419,8 +1429,7 @@ __global__ void __launch_bounds__(PR_SMALL_BLOCK) k_pr_small(DevGraph g, const i
         if (vb < nb1) {
             const int w = vb * WPB + (int)threadIdx.x / WAVE;
             if (w < c.c1) {  // whole waves
-                const unsigned long long b = pr_wave_item<PULL>(g, bcast(wl1[w]), kc);
-                if (lane_id() == 0) bytes += b;
+                bytes += pr_wave_item<PULL>(g, bcast(wl1[w]), kc);
             }
         } else {
             const int i = (vb - nb1) * BS + (int)threadIdx.x;
@@ -1858,14 +1867,8 @@ __device__ void solve_graph(GraphSlot& S, int mode, const GrTune& tune) {
         // push-relabel (Algorithm 2) over the three degree bins
         unsigned long long pb = 0;  // algorithmic bytes (counted while profiling)
         for (int i = tid; i < c0; i += BS) pb += pr_thread_item<false>(g, S.wl0[i], S.kc);
-        for (int i = tid / WAVE; i < c1; i += BS / WAVE) {
-            const unsigned long long b = pr_wave_item<false>(g, bcast(S.wl1[i]), S.kc);
-            if (lane == 0) pb += b;
-        }
-        for (int i = 0; i < c2; ++i) {
-            const unsigned long long b = pr_block_item<false, BS>(g, S.wl2[i], S.kc_long);
-            if (tid == 0) pb += b;
-        }
+        for (int i = tid / WAVE; i < c1; i += BS / WAVE) pb += pr_wave_item<false>(g, bcast(S.wl1[i]), S.kc);
+        for (int i = 0; i < c2; ++i) pb += pr_block_item<false, BS>(g, S.wl2[i], S.kc_long);
         if (g.count_bytes) {
             const unsigned long long b = wave_sum_u64(pb);
             if (lane == 0 && b) add_bytes(g, KC_PR, b);
