@@ -356,29 +356,34 @@ def bench_batched(args, mf, gen, torch, stream):
     log(f"batched static: {static_ms:.1f} ms")
     values = []
     step_ms = []
+    rep_ms = rep_bytes = None
     for r in range(rounds):
+        # the first round (untimed when there is a warm-up round) is the
+        # roofline's: its batched repair launch timed with events and its
+        # algorithmic bytes counted on the device
+        prof_round = r == 0 and args.warmup > 0
+        if prof_round:
+            B.profile(True)
         torch.cuda.synchronize()
         a = time.perf_counter()
         values.append(B.apply(batches[r]))
         torch.cuda.synchronize()
+        if prof_round:
+            rep_ms, rep_bytes = B.kernel_stats()
+            B.profile(False)
         if r >= args.warmup:
             step_ms.append((time.perf_counter() - a) * 1e3)
-    # roofline of the batched solve launch: one more repair round (the batches
-    # of round 0 again: valid updates on any state) timed with events, its
-    # algorithmic bytes counted on the device
-    B.profile(True)
-    B.apply(batches[0])
-    rep_ms, rep_bytes = B.kernel_stats()
-    B.profile(False)
     B.close()
-    roofline = {"bound": "hbm", "kernel_class": "batched repair launch (k_batch_repair_multi)",
-                "achieved": round(rep_bytes / (rep_ms * 1e-3) / 1e9, 2) if rep_ms > 0 else None,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(rep_bytes / (rep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5) if rep_ms > 0 else None,
-                "traffic": None, "launches": 1, "avg_launch_us": round(rep_ms * 1e3, 1),
-                "alg_bytes_per_launch": round(rep_bytes, 1),
-                "timed_over": "one extra repair round after the timed ones (HIP events around the launch)"}
-    log(f"batched repair launch {rep_ms:.2f} ms, {rep_bytes / 1e6:.1f} MB algorithmic")
+    roofline = None
+    if rep_ms:
+        roofline = {"bound": "hbm", "kernel_class": "batched repair launch (k_batch_repair_multi)",
+                    "achieved": round(rep_bytes / (rep_ms * 1e-3) / 1e9, 2),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(rep_bytes / (rep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                    "traffic": None, "launches": 1, "avg_launch_us": round(rep_ms * 1e3, 1),
+                    "alg_bytes_per_launch": round(rep_bytes, 1),
+                    "timed_over": "the warm-up round's batched repair launch (HIP events around it)"}
+        log(f"batched repair launch {rep_ms:.2f} ms, {rep_bytes / 1e6:.1f} MB algorithmic")
     # the same work one graph at a time
     single_static_ms, single_step_ms = 0.0, [0.0] * args.steps
     for i, g in enumerate(graphs):

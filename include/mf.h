@@ -75,7 +75,7 @@ typedef struct mf_options {
                                   exceed the unvisited slots ...; 0: 14, < 0: never bottom-up */
     int32_t bfs_beta;          /* ... and its frontier vertices times beta exceed n; <= 0: 64 */
     int32_t round_div;         /* push-relabel rounds per global relabel: BFS depth / round_div,
-                                  at least 1; <= 0: 8 */
+                                  at least 1; <= 0: 4 */
     int32_t bin_thread_max;    /* active rows up to this many slots get one thread ...; <= 0: 16 */
     int32_t bin_wave_max;      /* ... up to this many one 64-lane wave, longer ones a workgroup;
                                   <= 0: 512 */

@@ -52,6 +52,7 @@ struct mf_graph {
     int32_t* touched = nullptr;
     mf_update* upd = nullptr;
     mf_update* upd_h = nullptr;      // pinned staging of host-memory batches (k_cap entries)
+    mf_update* upd_h_dev = nullptr;  // the same buffer's device-side address
     int64_t k_cap = 0;
     mf::BatchTable tb{};
     uint8_t* side = nullptr;
@@ -83,7 +84,7 @@ struct mf_graph {
     DevCounters* snap_h[2] = {nullptr, nullptr};  // pinned: counters of the iterations in flight
     hipEvent_t snap_ev[2] = {nullptr, nullptr};
     int32_t kc_block = 1;     // push/relabel cycles of the workgroup bin (capped at kc)
-    int32_t round_div = 8;    // push-relabel rounds per global relabel: BFS depth / round_div ...
+    int32_t round_div = 4;    // push-relabel rounds per global relabel: BFS depth / round_div ...
     int32_t round_max = 4096; // ... at most this many
     int32_t round_min = 2;    // ... and at least this many (MF_ROUND_MIN)
     bool incremental_rounds = true;  // rounds take their worklist from the previous one plus activations
@@ -143,7 +144,7 @@ mf_status resolve_tuning(const mf_options& o, Tuning* t) {
     Tuning r{};
     r.kc_option = o.kernel_cycles > 0 ? o.kernel_cycles : 0;
     r.gr = GrTune{GR_BU_ALPHA, GR_BU_BETA, GR_STAGE_MIN, 0, 0, 0};
-    r.round_div = 8;
+    r.round_div = 4;
     if (o.bfs_stage_min > 0) r.gr.stage_min = o.bfs_stage_min;
     if (o.bfs_bottom_up < 0 || o.bfs_bottom_up > 2) return MF_ERR_INVALID;
     r.gr.bu_wide = o.bfs_bottom_up == 1;
@@ -301,6 +302,7 @@ void free_all(mf_graph* g) {
     dfree(g, g->upd);
     if (g->upd_h) (void)hipHostFree(g->upd_h);
     g->upd_h = nullptr;
+    g->upd_h_dev = nullptr;
     dfree(g, g->tb.key);
     dfree(g, g->tb.win);
     dfree(g, g->tb.slot);
@@ -397,6 +399,7 @@ void free_device_state(mf_graph* g) {
     dfree(g, g->upd);
     if (g->upd_h) (void)hipHostFree(g->upd_h);
     g->upd_h = nullptr;
+    g->upd_h_dev = nullptr;
     dfree(g, g->tb.key);
     dfree(g, g->tb.win);
     dfree(g, g->tb.slot);
@@ -461,10 +464,18 @@ mf_status ensure_batch_capacity(mf_graph* g, int64_t k) {
     dfree(g, g->tb.slot);
     if (g->upd_h) (void)hipHostFree(g->upd_h);
     g->upd_h = nullptr;
+    g->upd_h_dev = nullptr;
     if (hipHostMalloc((void**)&g->upd_h, sizeof(mf_update) * (size_t)cap, hipHostMallocDefault) != hipSuccess) {
         g->upd_h = nullptr;
         g->k_cap = 0;
         return MF_ERR_OUT_OF_MEMORY;
+    }
+    // its address for kernels (pinned host memory is mapped into the device's
+    // address space); without one the batch goes by hipMemcpyAsync
+    g->upd_h_dev = nullptr;
+    if (hipHostGetDevicePointer((void**)&g->upd_h_dev, g->upd_h, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        g->upd_h_dev = nullptr;
     }
     if (dalloc(g, &g->slot_of, cap) != hipSuccess || dalloc(g, &g->touched, cap) != hipSuccess ||
         dalloc(g, &g->upd, cap) != hipSuccess || dalloc(g, &g->tb.key, tcap) != hipSuccess ||
@@ -1686,7 +1697,15 @@ static mf_status apply_common(mf_graph* g, const mf_update* upd, int64_t k, int6
         // queued behind the work still on the stream (the last call's copy out
         // of the staging buffer finished before that call returned)
         std::memcpy(g->upd_h, upd, sizeof(mf_update) * (size_t)k);
-        MF_HIP(hipMemcpyAsync(g->upd, g->upd_h, sizeof(mf_update) * (size_t)k, hipMemcpyHostToDevice, g->stream));
+        if (g->upd_h_dev) {
+            // a copy kernel reads the pinned buffer over the bus (no DMA-engine round trip)
+            mf::launch_copy_i32(reinterpret_cast<int32_t*>(g->upd), reinterpret_cast<const int32_t*>(g->upd_h_dev),
+                                3 * k, g->stream);
+            MF_HIP(hipGetLastError());
+        } else {
+            MF_HIP(hipMemcpyAsync(g->upd, g->upd_h, sizeof(mf_update) * (size_t)k, hipMemcpyHostToDevice,
+                                  g->stream));
+        }
         d_upd = g->upd;
     }
     g->solved = false;

@@ -39,7 +39,7 @@ struct mf_batch {
     std::vector<int32_t> s_h, t_h;
     int32_t slack_min = 2, slack_pct = 12;
     int32_t relayouts = 0;
-    int32_t round_div = 8;
+    int32_t round_div = 4;
     int32_t bin0 = mf::BIN0_MAX, bin1 = mf::BIN1_MAX;
     int32_t block = 512;                 // threads per graph
     int32_t kc_option = 0;               // 0: round(m/n) per graph

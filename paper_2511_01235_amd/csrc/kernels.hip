@@ -327,6 +327,12 @@ __global__ void k_set_i32(int32_t* p, int32_t value) {
     if (threadIdx.x == 0) *p = value;
 }
 
+// dst[i] = src[i] (src may be pinned host memory mapped for the device)
+__global__ void k_copy_i32(int32_t* dst, const int32_t* src, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 __global__ void k_set_i64(long long* p, long long value) {
     if (threadIdx.x == 0) *p = value;
 }
@@ -2764,6 +2770,10 @@ void launch_halt_if_done(const DevCounters* ctr, int level_end, bool after_round
 
 void launch_set_i32(int32_t* p, int32_t value, hipStream_t st) {
     k_set_i32<<<1, 64, 0, st>>>(p, value);
+}
+
+void launch_copy_i32(int32_t* dst, const int32_t* src, int64_t count, hipStream_t st) {
+    if (count > 0) k_copy_i32<<<grid_for(count, 256, 1024), 256, 0, st>>>(dst, src, count);
 }
 
 void launch_set_i64(long long* p, long long value, hipStream_t st) {

@@ -319,6 +319,8 @@ void launch_next_worklist(const DevGraph& g, const int32_t* const in[3], const i
                           int32_t* out1, int32_t* out2, int32_t* mark, int32_t* epoch, DevCounters* ctr,
                           hipStream_t st);
 void launch_set_i64(long long* p, long long value, hipStream_t st);
+// dst[0..count) = src[0..count); src may be pinned host memory's device address
+void launch_copy_i32(int32_t* dst, const int32_t* src, int64_t count, hipStream_t st);
 void launch_set_i32(int32_t* p, int32_t value, hipStream_t st);
 // sets *halt when the iteration queued behind levels 0..level_end-1 ended the loop
 // (after_round: when its first round left no active vertex)
