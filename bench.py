@@ -136,7 +136,7 @@ def main():
     for kv in args.opt:
         key, _, val = kv.partition("=")
         if key not in ("bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max",
-                       "long_row_cycles") + mf.LOOP_FIELDS:
+                       "long_row_cycles", "insert_slack_min", "insert_slack_pct") + mf.LOOP_FIELDS:
             raise SystemExit(f"--opt: unknown setting {key!r}")
         extra[key] = int(val)
     G = mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0,

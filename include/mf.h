@@ -59,7 +59,8 @@ typedef struct mf_options {
                                   KERNEL_CYCLES); <= 0: round(m/n), at least 1 (Section 6.1) */
     int32_t topology_driven;   /* 1: one worker per vertex for push-relabel and remove-invalid-
                                   edges; 0 (default): active-vertex worklist (Section 5.2, O1) */
-    int32_t insert_slack_min;  /* free slots kept per row for inserted pairs; <= 0: 2 */
+    int32_t insert_slack_min;  /* free slots kept per row for inserted pairs; <= 0: 8 for a graph
+                                  handle, 2 for each graph of a batch */
     int32_t insert_slack_pct;  /* plus this percentage of the row's length; <= 0: 12 */
     int64_t max_iterations;    /* cap on global relabels per call; <= 0: 4n + 1000 */
     int32_t cold_start;        /* 0 (default): a repair first runs one push-relabel and remove-
@@ -138,6 +139,10 @@ typedef struct mf_options {
     int32_t round_narrow;      /* rounds between relabels whose worklist holds at most this many
                                   vertices (none above bin_wave_max slots) run in one workgroup,
                                   many rounds per launch; 0: 2048, < 0: never */
+    int32_t bfs_cap;           /* 1: a solve's relabel stops once every vertex with excess has its
+                                  height, the vertices not reached get depth + 1 (a valid labelling;
+                                  it only stops early while every excess vertex can reach the sink);
+                                  0 (default) or -1: every global relabel runs its BFS to the end */
 } mf_options;
 
 /* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its
@@ -173,6 +178,8 @@ typedef struct mf_stats {
     double kernel_bytes[8];
     int64_t last_rounds;       /* push-relabel rounds of the last call (two or more per global relabel
                                   that leaves active vertices, unless a round empties the worklist) */
+    int64_t last_capped_relabels; /* global relabels of the last call whose BFS stopped before the end
+                                  (bfs_cap) */
 } mf_stats;
 
 /* Fill *opt with the defaults. */

@@ -60,7 +60,7 @@ class Options(C.Structure):
                                         "bfs_medium_blocks", "bfs_level_blocks", "bfs_bottom_up",
                                         "bfs_lds_bitmap", "bfs_stage_min", "round_min", "round_max",
                                         "round_scan", "queue_rounds", "pipeline", "graph_capture", "trace",
-                                        "round_narrow")]
+                                        "round_narrow", "bfs_cap")]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -91,7 +91,8 @@ class TorchAllocator:
 # loop and relabel settings of a single-graph handle (0 = default; switches 1 on, -1 off)
 LOOP_FIELDS = ("bfs_first_chunk", "bfs_narrow_slots", "bfs_medium_slots", "bfs_medium_blocks",
                "bfs_level_blocks", "bfs_bottom_up", "bfs_lds_bitmap", "bfs_stage_min", "round_min",
-               "round_max", "round_scan", "queue_rounds", "pipeline", "graph_capture", "trace", "round_narrow")
+               "round_max", "round_scan", "queue_rounds", "pipeline", "graph_capture", "trace", "round_narrow",
+               "bfs_cap")
 # fields mf_graph_tune / mf_batch_tune apply to a live handle (mf_graph_tune also the loop fields)
 TUNING_FIELDS = ("kernel_cycles", "bfs_alpha", "bfs_beta", "round_div", "bin_thread_max", "bin_wave_max",
                  "batch_block", "long_row_cycles", "max_iterations") + LOOP_FIELDS
@@ -105,7 +106,7 @@ class Stats(C.Structure):
                 ("last_active_sum", C.c_int64), ("last_new_pairs", C.c_int64),
                 ("last_ms", C.c_double), ("kernel_ms", C.c_double * 8),
                 ("kernel_launches", C.c_int64 * 8), ("kernel_bytes", C.c_double * 8),
-                ("last_rounds", C.c_int64)]
+                ("last_rounds", C.c_int64), ("last_capped_relabels", C.c_int64)]
 
 
 class Update(C.Structure):

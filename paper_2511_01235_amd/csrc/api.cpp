@@ -64,6 +64,7 @@ struct mf_graph {
     // stats
     int32_t relayouts = 0;
     int64_t last_iterations = 0, last_levels = 0, last_active_sum = 0, last_new_pairs = 0, last_rounds = 0;
+    int64_t last_capped = 0;         // relabels of the last call whose BFS stopped early (bfs_cap)
     double last_ms = 0;
     uint32_t prof_mask = 0;
     double kernel_ms[8] = {0};
@@ -91,6 +92,7 @@ struct mf_graph {
     int64_t narrow_max = 4096;       // BFS frontiers of up to this many slots run in one workgroup (0: never)
     int64_t medium_max = 65536;      // ... up to this many in one cooperative launch of a few workgroups
     int32_t rn_limit = 2048;         // worklists of up to this many vertices run rounds in one workgroup
+    bool bfs_cap = false;            // solve relabels stop once every vertex with excess has a height
     int32_t medium_blocks = 16;      //     of this many 1024-thread blocks (0 where unsupported)
     bool coop_ok = false;            // the device supports cooperative launch
     std::atomic<bool> coop_broken{false};  // a cooperative launch failed: multi-block levels only
@@ -440,6 +442,7 @@ void apply_loop_options(mf_graph* g, const mf_options& o) {
     g->round_min = o.round_min > 0 ? o.round_min : 2;
     g->round_max = o.round_max > 0 ? o.round_max : 4096;
     g->rn_limit = o.round_narrow < 0 ? 0 : o.round_narrow > 0 ? o.round_narrow : 2048;
+    g->bfs_cap = on(o.bfs_cap, false);
     g->incremental_rounds = !on(o.round_scan, false);
     g->queue_rounds = on(o.queue_rounds, true);
     g->pipeline = on(o.pipeline, true);
@@ -878,7 +881,8 @@ hipGraphExec_t iteration_graph(mf_graph* g, const LoopMode& m, const LoopMode& q
     return exec;
 }
 
-mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
+mf_status run_loop(mf_graph* g, const LoopMode& m_in, int64_t* value) {
+    LoopMode m = m_in;
     // every buffer a loop launches on must be set (a mode built by hand
     // without a lane would hand the kernels null pointers)
     const Lane& L = m.L;
@@ -886,7 +890,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         !L.bits.fb || !L.ctr || !L.ctr_h || !m.dg.h || !m.dg.e || !m.dg.cr)
         return MF_ERR_INVALID;
     hipStream_t st = m.L.stream;
-    int64_t iters = 0, levels = 0, active_sum = 0, rounds = 0;
+    int64_t iters = 0, levels = 0, active_sum = 0, rounds = 0, capped = 0;
     // The main lane queues the worklist build and the first two rounds right
     // behind the relabel's first chunk of BFS levels, sized on the device:
     // an iteration whose BFS ends within that chunk reads the counters back
@@ -911,6 +915,14 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
     // those solves end after a relabel.)
     const bool shortcut =
         m.rie && !m.pull && m.sign == 1 && !m.forward && m.seed_deficits && m.L.main && !g->push_pull;
+    // Relabels of such a solve stop once every vertex with excess has its
+    // height (its BFS distance); the vertices not reached by then get depth +
+    // 1 -- a valid labelling, since each of them has a residual path to a
+    // sink only through vertices at that depth or beyond.  Excess that cannot
+    // reach a sink keeps the BFS going to its end, as before.  Pushes only
+    // need a valid labelling, and the loop's stop needs one too (A10); the
+    // cut is read after an exact relabel.
+    m.dg.bfs_cap = shortcut && g->bfs_cap && g->persistent_grid == 0 ? 1 : 0;
     LoopMode qm = m;
     if (queue) {
         mf_status rc = ensure_round_lists(g);
@@ -1028,11 +1040,12 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
             g->last_depth = c.levels;
             const int active = c.wl_in[3];  // the relabel's worklist (set aside before round 2's)
             active_sum += active;
+            capped += c.bfs_capped != 0;
             if (active == 0) {
                 *value = (int64_t)c.e_t + (int64_t)c.deficit_sum;
                 *m.L.ctr_h = c;
                 finished = true;
-                exact = true;
+                exact = !c.bfs_capped;
                 break;
             }
             if (shortcut && c.wl[3] == 0 && c.round_raised == 0) {  // the first round left no active vertex
@@ -1068,9 +1081,10 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         // the relabel's worklist (after queued rounds, the first round set its sizes aside)
         const int active = queued ? c.wl_in[3] : c.wl[3];  // (set aside by the next-worklist build)
         active_sum += active;
+        capped += c.bfs_capped != 0;
         if (active == 0) {
             *value = (int64_t)c.e_t + (int64_t)c.deficit_sum;
-            exact = true;
+            exact = !c.bfs_capped;
             break;
         }
         if (++iters > g->max_iter) {
@@ -1225,6 +1239,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m, int64_t* value) {
         g->last_levels = levels;
         g->last_active_sum = active_sum;
         g->last_rounds = rounds;
+        g->last_capped = capped;
     }
     return MF_OK;
 }
@@ -1535,7 +1550,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
         if (opt->struct_size != sizeof(mf_options)) return MF_ERR_INVALID;
         o = *opt;
     }
-    int32_t slack_min = o.insert_slack_min > 0 ? o.insert_slack_min : 2;
+    int32_t slack_min = o.insert_slack_min > 0 ? o.insert_slack_min : 8;
     int32_t slack_pct = o.insert_slack_pct > 0 ? o.insert_slack_pct : 12;
     mf::Tuning tuning;
     if (mf::resolve_tuning(o, &tuning) != MF_OK) return MF_ERR_INVALID;
@@ -2039,6 +2054,7 @@ mf_status mf_get_stats(const mf_graph* g, mf_stats* out) {
     out->last_active_sum = g->last_active_sum;
     out->last_new_pairs = g->last_new_pairs;
     out->last_rounds = g->last_rounds;
+    out->last_capped_relabels = g->last_capped;
     out->last_ms = g->last_ms;
     for (int c = 0; c < 8; ++c) {
         out->kernel_ms[c] = g->kernel_ms[c];

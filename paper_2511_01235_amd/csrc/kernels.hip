@@ -292,6 +292,12 @@ __global__ void k_zero_counters_front(DevCounters* ctr) {
         ctr->bar_count = 0;
         ctr->bar_err = 0;
         ctr->levels = 0;
+        ctr->bfs_total = 0;
+        ctr->bfs_capped = 0;
+    }
+    if (threadIdx.x < 3) {
+        ctr->bfs_disc[threadIdx.x] = 0;
+        ctr->bfs_cum[threadIdx.x] = 0;
     }
 }
 
@@ -432,6 +438,7 @@ template <bool WORDS = false>
 __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, int2* q0, DevCounters* ctr,
                                              const GrBits& bits, int seed_deficits, int cls = KC_GR) {
     const int N = g.n;
+    long long excess = 0;  // vertices with excess a capped relabel must label
     for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
         int v = base + threadIdx.x;
         int add = 0, slots = 0;
@@ -448,6 +455,7 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
             }
             bool seed = v == g.root || extra;
             g.h[v] = seed ? 0 : N;
+            if (g.bfs_cap && !seed && v != g.s && v != g.t && v != g.pinned && ld_e(g.e, v) > 0) excess++;
             if (seed) {
                 slots = g.row_len[v];
                 add = (slots + GR_CHUNK - 1) / GR_CHUNK;
@@ -472,6 +480,10 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
             if (front) set_bit(bits.fb, v);
         }
         append_entries(add, slots, v, q0, &ctr->front[0]);
+    }
+    if (g.bfs_cap) {
+        const long long x = wave_sum_i64(excess);
+        if (lane_id() == 0 && x) atomicAdd(&ctr->bfs_total, (int)x);
     }
     if (P.bid == 0 && threadIdx.x == 0) {
         // slots of every row that may be labelled, the seeds' included
@@ -506,9 +518,32 @@ constexpr int GR_TD_U = 4;
 
 // A vertex gets height lv+1: mark it visited and in the next frontier, queue
 // its entries, and return its slot count for the direction counters.
-__device__ __forceinline__ int discover(const DevGraph& g, const GrBits& bits, int lv, int v, int* add) {
+// A capped relabel counts the vertices with excess it labels (v gets height
+// lv + 1 here), per level.
+__device__ __forceinline__ void reached(const DevGraph& g, DevCounters* ctr, int lv, int v) {
+    if (g.bfs_cap && v != g.s && v != g.t && ld_e(g.e, v) > 0) atomicAdd(&ctr->bfs_disc[(lv + 1) % 3], 1);
+}
+
+// Whether a capped relabel stops before processing level lv: the vertices
+// with excess labelled at levels up to lv are all of them.  Reads only counts
+// final before level lv began (level lv - 1's cumulative count, the ones
+// labelled at lv), so every block decides alike.
+__device__ __forceinline__ int excess_labelled(DevCounters* ctr, int lv) {
+    // read at L2: a one-workgroup kernel runs many levels without a fresh L1
+    const int before = lv > 0 ? __hip_atomic_load(&ctr->bfs_cum[(lv + 2) % 3], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT) : 0;
+    return before + __hip_atomic_load(&ctr->bfs_disc[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int excess_total(DevCounters* ctr) {
+    return __hip_atomic_load(&ctr->bfs_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int discover(const DevGraph& g, DevCounters* ctr, const GrBits& bits, int lv, int v,
+                                        int* add) {
     set_bit(bits.visited, v);
     set_bit(bits.fb + (size_t)((lv + 1) % 3) * bits.nwords, v);
+    reached(g, ctr, lv, v);
     int len = g.row_len[v];
     *add = (len + GR_CHUNK - 1) / GR_CHUNK;
     return len;
@@ -601,6 +636,7 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
             int add = 0, slots = 0;
             if (s_hit[tid]) {
                 g.h[v] = lv + 1;
+                reached(g, ctr, lv, v);
                 add = (len + GR_CHUNK - 1) / GR_CHUNK;
                 slots = len;
                 found++;
@@ -669,6 +705,7 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
                 }
                 if (hit) {
                     g.h[v] = lv + 1;
+                    reached(g, ctr, lv, v);
                     add = (len + GR_CHUNK - 1) / GR_CHUNK;
                     slots = len;
                     found++;
@@ -712,7 +749,7 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
                 if (hit && lane == 0) {
                     g.h[w] = lv + 1;
                     int addw;
-                    discover(g, bits, lv, w, &addw);
+                    discover(g, ctr, bits, lv, w, &addw);
                     s_dhit[atomicAdd(&s_ndhit, 1)] = w;
                     found++;
                 }
@@ -774,7 +811,7 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
                     lens[k] = 0;
                     // pinned is marked visited at init
                     if (r[k] > 0 && !bit_of(bm_seen, v) && atomicCAS(&g.h[v], N, lv + 1) == N) {
-                        lens[k] = discover(g, bits, lv, v, &adds[k]);
+                        lens[k] = discover(g, ctr, bits, lv, v, &adds[k]);
                         found++;
                     }
                 }
@@ -818,11 +855,24 @@ template <bool FWD, int BS, bool AGG = true>
 __device__ __forceinline__ int gr_level_step(const Par& P, const DevGraph& g, int lv, const int2* qin,
                                              int2* qout, DevCounters* ctr, const GrBits& bits,
                                              const GrTune& tune, unsigned* s_dyn) {
-    const int cnt = bcast((int)(unsigned)(ctr->front[lv % 3] & 0xFFFFFFFFull));
+    // a capped relabel whose earlier levels labelled every vertex with excess
+    // stops here: this frontier keeps its height lv, the rest get lv + 1
+    // (k_build_worklist), and the BFS reads as over
+    const int labelled = g.bfs_cap ? bcast(excess_labelled(ctr, lv)) : 0;
+    const bool capped = g.bfs_cap && labelled >= bcast(excess_total(ctr));
+    const int cnt = capped ? 0 : bcast((int)(unsigned)(ctr->front[lv % 3] & 0xFFFFFFFFull));
     if (P.bid == 0 && threadIdx.x == 0) {
         ctr->front[(lv + 2) % 3] = 0;
+        if (g.bfs_cap) {
+            ctr->bfs_cum[lv % 3] = labelled;
+            ctr->bfs_disc[(lv + 2) % 3] = 0;  // counts the labels of level lv + 2 (set during level lv + 1)
+        }
         if (lv == 0) ctr->seed_front = ctr->front[0];
         if (cnt) ctr->levels = lv + 1;  // the BFS's depth so far (levels are launched in order)
+        if (capped && (ctr->front[lv % 3] & 0xFFFFFFFFull)) {
+            ctr->bfs_capped = lv + 1;  // the height of every vertex not reached
+            ctr->front[lv % 3] = 0;
+        }
     }
     if (cnt == 0) return 0;
     {   // the bitmap of level lv+2 (input of level lv-1, consumed) starts empty
@@ -866,12 +916,25 @@ template <bool FWD>
 __global__ void __launch_bounds__(NARROW_BLOCK) k_gr_narrow(DevGraph g, int lv0, int2* q0, int2* q1,
                                                             DevCounters* ctr, GrBits bits, long long max_slots) {
     __shared__ unsigned long long s_front;
+    __shared__ int s_stop;
     const Par P{0, 1};
     int lv = lv0;
-    if (threadIdx.x == 0) {
-        s_front = __hip_atomic_load(&ctr->front[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (lv == 0) ctr->seed_front = s_front;
-    }
+    // one thread reads the level's counts and takes the capped relabel's
+    // decision (as gr_level_step does); the block follows it
+    auto level_counts = [&](int l) {
+        if (threadIdx.x == 0) {
+            s_front = __hip_atomic_load(&ctr->front[l % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_stop = 0;
+            if (g.bfs_cap) {
+                const int labelled = excess_labelled(ctr, l);
+                s_stop = labelled >= excess_total(ctr);
+                ctr->bfs_cum[l % 3] = labelled;
+                ctr->bfs_disc[(l + 2) % 3] = 0;
+            }
+        }
+    };
+    level_counts(lv);
+    if (threadIdx.x == 0 && lv == 0) ctr->seed_front = s_front;
     __syncthreads();
     for (; lv <= g.n; ++lv) {
         const int2* qin = (lv & 1) ? q1 : q0;
@@ -881,6 +944,14 @@ __global__ void __launch_bounds__(NARROW_BLOCK) k_gr_narrow(DevGraph g, int lv0,
         // over (empty frontier), or a frontier with too many slots for one
         // workgroup: the multi-block levels take it
         if (cnt == 0 || (long long)(front >> 32) > max_slots) break;
+        // a capped relabel that has labelled every vertex with excess stops
+        if (s_stop) {
+            if (threadIdx.x == 0) {
+                ctr->bfs_capped = lv + 1;  // the height of every vertex not reached
+                ctr->front[lv % 3] = 0;
+            }
+            break;
+        }
         __syncthreads();  // s_front is rewritten below
         if (threadIdx.x == 0) {
             ctr->front[(lv + 2) % 3] = 0;
@@ -892,8 +963,7 @@ __global__ void __launch_bounds__(NARROW_BLOCK) k_gr_narrow(DevGraph g, int lv0,
         gr_level_body<FWD, NARROW_BLOCK, false>(P, g, lv, cnt, qin, qout, ctr, bits, false, false, false, nullptr,
                                                 KC_GRS);
         __syncthreads();
-        if (threadIdx.x == 0)
-            s_front = __hip_atomic_load(&ctr->front[(lv + 1) % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        level_counts(lv + 1);
         __syncthreads();
     }
     if (threadIdx.x == 0) ctr->levels = lv;
@@ -1025,6 +1095,9 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
                                               int32_t* wl2, DevCounters* ctr, int topology, int sign) {
     const int N = g.n;
     long long deficit = 0;
+    // after a capped relabel that stopped before level L, the vertices it did
+    // not reach get L + 1 (bfs_capped)
+    const int cap_h = g.bfs_cap ? ctr->bfs_capped : 0;
     for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
         int v = base + threadIdx.x;
         bool act = false, list = false;
@@ -1032,6 +1105,10 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
         if (v < N) {
             int64_t ev = g.e[v];
             int hv = g.h[v];
+            if (cap_h && hv == N && v != g.pinned) {
+                hv = cap_h;
+                g.h[v] = hv;
+            }
             bool other = v != g.s && v != g.t;
             act = other && (sign > 0 ? ev > 0 : ev < 0) && hv < N;
             if (other && ev < 0) deficit += ev;

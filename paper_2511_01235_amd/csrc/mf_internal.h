@@ -47,6 +47,8 @@ struct DevGraph {
                                          // worklist build clears it; remove-invalid-edges skips unset rows
     const int32_t* halt;                 // not null and set: the single-graph loop kernels leave at once
                                          // (a pipelined iteration queued behind the loop's last one)
+    int32_t bfs_cap;                     // 1: a relabel stops once every vertex with excess has its height
+                                         // (the rest get depth + 1: a valid labelling, not distances)
 };
 
 // Partial sums of algorithmic bytes: a kernel block adds into slot
@@ -83,7 +85,11 @@ struct DevCounters {
                                //     edges after the relabel); the loop may end there only if none
     int32_t rn_set;            // one-workgroup rounds: which list set holds the next list (0 in, 1 other)
     int32_t rn_rounds;         // ... and how many rounds they ran
-    int32_t rn_pad;
+    int32_t bfs_total;         // capped relabel: vertices with excess (counted by the init)
+    int32_t bfs_disc[3];       // ... of them labelled at level lv, in bfs_disc[lv % 3]
+    int32_t bfs_cum[3];        // ... labelled at levels <= lv, in bfs_cum[lv % 3]
+    int32_t bfs_capped;        // ... > 0: it stopped before processing level bfs_capped - 1, whose
+                               //     frontier keeps that height; the rest get bfs_capped
 };
 
 // KC_GR: multi-block BFS level launches; KC_GRS: the relabel's seeding and its

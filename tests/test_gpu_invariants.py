@@ -42,12 +42,13 @@ def _safe(inv):
     assert not bad, bad
 
 
+@pytest.mark.parametrize("cap", [1, 0])
 @pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
-def test_invariants_between_kernels(name):
+def test_invariants_between_kernels(name, cap):
     g, stream, k, _ = gen.workload(name)
-    say("invariants", name)
+    say("invariants", name, "cap", cap)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
-    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, bfs_cap=cap) as G:
         # zero flow as loaded
         inv = G.invariants()
         _safe(inv)

@@ -363,13 +363,17 @@ def test_dynamic_tiny_adversarial(seed):
             _cut_ok(n, s, t, side, cut, got, ms, md, mc)
 
 
+@pytest.mark.parametrize("cap", [1, 0])
 @pytest.mark.parametrize("warm", [False, True])
 @pytest.mark.parametrize("name,batches", [("er2000", 10), ("rmat12", 8), ("rmat14", 5),
                                           ("grid64", 5), ("grid256", 3)])
-def test_dynamic_workloads(name, batches, warm):
+def test_dynamic_workloads(name, batches, warm, cap):
+    """Repairs against the oracle after every batch, cut certificates, with
+    relabels that stop once every vertex with excess has its height (cap 1)
+    or run to the end (0, the default)."""
     g, stream, k, nb = gen.workload(name)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
-    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, warm_start=warm) as G:
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, warm_start=warm, bfs_cap=cap) as G:
         assert G.maxflow() == o.static()
         for b in range(min(batches, nb)):
             u, v, c = stream.next_batch(k)
@@ -380,6 +384,65 @@ def test_dynamic_workloads(name, batches, warm):
             cs, cd, cc = stream.current_edges()
             side, cut = G.min_cut()
             _cut_ok(g.n, g.s, g.t, side, cut, got, cs, cd, cc)
+
+
+def _comb_graph(side=64):
+    """A side x side grid (4-connected, capacity 1000 both ways) drained into
+    the sink t through one corner, and three vertices fed by the source at 10
+    that each reach the grid at 5, well inside it: every vertex with excess
+    reaches t at a depth well short of the grid's far side."""
+    s, t, xs, base = 0, 1, [2, 3, 4], 5
+    gid = lambda r, c: base + r * side + c
+    src, dst, cap = [], [], []
+    for r in range(side):
+        for c in range(side):
+            for dr, dc in ((0, 1), (1, 0)):
+                if r + dr < side and c + dc < side:
+                    src += [gid(r, c), gid(r + dr, c + dc)]
+                    dst += [gid(r + dr, c + dc), gid(r, c)]
+                    cap += [1000, 1000]
+    src.append(gid(0, 0)); dst.append(t); cap.append(1000)
+    for i, x in enumerate(xs):
+        src += [s, x]; dst += [x, gid(10 + 5 * i, 10)]; cap += [10, 5]
+    n = base + side * side
+    return n, s, t, xs, np.array(src, np.int32), np.array(dst, np.int32), np.array(cap, np.int32)
+
+
+@pytest.mark.parametrize("narrow,medium", [(0, 0), (-1, 1 << 30), (-1, -1)])
+def test_capped_relabel_stops_early(narrow, medium):
+    """With bfs_cap a solve's relabel stops once every vertex with excess has
+    its height: on a graph whose excess sits well short of the BFS's far end
+    the first relabel of the solve stops early (in the one-workgroup levels,
+    the cooperative mid-size levels or the multi-block levels), the value
+    and the cut match the oracle's, and without bfs_cap no relabel stops."""
+    n, s, t, xs, src, dst, cap = _comb_graph()
+    o = oracle.DynOracle(n, src, dst, cap, s, t)
+    want = o.static()
+    assert want == 15
+    for on in (1, 0):
+        say("capped relabel", narrow, medium, on)
+        with mf.MaxFlowGraph(n, src, dst, cap, s, t, bfs_cap=on, bfs_narrow_slots=narrow,
+                             bfs_medium_slots=medium) as G:
+            assert G.maxflow() == want
+            capped = G.stats()["last_capped_relabels"]
+            assert (capped >= 1) if on else (capped == 0), capped
+            side, cut = G.min_cut()
+            _cut_ok(n, s, t, side, cut, want, src, dst, cap)
+    # a repair that raises the feeds: the graph handle and the oracle agree
+    u = np.array(xs, np.int32)
+    v = np.array([5 + (10 + 5 * i) * 64 + 10 for i in range(3)], np.int32)
+    c = np.array([10, 10, 10], np.int32)
+    want = o.apply(u, v, c)
+    assert want == 30
+    with mf.MaxFlowGraph(n, src, dst, cap, s, t, bfs_cap=1, bfs_narrow_slots=narrow,
+                         bfs_medium_slots=medium) as G:
+        G.maxflow()
+        assert G.apply_batch(u, v, c) == want
+        src2 = np.concatenate([src[:-6], np.array([s, xs[0], s, xs[1], s, xs[2]], np.int32)])
+        dst2 = np.concatenate([dst[:-6], np.array([xs[0], v[0], xs[1], v[1], xs[2], v[2]], np.int32)])
+        cap2 = np.concatenate([cap[:-6], np.array([10, 10, 10, 10, 10, 10], np.int32)])
+        side, cut = G.min_cut()
+        _cut_ok(n, s, t, side, cut, want, src2, dst2, cap2)
 
 
 def test_dynamic_device_batches_match_host():
