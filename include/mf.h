@@ -139,10 +139,11 @@ typedef struct mf_options {
     int32_t round_narrow;      /* rounds between relabels whose worklist holds at most this many
                                   vertices (none above bin_wave_max slots) run in one workgroup,
                                   many rounds per launch; 0: 2048, < 0: never */
-    int32_t bfs_cap;           /* 1: a solve's relabel stops once every vertex with excess has its
-                                  height, the vertices not reached get depth + 1 (a valid labelling;
-                                  it only stops early while every excess vertex can reach the sink);
-                                  0 (default) or -1: every global relabel runs its BFS to the end */
+    int32_t bfs_cap;           /* 0 (default) or 1: a solve's relabels after its first one, when no
+                                  deficient vertex sits above height 0, stop once every vertex with
+                                  excess below |V| has its height; a vertex not reached keeps
+                                  max(depth + 1, its old height) (a valid labelling, not distances;
+                                  mf_min_cut relabels first).  -1: every relabel runs to the end */
 } mf_options;
 
 /* One update of a batch: set c(u,v) := cap.  cap == 0 deletes the edge (its

@@ -92,7 +92,7 @@ struct mf_graph {
     int64_t narrow_max = 4096;       // BFS frontiers of up to this many slots run in one workgroup (0: never)
     int64_t medium_max = 65536;      // ... up to this many in one cooperative launch of a few workgroups
     int32_t rn_limit = 2048;         // worklists of up to this many vertices run rounds in one workgroup
-    bool bfs_cap = false;            // solve relabels stop once every vertex with excess has a height
+    bool bfs_cap = true;             // solve relabels stop once every vertex with excess has a height
     int32_t medium_blocks = 16;      //     of this many 1024-thread blocks (0 where unsupported)
     bool coop_ok = false;            // the device supports cooperative launch
     std::atomic<bool> coop_broken{false};  // a cooperative launch failed: multi-block levels only
@@ -263,6 +263,7 @@ void free_structure(mf_graph* g) {
 }
 
 void free_round_lists(mf_graph* g) {
+    dfree(g, g->dg.h_prev);
     dfree(g, g->act_list);
     dfree(g, g->mark);
     for (auto& w : g->wlb) dfree(g, w);
@@ -442,7 +443,7 @@ void apply_loop_options(mf_graph* g, const mf_options& o) {
     g->round_min = o.round_min > 0 ? o.round_min : 2;
     g->round_max = o.round_max > 0 ? o.round_max : 4096;
     g->rn_limit = o.round_narrow < 0 ? 0 : o.round_narrow > 0 ? o.round_narrow : 2048;
-    g->bfs_cap = on(o.bfs_cap, false);
+    g->bfs_cap = on(o.bfs_cap, true);
     g->incremental_rounds = !on(o.round_scan, false);
     g->queue_rounds = on(o.queue_rounds, true);
     g->pipeline = on(o.pipeline, true);
@@ -820,8 +821,9 @@ std::vector<long long> capture_key(const mf_graph* g, const LoopMode& m, const L
                               (const void*)d->cr, (const void*)d->rev, (const void*)d->cap, (const void*)d->capsum,
                               (const void*)d->e, (const void*)d->h, (const void*)d->nslots,
                               (const void*)d->bytes_part, (const void*)d->side, (const void*)d->act,
-                              (const void*)d->act_cnt, (const void*)d->relab})
+                              (const void*)d->act_cnt, (const void*)d->relab, (const void*)d->h_prev})
             P(p);
+        k.push_back(d->bfs_cap);
     }
     const Lane& L = m.L;
     for (const void* p : {(const void*)L.q[0], (const void*)L.q[1], (const void*)L.wl[0], (const void*)L.wl[1],
@@ -915,14 +917,17 @@ mf_status run_loop(mf_graph* g, const LoopMode& m_in, int64_t* value) {
     // those solves end after a relabel.)
     const bool shortcut =
         m.rie && !m.pull && m.sign == 1 && !m.forward && m.seed_deficits && m.L.main && !g->push_pull;
-    // Relabels of such a solve stop once every vertex with excess has its
-    // height (its BFS distance); the vertices not reached by then get depth +
-    // 1 -- a valid labelling, since each of them has a residual path to a
-    // sink only through vertices at that depth or beyond.  Excess that cannot
-    // reach a sink keeps the BFS going to its end, as before.  Pushes only
-    // need a valid labelling, and the loop's stop needs one too (A10); the
-    // cut is read after an exact relabel.
-    m.dg.bfs_cap = shortcut && g->bfs_cap && g->persistent_grid == 0 ? 1 : 0;
+    // Optionally, the relabels of such a solve that follow a round (heights a
+    // valid labelling) with every deficient vertex at height 0 stop once
+    // every vertex with excess below |V| has its height (its BFS distance);
+    // a vertex not reached by then keeps max(depth + 1, its old height) -- a
+    // valid labelling (the kernels state why).  Excess that cannot reach a
+    // sink (or a deficit above height 0) keeps the BFS going to its end, as
+    // does the first relabel of every call.  Pushes only need a valid
+    // labelling, and the loop's stop needs one too (A10); the cut is read
+    // after an exact relabel.
+    m.dg.bfs_cap = shortcut && g->bfs_cap && g->persistent_grid == 0 && m.dg.h_prev ? 1 : 0;
+    if (m.dg.bfs_cap) mf::launch_set_i32(&m.L.ctr->lab_valid, 0, st);  // the first relabel runs to its end
     LoopMode qm = m;
     if (queue) {
         mf_status rc = ensure_round_lists(g);
@@ -1494,7 +1499,7 @@ mf_status push_pull_phase(mf_graph* g) {
 // runs only then).
 bool loop_ready(const mf_graph* g) {
     return g->act_list && g->mark && g->wlb[0] && g->snap_h[0] && g->snap_h[1] && g->snap_ev[0] && g->snap_ev[1] &&
-           (!g->push_pull || (g->h2 && g->q2_cap >= g->q_cap));
+           (!g->push_pull || (g->h2 && g->q2_cap >= g->q_cap)) && (!g->bfs_cap || g->dg.h_prev);
 }
 
 // Everything a solve or repair may allocate, taken before it changes any
@@ -1503,6 +1508,8 @@ mf_status prepare_loop(mf_graph* g) {
     mf_status rc = ensure_round_lists(g);
     if (rc == MF_OK) rc = ensure_snapshots(g);
     if (rc == MF_OK && g->push_pull) rc = ensure_lane2(g);
+    if (rc == MF_OK && g->bfs_cap && !g->dg.h_prev && dalloc(g, &g->dg.h_prev, g->n) != hipSuccess)
+        rc = MF_ERR_OUT_OF_MEMORY;
     return rc;
 }
 

@@ -278,6 +278,7 @@ mf_status upload_views(mf_batch* b) {
         g.nslots = nullptr;  // the batched kernels keep used_slots in the device-resident view
         g.halt = nullptr;
         g.bfs_cap = 0;
+        g.h_prev = nullptr;
         g.bytes_part = b->bytes_part;
         g.count_bytes = b->prof ? 1 : 0;
         g.bin0_max = b->bin0;

@@ -294,6 +294,9 @@ __global__ void k_zero_counters_front(DevCounters* ctr) {
         ctr->levels = 0;
         ctr->bfs_total = 0;
         ctr->bfs_capped = 0;
+        ctr->bfs_raised = 0;
+        ctr->bfs_ok = ctr->lab_valid;  // the heights this relabel replaces were a valid labelling
+        ctr->lab_valid = 0;
     }
     if (threadIdx.x < 3) {
         ctr->bfs_disc[threadIdx.x] = 0;
@@ -438,7 +441,12 @@ template <bool WORDS = false>
 __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, int2* q0, DevCounters* ctr,
                                              const GrBits& bits, int seed_deficits, int cls = KC_GR) {
     const int N = g.n;
-    long long excess = 0;  // vertices with excess a capped relabel must label
+    // capped relabel from a valid labelling: the old heights are kept in
+    // h_prev; it must label every vertex with excess below |V| (one at |V|
+    // cannot reach a sink while every sink is at height 0), and it may stop
+    // early only if no deficient vertex sits above height 0
+    const bool cap_ok = g.bfs_cap && ctr->bfs_ok;
+    long long excess = 0, raised = 0;
     for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
         int v = base + threadIdx.x;
         int add = 0, slots = 0;
@@ -449,13 +457,18 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
         } else if (v < N) {
             // seed_deficits 1: deficient vertices are extra roots; -1: overflowing ones
             bool extra = false;
-            if (seed_deficits && v != g.pinned && v != g.s && v != g.t) {
-                int64_t ev = ld_e(g.e, v);
-                extra = seed_deficits > 0 ? ev < 0 : ev > 0;
-            }
+            const bool other = v != g.pinned && v != g.s && v != g.t;
+            int64_t ev = 0;
+            if ((seed_deficits || cap_ok) && other) ev = ld_e(g.e, v);
+            if (seed_deficits && other) extra = seed_deficits > 0 ? ev < 0 : ev > 0;
             bool seed = v == g.root || extra;
+            if (cap_ok) {
+                const int ho = g.h[v];
+                g.h_prev[v] = ho;
+                if (other && ev > 0 && ho < N) excess++;
+                if (other && ev < 0 && ho > 0) raised++;
+            }
             g.h[v] = seed ? 0 : N;
-            if (g.bfs_cap && !seed && v != g.s && v != g.t && v != g.pinned && ld_e(g.e, v) > 0) excess++;
             if (seed) {
                 slots = g.row_len[v];
                 add = (slots + GR_CHUNK - 1) / GR_CHUNK;
@@ -481,9 +494,10 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
         }
         append_entries(add, slots, v, q0, &ctr->front[0]);
     }
-    if (g.bfs_cap) {
-        const long long x = wave_sum_i64(excess);
+    if (cap_ok) {
+        const long long x = wave_sum_i64(excess), r = wave_sum_i64(raised);
         if (lane_id() == 0 && x) atomicAdd(&ctr->bfs_total, (int)x);
+        if (lane_id() == 0 && r) atomicAdd(&ctr->bfs_raised, (int)r);
     }
     if (P.bid == 0 && threadIdx.x == 0) {
         // slots of every row that may be labelled, the seeds' included
@@ -535,8 +549,15 @@ __device__ __forceinline__ int excess_labelled(DevCounters* ctr, int lv) {
     return before + __hip_atomic_load(&ctr->bfs_disc[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The count to reach, or INT_MAX (never stop early) unless the relabel began
+// from a valid labelling with every deficient vertex at height 0: only then
+// are the old heights lower bounds on the new distances, which keeps the
+// labelling of a stopped BFS valid (see worklist_body).
 __device__ __forceinline__ int excess_total(DevCounters* ctr) {
-    return __hip_atomic_load(&ctr->bfs_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int ok = __hip_atomic_load(&ctr->bfs_ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int raised = __hip_atomic_load(&ctr->bfs_raised, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return ok && raised == 0 ? __hip_atomic_load(&ctr->bfs_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : INT_MAX;
 }
 
 __device__ __forceinline__ int discover(const DevGraph& g, DevCounters* ctr, const GrBits& bits, int lv, int v,
@@ -1095,8 +1116,13 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
                                               int32_t* wl2, DevCounters* ctr, int topology, int sign) {
     const int N = g.n;
     long long deficit = 0;
-    // after a capped relabel that stopped before level L, the vertices it did
-    // not reach get L + 1 (bfs_capped)
+    // after a capped relabel that stopped before level L, a vertex it did not
+    // reach gets max(L + 1, its old height).  That is a valid labelling: a
+    // residual slot between two such vertices keeps h(a) <= h(b) + 1 (it
+    // held for the old heights); from such a vertex a to a labelled b, b is
+    // at L (a level below L would have reached a) and the old h(a) <= old
+    // h(b) + 1 <= L + 1, the old heights being lower bounds on distances.
+    // Vertices at |V| stay there.
     const int cap_h = g.bfs_cap ? ctr->bfs_capped : 0;
     for (int base = P.bid * blockDim.x; base < N; base += P.nb * blockDim.x) {
         int v = base + threadIdx.x;
@@ -1106,7 +1132,7 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
             int64_t ev = g.e[v];
             int hv = g.h[v];
             if (cap_h && hv == N && v != g.pinned) {
-                hv = cap_h;
+                hv = max(cap_h, g.h_prev[v]);
                 g.h[v] = hv;
             }
             bool other = v != g.s && v != g.t;
@@ -1141,6 +1167,9 @@ __global__ void __launch_bounds__(256) k_build_worklist(DevGraph g, int32_t* wl0
     // the host knew whether the BFS ends there; a frontier still waiting at
     // guard_level means it did not, and this build is skipped
     if (guard_level >= 0 && (ctr->front[guard_level % 3] & 0xFFFFFFFFull) != 0) return;
+    // the heights are a valid labelling from here until the next relabel
+    // starts (push-relabel rounds with remove-invalid-edges keep it so)
+    if (g.bfs_cap && blockIdx.x == 0 && threadIdx.x == 0) ctr->lab_valid = 1;
     if (g.relab) {  // the rounds after this build start with no vertex marked as raised
         const int nw = (g.n + 31) >> 5;
         for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x) g.relab[w] = 0u;

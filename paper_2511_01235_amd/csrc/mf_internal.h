@@ -47,8 +47,10 @@ struct DevGraph {
                                          // worklist build clears it; remove-invalid-edges skips unset rows
     const int32_t* halt;                 // not null and set: the single-graph loop kernels leave at once
                                          // (a pipelined iteration queued behind the loop's last one)
-    int32_t bfs_cap;                     // 1: a relabel stops once every vertex with excess has its height
-                                         // (the rest get depth + 1: a valid labelling, not distances)
+    int32_t bfs_cap;                     // 1: a relabel that starts from a valid labelling with every sink
+                                         // at height 0 stops once every vertex with excess below |V| has its
+                                         // height; a vertex not reached keeps max(depth + 1, its old height)
+    int32_t* h_prev;                     // ... the old heights (copied by the relabel's init)
 };
 
 // Partial sums of algorithmic bytes: a kernel block adds into slot
@@ -89,7 +91,12 @@ struct DevCounters {
     int32_t bfs_disc[3];       // ... of them labelled at level lv, in bfs_disc[lv % 3]
     int32_t bfs_cum[3];        // ... labelled at levels <= lv, in bfs_cum[lv % 3]
     int32_t bfs_capped;        // ... > 0: it stopped before processing level bfs_capped - 1, whose
-                               //     frontier keeps that height; the rest get bfs_capped
+                               //     frontier keeps that height; the rest get bfs_capped or more
+    int32_t bfs_raised;        // ... deficient vertices above height 0 when it began (then no cap)
+    int32_t bfs_ok;            // ... it began from a valid labelling (lab_valid, taken by the init)
+    int32_t lab_valid;         // the heights are a valid labelling: set by a worklist build after a
+                               // finished relabel (the rounds behind it keep it so), cleared when the
+                               // next relabel starts and at the start of every solve
 };
 
 // KC_GR: multi-block BFS level launches; KC_GRS: the relabel's seeding and its

@@ -363,14 +363,14 @@ def test_dynamic_tiny_adversarial(seed):
             _cut_ok(n, s, t, side, cut, got, ms, md, mc)
 
 
-@pytest.mark.parametrize("cap", [1, 0])
+@pytest.mark.parametrize("cap", [0, -1])
 @pytest.mark.parametrize("warm", [False, True])
 @pytest.mark.parametrize("name,batches", [("er2000", 10), ("rmat12", 8), ("rmat14", 5),
                                           ("grid64", 5), ("grid256", 3)])
 def test_dynamic_workloads(name, batches, warm, cap):
     """Repairs against the oracle after every batch, cut certificates, with
-    relabels that stop once every vertex with excess has its height (cap 1)
-    or run to the end (0, the default)."""
+    relabels that stop once every vertex with excess has its height (cap 0,
+    the default) or run to the end (-1)."""
     g, stream, k, nb = gen.workload(name)
     o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
     with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, warm_start=warm, bfs_cap=cap) as G:
@@ -389,8 +389,9 @@ def test_dynamic_workloads(name, batches, warm, cap):
 def _comb_graph(side=64):
     """A side x side grid (4-connected, capacity 1000 both ways) drained into
     the sink t through one corner, and three vertices fed by the source at 10
-    that each reach the grid at 5, well inside it: every vertex with excess
-    reaches t at a depth well short of the grid's far side."""
+    that each reach the grid at 5, about 80 hops from t: the excess needs more
+    push-relabel rounds than one relabel's share (depth / 4), and every vertex
+    with excess sits well short of the grid's far corner (127 hops)."""
     s, t, xs, base = 0, 1, [2, 3, 4], 5
     gid = lambda r, c: base + r * side + c
     src, dst, cap = [], [], []
@@ -403,38 +404,40 @@ def _comb_graph(side=64):
                     cap += [1000, 1000]
     src.append(gid(0, 0)); dst.append(t); cap.append(1000)
     for i, x in enumerate(xs):
-        src += [s, x]; dst += [x, gid(10 + 5 * i, 10)]; cap += [10, 5]
+        src += [s, x]; dst += [x, gid(40 + 5 * i, 40)]; cap += [10, 5]
     n = base + side * side
-    return n, s, t, xs, np.array(src, np.int32), np.array(dst, np.int32), np.array(cap, np.int32)
+    feeds = np.array([gid(40 + 5 * i, 40) for i in range(3)], np.int32)
+    return (n, s, t, xs, feeds, np.array(src, np.int32), np.array(dst, np.int32),
+            np.array(cap, np.int32))
 
 
 @pytest.mark.parametrize("narrow,medium", [(0, 0), (-1, 1 << 30), (-1, -1)])
 def test_capped_relabel_stops_early(narrow, medium):
-    """With bfs_cap a solve's relabel stops once every vertex with excess has
-    its height: on a graph whose excess sits well short of the BFS's far end
-    the first relabel of the solve stops early (in the one-workgroup levels,
-    the cooperative mid-size levels or the multi-block levels), the value
-    and the cut match the oracle's, and without bfs_cap no relabel stops."""
-    n, s, t, xs, src, dst, cap = _comb_graph()
+    """By default (bfs_cap) the relabels of a solve that follow a round stop once
+    every vertex with excess below |V| has its height: on a graph whose
+    excess sits well short of the BFS's far end some relabel stops early (in
+    the one-workgroup levels, the cooperative mid-size levels or the
+    multi-block levels), the value and the cut match the oracle's, and
+    with bfs_cap = -1 no relabel stops."""
+    n, s, t, xs, feeds, src, dst, cap = _comb_graph()
     o = oracle.DynOracle(n, src, dst, cap, s, t)
     want = o.static()
     assert want == 15
-    for on in (1, 0):
+    for on in (0, -1):
         say("capped relabel", narrow, medium, on)
         with mf.MaxFlowGraph(n, src, dst, cap, s, t, bfs_cap=on, bfs_narrow_slots=narrow,
                              bfs_medium_slots=medium) as G:
             assert G.maxflow() == want
             capped = G.stats()["last_capped_relabels"]
-            assert (capped >= 1) if on else (capped == 0), capped
+            assert (capped >= 1) if on == 0 else (capped == 0), capped
             side, cut = G.min_cut()
             _cut_ok(n, s, t, side, cut, want, src, dst, cap)
     # a repair that raises the feeds: the graph handle and the oracle agree
-    u = np.array(xs, np.int32)
-    v = np.array([5 + (10 + 5 * i) * 64 + 10 for i in range(3)], np.int32)
+    u, v = np.array(xs, np.int32), feeds
     c = np.array([10, 10, 10], np.int32)
     want = o.apply(u, v, c)
     assert want == 30
-    with mf.MaxFlowGraph(n, src, dst, cap, s, t, bfs_cap=1, bfs_narrow_slots=narrow,
+    with mf.MaxFlowGraph(n, src, dst, cap, s, t, bfs_narrow_slots=narrow,
                          bfs_medium_slots=medium) as G:
         G.maxflow()
         assert G.apply_batch(u, v, c) == want
