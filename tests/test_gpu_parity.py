@@ -132,7 +132,7 @@ def test_push_rounds_between_relabels(name, div, scan, narrow):
 
 
 @pytest.mark.parametrize("narrow", [0, 16, 4096, 1 << 30])
-@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "rmat14", "grid64", "grid256"])
 def test_thin_frontier_levels_bit_exact(name, narrow):
     """BFS levels with frontiers of up to `narrow` slots run in one workgroup
     (0: never, 1 << 30: every level), handing larger ones to the multi-block
