@@ -94,6 +94,14 @@ struct mf_graph {
     int32_t rn_limit = 2048;         // worklists of up to this many vertices run rounds in one workgroup
     bool bfs_cap = true;             // solve relabels stop once every vertex with excess has a height
     int32_t medium_blocks = 16;      //     of this many 1024-thread blocks (0 where unsupported)
+    struct MedBufs {                 // their per-workgroup queue segments (made before a solve)
+        int4* q = nullptr;
+        int4* rec = nullptr;
+        unsigned long long* bar = nullptr;
+        int64_t seg = 0;
+        int blocks = 0;
+    };
+    MedBufs med, med2;               // main lane, pull lane
     bool coop_ok = false;            // the device supports cooperative launch
     std::atomic<bool> coop_broken{false};  // a cooperative launch failed: multi-block levels only
                                      // (set by either lane of a push-pull repair)
@@ -270,8 +278,17 @@ void free_round_lists(mf_graph* g) {
     g->epoch = 0;
 }
 
+void free_med(mf_graph* g, mf_graph::MedBufs& mb) {
+    dfree(g, mb.q);
+    dfree(g, mb.rec);
+    dfree(g, mb.bar);
+    mb.seg = 0;
+    mb.blocks = 0;
+}
+
 void free_lane2(mf_graph* g) {
     free_round_lists(g);
+    free_med(g, g->med2);
     dfree(g, g->q2[0]);
     dfree(g, g->q2[1]);
     g->q2_cap = 0;
@@ -289,6 +306,7 @@ void free_all(mf_graph* g) {
     if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
     g->cap_stream = nullptr;
     free_lane2(g);
+    free_med(g, g->med);
     if (g->ctr2_h) (void)hipHostFree(g->ctr2_h);
     g->ctr2_h = nullptr;
     free_structure(g);
@@ -392,6 +410,7 @@ hipError_t halloc(T** p, int64_t count) {
 // Every device buffer except the counters (the state is elsewhere by then).
 void free_device_state(mf_graph* g) {
     free_lane2(g);
+    free_med(g, g->med);
     free_structure(g);
     dfree(g, g->dg.e);
     dfree(g, g->dg.h);
@@ -513,8 +532,15 @@ struct Lane {
     mf::GrBits bits{};
     DevCounters* ctr = nullptr;
     DevCounters* ctr_h = nullptr;
+    mf::MedQueue mq{};      // mid-size levels' segments (mq.q null: none, multi-block levels instead)
+    int mq_blocks = 0;
     bool main = true;
 };
+
+void set_med(Lane& L, const mf_graph::MedBufs& mb) {
+    L.mq = mf::MedQueue{mb.q, mb.rec, mb.bar, mb.seg};
+    L.mq_blocks = mb.blocks;
+}
 
 Lane main_lane(mf_graph* g) {
     Lane L;
@@ -525,6 +551,7 @@ Lane main_lane(mf_graph* g) {
     L.bits = g->bits;
     L.ctr = g->ctr;
     L.ctr_h = g->ctr_h;
+    set_med(L, g->med);
     return L;
 }
 
@@ -589,10 +616,12 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out, in
     // small enough
     bool narrow = g->narrow_max > 0 && !g->trace_gr && (g->narrow_seed || !m.L.main);
     bool medium = false;  // set when a read finds a mid-size frontier waiting
+    const int64_t medium_cap = std::min<int64_t>(g->medium_max, m.L.mq.seg);
+    const int medium_grid = std::min<int>(g->medium_blocks, m.L.mq_blocks);
     auto mid_size = [&](int lv) {
         const int64_t slots = (int64_t)(m.L.ctr_h->front[lv % 3] >> 32);
-        return g->medium_blocks > 0 && !g->coop_broken && !g->trace_gr && slots > g->narrow_max &&
-               slots <= g->medium_max;
+        return medium_grid > 0 && m.L.mq.q && !g->coop_broken && !g->trace_gr && slots > g->narrow_max &&
+               slots <= medium_cap;
     };
     auto t_last = std::chrono::steady_clock::now();
     if (g->trace_gr) {
@@ -633,7 +662,7 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out, in
             hipError_t err = hipSuccess;
             timed(g, m.L, mf::KC_GRS, [&] {
                 err = mf::launch_gr_medium(m.dg, level, m.L.q[0], m.L.q[1], m.L.ctr, m.L.bits, g->tune,
-                                           g->medium_max, m.forward, g->medium_blocks, st);
+                                           medium_cap, m.forward, medium_grid, m.L.mq, st);
             });
             if (err != hipSuccess) {
                 (void)hipGetLastError();
@@ -645,6 +674,7 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out, in
                     g->poisoned = true;
                     return MF_ERR_DEVICE;
                 }
+                const int level_before = level;
                 level = m.L.ctr_h->levels;
                 const int cnt = (int)(unsigned)(m.L.ctr_h->front[level % 3] & 0xFFFFFFFFull);
                 if (cnt == 0) break;
@@ -652,6 +682,11 @@ mf_status global_relabel(mf_graph* g, const LoopMode& m, int64_t* levels_out, in
                     g->poisoned = true;
                     return MF_ERR_DEVICE;  // a BFS cannot have more than n levels
                 }
+                // the multi-block levels read the current frontier's bitmap,
+                // which the mid-size levels do not keep
+                if (level != level_before)
+                    timed(g, m.L, mf::KC_GRS,
+                          [&] { mf::launch_frontier_bitmap(m.L.q[level & 1], cnt, m.L.bits, level, st); });
                 chunk = g->first_chunk;
             }
             medium = false;  // a larger frontier waits: multi-block levels
@@ -776,6 +811,28 @@ mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const
 }
 
 // Buffers of the incremental worklists between relabels.
+// The mid-size levels' segments for the handle's settings: each workgroup
+// appends at most one entry per slot it scans, and those levels scan at most
+// medium_max slots (and fewer than the global queue holds).
+mf_status ensure_med(mf_graph* g, mf_graph::MedBufs& mb) {
+    const int blocks = std::min(g->medium_blocks, mf::MED_MAX_BLOCKS);
+    const int64_t seg = std::min<int64_t>(g->medium_max, g->q_cap);
+    if (blocks <= 0 || seg <= 0) {
+        free_med(g, mb);
+        return MF_OK;
+    }
+    if (mb.q && mb.blocks >= blocks && mb.seg >= seg) return MF_OK;
+    free_med(g, mb);
+    if (dalloc(g, &mb.q, 2 * (int64_t)blocks * seg) != hipSuccess || dalloc(g, &mb.rec, 2 * (int64_t)blocks) != hipSuccess ||
+        dalloc(g, &mb.bar, 1) != hipSuccess) {
+        free_med(g, mb);
+        return MF_ERR_OUT_OF_MEMORY;
+    }
+    mb.seg = seg;
+    mb.blocks = blocks;
+    return MF_OK;
+}
+
 mf_status ensure_round_lists(mf_graph* g) {
     if (g->act_list) return MF_OK;
     const int64_t n = g->n;
@@ -1419,7 +1476,7 @@ mf_status ensure_lane2(mf_graph* g) {
         mf::launch_clear_counters(g->ctr2, g->stream2);
         MF_HIP(hipStreamSynchronize(g->stream2));
     }
-    return MF_OK;
+    return ensure_med(g, g->med2);
 }
 
 // Section 5.2's O2 after a batch: the source side S of the last terminating
@@ -1460,6 +1517,7 @@ mf_status push_pull_phase(mf_graph* g) {
     L2.bits = g->bits2;
     L2.ctr = g->ctr2;
     L2.ctr_h = g->ctr2_h;
+    set_med(L2, g->med2);
     L2.main = false;
     int64_t v1 = 0, v2 = 0;
     mf_status rc2 = MF_OK;
@@ -1510,6 +1568,7 @@ mf_status prepare_loop(mf_graph* g) {
     if (rc == MF_OK && g->push_pull) rc = ensure_lane2(g);
     if (rc == MF_OK && g->bfs_cap && !g->dg.h_prev && dalloc(g, &g->dg.h_prev, g->n) != hipSuccess)
         rc = MF_ERR_OUT_OF_MEMORY;
+    if (rc == MF_OK) rc = ensure_med(g, g->med);
     return rc;
 }
 
@@ -1636,6 +1695,8 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
         return fail(MF_ERR_OUT_OF_MEMORY);
     rc = upload_structure(g, b, {});
     if (rc != MF_OK) return fail(rc);
+    rc = ensure_med(g, g->med);  // (needs q_cap)
+    if (rc != MF_OK) return fail(rc);
     mf::launch_fill_i32(g->need, 0, n, g->stream);
     mf::launch_fill_i32(g->dg.h, 0, n, g->stream);
     mf::launch_fill_i32(reinterpret_cast<int32_t*>(g->dg.e), 0, 2 * (int64_t)n, g->stream);
@@ -1645,8 +1706,9 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
         // several ms: pay it here rather than in the first solve (limit -1:
         // the kernel leaves at its first frontier check, changing nothing but
         // the level counter, which every relabel resets)
-        if (mf::launch_gr_medium(g->dg, 0, g->q[0], g->q[1], g->ctr, g->bits, g->tune, -1, false, g->medium_blocks,
-                                 g->stream) != hipSuccess) {
+        const mf::MedQueue mq{g->med.q, g->med.rec, g->med.bar, g->med.seg};
+        if (mf::launch_gr_medium(g->dg, 0, g->q[0], g->q[1], g->ctr, g->bits, g->tune, -1, false,
+                                 std::min(g->medium_blocks, g->med.blocks), mq, g->stream) != hipSuccess) {
             (void)hipGetLastError();
             g->coop_broken = true;
         }

@@ -1032,42 +1032,306 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
 
 // Mid-size frontiers (deep BFS of grid-like graphs, a few thousand to tens
 // of thousands of slots per level): a cooperative launch of a few 1024-thread
-// workgroups runs level after level of the multi-block level step (frontier
-// bitmaps kept up to date), separated by grid barriers -- a barrier of a few
-// arrivals costs less than a launch.  From level lv0 while the frontier
-// covers at most max_slots slots and the level goes top-down; stops at an
-// empty frontier, a larger one or a bottom-up level (not processed) or a
-// barrier error, and leaves the level to continue from in ctr->levels.  Every block reads the same counters after the barrier,
-// so all take the same exit.
+// workgroups runs top-down levels back to back, separated by grid barriers
+// -- a barrier of a few arrivals costs less than a launch.  Each workgroup
+// appends the vertices it labels to a segment of its own ({vertex, first
+// slot, slots}: one entry per vertex, whose row bounds are read once, when
+// it is labelled) and publishes its segment's counts in a record before the
+// barrier; after it, every workgroup reads all the records and so knows the
+// level's size, its direction and each segment's place in the level, with no
+// shared counter and no other read.  From level lv0 while the frontier
+// covers at most max_slots slots and the level goes top-down (the direction
+// rule of the multi-block levels); at an empty frontier the BFS is over, at a
+// capped relabel's stop it ends the same way, and a larger frontier or a
+// bottom-up level goes back to the global queue (GR_CHUNK pieces, as the
+// multi-block levels read it).  It keeps the visited bitmap, not the frontier
+// bitmaps (the host rebuilds the current one), and leaves the level to
+// continue from in ctr->levels and the counters the other level kernels read
+// (frontier ring, unvisited slots, capped-relabel counts) as they would have.
+// Every wait on the barrier is bounded: past the limit bar_err is set and
+// every workgroup leaves at the next check.
 constexpr int GRM_BLOCK = 1024;
+static_assert(MED_MAX_BLOCKS <= WAVE, "one record per lane of a wave");
+
+// Arrive on the launch's monotonic barrier counter (release) and wait until
+// all nb workgroups have arrived for round `round` (acquire).
+__device__ __forceinline__ void grid_sync_count(unsigned long long* bar, int nb, unsigned long long round,
+                                                DevCounters* ctr) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long target = (round + 1) * (unsigned long long)nb;
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > GRID_SYNC_SPIN_LIMIT) {
+                atomicOr(&ctr->bar_err, 1);
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
 
 template <bool FWD>
 __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, int2* q0, int2* q1,
                                                          DevCounters* ctr, GrBits bits, GrTune tune,
-                                                         long long max_slots) {
-    __shared__ unsigned long long s_front;
-    __shared__ int s_bad;
-    int lv = lv0;
-    for (; lv <= g.n; ++lv) {
-        if (threadIdx.x == 0) {
-            s_front = __hip_atomic_load(&ctr->front[lv % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_bad = __hip_atomic_load(&ctr->bar_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                                         long long max_slots, MedQueue mq) {
+    const int nb = (int)gridDim.x, bid = (int)blockIdx.x, tid = (int)threadIdx.x, lane = lane_id();
+    const int N = g.n;
+    const bool cap = g.bfs_cap != 0;
+    __shared__ int s_off[MED_MAX_BLOCKS + 1];   // entries of the segments before each one
+    __shared__ int s_choff[MED_MAX_BLOCKS + 1]; // ... their GR_CHUNK pieces (hand-back positions)
+    __shared__ int s_slots, s_bad;
+    __shared__ int s_cnt_b, s_ch_b, s_sl_b, s_disc_b;  // this workgroup's appends in the level
+    __shared__ int s_beg[GRM_BLOCK], s_pre[GRM_BLOCK + 1];
+    __shared__ int s_wsum[GRM_BLOCK / WAVE];
+    __shared__ long long s_mu;
+    __shared__ int s_lab, s_total;
+    int4* const seg_base = mq.q;
+    auto seg = [&](int ring, int b) { return seg_base + ((size_t)ring * nb + b) * mq.seg; };
+    // exclusive prefix sum over the workgroup, total in s_pre[GRM_BLOCK]
+    auto block_prefix = [&](int x) {
+        int wtot;
+        const int wex = wave_excl_scan(x, &wtot);
+        if (lane == 0) s_wsum[tid / WAVE] = wtot;
+        __syncthreads();
+        int woff = 0, total = 0;
+        for (int w = 0; w < GRM_BLOCK / WAVE; ++w) {
+            if (w < tid / WAVE) woff += s_wsum[w];
+            total += s_wsum[w];
+        }
+        s_pre[tid] = woff + wex;
+        if (tid == GRM_BLOCK - 1) s_pre[GRM_BLOCK] = total;
+        __syncthreads();
+        return s_pre[GRM_BLOCK];
+    };
+    unsigned long long round = 0;
+    // the incoming frontier (global queue, GR_CHUNK pieces) into segments of ring 0
+    int cnt0 = 0;
+    if (tid == 0) {
+        const unsigned long long f = __hip_atomic_load(&ctr->front[lv0 % 3], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+        s_slots = (int)(f >> 32);
+        s_cnt_b = (int)(unsigned)(f & 0xFFFFFFFFull);
+        s_mu = ctr->unv[(lv0 + 2) % 3];
+        s_lab = cap ? excess_labelled(ctr, lv0) : 0;
+        s_total = cap ? excess_total(ctr) : INT_MAX;
+        if (lv0 == 0 && bid == 0) ctr->seed_front = f;
+    }
+    __syncthreads();
+    cnt0 = s_cnt_b;
+    // nothing to do here (the host checks the same): the caller carries on from lv0
+    if (cnt0 == 0 || (long long)s_slots > max_slots) {
+        if (bid == 0 && tid == 0) ctr->levels = lv0;
+        return;
+    }
+    {
+        const int2* qin = (lv0 & 1) ? q1 : q0;
+        const int per = (cnt0 + nb - 1) / nb;
+        const int k0 = min(cnt0, bid * per), k1 = min(cnt0, bid * per + per);
+        int4* out = seg(0, bid);
+        int sl = 0;
+        for (int k = k0 + tid; k < k1; k += GRM_BLOCK) {
+            const int2 ent = qin[k];
+            const int len = min(g.row_len[ent.x] - ent.y, GR_CHUNK);
+            out[k - k0] = make_int4(ent.x, g.row_ptr[ent.x] + ent.y, len, 0);
+            sl += len;
+        }
+        const int bsl = (int)wave_sum_i64(sl);
+        if (tid == 0) s_sl_b = 0;
+        __syncthreads();
+        if (lane == 0 && bsl) atomicAdd(&s_sl_b, bsl);
+        __syncthreads();
+        if (tid == 0) mq.rec[bid] = make_int4(k1 - k0, k1 - k0, s_sl_b, 0);
+    }
+    grid_sync_count(mq.bar, nb, round++, ctr);
+    int lv = lv0, ring = 0, mode = 0;
+    unsigned long long scanned = 0, found = 0, staged = 0;
+    for (;;) {
+        // the level's records, one per lane of the first wave: sizes, and
+        // where each segment sits in the level
+        if (tid < WAVE) {
+            const int4 r = tid < nb ? mq.rec[(size_t)ring * nb + tid] : make_int4(0, 0, 0, 0);
+            int off_tot, ch_tot;
+            const int off = wave_excl_scan(r.x, &off_tot);
+            const int choff = wave_excl_scan(r.y, &ch_tot);
+            const int slots = (int)wave_sum_i64(r.z), disc = (int)wave_sum_i64(r.w);
+            if (tid < nb) {
+                s_off[tid] = off;
+                s_choff[tid] = choff;
+            }
+            if (tid == 0) {
+                s_off[nb] = off_tot;
+                s_choff[nb] = ch_tot;
+                s_slots = slots;
+                s_lab += lv > lv0 ? disc : 0;  // the vertices with excess labelled lv
+                s_bad = __hip_atomic_load(&ctr->bar_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         __syncthreads();
-        const unsigned long long front = s_front;
-        const int bad = s_bad;
-        __syncthreads();  // s_front / s_bad are rewritten next level
-        const long long cnt = (long long)(front & 0xFFFFFFFFull), fs = (long long)(front >> 32);
-        if (cnt == 0 || bad || fs > max_slots) break;
-        // a bottom-up level scans every unvisited vertex: the multi-block
-        // kernel's work (the direction rule as gr_level_step applies it)
-        const long long mu = ctr->unv[(lv + 2) % 3] - fs;
-        if (tune.bu_alpha > 0 && fs * tune.bu_alpha > mu && cnt * tune.bu_beta > (long long)g.n) break;
-        gr_level_step<FWD, GRM_BLOCK>(hw_par(), g, lv, (lv & 1) ? q1 : q0, (lv & 1) ? q0 : q1, ctr, bits, tune,
-                                      nullptr);
-        grid_sync(ctr);
+        const int cnt = s_off[nb];
+        const long long fs = s_slots;
+        if (s_bad) {
+            mode = 5;
+            break;
+        }
+        // 1: BFS over; 2: capped stop; 3: hand back (too large or bottom-up)
+        if (cnt == 0) mode = 1;
+        else if (s_lab >= s_total) mode = 2;
+        else if (fs > max_slots || lv >= N) mode = 3;
+        else if (tune.bu_alpha > 0 && fs * tune.bu_alpha > s_mu - fs && (long long)cnt * tune.bu_beta > (long long)N)
+            mode = 3;
+        if (mode) break;
+        __syncthreads();  // every thread has read s_mu above
+        if (tid == 0) {
+            s_mu -= fs;  // unvisited slots after this level's frontier
+            s_cnt_b = s_ch_b = s_sl_b = s_disc_b = 0;
+        }
+        // this workgroup's share of the level's entries, BS at a time
+        const int per = (cnt + nb - 1) / nb;
+        const int e0 = min(cnt, bid * per), e1 = min(cnt, bid * per + per);
+        int4* out = seg(ring ^ 1, bid);
+        for (int eb = e0; eb < e1; eb += GRM_BLOCK) {
+            const int e = eb + tid;
+            int len = 0;
+            if (e < e1) {
+                int lo = 0, hi = nb;  // the segment holding entry e
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_off[mid] <= e) lo = mid;
+                    else hi = mid;
+                }
+                const int4 ent = seg(ring, lo)[e - s_off[lo]];
+                s_beg[tid] = ent.y;
+                len = ent.z;
+                staged++;
+            }
+            const int total = block_prefix(len);
+            for (int base = 0; base < total; base += GR_TD_U * GRM_BLOCK) {
+                int vs[GR_TD_U];
+                int32_t r[GR_TD_U];
+#pragma unroll
+                for (int k = 0; k < GR_TD_U; ++k) {  // the loads of all U slots first
+                    const int i = base + k * GRM_BLOCK + tid;
+                    vs[k] = -1;
+                    r[k] = 0;
+                    if (i < total) {
+                        int lo = 0, hi = GRM_BLOCK;  // last staged entry with s_pre <= i
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_pre[mid] <= i) lo = mid;
+                            else hi = mid;
+                        }
+                        const int j = s_beg[lo] + (i - s_pre[lo]);
+                        const int2 c = g.cr[j];
+                        vs[k] = c.x;
+                        r[k] = FWD ? c.y : g.capsum[j] - c.y;
+                        scanned++;
+                    }
+                }
+                bool won[GR_TD_U];
+#pragma unroll
+                for (int k = 0; k < GR_TD_U; ++k) {
+                    const int v = vs[k];
+                    // the pinned vertex and the other side are marked visited at init
+                    won[k] = r[k] > 0 && !bit_of(bits.visited, v) && atomicCAS(&g.h[v], N, lv + 1) == N;
+                }
+                int rp[GR_TD_U], rl[GR_TD_U];
+                bool ex[GR_TD_U];
+#pragma unroll
+                for (int k = 0; k < GR_TD_U; ++k) {
+                    const int v = vs[k];
+                    rp[k] = 0;
+                    rl[k] = 0;
+                    ex[k] = false;
+                    if (won[k]) {
+                        set_bit(bits.visited, v);
+                        rp[k] = g.row_ptr[v];
+                        rl[k] = g.row_len[v];
+                        ex[k] = cap && v != g.s && v != g.t && ld_e(g.e, v) > 0;
+                        found++;
+                    }
+                }
+                int add = 0, ch = 0, sl = 0, disc = 0;
+#pragma unroll
+                for (int k = 0; k < GR_TD_U; ++k) {
+                    add += rl[k] > 0 ? 1 : 0;  // a vertex without slots needs no entry
+                    ch += (rl[k] + GR_CHUNK - 1) / GR_CHUNK;
+                    sl += rl[k];
+                    disc += ex[k] ? 1 : 0;
+                }
+                int atot;
+                const int aoff = wave_excl_scan(add, &atot);
+                const int wch = (int)wave_sum_i64(ch), wsl = (int)wave_sum_i64(sl), wdisc = (int)wave_sum_i64(disc);
+                int abase = 0;
+                if (lane == 0) {
+                    if (atot) abase = atomicAdd(&s_cnt_b, atot);
+                    if (wch) atomicAdd(&s_ch_b, wch);
+                    if (wsl) atomicAdd(&s_sl_b, wsl);
+                    if (wdisc) atomicAdd(&s_disc_b, wdisc);
+                }
+                int p = __shfl(abase, 0, WAVE) + aoff;
+#pragma unroll
+                for (int k = 0; k < GR_TD_U; ++k)
+                    if (rl[k] > 0) out[p++] = make_int4(vs[k], rp[k], rl[k], 0);
+            }
+            __syncthreads();  // s_beg / s_pre are restaged next round
+        }
+        __syncthreads();
+        if (tid == 0) mq.rec[(size_t)(ring ^ 1) * nb + bid] = make_int4(s_cnt_b, s_ch_b, s_sl_b, s_disc_b);
+        grid_sync_count(mq.bar, nb, round++, ctr);
+        ++lv;
+        ring ^= 1;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr->levels = lv;
+    if (mode == 3) {
+        // hand the level's frontier back to the global queue in GR_CHUNK
+        // pieces: this workgroup's segment from the prefix of pieces of the
+        // segments before it
+        int2* qout = (lv & 1) ? q1 : q0;
+        const int4* in = seg(ring, bid);
+        const int nmine = s_off[bid + 1] - s_off[bid];
+        int pos = s_choff[bid];
+        for (int eb = 0; eb < nmine; eb += GRM_BLOCK) {
+            const int e = eb + tid;
+            int4 ent = make_int4(0, 0, 0, 0);
+            int pieces = 0;
+            if (e < nmine) {
+                ent = in[e];
+                pieces = (ent.z + GR_CHUNK - 1) / GR_CHUNK;
+            }
+            const int tot = block_prefix(pieces);
+            const int at = pos + s_pre[tid];
+            // an entry read from the global queue at entry is one piece at its
+            // own offset; one labelled here starts at its row's first slot
+            const int first = e < nmine ? ent.y - g.row_ptr[ent.x] : 0;
+            for (int a = 0; a < pieces; ++a) qout[at + a] = make_int2(ent.x, first + a * GR_CHUNK);
+            pos += tot;
+            __syncthreads();
+        }
+    }
+    if (bid == 0 && tid == 0) {
+        const bool over = mode == 1 || mode == 2;
+        ctr->front[lv % 3] = over ? 0ull : (((unsigned long long)s_slots << 32) | (unsigned)s_choff[nb]);
+        ctr->front[(lv + 1) % 3] = 0;
+        ctr->front[(lv + 2) % 3] = 0;
+        if (mode == 2) ctr->bfs_capped = lv + 1;  // the height of every vertex not reached (or more)
+        ctr->unv[(lv + 2) % 3] = s_mu;
+        if (cap && lv > lv0) {  // the labelled count at level lv, as excess_labelled reads it
+            ctr->bfs_cum[(lv + 2) % 3] = s_lab;
+            ctr->bfs_disc[lv % 3] = 0;
+            ctr->bfs_disc[(lv + 1) % 3] = 0;
+        }
+        ctr->levels = lv;
+    }
+    if (g.count_bytes) {
+        // per scanned slot: col+res (8), capsum (4), the visited word (4);
+        // per staged entry its 16 bytes; per labelled vertex the CAS, its row
+        // bounds, excess, bitmap word and entry
+        const unsigned long long b = wave_sum_u64(16ull * scanned + 16ull * staged + 40ull * found);
+        if (lane == 0) add_bytes(g, KC_GRS, b);
+    }
 }
 
 // Global relabel and worklist build in one cooperative launch: seeds, then
@@ -2710,12 +2974,16 @@ hipError_t launch_gr_persistent(const DevGraph& g, int2* q0, int2* q1, DevCounte
 }
 
 hipError_t launch_gr_medium(const DevGraph& g, int lv0, int2* q0, int2* q1, DevCounters* ctr, const GrBits& bits,
-                            const GrTune& tune, long long max_slots, bool forward, int grid, hipStream_t st) {
+                            const GrTune& tune, long long max_slots, bool forward, int grid, const MedQueue& mq,
+                            hipStream_t st) {
+    if (!mq.q || grid < 1 || grid > MED_MAX_BLOCKS || max_slots > mq.seg) return hipErrorInvalidValue;
     DevGraph gg = g;
     GrBits bb = bits;
     GrTune tt = tune;
     tt.lds = 0;
-    void* args[] = {&gg, &lv0, &q0, &q1, &ctr, &bb, &tt, &max_slots};
+    MedQueue mm = mq;
+    k_set_i64<<<1, 64, 0, st>>>(reinterpret_cast<long long*>(mq.bar), 0);  // the barrier counts from zero
+    void* args[] = {&gg, &lv0, &q0, &q1, &ctr, &bb, &tt, &max_slots, &mm};
     const void* fn = forward ? reinterpret_cast<const void*>(&k_gr_medium<true>)
                              : reinterpret_cast<const void*>(&k_gr_medium<false>);
     return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(GRM_BLOCK), args, 0, st);

@@ -108,6 +108,19 @@ enum KernelClass { KC_GR = 0, KC_PR = 1, KC_RIE = 2, KC_WL = 3, KC_BATCH = 4, KC
 constexpr int BIN0_MAX = 16;
 constexpr int BIN1_MAX = 512;
 constexpr int BLOCK_PR = 1024;
+// Per-workgroup queue segments of the mid-size BFS levels (one cooperative
+// launch of up to MED_MAX_BLOCKS workgroups): two rings of `blocks` segments
+// of `seg` entries {vertex, first slot, slots, 0}, one record per segment and
+// ring {entries, GR_CHUNK pieces, slots, vertices with excess}, and the
+// launch's barrier counter.
+constexpr int MED_MAX_BLOCKS = 64;
+struct MedQueue {
+    int4* q;
+    int4* rec;
+    unsigned long long* bar;
+    long long seg;
+};
+
 // Global-relabel frontier entries cover at most GR_CHUNK slots of a row.
 constexpr int GR_CHUNK = 256;
 // Direction rule (Beamer, Asanovic, Patterson's direction-optimizing BFS:
@@ -309,7 +322,8 @@ void launch_gr_narrow(const DevGraph& g, int lv0, int2* q0, int2* q1, DevCounter
 // while the frontier covers at most max_slots slots (ctr->levels: where to
 // continue; ctr->bar_err set if a grid barrier gave up)
 hipError_t launch_gr_medium(const DevGraph& g, int lv0, int2* q0, int2* q1, DevCounters* ctr, const GrBits& bits,
-                            const GrTune& tune, long long max_slots, bool forward, int grid, hipStream_t st);
+                            const GrTune& tune, long long max_slots, bool forward, int grid, const MedQueue& mq,
+                            hipStream_t st);
 // zero the three frontier bitmaps, then set the current level's from its queue
 void launch_frontier_bitmap(const int2* q, int cnt, const GrBits& bits, int level, hipStream_t st);
 int64_t relayout_tiles(int32_t V);
