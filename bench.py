@@ -56,8 +56,9 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 40; batch512: 3 rounds, the workload being one batch per graph)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 2; batch512: 1)")
     ap.add_argument("--workload", default="rmat20",
                     help="one of " + ", ".join(sorted(WORKLOADS)) + ", or a scaled generator workload "
                          "(rmat<scale>, grid<width>)")
@@ -93,6 +94,10 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="serve64: offered rate as a fraction of the measured saturation throughput")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 3 if args.workload == "batch512" else 40
+    if args.warmup is None:
+        args.warmup = 1 if args.workload == "batch512" else 2
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each graph or batch "
               "stream runs on one device); run with --gpus 1", file=sys.stderr)
@@ -250,8 +255,11 @@ def main():
         G.profile(0)
     G.close()
 
-    # roofline of the dominant kernel class
-    cls = "global_relabel"
+    # roofline of the dominant kernel class: the relabel's BFS levels, in
+    # the multi-block level kernel (RMAT, random graphs) or in the seeding,
+    # one-workgroup and cooperative mid-size level kernels (grids), whichever
+    # took longer
+    cls = max(("global_relabel", "relabel_seed_narrow"), key=lambda c: prof["kernel_ms"][c])
     if args.profile_all:
         cls = max(prof["kernel_ms"], key=lambda c: prof["kernel_ms"][c])
         log("kernel ms by class: " + json.dumps({c: round(x, 3) for c, x in prof["kernel_ms"].items() if x}))
@@ -268,7 +276,10 @@ def main():
     traffic = None
     if cls == "global_relabel" and not args.cold_start and args.relabel_mode == 0:
         traffic = recorded_traffic(f"k_gr_level_{args.workload}", os.path.join(ROOT, "profiles"))
-    roofline = {"bound": "hbm", "kernel_class": cls, "achieved": round(achieved, 2),
+    kernel_names = {"global_relabel": "k_gr_level",
+                    "relabel_seed_narrow": "k_gr_init, k_gr_narrow, k_gr_medium"}
+    roofline = {"bound": "hbm", "kernel_class": cls, "kernel": kernel_names.get(cls, cls),
+                "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": traffic, "launches": launches,
                 "avg_launch_us": round(kms * 1e3 / launches, 3) if launches else None,
@@ -387,8 +398,10 @@ def bench_batched(args, mf, gen, torch, stream):
     # the same work one graph at a time
     single_static_ms, single_step_ms = 0.0, [0.0] * args.steps
     for i, g in enumerate(graphs):
+        # the pool's row slack (2 slots per row), so that both sides re-lay
+        # rows alike
         with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t, stream=stream, device=0,
-                             kernel_cycles=args.kc, warm_start=not args.cold_start) as G:
+                             kernel_cycles=args.kc, warm_start=not args.cold_start, insert_slack_min=2) as G:
             torch.cuda.synchronize()
             a = time.perf_counter()
             v = G.maxflow()
@@ -423,7 +436,7 @@ def bench_batched(args, mf, gen, torch, stream):
         "batched_speedup_static": round(single_static_ms / static_ms, 3),
         "graphs_per_s_static": round(512 / (static_ms * 1e-3), 1),
         "tuned": tuned,
-        "per_instance_options": "defaults",
+        "per_instance_options": "defaults, with the pool's row slack (insert_slack_min 2)",
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -664,7 +677,7 @@ def cpu_baseline(g, batches_np, static_val, gpu_values, budget_s):
         raise SystemExit(f"oracle static value {v} != GPU {static_val}")
     spent = static_s
     times = []
-    for i, (u, vv, c) in enumerate(batches_np):
+    for i, (u, vv, c) in enumerate(batches_np[:len(gpu_values)]):
         if spent > budget_s and times:
             break
         a = time.perf_counter()

@@ -104,7 +104,7 @@ typedef struct mf_options {
      * default; on/off switches take 1 = on, -1 = off. */
     int32_t bfs_first_chunk;   /* BFS levels launched before the host first checks whether the
                                   BFS is over (a relabel of depth d launches max(this, d + 1));
-                                  <= 0: 10 */
+                                  <= 0: 7 */
     int32_t bfs_narrow_slots;  /* frontiers of at most this many slots run in one workgroup, many
                                   levels per launch; 0: 4096, < 0: never */
     int32_t bfs_medium_slots;  /* larger frontiers up to this many slots run in one cooperative

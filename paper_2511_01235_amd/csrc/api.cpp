@@ -76,7 +76,7 @@ struct mf_graph {
     mf::GrBits bits{};
     mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0, 0};
     int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
-    int first_chunk = 10;     // BFS levels launched before the first frontier check (at least)
+    int first_chunk = 7;      // BFS levels launched before the first frontier check (at least)
     bool trace_gr = false;    // MF_GR_TRACE: one level per launch, each printed to stderr
     bool narrow_seed = true;  // start relabels in one workgroup (the last one's seeds were few enough)
     int32_t last_depth = 0;   // BFS levels of the last global relabel
@@ -451,7 +451,7 @@ void apply_tuning(mf_graph* g, const mf::Tuning& t) {
 // Loop and relabel settings of a handle from its options (0 = default).
 void apply_loop_options(mf_graph* g, const mf_options& o) {
     auto on = [](int32_t v, bool dflt) { return v > 0 ? true : v < 0 ? false : dflt; };
-    g->first_chunk = o.bfs_first_chunk > 0 ? o.bfs_first_chunk : 10;
+    g->first_chunk = o.bfs_first_chunk > 0 ? o.bfs_first_chunk : 7;
     g->narrow_max = o.bfs_narrow_slots < 0 ? 0 : o.bfs_narrow_slots > 0 ? o.bfs_narrow_slots : 4096;
     g->medium_max = o.bfs_medium_slots < 0 ? 0 : o.bfs_medium_slots > 0 ? o.bfs_medium_slots : 65536;
     g->medium_blocks = o.bfs_medium_blocks > 0 ? o.bfs_medium_blocks : 16;
