@@ -1531,7 +1531,10 @@ __device__ __forceinline__ void scan_group(const DevGraph& g, int b, int end, un
 }
 
 constexpr int PR_UNROLL = 4;
-constexpr int PR_UNROLL_BLOCK = 8;   // rows above the wave bin: more loads in flight per lane
+// Rows above the wave bin: loads in flight per lane.  Four keep the kernel
+// within 64 VGPRs, so that two 1024-thread workgroups fit a CU (eight: 80
+// VGPRs and one workgroup per CU; rmat20 repairs 1.26 -> 1.20 ms).
+constexpr int PR_UNROLL_BLOCK = 4;
 
 // Per-vertex bodies of Algorithm 2; each returns the algorithmic bytes it
 // moved.  A relabel is followed by the push of the next cycle on the same
@@ -1763,7 +1766,7 @@ __device__ __forceinline__ unsigned long long pr_block_item(DevGraph& g, int u, 
 }
 
 template <bool PULL>
-__global__ void __launch_bounds__(BLOCK_PR) k_pr_block(DevGraph g, const int32_t* wl, int count,
+__global__ void __launch_bounds__(BLOCK_PR, 8) k_pr_block(DevGraph g, const int32_t* wl, int count,
                                                        int kc, DevCounters* ctr, const int32_t* dcount) {
     if (halted(g)) return;
     (void)ctr;
