@@ -96,8 +96,7 @@ struct mf_graph {
     int32_t medium_blocks = 16;      //     of this many 1024-thread blocks (0 where unsupported)
     struct MedBufs {                 // their per-workgroup queue segments (made before a solve)
         int4* q = nullptr;
-        int4* rec = nullptr;
-        unsigned long long* bar = nullptr;
+        unsigned long long* rec = nullptr;
         int64_t seg = 0;
         int blocks = 0;
     };
@@ -281,7 +280,6 @@ void free_round_lists(mf_graph* g) {
 void free_med(mf_graph* g, mf_graph::MedBufs& mb) {
     dfree(g, mb.q);
     dfree(g, mb.rec);
-    dfree(g, mb.bar);
     mb.seg = 0;
     mb.blocks = 0;
 }
@@ -538,7 +536,7 @@ struct Lane {
 };
 
 void set_med(Lane& L, const mf_graph::MedBufs& mb) {
-    L.mq = mf::MedQueue{mb.q, mb.rec, mb.bar, mb.seg};
+    L.mq = mf::MedQueue{mb.q, mb.rec, mb.seg};
     L.mq_blocks = mb.blocks;
 }
 
@@ -813,18 +811,18 @@ mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const
 // Buffers of the incremental worklists between relabels.
 // The mid-size levels' segments for the handle's settings: each workgroup
 // appends at most one entry per slot it scans, and those levels scan at most
-// medium_max slots (and fewer than the global queue holds).
+// medium_max slots (and fewer than the global queue holds; larger frontiers
+// than MED_MAX_SEG slots go to the multi-block levels).
 mf_status ensure_med(mf_graph* g, mf_graph::MedBufs& mb) {
     const int blocks = std::min(g->medium_blocks, mf::MED_MAX_BLOCKS);
-    const int64_t seg = std::min<int64_t>(g->medium_max, g->q_cap);
+    const int64_t seg = std::min<int64_t>(std::min<int64_t>(g->medium_max, g->q_cap), mf::MED_MAX_SEG);
     if (blocks <= 0 || seg <= 0) {
         free_med(g, mb);
         return MF_OK;
     }
     if (mb.q && mb.blocks >= blocks && mb.seg >= seg) return MF_OK;
     free_med(g, mb);
-    if (dalloc(g, &mb.q, 2 * (int64_t)blocks * seg) != hipSuccess || dalloc(g, &mb.rec, 2 * (int64_t)blocks) != hipSuccess ||
-        dalloc(g, &mb.bar, 1) != hipSuccess) {
+    if (dalloc(g, &mb.q, 2 * (int64_t)blocks * seg) != hipSuccess || dalloc(g, &mb.rec, 3 * (int64_t)blocks) != hipSuccess) {
         free_med(g, mb);
         return MF_ERR_OUT_OF_MEMORY;
     }
@@ -1706,7 +1704,7 @@ mf_status mf_graph_load(int32_t n, int64_t m, const int32_t* src, const int32_t*
         // several ms: pay it here rather than in the first solve (limit -1:
         // the kernel leaves at its first frontier check, changing nothing but
         // the level counter, which every relabel resets)
-        const mf::MedQueue mq{g->med.q, g->med.rec, g->med.bar, g->med.seg};
+        const mf::MedQueue mq{g->med.q, g->med.rec, g->med.seg};
         if (mf::launch_gr_medium(g->dg, 0, g->q[0], g->q[1], g->ctr, g->bits, g->tune, -1, false,
                                  std::min(g->medium_blocks, g->med.blocks), mq, g->stream) != hipSuccess) {
             (void)hipGetLastError();

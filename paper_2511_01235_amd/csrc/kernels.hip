@@ -1039,7 +1039,10 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
 // it is labelled) and publishes its segment's counts in a record before the
 // barrier; after it, every workgroup reads all the records and so knows the
 // level's size, its direction and each segment's place in the level, with no
-// shared counter and no other read.  From level lv0 while the frontier
+// shared counter and no other read.  The records are the barrier: each is
+// one 64-bit word carrying the level it belongs to, stored with release
+// order after the workgroup's appends, and a level starts when every
+// workgroup's record of it is there.  From level lv0 while the frontier
 // covers at most max_slots slots and the level goes top-down (the direction
 // rule of the multi-block levels); at an empty frontier the BFS is over, at a
 // capped relabel's stop it ends the same way, and a larger frontier or a
@@ -1053,25 +1056,56 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
 constexpr int GRM_BLOCK = 1024;
 static_assert(MED_MAX_BLOCKS <= WAVE, "one record per lane of a wave");
 
-// Arrive on the launch's monotonic barrier counter (release) and wait until
-// all nb workgroups have arrived for round `round` (acquire).
-__device__ __forceinline__ void grid_sync_count(unsigned long long* bar, int nb, unsigned long long round,
-                                                DevCounters* ctr) {
+// A segment's record: bits 0..7 the tag of the level it belongs to (1..255,
+// the launch's level count modulo 255; 0: not written in this launch), then
+// the segment's entries and its vertices with excess (MED_CNT_BITS each) and
+// its slots (the rest, saturating: past max_slots the level is handed back
+// anyway).  Entries per segment stay below 2^MED_CNT_BITS (MED_MAX_SEG).
+constexpr int MED_CNT_BITS = 17;
+constexpr int MED_SLOT_BITS = 64 - 8 - 2 * MED_CNT_BITS;
+static_assert(MED_MAX_SEG < (1 << MED_CNT_BITS), "segment entries fit a record");
+
+__device__ __forceinline__ unsigned med_tag(int k) { return (unsigned)((k - 1) % 255) + 1u; }
+
+__device__ __forceinline__ unsigned long long med_record(unsigned tag, int cnt, int disc, int slots) {
+    const unsigned long long smax = (1ull << MED_SLOT_BITS) - 1;
+    const unsigned long long sl = (unsigned long long)slots < smax ? (unsigned long long)slots : smax;
+    return (unsigned long long)tag | ((unsigned long long)cnt << 8) | ((unsigned long long)disc << (8 + MED_CNT_BITS)) |
+           (sl << (8 + 2 * MED_CNT_BITS));
+}
+
+// Publish this workgroup's record once every thread's stores are done
+// (release: a workgroup that sees the record sees the segment).
+__device__ __forceinline__ void med_publish(unsigned long long* rec, unsigned long long v) {
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long target = (round + 1) * (unsigned long long)nb;
-        unsigned spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > GRID_SYNC_SPIN_LIMIT) {
-                atomicOr(&ctr->bar_err, 1);
-                break;
-            }
+    if (threadIdx.x == 0) __hip_atomic_store(rec, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by the first wave: wait until the records of all nb workgroups in
+// `rec` carry `tag`, then return lane b's.  The wait is bounded: past the
+// limit bar_err is set and *bad returned true.  A ring's record of level k
+// cannot be overwritten (by level k + 2) before every workgroup has read
+// it: writing level k + 2 needs every record of level k + 1, which each
+// workgroup publishes only after reading level k.
+__device__ __forceinline__ unsigned long long med_gather(const unsigned long long* rec, int nb, unsigned tag,
+                                                         DevCounters* ctr, bool* bad) {
+    const int lane = lane_id();
+    unsigned long long v = 0;
+    unsigned spins = 0;
+    *bad = false;
+    for (;;) {
+        if (lane < nb) v = __hip_atomic_load(&rec[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool ok = lane >= nb || (unsigned)(v & 0xFFull) == tag;
+        if (__all(ok)) break;  // wave-uniform
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > GRID_SYNC_SPIN_LIMIT) {
+            if (lane == 0) atomicOr(&ctr->bar_err, 1);
+            *bad = true;
+            break;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return lane < nb ? v : 0ull;
 }
 
 template <bool FWD>
@@ -1082,9 +1116,9 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
     const int N = g.n;
     const bool cap = g.bfs_cap != 0;
     __shared__ int s_off[MED_MAX_BLOCKS + 1];   // entries of the segments before each one
-    __shared__ int s_choff[MED_MAX_BLOCKS + 1]; // ... their GR_CHUNK pieces (hand-back positions)
+    __shared__ int s_choff[MED_MAX_BLOCKS + 1]; // GR_CHUNK pieces before each one (hand-back)
     __shared__ int s_slots, s_bad;
-    __shared__ int s_cnt_b, s_ch_b, s_sl_b, s_disc_b;  // this workgroup's appends in the level
+    __shared__ int s_cnt_b, s_sl_b, s_disc_b;  // this workgroup's appends in the level
     __shared__ int s_beg[GRM_BLOCK], s_pre[GRM_BLOCK + 1];
     __shared__ int s_wsum[GRM_BLOCK / WAVE];
     __shared__ long long s_mu;
@@ -1107,7 +1141,6 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
         __syncthreads();
         return s_pre[GRM_BLOCK];
     };
-    unsigned long long round = 0;
     // the incoming frontier (global queue, GR_CHUNK pieces) into segments of ring 0
     int cnt0 = 0;
     if (tid == 0) {
@@ -1144,30 +1177,28 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
         __syncthreads();
         if (lane == 0 && bsl) atomicAdd(&s_sl_b, bsl);
         __syncthreads();
-        if (tid == 0) mq.rec[bid] = make_int4(k1 - k0, k1 - k0, s_sl_b, 0);
+        med_publish(&mq.rec[bid], med_record(med_tag(1), k1 - k0, 0, s_sl_b));
     }
-    grid_sync_count(mq.bar, nb, round++, ctr);
     int lv = lv0, ring = 0, mode = 0;
     unsigned long long scanned = 0, found = 0, staged = 0;
     for (;;) {
-        // the level's records, one per lane of the first wave: sizes, and
-        // where each segment sits in the level
+        // the level's records, one per lane of the first wave (waiting for
+        // them is the level barrier): sizes, and where each segment sits
         if (tid < WAVE) {
-            const int4 r = tid < nb ? mq.rec[(size_t)ring * nb + tid] : make_int4(0, 0, 0, 0);
-            int off_tot, ch_tot;
-            const int off = wave_excl_scan(r.x, &off_tot);
-            const int choff = wave_excl_scan(r.y, &ch_tot);
-            const int slots = (int)wave_sum_i64(r.z), disc = (int)wave_sum_i64(r.w);
-            if (tid < nb) {
-                s_off[tid] = off;
-                s_choff[tid] = choff;
-            }
+            bool bad;
+            const unsigned long long r = med_gather(mq.rec + (size_t)ring * nb, nb, med_tag(lv - lv0 + 1), ctr, &bad);
+            const int rc = (int)((r >> 8) & ((1u << MED_CNT_BITS) - 1));
+            const int rd = (int)((r >> (8 + MED_CNT_BITS)) & ((1u << MED_CNT_BITS) - 1));
+            const int rs = (int)(r >> (8 + 2 * MED_CNT_BITS));
+            int off_tot;
+            const int off = wave_excl_scan(rc, &off_tot);
+            const int slots = (int)wave_sum_i64(rs), disc = (int)wave_sum_i64(rd);
+            if (tid < nb) s_off[tid] = off;
             if (tid == 0) {
                 s_off[nb] = off_tot;
-                s_choff[nb] = ch_tot;
                 s_slots = slots;
                 s_lab += lv > lv0 ? disc : 0;  // the vertices with excess labelled lv
-                s_bad = __hip_atomic_load(&ctr->bar_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s_bad = bad || __hip_atomic_load(&ctr->bar_err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         __syncthreads();
@@ -1187,7 +1218,7 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
         __syncthreads();  // every thread has read s_mu above
         if (tid == 0) {
             s_mu -= fs;  // unvisited slots after this level's frontier
-            s_cnt_b = s_ch_b = s_sl_b = s_disc_b = 0;
+            s_cnt_b = s_sl_b = s_disc_b = 0;
         }
         // this workgroup's share of the level's entries, BS at a time
         const int per = (cnt + nb - 1) / nb;
@@ -1254,21 +1285,19 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
                         found++;
                     }
                 }
-                int add = 0, ch = 0, sl = 0, disc = 0;
+                int add = 0, sl = 0, disc = 0;
 #pragma unroll
                 for (int k = 0; k < GR_TD_U; ++k) {
                     add += rl[k] > 0 ? 1 : 0;  // a vertex without slots needs no entry
-                    ch += (rl[k] + GR_CHUNK - 1) / GR_CHUNK;
                     sl += rl[k];
                     disc += ex[k] ? 1 : 0;
                 }
                 int atot;
                 const int aoff = wave_excl_scan(add, &atot);
-                const int wch = (int)wave_sum_i64(ch), wsl = (int)wave_sum_i64(sl), wdisc = (int)wave_sum_i64(disc);
+                const int wsl = (int)wave_sum_i64(sl), wdisc = (int)wave_sum_i64(disc);
                 int abase = 0;
                 if (lane == 0) {
                     if (atot) abase = atomicAdd(&s_cnt_b, atot);
-                    if (wch) atomicAdd(&s_ch_b, wch);
                     if (wsl) atomicAdd(&s_sl_b, wsl);
                     if (wdisc) atomicAdd(&s_disc_b, wdisc);
                 }
@@ -1280,18 +1309,35 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
             __syncthreads();  // s_beg / s_pre are restaged next round
         }
         __syncthreads();
-        if (tid == 0) mq.rec[(size_t)(ring ^ 1) * nb + bid] = make_int4(s_cnt_b, s_ch_b, s_sl_b, s_disc_b);
-        grid_sync_count(mq.bar, nb, round++, ctr);
+        med_publish(&mq.rec[(size_t)(ring ^ 1) * nb + bid], med_record(med_tag(lv - lv0 + 2), s_cnt_b, s_disc_b, s_sl_b));
         ++lv;
         ring ^= 1;
     }
     if (mode == 3) {
         // hand the level's frontier back to the global queue in GR_CHUNK
-        // pieces: this workgroup's segment from the prefix of pieces of the
-        // segments before it
+        // pieces: each workgroup counts its segment's pieces and publishes
+        // the count (a third ring of records); its own go after the pieces
+        // of the segments before it
         int2* qout = (lv & 1) ? q1 : q0;
         const int4* in = seg(ring, bid);
         const int nmine = s_off[bid + 1] - s_off[bid];
+        int mine = 0;
+        for (int e = tid; e < nmine; e += GRM_BLOCK) mine += (in[e].z + GR_CHUNK - 1) / GR_CHUNK;
+        const int wmine = (int)wave_sum_i64(mine);
+        if (tid == 0) s_cnt_b = 0;
+        __syncthreads();
+        if (lane == 0 && wmine) atomicAdd(&s_cnt_b, wmine);
+        __syncthreads();
+        med_publish(&mq.rec[(size_t)2 * nb + bid], (unsigned long long)s_cnt_b << 8 | 1ull);
+        if (tid < WAVE) {
+            bool bad;
+            const unsigned long long r = med_gather(mq.rec + (size_t)2 * nb, nb, 1u, ctr, &bad);
+            int tot;
+            const int off = wave_excl_scan((int)(r >> 8), &tot);
+            if (tid < nb) s_choff[tid] = off;
+            if (tid == 0) s_choff[nb] = tot;
+        }
+        __syncthreads();
         int pos = s_choff[bid];
         for (int eb = 0; eb < nmine; eb += GRM_BLOCK) {
             const int e = eb + tid;
@@ -2985,7 +3031,7 @@ hipError_t launch_gr_medium(const DevGraph& g, int lv0, int2* q0, int2* q1, DevC
     GrTune tt = tune;
     tt.lds = 0;
     MedQueue mm = mq;
-    k_set_i64<<<1, 64, 0, st>>>(reinterpret_cast<long long*>(mq.bar), 0);  // the barrier counts from zero
+    launch_fill_i32(reinterpret_cast<int32_t*>(mq.rec), 0, 6 * (int64_t)grid, st);  // no record of this launch yet
     void* args[] = {&gg, &lv0, &q0, &q1, &ctr, &bb, &tt, &max_slots, &mm};
     const void* fn = forward ? reinterpret_cast<const void*>(&k_gr_medium<true>)
                              : reinterpret_cast<const void*>(&k_gr_medium<false>);

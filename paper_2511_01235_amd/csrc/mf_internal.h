@@ -110,14 +110,14 @@ constexpr int BIN1_MAX = 512;
 constexpr int BLOCK_PR = 1024;
 // Per-workgroup queue segments of the mid-size BFS levels (one cooperative
 // launch of up to MED_MAX_BLOCKS workgroups): two rings of `blocks` segments
-// of `seg` entries {vertex, first slot, slots, 0}, one record per segment and
-// ring {entries, GR_CHUNK pieces, slots, vertices with excess}, and the
-// launch's barrier counter.
+// of `seg` entries {vertex, first slot, slots, 0} (at most MED_MAX_SEG), and
+// three rings of one 64-bit record per workgroup (the two level rings and
+// the hand-back's piece counts), cleared before every launch.
 constexpr int MED_MAX_BLOCKS = 64;
+constexpr int MED_MAX_SEG = (1 << 17) - 1;
 struct MedQueue {
     int4* q;
-    int4* rec;
-    unsigned long long* bar;
+    unsigned long long* rec;
     long long seg;
 };
 
