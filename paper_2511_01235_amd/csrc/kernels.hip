@@ -1055,6 +1055,11 @@ __device__ __forceinline__ void worklist_body(const Par& P, const DevGraph& g, i
 // every workgroup leaves at the next check.
 constexpr int GRM_BLOCK = 1024;
 static_assert(MED_MAX_BLOCKS <= WAVE, "one record per lane of a wave");
+// A workgroup also keeps the first MED_OWN entries it appends in LDS: when
+// every segment of a level fits there and none holds more than about twice
+// its share, each workgroup takes its own segment from LDS (no gather of
+// the level's entries, no search for their segment).
+constexpr int MED_OWN = 1024;
 
 // A segment's record: bits 0..7 the tag of the level it belongs to (1..255,
 // the launch's level count modulo 255; 0: not written in this launch), then
@@ -1120,6 +1125,8 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
     __shared__ int s_slots, s_bad;
     __shared__ int s_cnt_b, s_sl_b, s_disc_b;  // this workgroup's appends in the level
     __shared__ int s_beg[GRM_BLOCK], s_pre[GRM_BLOCK + 1];
+    __shared__ int4 s_own[2][MED_OWN];   // the first entries of this workgroup's segment, per ring
+    __shared__ int s_own_mode;
     __shared__ int s_wsum[GRM_BLOCK / WAVE];
     __shared__ long long s_mu;
     __shared__ int s_lab, s_total;
@@ -1169,7 +1176,9 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
         for (int k = k0 + tid; k < k1; k += GRM_BLOCK) {
             const int2 ent = qin[k];
             const int len = min(g.row_len[ent.x] - ent.y, GR_CHUNK);
-            out[k - k0] = make_int4(ent.x, g.row_ptr[ent.x] + ent.y, len, 0);
+            const int4 e4 = make_int4(ent.x, g.row_ptr[ent.x] + ent.y, len, 0);
+            out[k - k0] = e4;
+            if (k - k0 < MED_OWN) s_own[0][k - k0] = e4;
             sl += len;
         }
         const int bsl = (int)wave_sum_i64(sl);
@@ -1193,8 +1202,13 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
             int off_tot;
             const int off = wave_excl_scan(rc, &off_tot);
             const int slots = (int)wave_sum_i64(rs), disc = (int)wave_sum_i64(rd);
+            int cmax = rc;  // the largest segment
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) cmax = max(cmax, __shfl_xor(cmax, d, WAVE));
             if (tid < nb) s_off[tid] = off;
             if (tid == 0) {
+                const int share = (off_tot + nb - 1) / nb;
+                s_own_mode = cmax <= MED_OWN && cmax <= 2 * share + 64;
                 s_off[nb] = off_tot;
                 s_slots = slots;
                 s_lab += lv > lv0 ? disc : 0;  // the vertices with excess labelled lv
@@ -1220,21 +1234,31 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
             s_mu -= fs;  // unvisited slots after this level's frontier
             s_cnt_b = s_sl_b = s_disc_b = 0;
         }
-        // this workgroup's share of the level's entries, BS at a time
+        // this workgroup's entries of the level, BS at a time: its own
+        // segment from LDS when the level is balanced, else an equal share
+        // of the level's entries from the segments in memory
+        const bool own = s_own_mode != 0;
         const int per = (cnt + nb - 1) / nb;
-        const int e0 = min(cnt, bid * per), e1 = min(cnt, bid * per + per);
+        const int e0 = own ? 0 : min(cnt, bid * per);
+        const int e1 = own ? s_off[bid + 1] - s_off[bid] : min(cnt, bid * per + per);
         int4* out = seg(ring ^ 1, bid);
+        int4* own_next = s_own[ring ^ 1];
         for (int eb = e0; eb < e1; eb += GRM_BLOCK) {
             const int e = eb + tid;
             int len = 0;
             if (e < e1) {
-                int lo = 0, hi = nb;  // the segment holding entry e
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_off[mid] <= e) lo = mid;
-                    else hi = mid;
+                int4 ent;
+                if (own) {
+                    ent = s_own[ring][e];
+                } else {
+                    int lo = 0, hi = nb;  // the segment holding entry e
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_off[mid] <= e) lo = mid;
+                        else hi = mid;
+                    }
+                    ent = seg(ring, lo)[e - s_off[lo]];
                 }
-                const int4 ent = seg(ring, lo)[e - s_off[lo]];
                 s_beg[tid] = ent.y;
                 len = ent.z;
                 staged++;
@@ -1304,7 +1328,12 @@ __global__ void __launch_bounds__(GRM_BLOCK) k_gr_medium(DevGraph g, int lv0, in
                 int p = __shfl(abase, 0, WAVE) + aoff;
 #pragma unroll
                 for (int k = 0; k < GR_TD_U; ++k)
-                    if (rl[k] > 0) out[p++] = make_int4(vs[k], rp[k], rl[k], 0);
+                    if (rl[k] > 0) {
+                        const int4 e4 = make_int4(vs[k], rp[k], rl[k], 0);
+                        out[p] = e4;
+                        if (p < MED_OWN) own_next[p] = e4;
+                        ++p;
+                    }
             }
             __syncthreads();  // s_beg / s_pre are restaged next round
         }
