@@ -1400,21 +1400,49 @@ mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_
     g->last_new_pairs = 0;
     for (int attempt = 0; attempt < 3; ++attempt) {
         mf::launch_clear_counters(g->ctr, st);
+        // The validation, then everything else queued right behind it, with
+        // no host read of its outcome in between: the batch kernels leave at
+        // once on a rejected batch (nothing applied; the solve that follows
+        // finds the graph as the last call left it, at its max flow), and
+        // the host learns the outcome from the counters the solve reads.
         timed(g, mf::KC_BATCH, [&] {
             mf::launch_batch_locate(g->dg, d_upd, k, bs.slot_of, g->win, bs.tb, g->need, g->ctr, st);
+            mf::launch_batch_insert(g->dg, bs.tb, g->ctr, g->nslots_d, st);
+            mf::launch_batch_apply(g->dg, d_upd, k, bs.slot_of, g->win, bs.tb, bs.touched, g->ctr, st);
+            mf::launch_batch_clamp(g->dg, d_upd, k, bs.touched, g->ctr, st);
+            mf::launch_batch_cleanup(bs.tb, g->need, bs.slot_of, g->win, k, g->ctr, st);
         });
+        timed(g, mf::KC_INIT, [&] { mf::launch_saturate_source(g->dg, g->ctr, st); });
         MF_HIP(hipGetLastError());
-        mf_status rc = read_counters(g);
-        if (rc != MF_OK) return rc;
-        const DevCounters c = *g->ctr_h;
+        mf_status rc = MF_OK;
+        if (g->push_pull) {
+            // (the push-pull phase reads the counters: a rejected batch
+            // ends the call before it changes anything)
+            rc = read_counters(g);
+            if (rc != MF_OK) return rc;
+            const DevCounters& c0 = *g->ctr_h;
+            if (!(c0.err || c0.cap_overflow || c0.overflow)) rc = push_pull_phase(g);
+        } else if (!g->opt.cold_start) {
+            rc = warm_sweep(g);
+        }
+        if (rc == MF_OK) rc = run_loop(g, solve_mode(g), value);
+        if (rc != MF_OK) {
+            // a solve that failed may have read no counters: read them to
+            // tell a rejected batch, whose slots and scratch must be put right
+            mf_status rc2 = read_counters(g);
+            if (rc2 != MF_OK) return rc2;
+        }
+        const DevCounters c = *g->ctr_h;  // the batch's outcome (the loop kernels leave these words alone)
         if (c.err || c.cap_overflow || c.overflow) {
+            rc = MF_OK;
             if (c.overflow && !c.err && !c.cap_overflow) {
-                // need[] still holds the per-row demand: re-lay, then retry
+                // need[] still holds the per-row demand (the cleanup left the
+                // scratch alone): re-lay, then retry
                 if (may_allocate) rc = relayout(g);
                 else rc = MF_ERR_OUT_OF_MEMORY;
                 if (g->poisoned) return MF_ERR_DEVICE;
             }
-            mf::launch_batch_cleanup(bs.tb, g->need, bs.slot_of, g->win, k, st);
+            mf::launch_batch_cleanup(bs.tb, g->need, bs.slot_of, g->win, k, nullptr, st);
             MF_HIP(hipGetLastError());
             MF_HIP(hipStreamSynchronize(st));
             if (rc != MF_OK) return rc;
@@ -1422,25 +1450,10 @@ mf_status apply_batch_dev(mf_graph* g, const mf_update* d_upd, int64_t k, int64_
             if (c.cap_overflow) return MF_ERR_OVERFLOW;
             continue;
         }
+        if (rc != MF_OK) return rc;
         g->last_new_pairs = c.new_pairs;
-        timed(g, mf::KC_BATCH, [&] {
-            if (c.new_pairs) mf::launch_batch_insert(g->dg, bs.tb, g->need, st);
-            mf::launch_batch_apply(g->dg, d_upd, k, bs.slot_of, g->win, bs.tb, bs.touched, g->ctr, st);
-            mf::launch_batch_clamp(g->dg, d_upd, k, bs.touched, g->win, bs.tb, st);
-            mf::launch_batch_cleanup(bs.tb, g->need, bs.slot_of, g->win, k, st);
-        });
-        g->dg.used_slots += 2 * (int64_t)c.new_pairs;
-        if (c.new_pairs) mf::launch_set_i64(g->nslots_d, g->dg.used_slots, st);
-        timed(g, mf::KC_INIT, [&] { mf::launch_saturate_source(g->dg, g->ctr, st); });
-        MF_HIP(hipGetLastError());
-        if (g->push_pull) {
-            rc = push_pull_phase(g);
-            if (rc != MF_OK) return rc;
-        } else if (!g->opt.cold_start) {
-            rc = warm_sweep(g);
-            if (rc != MF_OK) return rc;
-        }
-        return run_loop(g, solve_mode(g), value);
+        g->dg.used_slots += 2 * (int64_t)c.new_pairs;  // (the insert kernel moved the device copy on)
+        return MF_OK;
     }
     return MF_ERR_OUT_OF_MEMORY;  // slack could not be made to fit
 }

@@ -2178,27 +2178,45 @@ __global__ void __launch_bounds__(256) k_batch_check(DevGraph g, const mf_update
     if (i < k) batch_check_one(g, upd, (int)i, slot_of, win, tb, ctr);
 }
 
-__global__ void __launch_bounds__(256) k_batch_insert(DevGraph g, BatchTable tb) {
+// The kernels queued behind the batch's validation without the host reading
+// its outcome first: each leaves at once when the validation rejected the
+// batch (an invalid update, a capacity sum beyond int32, a row without room
+// for its inserts), so a rejected batch changes nothing.
+__device__ __forceinline__ bool batch_rejected(const DevCounters* ctr) {
+    return (ctr->err | ctr->cap_overflow | ctr->overflow) != 0;
+}
+
+__global__ void __launch_bounds__(256) k_batch_insert(DevGraph g, BatchTable tb, const DevCounters* ctr,
+                                                      long long* nslots) {
+    if (batch_rejected(ctr)) return;
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < tb.capacity) batch_insert_one(g, tb, idx);
+    // the used slot count the loop kernels read: two per inserted pair
+    if (idx == 0 && nslots && ctr->new_pairs)
+        atomicAdd(reinterpret_cast<unsigned long long*>(nslots), 2ull * (unsigned long long)ctr->new_pairs);
 }
 
 __global__ void __launch_bounds__(256) k_batch_apply(DevGraph g, const mf_update* upd, int64_t k,
                                                      const int32_t* slot_of, const int32_t* win,
-                                                     BatchTable tb, int32_t* touched) {
+                                                     BatchTable tb, int32_t* touched, const DevCounters* ctr) {
+    if (batch_rejected(ctr)) return;
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < k) batch_apply_one(g, upd, (int)i, slot_of, win, tb, touched);
 }
 
 __global__ void __launch_bounds__(256) k_batch_clamp(DevGraph g, const mf_update* upd, int64_t k,
-                                                     const int32_t* touched) {
+                                                     const int32_t* touched, const DevCounters* ctr) {
+    if (batch_rejected(ctr)) return;
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < k) batch_clamp_one(g, upd, (int)i, touched);
 }
 
+// ctr not null: leaves the scratch as it is when a row ran out of room (the
+// re-layout reads the rows' demand in need[]; the host cleans up after it).
 __global__ void __launch_bounds__(256) k_batch_cleanup(BatchTable tb, int32_t* need,
                                                        const int32_t* slot_of, int32_t* win,
-                                                       int64_t k) {
+                                                       int64_t k, const DevCounters* ctr) {
+    if (ctr && ctr->overflow) return;
     batch_cleanup_one(tb, need, slot_of, win, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, k);
 }
 
@@ -3116,32 +3134,30 @@ void launch_batch_locate(const DevGraph& g, const mf_update* upd, int64_t k, int
     k_batch_check<<<grid, 256, 0, st>>>(g, upd, k, slot_of, win, tb, ctr);
 }
 
-void launch_batch_insert(const DevGraph& g, BatchTable tb, int32_t* need, hipStream_t st) {
-    (void)need;
-    k_batch_insert<<<(tb.capacity + 255) / 256, 256, 0, st>>>(g, tb);
+void launch_batch_insert(const DevGraph& g, BatchTable tb, const DevCounters* ctr, long long* nslots,
+                         hipStream_t st) {
+    if (tb.capacity <= 0) return;  // no table: no batch, no pairs to insert
+    k_batch_insert<<<(tb.capacity + 255) / 256, 256, 0, st>>>(g, tb, ctr, nslots);
 }
 
 void launch_batch_apply(const DevGraph& g, const mf_update* upd, int64_t k,
                         const int32_t* slot_of, int32_t* win, BatchTable tb, int32_t* touched,
-                        DevCounters* ctr, hipStream_t st) {
-    (void)ctr;
+                        const DevCounters* ctr, hipStream_t st) {
     if (k <= 0) return;
-    k_batch_apply<<<(int)((k + 255) / 256), 256, 0, st>>>(g, upd, k, slot_of, win, tb, touched);
+    k_batch_apply<<<(int)((k + 255) / 256), 256, 0, st>>>(g, upd, k, slot_of, win, tb, touched, ctr);
 }
 
 void launch_batch_clamp(const DevGraph& g, const mf_update* upd, int64_t k,
-                        const int32_t* touched, int32_t* win, BatchTable tb, hipStream_t st) {
-    (void)win;
-    (void)tb;
+                        const int32_t* touched, const DevCounters* ctr, hipStream_t st) {
     if (k <= 0) return;
-    k_batch_clamp<<<(int)((k + 255) / 256), 256, 0, st>>>(g, upd, k, touched);
+    k_batch_clamp<<<(int)((k + 255) / 256), 256, 0, st>>>(g, upd, k, touched, ctr);
 }
 
 void launch_batch_cleanup(BatchTable tb, int32_t* need, const int32_t* slot_of, int32_t* win,
-                          int64_t k, hipStream_t st) {
+                          int64_t k, const DevCounters* ctr, hipStream_t st) {
     int64_t items = k > tb.capacity ? k : tb.capacity;
     if (items <= 0) return;
-    k_batch_cleanup<<<(int)((items + 255) / 256), 256, 0, st>>>(tb, need, slot_of, win, k);
+    k_batch_cleanup<<<(int)((items + 255) / 256), 256, 0, st>>>(tb, need, slot_of, win, k, ctr);
 }
 
 void launch_flow_slots(const DevGraph& g, int32_t* flow_slot, unsigned long long* count,

@@ -287,14 +287,18 @@ void launch_reduce_bytes(const DevGraph& g, DevCounters* ctr, hipStream_t st);
 void launch_batch_locate(const DevGraph& g, const mf_update* upd, int64_t k, int32_t* slot_of,
                          int32_t* win, BatchTable tb, int32_t* need, DevCounters* ctr,
                          hipStream_t st);
-void launch_batch_insert(const DevGraph& g, BatchTable tb, int32_t* need, hipStream_t st);
+// insert / apply / clamp leave at once when the validation (locate) rejected
+// the batch; insert adds the new slots to *nslots (when not null)
+void launch_batch_insert(const DevGraph& g, BatchTable tb, const DevCounters* ctr, long long* nslots,
+                         hipStream_t st);
 void launch_batch_apply(const DevGraph& g, const mf_update* upd, int64_t k,
                         const int32_t* slot_of, int32_t* win, BatchTable tb, int32_t* touched,
-                        DevCounters* ctr, hipStream_t st);
+                        const DevCounters* ctr, hipStream_t st);
 void launch_batch_clamp(const DevGraph& g, const mf_update* upd, int64_t k,
-                        const int32_t* touched, int32_t* win, BatchTable tb, hipStream_t st);
+                        const int32_t* touched, const DevCounters* ctr, hipStream_t st);
+// ctr not null: skipped when a row ran out of room (its demand stays in need[])
 void launch_batch_cleanup(BatchTable tb, int32_t* need, const int32_t* slot_of, int32_t* win,
-                          int64_t k, hipStream_t st);
+                          int64_t k, const DevCounters* ctr, hipStream_t st);
 void launch_cut(const DevGraph& g, uint8_t* side, unsigned long long* cut, hipStream_t st);
 // out[8] (device): negative residuals, broken pair sums, broken pair links,
 // excess mismatches, sum of excesses, heights out of range, steep residual
