@@ -808,7 +808,6 @@ mf_status push_round(mf_graph* g, const LoopMode& m, int32_t* const wl[3], const
     return MF_OK;
 }
 
-// Buffers of the incremental worklists between relabels.
 // The mid-size levels' segments for the handle's settings: each workgroup
 // appends at most one entry per slot it scans, and those levels scan at most
 // medium_max slots (and fewer than the global queue holds; larger frontiers
@@ -831,6 +830,7 @@ mf_status ensure_med(mf_graph* g, mf_graph::MedBufs& mb) {
     return MF_OK;
 }
 
+// Buffers of the incremental worklists between relabels.
 mf_status ensure_round_lists(mf_graph* g) {
     if (g->act_list) return MF_OK;
     const int64_t n = g->n;

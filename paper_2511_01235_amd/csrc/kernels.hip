@@ -878,13 +878,15 @@ __device__ __forceinline__ int gr_level_step(const Par& P, const DevGraph& g, in
                                              const GrTune& tune, unsigned* s_dyn) {
     // a capped relabel whose earlier levels labelled every vertex with excess
     // stops here: this frontier keeps its height lv, the rest get lv + 1
-    // (k_build_worklist), and the BFS reads as over
-    const int labelled = g.bfs_cap ? bcast(excess_labelled(ctr, lv)) : 0;
-    const bool capped = g.bfs_cap && labelled >= bcast(excess_total(ctr));
-    const int cnt = capped ? 0 : bcast((int)(unsigned)(ctr->front[lv % 3] & 0xFFFFFFFFull));
+    // (k_build_worklist), and the BFS reads as over.  (The frontier size
+    // first: a launch past the BFS's end leaves after one read.)
+    const int front_cnt = bcast((int)(unsigned)(ctr->front[lv % 3] & 0xFFFFFFFFull));
+    const int labelled = g.bfs_cap && front_cnt ? bcast(excess_labelled(ctr, lv)) : 0;
+    const bool capped = g.bfs_cap && front_cnt && labelled >= bcast(excess_total(ctr));
+    const int cnt = capped ? 0 : front_cnt;
     if (P.bid == 0 && threadIdx.x == 0) {
         ctr->front[(lv + 2) % 3] = 0;
-        if (g.bfs_cap) {
+        if (g.bfs_cap && front_cnt) {
             ctr->bfs_cum[lv % 3] = labelled;
             ctr->bfs_disc[(lv + 2) % 3] = 0;  // counts the labels of level lv + 2 (set during level lv + 1)
         }
