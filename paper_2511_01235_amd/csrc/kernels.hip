@@ -2677,9 +2677,13 @@ __global__ void __launch_bounds__(RN_BLOCK) k_rounds_narrow(DevGraph g, int32_t*
     __shared__ int s_n[3];
     __shared__ int s_ep;
     __shared__ int s_na;
+    __shared__ int s_act;  // the round's activations: counted in LDS (one workgroup)
     const int tid = threadIdx.x;
     const int lane = lane_id();
+    DevGraph gl = g;
+    gl.act_cnt = &s_act;
     if (tid < 3) s_c[tid] = ctr->wl[tid];
+    if (tid == 0) s_ep = *epoch;  // moved on here once per round, stored back at the end
     __syncthreads();
     int set = 0, r = 0;
     for (; r < max_rounds; ++r) {
@@ -2688,28 +2692,29 @@ __global__ void __launch_bounds__(RN_BLOCK) k_rounds_narrow(DevGraph g, int32_t*
         const int32_t* in0 = set ? b0 : a0;
         const int32_t* in1 = set ? b1 : a1;
         int32_t* out[3] = {set ? a0 : b0, set ? a1 : b1, set ? a2 : b2};
-        if (tid == 0) *g.act_cnt = 0;
+        if (tid == 0) s_act = 0;
         __syncthreads();
         // push-relabel (Algorithm 2): one thread per short row, one wave per longer row
-        for (int i = tid; i < c0; i += BS) pr_thread_item<false>(g, in0[i], kc);
-        for (int w = tid / WAVE; w < c1; w += BS / WAVE) pr_wave_item<false>(g, bcast(in1[w]), kc);
+        for (int i = tid; i < c0; i += BS) pr_thread_item<false>(gl, in0[i], kc);
+        for (int w = tid / WAVE; w < c1; w += BS / WAVE) pr_wave_item<false>(gl, bcast(in1[w]), kc);
         __syncthreads();
         // remove invalid edges (Algorithm 3) over the same rows
         unsigned long long nb = 0;
         for (int i = tid; i < c0; i += BS) {
             const int u = in0[i];
-            const long long moved = rie_item<1>(g, u, 0, &nb);
+            const long long moved = rie_item<1>(gl, u, 0, &nb);
             if (moved) add_e(g.e, u, -moved);
         }
         for (int w = tid / WAVE; w < c1; w += BS / WAVE) {
             const int u = bcast(in1[w]);
-            const long long moved = wave_sum_i64(rie_item<WAVE>(g, u, lane, &nb));
+            const long long moved = wave_sum_i64(rie_item<WAVE>(gl, u, lane, &nb));
             if (lane == 0 && moved) add_e(g.e, u, -moved);
         }
+        // every wave's activations are counted before the count is read
+        __syncthreads();
         if (tid == 0) {
-            s_ep = *epoch + 1;
-            *epoch = s_ep;
-            s_na = __hip_atomic_load(g.act_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // counted by atomics
+            ++s_ep;
+            s_na = s_act;
         }
         if (tid < 3) s_n[tid] = 0;
         __syncthreads();
@@ -2741,6 +2746,7 @@ __global__ void __launch_bounds__(RN_BLOCK) k_rounds_narrow(DevGraph g, int32_t*
         ctr->wl[3] = s_c[0] + s_c[1] + s_c[2];
         ctr->rn_set = set;
         ctr->rn_rounds = r;
+        *epoch = s_ep;
     }
 }
 
