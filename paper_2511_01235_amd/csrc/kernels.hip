@@ -502,7 +502,9 @@ __device__ __forceinline__ void gr_init_body(const Par& P, const DevGraph& g, in
     if (P.bid == 0 && threadIdx.x == 0) {
         // slots of every row that may be labelled, the seeds' included
         ctr->unv[2] = (g.nslots ? *g.nslots : (long long)g.used_slots) - g.row_len[g.pinned];
-        add_bytes(g, cls, 12ull * (unsigned long long)N);
+        // per vertex: height, excess; a capped relabel also reads the old
+        // height and keeps it in h_prev
+        add_bytes(g, cls, (cap_ok ? 20ull : 12ull) * (unsigned long long)N);
     }
 }
 
@@ -845,10 +847,12 @@ __device__ __forceinline__ void gr_level_body(const Par& P, const DevGraph& g, i
     }
     // per scanned slot: col+res (8), capsum (4), plus h[col] (4) without the
     // LDS bitmap; per staged entry or unlabelled vertex its words; per
-    // discovered vertex the CAS, two bitmap words and its queue entry
+    // discovered vertex the CAS, two bitmap words and its queue entry, and
+    // with a capped relabel its excess (8)
     unsigned long long per_slot = (s_bm ? 12ull : 16ull) - ((bu && !FWD) ? 4ull : 0ull);
     if (g.count_bytes) {
-        unsigned long long b = wave_sum_u64(per_slot * scanned + 4ull * exam + 24ull * found);
+        const unsigned long long per_found = g.bfs_cap ? 32ull : 24ull;
+        unsigned long long b = wave_sum_u64(per_slot * scanned + 4ull * exam + per_found * found);
         if (lane == 0) add_bytes(g, cls, b);
     }
 }
