@@ -77,17 +77,17 @@ struct mf_graph {
     mf::GrTune tune{mf::GR_BU_ALPHA, mf::GR_BU_BETA, mf::GR_STAGE_MIN, 0, 0, 0};
     int persistent_grid = 0;  // > 0: global relabel as one cooperative launch of this many blocks
     int first_chunk = 7;      // BFS levels launched before the first frontier check (at least)
-    bool trace_gr = false;    // MF_GR_TRACE: one level per launch, each printed to stderr
+    bool trace_gr = false;    // option trace: one level per launch, each printed to stderr
     bool narrow_seed = true;  // start relabels in one workgroup (the last one's seeds were few enough)
     int32_t last_depth = 0;   // BFS levels of the last global relabel
-    bool queue_rounds = true; // MF_QUEUE_ROUNDS=0: no worklist build and rounds queued behind the relabel
-    bool pipeline = true;     // MF_PIPELINE=0: no relabel iteration queued ahead of the host's read
+    bool queue_rounds = true; // option queue_rounds: worklist build and rounds queued behind the relabel
+    bool pipeline = true;     // option pipeline: a relabel iteration queued ahead of the host's read
     DevCounters* snap_h[2] = {nullptr, nullptr};  // pinned: counters of the iterations in flight
     hipEvent_t snap_ev[2] = {nullptr, nullptr};
     int32_t kc_block = 1;     // push/relabel cycles of the workgroup bin (capped at kc)
     int32_t round_div = 4;    // push-relabel rounds per global relabel: BFS depth / round_div ...
     int32_t round_max = 4096; // ... at most this many
-    int32_t round_min = 2;    // ... and at least this many (MF_ROUND_MIN)
+    int32_t round_min = 2;    // ... and at least this many (option round_min)
     bool incremental_rounds = true;  // rounds take their worklist from the previous one plus activations
     int64_t narrow_max = 4096;       // BFS frontiers of up to this many slots run in one workgroup (0: never)
     int64_t medium_max = 65536;      // ... up to this many in one cooperative launch of a few workgroups

@@ -253,8 +253,8 @@ struct Tuning {
     int32_t batch_block;
     int32_t long_cycles;  // push/relabel cycles of the workgroup bin (capped at kc)
 };
-// MF_ERR_INVALID for inconsistent fields; environment overrides (MF_GR_*,
-// MF_ROUND_DIV, MF_KC_BLOCK) apply where the option is left 0.
+// MF_ERR_INVALID for inconsistent fields; a field left 0 takes its default
+// (the library reads no environment variable).
 mf_status resolve_tuning(const mf_options& o, Tuning* t);
 
 // ---- launch wrappers (kernels.hip) ---------------------------------------
