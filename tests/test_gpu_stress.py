@@ -9,7 +9,7 @@ and a random increase/decrease/insert mix.  After the static solve and after
 every batch the value must equal the oracle's; the cut returned at the end
 is checked as a certificate, and the labelling invariants are checked on
 the device after the last batch.  Seeds are fixed, so a failure names its
-case.
+case (each configuration gets every thirteenth seed).
 """
 import os
 import sys
@@ -37,9 +37,14 @@ CONFIGS = [
     {"pipeline": -1, "queue_rounds": -1},                  # one read per launch group
     {"warm_start": False},                                 # Algorithm 5 as printed
     {"round_div": 1, "kernel_cycles": 1},                  # many rounds, one cycle each
+    {"push_pull": True},                                   # parallel push-pull repairs (O2)
+    {"topology_driven": True},                             # every vertex a worker
+    {"relabel_mode": 1},                                   # relabel and worklist in one cooperative launch
+    {"bfs_bottom_up": 2},                                  # slot-parallel bottom-up levels
+    {"graph_capture": 1},                                  # pipelined iterations replayed from HIP graphs
 ]
 
-N_CASES = 96
+N_CASES = 104
 
 
 def say(*a):
