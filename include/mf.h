@@ -59,8 +59,7 @@ typedef struct mf_options {
                                   KERNEL_CYCLES); <= 0: round(m/n), at least 1 (Section 6.1) */
     int32_t topology_driven;   /* 1: one worker per vertex for push-relabel and remove-invalid-
                                   edges; 0 (default): active-vertex worklist (Section 5.2, O1) */
-    int32_t insert_slack_min;  /* free slots kept per row for inserted pairs; <= 0: 8 for a graph
-                                  handle, 2 for each graph of a batch */
+    int32_t insert_slack_min;  /* free slots kept per row for inserted pairs; <= 0: 8 */
     int32_t insert_slack_pct;  /* plus this percentage of the row's length; <= 0: 12 */
     int64_t max_iterations;    /* cap on global relabels per call; <= 0: 4n + 1000 */
     int32_t cold_start;        /* 0 (default): a repair first runs one push-relabel and remove-

@@ -400,7 +400,7 @@ mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edg
     if (edge_offset[0] != 0) return MF_ERR_INVALID;
     for (int i = 0; i < num_graphs; ++i)
         if (edge_offset[i + 1] < edge_offset[i]) return MF_ERR_INVALID;
-    int32_t slack_min = o.insert_slack_min > 0 ? o.insert_slack_min : 2;
+    int32_t slack_min = o.insert_slack_min > 0 ? o.insert_slack_min : 8;
     int32_t slack_pct = o.insert_slack_pct > 0 ? o.insert_slack_pct : 12;
     mf::Tuning tuning;
     if (mf::resolve_tuning(o, &tuning) != MF_OK) return MF_ERR_INVALID;
