@@ -692,7 +692,7 @@ def test_grid2048_full_size():
 
 
 @pytest.mark.parametrize("relabel_mode", [0, 1])
-@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
+@pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64", "rmat16"])
 def test_push_pull_matches_oracle(name, relabel_mode):
     """Section 5.2's O2: static push-pull (sink in-edges saturated first) and
     the parallel push-pull repair (old min cut saturated again, push inside
