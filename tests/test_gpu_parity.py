@@ -79,6 +79,28 @@ def test_initial_labels_bit_exact(name):
     assert np.unique(active).size == active.size
 
 
+@pytest.mark.parametrize("name", ["grid2048", "rmat20"])
+def test_full_size_initial_labels_bit_exact(name):
+    """Algorithm 1's initialisation and the first global relabel (Algorithms
+    4 and 6) at the benchmark shapes: the 2,049-level grid BFS runs through
+    the one-workgroup, cooperative and multi-block level kernels, the RMAT
+    one through top-down and bottom-up levels.  Every height and excess
+    equals the oracle's, and so does the active set."""
+    g, _, _, _ = gen.workload(name)
+    say("full-size initial labels", name, g.n, g.m)
+    o = oracle.DynOracle(g.n, g.src, g.dst, g.cap, g.s, g.t)
+    h_want, e_want = o.initial_labels()
+    with mf.MaxFlowGraph(g.n, g.src, g.dst, g.cap, g.s, g.t) as G:
+        h, e, active = G.initial_labels()
+    bad = np.flatnonzero(h != h_want)
+    assert bad.size == 0, (name, bad[:8], h[bad[:8]], h_want[bad[:8]])
+    assert np.array_equal(e, e_want)
+    others = np.ones(g.n, bool)
+    others[[g.s, g.t]] = False
+    want_active = np.flatnonzero(others & (e_want > 0) & (h_want < g.n))
+    assert np.array_equal(np.sort(active), want_active)
+
+
 @pytest.mark.parametrize("variant", ["rows4", "rows8", "slots"])
 @pytest.mark.parametrize("name", ["er2000", "rmat12", "grid64"])
 def test_bottom_up_levels_bit_exact(name, variant):
