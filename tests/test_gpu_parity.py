@@ -293,12 +293,16 @@ def test_static_tiny_vs_brute_force(seed):
     _cut_ok(n, s, t, side, cut, got, src, dst, cap)
 
 
-@pytest.mark.parametrize("name", ["er2000", "rmat12", "rmat16", "grid64", "grid256"])
-@pytest.mark.parametrize("opts", [{}, {"kernel_cycles": 1}, {"kernel_cycles": 64},
-                                  {"topology_driven": True}])
+# every graph with the defaults; the option sweep on the smaller ones
+_STATIC_CASES = [(name, {}) for name in ("er2000", "rmat12", "rmat16", "grid64", "grid256")] + [
+    (name, opts) for opts in ({"kernel_cycles": 1}, {"kernel_cycles": 64}, {"topology_driven": True})
+    for name in ("er2000", "rmat12", "grid64")]
+
+
+@pytest.mark.parametrize("name,opts", _STATIC_CASES,
+                         ids=[f"{n}-{'-'.join(f'{k}={v}' for k, v in o.items()) or 'defaults'}"
+                              for n, o in _STATIC_CASES])
 def test_static_workloads(name, opts):
-    if name in ("rmat16", "grid256") and opts:
-        pytest.skip("option sweep runs on the smaller graphs")
     g, _, _, _ = gen.workload(name)
     say("static", name, opts)
     want, got, side, cut = _solve_both(g.n, g.src, g.dst, g.cap, g.s, g.t, **opts)
