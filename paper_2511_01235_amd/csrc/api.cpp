@@ -850,6 +850,12 @@ mf_status ensure_round_lists(mf_graph* g) {
 // (at most two rounds per relabel).
 constexpr int PIPELINE_DEPTH = 16;
 
+// Rounds on a worklist short enough for the one-workgroup round kernel cost
+// a few microseconds each and stop as soon as the list empties: a relabel
+// whose worklist is that thin buys at least this many of them before the
+// next relabel (deep BFS on grids ends with many shallow relabels).
+constexpr int THIN_ROUNDS_MIN = 8;
+
 // The next-worklist marks compare with an epoch word in device memory
 // (mark[n]) that every next-worklist build moves on by one before it runs.
 // The host counts the builds it queues; before the word could wrap it clears
@@ -1151,7 +1157,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m_in, int64_t* value) {
             if (m.L.main) g->last_iterations = iters;
             return MF_ERR_NOT_CONVERGED;
         }
-        const int64_t R = std::min<int64_t>(g->round_max, std::max<int64_t>(g->round_min, depth / g->round_div));
+        int64_t R = std::min<int64_t>(g->round_max, std::max<int64_t>(g->round_min, depth / g->round_div));
         int cnt[3];
         int32_t* cur[3];
         if (g->trace_gr)
@@ -1161,6 +1167,9 @@ mf_status run_loop(mf_graph* g, const LoopMode& m_in, int64_t* value) {
         // previous one plus the vertices the round activated, not a scan of
         // every vertex
         const bool incremental = R > 1 && m.L.main && !m.pull && !m.topology && g->incremental_rounds;
+        auto thin = [&](const int b[3]) {
+            return incremental && g->rn_limit > 0 && b[2] == 0 && b[0] + b[1] <= g->rn_limit;
+        };
         LoopMode rm = m;
         if (incremental) {
             rc = ensure_round_lists(g);
@@ -1197,6 +1206,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m_in, int64_t* value) {
                 *value = (int64_t)c.round_e_t + (int64_t)c.round_deficit;
                 break;
             }
+            if (thin(cnt)) R = std::max<int64_t>(R, THIN_ROUNDS_MIN);
             if (c.wl[3] == 0 || R <= 2) continue;  // certified by the next relabel
             active_sum += c.wl[3];
         } else {
@@ -1257,7 +1267,8 @@ mf_status run_loop(mf_graph* g, const LoopMode& m_in, int64_t* value) {
             }
             // a short list without workgroup-bin rows: rounds in one workgroup,
             // many per launch, until the list grows or empties
-            if (incremental && g->rn_limit > 0 && cnt[2] == 0 && cnt[0] + cnt[1] <= g->rn_limit && R - done >= 4) {
+            if (thin(cnt)) R = std::max<int64_t>(R, THIN_ROUNDS_MIN);
+            if (thin(cnt) && R - done >= 4) {
                 int32_t* other[3];
                 for (int b = 0; b < 3; ++b) other[b] = cur[b] == m.L.wl[b] ? g->wlb[b] : m.L.wl[b];
                 const int most = (int)std::min<int64_t>(R - done, INT_MAX / 2);
