@@ -137,7 +137,8 @@ typedef struct mf_options {
                                   stderr, for diagnosis; slow */
     int32_t round_narrow;      /* rounds between relabels whose worklist holds at most this many
                                   vertices (none above bin_wave_max slots) run in one workgroup,
-                                  many rounds per launch; 0: 2048, < 0: never */
+                                  many rounds per launch, and such a relabel buys at least 8 of
+                                  them (they stop when the list empties); 0: 2048, < 0: never */
     int32_t bfs_cap;           /* 0 (default) or 1: a solve's relabels after its first one, when no
                                   deficient vertex sits above height 0, stop once every vertex with
                                   excess below |V| has its height; a vertex not reached keeps
