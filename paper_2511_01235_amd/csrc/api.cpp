@@ -1006,8 +1006,9 @@ mf_status run_loop(mf_graph* g, const LoopMode& m_in, int64_t* value) {
     const int bounds[3] = {(int)g->n, (int)g->n, (int)g->n};
     mf_status tail_rc = MF_OK;
     // The launches queued behind the relabel's first chunk of levels on
-    // stream `sm`'s lane: the guarded worklist build, round 1, round 2's
-    // worklist from round 1's (one next-worklist build: one epoch), round 2.
+    // stream `sm`'s lane: the guarded worklist build, the first round, the
+    // second round's worklist from the first's (one next-worklist build: one
+    // epoch), the second round.
     auto enqueue_tail = [&](const LoopMode& mm, const LoopMode& qq, int level_end) -> mf_status {
         hipStream_t s2 = mm.L.stream;
         timed(g, mm.L, mf::KC_WL, [&] {
@@ -1016,12 +1017,12 @@ mf_status run_loop(mf_graph* g, const LoopMode& m_in, int64_t* value) {
         });
         // the build cleared the activation count; the next-worklist build
         // sets the worklist counts aside in wl_in (the host reads the
-        // relabel's there), round 2 keeps its own in wl
+        // relabel's there), the second round keeps its own in wl
         mf_status rc = push_round(g, qq, mm.L.wl, bounds, true);
         timed(g, mm.L, mf::KC_WL, [&] {
             mf::launch_next_worklist(qq.dg, mm.L.wl, nullptr, g->wlb[0], g->wlb[1], g->wlb[2], g->mark,
                                      g->mark + g->n, mm.L.ctr, s2);
-            // round 1 left no active vertex: the value, and no second round
+            // the first round left no active vertex: the value, and no second round
             if (shortcut) mf::launch_value_if_empty(qq.dg, mm.L.ctr, level_end, s2);
         });
         mf::launch_zero_act(mm.L.ctr, s2);
@@ -1104,7 +1105,7 @@ mf_status run_loop(mf_graph* g, const LoopMode& m_in, int64_t* value) {
             // the BFS outlasted the chunk: the tail did nothing
             if ((c.front[chunk[k] % 3] & 0xFFFFFFFFull) != 0) break;
             g->last_depth = c.levels;
-            const int active = c.wl_in[3];  // the relabel's worklist (set aside before round 2's)
+            const int active = c.wl_in[3];  // the relabel's worklist (set aside before the second round's)
             active_sum += active;
             capped += c.bfs_capped != 0;
             if (active == 0) {
