@@ -399,7 +399,11 @@ typedef struct mf_batch mf_batch;
  * dst, cap (vertex ids local to the graph, 0..n[i]-1), source s[i], sink
  * t[i].  edge_offset has num_graphs + 1 entries, edge_offset[0] = 0.  Every
  * graph is validated as in mf_graph_load before anything is allocated.
- * opt (NULL: defaults) applies to every graph. */
+ * opt (NULL: defaults) applies to every graph.  On success *out owns the
+ * pooled device memory until mf_batch_free.  Errors: MF_ERR_INVALID (a null
+ * array, offsets that do not start at 0 or decrease, an invalid graph or
+ * options), MF_ERR_OVERFLOW (the pool's slots or vertices above INT32_MAX),
+ * MF_ERR_OUT_OF_MEMORY, MF_ERR_DEVICE; *out is not written on error. */
 mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edge_offset,
                         const int32_t* src, const int32_t* dst, const int32_t* cap, const int32_t* s,
                         const int32_t* t, const mf_options* opt, mf_batch** out);
@@ -419,7 +423,8 @@ mf_status mf_batch_apply(mf_batch* b, const int64_t* update_offset, const mf_upd
                          int64_t* values);
 
 /* Loop iterations (global relabels) of each graph in the last call
- * (int32[num_graphs], or NULL) and the call's host wall time in ms. */
+ * (int32[num_graphs], or NULL) and the call's host wall time in ms (or
+ * NULL).  Errors: MF_ERR_INVALID (b NULL). */
 mf_status mf_batch_info(const mf_batch* b, int32_t* iterations, double* last_ms);
 
 /* mf_graph_tune for a batch: the same fields plus batch_block (threads per
@@ -435,7 +440,8 @@ mf_status mf_batch_tune(mf_batch* b, const mf_options* opt);
 mf_status mf_batch_profile(mf_batch* b, int32_t on);
 
 /* The last profiled call's solve launch: its event time in ms and the
- * algorithmic bytes its kernels moved (0 when not profiling). */
+ * algorithmic bytes its kernels moved (0 when not profiling); either output
+ * may be NULL.  Errors: MF_ERR_INVALID (b NULL). */
 mf_status mf_batch_kernel_stats(const mf_batch* b, double* kernel_ms, double* alg_bytes);
 
 void mf_batch_free(mf_batch* b);
