@@ -402,7 +402,8 @@ typedef struct mf_batch mf_batch;
  * opt (NULL: defaults) applies to every graph.  On success *out owns the
  * pooled device memory until mf_batch_free.  Errors: MF_ERR_INVALID (a null
  * array, offsets that do not start at 0 or decrease, an invalid graph or
- * options), MF_ERR_OVERFLOW (the pool's slots or vertices above INT32_MAX),
+ * options), MF_ERR_OVERFLOW (a capacity pair above INT32_MAX, or the pool's
+ * slots or vertices above INT32_MAX),
  * MF_ERR_OUT_OF_MEMORY, MF_ERR_DEVICE; *out is not written on error. */
 mf_status mf_batch_load(int32_t num_graphs, const int32_t* n, const int64_t* edge_offset,
                         const int32_t* src, const int32_t* dst, const int32_t* cap, const int32_t* s,

@@ -144,3 +144,46 @@ def test_library_reads_no_environment_switches():
     import glob
     for path in glob.glob(os.path.join(ROOT, "paper_2511_01235_amd", "csrc", "*")):
         assert "getenv" not in open(path).read(), path
+
+
+def _batch_load(n, off, e, s, t, opt=None):
+    """mf_batch_load through the C ABI: returns (status, handle)."""
+    import ctypes as C
+    n = np.asarray(n, np.int32)
+    off = np.asarray(off, np.int64)
+    e = np.asarray(e, np.int32).reshape(-1, 3)
+    src, dst, cap = (np.ascontiguousarray(e[:, i]) for i in range(3))
+    s = np.asarray(s, np.int32)
+    t = np.asarray(t, np.int32)
+    h = C.c_void_p()
+    rc = mf.lib().mf_batch_load(int(n.size), n.ctypes.data, off.ctypes.data, src.ctypes.data,
+                                dst.ctypes.data, cap.ctypes.data, s.ctypes.data, t.ctypes.data,
+                                C.byref(opt) if opt is not None else None, C.byref(h))
+    return rc, h.value
+
+
+@pytest.mark.parametrize("case,want", [
+    (dict(n=[3], off=[1, 1], e=[[0, 1, 1]], s=[0], t=[2]), "invalid"),            # offsets start above 0
+    (dict(n=[3, 3], off=[0, 1, 0], e=[[0, 1, 1]], s=[0, 0], t=[2, 2]), "invalid"),  # offsets decrease
+    (dict(n=[3, 3], off=[0, 1, 2], e=[[0, 1, 1], [0, 1, 1]], s=[0, 1], t=[2, 1]), "invalid"),  # s == t
+    (dict(n=[3, 3], off=[0, 1, 2], e=[[0, 1, 1], [0, 3, 1]], s=[0, 0], t=[2, 2]), "invalid"),  # vertex id
+    (dict(n=[3], off=[0, 2], e=[[0, 1, 2**31 - 1], [1, 0, 1]], s=[0], t=[2]), "overflow"),  # pair sum
+])
+def test_batch_load_rejects_invalid(case, want):
+    """The batched load validates every graph on the host before it touches the
+    device: a bad offset table, an invalid graph or a capacity pair above int32
+    is rejected and no handle is returned."""
+    rc, h = _batch_load(**case)
+    assert rc == {"invalid": mf.MF_ERR_INVALID, "overflow": mf.MF_ERR_OVERFLOW}[want]
+    assert not h
+
+
+def test_batch_load_rejects_bad_options():
+    import ctypes as C
+    opt = mf.make_options()
+    opt.struct_size = C.sizeof(opt) - 4
+    rc, h = _batch_load([3], [0, 1], [[0, 1, 1]], [0], [2], opt=opt)
+    assert rc == mf.MF_ERR_INVALID and not h
+    rc, h = _batch_load([], [0], np.zeros((0, 3)), [], [])
+    assert rc == mf.MF_ERR_INVALID and not h
+
